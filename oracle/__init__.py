@@ -97,7 +97,7 @@ def lib():
             build()
         L = C.CDLL(_LIB_PATH)
         L.orc_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_uniform.argtypes = [C.c_uint64]
+        L.orc_uniform.argtypes = [C.c_uint64, C.c_int32]
         L.orc_uniform.restype = C.c_double
         L.orc_normals.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p]
         L.orc_resample_u.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
@@ -133,8 +133,8 @@ def philox(ctr, key) -> np.ndarray:
     return out
 
 
-def uniform(word: int) -> float:
-    return lib().orc_uniform(C.c_uint64(int(word)))
+def uniform(word: int, low_field: bool = False) -> float:
+    return lib().orc_uniform(C.c_uint64(int(word)), 1 if low_field else 0)
 
 
 def normals(seed: int, i: int, k: int, t: int) -> np.ndarray:

@@ -59,10 +59,12 @@ void philox4x64_10(const uint64_t in_ctr[4], const uint64_t in_key[2], uint64_t 
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Uniform on (0,1) from one 64-bit word: the top 23 bits plus one half,
- * scaled by 2^-23. The value is a dyadic rational with 24 significant bits,
- * so it is exact in binary32 as well as binary64. */
-double uniform_open(uint64_t w) { return ((double)(w >> 41) + 0.5) * 0x1p-23; }
+/* Uniforms on (0,1) from one 64-bit word: two disjoint 23-bit fields
+ * (bits 41..63 and bits 9..31), each plus one half, scaled by 2^-23. The
+ * values are dyadic rationals with 24 significant bits, so they are exact in
+ * binary32 as well as binary64. */
+double uniform_hi(uint64_t w) { return ((double)(w >> 41) + 0.5) * 0x1p-23; }
+double uniform_lo(uint64_t w) { return ((double)((w >> 9) & 0x7FFFFFULL) + 0.5) * 0x1p-23; }
 
 const double TWO_PI = 6.283185307179586476925286766559;
 
@@ -105,34 +107,32 @@ void orc_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
   philox4x64_10(ctr, key, out);
 }
 
-double orc_uniform(uint64_t w) { return uniform_open(w); }
+double orc_uniform(uint64_t w, int32_t low_field) { return low_field ? uniform_lo(w) : uniform_hi(w); }
 
-/* Eight standard normals for particle i of target t at frame k: two Philox
- * blocks with counters (i, k, t, 0) and (i, k, t, 1), key (seed, 0); words
- * taken in pairs (u1, u2) and mapped by Box-Muller,
- * z = sqrt(-2 ln u1) * (cos 2 pi u2, sin 2 pi u2). */
+/* Eight standard normals for particle i of target t at frame k: one Philox
+ * block with counter (i, k, t, 0) and key (seed, 0); word p gives the pair
+ * (u1, u2) = (high field, low field), mapped by Box-Muller,
+ * (z_2p, z_2p+1) = sqrt(-2 ln u1) * (cos 2 pi u2, sin 2 pi u2). */
 void orc_normals(uint64_t seed, uint64_t i, uint64_t k, uint64_t t, double z[8]) {
   const uint64_t key[2] = {seed, 0};
-  for (uint64_t s = 0; s < 2; ++s) {
-    const uint64_t ctr[4] = {i, k, t, s};
-    uint64_t out[4];
-    philox4x64_10(ctr, key, out);
-    for (int p = 0; p < 2; ++p) {
-      double u1 = uniform_open(out[2 * p]);
-      double u2 = uniform_open(out[2 * p + 1]);
-      double r = std::sqrt(-2.0 * std::log(u1));
-      z[4 * s + 2 * p] = r * std::cos(TWO_PI * u2);
-      z[4 * s + 2 * p + 1] = r * std::sin(TWO_PI * u2);
-    }
+  const uint64_t ctr[4] = {i, k, t, 0};
+  uint64_t out[4];
+  philox4x64_10(ctr, key, out);
+  for (int p = 0; p < 4; ++p) {
+    double u1 = uniform_hi(out[p]);
+    double u2 = uniform_lo(out[p]);
+    double r = std::sqrt(-2.0 * std::log(u1));
+    z[2 * p] = r * std::cos(TWO_PI * u2);
+    z[2 * p + 1] = r * std::sin(TWO_PI * u2);
   }
 }
 
 /* The one uniform of systematic resampling for target t at frame k:
- * word 0 of the Philox block with counter (0, k, t, 2), as (w >> 11) 2^-53,
+ * word 0 of the Philox block with counter (0, k, t, 1), as (w >> 11) 2^-53,
  * a value in [0, 1). */
 double orc_resample_u(uint64_t seed, uint64_t k, uint64_t t) {
   const uint64_t key[2] = {seed, 0};
-  const uint64_t ctr[4] = {0, k, t, 2};
+  const uint64_t ctr[4] = {0, k, t, 1};
   uint64_t out[4];
   philox4x64_10(ctr, key, out);
   return (double)(out[0] >> 11) * 0x1p-53;

@@ -40,22 +40,28 @@ def test_philox_matches_numpy(orc, ctr, key):
 
 
 def test_uniform_open_interval_and_exact_in_binary32(orc):
-    for wd in (0, 1, 2**41 - 1, 2**41, 2**63, 2**64 - 1, 0x0123456789ABCDEF):
-        u = orc.uniform(wd)
-        assert 0.0 < u < 1.0
-        assert float(np.float32(u)) == u  # 24 significant bits at most
-        assert u == float(Fraction(2 * (wd >> 41) + 1, 2**24))
+    for wd in (0, 1, 2**41 - 1, 2**41, 2**63, 2**64 - 1, 0x0123456789ABCDEF, 0xFFFFFE00, 0x1FF):
+        for low in (False, True):
+            u = orc.uniform(wd, low)
+            assert 0.0 < u < 1.0
+            assert float(np.float32(u)) == u  # 24 significant bits at most
+            field = ((wd >> 9) & (2**23 - 1)) if low else (wd >> 41)
+            assert u == float(Fraction(2 * field + 1, 2**24))
 
 
 def test_box_muller_invariant_and_moments(orc):
     seed = 77
-    # invariant of the Box-Muller map: z0^2 + z1^2 = -2 ln u1 for each pair
+    # invariant of the Box-Muller map: z0^2 + z1^2 = -2 ln u1 for each pair,
+    # and atan2(z1, z0) = 2 pi u2 (mod 2 pi)
     for i in range(50):
         z = orc.normals(seed, i, 3, 1)
         blk = orc.philox((i, 3, 1, 0), (seed, 0))
-        for p in range(2):
-            u1 = orc.uniform(int(blk[2 * p]))
+        for p in range(4):
+            u1 = orc.uniform(int(blk[p]), False)
+            u2 = orc.uniform(int(blk[p]), True)
             assert z[2 * p] ** 2 + z[2 * p + 1] ** 2 == pytest.approx(-2.0 * math.log(u1), rel=1e-12)
+            ang = math.atan2(z[2 * p + 1], z[2 * p]) % (2 * math.pi)
+            assert min(abs(ang - 2 * math.pi * u2), 2 * math.pi - abs(ang - 2 * math.pi * u2)) < 1e-9
     # moments over many draws: every slot is N(0, 1) and slots are uncorrelated
     Z = np.array([orc.normals(seed, i, 1, 0) for i in range(40000)])
     n = Z.shape[0]
@@ -393,7 +399,7 @@ def test_systematic_resampling_marginals(orc):
 
 
 def test_resample_uniform_counter(orc):
-    blk = orc.philox((0, 4, 9, 2), (31, 0))
+    blk = orc.philox((0, 4, 9, 1), (31, 0))
     assert orc.resample_u(31, 4, 9) == float(Fraction(int(blk[0]) >> 11, 2**53))
 
 
