@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark: particle-steps/s of SIR vs pcSIR at matched tracking RMSE on one MI355X.
+
+Workload (default "single-2d-512"): one 2D target, N = 10^6 particles, 512x512
+synthetic microscopy frames (Gaussian spot sigma 1.5 px, peak 50, background 10,
+Poisson noise), likelihood over a 15x15 window with 8x8 sub-pixel quadrature,
+bins h in {1, 0.5, 0.25, 0.1, 0.05} px.
+
+1. Untimed matching pass: SIR and pcSIR at every h track all frames from the
+   truth; the matched pcSIR operating point is the largest h whose RMSE is at
+   most 1.05x SIR's.
+2. Timed region: W warm-up frames, then K frames of pcSIR at the matched h
+   (inputs resident in HBM), bracketed by synchronisation; per-kernel times are
+   taken with HIP events on the library's stream inside the same region.
+3. The same for SIR (reported beside it).
+4. CPU baseline: the FP64 oracle on a bounded sample of the same workload.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VEC_TFLOPS = 157.3
+N_CU = 256
+CLOCK_GHZ = 2.4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="single-2d-512")
+    ap.add_argument("--lik", type=int, default=0, help="0 direct (per sub-sample), 1 separable")
+    ap.add_argument("--reps", type=int, default=2, help="repetitions of the RMSE matching pass")
+    ap.add_argument("--no-match", action="store_true", help="skip the RMSE matching pass (use --h)")
+    ap.add_argument("--h", type=float, default=0.5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="if > 0: only run this many pcSIR steps (for rocprofv3) and exit")
+    return ap.parse_args()
+
+
+def bytes_per_particle(kind: str, D: int, passes: int) -> dict:
+    """Algorithmic HBM bytes per particle of each kernel (see the design notes)."""
+    b = {
+        "propagate": 4 * D + 4 + 4 * D,          # parent state + ancestor index in, new state out
+        "keys": 4 * 2 + 4,                        # x, y in; key out
+        "sort_scatter": 8 + 8,                    # (key, index) in and out, per pass
+        "sort_hist": 4,                           # key in, per pass
+        "seg_reduce": 8 + 4 * D,                  # sorted (key, index) + gathered state
+        "cdf_sum": 4,                             # key (pcSIR) / log-likelihood (SIR)
+        "resample": 4 + 4,                        # key / log-likelihood in, s(j) out
+    }
+    return b
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "design only, see the design notes)"}))
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_1310_5541_amd import Config, Filter
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = synth.preset(args.workload)
+    K_total = max(w.K, args.warmup + args.steps)
+    w = synth.preset(args.workload, K=K_total)
+    t0 = time.time()
+    tr = synth.truth(w)
+    frames_np = synth.frames(w, tr)
+    counts = w.counts()
+    NT = int(counts.sum())
+    frames = torch.from_numpy(frames_np).to(dev)
+    init = torch.from_numpy(synth.initial_particles(w, tr[0], counts)).to(dev)
+    gen_s = time.time() - t0
+    T, D, dim = w.T, w.D, w.dim
+
+    def make(h, **kw):
+        m = int(round(1.0 / h))
+        bins = (m, m, m if dim == 3 else 1)
+        cfg = Config.from_workload(w, bins_per_px=bins, lik_mode=args.lik, seed=w.seed + 500, **kw)
+        return Filter(cfg, init)
+
+    def frame(k):
+        return frames[(k - 1) % frames.shape[0]]
+
+    if args.profile_steps > 0:
+        f = make(args.h)
+        for k in range(1, args.profile_steps + 1):
+            f.pcsir_step(frame(k), k)
+        torch.cuda.synchronize()
+        f.close()
+        print(json.dumps({"profiled_steps": args.profile_steps}))
+        return
+
+    # ---- 1. matching pass (untimed)
+    hs = [1.0, 0.5, 0.25, 0.1, 0.05]
+    rm = {}
+    if not args.no_match:
+        Kmatch = w.K if K_total == w.K else synth.preset(args.workload).K
+        for rep in range(args.reps):
+            wr = synth.preset(args.workload, seed=w.seed + 1000 * rep)
+            trr = synth.truth(wr)
+            frr = torch.from_numpy(synth.frames(wr, trr)).to(dev)
+            initr = torch.from_numpy(synth.initial_particles(wr, trr[0], counts)).to(dev)
+            for mode in ["sir"] + [f"h={h}" for h in hs]:
+                sir = mode == "sir"
+                h = 0.5 if sir else float(mode[2:])
+                m = int(round(1.0 / h))
+                cfg = Config.from_workload(wr, bins_per_px=(m, m, m if dim == 3 else 1), lik_mode=args.lik,
+                                           seed=wr.seed + 500)
+                f = Filter(cfg, initr)
+                est = np.zeros((Kmatch, T, D))
+                for k in range(1, Kmatch + 1):
+                    f.step(frr[k - 1], k, sir=sir)
+                    est[k - 1] = f.estimate()[0]
+                f.close()
+                rm.setdefault(mode, []).append(float(np.mean(synth.rmse(est, trr[:Kmatch + 1], dim))))
+        rmse = {k: float(np.mean(v)) for k, v in rm.items()}
+        ok = [h for h in hs if rmse[f"h={h}"] <= 1.05 * rmse["sir"]]
+        h_match = max(ok) if ok else min(hs)
+    else:
+        rmse = {}
+        h_match = args.h
+
+    # ---- 2./3. timed regions
+    def timed(sir, h):
+        f = make(h)
+        for k in range(1, args.warmup + 1):
+            f.step(frame(k), k, sir=sir)
+        torch.cuda.synchronize()
+        f.set_timing(True)
+        per = {}
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(args.warmup + 1, args.warmup + args.steps + 1):
+            f.step(frame(k), k, sir=sir)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t_start
+        for name, ms in f.kernel_times():
+            per.setdefault(name, []).append(ms)
+        B = int(f.dump("counts")[0].item()) if not sir else NT
+        passes = int(f.dump("counts")[1].item()) if not sir else 0
+        f.close()
+        return el, per, B, passes
+
+    el_pc, per_pc, B_pc, passes = timed(False, h_match)
+    el_sir, per_sir, _, _ = timed(True, h_match)
+    steps = args.steps
+    value = NT * steps / el_pc
+    sir_value = NT * steps / el_sir
+
+    # per-kernel: sum the launches of each name within one step (sort passes appear several times)
+    def summarise(per):
+        out = {}
+        for name, lst in per.items():
+            out[name] = float(np.sum(lst) / steps)
+        return out
+
+    k_pc, k_sir = summarise(per_pc), summarise(per_sir)
+    bpp = bytes_per_particle("pcsir", D, passes)
+    # dominant kernel of the pcSIR step
+    dom = max(k_pc, key=k_pc.get)
+    if dom in bpp:
+        nb = bpp[dom] * NT * (passes if dom.startswith("sort") else 1)
+        launches = passes if dom.startswith("sort") else 1
+        achieved = nb / (k_pc[dom] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_particle": bpp[dom], "launches_per_step": launches,
+                "avg_ms": round(k_pc[dom] / max(launches, 1), 5)}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None}
+    # all HBM-bound kernels of the step, achieved GB/s each
+    hbm = {}
+    for name, ms in k_pc.items():
+        if name in bpp and ms > 0:
+            mult = passes if name.startswith("sort") else 1
+            if mult == 0:
+                continue
+            hbm[name] = round(bpp[name] * NT * mult / (ms * 1e-3) / 1e9, 1)
+    # SIR likelihood: exp2 per sub-sample; ALU roofline from unit counts
+    P, q = w.patch, w.quad
+    exps = NT * P * P * (q * q if args.lik == 0 else 1) if args.lik == 0 else NT * 2 * P * q
+    lik_ms = k_sir.get("likelihood", float("nan"))
+    sir_lik = {"kernel": "likelihood (SIR)", "bound": "alu", "exp2_per_s": exps / (lik_ms * 1e-3),
+               "ms": lik_ms}
+
+    # ---- 4. CPU baseline: the oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        from paper_1310_5541_amd._lib import Config as _C  # noqa: F401
+        m = int(round(1.0 / h_match))
+        mdl = oracle.Model(dim=dim, m=(m, m, m if dim == 3 else 1), patch=w.patch, quad=w.quad,
+                           psf=1 if dim == 3 else 0, sigma_psf=w.sigma_psf, i_bg=w.i_bg, sigma_xi=w.sigma_xi,
+                           proc_sigma=w.proc_sigma, seed=w.seed + 500)
+        st = synth.initial_particles(w, tr[0], counts)
+        t1 = time.perf_counter()
+        kk = 0
+        ps = 0
+        while time.perf_counter() - t1 < args.cpu_seconds and kk < w.K:
+            kk += 1
+            st, _, _ = oracle.track(mdl, frames_np[kk - 1:kk], counts, st, k0=kk)[0], None, None
+            ps += NT
+        el_cpu = time.perf_counter() - t1
+        cpu = {"value": ps / el_cpu, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"pcSIR h={h_match}: {kk} frames of the full workload (N={NT}), FP64, 1 thread"}
+
+    out = {
+        "metric": "particle-steps/s: SIR vs pcSIR vs surrogate pcSIR at matched tracking RMSE",
+        "value": round(value, 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el_pc / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (normalisation and cumulative weights f64)",
+        "data": "synthetic",
+        "config": {"workload": w.name, "targets": T, "particles": NT, "frame": [w.H, w.W], "patch": w.patch,
+                   "quad": w.quad, "likelihood": "direct" if args.lik == 0 else "separable",
+                   "h_matched": h_match, "bins_at_h": B_pc, "sort_passes": passes},
+        "sir": {"value": round(sir_value, 1), "ms_per_step": round(1e3 * el_sir / steps, 4)},
+        "speedup_pcsir_over_sir": round(value / sir_value, 2),
+        "rmse_px": rmse,
+        "roofline": roof,
+        "hbm_gbs_per_kernel": hbm,
+        "kernel_ms_per_step": {"pcsir": {k: round(v, 5) for k, v in k_pc.items()},
+                               "sir": {k: round(v, 5) for k, v in k_sir.items()}},
+        "sir_likelihood": sir_lik,
+        "cpu_baseline": cpu,
+        "input_generation_s": round(gen_s, 2),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * pcsir.h — C ABI of the MI355X (gfx950) piecewise-constant SIR particle filter.
+ *
+ * The library advances T independent targets, each a set of N_t weighted
+ * particles, through one frame of classical SIR (paper Sec. 3, Algorithm
+ * "SIR") or of piecewise-constant SIR (paper Sec. 4, Algorithm "pcSIR"). The
+ * objects follow the problem statement of Sec. 3: a measurement per time step
+ * (a frame), the dynamics density (nearly-constant velocity, Sec. 5.1), the
+ * likelihood (Gaussian-PSF sum of squared differences, Sec. 5.2, Eq. object
+ * and Eq. likelihood), and a weighted particle set whose posterior mean is
+ * the state estimate.
+ *
+ * Conventions
+ *  - C99, plain pointers and sizes. "_dev" pointers are device (HBM) memory,
+ *    "_host" pointers are host memory. Nothing here allocates device memory:
+ *    the caller provides one workspace of pcsir_workspace_bytes() bytes.
+ *  - Every function returns a pcsir_status; PCSIR_OK is 0, errors are
+ *    negative. A failing call leaves a message in pcsir_last_error(ctx).
+ *  - All device work is enqueued on the stream given to pcsir_init, in call
+ *    order. pcsir_step / sir_step return without synchronising; device-side
+ *    conditions (bin range overflow, non-finite normalisation) are reported
+ *    by the next pcsir_estimate or pcsir_destroy.
+ *  - A context is not thread-safe; separate contexts may run on separate
+ *    streams. Outputs are bit-reproducible for equal inputs (config, initial
+ *    state, frames and frame indices k): no floating-point atomics are used.
+ *  - State layout is SoA: component d of particle i of target t sits at
+ *    [d * sum_N + off_t + i], off_t = n_0 + ... + n_{t-1}. Components are
+ *    (x, y, vx, vy, I0) in 2D and (x, y, z, vx, vy, vz, I0) in 3D; positions
+ *    are in pixels, pixel (c, r) has its centre at integer (c, r), x runs
+ *    along columns and y along rows.
+ */
+#ifndef PCSIR_H
+#define PCSIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCSIR_ABI_VERSION 1
+
+typedef struct pcsir_ctx pcsir_ctx; /* opaque; host memory owned by the library */
+
+typedef enum {
+  PCSIR_OK = 0,
+  PCSIR_E_INVAL = -1,       /* argument or config field out of range, null pointer */
+  PCSIR_E_NOMEM = -2,       /* workspace smaller than pcsir_workspace_bytes() */
+  PCSIR_E_HIP = -3,         /* a HIP runtime call failed (message in pcsir_last_error) */
+  PCSIR_E_STATE = -4,       /* call out of order, or frame size differs from the config */
+  PCSIR_E_NUMERIC = -5,     /* device-side condition: see pcsir_last_error */
+  PCSIR_E_UNSUPPORTED = -6  /* feature not available on this device or build */
+} pcsir_status;
+
+/* How the likelihood of Eq. likelihood is evaluated. Both exact modes compute
+ * the same value (the model image of Eq. object averaged over q x q midpoint
+ * sub-samples per pixel); they differ only in floating-point rounding.
+ *  DIRECT:    one exponential per sub-sample and pixel (P^2 q^2 per evaluation),
+ *             the image-formation simulation written out;
+ *  SEPARABLE: the Gaussian factorises over x and y, so 2 P q exponentials per
+ *             evaluation suffice. */
+typedef enum { PCSIR_LIK_DIRECT = 0, PCSIR_LIK_SEPARABLE = 1 } pcsir_lik_mode;
+
+typedef enum { PCSIR_PSF_GAUSS2D = 0, PCSIR_PSF_ASTIG3D = 1 } pcsir_psf;
+
+/* Dummy particle of a bin (Alg. pcSIR: mean state of the members; Sec. 5.5
+ * also uses the geometric cell centre, "CoC", for the positions). */
+typedef enum { PCSIR_DUMMY_COM = 0, PCSIR_DUMMY_COC = 1 } pcsir_dummy;
+
+typedef struct {
+  uint32_t abi_version;        /* must equal PCSIR_ABI_VERSION */
+  int32_t dim;                 /* spatial dimension: 2 (D = 5) or 3 (D = 7) */
+  int32_t n_targets;           /* T >= 1 */
+  const int64_t *n_particles;  /* host [T], each >= 1; sum < 2^31. Read during pcsir_init only. */
+  int32_t bins_per_px[3];      /* m_x, m_y, m_z in [1, 4096]: cells of edge h = 1/m, edges at
+                                  j/m - 1/2, so every pixel is a union of cells (Sec. 4.2:
+                                  m = 1 is pcSIR-1x1, m = 2 is pcSIR-2x2). m_z used in 3D only. */
+  int32_t patch;               /* P: side of the likelihood window, odd, 1..63 */
+  int32_t quad;                /* q: midpoint sub-samples per pixel axis, 1..16 */
+  int32_t psf;                 /* pcsir_psf; ASTIG3D requires dim == 3 */
+  int32_t dummy_mode;          /* pcsir_dummy */
+  int32_t lik_mode;            /* pcsir_lik_mode */
+  int32_t per_target_frames;   /* 0: one H x W frame for all targets; 1: a [T][H][W] stack */
+  int32_t frame_h, frame_w;    /* H, W >= 1: size of every frame */
+  float sigma_psf;             /* PSF sigma (pixels); 3D: sigma at focus */
+  float astig_gamma, astig_d;  /* 3D: sigma_x = s0 sqrt(1+((z-g)/d)^2), sigma_y = s0 sqrt(1+((z+g)/d)^2) */
+  float i_bg;                  /* background intensity; also the value of pixels outside the frame */
+  float sigma_xi;              /* likelihood width sigma_xi > 0 */
+  float proc_sigma[7];         /* process-noise standard deviation per state component and frame */
+  uint64_t seed;               /* Philox4x64-10 key word 0 */
+} pcsir_config;
+
+/* Bytes of device workspace that a context with this config needs (0 if the
+ * config is invalid). Grows linearly with sum N_t (about 150 B per particle
+ * in 2D) and with T. */
+size_t pcsir_workspace_bytes(const pcsir_config *cfg);
+
+/* Create a context. init_state_dev: SoA [D][sum N] float32, copied into the
+ * workspace (Alg. SIR / Alg. pcSIR initialisation: weights 1/N). workspace_dev:
+ * caller-owned device memory of workspace_bytes bytes, 256-byte aligned, kept
+ * alive and untouched until pcsir_destroy. hip_stream: the hipStream_t all work
+ * goes to (NULL: the legacy default stream). Synchronises the stream once. */
+pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, void *workspace_dev,
+                        size_t workspace_bytes, void *hip_stream, pcsir_ctx **out);
+
+/* One frame of pcSIR (Alg. pcSIR) for every target: propagate, assign to
+ * cells, form one dummy per occupied cell, evaluate the likelihood on the
+ * dummies, copy each dummy's weight to its members, normalise, compute N_eff
+ * and the posterior-mean estimate, and resample (systematic scheme, every
+ * frame). frame_dev: float32 [H][W], or [T][H][W] with per_target_frames;
+ * it must stay valid until the stream has passed this step. k >= 1 is the
+ * frame index; it is part of the random-number counter. Asynchronous. */
+pcsir_status pcsir_step(pcsir_ctx *ctx, const float *frame_dev, int32_t H, int32_t W, int64_t k);
+
+/* One frame of classical SIR (Alg. SIR): as pcsir_step, but the likelihood
+ * is evaluated for every particle. Asynchronous. */
+pcsir_status sir_step(pcsir_ctx *ctx, const float *frame_dev, int32_t H, int32_t W, int64_t k);
+
+/* Copy the estimates of the last step to the host: est_host [T][D] float64
+ * (posterior mean, taken after weighting and before resampling) and, if not
+ * NULL, neff_host [T] float64 (N_eff = 1 / sum w^2). Synchronises the stream.
+ * Returns PCSIR_E_NUMERIC if a device-side condition was raised since the
+ * last call (the flag is then cleared). */
+pcsir_status pcsir_estimate(pcsir_ctx *ctx, double *est_host, double *neff_host);
+
+/* Synchronise the stream and free the host context. The workspace may be
+ * freed by the caller afterwards. Returns the pending device-side status. */
+pcsir_status pcsir_destroy(pcsir_ctx *ctx);
+
+/* Last error message of this context (empty if none). Owned by ctx. */
+const char *pcsir_last_error(const pcsir_ctx *ctx);
+
+/* Current particle set (after the last resampling) into dst_dev, SoA
+ * [D][sum N] float32. Asynchronous. */
+pcsir_status pcsir_get_particles(pcsir_ctx *ctx, float *dst_dev);
+
+/* Replace the particle set by src_dev (SoA [D][sum N] float32), with uniform
+ * weights. Asynchronous. Used to resume from a checkpoint and by tests. */
+pcsir_status pcsir_set_particles(pcsir_ctx *ctx, const float *src_dev);
+
+/* Debug and parity views of the last step, copied into dst_dev (device
+ * memory of at least `bytes` bytes; PCSIR_E_INVAL if too small). Asynchronous
+ * except PCSIR_DUMP_COUNTS, which synchronises. Layouts:
+ *  PROPAGATED  float32 [D][sum N]   propagated states x~_k (before resampling)
+ *  KEYS        int32   [3][sum N]   cell index (kx, ky, kz) of every particle; SIR: pixel index
+ *  COUNTS      int64   [2]          host-visible copy of (bins B over all targets, passes of the sort)
+ *  BIN_TARGET  int32   [B]          target of every bin; bins in ascending (target, kz, ky, kx)
+ *  BIN_KEY     int32   [3][B]       cell index of every bin
+ *  BIN_N       int64   [B]          members per bin
+ *  BIN_MEAN    float64 [D][B]       mean state of the members of every bin (exact sums)
+ *  LOGLIK      float64 [B] (pcSIR) or [sum N] (SIR)  log-likelihood per bin or particle
+ *  WEIGHTS     float64 [sum N]      normalised weights, storage order
+ *  TARGET      float64 [T][4]       per target: max log-weight M, S = sum exp(logw - M),
+ *                                   N_eff, resampling uniform u
+ *  CDF         float64 [sum N]      cumulative weights per target, storage order
+ *  RESAMPLE    int32   [sum N]      s(j): parent of new particle j, index within its target */
+typedef enum {
+  PCSIR_DUMP_PROPAGATED = 0,
+  PCSIR_DUMP_KEYS = 1,
+  PCSIR_DUMP_COUNTS = 2,
+  PCSIR_DUMP_BIN_TARGET = 3,
+  PCSIR_DUMP_BIN_KEY = 4,
+  PCSIR_DUMP_BIN_N = 5,
+  PCSIR_DUMP_BIN_MEAN = 6,
+  PCSIR_DUMP_LOGLIK = 7,
+  PCSIR_DUMP_WEIGHTS = 8,
+  PCSIR_DUMP_TARGET = 9,
+  PCSIR_DUMP_CDF = 10,
+  PCSIR_DUMP_RESAMPLE = 11
+} pcsir_dump;
+
+pcsir_status pcsir_debug_dump(pcsir_ctx *ctx, int32_t what, void *dst_dev, size_t bytes);
+
+/* Keep the per-particle cumulative weights of later steps for
+ * PCSIR_DUMP_CDF (on != 0). Off by default: it adds 8 bytes of HBM writes per
+ * particle and step. */
+pcsir_status pcsir_set_debug(pcsir_ctx *ctx, int32_t on);
+
+/* Per-kernel times, in milliseconds, of every launch since timing was turned
+ * on (pcsir_set_timing) or since the previous pcsir_kernel_times call, taken
+ * with HIP events recorded on the context's stream between the launches (up
+ * to 8191 launches are kept). names/ms: host arrays of capacity `cap`; the
+ * number of entries written goes to *count. Synchronises and clears the log. */
+pcsir_status pcsir_set_timing(pcsir_ctx *ctx, int32_t on);
+pcsir_status pcsir_kernel_times(pcsir_ctx *ctx, const char **names, float *ms, int32_t cap, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCSIR_H */

@@ -1,0 +1,9 @@
+"""MI355X-native piecewise-constant SIR particle filter (gfx950 HIP kernels behind a C ABI).
+
+The filter step (propagate, bin, dummy, likelihood, weight copy, normalise,
+resample) runs entirely in ``libpcsir.so``. This package is argument
+marshalling only: torch supplies device memory and the stream.
+"""
+from ._lib import (  # noqa: F401
+    DUMP, Config, Filter, LibraryMissing, PcsirError, lib, lib_path,
+)

@@ -1,0 +1,280 @@
+"""ctypes binding of ``libpcsir.so`` (the C ABI declared in include/pcsir.h).
+
+Names follow the C ABI. Device memory comes from torch (``torch.empty`` on the
+current CUDA/HIP device) and work goes to torch's current stream; every step of
+the filter runs in the library's kernels. If the library is not built the
+binding raises :class:`LibraryMissing`: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libpcsir.so")
+
+ABI_VERSION = 1
+
+DUMP = dict(propagated=0, keys=1, counts=2, bin_target=3, bin_key=4, bin_n=5, bin_mean=6, loglik=7,
+            weights=8, target=9, cdf=10, resample=11)
+
+_STATUS = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP", -4: "E_STATE", -5: "E_NUMERIC",
+           -6: "E_UNSUPPORTED"}
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class PcsirError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pcsir {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Cfg(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("dim", C.c_int32), ("n_targets", C.c_int32),
+        ("n_particles", C.POINTER(C.c_int64)), ("bins_per_px", C.c_int32 * 3), ("patch", C.c_int32),
+        ("quad", C.c_int32), ("psf", C.c_int32), ("dummy_mode", C.c_int32), ("lik_mode", C.c_int32),
+        ("per_target_frames", C.c_int32), ("frame_h", C.c_int32), ("frame_w", C.c_int32),
+        ("sigma_psf", C.c_float), ("astig_gamma", C.c_float), ("astig_d", C.c_float), ("i_bg", C.c_float),
+        ("sigma_xi", C.c_float), ("proc_sigma", C.c_float * 7), ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def lib():
+    """Load libpcsir.so (built by ``__graft_entry__.build()``); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        raise LibraryMissing(f"{_LIB} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = C.CDLL(_LIB)
+    vp, i32, i64, u64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
+    L.pcsir_workspace_bytes.argtypes = [C.POINTER(_Cfg)]
+    L.pcsir_workspace_bytes.restype = sz
+    L.pcsir_init.argtypes = [C.POINTER(_Cfg), vp, vp, sz, vp, C.POINTER(vp)]
+    L.pcsir_step.argtypes = [vp, vp, i32, i32, i64]
+    L.sir_step.argtypes = [vp, vp, i32, i32, i64]
+    L.pcsir_estimate.argtypes = [vp, vp, vp]
+    L.pcsir_destroy.argtypes = [vp]
+    L.pcsir_last_error.argtypes = [vp]
+    L.pcsir_last_error.restype = C.c_char_p
+    L.pcsir_get_particles.argtypes = [vp, vp]
+    L.pcsir_set_particles.argtypes = [vp, vp]
+    L.pcsir_debug_dump.argtypes = [vp, i32, vp, sz]
+    L.pcsir_set_debug.argtypes = [vp, i32]
+    L.pcsir_set_timing.argtypes = [vp, i32]
+    L.pcsir_kernel_times.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(C.c_float), i32, C.POINTER(i32)]
+    for f in ("pcsir_init", "pcsir_step", "sir_step", "pcsir_estimate", "pcsir_destroy", "pcsir_get_particles",
+              "pcsir_set_particles", "pcsir_debug_dump", "pcsir_set_debug", "pcsir_set_timing",
+              "pcsir_kernel_times"):
+        getattr(L, f).restype = i32
+    _lib = L
+    return L
+
+
+@dataclass
+class Config:
+    """Python mirror of ``pcsir_config`` (include/pcsir.h)."""
+    n_particles: tuple
+    dim: int = 2
+    bins_per_px: tuple = (2, 2, 1)
+    patch: int = 11
+    quad: int = 2
+    psf: int = 0
+    dummy_mode: int = 0
+    lik_mode: int = 0          # 0 DIRECT, 1 SEPARABLE
+    per_target_frames: bool = False
+    frame_h: int = 64
+    frame_w: int = 64
+    sigma_psf: float = 1.5
+    astig_gamma: float = 2.0
+    astig_d: float = 4.0
+    i_bg: float = 10.0
+    sigma_xi: float = 10.0
+    proc_sigma: tuple = (0.5, 0.5, 0.1, 0.1, 2.0)
+    seed: int = 1
+
+    @property
+    def D(self) -> int:
+        return 2 * self.dim + 1
+
+    @property
+    def T(self) -> int:
+        return len(self.n_particles)
+
+    @property
+    def NT(self) -> int:
+        return int(np.sum(np.asarray(self.n_particles, dtype=np.int64)))
+
+    def _c(self):
+        n = np.ascontiguousarray(np.asarray(self.n_particles, dtype=np.int64))
+        c = _Cfg()
+        c.abi_version = ABI_VERSION
+        c.dim = self.dim
+        c.n_targets = int(n.shape[0])
+        c.n_particles = n.ctypes.data_as(C.POINTER(C.c_int64))
+        m = list(self.bins_per_px) + [1] * (3 - len(self.bins_per_px))
+        for a in range(3):
+            c.bins_per_px[a] = int(m[a])
+        c.patch, c.quad, c.psf, c.dummy_mode, c.lik_mode = self.patch, self.quad, self.psf, self.dummy_mode, self.lik_mode
+        c.per_target_frames = 1 if self.per_target_frames else 0
+        c.frame_h, c.frame_w = self.frame_h, self.frame_w
+        c.sigma_psf, c.astig_gamma, c.astig_d = self.sigma_psf, self.astig_gamma, self.astig_d
+        c.i_bg, c.sigma_xi = self.i_bg, self.sigma_xi
+        ps = list(self.proc_sigma) + [0.0] * (7 - len(self.proc_sigma))
+        for d in range(7):
+            c.proc_sigma[d] = float(ps[d])
+        c.seed = int(self.seed) & (2**64 - 1)
+        return c, n  # keep n alive while c is used
+
+    @classmethod
+    def from_workload(cls, w, **kw) -> "Config":
+        """Config for a ``synth.Workload`` (sizes and model constants only)."""
+        base = dict(n_particles=tuple(int(v) for v in w.counts()), dim=w.dim, bins_per_px=tuple(w.m),
+                    patch=w.patch, quad=w.quad, psf=1 if w.dim == 3 else 0, frame_h=w.H, frame_w=w.W,
+                    per_target_frames=w.per_target_frames, sigma_psf=w.sigma_psf, astig_gamma=w.astig_gamma,
+                    astig_d=w.astig_d, i_bg=w.i_bg, sigma_xi=w.sigma_xi, proc_sigma=tuple(w.proc_sigma))
+        base.update(kw)
+        return cls(**base)
+
+
+class Filter:
+    """One library context: T targets advanced by pcsir_step / sir_step."""
+
+    def __init__(self, cfg: Config, init_state, stream=None):
+        import torch
+        self._torch = torch
+        L = lib()
+        self.cfg = cfg
+        c, self._n = cfg._c()
+        nbytes = L.pcsir_workspace_bytes(C.byref(c))
+        if nbytes == 0:
+            raise PcsirError(-1, "invalid config")
+        assert init_state.is_cuda and init_state.dtype == torch.float32
+        assert tuple(init_state.shape) == (cfg.D, cfg.NT), (tuple(init_state.shape), (cfg.D, cfg.NT))
+        self.device = init_state.device
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        init = init_state.contiguous()
+        ctx = C.c_void_p()
+        st = L.pcsir_init(C.byref(c), C.c_void_p(init.data_ptr()), C.c_void_p(self.workspace.data_ptr()),
+                          nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if st != 0:
+            raise PcsirError(st, "pcsir_init failed (see stderr)")
+        self._ctx = ctx
+        self.workspace_bytes = int(nbytes)
+
+    # -- helpers
+    def _check(self, st: int):
+        if st != 0:
+            msg = lib().pcsir_last_error(self._ctx)
+            raise PcsirError(st, msg.decode() if msg else "")
+
+    def _frame(self, frame):
+        t = self._torch
+        assert frame.is_cuda and frame.dtype == t.float32 and frame.is_contiguous()
+        H, W = self.cfg.frame_h, self.cfg.frame_w
+        want = (self.cfg.T, H, W) if self.cfg.per_target_frames else (H, W)
+        assert tuple(frame.shape) == want, (tuple(frame.shape), want)
+        return C.c_void_p(frame.data_ptr()), H, W
+
+    # -- C ABI
+    def pcsir_step(self, frame, k: int):
+        fp, H, W = self._frame(frame)
+        self._check(lib().pcsir_step(self._ctx, fp, H, W, int(k)))
+
+    def sir_step(self, frame, k: int):
+        fp, H, W = self._frame(frame)
+        self._check(lib().sir_step(self._ctx, fp, H, W, int(k)))
+
+    def step(self, frame, k: int, sir: bool = False):
+        (self.sir_step if sir else self.pcsir_step)(frame, k)
+
+    def pcsir_estimate(self):
+        T, D = self.cfg.T, self.cfg.D
+        est = np.zeros((T, D), np.float64)
+        neff = np.zeros(T, np.float64)
+        self._check(lib().pcsir_estimate(self._ctx, est.ctypes.data_as(C.c_void_p), neff.ctypes.data_as(C.c_void_p)))
+        return est, neff
+
+    estimate = pcsir_estimate
+
+    def get_particles(self):
+        out = self._torch.empty((self.cfg.D, self.cfg.NT), dtype=self._torch.float32, device=self.device)
+        self._check(lib().pcsir_get_particles(self._ctx, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_particles(self, state):
+        s = state.contiguous()
+        assert tuple(s.shape) == (self.cfg.D, self.cfg.NT) and s.dtype == self._torch.float32 and s.is_cuda
+        self._check(lib().pcsir_set_particles(self._ctx, C.c_void_p(s.data_ptr())))
+        self._hold = s
+
+    def set_debug(self, on: bool = True):
+        self._check(lib().pcsir_set_debug(self._ctx, 1 if on else 0))
+
+    def dump(self, what: str):
+        """Debug / parity view of the last step as a torch tensor (see PCSIR_DUMP_* in pcsir.h)."""
+        t = self._torch
+        NT, T, D = self.cfg.NT, self.cfg.T, self.cfg.D
+        if what in ("bin_target", "bin_key", "bin_n", "bin_mean", "loglik"):
+            B = int(self.dump("counts")[0].item())
+        shapes = dict(propagated=((D, NT), t.float32), keys=((3, NT), t.int32), counts=((2,), t.int64),
+                      weights=((NT,), t.float64), target=((T, 4), t.float64), cdf=((NT,), t.float64),
+                      resample=((NT,), t.int32))
+        if what in shapes:
+            shape, dt = shapes[what]
+        elif what == "bin_target":
+            shape, dt = (B,), t.int32
+        elif what == "bin_key":
+            shape, dt = (3, B), t.int32
+        elif what == "bin_n":
+            shape, dt = (B,), t.int64
+        elif what == "bin_mean":
+            shape, dt = (D, B), t.float64
+        elif what == "loglik":
+            shape, dt = (B,), t.float64
+        else:
+            raise KeyError(what)
+        out = t.zeros(shape, dtype=dt, device=self.device)
+        nbytes = out.numel() * out.element_size()
+        self._check(lib().pcsir_debug_dump(self._ctx, DUMP[what], C.c_void_p(out.data_ptr()), max(nbytes, 1)))
+        self.stream.synchronize()
+        return out
+
+    def set_timing(self, on: bool = True):
+        self._check(lib().pcsir_set_timing(self._ctx, 1 if on else 0))
+
+    def kernel_times(self):
+        cap = 8192
+        names = (C.c_char_p * cap)()
+        ms = (C.c_float * cap)()
+        n = C.c_int32()
+        self._check(lib().pcsir_kernel_times(self._ctx, names, ms, cap, C.byref(n)))
+        return [(names[i].decode(), float(ms[i])) for i in range(n.value)]
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            st = lib().pcsir_destroy(self._ctx)
+            self._ctx = None
+            if st not in (0, -5):
+                raise PcsirError(st, "pcsir_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,274 @@
+// Device helpers for the gfx950 pcSIR kernels: counter-based RNG, exact cell
+// index, wave64 reductions and scans. Wave size is 64 on CDNA; every helper
+// here assumes it.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcsir {
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- Philox4x64-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds of two
+// 64x64->128 products (multipliers 0xD2E7470EE14C6C93, 0xCA5A826395121157)
+// with a Weyl key schedule (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B).
+struct U64x4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t lo0 = c0 * M0, hi0 = __umul64hi(c0, M0);
+    const uint64_t lo1 = c2 * M1, hi1 = __umul64hi(c2, M1);
+    const uint64_t n0 = hi1 ^ c1 ^ k0;
+    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  U64x4 o;
+  o.v[0] = c0;
+  o.v[1] = c1;
+  o.v[2] = c2;
+  o.v[3] = c3;
+  return o;
+}
+
+// Two uniforms on (0,1) from one word: 23-bit fields at bits 41..63 and
+// 9..31, plus one half, times 2^-23. Both are exact in binary32.
+__device__ __forceinline__ float u01_hi(uint64_t w) {
+  return ((float)(uint32_t)(w >> 41) + 0.5f) * 0x1p-23f;
+}
+__device__ __forceinline__ float u01_lo(uint64_t w) {
+  return ((float)((uint32_t)(w >> 9) & 0x7FFFFFu) + 0.5f) * 0x1p-23f;
+}
+
+// Eight N(0,1) draws (binary32 Box-Muller) for counter (i, k, t, 0), key (seed, 0).
+__device__ __forceinline__ void normals8(uint64_t seed, uint64_t i, uint64_t k, uint64_t t, float z[8]) {
+  const U64x4 b = philox4x64_10(i, k, t, 0, seed, 0);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const float u1 = u01_hi(b.v[p]);
+    const float u2 = u01_lo(b.v[p]);
+    const float r = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    z[2 * p] = r * c;
+    z[2 * p + 1] = r * s;
+  }
+}
+
+// Resampling uniform of target t at frame k: counter (0, k, t, 1), word 0,
+// (w >> 11) * 2^-53 in [0, 1).
+__device__ __forceinline__ double resample_uniform(uint64_t seed, uint64_t k, uint64_t t) {
+  const U64x4 b = philox4x64_10(0, k, t, 1, seed, 0);
+  return (double)(b.v[0] >> 11) * 0x1p-53;
+}
+
+// ---------------------------------------------------------------- exact cell index
+// floor((x + 1/2) * m) of the binary32 value x, computed exactly in integer
+// arithmetic from its sign, significand and exponent. x is clamped to
+// [-2^24, 2^24] (NaN -> 2^24), the result to [-2^30, 2^30]; 1 <= m <= 4096.
+__device__ __forceinline__ int32_t cell_index(float xf, int32_t m) {
+  uint32_t b = __float_as_uint(xf);
+  if (((b >> 23) & 0xFFu) == 0xFFu) {  // Inf or NaN
+    b = (b & 0x7FFFFFu) ? 0x4B800000u : ((b & 0x80000000u) | 0x4B800000u);  // NaN -> +2^24, Inf -> +-2^24
+  }
+  const uint32_t mag = b & 0x7FFFFFFFu;
+  if (mag > 0x4B800000u) b = (b & 0x80000000u) | 0x4B800000u;  // |x| > 2^24 -> +-2^24
+  const bool neg = (b >> 31) != 0;
+  const uint32_t ex = (b >> 23) & 0xFFu;
+  const int64_t half_m = (int64_t)(m >> 1);
+  const int64_t tiny = half_m - (((m & 1) == 0 && neg && (b & 0x7FFFFFFFu)) ? 1 : 0);
+  int64_t k;
+  if (ex == 0) {
+    k = tiny;  // zero or subnormal: |x m| < 1/2
+  } else {
+    const int64_t M = (int64_t)((b & 0x7FFFFFu) | 0x800000u);  // |x| = M 2^E
+    const int E = (int)ex - 150;
+    if (E >= -1) {
+      // 2x + 1 is an integer: (2x + 1) m / 2, floor by arithmetic shift
+      int64_t twox = M << (E + 1);
+      if (neg) twox = -twox;
+      k = ((twox + 1) * (int64_t)m) >> 1;
+    } else if (E >= -40) {
+      // (x + 1/2) m = (+-M + 2^q) m / 2^(q+1), q = -(E+1) in [1, 39]
+      const int q = -(E + 1);
+      const int64_t num = (neg ? -M : M) + ((int64_t)1 << q);
+      k = (num * (int64_t)m) >> (q + 1);
+    } else {
+      k = tiny;  // |x| < 2^-17: |x m| < 2^-5
+    }
+  }
+  const int64_t LIM = (int64_t)1 << 30;
+  k = k > LIM ? LIM : (k < -LIM ? -LIM : k);
+  return (int32_t)k;
+}
+
+__device__ __forceinline__ int32_t floor_div(int32_t a, int32_t m) {
+  int32_t q = a / m;
+  if ((a % m) != 0 && (a < 0)) q -= 1;
+  return q;
+}
+
+// ---------------------------------------------------------------- wave / block primitives
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / WAVE); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    T y = __shfl_xor(v, o, WAVE);
+    v = y > v ? y : v;
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    T y = __shfl_xor(v, o, WAVE);
+    v = y < v ? y : v;
+  }
+  return v;
+}
+
+// Inclusive wave scan (Kogge-Stone over shfl_up).
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    T y = __shfl_up(v, o, WAVE);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_incl_max_scan(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    T y = __shfl_up(v, o, WAVE);
+    if (lane >= o) v = y > v ? y : v;
+  }
+  return v;
+}
+
+// Compensated wave reduction that keeps the result as an unevaluated pair
+// (hi, lo), returned in FP64 registers of every lane.
+__device__ __forceinline__ void wave_sum_pair(float s, float e, double &hi, double &lo) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const float s2 = __shfl_xor(s, o, WAVE);
+    const float e2 = __shfl_xor(e, o, WAVE);
+    const float t = s + s2;
+    const float bp = t - s;
+    const float err = (s - (t - bp)) + (s2 - bp);
+    s = t;
+    e = e + e2 + err;
+  }
+  hi = (double)s;
+  lo = (double)e;
+}
+
+// Block (NT threads) reduction helpers using a small LDS scratch.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T *lds) {
+  v = wave_sum(v);
+  if (lane_id() == 0) lds[wave_id()] = v;
+  __syncthreads();
+  T r = lds[0];
+#pragma unroll
+  for (int w = 1; w < NT / WAVE; ++w) r += lds[w];
+  __syncthreads();
+  return r;
+}
+template <int NT, typename T>
+__device__ __forceinline__ T block_max(T v, T *lds) {
+  v = wave_max(v);
+  if (lane_id() == 0) lds[wave_id()] = v;
+  __syncthreads();
+  T r = lds[0];
+#pragma unroll
+  for (int w = 1; w < NT / WAVE; ++w) r = lds[w] > r ? lds[w] : r;
+  __syncthreads();
+  return r;
+}
+template <int NT, typename T>
+__device__ __forceinline__ T block_min(T v, T *lds) {
+  v = wave_min(v);
+  if (lane_id() == 0) lds[wave_id()] = v;
+  __syncthreads();
+  T r = lds[0];
+#pragma unroll
+  for (int w = 1; w < NT / WAVE; ++w) r = lds[w] < r ? lds[w] : r;
+  __syncthreads();
+  return r;
+}
+
+// Exclusive block scan of integers; *total receives the block sum.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *lds, T *total) {
+  const int lane = lane_id(), w = wave_id();
+  const T incl = wave_incl_scan(v);
+  if (lane == WAVE - 1) lds[w] = incl;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / WAVE; ++i) {
+    if (i < w) pre += lds[i];
+    tot += lds[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + incl - v;
+}
+
+// Exclusive block scan of non-negative doubles whose results are forced to be
+// non-decreasing in thread order (a running maximum after the sum scan), so
+// that boundaries derived from them never cross. *total is the block sum.
+template <int NT>
+__device__ __forceinline__ double block_excl_scan_monotone(double v, double *lds, double *total) {
+  const int lane = lane_id(), w = wave_id();
+  const double incl = wave_incl_scan(v);
+  double ex = __shfl_up(incl, 1, WAVE);
+  if (lane == 0) ex = 0.0;
+  if (lane == WAVE - 1) lds[w] = incl;
+  __syncthreads();
+  double pre = 0.0, tot = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / WAVE; ++i) {
+    if (i < w) pre += lds[i];
+    tot += lds[i];
+  }
+  __syncthreads();
+  double r = pre + ex;
+  r = wave_incl_max_scan(r);
+  // running maximum across waves: last lane of each earlier wave
+  if (lane == WAVE - 1) lds[w] = r;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NT / WAVE; ++i)
+    if (i < w) r = lds[i] > r ? lds[i] : r;
+  __syncthreads();
+  *total = tot;
+  return r;
+}
+
+}  // namespace pcsir

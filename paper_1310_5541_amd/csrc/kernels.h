@@ -1,0 +1,1072 @@
+// gfx950 kernels of one SIR / pcSIR frame. Particles are SoA float32 in HBM,
+// one thread per particle for the streaming stages, one wave64 per likelihood
+// evaluation, LSD radix sort on the compacted cell key for the binning.
+#pragma once
+#include "device_util.h"
+
+namespace pcsir {
+
+constexpr int TPB = 256;            // threads per block of the streaming kernels
+constexpr int SORT_ITEMS = 16;      // most keys per thread in the radix sort (chosen per size)
+constexpr int SEG_ITEMS = 4;        // rounds of 64 sorted slots per wave in the segmented reduction
+constexpr int SEG_CHUNK = TPB * SEG_ITEMS;
+constexpr int SCAN_ITEMS = 4;       // particles per thread in the weight scan
+constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+constexpr int LIK_WAVES = 4;        // likelihood evaluations per block (one per wave)
+
+// Fixed-point scales of the bin sums (integer sums are exact and order-free).
+constexpr float FX_POS = 4294967296.0f;  // 2^32: offsets from the cell's pixel, |d| <= 1/2
+constexpr float FX_VEL = 16777216.0f;    // 2^24: velocities, |v| < 2^7
+constexpr float FX_INT = 1048576.0f;     // 2^20: intensity, |I| < 2^15
+constexpr float LIM_VEL = 128.0f;
+constexpr float LIM_INT = 32768.0f;
+
+// Device-side status bits (meta[META_ERR]).
+constexpr uint64_t ERR_KEY_RANGE = 1;    // compacted cell range of all targets >= 2^32
+constexpr uint64_t ERR_FIXED_SAT = 2;    // a velocity or intensity outside the fixed-point range
+constexpr uint64_t ERR_NONFINITE = 4;    // a target's normalisation was not finite
+
+enum { META_PASSES = 0, META_RANGE = 1, META_B = 2, META_ERR = 3, META_N = 8 };
+
+struct Params {
+  int dim, D, T;
+  uint32_t NT;
+  int m[3];
+  int P, R, q;
+  int psf, dummy_mode, per_target_frames, H, W;
+  float sigma_psf, astig_gamma, astig_d, i_bg;
+  double inv2sxi2;  // 1 / (2 sigma_xi^2)
+  float proc_sigma[7];
+  uint64_t seed;
+  const int32_t *bbox_cur;  // [T][6] (x0, y0, z0, wx, wy, wz) of the current frame's cells
+};
+
+struct Tile {
+  int32_t t;   // target
+  uint32_t i0; // first particle of the tile, index within the target
+};
+
+// ---------------------------------------------------------------- propagation
+// Alg. SIR / Alg. pcSIR "draw a sample from pi": bootstrap proposal with the
+// nearly-constant-velocity dynamics of Sec. 5.1. The gather x_j <- x~_{s(j)}
+// of the previous frame's resampling is fused into the load. With KEYS, the
+// exact cell indices of the new positions are reduced to a per-target
+// bounding box (integer atomics).
+template <int DIM, bool KEYS>
+__global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restrict__ tiles,
+                                                   const uint32_t *__restrict__ off, const float *__restrict__ sin,
+                                                   float *__restrict__ sout, const uint32_t *__restrict__ anc,
+                                                   int pending, int64_t k, int32_t *__restrict__ bbox_part) {
+  constexpr int D = 2 * DIM + 1;
+  __shared__ int32_t red[TPB / WAVE];
+  const Tile tl = tiles[blockIdx.x];
+  const int t = tl.t;
+  const uint32_t base = off[t];
+  const uint32_t n = off[t + 1] - base;
+  const uint32_t i = tl.i0 + threadIdx.x;
+  const bool valid = i < n;
+  int32_t kmin[DIM], kmax[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    kmin[a] = 0x7FFFFFFF;
+    kmax[a] = -0x7FFFFFFF - 1;
+  }
+  if (valid) {
+    const uint32_t g = base + i;
+    const uint32_t src = pending ? base + min(anc[g], n - 1) : g;
+    float x[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[d] = sin[(size_t)d * p.NT + src];
+    float z[8];
+    normals8(p.seed, i, (uint64_t)k, (uint64_t)t, z);
+    float nx[D];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) nx[a] = fmaf(p.proc_sigma[a], z[a], x[a] + x[DIM + a]);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) nx[DIM + a] = fmaf(p.proc_sigma[DIM + a], z[DIM + a], x[DIM + a]);
+    nx[2 * DIM] = fmaf(p.proc_sigma[2 * DIM], z[2 * DIM], x[2 * DIM]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) sout[(size_t)d * p.NT + g] = nx[d];
+    if (KEYS) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const int32_t c = cell_index(nx[a], p.m[a]);
+        kmin[a] = c;
+        kmax[a] = c;
+      }
+    }
+  }
+  if (KEYS) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const int32_t lo = block_min<TPB>(kmin[a], red);
+      const int32_t hi = block_max<TPB>(kmax[a], red);
+      if (threadIdx.x == 0) {
+        bbox_part[(size_t)blockIdx.x * 6 + a] = lo;
+        bbox_part[(size_t)blockIdx.x * 6 + 3 + a] = hi;
+      }
+    }
+  }
+}
+
+// Per-target cell range from the propagate tiles' partial bounding boxes
+// (tiles of target t: t256_first[t] .. t256_first[t+1]-1). One block per target.
+__global__ __launch_bounds__(TPB) void k_bbox_reduce(int dim, const uint32_t *__restrict__ t256_first,
+                                                     const int32_t *__restrict__ bbox_part,
+                                                     int32_t *__restrict__ bbox_cur,
+                                                     unsigned long long *__restrict__ range) {
+  __shared__ int32_t red[TPB / WAVE];
+  const int t = blockIdx.x;
+  const uint32_t a0 = t256_first[t], a1 = t256_first[t + 1];
+  unsigned long long r = 1;
+  for (int a = 0; a < 3; ++a) {
+    int32_t lo = 0, wdt = 1;
+    if (a < dim) {
+      int32_t mn = 0x7FFFFFFF, mx = -0x7FFFFFFF - 1;
+      for (uint32_t b = a0 + threadIdx.x; b < a1; b += TPB) {
+        mn = min(mn, bbox_part[(size_t)b * 6 + a]);
+        mx = max(mx, bbox_part[(size_t)b * 6 + 3 + a]);
+      }
+      lo = block_min<TPB>(mn, red);
+      const int32_t hi = block_max<TPB>(mx, red);
+      long long w64 = (long long)hi - (long long)lo + 1;
+      w64 = w64 < 1 ? 1 : (w64 > 0x7FFFFFFFLL ? 0x7FFFFFFFLL : w64);  // flagged by the scan if too wide
+      wdt = (int32_t)w64;
+    }
+    if (threadIdx.x == 0) {
+      bbox_cur[t * 6 + a] = lo;
+      bbox_cur[t * 6 + 3 + a] = wdt;
+    }
+    r *= (unsigned long long)(uint32_t)wdt;
+    if (r > (1ull << 40)) r = (1ull << 40);
+  }
+  if (threadIdx.x == 0) range[t] = r;
+}
+
+// Exclusive scan of the per-target cell ranges -> compacted key bases, the
+// total range and the number of 8-bit sort passes it needs. One block.
+__global__ __launch_bounds__(TPB) void k_bbox_scan(int T, const unsigned long long *__restrict__ range,
+                                                   uint32_t *__restrict__ kbase, uint64_t *__restrict__ meta) {
+  __shared__ unsigned long long lds[TPB / WAVE];
+  unsigned long long carry = 0;
+  for (int t0 = 0; t0 < T; t0 += TPB) {
+    const int t = t0 + threadIdx.x;
+    const unsigned long long r = t < T ? range[t] : 0ull;
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan<TPB, unsigned long long>(r, lds, &tot);
+    if (t < T) kbase[t] = (uint32_t)(carry + ex);
+    carry += tot;
+    if (carry > (1ull << 40)) carry = (1ull << 40);
+  }
+  if (threadIdx.x == 0) {
+    kbase[T] = (uint32_t)carry;
+    meta[META_RANGE] = carry;
+    int bits = 0;
+    if (carry > 1) bits = 64 - __clzll((long long)(carry - 1));
+    int passes = (bits + 7) / 8;
+    if (carry > 0xFFFFFFFFull) {
+      meta[META_ERR] |= ERR_KEY_RANGE;
+      passes = 4;
+    }
+    meta[META_PASSES] = (uint64_t)passes;
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ uint32_t compact_key(const int32_t *c, const int32_t *bb, uint32_t kb) {
+  // key = base + ((kz - z0) * wy + (ky - y0)) * wx + (kx - x0): ascending (kz, ky, kx)
+  uint32_t l = 0;
+  if (DIM == 3) l = (uint32_t)(c[2] - bb[2]);
+  l = l * (uint32_t)bb[4] + (uint32_t)(c[1] - bb[1]);
+  l = l * (uint32_t)bb[3] + (uint32_t)(c[0] - bb[0]);
+  return kb + l;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(TPB) void k_keys(Params p, const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
+                                              const float *__restrict__ s, const int32_t *__restrict__ bbox_cur,
+                                              const uint32_t *__restrict__ kbase, uint32_t *__restrict__ key) {
+  const Tile tl = tiles[blockIdx.x];
+  const int t = tl.t;
+  const uint32_t base = off[t];
+  const uint32_t i = tl.i0 + threadIdx.x;
+  if (i >= off[t + 1] - base) return;
+  const uint32_t g = base + i;
+  int32_t c[3];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) c[a] = cell_index(s[(size_t)a * p.NT + g], p.m[a]);
+  int32_t bb[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) bb[a] = bbox_cur[t * 6 + a];
+  key[g] = compact_key<DIM>(c, bb, kbase[t]);
+}
+
+// ---------------------------------------------------------------- LSD radix sort
+// Stable sort of (key, index) by 8-bit digits; pass `pass` runs only if the
+// key range computed on the device needs it. Pass 0 reads the keys in
+// storage order with implicit indices 0..NT-1.
+// Lanes of the wave holding the same 8-bit digit d (invalid lanes: d = 256).
+__device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d) {
+  unsigned long long peers = __ballot(valid);
+  if (!valid) peers = ~peers;
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const unsigned long long bb = __ballot((d >> bit) & 1u);
+    peers &= ((d >> bit) & 1u) ? bb : ~bb;
+  }
+  return peers;
+}
+
+__global__ __launch_bounds__(TPB) void k_sort_hist(int pass, uint32_t NT, int items, const uint32_t *__restrict__ key,
+                                                   uint32_t *__restrict__ hist, uint32_t G,
+                                                   const uint64_t *__restrict__ meta) {
+  if ((uint64_t)pass >= meta[META_PASSES]) return;
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t b0 = blockIdx.x * (uint32_t)(items * TPB);
+  const int sh = 8 * pass;
+  const unsigned long long below = (1ull << lane_id()) - 1ull;
+  for (int it = 0; it < items; ++it) {
+    const uint32_t j = b0 + it * TPB + threadIdx.x;
+    const bool valid = j < NT;
+    const uint32_t d = valid ? (key[j] >> sh) & 255u : 256u;
+    const unsigned long long peers = digit_peers(valid, d);
+    if (valid && (peers & below) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * G + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of that digit's per-block counts.
+__global__ __launch_bounds__(TPB) void k_sort_scan(int pass, uint32_t *__restrict__ hist, uint32_t G,
+                                                   uint32_t *__restrict__ digit_total,
+                                                   const uint64_t *__restrict__ meta) {
+  if ((uint64_t)pass >= meta[META_PASSES]) return;
+  __shared__ uint32_t lds[TPB / WAVE];
+  uint32_t *h = hist + (size_t)blockIdx.x * G;
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < G; b0 += TPB) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t v = b < G ? h[b] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<TPB, uint32_t>(v, lds, &tot);
+    if (b < G) h[b] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int items, const uint32_t *__restrict__ key_in,
+                                                      const uint32_t *__restrict__ val_in,
+                                                      uint32_t *__restrict__ key_out, uint32_t *__restrict__ val_out,
+                                                      const uint32_t *__restrict__ hist, uint32_t G,
+                                                      const uint32_t *__restrict__ digit_total,
+                                                      const uint64_t *__restrict__ meta) {
+  if ((uint64_t)pass >= meta[META_PASSES]) return;
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[TPB / WAVE][257];
+  __shared__ uint32_t lds[TPB / WAVE];
+  const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+  {
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<TPB, uint32_t>(digit_total[tid], lds, &tot);
+    run[tid] = ex + hist[(size_t)tid * G + blockIdx.x];
+  }
+  for (int i = tid; i < (TPB / WAVE) * 257; i += TPB) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t b0 = blockIdx.x * (uint32_t)(items * TPB);
+  const int sh = 8 * pass;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int it = 0; it < items; ++it) {
+    const uint32_t j = b0 + it * TPB + tid;
+    const bool valid = j < NT;
+    uint32_t kk = 0, vv = 0, d = 256;
+    if (valid) {
+      kk = key_in[j];
+      vv = val_in ? val_in[j] : j;
+      d = (kk >> sh) & 255u;
+    }
+    const unsigned long long peers = digit_peers(valid, d);
+    const uint32_t rank = (uint32_t)__popcll(peers & below);
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = run[d] + rank;
+      for (int ww = 0; ww < w; ++ww) pre += wcnt[ww][d];
+      key_out[pre] = kk;
+      val_out[pre] = vv;
+    }
+    __syncthreads();
+    {
+      uint32_t add = 0;
+#pragma unroll
+      for (int ww = 0; ww < TPB / WAVE; ++ww) {
+        add += wcnt[ww][tid];
+        wcnt[ww][tid] = 0;
+      }
+      run[tid] += add;
+    }
+    __syncthreads();
+  }
+}
+
+// Sorted buffers chosen on the device from the number of passes that ran.
+struct SortBufs {
+  const uint32_t *key_store;  // storage order (0 passes)
+  const uint32_t *kA, *vA, *kB, *vB;
+};
+__device__ __forceinline__ void sorted_arrays(const SortBufs &sb, uint64_t passes, const uint32_t *&K,
+                                              const uint32_t *&V) {
+  if (passes == 0) {
+    K = sb.key_store;
+    V = nullptr;
+  } else if (passes & 1) {
+    K = sb.kB;
+    V = sb.vB;
+  } else {
+    K = sb.kA;
+    V = sb.vA;
+  }
+}
+
+// ---------------------------------------------------------------- segments (bins)
+// Sorted slots are processed in rounds of 64 consecutive slots per wave; a
+// block of 4 waves covers SEG_CHUNK slots. A bin is a run of equal keys.
+__device__ __forceinline__ bool seg_head(const uint32_t *__restrict__ K, uint32_t j) {
+  return j == 0 || K[j] != K[j - 1];
+}
+
+__global__ __launch_bounds__(TPB) void k_seg_count(uint32_t NT, SortBufs sb, const uint64_t *__restrict__ meta,
+                                                   uint32_t *__restrict__ chunk_heads) {
+  __shared__ uint32_t lds[TPB / WAVE];
+  const uint32_t *K, *V;
+  sorted_arrays(sb, meta[META_PASSES], K, V);
+  const uint32_t j0 = blockIdx.x * SEG_CHUNK;
+  uint32_t c = 0;
+  for (int it = 0; it < SEG_ITEMS; ++it) {
+    const uint32_t j = j0 + it * TPB + threadIdx.x;
+    if (j < NT && seg_head(K, j)) ++c;
+  }
+  const uint32_t s = block_sum<TPB, uint32_t>(c, lds);
+  if (threadIdx.x == 0) chunk_heads[blockIdx.x] = s;
+}
+
+// Exclusive scan of chunk head counts (one block); writes the bin count B.
+__global__ __launch_bounds__(TPB) void k_seg_scan(uint32_t *__restrict__ chunk_heads, uint32_t G,
+                                                  uint64_t *__restrict__ meta) {
+  __shared__ uint32_t lds[TPB / WAVE];
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < G; b0 += TPB) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t v = b < G ? chunk_heads[b] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<TPB, uint32_t>(v, lds, &tot);
+    if (b < G) chunk_heads[b] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) meta[META_B] = carry;
+}
+
+__global__ void k_seg_zero(const uint64_t *__restrict__ meta, unsigned long long *__restrict__ acc, int ncomp,
+                           uint32_t NT) {
+  const uint32_t B = (uint32_t)meta[META_B];
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < B; s += gridDim.x * blockDim.x)
+    for (int c = 0; c < ncomp; ++c) acc[(size_t)c * NT + s] = 0ull;
+}
+
+template <int DIM>
+__device__ __forceinline__ void decode_key(uint32_t key, int T, const uint32_t *__restrict__ kbase,
+                                           const int32_t *__restrict__ bbox_cur, int &t, int32_t c[3]) {
+  // target: last t with kbase[t] <= key
+  int lo = 0, hi = T - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (kbase[mid] <= key) lo = mid;
+    else hi = mid - 1;
+  }
+  t = lo;
+  uint32_t l = key - kbase[t];
+  const int32_t *bb = bbox_cur + t * 6;
+  c[0] = bb[0] + (int32_t)(l % (uint32_t)bb[3]);
+  l /= (uint32_t)bb[3];
+  if (DIM == 3) {
+    c[1] = bb[1] + (int32_t)(l % (uint32_t)bb[4]);
+    c[2] = bb[2] + (int32_t)(l / (uint32_t)bb[4]);
+  } else {
+    c[1] = bb[1] + (int32_t)l;
+    c[2] = 0;
+  }
+}
+
+// Sums of the members of every bin as exact fixed-point integers: count,
+// offsets of the positions from the pixel that holds them (the pixel of a
+// cell is the pixel of each member, so x - pixel is exact and |.| <= 1/2),
+// velocities and intensity. Within a round the wave forms segmented inclusive
+// sums over its 64 slots (shuffles, flag = first slot of a bin); the lane at
+// the end of each run adds its sums to the bin with 64-bit integer atomics
+// (exact, hence independent of order). Also records each bin's key and
+// target, and every particle's bin number (storage order).
+template <int DIM>
+__global__ __launch_bounds__(TPB) void k_seg_reduce(Params p, SortBufs sb, const uint64_t *__restrict__ meta_c,
+                                                    uint64_t *__restrict__ meta, const uint32_t *__restrict__ chunk_base,
+                                                    const float *__restrict__ s, const uint32_t *__restrict__ kbase,
+                                                    unsigned long long *__restrict__ acc,
+                                                    uint32_t *__restrict__ seg_key, int32_t *__restrict__ seg_t,
+                                                    uint32_t *__restrict__ segid) {
+  constexpr int D = 2 * DIM + 1;
+  constexpr int NC = 1 + D;
+  __shared__ uint32_t wheads[TPB / WAVE];
+  const uint32_t NT = p.NT;
+  const uint32_t *K, *V;
+  sorted_arrays(sb, meta_c[META_PASSES], K, V);
+  const int lane = lane_id(), w = wave_id();
+  const uint32_t wb = blockIdx.x * SEG_CHUNK + (uint32_t)w * (WAVE * SEG_ITEMS);
+  // heads before this wave's range
+  uint32_t cnt = 0;
+  for (int r = 0; r < SEG_ITEMS; ++r) {
+    const uint32_t j = wb + r * WAVE + lane;
+    cnt += (uint32_t)__popcll(__ballot(j < NT && seg_head(K, j)));
+  }
+  if (lane == 0) wheads[w] = cnt;
+  __syncthreads();
+  uint32_t running = chunk_base[blockIdx.x];
+  for (int i = 0; i < w; ++i) running += wheads[i];
+  const unsigned long long incl = (lane == WAVE - 1) ? ~0ull : ((2ull << lane) - 1ull);
+  bool sat = false;
+  for (int r = 0; r < SEG_ITEMS; ++r) {
+    const uint32_t j = wb + r * WAVE + lane;
+    if (wb + r * WAVE >= NT) break;  // wave-uniform
+    const bool valid = j < NT;
+    const uint32_t kj = valid ? K[j] : 0u;
+    const bool head = valid && (j == 0 || kj != K[j - 1]);
+    const unsigned long long hm = __ballot(head);
+    const uint32_t sid = running + (uint32_t)__popcll(hm & incl) - 1u;
+    running += (uint32_t)__popcll(hm);
+    long long val[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) val[c] = 0;
+    if (valid) {
+      const uint32_t v = V ? V[j] : j;
+      val[0] = 1;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const float x = s[(size_t)a * NT + v];
+        const float pix = (float)cell_index(x, 1);
+        val[1 + a] = __float2ll_rn((x - pix) * FX_POS);  // x - pix exact, |.| <= 1/2
+      }
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        float vel = s[(size_t)(DIM + a) * NT + v];
+        if (!(fabsf(vel) < LIM_VEL)) {
+          sat = true;
+          vel = 0.0f;
+        }
+        val[1 + DIM + a] = __float2ll_rn(vel * FX_VEL);
+      }
+      float in = s[(size_t)(2 * DIM) * NT + v];
+      if (!(fabsf(in) < LIM_INT)) {
+        sat = true;
+        in = 0.0f;
+      }
+      val[1 + 2 * DIM] = __float2ll_rn(in * FX_INT);
+      segid[v] = sid;
+      if (head) {
+        int t;
+        int32_t cell[3];
+        decode_key<DIM>(kj, p.T, kbase, p.bbox_cur, t, cell);
+        seg_key[sid] = kj;
+        seg_t[sid] = t;
+      }
+    }
+    // segmented inclusive scan over the wave (flag: a bin starts here, or no slot)
+    bool f = head || !valid;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const bool fu = __shfl_up((int)f, o, WAVE) != 0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const long long vu = __shfl_up(val[c], o, WAVE);
+        if (lane >= o && !f) val[c] += vu;
+      }
+      if (lane >= o) f = f || fu;
+    }
+    const bool next_starts = __shfl_down((int)(head || !valid), 1, WAVE) != 0;
+    const bool run_end = valid && (lane == WAVE - 1 || next_starts);
+    if (run_end) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + sid], (unsigned long long)val[c]);
+    }
+  }
+  if (sat) atomicOr((unsigned long long *)&meta[META_ERR], (unsigned long long)ERR_FIXED_SAT);
+}
+
+// Dummy particle of every bin: mean of the members (CoM) or the cell centre
+// (CoC) for the positions, mean of the other components. Positions are kept
+// as (pixel of the cell, offset from it) so the likelihood never subtracts
+// large coordinates. Also marks the first bin of every target.
+template <int DIM>
+__global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsigned long long *__restrict__ acc,
+                        const uint32_t *__restrict__ seg_key, const int32_t *__restrict__ seg_t,
+                        const uint32_t *__restrict__ kbase, const int32_t *__restrict__ bbox_cur,
+                        int32_t *__restrict__ dpix, float *__restrict__ doff, float *__restrict__ dint,
+                        uint32_t *__restrict__ seg_first) {
+  const uint32_t B = (uint32_t)meta[META_B];
+  const uint32_t NT = p.NT;
+  for (uint32_t sidx = blockIdx.x * blockDim.x + threadIdx.x; sidx < B; sidx += gridDim.x * blockDim.x) {
+    int t;
+    int32_t cell[3];
+    decode_key<DIM>(seg_key[sidx], p.T, kbase, bbox_cur, t, cell);
+    const double n = (double)(long long)acc[sidx];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const int32_t c0 = floor_div(cell[a], p.m[a]);
+      dpix[(size_t)a * NT + sidx] = c0;
+      float off;
+      if (p.dummy_mode == 1) {
+        const int32_t r = cell[a] - c0 * p.m[a];  // cell within its pixel, 0..m-1
+        off = (float)(((double)r + 0.5) / (double)p.m[a] - 0.5);
+      } else {
+        off = (float)((double)(long long)acc[(size_t)(1 + a) * NT + sidx] / (double)FX_POS / n);
+      }
+      doff[(size_t)a * NT + sidx] = off;
+    }
+    dint[sidx] = (float)((double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + sidx] / (double)FX_INT / n);
+    const int ts = seg_t[sidx];
+    if (sidx == 0 || seg_t[sidx - 1] != ts) seg_first[ts] = sidx;
+    if (sidx == B - 1) seg_first[p.T] = B;
+  }
+}
+
+// ---------------------------------------------------------------- likelihood
+// Eq. likelihood with the model image of Eq. object: one wave64 per
+// evaluation, lanes over the P x P window; each pixel's model value is the
+// PSF averaged over q x q midpoint sub-samples. DIRECT evaluates one exp2
+// per sub-sample; SEPARABLE uses g(x, y) = g_x(x) g_y(y) (2 P q exp2 per
+// evaluation, then one product per pixel through lane shuffles). The sum of
+// squares is reduced with compensated (TwoSum) arithmetic.
+struct LikInput {
+  // pcSIR: dummies; SIR: particles
+  const int32_t *dpix;  // [dim][E] pixel of the cell (pcSIR)
+  const float *doff;    // [dim][E] offset from it (pcSIR)
+  const float *dint;    // [E] intensity (pcSIR)
+  const int32_t *seg_t; // [E] target (pcSIR)
+  const float *state;   // SoA state (SIR)
+  const uint32_t *off;  // [T+1] (SIR)
+};
+
+// 2^(-a) for a >= 0 in binary32 with unbiased rounding: a = n - f with n the
+// nearest integer and f in [-1/2, 1/2] (exact), 2^f from a degree-6
+// polynomial fitted to the relative error (csrc/fit_exp2.py; 3.6e-9 before
+// rounding), then an exact scaling by 2^-n. Max error 0.75 ulp, mean error
+// ~0. The hardware exp2 instruction is not used here: its error, about one ulp
+// of consistent sign, adds up over the P^2 q^2 sub-samples of a window into a
+// relative error of the sum of squares of a few 1e-7.
+__device__ __forceinline__ float exp2_neg(float a) {
+  a = fminf(a, 200.0f);
+  const float n = rintf(a);
+  const float f = n - a;
+  float r = 0.00015238006f;
+  r = fmaf(r, f, 0.0013391137f);
+  r = fmaf(r, f, 0.009618841f);
+  r = fmaf(r, f, 0.055503592f);
+  r = fmaf(r, f, 0.24022645f);
+  r = fmaf(r, f, 0.6931472f);
+  r = fmaf(r, f, 1.0f);
+  return ldexpf(r, -(int)n);
+}
+
+// Exponent scale of exp(-u^2 / 2 s^2) = exp2(-u^2 k), k = log2(e) / (2 s^2), per
+// axis. k is formed in FP64 once per evaluation and applied as an FP32 pair
+// (hi + lo): a single rounded FP32 k would bias every sub-sample of the
+// window the same way and the bias would add up over the P^2 q^2 terms.
+struct ExpScale {
+  float xh, xl, yh, yl;
+};
+__device__ __forceinline__ ExpScale psf_scale(const Params &p, float zpos) {
+  const double LOG2E = 1.4426950408889634074;
+  const double s0 = (double)p.sigma_psf;
+  double sx2 = s0 * s0, sy2 = s0 * s0;
+  if (p.psf == 1) {
+    const double ax = ((double)zpos - (double)p.astig_gamma) / (double)p.astig_d;
+    const double ay = ((double)zpos + (double)p.astig_gamma) / (double)p.astig_d;
+    sx2 *= 1.0 + ax * ax;
+    sy2 *= 1.0 + ay * ay;
+  }
+  const double kx = LOG2E / (2.0 * sx2), ky = LOG2E / (2.0 * sy2);
+  ExpScale e;
+  e.xh = (float)kx;
+  e.xl = (float)(kx - (double)e.xh);
+  e.yh = (float)ky;
+  e.yl = (float)(ky - (double)e.yh);
+  return e;
+}
+__device__ __forceinline__ float scaled_sq(float u, float kh, float kl) {
+  const float uu = u * u;
+  return fmaf(uu, kl, uu * kh);
+}
+// Sub-sample offset within a pixel: (a + 1/2)/q - 1/2 = (2a + 1 - q) / (2q).
+__device__ __forceinline__ float sub_offset(int a, int q) { return (float)(2 * a + 1 - q) / (float)(2 * q); }
+
+template <int DIM, bool SIR, bool SEP, int Q>
+__global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64_t *__restrict__ meta,
+                                             const float *__restrict__ frame, double *__restrict__ ll) {
+  const uint32_t E = SIR ? p.NT : (uint32_t)meta[META_B];
+  const int lane = lane_id();
+  const int P = p.P, R = p.R, P2 = P * P;
+  const int q = Q ? Q : p.q;
+  for (uint32_t e = blockIdx.x * LIK_WAVES + wave_id(); e < E; e += gridDim.x * LIK_WAVES) {
+    int t;
+    int32_t c0, r0;
+    float dx, dy, I0, zpos = 0.0f;
+    if (SIR) {
+      int lo = 0, hi = p.T - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (in.off[mid] <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      t = lo;
+      const float x = in.state[e];
+      const float y = in.state[(size_t)p.NT + e];
+      c0 = cell_index(x, 1);
+      r0 = cell_index(y, 1);
+      dx = x - (float)c0;  // exact
+      dy = y - (float)r0;
+      if (DIM == 3) zpos = in.state[(size_t)2 * p.NT + e];
+      I0 = in.state[(size_t)(2 * DIM) * p.NT + e];
+    } else {
+      t = in.seg_t[e];
+      c0 = in.dpix[e];
+      r0 = in.dpix[(size_t)p.NT + e];
+      dx = in.doff[e];
+      dy = in.doff[(size_t)p.NT + e];
+      if (DIM == 3) zpos = (float)in.dpix[(size_t)2 * p.NT + e] + in.doff[(size_t)2 * p.NT + e];
+      I0 = in.dint[e];
+    }
+    const ExpScale ks = psf_scale(p, zpos);
+    const float Iq = I0 / (float)(q * q);
+    const float *fr = frame + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
+    float gxl = 0.0f, gyl = 0.0f;
+    if (SEP) {
+      if (lane < P) {
+        const float cc = (float)(lane - R);
+        for (int a = 0; a < q; ++a) {
+          const float o = sub_offset(a, q);
+          gxl += exp2_neg(scaled_sq((cc + o) - dx, ks.xh, ks.xl));
+          gyl += exp2_neg(scaled_sq((cc + o) - dy, ks.yh, ks.yl));
+        }
+      }
+    }
+    float ssd = 0.0f, err = 0.0f;
+    for (int pix0 = 0; pix0 < P2; pix0 += WAVE) {
+      const int pix = pix0 + lane;
+      const int pc = pix % P, pr = pix / P;
+      float g = 0.0f;
+      if (SEP) {
+        const float gx = __shfl(gxl, pc < P ? pc : 0, WAVE);
+        const float gy = __shfl(gyl, pr < P ? pr : 0, WAVE);
+        g = gx * gy;
+      } else if (pix < P2) {
+        const float cc = (float)(pc - R), rr = (float)(pr - R);
+        if (Q) {
+          float ax[Q > 0 ? Q : 1];
+#pragma unroll
+          for (int a = 0; a < Q; ++a) ax[a] = scaled_sq((cc + sub_offset(a, Q)) - dx, ks.xh, ks.xl);
+#pragma unroll
+          for (int b = 0; b < Q; ++b) {
+            const float ay = scaled_sq((rr + sub_offset(b, Q)) - dy, ks.yh, ks.yl);
+#pragma unroll
+            for (int a = 0; a < Q; ++a) g += exp2_neg(ax[a] + ay);
+          }
+        } else {
+          for (int b = 0; b < q; ++b) {
+            const float ay = scaled_sq((rr + sub_offset(b, q)) - dy, ks.yh, ks.yl);
+            for (int a = 0; a < q; ++a)
+              g += exp2_neg(scaled_sq((cc + sub_offset(a, q)) - dx, ks.xh, ks.xl) + ay);
+          }
+        }
+      }
+      if (pix < P2) {
+        const int c = c0 + pc - R, r = r0 + pr - R;
+        float zb = 0.0f;
+        if (c >= 0 && c < p.W && r >= 0 && r < p.H) zb = fr[(size_t)r * p.W + c] - p.i_bg;
+        // residual d = zb - Iq g and its square as FP32 (hi, lo) pairs: a residual
+        // of ~100 (a spot the model lacks) would otherwise lose 1e-5 of l per particle
+        const float mg = Iq * g;
+        const float mge = fmaf(Iq, g, -mg);          // Iq g = mg + mge exactly
+        const float dh = zb - mg;
+        const float bv = dh - zb;
+        const float dl = ((zb - (dh - bv)) + (-mg - bv)) - mge;  // zb - mg = dh + (..) exactly
+        const float sq = dh * dh;
+        const float sqe = fmaf(dh, dh, -sq) + 2.0f * dh * dl;   // d^2 = sq + sqe (+ dl^2)
+        const float tsum = ssd + sq;
+        const float bp = tsum - ssd;
+        err += ((ssd - (tsum - bp)) + (sq - bp)) + sqe;
+        ssd = tsum;
+      }
+    }
+    // compensated wave sum; the (hi, lo) result is combined and scaled in FP64,
+    // the precision of the normalisation that consumes it
+    double hi, lo;
+    wave_sum_pair(ssd, err, hi, lo);
+    if (lane == 0) ll[e] = -(hi + lo) * p.inv2sxi2;
+  }
+}
+
+// ---------------------------------------------------------------- normalisation
+// pcSIR, one block per target, at bin level: the members of bin b share its
+// log-likelihood, so S = sum_b n_b e^{l_b - M}, sum w^2 = sum_b n_b w_b^2 and
+// the posterior mean is sum_b w_b (sum of the members' states), with the
+// members' sums taken exactly from the fixed-point bin sums. FP64.
+template <int DIM>
+__global__ __launch_bounds__(TPB) void k_norm_bins(Params p, const uint32_t *__restrict__ seg_first,
+                                                   const double *__restrict__ ll, const unsigned long long *__restrict__ acc,
+                                                   const int32_t *__restrict__ dpix, int64_t k,
+                                                   double *__restrict__ wbin, double *__restrict__ tgt,
+                                                   double *__restrict__ est, int32_t *__restrict__ tflag,
+                                                   uint64_t *__restrict__ meta) {
+  constexpr int D = 2 * DIM + 1;
+  __shared__ double lds[TPB / WAVE];
+  const int t = blockIdx.x;
+  const uint32_t s0 = seg_first[t], s1 = seg_first[t + 1];
+  const uint32_t NT = p.NT;
+  double mx = -INFINITY;
+  for (uint32_t s = s0 + threadIdx.x; s < s1; s += TPB) mx = fmax(mx, ll[s]);
+  const double M = block_max<TPB, double>(mx, lds);
+  double S = 0.0, Q = 0.0, X[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) X[d] = 0.0;
+  for (uint32_t s = s0 + threadIdx.x; s < s1; s += TPB) {
+    const double n = (double)(long long)acc[s];
+    const double e = exp(ll[s] - M);
+    S += n * e;
+    Q += n * e * e;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const double sum = n * (double)dpix[(size_t)a * NT + s] +
+                         (double)(long long)acc[(size_t)(1 + a) * NT + s] / (double)FX_POS;
+      X[a] += e * sum;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) X[DIM + a] += e * ((double)(long long)acc[(size_t)(1 + DIM + a) * NT + s] / (double)FX_VEL);
+    X[2 * DIM] += e * ((double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + s] / (double)FX_INT);
+  }
+  S = block_sum<TPB, double>(S, lds);
+  Q = block_sum<TPB, double>(Q, lds);
+#pragma unroll
+  for (int d = 0; d < D; ++d) X[d] = block_sum<TPB, double>(X[d], lds);
+  const bool ok = isfinite(M) && isfinite(S) && S > 0.0;
+  for (uint32_t s = s0 + threadIdx.x; s < s1; s += TPB) wbin[s] = ok ? exp(ll[s] - M) / S : 0.0;
+  if (threadIdx.x == 0) {
+    tgt[t * 4 + 0] = M;
+    tgt[t * 4 + 1] = S;
+    tgt[t * 4 + 2] = S * S / Q;
+    tgt[t * 4 + 3] = resample_uniform(p.seed, (uint64_t)k, (uint64_t)t);
+#pragma unroll
+    for (int d = 0; d < D; ++d) est[t * D + d] = X[d] / S;
+    tflag[t] = ok ? 0 : 1;
+    if (!ok) atomicOr((unsigned long long *)&meta[META_ERR], (unsigned long long)ERR_NONFINITE);
+  }
+}
+
+// SIR: per-tile partials (max, S, Q, X[D]) over particles, then a per-target combine.
+template <int DIM>
+__global__ __launch_bounds__(TPB) void k_norm_part(Params p, const Tile *__restrict__ tiles,
+                                                   const uint32_t *__restrict__ off, const double *__restrict__ ll,
+                                                   const float *__restrict__ s, double *__restrict__ part) {
+  constexpr int D = 2 * DIM + 1;
+  __shared__ double lds[TPB / WAVE];
+  const Tile tl = tiles[blockIdx.x];
+  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  double mx = -INFINITY;
+  for (int it = 0; it < SCAN_ITEMS; ++it) {
+    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    if (i < n) mx = fmax(mx, ll[base + i]);
+  }
+  const double M = block_max<TPB, double>(mx, lds);
+  double S = 0.0, Q = 0.0, X[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) X[d] = 0.0;
+  for (int it = 0; it < SCAN_ITEMS; ++it) {
+    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    if (i < n) {
+      const uint32_t g = base + i;
+      const double e = exp(ll[g] - M);
+      S += e;
+      Q += e * e;
+#pragma unroll
+      for (int d = 0; d < D; ++d) X[d] += e * (double)s[(size_t)d * p.NT + g];
+    }
+  }
+  S = block_sum<TPB, double>(S, lds);
+  Q = block_sum<TPB, double>(Q, lds);
+#pragma unroll
+  for (int d = 0; d < D; ++d) X[d] = block_sum<TPB, double>(X[d], lds);
+  if (threadIdx.x == 0) {
+    double *o = part + (size_t)blockIdx.x * (3 + D);
+    o[0] = M;
+    o[1] = S;
+    o[2] = Q;
+#pragma unroll
+    for (int d = 0; d < D; ++d) o[3 + d] = X[d];
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(TPB) void k_norm_comb(Params p, const uint32_t *__restrict__ tfirst,
+                                                   const double *__restrict__ part, int64_t k,
+                                                   double *__restrict__ tgt, double *__restrict__ est,
+                                                   int32_t *__restrict__ tflag, uint64_t *__restrict__ meta) {
+  constexpr int D = 2 * DIM + 1;
+  constexpr int W = 3 + D;
+  __shared__ double lds[TPB / WAVE];
+  const int t = blockIdx.x;
+  const uint32_t a0 = tfirst[t], a1 = tfirst[t + 1];
+  double mx = -INFINITY;
+  for (uint32_t i = a0 + threadIdx.x; i < a1; i += TPB) mx = fmax(mx, part[(size_t)i * W]);
+  const double M = block_max<TPB, double>(mx, lds);
+  double S = 0.0, Q = 0.0, X[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) X[d] = 0.0;
+  for (uint32_t i = a0 + threadIdx.x; i < a1; i += TPB) {
+    const double *o = part + (size_t)i * W;
+    const double f = exp(o[0] - M);
+    if (f > 0.0) {
+      S += o[1] * f;
+      Q += o[2] * f * f;
+#pragma unroll
+      for (int d = 0; d < D; ++d) X[d] += o[3 + d] * f;
+    }
+  }
+  S = block_sum<TPB, double>(S, lds);
+  Q = block_sum<TPB, double>(Q, lds);
+#pragma unroll
+  for (int d = 0; d < D; ++d) X[d] = block_sum<TPB, double>(X[d], lds);
+  if (threadIdx.x == 0) {
+    const bool ok = isfinite(M) && isfinite(S) && S > 0.0;
+    tgt[t * 4 + 0] = M;
+    tgt[t * 4 + 1] = S;
+    tgt[t * 4 + 2] = S * S / Q;
+    tgt[t * 4 + 3] = resample_uniform(p.seed, (uint64_t)k, (uint64_t)t);
+#pragma unroll
+    for (int d = 0; d < D; ++d) est[t * D + d] = X[d] / S;
+    tflag[t] = ok ? 0 : 1;
+    if (!ok) atomicOr((unsigned long long *)&meta[META_ERR], (unsigned long long)ERR_NONFINITE);
+  }
+}
+
+// ---------------------------------------------------------------- weights, CDF, resampling
+// Weight of particle g (target t) in storage order. pcSIR: the weight of the
+// bin that holds it (binary search of its key among the target's sorted bin
+// keys); SIR: e^{l_g - M} / S.
+struct WeightSrc {
+  const uint32_t *segid;     // pcSIR: bin of every particle, storage order
+  const double *wbin;        // pcSIR: [B]
+  const double *ll;          // SIR: [NT]
+  const double *tgt;         // [T][4]
+};
+template <bool SIR>
+__device__ __forceinline__ double particle_weight(const WeightSrc &ws, int t, uint32_t g) {
+  if (SIR) return exp(ws.ll[g] - ws.tgt[t * 4]) / ws.tgt[t * 4 + 1];
+  return ws.wbin[ws.segid[g]];
+}
+
+template <bool SIR>
+__global__ __launch_bounds__(TPB) void k_cdf_sum(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
+                                                 WeightSrc ws, double *__restrict__ tile_sum) {
+  __shared__ double lds[TPB / WAVE];
+  const Tile tl = tiles[blockIdx.x];
+  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  double acc = 0.0;
+  for (int it = 0; it < SCAN_ITEMS; ++it) {
+    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    if (i < n) acc += particle_weight<SIR>(ws, tl.t, base + i);
+  }
+  const double tot = block_sum<TPB, double>(acc, lds);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+// Per target: exclusive, non-decreasing scan of its tiles' sums.
+__global__ __launch_bounds__(TPB) void k_cdf_prefix(const uint32_t *__restrict__ tfirst,
+                                                    const double *__restrict__ tile_sum,
+                                                    double *__restrict__ tile_pre) {
+  __shared__ double lds[TPB / WAVE];
+  const int t = blockIdx.x;
+  const uint32_t a0 = tfirst[t], a1 = tfirst[t + 1];
+  __shared__ double last;
+  double carry = 0.0;
+  for (uint32_t b0 = a0; b0 < a1; b0 += TPB) {
+    const uint32_t b = b0 + threadIdx.x;
+    const double v = b < a1 ? tile_sum[b] : 0.0;
+    double tot;
+    const double ex = block_excl_scan_monotone<TPB>(v, lds, &tot);
+    const double val = carry + ex;
+    if (b < a1) tile_pre[b] = val;
+    if (threadIdx.x == TPB - 1) last = val + v;
+    __syncthreads();
+    // the next chunk starts at or above every value written so far
+    const double nc = carry + tot;
+    carry = nc > last ? nc : last;
+    __syncthreads();
+  }
+}
+
+// Number of thresholds theta_j = (j + u) / n below c, for j in [0, n).
+__device__ __forceinline__ uint32_t count_below(double c, double u, uint32_t n) {
+  if (!(c > 0.0)) return 0;
+  if (!(c < 2.0)) return n;
+  const double dn = (double)n;
+  double e = ceil(c * dn - u);
+  e = e < 0.0 ? 0.0 : (e > dn ? dn : e);
+  uint32_t j = (uint32_t)e;
+  while (j > 0 && (((double)(j - 1) + u) / dn) >= c) --j;
+  while (j < n && (((double)j + u) / dn) < c) ++j;
+  return j;
+}
+
+// Systematic resampling fused with the cumulative-weight scan: particle l
+// owns the new particles j with C_{l-1} <= theta_j < C_l (the last particle
+// also takes any j left above C_{n-1} by rounding), which is
+// s(j) = min{ l : C_l > theta_j }. Every boundary C is taken from a single
+// source (the next thread's or tile's start), so the ranges partition [0, n).
+template <bool SIR>
+__global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
+                                                      const uint32_t *__restrict__ tile_last,
+                                                      WeightSrc ws, const double *__restrict__ tile_pre,
+                                                      const int32_t *__restrict__ tflag, uint32_t *__restrict__ anc,
+                                                      double *__restrict__ cdf_dbg) {
+  __shared__ double lds[TPB / WAVE];
+  __shared__ double bound[TPB + 1];
+  const Tile tl = tiles[blockIdx.x];
+  const int t = tl.t;
+  const uint32_t base = off[t], n = off[t + 1] - base;
+  const double u = ws.tgt[t * 4 + 3];
+  double w[SCAN_ITEMS];
+  double loc = 0.0;
+#pragma unroll
+  for (int it = 0; it < SCAN_ITEMS; ++it) {
+    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    w[it] = i < n ? particle_weight<SIR>(ws, t, base + i) : 0.0;
+    loc += w[it];
+  }
+  double tot;
+  const double ex = block_excl_scan_monotone<TPB>(loc, lds, &tot);
+  const double pre = tile_pre[blockIdx.x];
+  const bool last_tile = tile_last[blockIdx.x] != 0;
+  const double tile_end = last_tile ? INFINITY : tile_pre[blockIdx.x + 1];
+  // thread boundaries: non-decreasing, within [this tile's start, next tile's start]
+  {
+    const double b = pre + ex;
+    bound[threadIdx.x] = b < tile_end ? b : tile_end;
+  }
+  if (threadIdx.x == 0) bound[TPB] = tile_end;
+  __syncthreads();
+  const double start = bound[threadIdx.x];
+  double end = bound[threadIdx.x + 1];
+  if (end < start) end = start;
+  if (tflag[t]) {
+    // non-finite normalisation: keep the particles (identity resampling)
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+      const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+      if (i < n) anc[base + i] = i;
+    }
+    return;
+  }
+  double run = 0.0;
+  double cprev = start;
+  uint32_t lo = count_below(start, u, n);
+#pragma unroll
+  for (int it = 0; it < SCAN_ITEMS; ++it) {
+    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    if (i >= n) break;
+    run += w[it];
+    double c;
+    if (i + 1 == n) {
+      c = pre + (ex + run);  // the target's total; every j left over goes to this particle
+      c = c < cprev ? cprev : c;
+    } else {
+      c = (it == SCAN_ITEMS - 1) ? end : pre + (ex + run);
+      c = c < cprev ? cprev : (c > end ? end : c);
+    }
+    uint32_t hi = (i + 1 == n) ? n : count_below(c, u, n);
+    if (hi < lo) hi = lo;
+    for (uint32_t j = lo; j < hi; ++j) anc[base + j] = i;
+    if (cdf_dbg) cdf_dbg[base + i] = c;
+    lo = hi;
+    cprev = c;
+  }
+}
+
+// ---------------------------------------------------------------- helpers for the API
+// Materialise the current particle set (apply the pending resampling gather).
+__global__ __launch_bounds__(TPB) void k_gather(int D, uint32_t NT, const Tile *__restrict__ tiles,
+                                                const uint32_t *__restrict__ off, const float *__restrict__ s,
+                                                const uint32_t *__restrict__ anc, int pending, float *__restrict__ dst) {
+  const Tile tl = tiles[blockIdx.x];
+  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t i = tl.i0 + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t g = base + i;
+  const uint32_t src = pending ? base + min(anc[g], n - 1) : g;
+  for (int d = 0; d < D; ++d) dst[(size_t)d * NT + g] = s[(size_t)d * NT + src];
+}
+
+// anc[g] = index within the target (identity resampling).
+__global__ __launch_bounds__(TPB) void k_identity(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
+                                                  uint32_t *__restrict__ anc) {
+  const Tile tl = tiles[blockIdx.x];
+  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t i = tl.i0 + threadIdx.x;
+  if (i < n) anc[base + i] = i;
+}
+
+__global__ void k_dbg_keys(int dim, uint32_t NT, int m0, int m1, int m2, const float *__restrict__ s,
+                           int32_t *__restrict__ out) {
+  const int m[3] = {m0, m1, m2};
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < NT; g += gridDim.x * blockDim.x)
+    for (int a = 0; a < 3; ++a) out[(size_t)a * NT + g] = a < dim ? cell_index(s[(size_t)a * NT + g], m[a]) : 0;
+}
+
+template <int DIM>
+__global__ void k_dbg_bins(Params p, const uint64_t *__restrict__ meta, const unsigned long long *__restrict__ acc,
+                           const uint32_t *__restrict__ seg_key, const uint32_t *__restrict__ kbase,
+                           const int32_t *__restrict__ bbox_cur, int what, void *__restrict__ out) {
+  constexpr int D = 2 * DIM + 1;
+  const uint32_t B = (uint32_t)meta[META_B];
+  const uint32_t NT = p.NT;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < B; s += gridDim.x * blockDim.x) {
+    int t;
+    int32_t cell[3];
+    decode_key<DIM>(seg_key[s], p.T, kbase, bbox_cur, t, cell);
+    const double n = (double)(long long)acc[s];
+    if (what == 3) ((int32_t *)out)[s] = t;
+    if (what == 4)
+      for (int a = 0; a < 3; ++a) ((int32_t *)out)[(size_t)a * B + s] = cell[a];
+    if (what == 5) ((long long *)out)[s] = (long long)acc[s];
+    if (what == 6) {
+      double *o = (double *)out;
+      for (int a = 0; a < DIM; ++a) {
+        const double c0 = (double)floor_div(cell[a], p.m[a]);
+        o[(size_t)a * B + s] = c0 + (double)(long long)acc[(size_t)(1 + a) * NT + s] / (double)FX_POS / n;
+      }
+      for (int a = 0; a < DIM; ++a)
+        o[(size_t)(DIM + a) * B + s] = (double)(long long)acc[(size_t)(1 + DIM + a) * NT + s] / (double)FX_VEL / n;
+      o[(size_t)(2 * DIM) * B + s] = (double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + s] / (double)FX_INT / n;
+      (void)D;
+    }
+  }
+}
+
+template <bool SIR>
+__global__ __launch_bounds__(TPB) void k_dbg_weights(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
+                                                     WeightSrc ws, double *__restrict__ out) {
+  const Tile tl = tiles[blockIdx.x];
+  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t i = tl.i0 + threadIdx.x;
+  if (i >= n) return;
+  out[base + i] = particle_weight<SIR>(ws, tl.t, base + i);
+}
+
+}  // namespace pcsir

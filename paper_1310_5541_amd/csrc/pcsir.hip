@@ -1,0 +1,703 @@
+// Host side of the pcSIR library: workspace planning, tile tables, launch
+// sequences of one SIR / pcSIR frame, and the C ABI declared in pcsir.h.
+// The library never allocates device memory: every buffer is carved out of
+// the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pcsir.h"
+#include "kernels.h"
+
+using namespace pcsir;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+struct Layout {
+  size_t S0, S1, anc, key, kA, vA, kB, vB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
+      ll, wbin, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
+      tiles256, tilesS, tile_last, tfirst, t256_first, off;
+  int sort_items; // keys per thread in the radix sort (chosen to fill the device)
+  size_t total;
+  uint32_t G;    // sort chunks
+  uint32_t Gs;   // segment chunks
+  uint32_t n256; // propagate tiles
+  uint32_t nS;   // scan tiles
+};
+
+struct Tables {
+  std::vector<Tile> t256, tS;
+  std::vector<uint32_t> tile_last, tfirst, t256_first, off;
+};
+
+bool valid_config(const pcsir_config *c, std::string *why) {
+  auto bad = [&](const char *m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (!c) return bad("config is NULL");
+  if (c->abi_version != PCSIR_ABI_VERSION) return bad("abi_version mismatch");
+  if (c->dim != 2 && c->dim != 3) return bad("dim must be 2 or 3");
+  if (c->n_targets < 1) return bad("n_targets must be >= 1");
+  if (!c->n_particles) return bad("n_particles is NULL");
+  long long sum = 0;
+  for (int t = 0; t < c->n_targets; ++t) {
+    if (c->n_particles[t] < 1) return bad("every n_particles[t] must be >= 1");
+    sum += c->n_particles[t];
+    if (sum >= (1LL << 31)) return bad("sum of n_particles must be < 2^31");
+  }
+  for (int a = 0; a < c->dim; ++a)
+    if (c->bins_per_px[a] < 1 || c->bins_per_px[a] > 4096) return bad("bins_per_px must lie in [1, 4096]");
+  if (c->patch < 1 || c->patch > 63 || (c->patch % 2) == 0) return bad("patch must be odd and in [1, 63]");
+  if (c->quad < 1 || c->quad > 16) return bad("quad must lie in [1, 16]");
+  if (c->psf != PCSIR_PSF_GAUSS2D && c->psf != PCSIR_PSF_ASTIG3D) return bad("unknown psf");
+  if (c->psf == PCSIR_PSF_ASTIG3D && c->dim != 3) return bad("astigmatic PSF needs dim == 3");
+  if (c->dummy_mode != PCSIR_DUMMY_COM && c->dummy_mode != PCSIR_DUMMY_COC) return bad("unknown dummy_mode");
+  if (c->lik_mode != PCSIR_LIK_DIRECT && c->lik_mode != PCSIR_LIK_SEPARABLE) return bad("unknown lik_mode");
+  if (c->frame_h < 1 || c->frame_w < 1) return bad("frame_h and frame_w must be >= 1");
+  if (!(c->sigma_psf > 0.0f) || !(c->sigma_xi > 0.0f)) return bad("sigma_psf and sigma_xi must be > 0");
+  if (c->psf == PCSIR_PSF_ASTIG3D && !(c->astig_d > 0.0f)) return bad("astig_d must be > 0");
+  for (int d = 0; d < 2 * c->dim + 1; ++d)
+    if (!(c->proc_sigma[d] >= 0.0f)) return bad("proc_sigma must be >= 0");
+  return true;
+}
+
+void build_tables(const pcsir_config *c, Tables &tb) {
+  const int T = c->n_targets;
+  tb.off.assign(T + 1, 0);
+  tb.tfirst.assign(T + 1, 0);
+  tb.t256_first.assign(T + 1, 0);
+  tb.t256.clear();
+  tb.tS.clear();
+  tb.tile_last.clear();
+  for (int t = 0; t < T; ++t) {
+    const uint32_t n = (uint32_t)c->n_particles[t];
+    tb.off[t + 1] = tb.off[t] + n;
+    tb.t256_first[t] = (uint32_t)tb.t256.size();
+    for (uint32_t i0 = 0; i0 < n; i0 += TPB) tb.t256.push_back(Tile{t, i0});
+    tb.tfirst[t] = (uint32_t)tb.tS.size();
+    for (uint32_t i0 = 0; i0 < n; i0 += SCAN_TILE) {
+      tb.tS.push_back(Tile{t, i0});
+      tb.tile_last.push_back(i0 + SCAN_TILE >= n ? 1u : 0u);
+    }
+  }
+  tb.tfirst[T] = (uint32_t)tb.tS.size();
+  tb.t256_first[T] = (uint32_t)tb.t256.size();
+}
+
+// Keys per thread of the radix sort: enough blocks for about 8 per compute
+// unit on the 256-CU device, at most SORT_ITEMS.
+int sort_items_for(size_t NT) {
+  int it = 1;
+  while (it < SORT_ITEMS && NT > (size_t)it * TPB * 256 * 8) it *= 2;
+  return it;
+}
+
+Layout plan(const pcsir_config *c, const Tables &tb) {
+  Layout L;
+  const size_t NT = tb.off.back();
+  const size_t T = c->n_targets;
+  const size_t dim = c->dim, D = 2 * dim + 1;
+  L.sort_items = sort_items_for(NT);
+  L.G = (uint32_t)((NT + (size_t)L.sort_items * TPB - 1) / ((size_t)L.sort_items * TPB));
+  L.Gs = (uint32_t)((NT + SEG_CHUNK - 1) / SEG_CHUNK);
+  L.n256 = (uint32_t)tb.t256.size();
+  L.nS = (uint32_t)tb.tS.size();
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += (bytes + ALIGN - 1) / ALIGN * ALIGN;
+    return at;
+  };
+  L.S0 = take(4 * D * NT);
+  L.S1 = take(4 * D * NT);
+  L.anc = take(4 * NT);
+  L.key = take(4 * NT);
+  L.kA = take(4 * NT);
+  L.vA = take(4 * NT);
+  L.kB = take(4 * NT);
+  L.vB = take(4 * NT);
+  L.hist = take(4 * 256 * (size_t)L.G);
+  L.dtot = take(4 * 256);
+  L.chunk_heads = take(4 * (size_t)L.Gs);
+  L.acc = take(8 * (1 + D) * NT);
+  L.seg_key = take(4 * NT);
+  L.seg_t = take(4 * NT);
+  L.segid = take(4 * NT);
+  L.dpix = take(4 * dim * NT);
+  L.doff = take(4 * dim * NT);
+  L.dint = take(4 * NT);
+  L.ll = take(8 * NT);
+  L.wbin = take(8 * NT);
+  L.seg_first = take(4 * (T + 1));
+  L.bbox_part = take(4 * 6 * (size_t)L.n256);
+  L.range = take(8 * T);
+  L.bbox_cur = take(4 * 6 * T);
+  L.kbase = take(4 * (T + 1));
+  L.meta = take(8 * META_N);
+  L.tgt = take(8 * 4 * T);
+  L.est = take(8 * D * T);
+  L.tflag = take(4 * T);
+  L.part = take(8 * (3 + D) * (size_t)L.nS);
+  L.tile_sum = take(8 * (size_t)L.nS);
+  L.tile_pre = take(8 * (size_t)L.nS);
+  L.cdf = take(8 * NT);
+  L.tiles256 = take(sizeof(Tile) * (size_t)L.n256);
+  L.tilesS = take(sizeof(Tile) * (size_t)L.nS);
+  L.tile_last = take(4 * (size_t)L.nS);
+  L.tfirst = take(4 * (T + 1));
+  L.t256_first = take(4 * (T + 1));
+  L.off = take(4 * (T + 1));
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct pcsir_ctx {
+  pcsir_config cfg;
+  std::vector<int64_t> n;
+  Tables tb;
+  Layout L;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  Params p;
+  uint32_t NT = 0;
+  int cur = 0;       // state buffer holding the current particles (0: S0, 1: S1)
+  int pending = 0;   // a resampling gather is pending (anc holds s(j))
+  int stepped = 0;   // a step has run since init / set_particles
+  int last_sir = 0;  // kind of the last step
+  int debug = 0;     // keep the per-particle cumulative weights
+  int num_cus = 256;
+  std::string err;
+  // timing
+  int timing = 0;
+  std::vector<hipEvent_t> ev;
+  std::vector<const char *> ev_name;
+  int ev_used = 0;
+
+  template <typename T>
+  T *at(size_t off) const {
+    return reinterpret_cast<T *>(ws + off);
+  }
+  float *state(int which) const { return at<float>(which ? L.S1 : L.S0); }
+};
+
+namespace {
+
+pcsir_status fail(pcsir_ctx *c, pcsir_status s, const std::string &m) {
+  if (c) c->err = m;
+  return s;
+}
+
+pcsir_status check_hip(pcsir_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return PCSIR_OK;
+  return fail(c, PCSIR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void mark(pcsir_ctx *c, const char *name) {
+  if (!c->timing) return;
+  if (c->ev_used >= (int)c->ev.size()) return;
+  hipEventRecord(c->ev[c->ev_used], c->stream);
+  c->ev_name[c->ev_used] = name;
+  ++c->ev_used;
+}
+
+Params make_params(const pcsir_config *c, uint32_t NT) {
+  Params p;
+  memset(&p, 0, sizeof(p));
+  p.dim = c->dim;
+  p.D = 2 * c->dim + 1;
+  p.T = c->n_targets;
+  p.NT = NT;
+  for (int a = 0; a < 3; ++a) p.m[a] = a < c->dim ? c->bins_per_px[a] : 1;
+  p.P = c->patch;
+  p.R = (c->patch - 1) / 2;
+  p.q = c->quad;
+  p.psf = c->psf;
+  p.dummy_mode = c->dummy_mode;
+  p.per_target_frames = c->per_target_frames;
+  p.H = c->frame_h;
+  p.W = c->frame_w;
+  p.sigma_psf = c->sigma_psf;
+  p.astig_gamma = c->astig_gamma;
+  p.astig_d = c->astig_d;
+  p.i_bg = c->i_bg;
+  p.inv2sxi2 = 1.0 / (2.0 * (double)c->sigma_xi * (double)c->sigma_xi);
+  for (int d = 0; d < 7; ++d) p.proc_sigma[d] = c->proc_sigma[d];
+  p.seed = c->seed;
+  return p;
+}
+
+SortBufs sort_bufs(const pcsir_ctx *c) {
+  SortBufs sb;
+  sb.key_store = c->at<uint32_t>(c->L.key);
+  sb.kA = c->at<uint32_t>(c->L.kA);
+  sb.vA = c->at<uint32_t>(c->L.vA);
+  sb.kB = c->at<uint32_t>(c->L.kB);
+  sb.vB = c->at<uint32_t>(c->L.vB);
+  return sb;
+}
+
+WeightSrc weight_src(const pcsir_ctx *c) {
+  WeightSrc w;
+  w.segid = c->at<uint32_t>(c->L.segid);
+  w.wbin = c->at<double>(c->L.wbin);
+  w.ll = c->at<double>(c->L.ll);
+  w.tgt = c->at<double>(c->L.tgt);
+  return w;
+}
+
+uint32_t grid_stride_blocks(const pcsir_ctx *c, uint32_t work, uint32_t per_block) {
+  const uint32_t need = (work + per_block - 1) / per_block;
+  const uint32_t cap = (uint32_t)c->num_cus * 32;
+  return std::max(1u, std::min(need, cap));
+}
+
+template <int DIM, bool SIR, bool SEP>
+void launch_lik(pcsir_ctx *c, const LikInput &in, const float *frame) {
+  const uint32_t grid = grid_stride_blocks(c, c->p.NT, LIK_WAVES);
+  const uint64_t *meta = c->at<uint64_t>(c->L.meta);
+  double *ll = c->at<double>(c->L.ll);
+  hipStream_t st = c->stream;
+  if (SEP) {
+    k_lik<DIM, SIR, true, 0><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll);
+    return;
+  }
+  switch (c->p.q) {
+    case 2: k_lik<DIM, SIR, false, 2><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll); break;
+    case 4: k_lik<DIM, SIR, false, 4><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll); break;
+    case 8: k_lik<DIM, SIR, false, 8><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll); break;
+    default: k_lik<DIM, SIR, false, 0><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll); break;
+  }
+}
+
+template <int DIM, bool SEP>
+void launch_pcsir(pcsir_ctx *c, const float *frame, int64_t k) {
+  const Layout &L = c->L;
+  const Params &p = c->p;
+  hipStream_t st = c->stream;
+  const Tile *t256 = c->at<Tile>(L.tiles256);
+  const Tile *tS = c->at<Tile>(L.tilesS);
+  const uint32_t *off = c->at<uint32_t>(L.off);
+  float *sin = c->state(c->cur);
+  float *sout = c->state(1 - c->cur);
+  uint32_t *anc = c->at<uint32_t>(L.anc);
+  uint64_t *meta = c->at<uint64_t>(L.meta);
+
+  mark(c, "propagate");
+  k_propagate<DIM, true><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, k,
+                                                 c->at<int32_t>(L.bbox_part));
+  mark(c, "bbox");
+  k_bbox_reduce<<<p.T, TPB, 0, st>>>(p.dim, c->at<uint32_t>(L.t256_first), c->at<int32_t>(L.bbox_part),
+                                     c->at<int32_t>(L.bbox_cur), c->at<unsigned long long>(L.range));
+  k_bbox_scan<<<1, TPB, 0, st>>>(p.T, c->at<unsigned long long>(L.range), c->at<uint32_t>(L.kbase), meta);
+  mark(c, "keys");
+  k_keys<DIM><<<L.n256, TPB, 0, st>>>(p, t256, off, sout, c->at<int32_t>(L.bbox_cur), c->at<uint32_t>(L.kbase),
+                                      c->at<uint32_t>(L.key));
+  SortBufs sb = sort_bufs(c);
+  uint32_t *hist = c->at<uint32_t>(L.hist);
+  uint32_t *dtot = c->at<uint32_t>(L.dtot);
+  for (int pass = 0; pass < 4; ++pass) {
+    const uint32_t *kin = pass == 0 ? sb.key_store : ((pass & 1) ? sb.kB : sb.kA);
+    const uint32_t *vin = pass == 0 ? nullptr : ((pass & 1) ? sb.vB : sb.vA);
+    uint32_t *kout = (uint32_t *)((pass & 1) ? sb.kA : sb.kB);
+    uint32_t *vout = (uint32_t *)((pass & 1) ? sb.vA : sb.vB);
+    mark(c, "sort_hist");
+    k_sort_hist<<<L.G, TPB, 0, st>>>(pass, p.NT, L.sort_items, kin, hist, L.G, meta);
+    mark(c, "sort_scan");
+    k_sort_scan<<<256, TPB, 0, st>>>(pass, hist, L.G, dtot, meta);
+    mark(c, "sort_scatter");
+    k_sort_scatter<<<L.G, TPB, 0, st>>>(pass, p.NT, L.sort_items, kin, vin, kout, vout, hist, L.G, dtot, meta);
+  }
+  uint32_t *chunk = c->at<uint32_t>(L.chunk_heads);
+  unsigned long long *acc = c->at<unsigned long long>(L.acc);
+  mark(c, "seg_count");
+  k_seg_count<<<L.Gs, TPB, 0, st>>>(p.NT, sb, meta, chunk);
+  mark(c, "seg_scan");
+  k_seg_scan<<<1, TPB, 0, st>>>(chunk, L.Gs, meta);
+  mark(c, "seg_zero");
+  k_seg_zero<<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(meta, acc, 2 + 2 * DIM, p.NT);
+  mark(c, "seg_reduce");
+  k_seg_reduce<DIM><<<L.Gs, TPB, 0, st>>>(p, sb, meta, meta, chunk, sout, c->at<uint32_t>(L.kbase), acc,
+                                          c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t),
+                                          c->at<uint32_t>(L.segid));
+  mark(c, "dummy");
+  k_dummy<DIM><<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(
+      p, meta, acc, c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.kbase),
+      c->at<int32_t>(L.bbox_cur), c->at<int32_t>(L.dpix), c->at<float>(L.doff), c->at<float>(L.dint),
+      c->at<uint32_t>(L.seg_first));
+  LikInput in;
+  in.dpix = c->at<int32_t>(L.dpix);
+  in.doff = c->at<float>(L.doff);
+  in.dint = c->at<float>(L.dint);
+  in.seg_t = c->at<int32_t>(L.seg_t);
+  in.state = sout;
+  in.off = off;
+  mark(c, "likelihood");
+  launch_lik<DIM, false, SEP>(c, in, frame);
+  mark(c, "normalise");
+  k_norm_bins<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.seg_first), c->at<double>(L.ll), acc,
+                                        c->at<int32_t>(L.dpix), k, c->at<double>(L.wbin), c->at<double>(L.tgt),
+                                        c->at<double>(L.est), c->at<int32_t>(L.tflag), meta);
+  WeightSrc ws = weight_src(c);
+  mark(c, "cdf_sum");
+  k_cdf_sum<false><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.tile_sum));
+  mark(c, "cdf_prefix");
+  k_cdf_prefix<<<p.T, TPB, 0, st>>>(c->at<uint32_t>(L.tfirst), c->at<double>(L.tile_sum),
+                                    c->at<double>(L.tile_pre));
+  mark(c, "resample");
+  k_cdf_resample<false><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
+                                              c->at<int32_t>(L.tflag), anc,
+                                              c->debug ? c->at<double>(L.cdf) : nullptr);
+  mark(c, "end");
+}
+
+template <int DIM, bool SEP>
+void launch_sir(pcsir_ctx *c, const float *frame, int64_t k) {
+  const Layout &L = c->L;
+  const Params &p = c->p;
+  hipStream_t st = c->stream;
+  const Tile *t256 = c->at<Tile>(L.tiles256);
+  const Tile *tS = c->at<Tile>(L.tilesS);
+  const uint32_t *off = c->at<uint32_t>(L.off);
+  float *sin = c->state(c->cur);
+  float *sout = c->state(1 - c->cur);
+  uint32_t *anc = c->at<uint32_t>(L.anc);
+  uint64_t *meta = c->at<uint64_t>(L.meta);
+  mark(c, "propagate");
+  k_propagate<DIM, false><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, k, nullptr);
+  LikInput in;
+  memset(&in, 0, sizeof(in));
+  in.state = sout;
+  in.off = off;
+  mark(c, "likelihood");
+  launch_lik<DIM, true, SEP>(c, in, frame);
+  mark(c, "normalise");
+  k_norm_part<DIM><<<L.nS, TPB, 0, st>>>(p, tS, off, c->at<double>(L.ll), sout, c->at<double>(L.part));
+  k_norm_comb<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.tfirst), c->at<double>(L.part), k,
+                                        c->at<double>(L.tgt), c->at<double>(L.est), c->at<int32_t>(L.tflag), meta);
+  WeightSrc ws = weight_src(c);
+  mark(c, "cdf_sum");
+  k_cdf_sum<true><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.tile_sum));
+  mark(c, "cdf_prefix");
+  k_cdf_prefix<<<p.T, TPB, 0, st>>>(c->at<uint32_t>(L.tfirst), c->at<double>(L.tile_sum),
+                                    c->at<double>(L.tile_pre));
+  mark(c, "resample");
+  k_cdf_resample<true><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
+                                             c->at<int32_t>(L.tflag), anc, c->debug ? c->at<double>(L.cdf) : nullptr);
+  mark(c, "end");
+}
+
+pcsir_status run_step(pcsir_ctx *c, const float *frame, int32_t H, int32_t W, int64_t k, bool sir) {
+  if (!c) return PCSIR_E_INVAL;
+  if (!frame) return fail(c, PCSIR_E_INVAL, "frame_dev is NULL");
+  if (H != c->cfg.frame_h || W != c->cfg.frame_w) return fail(c, PCSIR_E_STATE, "frame size differs from the config");
+  if (k < 1) return fail(c, PCSIR_E_INVAL, "frame index k must be >= 1");
+  const bool sep = c->cfg.lik_mode == PCSIR_LIK_SEPARABLE;
+  if (sir) {
+    if (c->cfg.dim == 2) sep ? launch_sir<2, true>(c, frame, k) : launch_sir<2, false>(c, frame, k);
+    else sep ? launch_sir<3, true>(c, frame, k) : launch_sir<3, false>(c, frame, k);
+  } else {
+    if (c->cfg.dim == 2) sep ? launch_pcsir<2, true>(c, frame, k) : launch_pcsir<2, false>(c, frame, k);
+    else sep ? launch_pcsir<3, true>(c, frame, k) : launch_pcsir<3, false>(c, frame, k);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return check_hip(c, e, "kernel launch");
+  c->cur = 1 - c->cur;
+  c->pending = 1;
+  c->stepped = 1;
+  c->last_sir = sir ? 1 : 0;
+  return PCSIR_OK;
+}
+
+pcsir_status pull_device_status(pcsir_ctx *c) {
+  uint64_t meta[META_N];
+  hipError_t e = hipMemcpyAsync(meta, c->at<uint64_t>(c->L.meta), sizeof(meta), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return check_hip(c, e, "device status");
+  if (meta[META_ERR]) {
+    std::string m = "device condition:";
+    if (meta[META_ERR] & ERR_KEY_RANGE) m += " cell range of all targets exceeds 2^32 cells (clouds spread too far for these bins);";
+    if (meta[META_ERR] & ERR_FIXED_SAT) m += " a velocity (|v| >= 128) or intensity (|I| >= 32768) left the bin-sum range;";
+    if (meta[META_ERR] & ERR_NONFINITE) m += " a target's normalisation was not finite (its particles were kept, not resampled);";
+    uint64_t zero = 0;
+    hipMemcpyAsync(c->at<uint64_t>(c->L.meta) + META_ERR, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
+    hipStreamSynchronize(c->stream);
+    return fail(c, PCSIR_E_NUMERIC, m);
+  }
+  return PCSIR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pcsir_workspace_bytes(const pcsir_config *cfg) {
+  if (!valid_config(cfg, nullptr)) return 0;
+  Tables tb;
+  build_tables(cfg, tb);
+  return plan(cfg, tb).total;
+}
+
+pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, void *workspace_dev,
+                        size_t workspace_bytes, void *hip_stream, pcsir_ctx **out) {
+  if (!out) return PCSIR_E_INVAL;
+  *out = nullptr;
+  std::string why;
+  if (!valid_config(cfg, &why)) {
+    fprintf(stderr, "pcsir_init: invalid config: %s\n", why.c_str());
+    return PCSIR_E_INVAL;
+  }
+  if (!init_state_dev || !workspace_dev) return PCSIR_E_INVAL;
+  if (((uintptr_t)workspace_dev) % ALIGN) return PCSIR_E_INVAL;
+  pcsir_ctx *c = new pcsir_ctx();
+  c->cfg = *cfg;
+  c->n.assign(cfg->n_particles, cfg->n_particles + cfg->n_targets);
+  c->cfg.n_particles = c->n.data();
+  build_tables(&c->cfg, c->tb);
+  c->L = plan(&c->cfg, c->tb);
+  if (workspace_bytes < c->L.total) {
+    delete c;
+    return PCSIR_E_NOMEM;
+  }
+  c->ws = (char *)workspace_dev;
+  c->stream = (hipStream_t)hip_stream;
+  c->NT = c->tb.off.back();
+  c->p = make_params(&c->cfg, c->NT);
+  c->p.bbox_cur = c->at<int32_t>(c->L.bbox_cur);
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      c->num_cus = cus;
+  }
+  const Layout &L = c->L;
+  const int T = c->cfg.n_targets;
+  const int D = 2 * c->cfg.dim + 1;
+  hipError_t e = hipSuccess;
+  auto h2d = [&](size_t off, const void *src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+  };
+  h2d(L.tiles256, c->tb.t256.data(), sizeof(Tile) * c->tb.t256.size());
+  h2d(L.tilesS, c->tb.tS.data(), sizeof(Tile) * c->tb.tS.size());
+  h2d(L.tile_last, c->tb.tile_last.data(), 4 * c->tb.tile_last.size());
+  h2d(L.tfirst, c->tb.tfirst.data(), 4 * c->tb.tfirst.size());
+  h2d(L.off, c->tb.off.data(), 4 * c->tb.off.size());
+  h2d(L.t256_first, c->tb.t256_first.data(), 4 * c->tb.t256_first.size());
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.meta, 0, 8 * META_N, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tflag, 0, 4 * (size_t)T, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->state(0), init_state_dev, 4 * (size_t)D * c->NT, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) {
+    k_identity<<<L.n256, TPB, 0, c->stream>>>(c->at<Tile>(L.tiles256), c->at<uint32_t>(L.off), c->at<uint32_t>(L.anc));
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    fprintf(stderr, "pcsir_init: %s\n", hipGetErrorString(e));
+    delete c;
+    return PCSIR_E_HIP;
+  }
+  *out = c;
+  return PCSIR_OK;
+}
+
+pcsir_status pcsir_step(pcsir_ctx *ctx, const float *frame_dev, int32_t H, int32_t W, int64_t k) {
+  return run_step(ctx, frame_dev, H, W, k, false);
+}
+
+pcsir_status sir_step(pcsir_ctx *ctx, const float *frame_dev, int32_t H, int32_t W, int64_t k) {
+  return run_step(ctx, frame_dev, H, W, k, true);
+}
+
+pcsir_status pcsir_estimate(pcsir_ctx *c, double *est_host, double *neff_host) {
+  if (!c || !est_host) return PCSIR_E_INVAL;
+  if (!c->stepped) return fail(c, PCSIR_E_STATE, "no step has run since init or set_particles");
+  const int T = c->cfg.n_targets, D = 2 * c->cfg.dim + 1;
+  hipError_t e = hipMemcpyAsync(est_host, c->at<double>(c->L.est), 8 * (size_t)T * D, hipMemcpyDeviceToHost, c->stream);
+  std::vector<double> tg;
+  if (neff_host) {
+    tg.resize(4 * (size_t)T);
+    if (e == hipSuccess) e = hipMemcpyAsync(tg.data(), c->at<double>(c->L.tgt), 8 * tg.size(), hipMemcpyDeviceToHost, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return check_hip(c, e, "pcsir_estimate");
+  if (neff_host)
+    for (int t = 0; t < T; ++t) neff_host[t] = tg[4 * (size_t)t + 2];
+  return pull_device_status(c);
+}
+
+pcsir_status pcsir_destroy(pcsir_ctx *c) {
+  if (!c) return PCSIR_E_INVAL;
+  pcsir_status s = PCSIR_OK;
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) s = PCSIR_E_HIP;
+  else s = pull_device_status(c);
+  for (hipEvent_t ev : c->ev) hipEventDestroy(ev);
+  delete c;
+  return s;
+}
+
+const char *pcsir_last_error(const pcsir_ctx *c) { return c ? c->err.c_str() : "context is NULL"; }
+
+pcsir_status pcsir_get_particles(pcsir_ctx *c, float *dst_dev) {
+  if (!c || !dst_dev) return PCSIR_E_INVAL;
+  k_gather<<<c->L.n256, TPB, 0, c->stream>>>(c->p.D, c->NT, c->at<Tile>(c->L.tiles256), c->at<uint32_t>(c->L.off),
+                                             c->state(c->cur), c->at<uint32_t>(c->L.anc), c->pending, dst_dev);
+  return check_hip(c, hipGetLastError(), "pcsir_get_particles");
+}
+
+pcsir_status pcsir_set_particles(pcsir_ctx *c, const float *src_dev) {
+  if (!c || !src_dev) return PCSIR_E_INVAL;
+  const hipError_t e = hipMemcpyAsync(c->state(c->cur), src_dev, 4 * (size_t)c->p.D * c->NT, hipMemcpyDeviceToDevice,
+                                      c->stream);
+  c->pending = 0;
+  c->stepped = 0;
+  return check_hip(c, e, "pcsir_set_particles");
+}
+
+pcsir_status pcsir_set_debug(pcsir_ctx *c, int32_t on) {
+  if (!c) return PCSIR_E_INVAL;
+  c->debug = on ? 1 : 0;
+  return PCSIR_OK;
+}
+
+pcsir_status pcsir_debug_dump(pcsir_ctx *c, int32_t what, void *dst, size_t bytes) {
+  if (!c || !dst) return PCSIR_E_INVAL;
+  if (!c->stepped) return fail(c, PCSIR_E_STATE, "no step has run since init or set_particles");
+  const size_t NT = c->NT, T = c->cfg.n_targets, D = c->p.D;
+  const Layout &L = c->L;
+  hipStream_t st = c->stream;
+  // the propagated states of the last step sit in the current buffer
+  const float *prop = c->state(c->cur);
+  uint64_t B = 0;
+  if (what >= PCSIR_DUMP_COUNTS && what <= PCSIR_DUMP_BIN_MEAN) {
+    uint64_t meta[META_N];
+    hipError_t e = hipMemcpyAsync(meta, c->at<uint64_t>(L.meta), sizeof(meta), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(c, e, "debug dump");
+    B = c->last_sir ? NT : meta[META_B];
+    if (what == PCSIR_DUMP_COUNTS) {
+      if (bytes < 16) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      int64_t v[2] = {(int64_t)B, (int64_t)(c->last_sir ? 0 : meta[META_PASSES])};
+      return check_hip(c, hipMemcpy(dst, v, 16, hipMemcpyHostToDevice), "debug dump");
+    }
+    if (c->last_sir) return fail(c, PCSIR_E_STATE, "bins exist only after pcsir_step");
+  }
+  auto need = [&](size_t b) { return bytes >= b; };
+  const uint32_t gb = grid_stride_blocks(c, (uint32_t)NT, TPB);
+  hipError_t e = hipSuccess;
+  switch (what) {
+    case PCSIR_DUMP_PROPAGATED:
+      if (!need(4 * D * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      e = hipMemcpyAsync(dst, prop, 4 * D * NT, hipMemcpyDeviceToDevice, st);
+      break;
+    case PCSIR_DUMP_KEYS: {
+      if (!need(4 * 3 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      // SIR: the pixel index (cells with m = 1) that centres each particle's window
+      const int m0 = c->last_sir ? 1 : c->p.m[0], m1 = c->last_sir ? 1 : c->p.m[1], m2 = c->last_sir ? 1 : c->p.m[2];
+      k_dbg_keys<<<gb, TPB, 0, st>>>(c->p.dim, (uint32_t)NT, m0, m1, m2, prop, (int32_t *)dst);
+      break;
+    }
+    case PCSIR_DUMP_BIN_TARGET:
+    case PCSIR_DUMP_BIN_KEY:
+    case PCSIR_DUMP_BIN_N:
+    case PCSIR_DUMP_BIN_MEAN: {
+      const size_t per = what == PCSIR_DUMP_BIN_TARGET ? 4 : what == PCSIR_DUMP_BIN_KEY ? 12
+                         : what == PCSIR_DUMP_BIN_N ? 8 : 8 * D;
+      if (!need(per * B)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      if (c->p.dim == 2)
+        k_dbg_bins<2><<<gb, TPB, 0, st>>>(c->p, c->at<uint64_t>(L.meta), c->at<unsigned long long>(L.acc),
+                                          c->at<uint32_t>(L.seg_key), c->at<uint32_t>(L.kbase),
+                                          c->at<int32_t>(L.bbox_cur), what, dst);
+      else
+        k_dbg_bins<3><<<gb, TPB, 0, st>>>(c->p, c->at<uint64_t>(L.meta), c->at<unsigned long long>(L.acc),
+                                          c->at<uint32_t>(L.seg_key), c->at<uint32_t>(L.kbase),
+                                          c->at<int32_t>(L.bbox_cur), what, dst);
+      break;
+    }
+    case PCSIR_DUMP_LOGLIK: {
+      size_t n = NT;
+      if (!c->last_sir) {
+        uint64_t meta[META_N];
+        e = hipMemcpyAsync(meta, c->at<uint64_t>(L.meta), sizeof(meta), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        n = meta[META_B];
+      }
+      if (!need(8 * n)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      if (e == hipSuccess) e = hipMemcpyAsync(dst, c->at<double>(L.ll), 8 * n, hipMemcpyDeviceToDevice, st);
+      break;
+    }
+    case PCSIR_DUMP_WEIGHTS:
+      if (!need(8 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      if (c->last_sir)
+        k_dbg_weights<true><<<L.n256, TPB, 0, st>>>(c->at<Tile>(L.tiles256), c->at<uint32_t>(L.off), weight_src(c),
+                                                    (double *)dst);
+      else
+        k_dbg_weights<false><<<L.n256, TPB, 0, st>>>(c->at<Tile>(L.tiles256), c->at<uint32_t>(L.off), weight_src(c),
+                                                     (double *)dst);
+      break;
+    case PCSIR_DUMP_TARGET:
+      if (!need(8 * 4 * T)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      e = hipMemcpyAsync(dst, c->at<double>(L.tgt), 8 * 4 * T, hipMemcpyDeviceToDevice, st);
+      break;
+    case PCSIR_DUMP_CDF:
+      if (!c->debug) return fail(c, PCSIR_E_STATE, "cumulative weights are kept only with pcsir_set_debug(ctx, 1)");
+      if (!need(8 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      e = hipMemcpyAsync(dst, c->at<double>(L.cdf), 8 * NT, hipMemcpyDeviceToDevice, st);
+      break;
+    case PCSIR_DUMP_RESAMPLE:
+      if (!need(4 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      e = hipMemcpyAsync(dst, c->at<uint32_t>(L.anc), 4 * NT, hipMemcpyDeviceToDevice, st);
+      break;
+    default:
+      return fail(c, PCSIR_E_INVAL, "unknown dump");
+  }
+  if (e != hipSuccess) return check_hip(c, e, "debug dump");
+  return check_hip(c, hipGetLastError(), "debug dump");
+}
+
+pcsir_status pcsir_set_timing(pcsir_ctx *c, int32_t on) {
+  if (!c) return PCSIR_E_INVAL;
+  c->timing = on ? 1 : 0;
+  if (c->timing && c->ev.empty()) {
+    c->ev.resize(8192);
+    c->ev_name.assign(8192, "");
+    for (auto &ev : c->ev) {
+      const hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return check_hip(c, e, "hipEventCreate");
+    }
+  }
+  c->ev_used = 0;
+  return PCSIR_OK;
+}
+
+pcsir_status pcsir_kernel_times(pcsir_ctx *c, const char **names, float *ms, int32_t cap, int32_t *count) {
+  if (!c || !count) return PCSIR_E_INVAL;
+  *count = 0;
+  if (!c->timing || c->ev_used < 2) return PCSIR_OK;
+  const hipError_t e = hipEventSynchronize(c->ev[c->ev_used - 1]);
+  if (e != hipSuccess) return check_hip(c, e, "hipEventSynchronize");
+  int n = 0;
+  for (int i = 0; i + 1 < c->ev_used && n < cap; ++i) {
+    if (strcmp(c->ev_name[i], "end") == 0) continue;  // gap between two steps
+    float t = 0.0f;
+    hipEventElapsedTime(&t, c->ev[i], c->ev[i + 1]);
+    if (names) names[n] = c->ev_name[i];
+    if (ms) ms[n] = t;
+    ++n;
+  }
+  *count = n;
+  c->ev_used = 0;
+  return PCSIR_OK;
+}
+
+}  // extern "C"

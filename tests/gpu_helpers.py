@@ -1,0 +1,175 @@
+"""Stage-wise parity of one GPU filter step against the FP64 oracle.
+
+The GPU and the oracle share no code. Propagation is compared on the same
+parent states and counters; every later stage is compared by running the
+oracle on the GPU's propagated (binary32) states, so that keys, counts and
+resampling indices can be required bit-exact.
+
+Tolerances (derived in the design notes from the FP32 arithmetic of the path):
+  propagate      |d| <= 1e-6 * |x| + 2e-6
+  keys, bins     bit-exact (keys, counts, bin order, targets)
+  bin means      positions 1e-7 px, velocities 1e-7, intensity 1e-6
+  log-likelihood |d| <= 5e-6 + 3e-7 |l|: the window's sum of squares S = -2 sigma_xi^2 l
+                 is formed in FP32 from P^2 q^2 hardware exp2 values; a bias of a
+                 few ulp in them shifts every model pixel the same way, so the
+                 error grows with S (about 2.5 FP32 ulp of l). Near the weight
+                 maximum |l| is small and the bound stays below the 1e-5 that
+                 the weights allow; far from it the weights are negligible.
+  weights        |dw| <= 1e-5 w + 1e-10 max w; for windows that hold spots the
+                 one-spot model lacks (|l| of several hundred), the FP32 sum of
+                 squares has a relative precision of a few 1e-8, and the bound
+                 becomes (1e-5 + 4e-8 |l|) w + 1e-10 max w
+  estimates      rel 1e-5 (abs 1e-5); N_eff rel 1e-5
+  resampling u   bit-exact
+  s(j)           bit-exact except where the oracle's cumulative weight lies
+                 within 1e-6 of theta_j; and, from the GPU's own weights,
+                 bit-exact except within 1e-9.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+LL_ATOL = 5e-6
+LL_RTOL = 3e-7
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_model(cfg, seed=None):
+    import oracle
+    return oracle.Model(dim=cfg.dim, m=tuple(cfg.bins_per_px), patch=cfg.patch, quad=cfg.quad, psf=cfg.psf,
+                        dummy_mode=cfg.dummy_mode, sigma_psf=cfg.sigma_psf, astig_gamma=cfg.astig_gamma,
+                        astig_d=cfg.astig_d, i_bg=cfg.i_bg, sigma_xi=cfg.sigma_xi,
+                        proc_sigma=tuple(cfg.proc_sigma), seed=cfg.seed if seed is None else seed)
+
+
+def exempt_mask(cdf, s, theta, eps):
+    """j whose threshold lies within eps of a cumulative weight bracketing it."""
+    N = cdf.shape[0]
+    hi = cdf[s]
+    lo = np.where(s > 0, cdf[np.maximum(s - 1, 0)], 0.0)
+    return (np.abs(hi - theta) <= eps) | (np.abs(lo - theta) <= eps)
+
+
+def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, w_cond=0.0):
+    """cloud: [D, NT] float32 (host); frames: [H, W] or [T, H, W] float32 (host).
+    Runs one GPU step from `cloud` and checks every stage against the oracle.
+    Returns a dict of the largest deviations."""
+    import torch
+
+    import oracle
+    from paper_1310_5541_amd import Filter
+
+    T, D, dim = cfg.T, cfg.D, cfg.dim
+    n = np.asarray(cfg.n_particles, dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(n)])
+    mdl = oracle_model(cfg)
+    f = Filter(cfg, torch.from_numpy(np.ascontiguousarray(cloud)).cuda())
+    f.set_debug(True)
+    fr_t = torch.from_numpy(np.ascontiguousarray(frames)).cuda()
+    f.step(fr_t, k, sir=sir)
+    est, neff = f.estimate()
+    prop = f.dump("propagated").cpu().numpy()
+    keys = f.dump("keys").cpu().numpy()
+    ll_gpu = f.dump("loglik").cpu().numpy()
+    w_gpu = f.dump("weights").cpu().numpy()
+    tgt = f.dump("target").cpu().numpy()
+    cdf_gpu = f.dump("cdf").cpu().numpy()
+    s_gpu = f.dump("resample").cpu().numpy().astype(np.int64)
+    if not sir:
+        counts = f.dump("counts").cpu().numpy()
+        b_t = f.dump("bin_target").cpu().numpy()
+        b_key = f.dump("bin_key").cpu().numpy()
+        b_n = f.dump("bin_n").cpu().numpy()
+        b_mean = f.dump("bin_mean").cpu().numpy()
+    after = f.get_particles().cpu().numpy()
+    f.close()
+
+    dev = dict(prop=0.0, mean_pos=0.0, mean_vel=0.0, mean_int=0.0, ll=0.0, w=0.0, est=0.0, neff=0.0,
+               exempt=0, mismatch=0, B=0)
+    bofs = 0
+    for t in range(T):
+        a, b = off[t], off[t + 1]
+        fr = frames[t] if cfg.per_target_frames else frames
+        if check_prop:
+            op = oracle.propagate(mdl, cloud[:, a:b], k, t)
+            err = np.abs(prop[:, a:b].astype(np.float64) - op)
+            tol = 1e-6 * np.abs(op.astype(np.float64)) + 2e-6
+            assert np.all(err <= tol), f"target {t}: propagate off by {err.max()}"
+            dev["prop"] = max(dev["prop"], float(err.max()))
+        r = oracle.weigh(mdl, fr, prop[:, a:b], sir=sir)
+        assert np.array_equal(keys[:dim, a:b], r["keys"][:dim]), f"target {t}: keys differ"
+        B = r["B"]
+        if sir:
+            ll_o = r["ll"]
+            ll_g = ll_gpu[a:b].astype(np.float64)
+        else:
+            gsl = slice(bofs, bofs + B)
+            assert np.all(b_t[gsl] == t), f"target {t}: bin targets"
+            assert np.array_equal(b_key[:dim, gsl], r["bin_key"][:dim]), f"target {t}: bin keys"
+            assert np.array_equal(b_n[gsl], r["bin_n"]), f"target {t}: bin counts"
+            gm, om = b_mean[:, gsl], r["bin_mean"]
+            e_pos = np.abs(gm[:dim] - om[:dim]).max()
+            e_vel = np.abs(gm[dim:2 * dim] - om[dim:2 * dim]).max()
+            e_int = np.abs(gm[2 * dim] - om[2 * dim]).max()
+            if cfg.dummy_mode == 0:
+                assert e_pos <= 1e-7, f"target {t}: bin mean positions off by {e_pos}"
+            assert e_vel <= 1e-7 and e_int <= 1e-6, (e_vel, e_int)
+            dev["mean_pos"] = max(dev["mean_pos"], float(e_pos))
+            dev["mean_vel"] = max(dev["mean_vel"], float(e_vel))
+            dev["mean_int"] = max(dev["mean_int"], float(e_int))
+            ll_o = r["ll"]
+            ll_g = ll_gpu[gsl].astype(np.float64)
+            bofs += B
+            dev["B"] += B
+        d_ll = np.abs(ll_g - ll_o)
+        bad = d_ll > LL_ATOL + LL_RTOL * np.abs(ll_o)
+        assert not np.any(bad), (f"target {t}: log-likelihood off by {d_ll[bad].max()} at l = "
+                                 f"{ll_o[bad][np.argmax(d_ll[bad])]}")
+        dev["ll"] = max(dev["ll"], float(d_ll.max()))
+        dev["ll_rel"] = max(dev.get("ll_rel", 0.0), float(np.max(d_ll / np.maximum(np.abs(ll_o), 1.0))))
+        wg, wo = w_gpu[a:b], r["w"]
+        # w_cond > 0 widens the bound by the FP32 conditioning of a large sum of
+        # squares (|l| in the hundreds: a window holding a spot the model lacks)
+        e_w = np.abs(wg - wo) - ((1e-5 + w_cond * np.abs(r["ll"][r["bin_of"]])) * wo + 1e-10 * wo.max())
+        assert np.all(e_w <= 0), f"target {t}: weights off, worst excess {e_w.max()}"
+        dev["w"] = max(dev["w"], float(np.max(np.abs(wg - wo) / np.maximum(wo, 1e-300))))
+        assert abs(wg.sum() - 1.0) < 1e-12
+        e_est = np.abs(est[t] - r["est"]) / np.maximum(np.abs(r["est"]), 1.0)
+        assert np.all(e_est <= 1e-5), f"target {t}: estimate off by {e_est.max()}"
+        dev["est"] = max(dev["est"], float(e_est.max()))
+        e_neff = abs(neff[t] - r["neff"]) / r["neff"]
+        assert e_neff <= 1e-5, f"target {t}: N_eff off by {e_neff}"
+        dev["neff"] = max(dev["neff"], float(e_neff))
+        u = oracle.resample_u(cfg.seed, k, t)
+        assert tgt[t, 3] == u, f"target {t}: resampling uniform"
+        N = b - a
+        theta = (np.arange(N, dtype=np.float64) + u) / N
+        # (1) from the oracle's weights: exact except near a threshold
+        cdf_o, s_o = oracle.resample(wo, u)
+        sg = s_gpu[a:b]
+        diff = sg != s_o
+        ex = exempt_mask(cdf_o, s_o, theta, 1e-6)
+        assert not np.any(diff & ~ex), f"target {t}: {int(np.sum(diff & ~ex))} resampling indices differ"
+        dev["exempt"] += int(np.sum(ex))
+        dev["mismatch"] += int(np.sum(diff))
+        # (2) from the GPU's own weights: the scan and the search
+        cdf_g, s_g = oracle.resample(wg, u)
+        e_cdf = np.abs(cdf_gpu[a:b] - cdf_g).max()
+        assert e_cdf <= 1e-12, f"target {t}: cumulative weights off by {e_cdf}"
+        diff2 = sg != s_g
+        ex2 = exempt_mask(cdf_g, s_g, theta, 1e-9)
+        assert not np.any(diff2 & ~ex2), f"target {t}: resampling from the GPU's weights differs"
+        assert np.all((sg >= 0) & (sg < N)) and np.all(np.diff(sg) >= 0)
+        # the resampled set is the gather of the propagated states
+        assert np.array_equal(after[:, a:b], prop[:, a:b][:, sg])
+    if not sir:
+        assert int(counts[0]) == dev["B"]
+    if report is not None:
+        report.update(dev)
+    return dev, after

@@ -1,0 +1,105 @@
+"""C ABI checks that need no GPU: the library loads, exports every function that
+include/pcsir.h declares, and its host-side config validation and workspace
+planning behave as documented."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pcsir.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:pcsir_status|size_t|const char\s*\*)\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1310_5541_amd as P
+    if not os.path.exists(P.lib_path()):
+        from paper_1310_5541_amd import build
+        build.build()
+    return P.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    import paper_1310_5541_amd as P
+    names = _declared()
+    assert {"pcsir_init", "pcsir_step", "sir_step", "pcsir_estimate", "pcsir_workspace_bytes"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", P.lib_path()], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        getattr(L, n)
+
+
+def test_library_is_built_for_gfx950_only():
+    import paper_1310_5541_amd as P
+    out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", P.lib_path()], capture_output=True, text=True)
+    if out.returncode != 0:
+        pytest.skip("roc-obj-ls not available")
+    targets = set(re.findall(r"gfx\w+", out.stdout))
+    assert targets == {"gfx950"}, targets
+
+
+def _cfg(**kw):
+    from paper_1310_5541_amd import Config
+    base = dict(n_particles=(1000, 37), frame_h=64, frame_w=64)
+    base.update(kw)
+    return Config(**base)
+
+
+def test_workspace_bytes_and_validation(L):
+    c, keep = _cfg()._c()
+    b = L.pcsir_workspace_bytes(C.byref(c))
+    assert b > 0 and b % 256 == 0
+    # grows with the particle count, roughly linearly
+    c2, keep2 = _cfg(n_particles=(100000, 3700))._c()
+    b2 = L.pcsir_workspace_bytes(C.byref(c2))
+    assert 50 * b < b2 < 150 * b
+    bad = [dict(dim=4), dict(n_particles=(0,)), dict(bins_per_px=(0, 2, 1)), dict(bins_per_px=(5000, 2, 1)),
+           dict(patch=10), dict(patch=65), dict(quad=0), dict(quad=17), dict(psf=1), dict(lik_mode=7),
+           dict(sigma_xi=0.0), dict(sigma_psf=-1.0), dict(frame_h=0), dict(dummy_mode=3),
+           dict(proc_sigma=(-1, 0, 0, 0, 0))]
+    for kw in bad:
+        cb, kb = _cfg(**kw)._c()
+        assert L.pcsir_workspace_bytes(C.byref(cb)) == 0, kw
+    cb, kb = _cfg()._c()
+    cb.abi_version = 99
+    assert L.pcsir_workspace_bytes(C.byref(cb)) == 0
+    # 3D with the astigmatic PSF is valid
+    c3, k3 = _cfg(dim=3, psf=1, bins_per_px=(4, 4, 4), proc_sigma=(0.5,) * 7)._c()
+    assert L.pcsir_workspace_bytes(C.byref(c3)) > 0
+
+
+def test_null_arguments_are_rejected_without_a_device(L):
+    c, keep = _cfg()._c()
+    out = C.c_void_p()
+    assert L.pcsir_init(C.byref(c), None, None, 0, None, C.byref(out)) == -1
+    assert L.pcsir_step(None, None, 64, 64, 1) == -1
+    assert L.sir_step(None, None, 64, 64, 1) == -1
+    assert L.pcsir_estimate(None, None, None) == -1
+    assert L.pcsir_destroy(None) == -1
+
+
+def test_product_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1310_5541_amd")
+    for dp, _, fs in os.walk(pkg):
+        for f in fs:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dp, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt and "pcsir_oracle" not in txt, f
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_1310_5541_amd._lib as lib
+    monkeypatch.setattr(lib, "_LIB", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(lib, "_lib", None)
+    with pytest.raises(lib.LibraryMissing):
+        lib.lib()
