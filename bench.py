@@ -143,27 +143,38 @@ def main():
 
     # ---- 2./3. timed regions
     def timed(sir, h):
+        """Timed region: K steps replayed as HIP graphs. Then the same K frames again,
+        kernels launched one by one with HIP events between them on the library's
+        stream, for the per-kernel durations."""
         f = make(h)
         for k in range(1, args.warmup + 1):
             f.step(frame(k), k, sir=sir)
-        torch.cuda.synchronize()
-        f.set_timing(True)
-        per = {}
+        state = f.get_particles()
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for k in range(args.warmup + 1, args.warmup + args.steps + 1):
             f.step(frame(k), k, sir=sir)
         torch.cuda.synchronize()
         el = time.perf_counter() - t_start
-        for name, ms in f.kernel_times():
-            per.setdefault(name, []).append(ms)
         B = int(f.dump("counts")[0].item()) if not sir else NT
         passes = int(f.dump("counts")[1].item()) if not sir else 0
+        # per-kernel event timing over the same frames from the same start
+        f.set_particles(state)
+        f.set_timing(True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for k in range(args.warmup + 1, args.warmup + args.steps + 1):
+            f.step(frame(k), k, sir=sir)
+        torch.cuda.synchronize()
+        el_events = time.perf_counter() - t2
+        per = {}
+        for name, ms in f.kernel_times():
+            per.setdefault(name, []).append(ms)
         f.close()
-        return el, per, B, passes
+        return el, per, B, passes, el_events
 
-    el_pc, per_pc, B_pc, passes = timed(False, h_match)
-    el_sir, per_sir, _, _ = timed(True, h_match)
+    el_pc, per_pc, B_pc, passes, ev_pc = timed(False, h_match)
+    el_sir, per_sir, _, _, ev_sir = timed(True, h_match)
     steps = args.steps
     value = NT * steps / el_pc
     sir_value = NT * steps / el_sir
@@ -243,6 +254,7 @@ def main():
                    "quad": w.quad, "likelihood": "direct" if args.lik == 0 else "separable",
                    "h_matched": h_match, "bins_at_h": B_pc, "sort_passes": passes},
         "sir": {"value": round(sir_value, 1), "ms_per_step": round(1e3 * el_sir / steps, 4)},
+        "ms_per_step_kernel_by_kernel": {"pcsir": round(1e3 * ev_pc / steps, 4), "sir": round(1e3 * ev_sir / steps, 4)},
         "speedup_pcsir_over_sir": round(value / sir_value, 2),
         "rmse_px": rmse,
         "roofline": roof,

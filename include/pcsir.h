@@ -172,6 +172,14 @@ typedef enum {
 
 pcsir_status pcsir_debug_dump(pcsir_ctx *ctx, int32_t what, void *dst_dev, size_t bytes);
 
+/* Replay each step as a captured HIP graph (on != 0, the default) or launch
+ * its kernels one by one. The graph of a step kind is captured on its first
+ * use (on a private stream; nothing runs during capture) and launched on the
+ * context's stream; per-step values (frame pointer, frame index) are passed
+ * through device memory, so replays need no parameter updates. Steps launch
+ * kernels one by one while timing is on. */
+pcsir_status pcsir_set_graphs(pcsir_ctx *ctx, int32_t on);
+
 /* Keep the per-particle cumulative weights of later steps for
  * PCSIR_DUMP_CDF (on != 0). Off by default: it adds 8 bytes of HBM writes per
  * particle and step. */

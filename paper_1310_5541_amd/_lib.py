@@ -75,10 +75,11 @@ def lib():
     L.pcsir_set_particles.argtypes = [vp, vp]
     L.pcsir_debug_dump.argtypes = [vp, i32, vp, sz]
     L.pcsir_set_debug.argtypes = [vp, i32]
+    L.pcsir_set_graphs.argtypes = [vp, i32]
     L.pcsir_set_timing.argtypes = [vp, i32]
     L.pcsir_kernel_times.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(C.c_float), i32, C.POINTER(i32)]
     for f in ("pcsir_init", "pcsir_step", "sir_step", "pcsir_estimate", "pcsir_destroy", "pcsir_get_particles",
-              "pcsir_set_particles", "pcsir_debug_dump", "pcsir_set_debug", "pcsir_set_timing",
+              "pcsir_set_particles", "pcsir_debug_dump", "pcsir_set_debug", "pcsir_set_graphs", "pcsir_set_timing",
               "pcsir_kernel_times"):
         getattr(L, f).restype = i32
     _lib = L
@@ -254,6 +255,9 @@ class Filter:
         self._check(lib().pcsir_debug_dump(self._ctx, DUMP[what], C.c_void_p(out.data_ptr()), max(nbytes, 1)))
         self.stream.synchronize()
         return out
+
+    def set_graphs(self, on: bool = True):
+        self._check(lib().pcsir_set_graphs(self._ctx, 1 if on else 0))
 
     def set_timing(self, on: bool = True):
         self._check(lib().pcsir_set_timing(self._ctx, 1 if on else 0))

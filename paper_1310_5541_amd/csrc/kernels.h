@@ -26,7 +26,9 @@ constexpr uint64_t ERR_KEY_RANGE = 1;    // compacted cell range of all targets 
 constexpr uint64_t ERR_FIXED_SAT = 2;    // a velocity or intensity outside the fixed-point range
 constexpr uint64_t ERR_NONFINITE = 4;    // a target's normalisation was not finite
 
-enum { META_PASSES = 0, META_RANGE = 1, META_B = 2, META_ERR = 3, META_N = 8 };
+enum { META_PASSES = 0, META_RANGE = 1, META_B = 2, META_ERR = 3, META_DIGIT = 4, META_DIRTY = 5, META_N = 8 };
+constexpr int MAX_DIGIT_BITS = 11;  // radix digit of at most 2048 buckets (LDS histogram)
+constexpr int MAX_BUCKETS = 1 << MAX_DIGIT_BITS;
 
 struct Params {
   int dim, D, T;
@@ -41,6 +43,19 @@ struct Params {
   const int32_t *bbox_cur;  // [T][6] (x0, y0, z0, wx, wy, wz) of the current frame's cells
 };
 
+// Per-step values that change from frame to frame. They live in device memory
+// (written by k_set_desc before each step) so that the kernel sequence of a
+// step can be captured once in a HIP graph and replayed.
+struct StepDesc {
+  const float *frame;
+  int64_t k;
+};
+
+__global__ void k_set_desc(StepDesc *__restrict__ d, const float *frame, int64_t k) {
+  d->frame = frame;
+  d->k = k;
+}
+
 struct Tile {
   int32_t t;   // target
   uint32_t i0; // first particle of the tile, index within the target
@@ -52,11 +67,18 @@ struct Tile {
 // of the previous frame's resampling is fused into the load. With KEYS, the
 // exact cell indices of the new positions are reduced to a per-target
 // bounding box (integer atomics).
+// With KEYS (pcSIR) it also writes each particle's state as one packed
+// 32-byte record (components in SoA order, zero padded), so that the bin sums
+// gather one sector per particle in sorted order, and it clears the bin
+// accumulators that the previous frame used (meta[META_DIRTY] of them).
 template <int DIM, bool KEYS>
 __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restrict__ tiles,
                                                    const uint32_t *__restrict__ off, const float *__restrict__ sin,
                                                    float *__restrict__ sout, const uint32_t *__restrict__ anc,
-                                                   int pending, int64_t k, int32_t *__restrict__ bbox_part) {
+                                                   int pending, const StepDesc *__restrict__ desc,
+                                                   int32_t *__restrict__ bbox_part,
+                                                   float4 *__restrict__ rec, unsigned long long *__restrict__ acc,
+                                                   const uint64_t *__restrict__ meta) {
   constexpr int D = 2 * DIM + 1;
   __shared__ int32_t red[TPB / WAVE];
   const Tile tl = tiles[blockIdx.x];
@@ -78,7 +100,7 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
 #pragma unroll
     for (int d = 0; d < D; ++d) x[d] = sin[(size_t)d * p.NT + src];
     float z[8];
-    normals8(p.seed, i, (uint64_t)k, (uint64_t)t, z);
+    normals8(p.seed, i, (uint64_t)desc->k, (uint64_t)t, z);
     float nx[D];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) nx[a] = fmaf(p.proc_sigma[a], z[a], x[a] + x[DIM + a]);
@@ -93,6 +115,16 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
         const int32_t c = cell_index(nx[a], p.m[a]);
         kmin[a] = c;
         kmax[a] = c;
+      }
+      float r8[8];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) r8[d] = d < D ? nx[d] : 0.0f;
+      rec[2 * (size_t)g] = make_float4(r8[0], r8[1], r8[2], r8[3]);
+      rec[2 * (size_t)g + 1] = make_float4(r8[4], r8[5], r8[6], r8[7]);
+      const uint32_t dirty = (uint32_t)meta[META_DIRTY];
+      if (g < dirty) {
+#pragma unroll
+        for (int c = 0; c < 1 + D; ++c) acc[(size_t)c * p.NT + g] = 0ull;
       }
     }
   }
@@ -163,12 +195,15 @@ __global__ __launch_bounds__(TPB) void k_bbox_scan(int T, const unsigned long lo
     meta[META_RANGE] = carry;
     int bits = 0;
     if (carry > 1) bits = 64 - __clzll((long long)(carry - 1));
-    int passes = (bits + 7) / 8;
     if (carry > 0xFFFFFFFFull) {
       meta[META_ERR] |= ERR_KEY_RANGE;
-      passes = 4;
+      bits = 32;
     }
+    // fewest passes of at most MAX_DIGIT_BITS bits, digits as narrow as that allows
+    const int passes = (bits + MAX_DIGIT_BITS - 1) / MAX_DIGIT_BITS;
+    const int width = passes ? (bits + passes - 1) / passes : 1;
     meta[META_PASSES] = (uint64_t)passes;
+    meta[META_DIGIT] = (uint64_t)width;
   }
 }
 
@@ -205,37 +240,41 @@ __global__ __launch_bounds__(TPB) void k_keys(Params p, const Tile *__restrict__
 // Stable sort of (key, index) by 8-bit digits; pass `pass` runs only if the
 // key range computed on the device needs it. Pass 0 reads the keys in
 // storage order with implicit indices 0..NT-1.
-// Lanes of the wave holding the same 8-bit digit d (invalid lanes: d = 256).
-__device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d) {
+// Lanes of the wave holding the same digit d (at most MAX_DIGIT_BITS bits;
+// invalid lanes carry d = MAX_BUCKETS and match only each other).
+__device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d, int width) {
   unsigned long long peers = __ballot(valid);
   if (!valid) peers = ~peers;
-#pragma unroll
-  for (int bit = 0; bit < 8; ++bit) {
+  for (int bit = 0; bit < width; ++bit) {
     const unsigned long long bb = __ballot((d >> bit) & 1u);
     peers &= ((d >> bit) & 1u) ? bb : ~bb;
   }
   return peers;
 }
 
+// Per-block digit histograms of pass `pass`; the digit width comes from the
+// device (meta[META_DIGIT]) and the pass runs only if the key range needs it.
 __global__ __launch_bounds__(TPB) void k_sort_hist(int pass, uint32_t NT, int items, const uint32_t *__restrict__ key,
                                                    uint32_t *__restrict__ hist, uint32_t G,
                                                    const uint64_t *__restrict__ meta) {
   if ((uint64_t)pass >= meta[META_PASSES]) return;
-  __shared__ uint32_t cnt[256];
-  cnt[threadIdx.x] = 0;
+  const int width = (int)meta[META_DIGIT];
+  const uint32_t nb = 1u << width, mask = nb - 1u;
+  __shared__ uint32_t cnt[MAX_BUCKETS];
+  for (uint32_t d = threadIdx.x; d < nb; d += TPB) cnt[d] = 0;
   __syncthreads();
   const uint32_t b0 = blockIdx.x * (uint32_t)(items * TPB);
-  const int sh = 8 * pass;
+  const int sh = width * pass;
   const unsigned long long below = (1ull << lane_id()) - 1ull;
   for (int it = 0; it < items; ++it) {
     const uint32_t j = b0 + it * TPB + threadIdx.x;
     const bool valid = j < NT;
-    const uint32_t d = valid ? (key[j] >> sh) & 255u : 256u;
-    const unsigned long long peers = digit_peers(valid, d);
+    const uint32_t d = valid ? (key[j] >> sh) & mask : (uint32_t)MAX_BUCKETS;
+    const unsigned long long peers = digit_peers(valid, d, width);
     if (valid && (peers & below) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * G + blockIdx.x] = cnt[threadIdx.x];
+  for (uint32_t d = threadIdx.x; d < nb; d += TPB) hist[(size_t)d * G + blockIdx.x] = cnt[d];
 }
 
 // One block per digit: exclusive scan of that digit's per-block counts.
@@ -243,6 +282,7 @@ __global__ __launch_bounds__(TPB) void k_sort_scan(int pass, uint32_t *__restric
                                                    uint32_t *__restrict__ digit_total,
                                                    const uint64_t *__restrict__ meta) {
   if ((uint64_t)pass >= meta[META_PASSES]) return;
+  if (blockIdx.x >= (1u << (int)meta[META_DIGIT])) return;
   __shared__ uint32_t lds[TPB / WAVE];
   uint32_t *h = hist + (size_t)blockIdx.x * G;
   uint32_t carry = 0;
@@ -257,6 +297,10 @@ __global__ __launch_bounds__(TPB) void k_sort_scan(int pass, uint32_t *__restric
   if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
+// Stable scatter of pass `pass`: slots in (round, wave, lane) order; within a
+// round each wave ranks its lanes by digit with ballots, waves are ordered
+// through per-wave digit counts in LDS, and a per-digit running offset
+// carries the order across rounds.
 __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int items, const uint32_t *__restrict__ key_in,
                                                       const uint32_t *__restrict__ val_in,
                                                       uint32_t *__restrict__ key_out, uint32_t *__restrict__ val_out,
@@ -264,48 +308,61 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int
                                                       const uint32_t *__restrict__ digit_total,
                                                       const uint64_t *__restrict__ meta) {
   if ((uint64_t)pass >= meta[META_PASSES]) return;
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[TPB / WAVE][257];
+  const int width = (int)meta[META_DIGIT];
+  const uint32_t nb = 1u << width, mask = nb - 1u;
+  constexpr int PER = MAX_BUCKETS / TPB;
+  __shared__ uint32_t run[MAX_BUCKETS];
+  __shared__ uint32_t wcnt[TPB / WAVE][MAX_BUCKETS];
   __shared__ uint32_t lds[TPB / WAVE];
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
   {
+    // exclusive scan of the digit totals: each thread owns PER consecutive digits
+    uint32_t loc[PER], s = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const uint32_t d = (uint32_t)(tid * PER + i);
+      loc[i] = d < nb ? digit_total[d] : 0u;
+      s += loc[i];
+    }
     uint32_t tot;
-    const uint32_t ex = block_excl_scan<TPB, uint32_t>(digit_total[tid], lds, &tot);
-    run[tid] = ex + hist[(size_t)tid * G + blockIdx.x];
+    uint32_t ex = block_excl_scan<TPB, uint32_t>(s, lds, &tot);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const uint32_t d = (uint32_t)(tid * PER + i);
+      if (d < nb) run[d] = ex + hist[(size_t)d * G + blockIdx.x];
+      ex += loc[i];
+      for (int ww = 0; ww < TPB / WAVE; ++ww) wcnt[ww][d] = 0;
+    }
   }
-  for (int i = tid; i < (TPB / WAVE) * 257; i += TPB) (&wcnt[0][0])[i] = 0;
   __syncthreads();
   const uint32_t b0 = blockIdx.x * (uint32_t)(items * TPB);
-  const int sh = 8 * pass;
+  const int sh = width * pass;
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int it = 0; it < items; ++it) {
     const uint32_t j = b0 + it * TPB + tid;
     const bool valid = j < NT;
-    uint32_t kk = 0, vv = 0, d = 256;
+    uint32_t kk = 0, vv = 0, d = (uint32_t)MAX_BUCKETS;
     if (valid) {
       kk = key_in[j];
       vv = val_in ? val_in[j] : j;
-      d = (kk >> sh) & 255u;
+      d = (kk >> sh) & mask;
     }
-    const unsigned long long peers = digit_peers(valid, d);
+    const unsigned long long peers = digit_peers(valid, d, width);
     const uint32_t rank = (uint32_t)__popcll(peers & below);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    const bool leader = valid && rank == 0;
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    if (leader) wcnt[w][d] = cnt;
     __syncthreads();
     if (valid) {
-      uint32_t pre = run[d] + rank;
-      for (int ww = 0; ww < w; ++ww) pre += wcnt[ww][d];
-      key_out[pre] = kk;
-      val_out[pre] = vv;
+      uint32_t pos = run[d] + rank;
+      for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][d];
+      key_out[pos] = kk;
+      val_out[pos] = vv;
     }
     __syncthreads();
-    {
-      uint32_t add = 0;
-#pragma unroll
-      for (int ww = 0; ww < TPB / WAVE; ++ww) {
-        add += wcnt[ww][tid];
-        wcnt[ww][tid] = 0;
-      }
-      run[tid] += add;
+    if (leader) {
+      atomicAdd(&run[d], cnt);
+      wcnt[w][d] = 0;
     }
     __syncthreads();
   }
@@ -365,14 +422,10 @@ __global__ __launch_bounds__(TPB) void k_seg_scan(uint32_t *__restrict__ chunk_h
     if (b < G) chunk_heads[b] = carry + ex;
     carry += tot;
   }
-  if (threadIdx.x == 0) meta[META_B] = carry;
-}
-
-__global__ void k_seg_zero(const uint64_t *__restrict__ meta, unsigned long long *__restrict__ acc, int ncomp,
-                           uint32_t NT) {
-  const uint32_t B = (uint32_t)meta[META_B];
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < B; s += gridDim.x * blockDim.x)
-    for (int c = 0; c < ncomp; ++c) acc[(size_t)c * NT + s] = 0ull;
+  if (threadIdx.x == 0) {
+    meta[META_B] = carry;
+    meta[META_DIRTY] = carry;  // accumulators [0, B) are written this frame
+  }
 }
 
 template <int DIM>
@@ -410,7 +463,7 @@ __device__ __forceinline__ void decode_key(uint32_t key, int T, const uint32_t *
 template <int DIM>
 __global__ __launch_bounds__(TPB) void k_seg_reduce(Params p, SortBufs sb, const uint64_t *__restrict__ meta_c,
                                                     uint64_t *__restrict__ meta, const uint32_t *__restrict__ chunk_base,
-                                                    const float *__restrict__ s, const uint32_t *__restrict__ kbase,
+                                                    const float4 *__restrict__ rec, const uint32_t *__restrict__ kbase,
                                                     unsigned long long *__restrict__ acc,
                                                     uint32_t *__restrict__ seg_key, int32_t *__restrict__ seg_t,
                                                     uint32_t *__restrict__ segid) {
@@ -448,23 +501,25 @@ __global__ __launch_bounds__(TPB) void k_seg_reduce(Params p, SortBufs sb, const
     for (int c = 0; c < NC; ++c) val[c] = 0;
     if (valid) {
       const uint32_t v = V ? V[j] : j;
+      const float4 ra = rec[2 * (size_t)v], rb = rec[2 * (size_t)v + 1];
+      const float st[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
       val[0] = 1;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        const float x = s[(size_t)a * NT + v];
+        const float x = st[a];
         const float pix = (float)cell_index(x, 1);
         val[1 + a] = __float2ll_rn((x - pix) * FX_POS);  // x - pix exact, |.| <= 1/2
       }
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        float vel = s[(size_t)(DIM + a) * NT + v];
+        float vel = st[DIM + a];
         if (!(fabsf(vel) < LIM_VEL)) {
           sat = true;
           vel = 0.0f;
         }
         val[1 + DIM + a] = __float2ll_rn(vel * FX_VEL);
       }
-      float in = s[(size_t)(2 * DIM) * NT + v];
+      float in = st[2 * DIM];
       if (!(fabsf(in) < LIM_INT)) {
         sat = true;
         in = 0.0f;
@@ -610,7 +665,8 @@ __device__ __forceinline__ float sub_offset(int a, int q) { return (float)(2 * a
 
 template <int DIM, bool SIR, bool SEP, int Q>
 __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64_t *__restrict__ meta,
-                                             const float *__restrict__ frame, double *__restrict__ ll) {
+                                             const StepDesc *__restrict__ desc, double *__restrict__ ll) {
+  const float *__restrict__ frame = desc->frame;
   const uint32_t E = SIR ? p.NT : (uint32_t)meta[META_B];
   const int lane = lane_id();
   const int P = p.P, R = p.R, P2 = P * P;
@@ -722,7 +778,7 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
 template <int DIM>
 __global__ __launch_bounds__(TPB) void k_norm_bins(Params p, const uint32_t *__restrict__ seg_first,
                                                    const double *__restrict__ ll, const unsigned long long *__restrict__ acc,
-                                                   const int32_t *__restrict__ dpix, int64_t k,
+                                                   const int32_t *__restrict__ dpix, const StepDesc *__restrict__ desc,
                                                    double *__restrict__ wbin, double *__restrict__ tgt,
                                                    double *__restrict__ est, int32_t *__restrict__ tflag,
                                                    uint64_t *__restrict__ meta) {
@@ -762,7 +818,7 @@ __global__ __launch_bounds__(TPB) void k_norm_bins(Params p, const uint32_t *__r
     tgt[t * 4 + 0] = M;
     tgt[t * 4 + 1] = S;
     tgt[t * 4 + 2] = S * S / Q;
-    tgt[t * 4 + 3] = resample_uniform(p.seed, (uint64_t)k, (uint64_t)t);
+    tgt[t * 4 + 3] = resample_uniform(p.seed, (uint64_t)desc->k, (uint64_t)t);
 #pragma unroll
     for (int d = 0; d < D; ++d) est[t * D + d] = X[d] / S;
     tflag[t] = ok ? 0 : 1;
@@ -815,7 +871,7 @@ __global__ __launch_bounds__(TPB) void k_norm_part(Params p, const Tile *__restr
 
 template <int DIM>
 __global__ __launch_bounds__(TPB) void k_norm_comb(Params p, const uint32_t *__restrict__ tfirst,
-                                                   const double *__restrict__ part, int64_t k,
+                                                   const double *__restrict__ part, const StepDesc *__restrict__ desc,
                                                    double *__restrict__ tgt, double *__restrict__ est,
                                                    int32_t *__restrict__ tflag, uint64_t *__restrict__ meta) {
   constexpr int D = 2 * DIM + 1;
@@ -848,7 +904,7 @@ __global__ __launch_bounds__(TPB) void k_norm_comb(Params p, const uint32_t *__r
     tgt[t * 4 + 0] = M;
     tgt[t * 4 + 1] = S;
     tgt[t * 4 + 2] = S * S / Q;
-    tgt[t * 4 + 3] = resample_uniform(p.seed, (uint64_t)k, (uint64_t)t);
+    tgt[t * 4 + 3] = resample_uniform(p.seed, (uint64_t)desc->k, (uint64_t)t);
 #pragma unroll
     for (int d = 0; d < D; ++d) est[t * D + d] = X[d] / S;
     tflag[t] = ok ? 0 : 1;

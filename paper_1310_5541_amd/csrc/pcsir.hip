@@ -21,8 +21,8 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 struct Layout {
-  size_t S0, S1, anc, key, kA, vA, kB, vB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
-      ll, wbin, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
+  size_t S0, S1, rec, anc, key, kA, vA, kB, vB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
+      ll, wbin, desc, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tile_last, tfirst, t256_first, off;
   int sort_items; // keys per thread in the radix sort (chosen to fill the device)
   size_t total;
@@ -94,6 +94,8 @@ void build_tables(const pcsir_config *c, Tables &tb) {
 
 // Keys per thread of the radix sort: enough blocks for about 8 per compute
 // unit on the 256-CU device, at most SORT_ITEMS.
+constexpr int MAX_PASSES = (32 + MAX_DIGIT_BITS - 1) / MAX_DIGIT_BITS;
+
 int sort_items_for(size_t NT) {
   int it = 1;
   while (it < SORT_ITEMS && NT > (size_t)it * TPB * 256 * 8) it *= 2;
@@ -118,14 +120,15 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   };
   L.S0 = take(4 * D * NT);
   L.S1 = take(4 * D * NT);
+  L.rec = take(32 * NT);
   L.anc = take(4 * NT);
   L.key = take(4 * NT);
   L.kA = take(4 * NT);
   L.vA = take(4 * NT);
   L.kB = take(4 * NT);
   L.vB = take(4 * NT);
-  L.hist = take(4 * 256 * (size_t)L.G);
-  L.dtot = take(4 * 256);
+  L.hist = take(4 * (size_t)MAX_BUCKETS * (size_t)L.G);
+  L.dtot = take(4 * (size_t)MAX_BUCKETS);
   L.chunk_heads = take(4 * (size_t)L.Gs);
   L.acc = take(8 * (1 + D) * NT);
   L.seg_key = take(4 * NT);
@@ -136,6 +139,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.dint = take(4 * NT);
   L.ll = take(8 * NT);
   L.wbin = take(8 * NT);
+  L.desc = take(sizeof(StepDesc));
   L.seg_first = take(4 * (T + 1));
   L.bbox_part = take(4 * 6 * (size_t)L.n256);
   L.range = take(8 * T);
@@ -182,6 +186,10 @@ struct pcsir_ctx {
   std::vector<hipEvent_t> ev;
   std::vector<const char *> ev_name;
   int ev_used = 0;
+  // captured step graphs, by (sir, buffer parity, pending gather)
+  int use_graphs = 1;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[2][2][2] = {};
 
   template <typename T>
   T *at(size_t off) const {
@@ -262,28 +270,28 @@ uint32_t grid_stride_blocks(const pcsir_ctx *c, uint32_t work, uint32_t per_bloc
 }
 
 template <int DIM, bool SIR, bool SEP>
-void launch_lik(pcsir_ctx *c, const LikInput &in, const float *frame) {
+void launch_lik(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   const uint32_t grid = grid_stride_blocks(c, c->p.NT, LIK_WAVES);
   const uint64_t *meta = c->at<uint64_t>(c->L.meta);
   double *ll = c->at<double>(c->L.ll);
-  hipStream_t st = c->stream;
+  const StepDesc *desc = c->at<StepDesc>(c->L.desc);
   if (SEP) {
-    k_lik<DIM, SIR, true, 0><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll);
+    k_lik<DIM, SIR, true, 0><<<grid, TPB, 0, st>>>(c->p, in, meta, desc, ll);
     return;
   }
   switch (c->p.q) {
-    case 2: k_lik<DIM, SIR, false, 2><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll); break;
-    case 4: k_lik<DIM, SIR, false, 4><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll); break;
-    case 8: k_lik<DIM, SIR, false, 8><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll); break;
-    default: k_lik<DIM, SIR, false, 0><<<grid, TPB, 0, st>>>(c->p, in, meta, frame, ll); break;
+    case 2: k_lik<DIM, SIR, false, 2><<<grid, TPB, 0, st>>>(c->p, in, meta, desc, ll); break;
+    case 4: k_lik<DIM, SIR, false, 4><<<grid, TPB, 0, st>>>(c->p, in, meta, desc, ll); break;
+    case 8: k_lik<DIM, SIR, false, 8><<<grid, TPB, 0, st>>>(c->p, in, meta, desc, ll); break;
+    default: k_lik<DIM, SIR, false, 0><<<grid, TPB, 0, st>>>(c->p, in, meta, desc, ll); break;
   }
 }
 
 template <int DIM, bool SEP>
-void launch_pcsir(pcsir_ctx *c, const float *frame, int64_t k) {
+void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   const Layout &L = c->L;
   const Params &p = c->p;
-  hipStream_t st = c->stream;
+  const StepDesc *desc = c->at<StepDesc>(L.desc);
   const Tile *t256 = c->at<Tile>(L.tiles256);
   const Tile *tS = c->at<Tile>(L.tilesS);
   const uint32_t *off = c->at<uint32_t>(L.off);
@@ -293,8 +301,9 @@ void launch_pcsir(pcsir_ctx *c, const float *frame, int64_t k) {
   uint64_t *meta = c->at<uint64_t>(L.meta);
 
   mark(c, "propagate");
-  k_propagate<DIM, true><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, k,
-                                                 c->at<int32_t>(L.bbox_part));
+  k_propagate<DIM, true><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc,
+                                                 c->at<int32_t>(L.bbox_part), c->at<float4>(L.rec),
+                                                 c->at<unsigned long long>(L.acc), meta);
   mark(c, "bbox");
   k_bbox_reduce<<<p.T, TPB, 0, st>>>(p.dim, c->at<uint32_t>(L.t256_first), c->at<int32_t>(L.bbox_part),
                                      c->at<int32_t>(L.bbox_cur), c->at<unsigned long long>(L.range));
@@ -305,7 +314,7 @@ void launch_pcsir(pcsir_ctx *c, const float *frame, int64_t k) {
   SortBufs sb = sort_bufs(c);
   uint32_t *hist = c->at<uint32_t>(L.hist);
   uint32_t *dtot = c->at<uint32_t>(L.dtot);
-  for (int pass = 0; pass < 4; ++pass) {
+  for (int pass = 0; pass < MAX_PASSES; ++pass) {
     const uint32_t *kin = pass == 0 ? sb.key_store : ((pass & 1) ? sb.kB : sb.kA);
     const uint32_t *vin = pass == 0 ? nullptr : ((pass & 1) ? sb.vB : sb.vA);
     uint32_t *kout = (uint32_t *)((pass & 1) ? sb.kA : sb.kB);
@@ -313,7 +322,7 @@ void launch_pcsir(pcsir_ctx *c, const float *frame, int64_t k) {
     mark(c, "sort_hist");
     k_sort_hist<<<L.G, TPB, 0, st>>>(pass, p.NT, L.sort_items, kin, hist, L.G, meta);
     mark(c, "sort_scan");
-    k_sort_scan<<<256, TPB, 0, st>>>(pass, hist, L.G, dtot, meta);
+    k_sort_scan<<<MAX_BUCKETS, TPB, 0, st>>>(pass, hist, L.G, dtot, meta);
     mark(c, "sort_scatter");
     k_sort_scatter<<<L.G, TPB, 0, st>>>(pass, p.NT, L.sort_items, kin, vin, kout, vout, hist, L.G, dtot, meta);
   }
@@ -323,10 +332,8 @@ void launch_pcsir(pcsir_ctx *c, const float *frame, int64_t k) {
   k_seg_count<<<L.Gs, TPB, 0, st>>>(p.NT, sb, meta, chunk);
   mark(c, "seg_scan");
   k_seg_scan<<<1, TPB, 0, st>>>(chunk, L.Gs, meta);
-  mark(c, "seg_zero");
-  k_seg_zero<<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(meta, acc, 2 + 2 * DIM, p.NT);
   mark(c, "seg_reduce");
-  k_seg_reduce<DIM><<<L.Gs, TPB, 0, st>>>(p, sb, meta, meta, chunk, sout, c->at<uint32_t>(L.kbase), acc,
+  k_seg_reduce<DIM><<<L.Gs, TPB, 0, st>>>(p, sb, meta, meta, chunk, c->at<float4>(L.rec), c->at<uint32_t>(L.kbase), acc,
                                           c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t),
                                           c->at<uint32_t>(L.segid));
   mark(c, "dummy");
@@ -342,10 +349,10 @@ void launch_pcsir(pcsir_ctx *c, const float *frame, int64_t k) {
   in.state = sout;
   in.off = off;
   mark(c, "likelihood");
-  launch_lik<DIM, false, SEP>(c, in, frame);
+  launch_lik<DIM, false, SEP>(c, in, st);
   mark(c, "normalise");
   k_norm_bins<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.seg_first), c->at<double>(L.ll), acc,
-                                        c->at<int32_t>(L.dpix), k, c->at<double>(L.wbin), c->at<double>(L.tgt),
+                                        c->at<int32_t>(L.dpix), desc, c->at<double>(L.wbin), c->at<double>(L.tgt),
                                         c->at<double>(L.est), c->at<int32_t>(L.tflag), meta);
   WeightSrc ws = weight_src(c);
   mark(c, "cdf_sum");
@@ -361,10 +368,10 @@ void launch_pcsir(pcsir_ctx *c, const float *frame, int64_t k) {
 }
 
 template <int DIM, bool SEP>
-void launch_sir(pcsir_ctx *c, const float *frame, int64_t k) {
+void launch_sir(pcsir_ctx *c, hipStream_t st) {
   const Layout &L = c->L;
   const Params &p = c->p;
-  hipStream_t st = c->stream;
+  const StepDesc *desc = c->at<StepDesc>(L.desc);
   const Tile *t256 = c->at<Tile>(L.tiles256);
   const Tile *tS = c->at<Tile>(L.tilesS);
   const uint32_t *off = c->at<uint32_t>(L.off);
@@ -373,16 +380,17 @@ void launch_sir(pcsir_ctx *c, const float *frame, int64_t k) {
   uint32_t *anc = c->at<uint32_t>(L.anc);
   uint64_t *meta = c->at<uint64_t>(L.meta);
   mark(c, "propagate");
-  k_propagate<DIM, false><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, k, nullptr);
+  k_propagate<DIM, false><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc, nullptr, nullptr,
+                                                  nullptr, meta);
   LikInput in;
   memset(&in, 0, sizeof(in));
   in.state = sout;
   in.off = off;
   mark(c, "likelihood");
-  launch_lik<DIM, true, SEP>(c, in, frame);
+  launch_lik<DIM, true, SEP>(c, in, st);
   mark(c, "normalise");
   k_norm_part<DIM><<<L.nS, TPB, 0, st>>>(p, tS, off, c->at<double>(L.ll), sout, c->at<double>(L.part));
-  k_norm_comb<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.tfirst), c->at<double>(L.part), k,
+  k_norm_comb<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.tfirst), c->at<double>(L.part), desc,
                                         c->at<double>(L.tgt), c->at<double>(L.est), c->at<int32_t>(L.tflag), meta);
   WeightSrc ws = weight_src(c);
   mark(c, "cdf_sum");
@@ -396,18 +404,63 @@ void launch_sir(pcsir_ctx *c, const float *frame, int64_t k) {
   mark(c, "end");
 }
 
+void launch_step(pcsir_ctx *c, bool sir, hipStream_t st) {
+  const bool sep = c->cfg.lik_mode == PCSIR_LIK_SEPARABLE;
+  if (sir) {
+    if (c->cfg.dim == 2) sep ? launch_sir<2, true>(c, st) : launch_sir<2, false>(c, st);
+    else sep ? launch_sir<3, true>(c, st) : launch_sir<3, false>(c, st);
+  } else {
+    if (c->cfg.dim == 2) sep ? launch_pcsir<2, true>(c, st) : launch_pcsir<2, false>(c, st);
+    else sep ? launch_pcsir<3, true>(c, st) : launch_pcsir<3, false>(c, st);
+  }
+}
+
+// Capture the kernel sequence of one step for the current (kind, buffer
+// parity, pending gather) once, on a private stream, and keep the executable.
+pcsir_status step_graph(pcsir_ctx *c, bool sir, hipGraphExec_t *out) {
+  hipGraphExec_t &ex = c->gexec[sir ? 1 : 0][c->cur][c->pending];
+  if (ex) {
+    *out = ex;
+    return PCSIR_OK;
+  }
+  hipError_t e = hipSuccess;
+  if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return check_hip(c, e, "hipStreamCreate");
+  e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return check_hip(c, e, "hipStreamBeginCapture");
+  launch_step(c, sir, c->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t el = hipGetLastError();
+  e = hipStreamEndCapture(c->cap_stream, &g);
+  if (el != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return check_hip(c, el, "kernel launch during capture");
+  }
+  if (e != hipSuccess) return check_hip(c, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    ex = nullptr;
+    return check_hip(c, e, "hipGraphInstantiate");
+  }
+  *out = ex;
+  return PCSIR_OK;
+}
+
 pcsir_status run_step(pcsir_ctx *c, const float *frame, int32_t H, int32_t W, int64_t k, bool sir) {
   if (!c) return PCSIR_E_INVAL;
   if (!frame) return fail(c, PCSIR_E_INVAL, "frame_dev is NULL");
   if (H != c->cfg.frame_h || W != c->cfg.frame_w) return fail(c, PCSIR_E_STATE, "frame size differs from the config");
   if (k < 1) return fail(c, PCSIR_E_INVAL, "frame index k must be >= 1");
-  const bool sep = c->cfg.lik_mode == PCSIR_LIK_SEPARABLE;
-  if (sir) {
-    if (c->cfg.dim == 2) sep ? launch_sir<2, true>(c, frame, k) : launch_sir<2, false>(c, frame, k);
-    else sep ? launch_sir<3, true>(c, frame, k) : launch_sir<3, false>(c, frame, k);
+  k_set_desc<<<1, 1, 0, c->stream>>>(c->at<StepDesc>(c->L.desc), frame, k);
+  if (c->use_graphs && !c->timing) {
+    hipGraphExec_t ex = nullptr;
+    const pcsir_status s = step_graph(c, sir, &ex);
+    if (s != PCSIR_OK) return s;
+    const hipError_t e = hipGraphLaunch(ex, c->stream);
+    if (e != hipSuccess) return check_hip(c, e, "hipGraphLaunch");
   } else {
-    if (c->cfg.dim == 2) sep ? launch_pcsir<2, true>(c, frame, k) : launch_pcsir<2, false>(c, frame, k);
-    else sep ? launch_pcsir<3, true>(c, frame, k) : launch_pcsir<3, false>(c, frame, k);
+    launch_step(c, sir, c->stream);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return check_hip(c, e, "kernel launch");
@@ -494,6 +547,7 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   h2d(L.t256_first, c->tb.t256_first.data(), 4 * c->tb.t256_first.size());
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.meta, 0, 8 * META_N, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tflag, 0, 4 * (size_t)T, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.acc, 0, 8 * (size_t)(1 + D) * c->NT, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->state(0), init_state_dev, 4 * (size_t)D * c->NT, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) {
@@ -542,6 +596,11 @@ pcsir_status pcsir_destroy(pcsir_ctx *c) {
   if (e != hipSuccess) s = PCSIR_E_HIP;
   else s = pull_device_status(c);
   for (hipEvent_t ev : c->ev) hipEventDestroy(ev);
+  for (auto &a : c->gexec)
+    for (auto &b : a)
+      for (auto &x : b)
+        if (x) hipGraphExecDestroy(x);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   delete c;
   return s;
 }
@@ -564,8 +623,26 @@ pcsir_status pcsir_set_particles(pcsir_ctx *c, const float *src_dev) {
   return check_hip(c, e, "pcsir_set_particles");
 }
 
+pcsir_status pcsir_set_graphs(pcsir_ctx *c, int32_t on) {
+  if (!c) return PCSIR_E_INVAL;
+  c->use_graphs = on ? 1 : 0;
+  return PCSIR_OK;
+}
+
+void drop_graphs(pcsir_ctx *c) {
+  hipStreamSynchronize(c->stream);
+  for (auto &a : c->gexec)
+    for (auto &b : a)
+      for (auto &x : b)
+        if (x) {
+          hipGraphExecDestroy(x);
+          x = nullptr;
+        }
+}
+
 pcsir_status pcsir_set_debug(pcsir_ctx *c, int32_t on) {
   if (!c) return PCSIR_E_INVAL;
+  if (c->debug != (on ? 1 : 0)) drop_graphs(c);  // captured graphs hold the debug pointers
   c->debug = on ? 1 : 0;
   return PCSIR_OK;
 }
