@@ -53,18 +53,20 @@ def parse():
     return ap.parse_args()
 
 
-def bytes_per_particle(kind: str, D: int, passes: int) -> dict:
-    """Algorithmic HBM bytes per particle of each kernel (see the design notes)."""
-    b = {
-        "propagate": 4 * D + 4 + 4 * D,          # parent state + ancestor index in, new state out
-        "keys": 4 * 2 + 4,                        # x, y in; key out
-        "sort_scatter": 8 + 8,                    # (key, index) in and out, per pass
-        "sort_hist": 4,                           # key in, per pass
-        "seg_reduce": 8 + 4 * D,                  # sorted (key, index) + gathered state
-        "cdf_sum": 4,                             # key (pcSIR) / log-likelihood (SIR)
-        "resample": 4 + 4,                        # key / log-likelihood in, s(j) out
+def bytes_per_particle(D: int) -> dict:
+    """Algorithmic HBM bytes per particle of each HBM-bound kernel of the pcSIR
+    step (reads + writes the kernel cannot avoid); sort kernels per pass."""
+    return {
+        "propagate": 4 * D + 4 + 4 * D,   # parent state + ancestor index in, new state out
+        "keys": 4 * 2 + 4,                 # x, y in; cell key out
+        "sort_hist": 4,                    # key in
+        "sort_scatter": 4 + 4,             # key in, key out
+        "seg_count": 4,                    # sorted key in
+        "seg_mark": 4,                     # sorted key in
+        "bin_sums": 4 + 4 * D + 4,         # key + state in, bin number out
+        "cdf_sum": 4,                      # bin number in
+        "resample": 4 + 4,                 # bin number in, parent index out
     }
-    return b
 
 
 def main():
@@ -187,7 +189,7 @@ def main():
         return out
 
     k_pc, k_sir = summarise(per_pc), summarise(per_sir)
-    bpp = bytes_per_particle("pcsir", D, passes)
+    bpp = bytes_per_particle(D)
     # dominant kernel of the pcSIR step
     dom = max(k_pc, key=k_pc.get)
     if dom in bpp:

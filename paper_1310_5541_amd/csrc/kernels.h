@@ -13,6 +13,7 @@ constexpr int SEG_CHUNK = TPB * SEG_ITEMS;
 constexpr int SCAN_ITEMS = 4;       // particles per thread in the weight scan
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 constexpr int LIK_WAVES = 4;        // likelihood evaluations per block (one per wave)
+constexpr int BIN_TILES = 4;        // scan tiles of one target per block of the bin sums
 
 // Fixed-point scales of the bin sums (integer sums are exact and order-free).
 constexpr float FX_POS = 4294967296.0f;  // 2^32: offsets from the cell's pixel, |d| <= 1/2
@@ -67,17 +68,14 @@ struct Tile {
 // of the previous frame's resampling is fused into the load. With KEYS, the
 // exact cell indices of the new positions are reduced to a per-target
 // bounding box (integer atomics).
-// With KEYS (pcSIR) it also writes each particle's state as one packed
-// 32-byte record (components in SoA order, zero padded), so that the bin sums
-// gather one sector per particle in sorted order, and it clears the bin
-// accumulators that the previous frame used (meta[META_DIRTY] of them).
+// With KEYS (pcSIR) it also clears the bin accumulators that the previous
+// frame used (meta[META_DIRTY] of them).
 template <int DIM, bool KEYS>
 __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restrict__ tiles,
                                                    const uint32_t *__restrict__ off, const float *__restrict__ sin,
                                                    float *__restrict__ sout, const uint32_t *__restrict__ anc,
                                                    int pending, const StepDesc *__restrict__ desc,
-                                                   int32_t *__restrict__ bbox_part,
-                                                   float4 *__restrict__ rec, unsigned long long *__restrict__ acc,
+                                                   int32_t *__restrict__ bbox_part, unsigned long long *__restrict__ acc,
                                                    const uint64_t *__restrict__ meta) {
   constexpr int D = 2 * DIM + 1;
   __shared__ int32_t red[TPB / WAVE];
@@ -116,11 +114,6 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
         kmin[a] = c;
         kmax[a] = c;
       }
-      float r8[8];
-#pragma unroll
-      for (int d = 0; d < 8; ++d) r8[d] = d < D ? nx[d] : 0.0f;
-      rec[2 * (size_t)g] = make_float4(r8[0], r8[1], r8[2], r8[3]);
-      rec[2 * (size_t)g + 1] = make_float4(r8[4], r8[5], r8[6], r8[7]);
       const uint32_t dirty = (uint32_t)meta[META_DIRTY];
       if (g < dirty) {
 #pragma unroll
@@ -302,8 +295,7 @@ __global__ __launch_bounds__(TPB) void k_sort_scan(int pass, uint32_t *__restric
 // through per-wave digit counts in LDS, and a per-digit running offset
 // carries the order across rounds.
 __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int items, const uint32_t *__restrict__ key_in,
-                                                      const uint32_t *__restrict__ val_in,
-                                                      uint32_t *__restrict__ key_out, uint32_t *__restrict__ val_out,
+                                                      uint32_t *__restrict__ key_out,
                                                       const uint32_t *__restrict__ hist, uint32_t G,
                                                       const uint32_t *__restrict__ digit_total,
                                                       const uint64_t *__restrict__ meta) {
@@ -341,10 +333,9 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int
   for (int it = 0; it < items; ++it) {
     const uint32_t j = b0 + it * TPB + tid;
     const bool valid = j < NT;
-    uint32_t kk = 0, vv = 0, d = (uint32_t)MAX_BUCKETS;
+    uint32_t kk = 0, d = (uint32_t)MAX_BUCKETS;
     if (valid) {
       kk = key_in[j];
-      vv = val_in ? val_in[j] : j;
       d = (kk >> sh) & mask;
     }
     const unsigned long long peers = digit_peers(valid, d, width);
@@ -357,7 +348,6 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int
       uint32_t pos = run[d] + rank;
       for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][d];
       key_out[pos] = kk;
-      val_out[pos] = vv;
     }
     __syncthreads();
     if (leader) {
@@ -369,27 +359,20 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int
 }
 
 // Sorted buffers chosen on the device from the number of passes that ran.
+// Only the keys are sorted: a bin needs nothing but its key; the members'
+// sums are formed afterwards in storage order (k_bin_sums).
 struct SortBufs {
   const uint32_t *key_store;  // storage order (0 passes)
-  const uint32_t *kA, *vA, *kB, *vB;
+  const uint32_t *kA, *kB;
 };
-__device__ __forceinline__ void sorted_arrays(const SortBufs &sb, uint64_t passes, const uint32_t *&K,
-                                              const uint32_t *&V) {
-  if (passes == 0) {
-    K = sb.key_store;
-    V = nullptr;
-  } else if (passes & 1) {
-    K = sb.kB;
-    V = sb.vB;
-  } else {
-    K = sb.kA;
-    V = sb.vA;
-  }
+__device__ __forceinline__ const uint32_t *sorted_keys(const SortBufs &sb, uint64_t passes) {
+  return passes == 0 ? sb.key_store : ((passes & 1) ? sb.kB : sb.kA);
 }
 
 // ---------------------------------------------------------------- segments (bins)
-// Sorted slots are processed in rounds of 64 consecutive slots per wave; a
-// block of 4 waves covers SEG_CHUNK slots. A bin is a run of equal keys.
+// A bin is a run of equal keys in sorted order. Bins are numbered in sorted
+// order: chunk head counts, their scan, then one pass that records each bin's
+// key, target and the first bin of every target.
 __device__ __forceinline__ bool seg_head(const uint32_t *__restrict__ K, uint32_t j) {
   return j == 0 || K[j] != K[j - 1];
 }
@@ -397,12 +380,11 @@ __device__ __forceinline__ bool seg_head(const uint32_t *__restrict__ K, uint32_
 __global__ __launch_bounds__(TPB) void k_seg_count(uint32_t NT, SortBufs sb, const uint64_t *__restrict__ meta,
                                                    uint32_t *__restrict__ chunk_heads) {
   __shared__ uint32_t lds[TPB / WAVE];
-  const uint32_t *K, *V;
-  sorted_arrays(sb, meta[META_PASSES], K, V);
-  const uint32_t j0 = blockIdx.x * SEG_CHUNK;
+  const uint32_t *K = sorted_keys(sb, meta[META_PASSES]);
+  const uint32_t j0 = blockIdx.x * SEG_CHUNK + threadIdx.x * SEG_ITEMS;
   uint32_t c = 0;
   for (int it = 0; it < SEG_ITEMS; ++it) {
-    const uint32_t j = j0 + it * TPB + threadIdx.x;
+    const uint32_t j = j0 + it;
     if (j < NT && seg_head(K, j)) ++c;
   }
   const uint32_t s = block_sum<TPB, uint32_t>(c, lds);
@@ -410,8 +392,8 @@ __global__ __launch_bounds__(TPB) void k_seg_count(uint32_t NT, SortBufs sb, con
 }
 
 // Exclusive scan of chunk head counts (one block); writes the bin count B.
-__global__ __launch_bounds__(TPB) void k_seg_scan(uint32_t *__restrict__ chunk_heads, uint32_t G,
-                                                  uint64_t *__restrict__ meta) {
+__global__ __launch_bounds__(TPB) void k_seg_scan(int T, uint32_t *__restrict__ chunk_heads, uint32_t G,
+                                                  uint64_t *__restrict__ meta, uint32_t *__restrict__ seg_first) {
   __shared__ uint32_t lds[TPB / WAVE];
   uint32_t carry = 0;
   for (uint32_t b0 = 0; b0 < G; b0 += TPB) {
@@ -425,6 +407,7 @@ __global__ __launch_bounds__(TPB) void k_seg_scan(uint32_t *__restrict__ chunk_h
   if (threadIdx.x == 0) {
     meta[META_B] = carry;
     meta[META_DIRTY] = carry;  // accumulators [0, B) are written this frame
+    seg_first[T] = carry;
   }
 }
 
@@ -452,105 +435,168 @@ __device__ __forceinline__ void decode_key(uint32_t key, int T, const uint32_t *
   }
 }
 
-// Sums of the members of every bin as exact fixed-point integers: count,
-// offsets of the positions from the pixel that holds them (the pixel of a
-// cell is the pixel of each member, so x - pixel is exact and |.| <= 1/2),
-// velocities and intensity. Within a round the wave forms segmented inclusive
-// sums over its 64 slots (shuffles, flag = first slot of a bin); the lane at
-// the end of each run adds its sums to the bin with 64-bit integer atomics
-// (exact, hence independent of order). Also records each bin's key and
-// target, and every particle's bin number (storage order).
-template <int DIM>
-__global__ __launch_bounds__(TPB) void k_seg_reduce(Params p, SortBufs sb, const uint64_t *__restrict__ meta_c,
-                                                    uint64_t *__restrict__ meta, const uint32_t *__restrict__ chunk_base,
-                                                    const float4 *__restrict__ rec, const uint32_t *__restrict__ kbase,
-                                                    unsigned long long *__restrict__ acc,
-                                                    uint32_t *__restrict__ seg_key, int32_t *__restrict__ seg_t,
-                                                    uint32_t *__restrict__ segid) {
-  constexpr int D = 2 * DIM + 1;
-  constexpr int NC = 1 + D;
-  __shared__ uint32_t wheads[TPB / WAVE];
-  const uint32_t NT = p.NT;
-  const uint32_t *K, *V;
-  sorted_arrays(sb, meta_c[META_PASSES], K, V);
-  const int lane = lane_id(), w = wave_id();
-  const uint32_t wb = blockIdx.x * SEG_CHUNK + (uint32_t)w * (WAVE * SEG_ITEMS);
-  // heads before this wave's range
-  uint32_t cnt = 0;
-  for (int r = 0; r < SEG_ITEMS; ++r) {
-    const uint32_t j = wb + r * WAVE + lane;
-    cnt += (uint32_t)__popcll(__ballot(j < NT && seg_head(K, j)));
+__device__ __forceinline__ int key_target(uint32_t key, int T, const uint32_t *__restrict__ kbase) {
+  int lo = 0, hi = T - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (kbase[mid] <= key) lo = mid;
+    else hi = mid - 1;
   }
-  if (lane == 0) wheads[w] = cnt;
-  __syncthreads();
-  uint32_t running = chunk_base[blockIdx.x];
-  for (int i = 0; i < w; ++i) running += wheads[i];
-  const unsigned long long incl = (lane == WAVE - 1) ? ~0ull : ((2ull << lane) - 1ull);
-  bool sat = false;
-  for (int r = 0; r < SEG_ITEMS; ++r) {
-    const uint32_t j = wb + r * WAVE + lane;
-    if (wb + r * WAVE >= NT) break;  // wave-uniform
-    const bool valid = j < NT;
-    const uint32_t kj = valid ? K[j] : 0u;
-    const bool head = valid && (j == 0 || kj != K[j - 1]);
-    const unsigned long long hm = __ballot(head);
-    const uint32_t sid = running + (uint32_t)__popcll(hm & incl) - 1u;
-    running += (uint32_t)__popcll(hm);
-    long long val[NC];
+  return lo;
+}
+
+// Record every bin: its key, its target, and the first bin of each target.
+__global__ __launch_bounds__(TPB) void k_seg_mark(Params p, SortBufs sb, const uint64_t *__restrict__ meta,
+                                                  const uint32_t *__restrict__ chunk_base,
+                                                  const uint32_t *__restrict__ kbase, uint32_t *__restrict__ seg_key,
+                                                  int32_t *__restrict__ seg_t, uint32_t *__restrict__ seg_first) {
+  __shared__ uint32_t lds[TPB / WAVE];
+  const uint32_t NT = p.NT;
+  const uint32_t *K = sorted_keys(sb, meta[META_PASSES]);
+  const uint32_t j0 = blockIdx.x * SEG_CHUNK + threadIdx.x * SEG_ITEMS;
+  uint32_t c = 0;
+  for (int it = 0; it < SEG_ITEMS; ++it) {
+    const uint32_t j = j0 + it;
+    if (j < NT && seg_head(K, j)) ++c;
+  }
+  uint32_t tot;
+  uint32_t heads = chunk_base[blockIdx.x] + block_excl_scan<TPB, uint32_t>(c, lds, &tot);
+  for (int it = 0; it < SEG_ITEMS; ++it) {
+    const uint32_t j = j0 + it;
+    if (j >= NT) break;
+    const uint32_t kj = K[j];
+    if (j == 0 || kj != K[j - 1]) {
+      const uint32_t sid = heads++;
+      const int t = key_target(kj, p.T, kbase);
+      seg_key[sid] = kj;
+      seg_t[sid] = t;
+      if (j == 0 || key_target(K[j - 1], p.T, kbase) != t) seg_first[t] = sid;
+    }
+  }
+}
+
+// Members' sums of every bin as exact fixed-point integers: count, offsets of
+// the positions from the pixel that holds them (the pixel of a cell is the
+// pixel of each member, so x - pixel is exact and |.| <= 1/2), velocities and
+// intensity. Particles are read in storage order (coalesced); a block holds
+// one target's tile, finds each particle's bin by binary search of its key
+// among the target's sorted bin keys (staged in LDS), and accumulates in LDS
+// with 64-bit integer atomics before one flush per bin to HBM. Integer sums
+// are exact, so the result does not depend on order. Targets with more bins
+// than the LDS table holds add straight into the global sums. Also writes
+// every particle's bin number (storage order).
+template <int DIM>
+struct BinLds {
+  static constexpr int NC = 2 + 2 * DIM;                // count + D components
+  static constexpr int BINS = DIM == 2 ? 1024 : 896;    // table fits in 64 KB with the keys
+};
+
+// Bin-sum work item: up to BIN_TILES * SCAN_TILE consecutive particles of one target.
+struct BinTile {
+  int32_t t;
+  uint32_t i0, i1;  // particles [i0, i1) of target t
+};
+
+template <int DIM>
+__global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__restrict__ tiles,
+                                                  const uint32_t *__restrict__ off, const float *__restrict__ s,
+                                                  const uint32_t *__restrict__ key, const uint32_t *__restrict__ seg_key,
+                                                  const uint32_t *__restrict__ seg_first,
+                                                  unsigned long long *__restrict__ acc, uint32_t *__restrict__ segid,
+                                                  uint64_t *__restrict__ meta) {
+  constexpr int D = 2 * DIM + 1;
+  constexpr int NC = BinLds<DIM>::NC;
+  constexpr int BINS = BinLds<DIM>::BINS;
+  constexpr int R = 4;  // particles per thread per round, loaded together
+  __shared__ uint32_t bkey[BINS];
+  __shared__ unsigned long long bacc[NC][BINS];
+  const uint32_t NT = p.NT;
+  const BinTile tl = tiles[blockIdx.x];
+  const int t = tl.t;
+  const uint32_t base = off[t];
+  const uint32_t s0 = seg_first[t], nb = seg_first[t + 1] - s0;
+  const bool local = nb <= (uint32_t)BINS;
+  if (local) {
+    for (uint32_t b = threadIdx.x; b < nb; b += TPB) {
+      bkey[b] = seg_key[s0 + b];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) val[c] = 0;
-    if (valid) {
-      const uint32_t v = V ? V[j] : j;
-      const float4 ra = rec[2 * (size_t)v], rb = rec[2 * (size_t)v + 1];
-      const float st[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+      for (int c = 0; c < NC; ++c) bacc[c][b] = 0ull;
+    }
+  }
+  __syncthreads();
+  bool sat = false;
+  for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * TPB) {
+    uint32_t kk[R];
+    float x[R][D];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const uint32_t i = r0 + q * TPB + threadIdx.x;
+      if (i < tl.i1) {
+        const uint32_t g = base + i;
+        kk[q] = key[g];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + g];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const uint32_t i = r0 + q * TPB + threadIdx.x;
+      if (i >= tl.i1) continue;
+      const uint32_t g = base + i;
+      uint32_t lo = 0, hi = nb - 1;
+      if (local) {
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (bkey[mid] < kk[q]) lo = mid + 1;
+          else hi = mid;
+        }
+      } else {
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (seg_key[s0 + mid] < kk[q]) lo = mid + 1;
+          else hi = mid;
+        }
+      }
+      segid[g] = s0 + lo;
+      long long val[NC];
       val[0] = 1;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        const float x = st[a];
-        const float pix = (float)cell_index(x, 1);
-        val[1 + a] = __float2ll_rn((x - pix) * FX_POS);  // x - pix exact, |.| <= 1/2
+        const float pix = (float)cell_index(x[q][a], 1);
+        val[1 + a] = __float2ll_rn((x[q][a] - pix) * FX_POS);  // x - pix exact, |.| <= 1/2
       }
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        float vel = st[DIM + a];
+        float vel = x[q][DIM + a];
         if (!(fabsf(vel) < LIM_VEL)) {
           sat = true;
           vel = 0.0f;
         }
         val[1 + DIM + a] = __float2ll_rn(vel * FX_VEL);
       }
-      float in = st[2 * DIM];
-      if (!(fabsf(in) < LIM_INT)) {
-        sat = true;
-        in = 0.0f;
+      {
+        float in = x[q][2 * DIM];
+        if (!(fabsf(in) < LIM_INT)) {
+          sat = true;
+          in = 0.0f;
+        }
+        val[1 + 2 * DIM] = __float2ll_rn(in * FX_INT);
       }
-      val[1 + 2 * DIM] = __float2ll_rn(in * FX_INT);
-      segid[v] = sid;
-      if (head) {
-        int t;
-        int32_t cell[3];
-        decode_key<DIM>(kj, p.T, kbase, p.bbox_cur, t, cell);
-        seg_key[sid] = kj;
-        seg_t[sid] = t;
+      if (local) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) atomicAdd(&bacc[c][lo], (unsigned long long)val[c]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + s0 + lo], (unsigned long long)val[c]);
       }
     }
-    // segmented inclusive scan over the wave (flag: a bin starts here, or no slot)
-    bool f = head || !valid;
+  }
+  __syncthreads();
+  if (local) {
+    for (uint32_t b = threadIdx.x; b < nb; b += TPB) {
+      if (bacc[0][b] == 0ull) continue;
 #pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-      const bool fu = __shfl_up((int)f, o, WAVE) != 0;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const long long vu = __shfl_up(val[c], o, WAVE);
-        if (lane >= o && !f) val[c] += vu;
-      }
-      if (lane >= o) f = f || fu;
-    }
-    const bool next_starts = __shfl_down((int)(head || !valid), 1, WAVE) != 0;
-    const bool run_end = valid && (lane == WAVE - 1 || next_starts);
-    if (run_end) {
-#pragma unroll
-      for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + sid], (unsigned long long)val[c]);
+      for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + s0 + b], bacc[c][b]);
     }
   }
   if (sat) atomicOr((unsigned long long *)&meta[META_ERR], (unsigned long long)ERR_FIXED_SAT);
@@ -587,9 +633,6 @@ __global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsig
       doff[(size_t)a * NT + sidx] = off;
     }
     dint[sidx] = (float)((double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + sidx] / (double)FX_INT / n);
-    const int ts = seg_t[sidx];
-    if (sidx == 0 || seg_t[sidx - 1] != ts) seg_first[ts] = sidx;
-    if (sidx == B - 1) seg_first[p.T] = B;
   }
 }
 
@@ -981,11 +1024,16 @@ __device__ __forceinline__ uint32_t count_below(double c, double u, uint32_t n) 
   return j;
 }
 
-// Systematic resampling fused with the cumulative-weight scan: particle l
-// owns the new particles j with C_{l-1} <= theta_j < C_l (the last particle
-// also takes any j left above C_{n-1} by rounding), which is
-// s(j) = min{ l : C_l > theta_j }. Every boundary C is taken from a single
-// source (the next thread's or tile's start), so the ranges partition [0, n).
+// Systematic resampling fused with the cumulative-weight scan. The new
+// particle j takes the parent s(j) = min{ l : C_l > theta_j }, theta_j =
+// (j + u) / n; the last particle also takes any j left above C_{n-1} by
+// rounding. Each tile first forms the cumulative weights of its particles
+// (block scan), with every boundary taken from one source (the next thread's
+// or tile's start, made non-decreasing), so consecutive tiles partition the
+// new particles. The tile's new particles [count(tile start), count(tile end))
+// are then dealt to the threads in interleaved order (coalesced writes, and
+// no thread serialises the many offspring of a heavy particle); each finds its
+// parent by binary search over the tile's cumulative weights in LDS.
 template <bool SIR>
 __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
                                                       const uint32_t *__restrict__ tile_last,
@@ -994,9 +1042,11 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
                                                       double *__restrict__ cdf_dbg) {
   __shared__ double lds[TPB / WAVE];
   __shared__ double bound[TPB + 1];
+  __shared__ double cl[SCAN_TILE];
   const Tile tl = tiles[blockIdx.x];
   const int t = tl.t;
   const uint32_t base = off[t], n = off[t + 1] - base;
+  const uint32_t m = min((uint32_t)SCAN_TILE, n - tl.i0);  // particles in this tile
   const double u = ws.tgt[t * 4 + 3];
   double w[SCAN_ITEMS];
   double loc = 0.0;
@@ -1018,9 +1068,6 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
   }
   if (threadIdx.x == 0) bound[TPB] = tile_end;
   __syncthreads();
-  const double start = bound[threadIdx.x];
-  double end = bound[threadIdx.x + 1];
-  if (end < start) end = start;
   if (tflag[t]) {
     // non-finite normalisation: keep the particles (identity resampling)
 #pragma unroll
@@ -1030,28 +1077,52 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
     }
     return;
   }
+  const double start = bound[threadIdx.x];
+  double end = bound[threadIdx.x + 1];
+  if (end < start) end = start;
   double run = 0.0;
   double cprev = start;
-  uint32_t lo = count_below(start, u, n);
 #pragma unroll
   for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    const uint32_t li = threadIdx.x * SCAN_ITEMS + it;
+    const uint32_t i = tl.i0 + li;
     if (i >= n) break;
     run += w[it];
     double c;
     if (i + 1 == n) {
-      c = pre + (ex + run);  // the target's total; every j left over goes to this particle
+      c = pre + (ex + run);  // the target's total
       c = c < cprev ? cprev : c;
+      if (cdf_dbg) cdf_dbg[base + i] = c;
+      cl[li] = INFINITY;     // the last particle takes every j left over
     } else {
       c = (it == SCAN_ITEMS - 1) ? end : pre + (ex + run);
       c = c < cprev ? cprev : (c > end ? end : c);
+      if (cdf_dbg) cdf_dbg[base + i] = c;
+      cl[li] = c;
     }
-    uint32_t hi = (i + 1 == n) ? n : count_below(c, u, n);
-    if (hi < lo) hi = lo;
-    for (uint32_t j = lo; j < hi; ++j) anc[base + j] = i;
-    if (cdf_dbg) cdf_dbg[base + i] = c;
-    lo = hi;
     cprev = c;
+  }
+  __syncthreads();
+  const uint32_t jlo = count_below(pre, u, n);
+  const uint32_t jhi = last_tile ? n : count_below(tile_end, u, n);
+  const double dn = (double)n;
+  uint32_t prev = 0;  // parents are non-decreasing in j: search forward from the last one
+  for (uint32_t j = jlo + threadIdx.x; j < jhi; j += TPB) {
+    const double theta = ((double)j + u) / dn;
+    // smallest l >= prev with cl[l] > theta (cl[m-1] > theta for every j < jhi)
+    uint32_t lo = prev, step = 1, hi = prev;
+    while (hi < m - 1 && !(cl[hi] > theta)) {
+      lo = hi + 1;
+      hi = min(hi + step, m - 1);
+      step *= 2;
+    }
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (cl[mid] > theta) hi = mid;
+      else lo = mid + 1;
+    }
+    prev = lo;
+    anc[base + j] = tl.i0 + lo;
   }
 }
 

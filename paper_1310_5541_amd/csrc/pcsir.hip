@@ -21,19 +21,21 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 struct Layout {
-  size_t S0, S1, rec, anc, key, kA, vA, kB, vB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
+  size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
       ll, wbin, desc, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
-      tiles256, tilesS, tile_last, tfirst, t256_first, off;
+      tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off;
   int sort_items; // keys per thread in the radix sort (chosen to fill the device)
   size_t total;
   uint32_t G;    // sort chunks
   uint32_t Gs;   // segment chunks
   uint32_t n256; // propagate tiles
   uint32_t nS;   // scan tiles
+  uint32_t nB;   // bin-sum tiles
 };
 
 struct Tables {
   std::vector<Tile> t256, tS;
+  std::vector<BinTile> tB;
   std::vector<uint32_t> tile_last, tfirst, t256_first, off;
 };
 
@@ -77,6 +79,7 @@ void build_tables(const pcsir_config *c, Tables &tb) {
   tb.t256.clear();
   tb.tS.clear();
   tb.tile_last.clear();
+  tb.tB.clear();
   for (int t = 0; t < T; ++t) {
     const uint32_t n = (uint32_t)c->n_particles[t];
     tb.off[t + 1] = tb.off[t] + n;
@@ -87,6 +90,8 @@ void build_tables(const pcsir_config *c, Tables &tb) {
       tb.tS.push_back(Tile{t, i0});
       tb.tile_last.push_back(i0 + SCAN_TILE >= n ? 1u : 0u);
     }
+    for (uint32_t i0 = 0; i0 < n; i0 += BIN_TILES * SCAN_TILE)
+      tb.tB.push_back(BinTile{t, i0, std::min<uint32_t>(n, i0 + BIN_TILES * SCAN_TILE)});
   }
   tb.tfirst[T] = (uint32_t)tb.tS.size();
   tb.t256_first[T] = (uint32_t)tb.t256.size();
@@ -112,6 +117,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.Gs = (uint32_t)((NT + SEG_CHUNK - 1) / SEG_CHUNK);
   L.n256 = (uint32_t)tb.t256.size();
   L.nS = (uint32_t)tb.tS.size();
+  L.nB = (uint32_t)tb.tB.size();
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -120,13 +126,10 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   };
   L.S0 = take(4 * D * NT);
   L.S1 = take(4 * D * NT);
-  L.rec = take(32 * NT);
   L.anc = take(4 * NT);
   L.key = take(4 * NT);
   L.kA = take(4 * NT);
-  L.vA = take(4 * NT);
   L.kB = take(4 * NT);
-  L.vB = take(4 * NT);
   L.hist = take(4 * (size_t)MAX_BUCKETS * (size_t)L.G);
   L.dtot = take(4 * (size_t)MAX_BUCKETS);
   L.chunk_heads = take(4 * (size_t)L.Gs);
@@ -155,6 +158,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.cdf = take(8 * NT);
   L.tiles256 = take(sizeof(Tile) * (size_t)L.n256);
   L.tilesS = take(sizeof(Tile) * (size_t)L.nS);
+  L.tilesB = take(sizeof(BinTile) * (size_t)L.nB);
   L.tile_last = take(4 * (size_t)L.nS);
   L.tfirst = take(4 * (T + 1));
   L.t256_first = take(4 * (T + 1));
@@ -248,9 +252,7 @@ SortBufs sort_bufs(const pcsir_ctx *c) {
   SortBufs sb;
   sb.key_store = c->at<uint32_t>(c->L.key);
   sb.kA = c->at<uint32_t>(c->L.kA);
-  sb.vA = c->at<uint32_t>(c->L.vA);
   sb.kB = c->at<uint32_t>(c->L.kB);
-  sb.vB = c->at<uint32_t>(c->L.vB);
   return sb;
 }
 
@@ -302,8 +304,7 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
 
   mark(c, "propagate");
   k_propagate<DIM, true><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc,
-                                                 c->at<int32_t>(L.bbox_part), c->at<float4>(L.rec),
-                                                 c->at<unsigned long long>(L.acc), meta);
+                                                 c->at<int32_t>(L.bbox_part), c->at<unsigned long long>(L.acc), meta);
   mark(c, "bbox");
   k_bbox_reduce<<<p.T, TPB, 0, st>>>(p.dim, c->at<uint32_t>(L.t256_first), c->at<int32_t>(L.bbox_part),
                                      c->at<int32_t>(L.bbox_cur), c->at<unsigned long long>(L.range));
@@ -316,26 +317,26 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   uint32_t *dtot = c->at<uint32_t>(L.dtot);
   for (int pass = 0; pass < MAX_PASSES; ++pass) {
     const uint32_t *kin = pass == 0 ? sb.key_store : ((pass & 1) ? sb.kB : sb.kA);
-    const uint32_t *vin = pass == 0 ? nullptr : ((pass & 1) ? sb.vB : sb.vA);
     uint32_t *kout = (uint32_t *)((pass & 1) ? sb.kA : sb.kB);
-    uint32_t *vout = (uint32_t *)((pass & 1) ? sb.vA : sb.vB);
     mark(c, "sort_hist");
     k_sort_hist<<<L.G, TPB, 0, st>>>(pass, p.NT, L.sort_items, kin, hist, L.G, meta);
     mark(c, "sort_scan");
     k_sort_scan<<<MAX_BUCKETS, TPB, 0, st>>>(pass, hist, L.G, dtot, meta);
     mark(c, "sort_scatter");
-    k_sort_scatter<<<L.G, TPB, 0, st>>>(pass, p.NT, L.sort_items, kin, vin, kout, vout, hist, L.G, dtot, meta);
+    k_sort_scatter<<<L.G, TPB, 0, st>>>(pass, p.NT, L.sort_items, kin, kout, hist, L.G, dtot, meta);
   }
   uint32_t *chunk = c->at<uint32_t>(L.chunk_heads);
   unsigned long long *acc = c->at<unsigned long long>(L.acc);
   mark(c, "seg_count");
   k_seg_count<<<L.Gs, TPB, 0, st>>>(p.NT, sb, meta, chunk);
   mark(c, "seg_scan");
-  k_seg_scan<<<1, TPB, 0, st>>>(chunk, L.Gs, meta);
-  mark(c, "seg_reduce");
-  k_seg_reduce<DIM><<<L.Gs, TPB, 0, st>>>(p, sb, meta, meta, chunk, c->at<float4>(L.rec), c->at<uint32_t>(L.kbase), acc,
-                                          c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t),
-                                          c->at<uint32_t>(L.segid));
+  k_seg_scan<<<1, TPB, 0, st>>>(p.T, chunk, L.Gs, meta, c->at<uint32_t>(L.seg_first));
+  mark(c, "seg_mark");
+  k_seg_mark<<<L.Gs, TPB, 0, st>>>(p, sb, meta, chunk, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
+                                   c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.seg_first));
+  mark(c, "bin_sums");
+  k_bin_sums<DIM><<<L.nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<uint32_t>(L.key), c->at<uint32_t>(L.seg_key),
+                                        c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta);
   mark(c, "dummy");
   k_dummy<DIM><<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(
       p, meta, acc, c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.kbase),
@@ -381,7 +382,7 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
   uint64_t *meta = c->at<uint64_t>(L.meta);
   mark(c, "propagate");
   k_propagate<DIM, false><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc, nullptr, nullptr,
-                                                  nullptr, meta);
+                                                  meta);
   LikInput in;
   memset(&in, 0, sizeof(in));
   in.state = sout;
@@ -541,6 +542,7 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   };
   h2d(L.tiles256, c->tb.t256.data(), sizeof(Tile) * c->tb.t256.size());
   h2d(L.tilesS, c->tb.tS.data(), sizeof(Tile) * c->tb.tS.size());
+  h2d(L.tilesB, c->tb.tB.data(), sizeof(BinTile) * c->tb.tB.size());
   h2d(L.tile_last, c->tb.tile_last.data(), 4 * c->tb.tile_last.size());
   h2d(L.tfirst, c->tb.tfirst.data(), 4 * c->tb.tfirst.size());
   h2d(L.off, c->tb.off.data(), 4 * c->tb.off.size());
