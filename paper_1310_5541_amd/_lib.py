@@ -78,6 +78,15 @@ def lib():
     L.pcsir_set_graphs.argtypes = [vp, i32]
     L.pcsir_set_timing.argtypes = [vp, i32]
     L.pcsir_kernel_times.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(C.c_float), i32, C.POINTER(i32)]
+    L.pcsir_mlp_param_count.argtypes = []
+    L.pcsir_mlp_param_count.restype = sz
+    L.pcsir_mlp_train_bytes.argtypes = [i32]
+    L.pcsir_mlp_train_bytes.restype = sz
+    L.pcsir_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, i32, vp, sz, vp, vp, vp]
+    L.pcsir_mlp_forward_train_path.argtypes = [vp, vp, i32, vp, vp, sz, vp]
+    L.pcsir_mlp_gemm_bf16.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp]
+    for f in ("pcsir_mlp_train_step", "pcsir_mlp_forward_train_path", "pcsir_mlp_gemm_bf16"):
+        getattr(L, f).restype = i32
     for f in ("pcsir_init", "pcsir_step", "sir_step", "pcsir_estimate", "pcsir_destroy", "pcsir_get_particles",
               "pcsir_set_particles", "pcsir_debug_dump", "pcsir_set_debug", "pcsir_set_graphs", "pcsir_set_timing",
               "pcsir_kernel_times"):
@@ -282,3 +291,90 @@ class Filter:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- surrogate network
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device=None):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def mlp_param_count() -> int:
+    return int(lib().pcsir_mlp_param_count())
+
+
+def gemm_bf16(A, B, a_trans: bool = False, b_trans: bool = False):
+    """C = op(A) op(B) with the library's BF16 MFMA GEMM (tests)."""
+    import torch
+    assert A.dtype == torch.bfloat16 and B.dtype == torch.bfloat16 and A.is_contiguous() and B.is_contiguous()
+    M = A.shape[1] if a_trans else A.shape[0]
+    K = A.shape[0] if a_trans else A.shape[1]
+    N = B.shape[0] if b_trans else B.shape[1]
+    assert (B.shape[1] if b_trans else B.shape[0]) == K
+    Cm = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    st = lib().pcsir_mlp_gemm_bf16(M, N, K, _ptr(A), A.shape[1], 1 if a_trans else 0, _ptr(B), B.shape[1],
+                                   1 if b_trans else 0, _ptr(Cm), N, _stream(A.device))
+    if st != 0:
+        raise PcsirError(st, "pcsir_mlp_gemm_bf16")
+    return Cm
+
+
+class MLPTrainer:
+    """FP32 master parameters, Adam moments and a training workspace on the device."""
+
+    def __init__(self, params, batch: int):
+        import torch
+        self._torch = torch
+        n = mlp_param_count()
+        assert params.dtype == torch.float32 and params.numel() == n and params.is_cuda
+        self.params = params.contiguous().clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.batch = batch
+        nb = lib().pcsir_mlp_train_bytes(batch)
+        if nb == 0:
+            raise PcsirError(-1, "batch must be a positive multiple of 64")
+        self.ws = torch.empty(int(nb), dtype=torch.uint8, device=self.params.device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.params.device)
+        self.t = 0
+
+    def _run(self, X, y, lr, adam: bool):
+        assert X.dtype == self._torch.bfloat16 and X.shape == (self.batch, 256) and X.is_contiguous()
+        assert y.dtype == self._torch.float32 and y.shape == (self.batch,)
+        if adam:
+            self.t += 1
+        st = lib().pcsir_mlp_train_step(_ptr(self.params), _ptr(self.m) if adam else None,
+                                        _ptr(self.v) if adam else None, _ptr(X), _ptr(y), self.batch,
+                                        float(lr), self.t if adam else 0, _ptr(self.ws), self.ws.numel(),
+                                        _stream(X.device), _ptr(self.loss), _ptr(self.grad))
+        if st != 0:
+            raise PcsirError(st, "pcsir_mlp_train_step")
+
+    def step(self, X, y, lr: float):
+        """One Adam step on a batch; returns the loss tensor (device, before the step)."""
+        self._run(X, y, lr, True)
+        return self.loss
+
+    def gradients(self, X, y):
+        """Gradient of the batch loss without updating the parameters."""
+        self._run(X, y, 0.0, False)
+        return self.grad.clone(), float(self.loss.item())
+
+    def forward(self, X, params=None):
+        import torch
+        n = X.shape[0]
+        assert n % 64 == 0 and X.dtype == torch.bfloat16
+        nb = lib().pcsir_mlp_train_bytes(n)
+        ws = torch.empty(int(nb), dtype=torch.uint8, device=X.device)
+        f = torch.empty(n, dtype=torch.float32, device=X.device)
+        p = self.params if params is None else params
+        st = lib().pcsir_mlp_forward_train_path(_ptr(p), _ptr(X), n, _ptr(f), _ptr(ws), ws.numel(),
+                                                _stream(X.device))
+        if st != 0:
+            raise PcsirError(st, "pcsir_mlp_forward_train_path")
+        return f

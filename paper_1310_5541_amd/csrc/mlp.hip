@@ -1,0 +1,274 @@
+// Surrogate-network training on gfx950: BF16 MFMA GEMMs with FP32
+// accumulation and fused epilogues (bias + GELU forward, GELU' backward,
+// weight gradients), the output unit, column sums for the bias gradients,
+// and Adam on FP32 master parameters. C ABI in include/pcsir_mlp.h.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "../../include/pcsir_mlp.h"
+#include "device_util.h"
+#include "mlp_device.h"
+
+using namespace pcsir;
+
+namespace {
+
+constexpr int GT = 64;    // GEMM block tile (rows and columns)
+constexpr int GK = 32;    // k chunk staged in LDS
+constexpr int GPAD = 8;   // LDS row padding (bf16 elements)
+
+enum { EPI_FWD = 0, EPI_BWD = 1, EPI_STORE = 2 };
+
+// C = op(A) op(B), A(m,k) = a_t ? A[k lda + m] : A[m lda + k], B(k,n) = b_t ? B[n ldb + k] : B[k ldb + n],
+// BF16 inputs, FP32 accumulation. M, N multiples of 64, K a multiple of 32.
+// EPI_FWD:   z = acc + bias[n]; Zout[m][n] = z; Hout[m][n] = bf16(gelu(z))
+// EPI_BWD:   Hout[m][n] = bf16(acc * gelu'(Zin[m][n]))
+// EPI_STORE: Cout[m][n] = acc
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, int lda, int a_t,
+                                              const uint16_t *__restrict__ B, int ldb, int b_t,
+                                              const float *__restrict__ bias, const float *__restrict__ Zin,
+                                              float *__restrict__ Zout, uint16_t *__restrict__ Hout,
+                                              float *__restrict__ Cout, int ldc) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GT][GK + GPAD];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GK + GPAD];  // [n][k]
+  const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    // stage A and B chunks; the fastest-moving index follows the contiguous one in memory
+    for (int e = tid; e < GT * GK; e += 256) {
+      int m, k;
+      if (a_t) { m = e % GT; k = e / GT; }
+      else { k = e % GK; m = e / GK; }
+      As[m][k] = a_t ? A[(size_t)(k0 + k) * lda + (m0 + m)] : A[(size_t)(m0 + m) * lda + (k0 + k)];
+    }
+    for (int e = tid; e < GT * GK; e += 256) {
+      int n, k;
+      if (b_t) { k = e % GK; n = e / GK; }
+      else { n = e % GT; k = e / GT; }
+      Bs[n][k] = b_t ? B[(size_t)(n0 + n) * ldb + (k0 + k)] : B[(size_t)(k0 + k) * ldb + (n0 + n)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 16) {
+      const uint4 a = *reinterpret_cast<const uint4 *>(&As[wm + mfma_col(lane)][kk + mfma_k0(lane)]);
+      const uint4 b = *reinterpret_cast<const uint4 *>(&Bs[wn + mfma_col(lane)][kk + mfma_k0(lane)]);
+      acc = mfma_bf16(a, b, acc);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + wm + mfma_row(lane, r);
+    const int n = n0 + wn + mfma_col(lane);
+    const size_t o = (size_t)m * ldc + n;
+    if (EPI == EPI_FWD) {
+      const float z = acc[r] + bias[n];
+      Zout[o] = z;
+      Hout[o] = f2bf(gelu(z));
+    } else if (EPI == EPI_BWD) {
+      Hout[o] = f2bf(acc[r] * gelu_grad(Zin[o]));
+    } else {
+      Cout[o] = acc[r];
+    }
+  }
+}
+
+__global__ void k_f32_to_bf16(int n, const float *__restrict__ src, uint16_t *__restrict__ dst) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = f2bf(src[i]);
+}
+
+// Output unit, one thread per row: f = H3 . w4 + b4; with targets, the loss
+// residual r = f - y, the row's share of d loss / d f = 2 r / M, and
+// dZ3[m][n] = (2 r / M) w4[n] gelu'(Z3[m][n]). Per-block sums of r^2 for the loss.
+__global__ __launch_bounds__(256) void k_head(int M, const uint16_t *__restrict__ H3, const float *__restrict__ Z3,
+                                              const float *__restrict__ params, const float *__restrict__ y,
+                                              float *__restrict__ f_out, float *__restrict__ df,
+                                              uint16_t *__restrict__ dZ3, float *__restrict__ loss_part) {
+  __shared__ float lds[4];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const float *w4 = params + MLP_OFF_W4;
+  float r2 = 0.0f;
+  if (m < M) {
+    float f = params[MLP_OFF_B4];
+    for (int n = 0; n < MLP_H; ++n) f = fmaf(bf2f(H3[(size_t)m * MLP_H + n]), w4[n], f);
+    if (f_out) f_out[m] = f;
+    if (y) {
+      const float r = f - y[m];
+      r2 = r * r;
+      const float d = 2.0f * r / (float)M;
+      df[m] = d;
+      for (int n = 0; n < MLP_H; ++n)
+        dZ3[(size_t)m * MLP_H + n] = f2bf(d * w4[n] * gelu_grad(Z3[(size_t)m * MLP_H + n]));
+    }
+  }
+  if (loss_part) {
+    const float s = block_sum<256, float>(r2, lds);
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = s;
+  }
+}
+
+// out[n] = sum_m X[m][n] * (v ? v[m] : 1), FP32, fixed order (one thread per column).
+__global__ void k_colsum(int M, int N, const uint16_t *__restrict__ X, const float *__restrict__ v,
+                         float *__restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int m = 0; m < M; ++m) s = fmaf(bf2f(X[(size_t)m * N + n]), v ? v[m] : 1.0f, s);
+  out[n] = s;
+}
+
+__global__ void k_sum(int n, const float *__restrict__ v, float *__restrict__ out, float scale) {
+  __shared__ float lds[4];
+  float s = 0.0f;
+  for (int i = threadIdx.x; i < n; i += 256) s += v[i];
+  s = block_sum<256, float>(s, lds);
+  if (threadIdx.x == 0) *out = s * scale;
+}
+
+// Adam (Kingma & Ba 2015): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+// theta -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
+__global__ void k_adam(int n, float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, float lr, float c1, float c2) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float mi = b1 * m[i] + (1.0f - b1) * g[i];
+    const float vi = b2 * v[i] + (1.0f - b2) * g[i] * g[i];
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+struct TrainLayout {
+  size_t wb[3], Z[3], Hh[3], dZ[3], f, df, loss_part, total;
+};
+
+TrainLayout train_layout(int B) {
+  TrainLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  for (int l = 0; l < 3; ++l) L.wb[l] = take(2 * (size_t)MLP_H * MLP_H);
+  for (int l = 0; l < 3; ++l) L.Z[l] = take(4 * (size_t)B * MLP_H);
+  for (int l = 0; l < 3; ++l) L.Hh[l] = take(2 * (size_t)B * MLP_H);
+  for (int l = 0; l < 3; ++l) L.dZ[l] = take(2 * (size_t)B * MLP_H);
+  L.f = take(4 * (size_t)B);
+  L.df = take(4 * (size_t)B);
+  L.loss_part = take(4 * (size_t)((B + 255) / 256));
+  L.total = o;
+  return L;
+}
+
+template <int EPI>
+void gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int lda, int a_t, const uint16_t *B, int ldb, int b_t,
+          const float *bias, const float *Zin, float *Zout, uint16_t *Hout, float *Cout, int ldc) {
+  dim3 grid(N / GT, M / GT);
+  k_gemm<EPI><<<grid, 256, 0, st>>>(M, N, K, A, lda, a_t, B, ldb, b_t, bias, Zin, Zout, Hout, Cout, ldc);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pcsir_mlp_param_count(void) { return (size_t)MLP_N_PARAMS; }
+
+size_t pcsir_mlp_train_bytes(int32_t batch) {
+  if (batch < 64 || batch % 64) return 0;
+  return train_layout(batch).total;
+}
+
+pcsir_status pcsir_mlp_train_step(float *params, float *adam_m, float *adam_v, const uint16_t *X, const float *y,
+                                  int32_t batch, float lr, int32_t t, void *ws, size_t ws_bytes, void *stream,
+                                  float *loss_dev, float *grad_dev) {
+  if (!params || !X || !y || !ws || batch < 64 || batch % 64) return PCSIR_E_INVAL;
+  if (!grad_dev && (!adam_m || !adam_v || t < 1)) return PCSIR_E_INVAL;
+  const TrainLayout L = train_layout(batch);
+  if (ws_bytes < L.total) return PCSIR_E_NOMEM;
+  if (!grad_dev) return PCSIR_E_INVAL;  // the caller provides the gradient buffer (used for Adam too)
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  auto at16 = [&](size_t o) { return (uint16_t *)(w + o); };
+  auto at32 = [&](size_t o) { return (float *)(w + o); };
+  const int H = MLP_H, M = batch;
+  const int offW[3] = {MLP_OFF_W1, MLP_OFF_W2, MLP_OFF_W3};
+  const int offB[3] = {MLP_OFF_B1, MLP_OFF_B2, MLP_OFF_B3};
+  for (int l = 0; l < 3; ++l) k_f32_to_bf16<<<64, 256, 0, st>>>(H * H, params + offW[l], at16(L.wb[l]));
+  // forward
+  const uint16_t *in = X;
+  for (int l = 0; l < 3; ++l) {
+    gemm<EPI_FWD>(st, M, H, H, in, H, 0, at16(L.wb[l]), H, 0, params + offB[l], nullptr, at32(L.Z[l]),
+                  at16(L.Hh[l]), nullptr, H);
+    in = at16(L.Hh[l]);
+  }
+  const int hb = (M + 255) / 256;
+  k_head<<<hb, 256, 0, st>>>(M, at16(L.Hh[2]), at32(L.Z[2]), params, y, at32(L.f), at32(L.df), at16(L.dZ[2]),
+                             at32(L.loss_part));
+  if (loss_dev) k_sum<<<1, 256, 0, st>>>(hb, at32(L.loss_part), loss_dev, 1.0f / (float)M);
+  // backward: output unit
+  float *g = grad_dev;
+  k_colsum<<<1, 256, 0, st>>>(M, H, at16(L.Hh[2]), at32(L.df), g + MLP_OFF_W4);
+  k_sum<<<1, 256, 0, st>>>(M, at32(L.df), g + MLP_OFF_B4, 1.0f);
+  for (int l = 2; l >= 0; --l) {
+    const uint16_t *hin = l > 0 ? at16(L.Hh[l - 1]) : X;
+    // dW_l = H_{l-1}^T dZ_l  (K = batch)
+    gemm<EPI_STORE>(st, H, H, M, hin, H, 1, at16(L.dZ[l]), H, 0, nullptr, nullptr, nullptr, nullptr, g + offW[l], H);
+    k_colsum<<<1, 256, 0, st>>>(M, H, at16(L.dZ[l]), nullptr, g + offB[l]);
+    if (l > 0) {
+      // dZ_{l-1} = (dZ_l W_l^T) * gelu'(Z_{l-1})
+      gemm<EPI_BWD>(st, M, H, H, at16(L.dZ[l]), H, 0, at16(L.wb[l]), H, 1, nullptr, at32(L.Z[l - 1]), nullptr,
+                    at16(L.dZ[l - 1]), nullptr, H);
+    }
+  }
+  if (adam_m && adam_v && t >= 1) {
+    const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
+    k_adam<<<256, 256, 0, st>>>(MLP_N_PARAMS, params, adam_m, adam_v, g, lr, c1, c2);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PCSIR_OK : PCSIR_E_HIP;
+}
+
+pcsir_status pcsir_mlp_forward_train_path(const float *params, const uint16_t *X, int32_t n, float *f_out, void *ws,
+                                          size_t ws_bytes, void *stream) {
+  if (!params || !X || !f_out || !ws || n < 64 || n % 64) return PCSIR_E_INVAL;
+  const TrainLayout L = train_layout(n);
+  if (ws_bytes < L.total) return PCSIR_E_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  auto at16 = [&](size_t o) { return (uint16_t *)(w + o); };
+  auto at32 = [&](size_t o) { return (float *)(w + o); };
+  const int H = MLP_H;
+  const int offW[3] = {MLP_OFF_W1, MLP_OFF_W2, MLP_OFF_W3};
+  const int offB[3] = {MLP_OFF_B1, MLP_OFF_B2, MLP_OFF_B3};
+  for (int l = 0; l < 3; ++l) k_f32_to_bf16<<<64, 256, 0, st>>>(H * H, params + offW[l], at16(L.wb[l]));
+  const uint16_t *in = X;
+  for (int l = 0; l < 3; ++l) {
+    gemm<EPI_FWD>(st, n, H, H, in, H, 0, at16(L.wb[l]), H, 0, params + offB[l], nullptr, at32(L.Z[l]),
+                  at16(L.Hh[l]), nullptr, H);
+    in = at16(L.Hh[l]);
+  }
+  k_head<<<(n + 255) / 256, 256, 0, st>>>(n, at16(L.Hh[2]), at32(L.Z[2]), params, nullptr, f_out, nullptr, nullptr,
+                                         nullptr);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PCSIR_OK : PCSIR_E_HIP;
+}
+
+pcsir_status pcsir_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A, int32_t lda, int32_t a_trans,
+                                 const uint16_t *B, int32_t ldb, int32_t b_trans, float *C, int32_t ldc, void *stream) {
+  if (!A || !B || !C || M <= 0 || N <= 0 || K <= 0 || M % GT || N % GT || K % GK) return PCSIR_E_INVAL;
+  gemm<EPI_STORE>((hipStream_t)stream, M, N, K, A, lda, a_trans ? 1 : 0, B, ldb, b_trans ? 1 : 0, nullptr, nullptr,
+                  nullptr, nullptr, C, ldc);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PCSIR_OK : PCSIR_E_HIP;
+}
+
+}  // extern "C"
