@@ -60,7 +60,16 @@ typedef enum {
  *             the image-formation simulation written out;
  *  SEPARABLE: the Gaussian factorises over x and y, so 2 P q exponentials per
  *             evaluation suffice. */
-typedef enum { PCSIR_LIK_DIRECT = 0, PCSIR_LIK_SEPARABLE = 1 } pcsir_lik_mode;
+typedef enum {
+  PCSIR_LIK_DIRECT = 0,
+  PCSIR_LIK_SEPARABLE = 1,
+  /* Learned surrogate of the dummies' log-likelihood (pcsir_mlp.h), BF16 or
+   * FP8 matrix-core inference, with an exact check of a random share of the
+   * dummies each frame and exact recomputation (DIRECT) of every target whose
+   * check fails. pcsir_step only; sir_step stays exact (DIRECT). */
+  PCSIR_LIK_SURR_BF16 = 2,
+  PCSIR_LIK_SURR_FP8 = 3
+} pcsir_lik_mode;
 
 typedef enum { PCSIR_PSF_GAUSS2D = 0, PCSIR_PSF_ASTIG3D = 1 } pcsir_psf;
 

@@ -64,6 +64,56 @@ pcsir_status pcsir_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t
                                  const uint16_t *B, int32_t ldb, int32_t b_trans, float *C, int32_t ldc,
                                  void *hip_stream);
 
+/* ---------------------------------------------------------------- inference
+ * Inference form of the network: one device block of pcsir_surr_bytes() (256-
+ * byte aligned) holding the weights transposed to [layer][unit][input] in BF16
+ * and in FP8 E4M3 (scaled per layer by max|W| / 448), the FP32 biases and the
+ * output unit, and the FP8 input scales s_l of the three layers: in FP8 mode a
+ * layer's input x is quantised as fp8(clamp(x / s_l, +-448)). One fused kernel
+ * runs the three layers on 64 rows per workgroup with FP32 accumulation; the
+ * activations between layers are rounded to BF16. */
+size_t pcsir_surr_bytes(void);
+
+/* Fill the inference block from the FP32 parameter vector. act_scale_host: [3]
+ * host floats s_l (finite, > 0), or NULL for 1 (enough for BF16 inference).
+ * Synchronises `hip_stream`. E_INVAL on NULL pointers, a short or unaligned
+ * block, or bad scales. */
+pcsir_status pcsir_surr_prepare(const float *params_dev, const float *act_scale_host, void *surr_dev, size_t bytes,
+                                void *hip_stream);
+
+/* Network outputs f [n] for BF16 feature rows X [n][256] (16-byte aligned)
+ * through the fused inference kernel, BF16 (fp8 = 0) or FP8 (fp8 != 0)
+ * operands. absmax_dev: NULL, or [3] FP32 values (initialise to 0) into which
+ * the largest |input| of each layer is max-accumulated (FP8 scale calibration;
+ * s_l = absmax_l / 448 uses the full range). Asynchronous on hip_stream. */
+pcsir_status pcsir_surr_rows(const void *surr_dev, const uint16_t *X_dev, int32_t n, int32_t fp8, float *f_dev,
+                             float *absmax_dev, void *hip_stream);
+
+/* Install the surrogate on a filter made with lik_mode PCSIR_LIK_SURR_BF16 or
+ * PCSIR_LIK_SURR_FP8 (required before its first pcsir_step; may be called
+ * again to replace the weights). Per frame, each dummy is checked against its
+ * exact log-likelihood with probability check_fraction (a counter-based
+ * uniform of (dummy index, frame, target)); a target with any checked dummy
+ * off by more than tol_nats has all its dummies evaluated exactly in that
+ * frame. Checked dummies keep their exact value. act_scale_host as in
+ * pcsir_surr_prepare, required for FP8. Synchronises the filter's stream. */
+pcsir_status pcsir_set_surrogate(pcsir_ctx *ctx, const float *params_dev, const float *act_scale_host,
+                                 float check_fraction, float tol_nats);
+
+/* Training rows from the dummies of the last pcsir_step (any likelihood mode;
+ * exact modes give exact targets): features X [min(B, cap)][256] BF16 as
+ * described above and targets y = (l + A(z)) / 100 FP32, with l the dummy's
+ * log-likelihood of that step. *count = B, the number of dummies (may exceed
+ * cap). The frame given to that step must still be valid. Asynchronous after
+ * one read of B. E_STATE when the last step was not a pcsir_step. */
+pcsir_status pcsir_surrogate_features(pcsir_ctx *ctx, uint16_t *X_dev, float *y_dev, int32_t cap, int32_t *count);
+
+/* Cumulative surrogate statistics since init or the last reset: dummies
+ * checked, target-frames that fell back to exact evaluation, the largest
+ * |l_surrogate - l_exact| seen. Any output may be NULL. Synchronises. */
+pcsir_status pcsir_surrogate_stats(pcsir_ctx *ctx, uint64_t *checked, uint64_t *fallbacks, float *max_err,
+                                   int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

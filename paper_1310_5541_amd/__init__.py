@@ -5,5 +5,6 @@ resample) runs entirely in ``libpcsir.so``. This package is argument
 marshalling only: torch supplies device memory and the stream.
 """
 from ._lib import (  # noqa: F401
-    DUMP, Config, Filter, LibraryMissing, PcsirError, lib, lib_path,
+    DUMP, Config, Filter, LibraryMissing, MLPTrainer, PcsirError, SurrogateNet, gemm_bf16, lib, lib_path,
+    mlp_param_count,
 )

@@ -85,7 +85,15 @@ def lib():
     L.pcsir_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, i32, vp, sz, vp, vp, vp]
     L.pcsir_mlp_forward_train_path.argtypes = [vp, vp, i32, vp, vp, sz, vp]
     L.pcsir_mlp_gemm_bf16.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp]
-    for f in ("pcsir_mlp_train_step", "pcsir_mlp_forward_train_path", "pcsir_mlp_gemm_bf16"):
+    L.pcsir_surr_bytes.argtypes = []
+    L.pcsir_surr_bytes.restype = sz
+    L.pcsir_surr_prepare.argtypes = [vp, vp, vp, sz, vp]
+    L.pcsir_surr_rows.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    L.pcsir_set_surrogate.argtypes = [vp, vp, vp, C.c_float, C.c_float]
+    L.pcsir_surrogate_features.argtypes = [vp, vp, vp, i32, C.POINTER(i32)]
+    L.pcsir_surrogate_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_float), i32]
+    for f in ("pcsir_mlp_train_step", "pcsir_mlp_forward_train_path", "pcsir_mlp_gemm_bf16", "pcsir_surr_prepare",
+              "pcsir_surr_rows", "pcsir_set_surrogate", "pcsir_surrogate_features", "pcsir_surrogate_stats"):
         getattr(L, f).restype = i32
     for f in ("pcsir_init", "pcsir_step", "sir_step", "pcsir_estimate", "pcsir_destroy", "pcsir_get_particles",
               "pcsir_set_particles", "pcsir_debug_dump", "pcsir_set_debug", "pcsir_set_graphs", "pcsir_set_timing",
@@ -105,7 +113,7 @@ class Config:
     quad: int = 2
     psf: int = 0
     dummy_mode: int = 0
-    lik_mode: int = 0          # 0 DIRECT, 1 SEPARABLE
+    lik_mode: int = 0          # 0 DIRECT, 1 SEPARABLE, 2 surrogate BF16, 3 surrogate FP8
     per_target_frames: bool = False
     frame_h: int = 64
     frame_w: int = 64
@@ -235,6 +243,30 @@ class Filter:
 
     def set_debug(self, on: bool = True):
         self._check(lib().pcsir_set_debug(self._ctx, 1 if on else 0))
+
+    # -- learned surrogate (lik_mode 2 / 3)
+    def set_surrogate(self, params, act_scale=None, check_fraction: float = 0.01, tol_nats: float = 1.0):
+        """Install surrogate weights (FP32 device vector) on a filter made with a surrogate lik_mode."""
+        assert params.dtype == self._torch.float32 and params.is_cuda and params.numel() == mlp_param_count()
+        sc = None if act_scale is None else (C.c_float * 3)(*[float(v) for v in act_scale])
+        self._check(lib().pcsir_set_surrogate(self._ctx, _ptr(params.contiguous()), sc, float(check_fraction),
+                                              float(tol_nats)))
+
+    def surrogate_features(self, cap: int):
+        """(X bf16 [n, 256], y fp32 [n], B) training rows from the dummies of the last pcsir_step."""
+        t = self._torch
+        X = t.empty((max(cap, 1), 256), dtype=t.bfloat16, device=self.device)
+        y = t.empty(max(cap, 1), dtype=t.float32, device=self.device)
+        cnt = C.c_int32(0)
+        self._check(lib().pcsir_surrogate_features(self._ctx, _ptr(X), _ptr(y), int(cap), C.byref(cnt)))
+        n = min(cnt.value, cap)
+        return X[:n], y[:n], cnt.value
+
+    def surrogate_stats(self, reset: bool = False):
+        """(dummies checked, target-frames that fell back, largest |error| in nats), cumulative."""
+        a, b, m = C.c_uint64(0), C.c_uint64(0), C.c_float(0.0)
+        self._check(lib().pcsir_surrogate_stats(self._ctx, C.byref(a), C.byref(b), C.byref(m), 1 if reset else 0))
+        return int(a.value), int(b.value), float(m.value)
 
     def dump(self, what: str):
         """Debug / parity view of the last step as a torch tensor (see PCSIR_DUMP_* in pcsir.h)."""
@@ -378,3 +410,37 @@ class MLPTrainer:
         if st != 0:
             raise PcsirError(st, "pcsir_mlp_forward_train_path")
         return f
+
+
+class SurrogateNet:
+    """Inference form of the surrogate network (fused BF16 / FP8 MFMA kernel)."""
+
+    def __init__(self, params, act_scale=None):
+        import torch
+        self._torch = torch
+        assert params.dtype == torch.float32 and params.is_cuda and params.numel() == mlp_param_count()
+        self.device = params.device
+        self.block = torch.empty(int(lib().pcsir_surr_bytes()), dtype=torch.uint8, device=self.device)
+        self.act_scale = None if act_scale is None else [float(v) for v in act_scale]
+        sc = None if act_scale is None else (C.c_float * 3)(*self.act_scale)
+        st = lib().pcsir_surr_prepare(_ptr(params.contiguous()), sc, _ptr(self.block), self.block.numel(),
+                                      _stream(self.device))
+        if st != 0:
+            raise PcsirError(st, "pcsir_surr_prepare")
+
+    def rows(self, X, fp8: bool = False, absmax=None):
+        """f for BF16 feature rows X [n, 256]; absmax: optional fp32 [3] device tensor (max-accumulated)."""
+        t = self._torch
+        assert X.dtype == t.bfloat16 and X.is_contiguous() and X.shape[1] == 256
+        f = t.empty(X.shape[0], dtype=t.float32, device=self.device)
+        st = lib().pcsir_surr_rows(_ptr(self.block), _ptr(X), X.shape[0], 1 if fp8 else 0, _ptr(f),
+                                   _ptr(absmax), _stream(self.device))
+        if st != 0:
+            raise PcsirError(st, "pcsir_surr_rows")
+        return f
+
+    def calibrate(self, X, margin: float = 1.0):
+        """FP8 input scales of the three layers from the BF16 activations of rows X."""
+        a = self._torch.zeros(3, dtype=self._torch.float32, device=self.device)
+        self.rows(X, fp8=False, absmax=a)
+        return [max(float(v), 1e-30) * margin / 448.0 for v in a.cpu()]

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcsir.so")
 SOURCES = [os.path.join(CSRC, "pcsir.hip"), os.path.join(CSRC, "mlp.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("kernels.h", "device_util.h", "mlp_device.h")] + [
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("kernels.h", "device_util.h", "mlp_device.h", "surrogate.h")] + [
     os.path.join(os.path.dirname(HERE), "include", h) for h in ("pcsir.h", "pcsir_mlp.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

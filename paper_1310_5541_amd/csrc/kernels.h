@@ -27,7 +27,13 @@ constexpr uint64_t ERR_KEY_RANGE = 1;    // compacted cell range of all targets 
 constexpr uint64_t ERR_FIXED_SAT = 2;    // a velocity or intensity outside the fixed-point range
 constexpr uint64_t ERR_NONFINITE = 4;    // a target's normalisation was not finite
 
-enum { META_PASSES = 0, META_RANGE = 1, META_B = 2, META_ERR = 3, META_DIGIT = 4, META_DIRTY = 5, META_N = 8 };
+enum {
+  META_PASSES = 0, META_RANGE = 1, META_B = 2, META_ERR = 3, META_DIGIT = 4, META_DIRTY = 5,
+  META_CHECKED = 6,   // surrogate: dummies checked against the exact likelihood (cumulative)
+  META_MAXERR = 7,    // surrogate: largest |l_surrogate - l_exact| seen (float bits)
+  META_FALLBACK = 8,  // surrogate: target-frames recomputed exactly (cumulative)
+  META_N = 12
+};
 constexpr int MAX_DIGIT_BITS = 11;  // radix digit of at most 2048 buckets (LDS histogram)
 constexpr int MAX_BUCKETS = 1 << MAX_DIGIT_BITS;
 
@@ -139,7 +145,8 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
 __global__ __launch_bounds__(TPB) void k_bbox_reduce(int dim, const uint32_t *__restrict__ t256_first,
                                                      const int32_t *__restrict__ bbox_part,
                                                      int32_t *__restrict__ bbox_cur,
-                                                     unsigned long long *__restrict__ range) {
+                                                     unsigned long long *__restrict__ range,
+                                                     int32_t *__restrict__ tfallback) {
   __shared__ int32_t red[TPB / WAVE];
   const int t = blockIdx.x;
   const uint32_t a0 = t256_first[t], a1 = t256_first[t + 1];
@@ -165,7 +172,10 @@ __global__ __launch_bounds__(TPB) void k_bbox_reduce(int dim, const uint32_t *__
     r *= (unsigned long long)(uint32_t)wdt;
     if (r > (1ull << 40)) r = (1ull << 40);
   }
-  if (threadIdx.x == 0) range[t] = r;
+  if (threadIdx.x == 0) {
+    range[t] = r;
+    tfallback[t] = 0;
+  }
 }
 
 // Exclusive scan of the per-target cell ranges -> compacted key bases, the
@@ -611,7 +621,7 @@ __global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsig
                         const uint32_t *__restrict__ seg_key, const int32_t *__restrict__ seg_t,
                         const uint32_t *__restrict__ kbase, const int32_t *__restrict__ bbox_cur,
                         int32_t *__restrict__ dpix, float *__restrict__ doff, float *__restrict__ dint,
-                        uint32_t *__restrict__ seg_first) {
+                        float *__restrict__ dvel) {
   const uint32_t B = (uint32_t)meta[META_B];
   const uint32_t NT = p.NT;
   for (uint32_t sidx = blockIdx.x * blockDim.x + threadIdx.x; sidx < B; sidx += gridDim.x * blockDim.x) {
@@ -633,6 +643,9 @@ __global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsig
       doff[(size_t)a * NT + sidx] = off;
     }
     dint[sidx] = (float)((double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + sidx] / (double)FX_INT / n);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      dvel[(size_t)a * NT + sidx] = (float)((double)(long long)acc[(size_t)(1 + DIM + a) * NT + sidx] / (double)FX_VEL / n);
   }
 }
 
@@ -706,15 +719,35 @@ __device__ __forceinline__ float scaled_sq(float u, float kh, float kl) {
 // Sub-sample offset within a pixel: (a + 1/2)/q - 1/2 = (2a + 1 - q) / (2q).
 __device__ __forceinline__ float sub_offset(int a, int q) { return (float)(2 * a + 1 - q) / (float)(2 * q); }
 
-template <int DIM, bool SIR, bool SEP, int Q>
+// Evaluation sets of k_lik: every dummy / particle; the dummies picked for
+// the surrogate's exact check (a counter-based uniform below the check
+// fraction: counter (dummy, k, target, 2)); the dummies of targets whose
+// check failed (exact recomputation, the surrogate's fallback).
+enum { LIK_ALL = 0, LIK_CHECK = 1, LIK_FALLBACK = 2 };
+struct SurrCheck {
+  float fraction;            // share of dummies checked per frame
+  float tol;                 // largest accepted |l_surrogate - l_exact| (nats)
+  int32_t *tfallback;        // [T] per-target fallback flag of this frame
+};
+
+__device__ __forceinline__ bool surr_checked(uint64_t seed, uint32_t e, int64_t k, int t, float fraction) {
+  const U64x4 b = philox4x64_10(e, (uint64_t)k, (uint64_t)t, 2, seed, 0);
+  return (double)(b.v[0] >> 11) * 0x1p-53 < (double)fraction;
+}
+
+template <int DIM, bool SIR, bool SEP, int Q, int MODE = LIK_ALL>
 __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64_t *__restrict__ meta,
-                                             const StepDesc *__restrict__ desc, double *__restrict__ ll) {
+                                             const StepDesc *__restrict__ desc, double *__restrict__ ll,
+                                             SurrCheck chk = SurrCheck{0.0f, 0.0f, nullptr},
+                                             uint64_t *__restrict__ stats = nullptr) {
   const float *__restrict__ frame = desc->frame;
   const uint32_t E = SIR ? p.NT : (uint32_t)meta[META_B];
   const int lane = lane_id();
   const int P = p.P, R = p.R, P2 = P * P;
   const int q = Q ? Q : p.q;
   for (uint32_t e = blockIdx.x * LIK_WAVES + wave_id(); e < E; e += gridDim.x * LIK_WAVES) {
+    if (MODE == LIK_CHECK && !surr_checked(p.seed, e, desc->k, in.seg_t[e], chk.fraction)) continue;
+    if (MODE == LIK_FALLBACK && !chk.tfallback[in.seg_t[e]]) continue;
     int t;
     int32_t c0, r0;
     float dx, dy, I0, zpos = 0.0f;
@@ -809,7 +842,16 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
     // the precision of the normalisation that consumes it
     double hi, lo;
     wave_sum_pair(ssd, err, hi, lo);
-    if (lane == 0) ll[e] = -(hi + lo) * p.inv2sxi2;
+    const double lx = -(hi + lo) * p.inv2sxi2;
+    if (MODE == LIK_CHECK) {
+      if (lane == 0) {
+        const float d = (float)fabs(lx - ll[e]);
+        atomicAdd((unsigned long long *)&stats[META_CHECKED], 1ull);
+        atomicMax((unsigned long long *)&stats[META_MAXERR], (unsigned long long)__float_as_uint(d));
+        if (!(d <= chk.tol)) atomicOr(&chk.tfallback[t], 1);
+      }
+    }
+    if (lane == 0) ll[e] = lx;
   }
 }
 
@@ -824,7 +866,7 @@ __global__ __launch_bounds__(TPB) void k_norm_bins(Params p, const uint32_t *__r
                                                    const int32_t *__restrict__ dpix, const StepDesc *__restrict__ desc,
                                                    double *__restrict__ wbin, double *__restrict__ tgt,
                                                    double *__restrict__ est, int32_t *__restrict__ tflag,
-                                                   uint64_t *__restrict__ meta) {
+                                                   uint64_t *__restrict__ meta, const int32_t *__restrict__ tfallback) {
   constexpr int D = 2 * DIM + 1;
   __shared__ double lds[TPB / WAVE];
   const int t = blockIdx.x;
@@ -866,6 +908,7 @@ __global__ __launch_bounds__(TPB) void k_norm_bins(Params p, const uint32_t *__r
     for (int d = 0; d < D; ++d) est[t * D + d] = X[d] / S;
     tflag[t] = ok ? 0 : 1;
     if (!ok) atomicOr((unsigned long long *)&meta[META_ERR], (unsigned long long)ERR_NONFINITE);
+    if (tfallback && tfallback[t]) atomicAdd((unsigned long long *)&meta[META_FALLBACK], 1ull);
   }
 }
 

@@ -13,6 +13,8 @@
 
 #include "../../include/pcsir.h"
 #include "kernels.h"
+#include "surrogate.h"
+#include "../../include/pcsir_mlp.h"
 
 using namespace pcsir;
 
@@ -22,7 +24,7 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
-      ll, wbin, desc, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
+      ll, wbin, desc, dvel, surr, tfb, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off;
   int sort_items; // keys per thread in the radix sort (chosen to fill the device)
   size_t total;
@@ -62,7 +64,9 @@ bool valid_config(const pcsir_config *c, std::string *why) {
   if (c->psf != PCSIR_PSF_GAUSS2D && c->psf != PCSIR_PSF_ASTIG3D) return bad("unknown psf");
   if (c->psf == PCSIR_PSF_ASTIG3D && c->dim != 3) return bad("astigmatic PSF needs dim == 3");
   if (c->dummy_mode != PCSIR_DUMMY_COM && c->dummy_mode != PCSIR_DUMMY_COC) return bad("unknown dummy_mode");
-  if (c->lik_mode != PCSIR_LIK_DIRECT && c->lik_mode != PCSIR_LIK_SEPARABLE) return bad("unknown lik_mode");
+  if (c->lik_mode < PCSIR_LIK_DIRECT || c->lik_mode > PCSIR_LIK_SURR_FP8) return bad("unknown lik_mode");
+  if (c->lik_mode >= PCSIR_LIK_SURR_BF16 && c->patch * c->patch + 2 * c->dim + 1 > MLP_F)
+    return bad("surrogate features (patch^2 + 2 dim + 1) exceed 256");
   if (c->frame_h < 1 || c->frame_w < 1) return bad("frame_h and frame_w must be >= 1");
   if (!(c->sigma_psf > 0.0f) || !(c->sigma_xi > 0.0f)) return bad("sigma_psf and sigma_xi must be > 0");
   if (c->psf == PCSIR_PSF_ASTIG3D && !(c->astig_d > 0.0f)) return bad("astig_d must be > 0");
@@ -140,9 +144,12 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.dpix = take(4 * dim * NT);
   L.doff = take(4 * dim * NT);
   L.dint = take(4 * NT);
+  L.dvel = take(4 * dim * NT);
   L.ll = take(8 * NT);
   L.wbin = take(8 * NT);
   L.desc = take(sizeof(StepDesc));
+  L.surr = c->lik_mode >= PCSIR_LIK_SURR_BF16 ? take(SURR_BYTES) : 0;  // surrogate weights
+  L.tfb = take(4 * T);
   L.seg_first = take(4 * (T + 1));
   L.bbox_part = take(4 * 6 * (size_t)L.n256);
   L.range = take(8 * T);
@@ -192,6 +199,8 @@ struct pcsir_ctx {
   int ev_used = 0;
   // captured step graphs, by (sir, buffer parity, pending gather)
   int use_graphs = 1;
+  int surr_ready = 0;      // surrogate weights installed
+  float surr_fraction = 0.01f, surr_tol = 1.0f;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2][2][2] = {};
 
@@ -217,7 +226,7 @@ pcsir_status check_hip(pcsir_ctx *c, hipError_t e, const char *what) {
 void mark(pcsir_ctx *c, const char *name) {
   if (!c->timing) return;
   if (c->ev_used >= (int)c->ev.size()) return;
-  hipEventRecord(c->ev[c->ev_used], c->stream);
+  (void)hipEventRecord(c->ev[c->ev_used], c->stream);
   c->ev_name[c->ev_used] = name;
   ++c->ev_used;
 }
@@ -289,6 +298,49 @@ void launch_lik(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   }
 }
 
+SurrWeights surr_weights(const pcsir_ctx *c) { return surr_view(c->at<char>(c->L.surr)); }
+
+// Surrogate log-likelihood of every dummy, then the exact check of a random
+// share of dummies and the exact recomputation of targets that failed it.
+template <int DIM>
+void launch_surrogate(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
+  const Layout &L = c->L;
+  DummyView dv;
+  dv.dpix = in.dpix;
+  dv.doff = in.doff;
+  dv.dvel = c->at<float>(L.dvel);
+  dv.dint = in.dint;
+  dv.seg_t = in.seg_t;
+  const uint64_t *meta = c->at<uint64_t>(L.meta);
+  const StepDesc *desc = c->at<StepDesc>(L.desc);
+  double *ll = c->at<double>(L.ll);
+  const uint32_t grid = grid_stride_blocks(c, c->p.NT, SURR_ROWS);
+  if (c->cfg.lik_mode == PCSIR_LIK_SURR_FP8)
+    k_surr_infer<DIM, true><<<grid, 256, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll);
+  else
+    k_surr_infer<DIM, false><<<grid, 256, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll);
+  SurrCheck chk;
+  chk.fraction = c->surr_fraction;
+  chk.tol = c->surr_tol;
+  chk.tfallback = c->at<int32_t>(L.tfb);
+  uint64_t *stats = c->at<uint64_t>(L.meta);
+  const uint32_t lg = grid_stride_blocks(c, c->p.NT, LIK_WAVES);
+  const Params &p = c->p;
+  mark(c, "surr_check");
+  switch (p.q) {
+    case 8:
+      k_lik<DIM, false, false, 8, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, stats);
+      mark(c, "surr_fallback");
+      k_lik<DIM, false, false, 8, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, stats);
+      break;
+    default:
+      k_lik<DIM, false, false, 0, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, stats);
+      mark(c, "surr_fallback");
+      k_lik<DIM, false, false, 0, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, stats);
+      break;
+  }
+}
+
 template <int DIM, bool SEP>
 void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   const Layout &L = c->L;
@@ -307,7 +359,8 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
                                                  c->at<int32_t>(L.bbox_part), c->at<unsigned long long>(L.acc), meta);
   mark(c, "bbox");
   k_bbox_reduce<<<p.T, TPB, 0, st>>>(p.dim, c->at<uint32_t>(L.t256_first), c->at<int32_t>(L.bbox_part),
-                                     c->at<int32_t>(L.bbox_cur), c->at<unsigned long long>(L.range));
+                                     c->at<int32_t>(L.bbox_cur), c->at<unsigned long long>(L.range),
+                                     c->at<int32_t>(L.tfb));
   k_bbox_scan<<<1, TPB, 0, st>>>(p.T, c->at<unsigned long long>(L.range), c->at<uint32_t>(L.kbase), meta);
   mark(c, "keys");
   k_keys<DIM><<<L.n256, TPB, 0, st>>>(p, t256, off, sout, c->at<int32_t>(L.bbox_cur), c->at<uint32_t>(L.kbase),
@@ -341,7 +394,7 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   k_dummy<DIM><<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(
       p, meta, acc, c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.kbase),
       c->at<int32_t>(L.bbox_cur), c->at<int32_t>(L.dpix), c->at<float>(L.doff), c->at<float>(L.dint),
-      c->at<uint32_t>(L.seg_first));
+      c->at<float>(L.dvel));
   LikInput in;
   in.dpix = c->at<int32_t>(L.dpix);
   in.doff = c->at<float>(L.doff);
@@ -350,11 +403,16 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   in.state = sout;
   in.off = off;
   mark(c, "likelihood");
-  launch_lik<DIM, false, SEP>(c, in, st);
+  if (c->cfg.lik_mode >= PCSIR_LIK_SURR_BF16) {
+    launch_surrogate<DIM>(c, in, st);
+  } else {
+    launch_lik<DIM, false, SEP>(c, in, st);
+  }
   mark(c, "normalise");
   k_norm_bins<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.seg_first), c->at<double>(L.ll), acc,
                                         c->at<int32_t>(L.dpix), desc, c->at<double>(L.wbin), c->at<double>(L.tgt),
-                                        c->at<double>(L.est), c->at<int32_t>(L.tflag), meta);
+                                        c->at<double>(L.est), c->at<int32_t>(L.tflag), meta,
+                                        c->at<int32_t>(L.tfb));
   WeightSrc ws = weight_src(c);
   mark(c, "cdf_sum");
   k_cdf_sum<false><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.tile_sum));
@@ -434,12 +492,12 @@ pcsir_status step_graph(pcsir_ctx *c, bool sir, hipGraphExec_t *out) {
   const hipError_t el = hipGetLastError();
   e = hipStreamEndCapture(c->cap_stream, &g);
   if (el != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return check_hip(c, el, "kernel launch during capture");
   }
   if (e != hipSuccess) return check_hip(c, e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     ex = nullptr;
     return check_hip(c, e, "hipGraphInstantiate");
@@ -453,6 +511,8 @@ pcsir_status run_step(pcsir_ctx *c, const float *frame, int32_t H, int32_t W, in
   if (!frame) return fail(c, PCSIR_E_INVAL, "frame_dev is NULL");
   if (H != c->cfg.frame_h || W != c->cfg.frame_w) return fail(c, PCSIR_E_STATE, "frame size differs from the config");
   if (k < 1) return fail(c, PCSIR_E_INVAL, "frame index k must be >= 1");
+  if (!sir && c->cfg.lik_mode >= PCSIR_LIK_SURR_BF16 && !c->surr_ready)
+    return fail(c, PCSIR_E_STATE, "surrogate mode: call pcsir_set_surrogate before the first step");
   k_set_desc<<<1, 1, 0, c->stream>>>(c->at<StepDesc>(c->L.desc), frame, k);
   if (c->use_graphs && !c->timing) {
     hipGraphExec_t ex = nullptr;
@@ -472,6 +532,40 @@ pcsir_status run_step(pcsir_ctx *c, const float *frame, int32_t H, int32_t W, in
   return PCSIR_OK;
 }
 
+void drop_graphs(pcsir_ctx *c) {
+  (void)hipStreamSynchronize(c->stream);
+  for (auto &a : c->gexec)
+    for (auto &b : a)
+      for (auto &x : b)
+        if (x) {
+          (void)hipGraphExecDestroy(x);
+          x = nullptr;
+        }
+}
+
+// Inference copy of the surrogate's weights (layout of surr_view) from the
+// FP32 parameter vector, plus the FP8 input scales of the three layers.
+hipError_t surr_prepare(const float *params, const float *act_scale_host, char *block, hipStream_t st) {
+  float *sw = (float *)(block + SURR_OFF_SW);
+  k_surr_scales<<<3, 256, 0, st>>>(params, sw);
+  k_surr_prep<<<768, 256, 0, st>>>(params, sw, (uint16_t *)(block + SURR_OFF_WT), (uint8_t *)(block + SURR_OFF_WT8),
+                                   (float *)(block + SURR_OFF_BIAS), (float *)(block + SURR_OFF_W4),
+                                   (float *)(block + SURR_OFF_B4));
+  hipError_t e = hipGetLastError();
+  const float one[3] = {1.0f, 1.0f, 1.0f};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(block + SURR_OFF_SX, act_scale_host ? act_scale_host : one, sizeof one, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host scales are read before returning
+  return e;
+}
+
+bool valid_act_scales(const float *s) {
+  if (!s) return true;
+  for (int l = 0; l < 3; ++l)
+    if (!(s[l] > 0.0f) || !std::isfinite(s[l])) return false;
+  return true;
+}
+
 pcsir_status pull_device_status(pcsir_ctx *c) {
   uint64_t meta[META_N];
   hipError_t e = hipMemcpyAsync(meta, c->at<uint64_t>(c->L.meta), sizeof(meta), hipMemcpyDeviceToHost, c->stream);
@@ -483,8 +577,8 @@ pcsir_status pull_device_status(pcsir_ctx *c) {
     if (meta[META_ERR] & ERR_FIXED_SAT) m += " a velocity (|v| >= 128) or intensity (|I| >= 32768) left the bin-sum range;";
     if (meta[META_ERR] & ERR_NONFINITE) m += " a target's normalisation was not finite (its particles were kept, not resampled);";
     uint64_t zero = 0;
-    hipMemcpyAsync(c->at<uint64_t>(c->L.meta) + META_ERR, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
-    hipStreamSynchronize(c->stream);
+    (void)hipMemcpyAsync(c->at<uint64_t>(c->L.meta) + META_ERR, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
+    (void)hipStreamSynchronize(c->stream);
     return fail(c, PCSIR_E_NUMERIC, m);
   }
   return PCSIR_OK;
@@ -597,12 +691,12 @@ pcsir_status pcsir_destroy(pcsir_ctx *c) {
   const hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) s = PCSIR_E_HIP;
   else s = pull_device_status(c);
-  for (hipEvent_t ev : c->ev) hipEventDestroy(ev);
+  for (hipEvent_t ev : c->ev) (void)hipEventDestroy(ev);
   for (auto &a : c->gexec)
     for (auto &b : a)
       for (auto &x : b)
-        if (x) hipGraphExecDestroy(x);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+        if (x) (void)hipGraphExecDestroy(x);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return s;
 }
@@ -629,17 +723,6 @@ pcsir_status pcsir_set_graphs(pcsir_ctx *c, int32_t on) {
   if (!c) return PCSIR_E_INVAL;
   c->use_graphs = on ? 1 : 0;
   return PCSIR_OK;
-}
-
-void drop_graphs(pcsir_ctx *c) {
-  hipStreamSynchronize(c->stream);
-  for (auto &a : c->gexec)
-    for (auto &b : a)
-      for (auto &x : b)
-        if (x) {
-          hipGraphExecDestroy(x);
-          x = nullptr;
-        }
 }
 
 pcsir_status pcsir_set_debug(pcsir_ctx *c, int32_t on) {
@@ -769,13 +852,108 @@ pcsir_status pcsir_kernel_times(pcsir_ctx *c, const char **names, float *ms, int
   for (int i = 0; i + 1 < c->ev_used && n < cap; ++i) {
     if (strcmp(c->ev_name[i], "end") == 0) continue;  // gap between two steps
     float t = 0.0f;
-    hipEventElapsedTime(&t, c->ev[i], c->ev[i + 1]);
+    (void)hipEventElapsedTime(&t, c->ev[i], c->ev[i + 1]);
     if (names) names[n] = c->ev_name[i];
     if (ms) ms[n] = t;
     ++n;
   }
   *count = n;
   c->ev_used = 0;
+  return PCSIR_OK;
+}
+
+size_t pcsir_surr_bytes(void) { return SURR_BYTES; }
+
+pcsir_status pcsir_surr_prepare(const float *params_dev, const float *act_scale_host, void *surr_dev, size_t bytes,
+                                void *hip_stream) {
+  if (!params_dev || !surr_dev || bytes < SURR_BYTES || ((uintptr_t)surr_dev) % ALIGN) return PCSIR_E_INVAL;
+  if (!valid_act_scales(act_scale_host)) return PCSIR_E_INVAL;
+  return surr_prepare(params_dev, act_scale_host, (char *)surr_dev, (hipStream_t)hip_stream) == hipSuccess
+             ? PCSIR_OK
+             : PCSIR_E_HIP;
+}
+
+pcsir_status pcsir_surr_rows(const void *surr_dev, const uint16_t *X_dev, int32_t n, int32_t fp8, float *f_dev,
+                             float *absmax_dev, void *hip_stream) {
+  if (!surr_dev || n < 0 || (n > 0 && (!X_dev || !f_dev))) return PCSIR_E_INVAL;
+  if (((uintptr_t)surr_dev) % ALIGN || ((uintptr_t)X_dev) % 16) return PCSIR_E_INVAL;
+  if (n == 0) return PCSIR_OK;
+  const hipStream_t st = (hipStream_t)hip_stream;
+  const SurrWeights sw = surr_view((void *)surr_dev);
+  const int grid = std::min((n + SURR_ROWS - 1) / SURR_ROWS, 8192);
+  if (fp8)
+    k_surr_rows<true><<<grid, 256, 0, st>>>(n, X_dev, sw, f_dev, (unsigned int *)absmax_dev);
+  else
+    k_surr_rows<false><<<grid, 256, 0, st>>>(n, X_dev, sw, f_dev, (unsigned int *)absmax_dev);
+  return hipGetLastError() == hipSuccess ? PCSIR_OK : PCSIR_E_HIP;
+}
+
+pcsir_status pcsir_set_surrogate(pcsir_ctx *c, const float *params_dev, const float *act_scale_host,
+                                 float check_fraction, float tol_nats) {
+  if (!c) return PCSIR_E_INVAL;
+  if (c->cfg.lik_mode < PCSIR_LIK_SURR_BF16) return fail(c, PCSIR_E_STATE, "the filter was not made with a surrogate lik_mode");
+  if (!params_dev) return fail(c, PCSIR_E_INVAL, "params_dev is NULL");
+  if (!(check_fraction >= 0.0f && check_fraction <= 1.0f)) return fail(c, PCSIR_E_INVAL, "check_fraction not in [0, 1]");
+  if (!(tol_nats >= 0.0f)) return fail(c, PCSIR_E_INVAL, "tol_nats must be >= 0 (may be +inf)");
+  if (!valid_act_scales(act_scale_host)) return fail(c, PCSIR_E_INVAL, "activation scales must be finite and > 0");
+  if (c->cfg.lik_mode == PCSIR_LIK_SURR_FP8 && !act_scale_host)
+    return fail(c, PCSIR_E_INVAL, "FP8 surrogate needs the activation scales");
+  drop_graphs(c);  // captured graphs hold the check fraction and tolerance
+  const hipError_t e = surr_prepare(params_dev, act_scale_host, c->at<char>(c->L.surr), c->stream);
+  if (e != hipSuccess) return check_hip(c, e, "pcsir_set_surrogate");
+  c->surr_fraction = check_fraction;
+  c->surr_tol = tol_nats;
+  c->surr_ready = 1;
+  return PCSIR_OK;
+}
+
+pcsir_status pcsir_surrogate_features(pcsir_ctx *c, uint16_t *X_dev, float *y_dev, int32_t cap, int32_t *count) {
+  if (!c || !count || cap < 0 || (cap > 0 && (!X_dev || !y_dev))) return PCSIR_E_INVAL;
+  *count = 0;
+  if (!c->stepped || c->last_sir) return fail(c, PCSIR_E_STATE, "features exist only after pcsir_step");
+  uint64_t B = 0;
+  hipError_t e = hipMemcpyAsync(&B, c->at<uint64_t>(c->L.meta) + META_B, 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return check_hip(c, e, "pcsir_surrogate_features");
+  const Layout &L = c->L;
+  DummyView dv;
+  dv.dpix = c->at<int32_t>(L.dpix);
+  dv.doff = c->at<float>(L.doff);
+  dv.dvel = c->at<float>(L.dvel);
+  dv.dint = c->at<float>(L.dint);
+  dv.seg_t = c->at<int32_t>(L.seg_t);
+  const uint64_t n = std::min<uint64_t>(B, (uint64_t)cap);
+  if (n) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(n, (uint64_t)c->num_cus * 32);
+    if (c->cfg.dim == 2)
+      k_surr_features<2><<<grid, 256, 0, c->stream>>>(c->p, dv, c->at<uint64_t>(L.meta), c->at<StepDesc>(L.desc),
+                                                      c->at<double>(L.ll), (uint32_t)cap, X_dev, y_dev);
+    else
+      k_surr_features<3><<<grid, 256, 0, c->stream>>>(c->p, dv, c->at<uint64_t>(L.meta), c->at<StepDesc>(L.desc),
+                                                      c->at<double>(L.ll), (uint32_t)cap, X_dev, y_dev);
+    e = hipGetLastError();
+    if (e != hipSuccess) return check_hip(c, e, "pcsir_surrogate_features");
+  }
+  *count = (int32_t)B;
+  return PCSIR_OK;
+}
+
+pcsir_status pcsir_surrogate_stats(pcsir_ctx *c, uint64_t *checked, uint64_t *fallbacks, float *max_err, int32_t reset) {
+  if (!c) return PCSIR_E_INVAL;
+  uint64_t m[META_N];
+  hipError_t e = hipMemcpyAsync(m, c->at<uint64_t>(c->L.meta), sizeof m, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && reset) {
+    e = hipMemsetAsync(c->at<uint64_t>(c->L.meta) + META_CHECKED, 0, 8 * 3, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  if (e != hipSuccess) return check_hip(c, e, "pcsir_surrogate_stats");
+  if (checked) *checked = m[META_CHECKED];
+  if (fallbacks) *fallbacks = m[META_FALLBACK];
+  if (max_err) {
+    const uint32_t b = (uint32_t)m[META_MAXERR];
+    memcpy(max_err, &b, 4);
+  }
   return PCSIR_OK;
 }
 

@@ -56,9 +56,12 @@ def exempt_mask(cdf, s, theta, eps):
     return (np.abs(hi - theta) <= eps) | (np.abs(lo - theta) <= eps)
 
 
-def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, w_cond=0.0):
+def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, w_cond=0.0, surrogate=None,
+                    on_filter=None):
     """cloud: [D, NT] float32 (host); frames: [H, W] or [T, H, W] float32 (host).
     Runs one GPU step from `cloud` and checks every stage against the oracle.
+    surrogate: (params, act_scale, check_fraction, tol) installed before the step
+    (a surrogate lik_mode); on_filter(f) runs after the dumps, before close.
     Returns a dict of the largest deviations."""
     import torch
 
@@ -71,6 +74,8 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, w_
     mdl = oracle_model(cfg)
     f = Filter(cfg, torch.from_numpy(np.ascontiguousarray(cloud)).cuda())
     f.set_debug(True)
+    if surrogate is not None:
+        f.set_surrogate(*surrogate)
     fr_t = torch.from_numpy(np.ascontiguousarray(frames)).cuda()
     f.step(fr_t, k, sir=sir)
     est, neff = f.estimate()
@@ -88,6 +93,8 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, w_
         b_n = f.dump("bin_n").cpu().numpy()
         b_mean = f.dump("bin_mean").cpu().numpy()
     after = f.get_particles().cpu().numpy()
+    if on_filter is not None:
+        on_filter(f)
     f.close()
 
     dev = dict(prop=0.0, mean_pos=0.0, mean_vel=0.0, mean_int=0.0, ll=0.0, w=0.0, est=0.0, neff=0.0,

@@ -86,6 +86,19 @@ def test_null_arguments_are_rejected_without_a_device(L):
     assert L.sir_step(None, None, 64, 64, 1) == -1
     assert L.pcsir_estimate(None, None, None) == -1
     assert L.pcsir_destroy(None) == -1
+    # surrogate calls
+    assert L.pcsir_surr_bytes() > 0 and L.pcsir_surr_bytes() % 256 == 0
+    assert L.pcsir_surr_prepare(None, None, None, 0, None) == -1
+    assert L.pcsir_surr_rows(None, None, 0, 0, None, None, None) == -1
+    assert L.pcsir_set_surrogate(None, None, None, C.c_float(0.01), C.c_float(1.0)) == -1
+    cnt = C.c_int32(0)
+    assert L.pcsir_surrogate_features(None, None, None, 0, C.byref(cnt)) == -1
+    assert L.pcsir_surrogate_stats(None, None, None, None, 0) == -1
+    # a surrogate mode with a window too large for the 256 features is refused
+    bad, keep2 = _cfg(lik_mode=2, patch=17)._c()
+    assert L.pcsir_workspace_bytes(C.byref(bad)) == 0
+    ok, keep3 = _cfg(lik_mode=3, patch=15)._c()
+    assert L.pcsir_workspace_bytes(C.byref(ok)) > 0
 
 
 def test_product_never_imports_the_oracle():

@@ -1,0 +1,331 @@
+"""GPU checks of the learned log-likelihood surrogate (through the C ABI).
+
+* Fused inference kernel (BF16 and FP8 E4M3 operands) against a numpy
+  emulation of the same arithmetic (tests/fp_emul.py, pinned on the CPU): the
+  kernel rounds each hidden activation to BF16, and FP8 mode quantises each
+  layer's input and weights; a rounding boundary crossed differently under a
+  different FP32 summation order moves a hidden unit by one BF16 (or E4M3)
+  step, so the bound on f is one BF16 step of every last-layer unit:
+  2^-8 sum_n |w4_n h3_n| (FP8: 98% of rows within it, all within 2^-4 of it).
+* Training rows from an exact pcSIR step against features built from the
+  oracle's bins (window features bit-exact, state features within one BF16
+  step, targets within the log-likelihood tolerance / 100).
+* The surrogate inside the step: with no exact check, l = 100 f - A(z) of the
+  fused kernel; with every dummy checked and tolerance 0, every target falls
+  back and the step has full oracle parity; with a small check fraction, the
+  checked set and the fallback targets follow the counter-based draw exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from fp_emul import bf16_round, e4m3_round
+from gpu_helpers import LL_ATOL, LL_RTOL, log, oracle_model, run_step_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1310_5541_amd import lib
+    lib()
+
+
+def _params(seed, n_in=230):
+    from oracle import mlp
+    th = mlp.init_params(seed, n_in=n_in)
+    p = mlp.unpack(th)
+    rng = np.random.default_rng(seed + 1)
+    for b in ("b1", "b2", "b3"):
+        p[b][:] = rng.normal(0.0, 0.1, 256)
+    p["b4"][:] = 0.3
+    return mlp.pack(p).astype(np.float32)
+
+
+def _rows(n, seed, n_in=230):
+    rng = np.random.default_rng(seed)
+    X = np.zeros((n, 256), np.float32)
+    X[:, :n_in - 5] = rng.normal(0.0, 0.3, (n, n_in - 5))
+    X[:, n_in - 5:n_in] = rng.uniform(-0.5, 0.5, (n, 5))
+    return bf16_round(X)
+
+
+def _gelu32(z):
+    from scipy.special import erf
+    z = z.astype(np.float64)
+    return (0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))).astype(np.float32)
+
+
+def _emulate(th32, X, fp8=False, act_scale=None):
+    """f [n], |w4| |h3| row sums, per-layer input absmax."""
+    from oracle import mlp
+    p = mlp.unpack(th32.astype(np.float64))
+    h = X.astype(np.float32)
+    absmax = []
+    for l, (W, b) in enumerate((("W1", "b1"), ("W2", "b2"), ("W3", "b3"))):
+        absmax.append(float(np.abs(h).max()))
+        W32 = p[W].astype(np.float32)
+        b32 = p[b].astype(np.float32)
+        if fp8:
+            sw = np.float32(np.float32(np.abs(W32).max()) / np.float32(448.0))
+            Wq = e4m3_round(np.clip(W32 / sw, -448, 448).astype(np.float32))
+            inv = np.float32(1.0) / np.float32(act_scale[l])
+            hq = e4m3_round(np.clip(h * inv, -448, 448).astype(np.float32))
+            acc = hq @ Wq
+            sc = np.float64(np.float32(act_scale[l]) * sw)
+            z = (acc * sc + b32).astype(np.float32)
+        else:
+            acc = h.astype(np.float64) @ bf16_round(W32).astype(np.float64)
+            z = (acc.astype(np.float32) + b32).astype(np.float32)
+        h = bf16_round(_gelu32(z))
+    w4 = p["w4"].astype(np.float64)
+    f = h.astype(np.float64) @ w4 + p["b4"][0]
+    scale = np.abs(h.astype(np.float64)) @ np.abs(w4)
+    return f, scale, absmax
+
+
+def test_fused_bf16_matches_emulation_and_training_path():
+    import torch
+
+    from paper_1310_5541_amd import MLPTrainer, SurrogateNet
+    th = _params(11)
+    n = 64 * 7 + 13                     # ragged last block
+    X = _rows(n, 12)
+    pt = torch.from_numpy(th).cuda()
+    Xt = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    log("case fused_bf16 n=461")
+    net = SurrogateNet(pt)
+    f = net.rows(Xt).cpu().numpy().astype(np.float64)
+    f_e, scale, _ = _emulate(th, X)
+    err = np.abs(f - f_e)
+    tol = 2.0 ** -8 * scale + 1e-5 * (1 + np.abs(f_e))
+    log(f"  max |f - emulation| {err.max():.3e}, max ratio to bound {np.max(err / tol):.3f}")
+    assert np.all(err <= tol)
+    # the training path's forward (same network, separate GEMM kernels)
+    n64 = 64 * 7
+    f_tr = MLPTrainer(pt, 64).forward(Xt[:n64].contiguous()).cpu().numpy().astype(np.float64)
+    err2 = np.abs(f[:n64] - f_tr)
+    assert np.all(err2 <= tol[:n64]), err2.max()
+    # a zero-row call is a no-op
+    assert net.rows(Xt[:0]).numel() == 0
+
+
+def test_fused_fp8_matches_emulation_and_calibration():
+    import torch
+
+    from paper_1310_5541_amd import SurrogateNet
+    th = _params(21)
+    n = 64 * 9 + 5
+    X = _rows(n, 22)
+    pt = torch.from_numpy(th).cuda()
+    Xt = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    log("case fused_fp8 calibration")
+    net = SurrogateNet(pt)
+    am = torch.zeros(3, dtype=torch.float32, device="cuda")
+    net.rows(Xt, absmax=am)
+    am = am.cpu().numpy()
+    _, _, am_e = _emulate(th, X)
+    assert am[0] == np.float32(am_e[0])
+    np.testing.assert_allclose(am[1:], am_e[1:], rtol=2.0 ** -7)
+    scales = [float(a) / 448.0 for a in am]
+    log(f"  absmax {am}, scales {scales}")
+    net8 = SurrogateNet(pt, act_scale=scales)
+    f8 = net8.rows(Xt, fp8=True).cpu().numpy().astype(np.float64)
+    f_e, scale, _ = _emulate(th, X, fp8=True, act_scale=scales)
+    err = np.abs(f8 - f_e)
+    tol = 2.0 ** -8 * scale + 1e-5 * (1 + np.abs(f_e))
+    within = np.mean(err <= tol)
+    log(f"  FP8: max |f - emulation| {err.max():.3e}, share within bound {within:.4f}")
+    assert within >= 0.98 and np.all(err <= 16 * tol)
+    # FP8 against BF16 inference of the same network: quantisation error only
+    fb = net.rows(Xt).cpu().numpy().astype(np.float64)
+    rel = np.sqrt(np.mean((f8 - fb) ** 2)) / np.sqrt(np.mean(fb ** 2))
+    log(f"  FP8 vs BF16 relative RMS {rel:.4f}")
+    assert rel < 0.1
+
+
+# ------------------------------------------------------------------ in the step
+def _scene(counts, seed=9, H=96, m=4, patch=11):
+    w = synth.preset("tiny", H=H, W=H, T=len(counts), n=counts, m=(m, m, 1), K=2, i0=(20.0, 100.0),
+                     speed=(0.5, 1.0), patch=patch)
+    tr = synth.truth(w, seed=seed)
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < len(counts):
+        p = rng.uniform(12.0, H - 12.0, 2)
+        if all(np.hypot(*(p - q)) >= 24.0 for q in pts):
+            pts.append(p)
+    tr[:, :, :2] += (np.array(pts) - tr[1, :, :2])[None]
+    fr = synth.frames(w, tr, seed=seed)
+    parts = [synth.random_cloud(w, tr[1, t], int(n), 0.6, 11 + t) for t, n in enumerate(counts)]
+    return w, tr, fr, np.ascontiguousarray(np.concatenate(parts, axis=1))
+
+
+def _oracle_rows(cfg, frame, prop, off):
+    """Expected features (float32, before BF16 rounding), A(z) and the oracle's l per dummy, all targets."""
+    import oracle
+    mdl = oracle_model(cfg)
+    P, R = cfg.patch, cfg.patch // 2
+    Hh, Ww = cfg.frame_h, cfg.frame_w
+    ibg = np.float32(cfg.i_bg)
+    feats, A, ll, tgt = [], [], [], []
+    for t in range(cfg.T):
+        a, b = off[t], off[t + 1]
+        r = oracle.weigh(mdl, frame, prop[:, a:b], sir=False)
+        for j in range(r["B"]):
+            cx, cy = int(r["bin_key"][0, j]), int(r["bin_key"][1, j])
+            c0, r0 = cx // cfg.bins_per_px[0], cy // cfg.bins_per_px[1]
+            row = np.zeros(256, np.float32)
+            s = 0.0
+            for dy in range(P):
+                for dx in range(P):
+                    c, rr = c0 + dx - R, r0 + dy - R
+                    if 0 <= c < Ww and 0 <= rr < Hh:
+                        zb = np.float32(np.float32(frame[rr, c]) - ibg)
+                        row[dy * P + dx] = zb * np.float32(0.01)
+                        s += (float(frame[rr, c]) - float(cfg.i_bg)) ** 2
+            mean = r["bin_mean"][:, j]
+            row[P * P] = mean[0] - c0
+            row[P * P + 1] = mean[1] - r0
+            row[P * P + 2] = np.float32(mean[2]) * np.float32(0.1)
+            row[P * P + 3] = np.float32(mean[3]) * np.float32(0.1)
+            row[P * P + 4] = np.float32(mean[4]) * np.float32(0.01)
+            feats.append(row)
+            A.append(s / (2.0 * cfg.sigma_xi ** 2))
+            ll.append(r["ll"][j])
+            tgt.append(t)
+    return np.array(feats), np.array(A), np.array(ll), np.array(tgt)
+
+
+def _cfg(w, **kw):
+    from paper_1310_5541_amd import Config
+    return Config.from_workload(w, **kw)
+
+
+def test_training_rows_from_an_exact_step():
+    import torch
+    counts = (1, 255, 2049, 5000)
+    w, tr, fr, cloud = _scene(counts)
+    cfg = _cfg(w, seed=5, lik_mode=0)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    got = {}
+
+    def grab(f):
+        got["prop"] = f.dump("propagated").cpu().numpy()
+        X, y, B = f.surrogate_features(cap=100_000)
+        got["X"] = X.float().cpu().numpy()
+        got["y"] = y.cpu().numpy()
+        got["B"] = B
+        Xs, ys, Bs = f.surrogate_features(cap=7)     # a cap below B
+        assert Bs == B and Xs.shape[0] == 7
+        np.testing.assert_array_equal(Xs.float().cpu().numpy(), got["X"][:7])
+
+    log("case training_rows_from_an_exact_step")
+    run_step_parity(cfg, cloud, fr[1], 3, False, on_filter=grab)
+    feats, A, ll, _ = _oracle_rows(cfg, fr[1], got["prop"], off)
+    assert got["B"] == feats.shape[0]
+    X, y = got["X"], got["y"]
+    P2 = cfg.patch ** 2
+    np.testing.assert_array_equal(X[:, :P2], bf16_round(feats[:, :P2]))
+    d = np.abs(X[:, P2:P2 + 5] - bf16_round(feats[:, P2:P2 + 5]))
+    assert np.all(d <= 2.0 ** -7 * np.abs(feats[:, P2:P2 + 5]) + 1e-30), d.max()
+    assert np.all(X[:, P2 + 5:] == 0)
+    y_e = (ll + A) / 100.0
+    tol = (LL_ATOL + LL_RTOL * np.abs(ll)) / 100.0 + 2.0 ** -22 * np.abs(y_e)
+    assert np.all(np.abs(y - y_e) <= tol), np.abs(y - y_e).max()
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_surrogate_step_without_check_is_the_fused_network(mode):
+    import torch
+
+    from paper_1310_5541_amd import Filter, SurrogateNet
+    counts = (300, 2049, 4097)
+    w, tr, fr, cloud = _scene(counts, seed=4, patch=15)
+    cfg = _cfg(w, seed=6, lik_mode=mode)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    th = _params(31)
+    pt = torch.from_numpy(th).cuda()
+    scales = [0.02, 0.01, 0.01] if mode == 3 else None
+    log(f"case surrogate_step_without_check mode={mode}")
+    f = Filter(cfg, torch.from_numpy(cloud).cuda())
+    f.set_debug(True)
+    f.set_surrogate(pt, scales, check_fraction=0.0, tol_nats=float("inf"))
+    frame = torch.from_numpy(fr[1]).cuda()   # read again by surrogate_features: keep it alive
+    f.step(frame, 3)
+    ll = f.dump("loglik").cpu().numpy()
+    prop = f.dump("propagated").cpu().numpy()
+    X, _, B = f.surrogate_features(cap=1 << 20)
+    checked, fb, _ = f.surrogate_stats()
+    f.close()
+    assert checked == 0 and fb == 0 and B == ll.shape[0]
+    net = SurrogateNet(pt, act_scale=scales)
+    fo = net.rows(X.contiguous(), fp8=(mode == 3)).cpu().numpy().astype(np.float64)
+    _, A, _, _ = _oracle_rows(cfg, fr[1], prop, off)
+    exp = 100.0 * fo - A
+    assert np.all(np.abs(ll - exp) <= 1e-9 * (1.0 + np.abs(A))), np.abs(ll - exp).max()
+
+
+def test_surrogate_full_check_falls_back_to_exact_parity():
+    import torch
+    counts = (1, 255, 256, 2049, 5000)
+    w, tr, fr, cloud = _scene(counts, seed=7)
+    cfg = _cfg(w, seed=8, lik_mode=2)
+    pt = torch.from_numpy(_params(41)).cuda()
+    st = {}
+
+    def grab(f):
+        st["stats"] = f.surrogate_stats()
+        st["B"] = f.dump("counts").cpu().numpy()[0]
+
+    log("case surrogate_full_check_falls_back")
+    dev, _ = run_step_parity(cfg, cloud, fr[1], 3, False, surrogate=(pt, None, 1.0, 0.0), on_filter=grab)
+    checked, fb, mx = st["stats"]
+    log(f"  deviations {dev}; stats {st['stats']}")
+    assert checked == int(st["B"]) and fb == len(counts) and mx > 0
+
+
+def test_surrogate_partial_check_follows_the_draw():
+    import torch
+
+    import oracle
+    from paper_1310_5541_amd import Filter, SurrogateNet
+    counts = (1, 3, 40, 255, 2047, 5000)
+    w, tr, fr, cloud = _scene(counts, seed=3, m=2)
+    frac = 0.02
+    cfg = _cfg(w, seed=9, lik_mode=2)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    th = _params(51)
+    pt = torch.from_numpy(th).cuda()
+    k = 3
+    log("case surrogate_partial_check")
+    f = Filter(cfg, torch.from_numpy(cloud).cuda())
+    f.set_debug(True)
+    f.set_surrogate(pt, None, check_fraction=frac, tol_nats=0.0)
+    frame = torch.from_numpy(fr[1]).cuda()
+    f.step(frame, k)
+    ll = f.dump("loglik").cpu().numpy()
+    prop = f.dump("propagated").cpu().numpy()
+    X, _, B = f.surrogate_features(cap=1 << 20)
+    checked, fb, _ = f.surrogate_stats()
+    f.close()
+    feats, A, ll_o, tgt = _oracle_rows(cfg, fr[1], prop, off)
+    fo = SurrogateNet(pt).rows(X.contiguous()).cpu().numpy().astype(np.float64)
+    surr = 100.0 * fo - A
+    # the draw: uniform of counter (dummy, k, target, 2) below the fraction
+    pick = np.array([(int(oracle.philox([e, k, int(tgt[e]), 2], [cfg.seed, 0])[0]) >> 11) * 2.0 ** -53
+                     < float(np.float32(frac)) for e in range(B)])
+    fall = np.zeros(len(counts), bool)
+    fall[np.unique(tgt[pick])] = True
+    log(f"  B {B}, checked {int(pick.sum())}, fallback targets {np.flatnonzero(fall).tolist()}")
+    assert fall.any() and not fall.all(), "the draw should leave both kinds of target"
+    assert checked == int(pick.sum()) and fb == int(fall.sum())
+    exact = fall[tgt] | pick
+    d_ex = np.abs(ll - ll_o)
+    assert np.all(d_ex[exact] <= LL_ATOL + LL_RTOL * np.abs(ll_o[exact]))
+    assert np.all(np.abs(ll - surr)[~exact] <= 1e-9 * (1.0 + np.abs(A[~exact])))
