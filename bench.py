@@ -1,21 +1,29 @@
 #!/usr/bin/env python3
-"""Benchmark: particle-steps/s of SIR vs pcSIR at matched tracking RMSE on one MI355X.
+"""Benchmark: particle-steps/s of SIR vs pcSIR vs surrogate pcSIR at matched tracking RMSE, one MI355X.
 
-Workload (default "single-2d-512"): one 2D target, N = 10^6 particles, 512x512
-synthetic microscopy frames (Gaussian spot sigma 1.5 px, peak 50, background 10,
-Poisson noise), likelihood over a 15x15 window with 8x8 sub-pixel quadrature,
-bins h in {1, 0.5, 0.25, 0.1, 0.05} px.
+Default workload "batched-2d-1024": 1000 targets placed uniformly in 1024x1024
+synthetic microscopy frames (Gaussian spots sigma 1.5 px, peaks U[20, 100],
+background 10, Poisson noise), per-target particle counts floor(10^U[3, 5])
+(2.17e7 in all), likelihood over a 15x15 window with 8x8 sub-pixel
+quadrature, one graph launch per frame. "single-2d-512" (N = 10^6, one target)
+and "3d-astig" (200 targets x 5e4, D = 7) are selectable.
 
-1. Untimed matching pass: SIR and pcSIR at every h track all frames from the
-   truth; the matched pcSIR operating point is the largest h whose RMSE is at
-   most 1.05x SIR's.
-2. Timed region: W warm-up frames, then K frames of pcSIR at the matched h
-   (inputs resident in HBM), bracketed by synchronisation; per-kernel times are
-   taken with HIP events on the library's stream inside the same region.
-3. The same for SIR (reported beside it).
+1. Matching pass (untimed): SIR and pcSIR at h in {1, 0.5, 0.25, 0.1, 0.05}
+   track every frame from the truth on R seeded sequences; the matched pcSIR
+   operating point is the largest h whose mean RMSE is at most 1.05x SIR's.
+2. Surrogate (untimed, reported separately): training rows from exact pcSIR
+   steps at the matched h on 512x512 training sequences (other seeds, the same
+   spot density), GPU training with the library's MFMA kernels, FP8 scale
+   calibration, error against the exact log-likelihood on held-out dummies of
+   this workload, and tracking RMSE on the matching sequences.
+3. Timed regions (inputs resident in HBM, K frames after W warm-up frames,
+   bracketed by device synchronisation): exact pcSIR and SIR with the
+   separable and the per-sub-sample likelihood, surrogate pcSIR in BF16 and
+   FP8. Per-kernel times come from HIP events on the library's stream, over
+   the same frames from the same start.
 4. CPU baseline: the FP64 oracle on a bounded sample of the same workload.
 
-Prints one JSON line.
+`value` is exact pcSIR (separable likelihood) at the matched h. Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -31,9 +39,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VEC_TFLOPS = 157.3
-N_CU = 256
-CLOCK_GHZ = 2.4
+BF16_PEAK_TFLOPS = 2500.0
+FP8_PEAK_TFLOPS = 5000.0
+METRIC = "particle-steps/s: SIR vs pcSIR vs surrogate pcSIR at matched tracking RMSE"
+LIK_SEP, LIK_DIRECT, LIK_SURR_BF16, LIK_SURR_FP8 = 1, 0, 2, 3
 
 
 def parse():
@@ -41,15 +50,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="single-2d-512")
-    ap.add_argument("--lik", type=int, default=0, help="0 direct (per sub-sample), 1 separable")
-    ap.add_argument("--reps", type=int, default=2, help="repetitions of the RMSE matching pass")
+    ap.add_argument("--workload", default="batched-2d-1024")
+    ap.add_argument("--reps", type=int, default=2, help="sequences of the RMSE matching pass")
     ap.add_argument("--no-match", action="store_true", help="skip the RMSE matching pass (use --h)")
     ap.add_argument("--h", type=float, default=0.5)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--train-rows", type=int, default=1_000_000)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--check", type=float, default=0.01, help="share of dummies checked exactly per frame")
+    ap.add_argument("--tol", type=float, default=2.0, help="surrogate fallback threshold (nats)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=0,
-                    help="if > 0: only run this many pcSIR steps (for rocprofv3) and exit")
+                    help="if > 0: only run this many exact pcSIR steps (--lik) and exit (for rocprofv3)")
+    ap.add_argument("--lik", type=int, default=LIK_SEP, help="profile mode: 0 direct, 1 separable")
     return ap.parse_args()
 
 
@@ -58,7 +72,7 @@ def bytes_per_particle(D: int) -> dict:
     step (reads + writes the kernel cannot avoid); sort kernels per pass."""
     return {
         "propagate": 4 * D + 4 + 4 * D,   # parent state + ancestor index in, new state out
-        "keys": 4 * 2 + 4,                 # x, y in; cell key out
+        "keys": 4 * 2 + 4,                 # x, y in; cell key out (3D: + z, see below)
         "sort_hist": 4,                    # key in
         "sort_scatter": 4 + 4,             # key in, key out
         "seg_count": 4,                    # sorted key in
@@ -69,21 +83,26 @@ def bytes_per_particle(D: int) -> dict:
     }
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "design only, see the design notes)"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (sharding over several GPUs "
+                                   "is a design, not built)"}))
         sys.exit(2)
     import torch
 
     import synth
     from paper_1310_5541_amd import Config, Filter
+    from paper_1310_5541_amd import surrogate as sg
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    w = synth.preset(args.workload)
-    K_total = max(w.K, args.warmup + args.steps)
+    w0 = synth.preset(args.workload)
+    K_total = max(w0.K, args.warmup + args.steps)
     w = synth.preset(args.workload, K=K_total)
     t0 = time.time()
     tr = synth.truth(w)
@@ -94,61 +113,121 @@ def main():
     init = torch.from_numpy(synth.initial_particles(w, tr[0], counts)).to(dev)
     gen_s = time.time() - t0
     T, D, dim = w.T, w.D, w.dim
+    log(f"inputs: {args.workload}, {T} targets, {NT} particles, {K_total} frames, {gen_s:.1f} s")
 
-    def make(h, **kw):
+    def bins(h):
         m = int(round(1.0 / h))
-        bins = (m, m, m if dim == 3 else 1)
-        cfg = Config.from_workload(w, bins_per_px=bins, lik_mode=args.lik, seed=w.seed + 500, **kw)
-        return Filter(cfg, init)
+        return (m, m, m if dim == 3 else 1)
+
+    def make(wk, init_state, h, lik, seed_off=500):
+        cfg = Config.from_workload(wk, bins_per_px=bins(h), lik_mode=lik, seed=wk.seed + seed_off)
+        return Filter(cfg, init_state)
 
     def frame(k):
         return frames[(k - 1) % frames.shape[0]]
 
     if args.profile_steps > 0:
-        f = make(args.h)
+        f = make(w, init, args.h, args.lik)
         for k in range(1, args.profile_steps + 1):
             f.pcsir_step(frame(k), k)
         torch.cuda.synchronize()
         f.close()
-        print(json.dumps({"profiled_steps": args.profile_steps}))
+        print(json.dumps({"profiled_steps": args.profile_steps, "workload": w.name, "h": args.h, "lik": args.lik}))
         return
 
     # ---- 1. matching pass (untimed)
     hs = [1.0, 0.5, 0.25, 0.1, 0.05]
-    rm = {}
+    Kmatch = w0.K
+    seqs = []
+    for rep in range(args.reps):
+        wr = synth.preset(args.workload, seed=w.seed + 1000 * rep)
+        trr = synth.truth(wr)
+        frr = torch.from_numpy(synth.frames(wr, trr)).to(dev)
+        initr = torch.from_numpy(synth.initial_particles(wr, trr[0], wr.counts())).to(dev)
+        seqs.append((wr, trr, frr, initr))
+
+    def track_rmse(mode_sir, h, lik, params=None, scales=None, stats=None):
+        out = []
+        for wr, trr, frr, initr in seqs:
+            f = make(wr, initr, h, lik)
+            if params is not None:
+                f.set_surrogate(params, scales, args.check, args.tol)
+            est = np.zeros((Kmatch, T, D))
+            for k in range(1, Kmatch + 1):
+                f.step(frr[k - 1], k, sir=mode_sir)
+                est[k - 1] = f.estimate()[0]
+            if stats is not None:
+                stats.append(f.surrogate_stats())
+            f.close()
+            out.append(float(np.mean(synth.rmse(est, trr[:Kmatch + 1], dim))))
+        return float(np.mean(out))
+
+    rmse = {}
     if not args.no_match:
-        Kmatch = w.K if K_total == w.K else synth.preset(args.workload).K
-        for rep in range(args.reps):
-            wr = synth.preset(args.workload, seed=w.seed + 1000 * rep)
-            trr = synth.truth(wr)
-            frr = torch.from_numpy(synth.frames(wr, trr)).to(dev)
-            initr = torch.from_numpy(synth.initial_particles(wr, trr[0], counts)).to(dev)
-            for mode in ["sir"] + [f"h={h}" for h in hs]:
-                sir = mode == "sir"
-                h = 0.5 if sir else float(mode[2:])
-                m = int(round(1.0 / h))
-                cfg = Config.from_workload(wr, bins_per_px=(m, m, m if dim == 3 else 1), lik_mode=args.lik,
-                                           seed=wr.seed + 500)
-                f = Filter(cfg, initr)
-                est = np.zeros((Kmatch, T, D))
-                for k in range(1, Kmatch + 1):
-                    f.step(frr[k - 1], k, sir=sir)
-                    est[k - 1] = f.estimate()[0]
-                f.close()
-                rm.setdefault(mode, []).append(float(np.mean(synth.rmse(est, trr[:Kmatch + 1], dim))))
-        rmse = {k: float(np.mean(v)) for k, v in rm.items()}
+        rmse["sir"] = track_rmse(True, 0.5, LIK_SEP)
+        for h in hs:
+            rmse[f"h={h}"] = track_rmse(False, h, LIK_SEP)
+            log(f"rmse h={h}: {rmse[f'h={h}']:.4f} (SIR {rmse['sir']:.4f})")
         ok = [h for h in hs if rmse[f"h={h}"] <= 1.05 * rmse["sir"]]
         h_match = max(ok) if ok else min(hs)
     else:
-        rmse = {}
         h_match = args.h
 
-    # ---- 2./3. timed regions
-    def timed(sir, h):
-        """Timed region: K steps replayed as HIP graphs. Then the same K frames again,
-        kernels launched one by one with HIP events between them on the library's
-        stream, for the per-kernel durations."""
-        f = make(h)
+    # ---- 2. surrogate: training rows, training, calibration, held-out error, tracking RMSE
+    surr = None
+    params = scales = None
+    if not args.no_surrogate:
+        t1 = time.perf_counter()
+        wt = synth.preset("train-3d" if dim == 3 else "train-2d-512")
+        cap = args.train_rows
+        X = torch.empty((cap, 256), dtype=torch.bfloat16, device=dev)
+        y = torch.empty(cap, dtype=torch.float32, device=dev)
+        n_rows, seq = 0, 0
+        while n_rows < cap and seq < 20:
+            ws = synth.preset(wt.name, seed=wt.seed + 100 * seq)
+            trs = synth.truth(ws)
+            frs = torch.from_numpy(synth.frames(ws, trs)).to(dev)
+            ins = torch.from_numpy(synth.initial_particles(ws, trs[0], ws.counts())).to(dev)
+            f = make(ws, ins, h_match, LIK_SEP)
+            n_rows = sg.rows(f, frs, 1, ws.K, cap, X, y, start=n_rows)
+            f.close()
+            seq += 1
+        gen_rows_s = time.perf_counter() - t1
+        log(f"surrogate: {n_rows} training rows from {seq} sequences in {gen_rows_s:.1f} s")
+        n_in = w.patch ** 2 + 2 * dim + 1
+        params, hist = sg.train(X[:n_rows], y[:n_rows], epochs=args.epochs, n_in=n_in, log=log)
+        scales = sg.calibrate(params, X[:n_rows])
+        del X, y
+        # held-out rows: exact pcSIR dummies of this workload (matching sequence 0)
+        wr, trr, frr, initr = seqs[0]
+        Xe = torch.empty((400_000, 256), dtype=torch.bfloat16, device=dev)
+        ye = torch.empty(400_000, dtype=torch.float32, device=dev)
+        f.close()
+        f = make(wr, initr, h_match, LIK_SEP)
+        n_ev = sg.rows(f, frr, 1, min(Kmatch, 10), 400_000, Xe, ye)
+        f.close()
+        err_bf16 = sg.evaluate(params, Xe[:n_ev], ye[:n_ev])
+        err_fp8 = sg.evaluate(params, Xe[:n_ev], ye[:n_ev], act_scale=scales, fp8=True)
+        del Xe, ye
+        log(f"surrogate error (nats) bf16 {err_bf16}\n  fp8 {err_fp8}")
+        st_b, st_8 = [], []
+        r_b = track_rmse(False, h_match, LIK_SURR_BF16, params, None, st_b) if not args.no_match else None
+        r_8 = track_rmse(False, h_match, LIK_SURR_FP8, params, scales, st_8) if not args.no_match else None
+        surr = {"train": {"rows": n_rows, "sequences": seq, "workload": wt.name, "row_generation_s":
+                          round(gen_rows_s, 2), "train_s": round(hist["train_s"], 2), "epochs": args.epochs,
+                          "batch": hist["batch"], "steps": hist["steps"],
+                          "rms_nats_per_epoch": [round(float(np.sqrt(m)) * 100, 4) for m in hist["mse_per_epoch"]]},
+                "error_nats_vs_exact": {"bf16": err_bf16, "fp8": err_fp8, "rows": n_ev,
+                                        "rows_from": f"exact pcSIR dummies, first {min(Kmatch, 10)} frames"},
+                "fp8_scales": [float(s) for s in scales], "check_fraction": args.check, "tol_nats": args.tol,
+                "rmse_px": {"bf16": r_b, "fp8": r_8},
+                "checks_fallbacks": {"bf16": st_b, "fp8": st_8}}
+
+    # ---- 3. timed regions
+    def timed(sir, h, lik, with_events):
+        f = make(w, init, h, lik)
+        if lik >= LIK_SURR_BF16:
+            f.set_surrogate(params, scales if lik == LIK_SURR_FP8 else None, args.check, args.tol)
         for k in range(1, args.warmup + 1):
             f.step(frame(k), k, sir=sir)
         state = f.get_particles()
@@ -160,110 +239,126 @@ def main():
         el = time.perf_counter() - t_start
         B = int(f.dump("counts")[0].item()) if not sir else NT
         passes = int(f.dump("counts")[1].item()) if not sir else 0
-        # per-kernel event timing over the same frames from the same start
-        f.set_particles(state)
-        f.set_timing(True)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        for k in range(args.warmup + 1, args.warmup + args.steps + 1):
-            f.step(frame(k), k, sir=sir)
-        torch.cuda.synchronize()
-        el_events = time.perf_counter() - t2
-        per = {}
-        for name, ms in f.kernel_times():
-            per.setdefault(name, []).append(ms)
+        per, el_ev = {}, None
+        if with_events:
+            f.set_particles(state)
+            f.set_timing(True)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for k in range(args.warmup + 1, args.warmup + args.steps + 1):
+                f.step(frame(k), k, sir=sir)
+            torch.cuda.synchronize()
+            el_ev = time.perf_counter() - t2
+            for name, ms in f.kernel_times():
+                per.setdefault(name, []).append(ms)
+        stats = f.surrogate_stats() if lik >= LIK_SURR_BF16 else None
         f.close()
-        return el, per, B, passes, el_events
+        return {"el": el, "per": {k: float(np.sum(v) / args.steps) for k, v in per.items()}, "B": B,
+                "passes": passes, "el_ev": el_ev, "stats": stats}
 
-    el_pc, per_pc, B_pc, passes, ev_pc = timed(False, h_match)
-    el_sir, per_sir, _, _, ev_sir = timed(True, h_match)
     steps = args.steps
-    value = NT * steps / el_pc
-    sir_value = NT * steps / el_sir
+    runs = {}
+    runs["pcsir_sep"] = timed(False, h_match, LIK_SEP, True)
+    runs["pcsir_direct"] = timed(False, h_match, LIK_DIRECT, True)
+    runs["sir_sep"] = timed(True, h_match, LIK_SEP, True)
+    runs["sir_direct"] = timed(True, h_match, LIK_DIRECT, True)
+    if params is not None:
+        runs["surr_bf16"] = timed(False, h_match, LIK_SURR_BF16, True)
+        runs["surr_fp8"] = timed(False, h_match, LIK_SURR_FP8, True)
+    val = {k: NT * steps / r["el"] for k, r in runs.items()}
+    for k, r in runs.items():
+        log(f"{k}: {1e3 * r['el'] / steps:.4f} ms/step, {val[k]:.4g} particle-steps/s")
 
-    # per-kernel: sum the launches of each name within one step (sort passes appear several times)
-    def summarise(per):
-        out = {}
-        for name, lst in per.items():
-            out[name] = float(np.sum(lst) / steps)
-        return out
-
-    k_pc, k_sir = summarise(per_pc), summarise(per_sir)
+    head = runs["pcsir_sep"]
+    passes, B_pc = head["passes"], head["B"]
+    k_pc = head["per"]
     bpp = bytes_per_particle(D)
-    # dominant kernel of the pcSIR step
-    dom = max(k_pc, key=k_pc.get)
-    if dom in bpp:
-        nb = bpp[dom] * NT * (passes if dom.startswith("sort") else 1)
-        launches = passes if dom.startswith("sort") else 1
-        achieved = nb / (k_pc[dom] * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_particle": bpp[dom], "launches_per_step": launches,
-                "avg_ms": round(k_pc[dom] / max(launches, 1), 5)}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-                "traffic": None}
-    # all HBM-bound kernels of the step, achieved GB/s each
+    if dim == 3:
+        bpp["keys"] = 4 * 3 + 4
+    dom = max((k for k in k_pc if k in bpp), key=k_pc.get)
+    launches = passes if dom.startswith("sort") else 1
+    nb = bpp[dom] * NT * launches
+    achieved = nb / (k_pc[dom] * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_particle": bpp[dom],
+            "particles_per_launch": NT, "launches_per_step": launches,
+            "avg_launch_ms": round(k_pc[dom] / max(launches, 1), 5)}
     hbm = {}
     for name, ms in k_pc.items():
-        if name in bpp and ms > 0:
-            mult = passes if name.startswith("sort") else 1
-            if mult == 0:
-                continue
+        mult = passes if name.startswith("sort") else 1
+        if name in bpp and ms > 0 and mult > 0:
             hbm[name] = round(bpp[name] * NT * mult / (ms * 1e-3) / 1e9, 1)
-    # SIR likelihood: exp2 per sub-sample; ALU roofline from unit counts
     P, q = w.patch, w.quad
-    exps = NT * P * P * (q * q if args.lik == 0 else 1) if args.lik == 0 else NT * 2 * P * q
-    lik_ms = k_sir.get("likelihood", float("nan"))
-    sir_lik = {"kernel": "likelihood (SIR)", "bound": "alu", "exp2_per_s": exps / (lik_ms * 1e-3),
-               "ms": lik_ms}
+    lik_direct_ms = runs["sir_direct"]["per"].get("likelihood", float("nan"))
+    sir_lik = {"kernel": "likelihood (SIR, per sub-sample)", "bound": "alu",
+               "exp2_per_s": NT * P * P * q * q / (lik_direct_ms * 1e-3), "ms": lik_direct_ms}
+    if params is not None:
+        sb = runs["surr_bf16"]
+        inf_ms = sb["per"].get("likelihood", float("nan"))
+        flops = 2.0 * (w.patch ** 2 + 2 * dim + 1) * 256 + 2 * 2 * 256 * 256 + 2 * 256   # useful MLP work per dummy
+        flops_padded = 2.0 * 3 * 256 * 256 + 2 * 256                                       # as computed (256 inputs)
+        surr["timed"] = {
+            "bf16": {"value": round(val["surr_bf16"], 1), "ms_per_step": round(1e3 * sb["el"] / steps, 4),
+                     "stats": sb["stats"]},
+            "fp8": {"value": round(val["surr_fp8"], 1),
+                    "ms_per_step": round(1e3 * runs["surr_fp8"]["el"] / steps, 4), "stats": runs["surr_fp8"]["stats"]},
+            "inference_roofline_bf16": {"bound": "mfma", "unit": "TFLOP/s", "peak": BF16_PEAK_TFLOPS,
+                                        "achieved": round(B_pc * flops_padded / (inf_ms * 1e-3) / 1e12, 2),
+                                        "useful_flop_per_dummy": flops, "flop_per_dummy_as_computed": flops_padded,
+                                        "ms": inf_ms},
+            "speedup_over_exact_direct": round(val["surr_bf16"] / val["pcsir_direct"], 3),
+            "speedup_over_exact_separable": round(val["surr_bf16"] / val["pcsir_sep"], 3)}
+        if surr["rmse_px"]["bf16"] is not None and f"h={h_match}" in rmse:
+            surr["rmse_vs_exact_pcsir"] = {m: round(surr["rmse_px"][m] / rmse[f"h={h_match}"], 4)
+                                           for m in ("bf16", "fp8")}
 
     # ---- 4. CPU baseline: the oracle on a bounded sample
     cpu = None
     if not args.no_cpu:
         import oracle
-        from paper_1310_5541_amd._lib import Config as _C  # noqa: F401
-        m = int(round(1.0 / h_match))
-        mdl = oracle.Model(dim=dim, m=(m, m, m if dim == 3 else 1), patch=w.patch, quad=w.quad,
-                           psf=1 if dim == 3 else 0, sigma_psf=w.sigma_psf, i_bg=w.i_bg, sigma_xi=w.sigma_xi,
-                           proc_sigma=w.proc_sigma, seed=w.seed + 500)
+        mdl = oracle.Model(dim=dim, m=bins(h_match), patch=w.patch, quad=w.quad, psf=1 if dim == 3 else 0,
+                           sigma_psf=w.sigma_psf, astig_gamma=w.astig_gamma, astig_d=w.astig_d, i_bg=w.i_bg,
+                           sigma_xi=w.sigma_xi, proc_sigma=w.proc_sigma, seed=w.seed + 500)
         st = synth.initial_particles(w, tr[0], counts)
         t1 = time.perf_counter()
-        kk = 0
-        ps = 0
+        kk = ps = 0
         while time.perf_counter() - t1 < args.cpu_seconds and kk < w.K:
             kk += 1
-            st, _, _ = oracle.track(mdl, frames_np[kk - 1:kk], counts, st, k0=kk)[0], None, None
+            fr_k = frames_np[kk - 1:kk]
+            st = oracle.track(mdl, fr_k, counts, st, k0=kk)[0]
             ps += NT
         el_cpu = time.perf_counter() - t1
         cpu = {"value": ps / el_cpu, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"pcSIR h={h_match}: {kk} frames of the full workload (N={NT}), FP64, 1 thread"}
+               "sample": f"exact pcSIR h={h_match}: {kk} frame(s) of the full workload ({NT} particles), "
+                         f"FP64, one thread"}
 
     out = {
-        "metric": "particle-steps/s: SIR vs pcSIR vs surrogate pcSIR at matched tracking RMSE",
-        "value": round(value, 1),
+        "metric": METRIC,
+        "value": round(val["pcsir_sep"], 1),
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * el_pc / steps, 4),
+        "ms_per_step": round(1e3 * head["el"] / steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (normalisation and cumulative weights f64)",
         "data": "synthetic",
         "config": {"workload": w.name, "targets": T, "particles": NT, "frame": [w.H, w.W], "patch": w.patch,
-                   "quad": w.quad, "likelihood": "direct" if args.lik == 0 else "separable",
-                   "h_matched": h_match, "bins_at_h": B_pc, "sort_passes": passes},
-        "sir": {"value": round(sir_value, 1), "ms_per_step": round(1e3 * el_sir / steps, 4)},
-        "ms_per_step_kernel_by_kernel": {"pcsir": round(1e3 * ev_pc / steps, 4), "sir": round(1e3 * ev_sir / steps, 4)},
-        "speedup_pcsir_over_sir": round(value / sir_value, 2),
+                   "quad": w.quad, "likelihood": "exact, separable", "h_matched": h_match, "bins_at_h": B_pc,
+                   "sort_passes": passes, "graphs": "one graph launch per frame"},
+        "modes": {k: {"value": round(v, 1), "ms_per_step": round(1e3 * runs[k]["el"] / steps, 4),
+                      "ms_per_step_event_timed": round(1e3 * runs[k]["el_ev"] / steps, 4)}
+                  for k, v in val.items()},
+        "speedup_pcsir_over_sir": {"separable": round(val["pcsir_sep"] / val["sir_sep"], 2),
+                                   "direct": round(val["pcsir_direct"] / val["sir_direct"], 2)},
         "rmse_px": rmse,
         "roofline": roof,
         "hbm_gbs_per_kernel": hbm,
-        "kernel_ms_per_step": {"pcsir": {k: round(v, 5) for k, v in k_pc.items()},
-                               "sir": {k: round(v, 5) for k, v in k_sir.items()}},
+        "kernel_ms_per_step": {k: {n: round(v, 5) for n, v in r["per"].items()} for k, r in runs.items()},
         "sir_likelihood": sir_lik,
+        "surrogate": surr,
         "cpu_baseline": cpu,
         "input_generation_s": round(gen_s, 2),
     }

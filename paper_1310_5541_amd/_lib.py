@@ -252,11 +252,15 @@ class Filter:
         self._check(lib().pcsir_set_surrogate(self._ctx, _ptr(params.contiguous()), sc, float(check_fraction),
                                               float(tol_nats)))
 
-    def surrogate_features(self, cap: int):
-        """(X bf16 [n, 256], y fp32 [n], B) training rows from the dummies of the last pcsir_step."""
+    def surrogate_features(self, cap: int, X=None, y=None):
+        """(X bf16 [n, 256], y fp32 [n], B) training rows from the dummies of the last pcsir_step,
+        n = min(B, cap); written into X[:n], y[:n] when those are given (contiguous, >= cap rows)."""
         t = self._torch
-        X = t.empty((max(cap, 1), 256), dtype=t.bfloat16, device=self.device)
-        y = t.empty(max(cap, 1), dtype=t.float32, device=self.device)
+        if X is None:
+            X = t.empty((max(cap, 1), 256), dtype=t.bfloat16, device=self.device)
+            y = t.empty(max(cap, 1), dtype=t.float32, device=self.device)
+        assert X.dtype == t.bfloat16 and X.is_contiguous() and X.shape[0] >= cap and X.shape[1] == 256
+        assert y.dtype == t.float32 and y.is_contiguous() and y.shape[0] >= cap
         cnt = C.c_int32(0)
         self._check(lib().pcsir_surrogate_features(self._ctx, _ptr(X), _ptr(y), int(cap), C.byref(cnt)))
         n = min(cnt.value, cap)

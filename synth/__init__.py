@@ -82,6 +82,15 @@ def preset(name: str, **kw) -> Workload:
         "batched-2d-1024": Workload(name="batched-2d-1024", H=1024, W=1024, K=50, T=1000, n_rule="loguniform",
                                     n_lo=3.0, n_hi=5.0, m=(2, 2, 1), patch=15, quad=8, i0=(20.0, 100.0),
                                     speed=(2.0, 4.0), mid_lo=100.0, mid_hi=924.0),
+        # surrogate training data: 512x512 frames (the single-target workload's
+        # frame size, PSF, window and quadrature) holding spots at the batched
+        # workload's density (250 in the central 412^2), intensities U[20, 100]
+        "train-2d-512": Workload(name="train-2d-512", H=512, W=512, K=60, T=250, n_rule="loguniform", n_lo=3.0,
+                                 n_hi=4.0, m=(2, 2, 1), patch=15, quad=8, i0=(20.0, 100.0), speed=(2.0, 4.0),
+                                 mid_lo=50.0, mid_hi=462.0, seed=7000),
+        "train-3d": Workload(name="train-3d", dim=3, H=256, W=256, K=20, T=100, n=(5_000,), m=(4, 4, 4), patch=15,
+                             quad=8, i0=(20.0, 100.0), speed=(2.0, 4.0),
+                             proc_sigma=(0.5, 0.5, 0.5, 0.1, 0.1, 0.1, 2.0), per_target_frames=True, seed=8000),
         "3d-astig": Workload(name="3d-astig", dim=3, H=256, W=256, K=20, T=200, n=(50_000,), m=(4, 4, 4),
                              patch=15, quad=8, i0=(20.0, 100.0), speed=(2.0, 4.0),
                              proc_sigma=(0.5, 0.5, 0.5, 0.1, 0.1, 0.1, 2.0), per_target_frames=True),
