@@ -64,20 +64,25 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many exact pcSIR steps (--lik) and exit (for rocprofv3)")
     ap.add_argument("--lik", type=int, default=LIK_SEP, help="profile mode: 0 direct, 1 separable")
+    ap.add_argument("--no-graphs", action="store_true", help="profile mode: launch kernels one by one")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="if > 0: only copy this many bytes device to device 3 times and exit "
+                         "(calibration of the HBM byte counters)")
     return ap.parse_args()
 
 
 def bytes_per_particle(D: int) -> dict:
-    """Algorithmic HBM bytes per particle of each HBM-bound kernel of the pcSIR
-    step (reads + writes the kernel cannot avoid); sort kernels per pass."""
+    """Algorithmic HBM bytes per unit of each HBM-bound kernel of the pcSIR step
+    (reads + writes the kernel cannot avoid): per particle, or for the sort and
+    segment kernels per entry of the distinct (tile, cell) key list (sort: per pass)."""
     return {
         "propagate": 4 * D + 4 + 4 * D,   # parent state + ancestor index in, new state out
-        "keys": 4 * 2 + 4,                 # x, y in; cell key out (3D: + z, see below)
-        "sort_hist": 4,                    # key in
-        "sort_scatter": 4 + 4,             # key in, key out
-        "seg_count": 4,                    # sorted key in
-        "seg_mark": 4,                     # sorted key in
-        "bin_sums": 4 + 4 * D + 4,         # key + state in, bin number out
+        "keys": 4 * 2,                     # x, y in (3D: + z); distinct keys out (per list entry, small)
+        "sort_hist": 4,                    # per list entry: key in
+        "sort_scatter": 4 + 4,             # per list entry: key in, key out
+        "seg_count": 4,                    # per list entry: sorted key in
+        "seg_mark": 4,                     # per list entry: sorted key in
+        "bin_sums": 4 * D + 4,             # state in (key recomputed), bin number out
         "cdf_sum": 4,                      # bin number in
         "resample": 4 + 4,                 # bin number in, parent index out
     }
@@ -101,6 +106,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_bytes > 0:
+        a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes": a.numel() * 4, "times": 3}))
+        return
     w0 = synth.preset(args.workload)
     K_total = max(w0.K, args.warmup + args.steps)
     w = synth.preset(args.workload, K=K_total)
@@ -127,12 +140,16 @@ def main():
         return frames[(k - 1) % frames.shape[0]]
 
     if args.profile_steps > 0:
+        # the timed region's frames: W warm-up frames, then the profiled ones
         f = make(w, init, args.h, args.lik)
-        for k in range(1, args.profile_steps + 1):
+        f.set_graphs(not args.no_graphs)
+        for k in range(1, args.warmup + args.profile_steps + 1):
             f.pcsir_step(frame(k), k)
         torch.cuda.synchronize()
+        B = int(f.dump("counts")[0].item())
         f.close()
-        print(json.dumps({"profiled_steps": args.profile_steps, "workload": w.name, "h": args.h, "lik": args.lik}))
+        print(json.dumps({"profiled_steps": args.profile_steps, "warmup": args.warmup, "workload": w.name,
+                          "h": args.h, "lik": args.lik, "bins_last_step": B}))
         return
 
     # ---- 1. matching pass (untimed)
@@ -237,8 +254,10 @@ def main():
             f.step(frame(k), k, sir=sir)
         torch.cuda.synchronize()
         el = time.perf_counter() - t_start
-        B = int(f.dump("counts")[0].item()) if not sir else NT
-        passes = int(f.dump("counts")[1].item()) if not sir else 0
+        cnt = f.dump("counts").cpu().numpy() if not sir else None
+        B = int(cnt[0]) if not sir else NT
+        passes = int(cnt[1]) if not sir else 0
+        Llist = int(cnt[2]) if not sir else 0
         per, el_ev = {}, None
         if with_events:
             f.set_particles(state)
@@ -254,7 +273,7 @@ def main():
         stats = f.surrogate_stats() if lik >= LIK_SURR_BF16 else None
         f.close()
         return {"el": el, "per": {k: float(np.sum(v) / args.steps) for k, v in per.items()}, "B": B,
-                "passes": passes, "el_ev": el_ev, "stats": stats}
+                "passes": passes, "L": Llist, "el_ev": el_ev, "stats": stats}
 
     steps = args.steps
     runs = {}
@@ -272,22 +291,27 @@ def main():
     head = runs["pcsir_sep"]
     passes, B_pc = head["passes"], head["B"]
     k_pc = head["per"]
+    Llist = head["L"]
     bpp = bytes_per_particle(D)
     if dim == 3:
-        bpp["keys"] = 4 * 3 + 4
+        bpp["keys"] = 4 * 3
+    # elements each kernel streams: particles, or entries of the distinct-key list
+    units = {k: NT for k in bpp}
+    for k in ("sort_hist", "sort_scatter", "seg_count", "seg_mark"):
+        units[k] = Llist
     dom = max((k for k in k_pc if k in bpp), key=k_pc.get)
     launches = passes if dom.startswith("sort") else 1
-    nb = bpp[dom] * NT * launches
+    nb = bpp[dom] * units[dom] * launches
     achieved = nb / (k_pc[dom] * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_particle": bpp[dom],
-            "particles_per_launch": NT, "launches_per_step": launches,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_unit": bpp[dom],
+            "units_per_launch": units[dom], "launches_per_step": launches,
             "avg_launch_ms": round(k_pc[dom] / max(launches, 1), 5)}
     hbm = {}
     for name, ms in k_pc.items():
         mult = passes if name.startswith("sort") else 1
         if name in bpp and ms > 0 and mult > 0:
-            hbm[name] = round(bpp[name] * NT * mult / (ms * 1e-3) / 1e9, 1)
+            hbm[name] = round(bpp[name] * units[name] * mult / (ms * 1e-3) / 1e9, 1)
     P, q = w.patch, w.quad
     lik_direct_ms = runs["sir_direct"]["per"].get("likelihood", float("nan"))
     sir_lik = {"kernel": "likelihood (SIR, per sub-sample)", "bound": "alu",
@@ -347,7 +371,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "targets": T, "particles": NT, "frame": [w.H, w.W], "patch": w.patch,
                    "quad": w.quad, "likelihood": "exact, separable", "h_matched": h_match, "bins_at_h": B_pc,
-                   "sort_passes": passes, "graphs": "one graph launch per frame"},
+                   "distinct_tile_keys": Llist, "sort_passes": passes, "graphs": "one graph launch per frame"},
         "modes": {k: {"value": round(v, 1), "ms_per_step": round(1e3 * runs[k]["el"] / steps, 4),
                       "ms_per_step_event_timed": round(1e3 * runs[k]["el_ev"] / steps, 4)}
                   for k, v in val.items()},

@@ -153,7 +153,8 @@ pcsir_status pcsir_set_particles(pcsir_ctx *ctx, const float *src_dev);
  * except PCSIR_DUMP_COUNTS, which synchronises. Layouts:
  *  PROPAGATED  float32 [D][sum N]   propagated states x~_k (before resampling)
  *  KEYS        int32   [3][sum N]   cell index (kx, ky, kz) of every particle; SIR: pixel index
- *  COUNTS      int64   [2]          host-visible copy of (bins B over all targets, passes of the sort)
+ *  COUNTS      int64   [2] or [3]   (bins B over all targets, passes of the sort, length of the sorted
+ *                                   list of distinct per-tile cell keys); the third when bytes >= 24
  *  BIN_TARGET  int32   [B]          target of every bin; bins in ascending (target, kz, ky, kx)
  *  BIN_KEY     int32   [3][B]       cell index of every bin
  *  BIN_N       int64   [B]          members per bin

@@ -278,7 +278,7 @@ class Filter:
         NT, T, D = self.cfg.NT, self.cfg.T, self.cfg.D
         if what in ("bin_target", "bin_key", "bin_n", "bin_mean", "loglik"):
             B = int(self.dump("counts")[0].item())
-        shapes = dict(propagated=((D, NT), t.float32), keys=((3, NT), t.int32), counts=((2,), t.int64),
+        shapes = dict(propagated=((D, NT), t.float32), keys=((3, NT), t.int32), counts=((3,), t.int64),
                       weights=((NT,), t.float64), target=((T, 4), t.float64), cdf=((NT,), t.float64),
                       resample=((NT,), t.int32))
         if what in shapes:

@@ -74,43 +74,22 @@ __device__ __forceinline__ double resample_uniform(uint64_t seed, uint64_t k, ui
 }
 
 // ---------------------------------------------------------------- exact cell index
-// floor((x + 1/2) * m) of the binary32 value x, computed exactly in integer
-// arithmetic from its sign, significand and exponent. x is clamped to
+// floor((x + 1/2) * m) of the binary32 value x, exactly. x is clamped to
 // [-2^24, 2^24] (NaN -> 2^24), the result to [-2^30, 2^30]; 1 <= m <= 4096.
+// For |x| >= 2^-17, x + 1/2 has at most 40 significant bits and m at most
+// 13, so (x + 1/2) m is exact in binary64 and so is its floor. Below, |x m|
+// < 2^-5 and the floor is m/2 rounded down, less one when m is even and
+// x < 0 (x in (-2^-17, 0) pushes (x + 1/2) m just below m/2).
 __device__ __forceinline__ int32_t cell_index(float xf, int32_t m) {
-  uint32_t b = __float_as_uint(xf);
-  if (((b >> 23) & 0xFFu) == 0xFFu) {  // Inf or NaN
-    b = (b & 0x7FFFFFu) ? 0x4B800000u : ((b & 0x80000000u) | 0x4B800000u);  // NaN -> +2^24, Inf -> +-2^24
+  float x = xf;
+  if (x != x) x = 16777216.0f;
+  x = fminf(fmaxf(x, -16777216.0f), 16777216.0f);
+  if (fabsf(x) >= 0x1p-17f) {
+    double v = floor(((double)x + 0.5) * (double)m);
+    v = fmin(fmax(v, -1073741824.0), 1073741824.0);
+    return (int32_t)v;
   }
-  const uint32_t mag = b & 0x7FFFFFFFu;
-  if (mag > 0x4B800000u) b = (b & 0x80000000u) | 0x4B800000u;  // |x| > 2^24 -> +-2^24
-  const bool neg = (b >> 31) != 0;
-  const uint32_t ex = (b >> 23) & 0xFFu;
-  const int64_t half_m = (int64_t)(m >> 1);
-  const int64_t tiny = half_m - (((m & 1) == 0 && neg && (b & 0x7FFFFFFFu)) ? 1 : 0);
-  int64_t k;
-  if (ex == 0) {
-    k = tiny;  // zero or subnormal: |x m| < 1/2
-  } else {
-    const int64_t M = (int64_t)((b & 0x7FFFFFu) | 0x800000u);  // |x| = M 2^E
-    const int E = (int)ex - 150;
-    if (E >= -1) {
-      // 2x + 1 is an integer: (2x + 1) m / 2, floor by arithmetic shift
-      int64_t twox = M << (E + 1);
-      if (neg) twox = -twox;
-      k = ((twox + 1) * (int64_t)m) >> 1;
-    } else if (E >= -40) {
-      // (x + 1/2) m = (+-M + 2^q) m / 2^(q+1), q = -(E+1) in [1, 39]
-      const int q = -(E + 1);
-      const int64_t num = (neg ? -M : M) + ((int64_t)1 << q);
-      k = (num * (int64_t)m) >> (q + 1);
-    } else {
-      k = tiny;  // |x| < 2^-17: |x m| < 2^-5
-    }
-  }
-  const int64_t LIM = (int64_t)1 << 30;
-  k = k > LIM ? LIM : (k < -LIM ? -LIM : k);
-  return (int32_t)k;
+  return (m >> 1) - (((m & 1) == 0 && x < 0.0f) ? 1 : 0);
 }
 
 __device__ __forceinline__ int32_t floor_div(int32_t a, int32_t m) {

@@ -1,19 +1,18 @@
 // gfx950 kernels of one SIR / pcSIR frame. Particles are SoA float32 in HBM,
 // one thread per particle for the streaming stages, one wave64 per likelihood
-// evaluation, LSD radix sort on the compacted cell key for the binning.
+// evaluation. Binning: the distinct cell keys of every tile (LDS hash set),
+// an LSD radix sort of that list, runs of equal keys as bins.
 #pragma once
 #include "device_util.h"
 
 namespace pcsir {
 
 constexpr int TPB = 256;            // threads per block of the streaming kernels
-constexpr int SORT_ITEMS = 16;      // most keys per thread in the radix sort (chosen per size)
-constexpr int SEG_ITEMS = 4;        // rounds of 64 sorted slots per wave in the segmented reduction
-constexpr int SEG_CHUNK = TPB * SEG_ITEMS;
+constexpr int LIST_BLOCKS = 1024;   // workgroups of the sort / segment passes over the key list
 constexpr int SCAN_ITEMS = 4;       // particles per thread in the weight scan
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 constexpr int LIK_WAVES = 4;        // likelihood evaluations per block (one per wave)
-constexpr int BIN_TILES = 4;        // scan tiles of one target per block of the bin sums
+constexpr int BIN_TILES = 4;        // scan tiles of one target per block of the key dedup and bin sums
 
 // Fixed-point scales of the bin sums (integer sums are exact and order-free).
 constexpr float FX_POS = 4294967296.0f;  // 2^32: offsets from the cell's pixel, |d| <= 1/2
@@ -32,6 +31,7 @@ enum {
   META_CHECKED = 6,   // surrogate: dummies checked against the exact likelihood (cumulative)
   META_MAXERR = 7,    // surrogate: largest |l_surrogate - l_exact| seen (float bits)
   META_FALLBACK = 8,  // surrogate: target-frames recomputed exactly (cumulative)
+  META_L = 9,         // length of this frame's list of distinct (tile, cell) keys
   META_N = 12
 };
 constexpr int MAX_DIGIT_BITS = 11;  // radix digit of at most 2048 buckets (LDS histogram)
@@ -66,6 +66,12 @@ __global__ void k_set_desc(StepDesc *__restrict__ d, const float *frame, int64_t
 struct Tile {
   int32_t t;   // target
   uint32_t i0; // first particle of the tile, index within the target
+};
+
+// Bin-sum work item: up to BIN_TILES * SCAN_TILE consecutive particles of one target.
+struct BinTile {
+  int32_t t;
+  uint32_t i0, i1;  // particles [i0, i1) of target t
 };
 
 // ---------------------------------------------------------------- propagation
@@ -179,7 +185,8 @@ __global__ __launch_bounds__(TPB) void k_bbox_reduce(int dim, const uint32_t *__
 }
 
 // Exclusive scan of the per-target cell ranges -> compacted key bases, the
-// total range and the number of 8-bit sort passes it needs. One block.
+// total range, and the radix digit width and number of sort passes it needs;
+// also resets the length of the frame's key list. One block.
 __global__ __launch_bounds__(TPB) void k_bbox_scan(int T, const unsigned long long *__restrict__ range,
                                                    uint32_t *__restrict__ kbase, uint64_t *__restrict__ meta) {
   __shared__ unsigned long long lds[TPB / WAVE];
@@ -207,6 +214,7 @@ __global__ __launch_bounds__(TPB) void k_bbox_scan(int T, const unsigned long lo
     const int width = passes ? (bits + passes - 1) / passes : 1;
     meta[META_PASSES] = (uint64_t)passes;
     meta[META_DIGIT] = (uint64_t)width;
+    meta[META_L] = 0;
   }
 }
 
@@ -221,28 +229,93 @@ __device__ __forceinline__ uint32_t compact_key(const int32_t *c, const int32_t 
 }
 
 template <int DIM>
-__global__ __launch_bounds__(TPB) void k_keys(Params p, const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
-                                              const float *__restrict__ s, const int32_t *__restrict__ bbox_cur,
-                                              const uint32_t *__restrict__ kbase, uint32_t *__restrict__ key) {
-  const Tile tl = tiles[blockIdx.x];
-  const int t = tl.t;
-  const uint32_t base = off[t];
-  const uint32_t i = tl.i0 + threadIdx.x;
-  if (i >= off[t + 1] - base) return;
-  const uint32_t g = base + i;
+__device__ __forceinline__ uint32_t particle_key(const float *__restrict__ s, uint32_t NT, uint32_t g, const int *m,
+                                                 const int32_t *bb, uint32_t kb) {
   int32_t c[3];
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) c[a] = cell_index(s[(size_t)a * p.NT + g], p.m[a]);
+  for (int a = 0; a < DIM; ++a) c[a] = cell_index(s[(size_t)a * NT + g], m[a]);
+  return compact_key<DIM>(c, bb, kb);
+}
+
+// Distinct cell keys of one bin-sum tile (at most BIN_TILES * SCAN_TILE
+// particles of one target), found with an open-addressing hash set in LDS of
+// twice that many slots (so it never fills), appended to the frame's key list.
+// The list holds every occupied cell at least once; its order depends on the
+// order in which workgroups append, which the sort that follows removes.
+constexpr int DEDUP_SLOTS = 2 * BIN_TILES * SCAN_TILE;
+constexpr int DEDUP_SHIFT = 32 - 13;
+static_assert(DEDUP_SLOTS == 1 << 13, "hash slots");
+constexpr uint32_t KEY_EMPTY = 0xFFFFFFFFu;  // compacted keys are < 2^32 - 1 (checked range)
+
+template <int DIM>
+__global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restrict__ tiles,
+                                              const uint32_t *__restrict__ off, const float *__restrict__ s,
+                                              const int32_t *__restrict__ bbox_cur, const uint32_t *__restrict__ kbase,
+                                              uint32_t *__restrict__ list, uint64_t *__restrict__ meta) {
+  constexpr int R = 4;
+  constexpr int PER = DEDUP_SLOTS / TPB;
+  __shared__ uint32_t tab[DEDUP_SLOTS];
+  __shared__ uint32_t lds[TPB / WAVE];
+  __shared__ uint32_t sbase;
+  const BinTile tl = tiles[blockIdx.x];
+  const int t = tl.t;
+  const uint32_t base = off[t];
   int32_t bb[6];
 #pragma unroll
   for (int a = 0; a < 6; ++a) bb[a] = bbox_cur[t * 6 + a];
-  key[g] = compact_key<DIM>(c, bb, kbase[t]);
+  const uint32_t kb = kbase[t];
+  for (int i = threadIdx.x; i < DEDUP_SLOTS; i += TPB) tab[i] = KEY_EMPTY;
+  __syncthreads();
+  for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * TPB) {
+    uint32_t kk[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const uint32_t i = r0 + q * TPB + threadIdx.x;
+      kk[q] = i < tl.i1 ? particle_key<DIM>(s, p.NT, base + i, p.m, bb, kb) : KEY_EMPTY;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const uint32_t k = kk[q];
+      if (k == KEY_EMPTY) continue;
+      uint32_t h = (k * 0x9E3779B1u) >> DEDUP_SHIFT;  // Fibonacci hashing: top bits of the product
+      while (true) {
+        uint32_t v = tab[h];
+        if (v == k) break;
+        if (v == KEY_EMPTY) {
+          v = atomicCAS(&tab[h], KEY_EMPTY, k);
+          if (v == KEY_EMPTY || v == k) break;
+        }
+        h = (h + 1) & (DEDUP_SLOTS - 1);
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) c += tab[threadIdx.x * PER + j] != KEY_EMPTY ? 1u : 0u;
+  uint32_t tot;
+  uint32_t o = block_excl_scan<TPB, uint32_t>(c, lds, &tot);
+  if (threadIdx.x == 0) sbase = (uint32_t)atomicAdd((unsigned long long *)&meta[META_L], (unsigned long long)tot);
+  __syncthreads();
+  o += sbase;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const uint32_t v = tab[threadIdx.x * PER + j];
+    if (v != KEY_EMPTY) list[o++] = v;
+  }
+}
+
+// Contiguous share of a device-sized list for block b of G.
+__device__ __forceinline__ void list_range(uint32_t L, uint32_t G, uint32_t b, uint32_t &j0, uint32_t &j1) {
+  const uint32_t chunk = (L + G - 1) / G;
+  j0 = min(L, b * chunk);
+  j1 = min(L, j0 + chunk);
 }
 
 // ---------------------------------------------------------------- LSD radix sort
-// Stable sort of (key, index) by 8-bit digits; pass `pass` runs only if the
-// key range computed on the device needs it. Pass 0 reads the keys in
-// storage order with implicit indices 0..NT-1.
+// Sort of the key list (length meta[META_L]) by digits of meta[META_DIGIT]
+// bits; pass `pass` runs only if the frame's key range needs it. Each of the
+// G workgroups owns one contiguous share of the list.
 // Lanes of the wave holding the same digit d (at most MAX_DIGIT_BITS bits;
 // invalid lanes carry d = MAX_BUCKETS and match only each other).
 __device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d, int width) {
@@ -257,7 +330,7 @@ __device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d
 
 // Per-block digit histograms of pass `pass`; the digit width comes from the
 // device (meta[META_DIGIT]) and the pass runs only if the key range needs it.
-__global__ __launch_bounds__(TPB) void k_sort_hist(int pass, uint32_t NT, int items, const uint32_t *__restrict__ key,
+__global__ __launch_bounds__(TPB) void k_sort_hist(int pass, const uint32_t *__restrict__ key,
                                                    uint32_t *__restrict__ hist, uint32_t G,
                                                    const uint64_t *__restrict__ meta) {
   if ((uint64_t)pass >= meta[META_PASSES]) return;
@@ -266,12 +339,13 @@ __global__ __launch_bounds__(TPB) void k_sort_hist(int pass, uint32_t NT, int it
   __shared__ uint32_t cnt[MAX_BUCKETS];
   for (uint32_t d = threadIdx.x; d < nb; d += TPB) cnt[d] = 0;
   __syncthreads();
-  const uint32_t b0 = blockIdx.x * (uint32_t)(items * TPB);
+  uint32_t j0, j1;
+  list_range((uint32_t)meta[META_L], G, blockIdx.x, j0, j1);
   const int sh = width * pass;
   const unsigned long long below = (1ull << lane_id()) - 1ull;
-  for (int it = 0; it < items; ++it) {
-    const uint32_t j = b0 + it * TPB + threadIdx.x;
-    const bool valid = j < NT;
+  for (uint32_t r0 = j0; r0 < j1; r0 += TPB) {
+    const uint32_t j = r0 + threadIdx.x;
+    const bool valid = j < j1;
     const uint32_t d = valid ? (key[j] >> sh) & mask : (uint32_t)MAX_BUCKETS;
     const unsigned long long peers = digit_peers(valid, d, width);
     if (valid && (peers & below) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
@@ -304,7 +378,7 @@ __global__ __launch_bounds__(TPB) void k_sort_scan(int pass, uint32_t *__restric
 // round each wave ranks its lanes by digit with ballots, waves are ordered
 // through per-wave digit counts in LDS, and a per-digit running offset
 // carries the order across rounds.
-__global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int items, const uint32_t *__restrict__ key_in,
+__global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, const uint32_t *__restrict__ key_in,
                                                       uint32_t *__restrict__ key_out,
                                                       const uint32_t *__restrict__ hist, uint32_t G,
                                                       const uint32_t *__restrict__ digit_total,
@@ -337,12 +411,13 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int
     }
   }
   __syncthreads();
-  const uint32_t b0 = blockIdx.x * (uint32_t)(items * TPB);
+  uint32_t j0, j1;
+  list_range((uint32_t)meta[META_L], G, blockIdx.x, j0, j1);
   const int sh = width * pass;
   const unsigned long long below = (1ull << lane) - 1ull;
-  for (int it = 0; it < items; ++it) {
-    const uint32_t j = b0 + it * TPB + tid;
-    const bool valid = j < NT;
+  for (uint32_t r0 = j0; r0 < j1; r0 += TPB) {
+    const uint32_t j = r0 + tid;
+    const bool valid = j < j1;
     uint32_t kk = 0, d = (uint32_t)MAX_BUCKETS;
     if (valid) {
       kk = key_in[j];
@@ -369,10 +444,10 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, uint32_t NT, int
 }
 
 // Sorted buffers chosen on the device from the number of passes that ran.
-// Only the keys are sorted: a bin needs nothing but its key; the members'
-// sums are formed afterwards in storage order (k_bin_sums).
+// Only keys are sorted: a bin needs nothing but its key; the members' sums
+// are formed afterwards in storage order (k_bin_sums).
 struct SortBufs {
-  const uint32_t *key_store;  // storage order (0 passes)
+  const uint32_t *key_store;  // the unsorted list (0 passes: a single key value)
   const uint32_t *kA, *kB;
 };
 __device__ __forceinline__ const uint32_t *sorted_keys(const SortBufs &sb, uint64_t passes) {
@@ -380,23 +455,22 @@ __device__ __forceinline__ const uint32_t *sorted_keys(const SortBufs &sb, uint6
 }
 
 // ---------------------------------------------------------------- segments (bins)
-// A bin is a run of equal keys in sorted order. Bins are numbered in sorted
-// order: chunk head counts, their scan, then one pass that records each bin's
-// key, target and the first bin of every target.
+// A bin is a run of equal keys in the sorted list. Bins are numbered in
+// sorted order: per-block head counts, their scan, then one pass that records
+// each bin's key and target, and a search for the first bin of every target.
 __device__ __forceinline__ bool seg_head(const uint32_t *__restrict__ K, uint32_t j) {
   return j == 0 || K[j] != K[j - 1];
 }
 
-__global__ __launch_bounds__(TPB) void k_seg_count(uint32_t NT, SortBufs sb, const uint64_t *__restrict__ meta,
+__global__ __launch_bounds__(TPB) void k_seg_count(uint32_t G, SortBufs sb, const uint64_t *__restrict__ meta,
                                                    uint32_t *__restrict__ chunk_heads) {
   __shared__ uint32_t lds[TPB / WAVE];
   const uint32_t *K = sorted_keys(sb, meta[META_PASSES]);
-  const uint32_t j0 = blockIdx.x * SEG_CHUNK + threadIdx.x * SEG_ITEMS;
+  uint32_t j0, j1;
+  list_range((uint32_t)meta[META_L], G, blockIdx.x, j0, j1);
   uint32_t c = 0;
-  for (int it = 0; it < SEG_ITEMS; ++it) {
-    const uint32_t j = j0 + it;
-    if (j < NT && seg_head(K, j)) ++c;
-  }
+  for (uint32_t j = j0 + threadIdx.x; j < j1; j += TPB)
+    if (seg_head(K, j)) ++c;
   const uint32_t s = block_sum<TPB, uint32_t>(c, lds);
   if (threadIdx.x == 0) chunk_heads[blockIdx.x] = s;
 }
@@ -455,62 +529,75 @@ __device__ __forceinline__ int key_target(uint32_t key, int T, const uint32_t *_
   return lo;
 }
 
-// Record every bin: its key, its target, and the first bin of each target.
-__global__ __launch_bounds__(TPB) void k_seg_mark(Params p, SortBufs sb, const uint64_t *__restrict__ meta,
+// Record every bin: its key and its target.
+__global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs sb, const uint64_t *__restrict__ meta,
                                                   const uint32_t *__restrict__ chunk_base,
                                                   const uint32_t *__restrict__ kbase, uint32_t *__restrict__ seg_key,
-                                                  int32_t *__restrict__ seg_t, uint32_t *__restrict__ seg_first) {
+                                                  int32_t *__restrict__ seg_t) {
   __shared__ uint32_t lds[TPB / WAVE];
-  const uint32_t NT = p.NT;
   const uint32_t *K = sorted_keys(sb, meta[META_PASSES]);
-  const uint32_t j0 = blockIdx.x * SEG_CHUNK + threadIdx.x * SEG_ITEMS;
-  uint32_t c = 0;
-  for (int it = 0; it < SEG_ITEMS; ++it) {
-    const uint32_t j = j0 + it;
-    if (j < NT && seg_head(K, j)) ++c;
-  }
-  uint32_t tot;
-  uint32_t heads = chunk_base[blockIdx.x] + block_excl_scan<TPB, uint32_t>(c, lds, &tot);
-  for (int it = 0; it < SEG_ITEMS; ++it) {
-    const uint32_t j = j0 + it;
-    if (j >= NT) break;
-    const uint32_t kj = K[j];
-    if (j == 0 || kj != K[j - 1]) {
-      const uint32_t sid = heads++;
-      const int t = key_target(kj, p.T, kbase);
-      seg_key[sid] = kj;
-      seg_t[sid] = t;
-      if (j == 0 || key_target(K[j - 1], p.T, kbase) != t) seg_first[t] = sid;
+  uint32_t j0, j1;
+  list_range((uint32_t)meta[META_L], G, blockIdx.x, j0, j1);
+  uint32_t heads = chunk_base[blockIdx.x];
+  for (uint32_t r0 = j0; r0 < j1; r0 += TPB) {
+    const uint32_t j = r0 + threadIdx.x;
+    const bool h = j < j1 && seg_head(K, j);
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<TPB, uint32_t>(h ? 1u : 0u, lds, &tot);
+    if (h) {
+      const uint32_t kj = K[j];
+      seg_key[heads + ex] = kj;
+      seg_t[heads + ex] = key_target(kj, p.T, kbase);
     }
+    heads += tot;
   }
+}
+
+// First bin of every target: the first bin whose key is >= the target's key
+// base (bins are sorted by key and targets own consecutive key ranges);
+// seg_first[T] = B. Defined for every target whatever the keys hold.
+__global__ __launch_bounds__(TPB) void k_seg_first(int T, const uint32_t *__restrict__ kbase,
+                                                   const uint32_t *__restrict__ seg_key,
+                                                   const uint64_t *__restrict__ meta, uint32_t *__restrict__ seg_first) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  if (t > T) return;
+  const uint32_t B = (uint32_t)meta[META_B];
+  if (t == T) {
+    seg_first[T] = B;
+    return;
+  }
+  const uint32_t kb = kbase[t];
+  uint32_t lo = 0, hi = B;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (seg_key[mid] < kb) lo = mid + 1;
+    else hi = mid;
+  }
+  seg_first[t] = lo;
 }
 
 // Members' sums of every bin as exact fixed-point integers: count, offsets of
 // the positions from the pixel that holds them (the pixel of a cell is the
 // pixel of each member, so x - pixel is exact and |.| <= 1/2), velocities and
 // intensity. Particles are read in storage order (coalesced); a block holds
-// one target's tile, finds each particle's bin by binary search of its key
-// among the target's sorted bin keys (staged in LDS), and accumulates in LDS
-// with 64-bit integer atomics before one flush per bin to HBM. Integer sums
-// are exact, so the result does not depend on order. Targets with more bins
-// than the LDS table holds add straight into the global sums. Also writes
-// every particle's bin number (storage order).
+// one target's tile and recomputes each particle's cell key. The target's
+// sorted bin keys are staged in LDS in chunks of BINS: for each chunk, the
+// tile's particles whose key falls in the chunk find their bin by binary
+// search and accumulate in LDS with 64-bit integer atomics, then each bin of
+// the chunk is flushed to HBM once. Integer sums are exact, so the result
+// does not depend on order. Also writes every particle's bin number.
 template <int DIM>
 struct BinLds {
   static constexpr int NC = 2 + 2 * DIM;                // count + D components
   static constexpr int BINS = DIM == 2 ? 1024 : 896;    // table fits in 64 KB with the keys
 };
 
-// Bin-sum work item: up to BIN_TILES * SCAN_TILE consecutive particles of one target.
-struct BinTile {
-  int32_t t;
-  uint32_t i0, i1;  // particles [i0, i1) of target t
-};
-
 template <int DIM>
 __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__restrict__ tiles,
                                                   const uint32_t *__restrict__ off, const float *__restrict__ s,
-                                                  const uint32_t *__restrict__ key, const uint32_t *__restrict__ seg_key,
+                                                  const int32_t *__restrict__ bbox_cur,
+                                                  const uint32_t *__restrict__ kbase,
+                                                  const uint32_t *__restrict__ seg_key,
                                                   const uint32_t *__restrict__ seg_first,
                                                   unsigned long long *__restrict__ acc, uint32_t *__restrict__ segid,
                                                   uint64_t *__restrict__ meta) {
@@ -525,89 +612,94 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
   const int t = tl.t;
   const uint32_t base = off[t];
   const uint32_t s0 = seg_first[t], nb = seg_first[t + 1] - s0;
-  const bool local = nb <= (uint32_t)BINS;
-  if (local) {
-    for (uint32_t b = threadIdx.x; b < nb; b += TPB) {
-      bkey[b] = seg_key[s0 + b];
+  int32_t bb[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) bb[a] = bbox_cur[t * 6 + a];
+  const uint32_t kb = kbase[t];
+  if (nb == 0) {
+    // only when the frame's key range overflowed (reported): keep segid in range
+    for (uint32_t i = tl.i0 + threadIdx.x; i < tl.i1; i += TPB) segid[base + i] = 0;
+    return;
+  }
+  bool sat = false;
+  for (uint32_t c0 = 0; c0 < nb; c0 += BINS) {
+    const uint32_t cn = min((uint32_t)BINS, nb - c0);
+    for (uint32_t b = threadIdx.x; b < cn; b += TPB) {
+      bkey[b] = seg_key[s0 + c0 + b];
 #pragma unroll
       for (int c = 0; c < NC; ++c) bacc[c][b] = 0ull;
     }
-  }
-  __syncthreads();
-  bool sat = false;
-  for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * TPB) {
-    uint32_t kk[R];
-    float x[R][D];
+    __syncthreads();
+    const uint32_t klo = bkey[0], khi = bkey[cn - 1];
+    const bool first = c0 == 0, last = c0 + cn == nb;
+    for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * TPB) {
+      float x[R][D];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const uint32_t i = r0 + q * TPB + threadIdx.x;
-      if (i < tl.i1) {
+      for (int q = 0; q < R; ++q) {
+        const uint32_t i = r0 + q * TPB + threadIdx.x;
+        if (i < tl.i1) {
+#pragma unroll
+          for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + base + i];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint32_t i = r0 + q * TPB + threadIdx.x;
+        if (i >= tl.i1) continue;
         const uint32_t g = base + i;
-        kk[q] = key[g];
+        int32_t cc[3];
 #pragma unroll
-        for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + g];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const uint32_t i = r0 + q * TPB + threadIdx.x;
-      if (i >= tl.i1) continue;
-      const uint32_t g = base + i;
-      uint32_t lo = 0, hi = nb - 1;
-      if (local) {
+        for (int a = 0; a < DIM; ++a) cc[a] = cell_index(x[q][a], p.m[a]);
+        const uint32_t k = compact_key<DIM>(cc, bb, kb);
+        if (k < klo || k > khi) {
+          // a bin of another chunk; the first chunk gives every particle a
+          // valid bin number, which the particle's own chunk overwrites
+          if (first && !last) segid[g] = s0;
+          continue;
+        }
+        uint32_t lo = 0, hi = cn - 1;
         while (lo < hi) {
           const uint32_t mid = (lo + hi) >> 1;
-          if (bkey[mid] < kk[q]) lo = mid + 1;
+          if (bkey[mid] < k) lo = mid + 1;
           else hi = mid;
         }
-      } else {
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (seg_key[s0 + mid] < kk[q]) lo = mid + 1;
-          else hi = mid;
-        }
-      }
-      segid[g] = s0 + lo;
-      long long val[NC];
-      val[0] = 1;
+        segid[g] = s0 + c0 + lo;
+        long long val[NC];
+        val[0] = 1;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const float pix = (float)cell_index(x[q][a], 1);
-        val[1 + a] = __float2ll_rn((x[q][a] - pix) * FX_POS);  // x - pix exact, |.| <= 1/2
-      }
+        for (int a = 0; a < DIM; ++a) {
+          // x - pix is exact and in [-1/2, 1/2), so the scaled value is in [-2^31, 2^31)
+          const float pix = (float)cell_index(x[q][a], 1);
+          val[1 + a] = (long long)__float2int_rn((x[q][a] - pix) * FX_POS);
+        }
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        float vel = x[q][DIM + a];
-        if (!(fabsf(vel) < LIM_VEL)) {
-          sat = true;
-          vel = 0.0f;
+        for (int a = 0; a < DIM; ++a) {
+          float vel = x[q][DIM + a];
+          if (!(fabsf(vel) < LIM_VEL)) {
+            sat = true;
+            vel = 0.0f;
+          }
+          val[1 + DIM + a] = (long long)__float2int_rn(vel * FX_VEL);  // |v 2^24| < 2^31
         }
-        val[1 + DIM + a] = __float2ll_rn(vel * FX_VEL);
-      }
-      {
-        float in = x[q][2 * DIM];
-        if (!(fabsf(in) < LIM_INT)) {
-          sat = true;
-          in = 0.0f;
+        {
+          float in = x[q][2 * DIM];
+          if (!(fabsf(in) < LIM_INT)) {
+            sat = true;
+            in = 0.0f;
+          }
+          val[1 + 2 * DIM] = __float2ll_rn(in * FX_INT);
         }
-        val[1 + 2 * DIM] = __float2ll_rn(in * FX_INT);
-      }
-      if (local) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) atomicAdd(&bacc[c][lo], (unsigned long long)val[c]);
-      } else {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + s0 + lo], (unsigned long long)val[c]);
       }
     }
-  }
-  __syncthreads();
-  if (local) {
-    for (uint32_t b = threadIdx.x; b < nb; b += TPB) {
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < cn; b += TPB) {
       if (bacc[0][b] == 0ull) continue;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + s0 + b], bacc[c][b]);
+      for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + s0 + c0 + b], bacc[c][b]);
     }
+    __syncthreads();
   }
   if (sat) atomicOr((unsigned long long *)&meta[META_ERR], (unsigned long long)ERR_FIXED_SAT);
 }

@@ -26,10 +26,8 @@ struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
       ll, wbin, desc, dvel, surr, tfb, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off;
-  int sort_items; // keys per thread in the radix sort (chosen to fill the device)
   size_t total;
-  uint32_t G;    // sort chunks
-  uint32_t Gs;   // segment chunks
+  uint32_t G;    // workgroups of the sort and segment passes over the key list
   uint32_t n256; // propagate tiles
   uint32_t nS;   // scan tiles
   uint32_t nB;   // bin-sum tiles
@@ -101,24 +99,14 @@ void build_tables(const pcsir_config *c, Tables &tb) {
   tb.t256_first[T] = (uint32_t)tb.t256.size();
 }
 
-// Keys per thread of the radix sort: enough blocks for about 8 per compute
-// unit on the 256-CU device, at most SORT_ITEMS.
 constexpr int MAX_PASSES = (32 + MAX_DIGIT_BITS - 1) / MAX_DIGIT_BITS;
-
-int sort_items_for(size_t NT) {
-  int it = 1;
-  while (it < SORT_ITEMS && NT > (size_t)it * TPB * 256 * 8) it *= 2;
-  return it;
-}
 
 Layout plan(const pcsir_config *c, const Tables &tb) {
   Layout L;
   const size_t NT = tb.off.back();
   const size_t T = c->n_targets;
   const size_t dim = c->dim, D = 2 * dim + 1;
-  L.sort_items = sort_items_for(NT);
-  L.G = (uint32_t)((NT + (size_t)L.sort_items * TPB - 1) / ((size_t)L.sort_items * TPB));
-  L.Gs = (uint32_t)((NT + SEG_CHUNK - 1) / SEG_CHUNK);
+  L.G = (uint32_t)std::max<size_t>(1, std::min<size_t>(LIST_BLOCKS, (NT + TPB - 1) / TPB));
   L.n256 = (uint32_t)tb.t256.size();
   L.nS = (uint32_t)tb.tS.size();
   L.nB = (uint32_t)tb.tB.size();
@@ -136,7 +124,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.kB = take(4 * NT);
   L.hist = take(4 * (size_t)MAX_BUCKETS * (size_t)L.G);
   L.dtot = take(4 * (size_t)MAX_BUCKETS);
-  L.chunk_heads = take(4 * (size_t)L.Gs);
+  L.chunk_heads = take(4 * (size_t)L.G);
   L.acc = take(8 * (1 + D) * NT);
   L.seg_key = take(4 * NT);
   L.seg_t = take(4 * NT);
@@ -363,8 +351,8 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
                                      c->at<int32_t>(L.tfb));
   k_bbox_scan<<<1, TPB, 0, st>>>(p.T, c->at<unsigned long long>(L.range), c->at<uint32_t>(L.kbase), meta);
   mark(c, "keys");
-  k_keys<DIM><<<L.n256, TPB, 0, st>>>(p, t256, off, sout, c->at<int32_t>(L.bbox_cur), c->at<uint32_t>(L.kbase),
-                                      c->at<uint32_t>(L.key));
+  k_keys<DIM><<<L.nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+                                    c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.key), meta);
   SortBufs sb = sort_bufs(c);
   uint32_t *hist = c->at<uint32_t>(L.hist);
   uint32_t *dtot = c->at<uint32_t>(L.dtot);
@@ -372,23 +360,26 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
     const uint32_t *kin = pass == 0 ? sb.key_store : ((pass & 1) ? sb.kB : sb.kA);
     uint32_t *kout = (uint32_t *)((pass & 1) ? sb.kA : sb.kB);
     mark(c, "sort_hist");
-    k_sort_hist<<<L.G, TPB, 0, st>>>(pass, p.NT, L.sort_items, kin, hist, L.G, meta);
+    k_sort_hist<<<L.G, TPB, 0, st>>>(pass, kin, hist, L.G, meta);
     mark(c, "sort_scan");
     k_sort_scan<<<MAX_BUCKETS, TPB, 0, st>>>(pass, hist, L.G, dtot, meta);
     mark(c, "sort_scatter");
-    k_sort_scatter<<<L.G, TPB, 0, st>>>(pass, p.NT, L.sort_items, kin, kout, hist, L.G, dtot, meta);
+    k_sort_scatter<<<L.G, TPB, 0, st>>>(pass, kin, kout, hist, L.G, dtot, meta);
   }
   uint32_t *chunk = c->at<uint32_t>(L.chunk_heads);
   unsigned long long *acc = c->at<unsigned long long>(L.acc);
   mark(c, "seg_count");
-  k_seg_count<<<L.Gs, TPB, 0, st>>>(p.NT, sb, meta, chunk);
+  k_seg_count<<<L.G, TPB, 0, st>>>(L.G, sb, meta, chunk);
   mark(c, "seg_scan");
-  k_seg_scan<<<1, TPB, 0, st>>>(p.T, chunk, L.Gs, meta, c->at<uint32_t>(L.seg_first));
+  k_seg_scan<<<1, TPB, 0, st>>>(p.T, chunk, L.G, meta, c->at<uint32_t>(L.seg_first));
   mark(c, "seg_mark");
-  k_seg_mark<<<L.Gs, TPB, 0, st>>>(p, sb, meta, chunk, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
-                                   c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.seg_first));
+  k_seg_mark<<<L.G, TPB, 0, st>>>(p, L.G, sb, meta, chunk, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
+                                  c->at<int32_t>(L.seg_t));
+  k_seg_first<<<(p.T + 1 + TPB - 1) / TPB, TPB, 0, st>>>(p.T, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
+                                                         meta, c->at<uint32_t>(L.seg_first));
   mark(c, "bin_sums");
-  k_bin_sums<DIM><<<L.nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<uint32_t>(L.key), c->at<uint32_t>(L.seg_key),
+  k_bin_sums<DIM><<<L.nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+                                        c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta);
   mark(c, "dummy");
   k_dummy<DIM><<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(
@@ -749,8 +740,9 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *c, int32_t what, void *dst, size_t byte
     B = c->last_sir ? NT : meta[META_B];
     if (what == PCSIR_DUMP_COUNTS) {
       if (bytes < 16) return fail(c, PCSIR_E_INVAL, "buffer too small");
-      int64_t v[2] = {(int64_t)B, (int64_t)(c->last_sir ? 0 : meta[META_PASSES])};
-      return check_hip(c, hipMemcpy(dst, v, 16, hipMemcpyHostToDevice), "debug dump");
+      const int64_t v[3] = {(int64_t)B, (int64_t)(c->last_sir ? 0 : meta[META_PASSES]),
+                            (int64_t)(c->last_sir ? 0 : meta[META_L])};
+      return check_hip(c, hipMemcpy(dst, v, bytes >= 24 ? 24 : 16, hipMemcpyHostToDevice), "debug dump");
     }
     if (c->last_sir) return fail(c, PCSIR_E_STATE, "bins exist only after pcsir_step");
   }

@@ -281,3 +281,47 @@ def test_graph_replays_match_eager_launches(sir):
     assert torch.equal(fg.get_particles(), fe.get_particles())
     fg.close()
     fe.close()
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 5, 10, 20])
+def test_cell_index_at_adversarial_positions(m):
+    """Cells of positions within a few ulp of every cell edge j/m - 1/2, tiny
+    values around the 2^-17 switch of the GPU's method, signed zeros and
+    negatives; compared with the oracle's exact floor. Zero process noise and
+    zero velocity leave the positions unchanged by propagation."""
+    import torch
+
+    import oracle
+    from paper_1310_5541_amd import Config, Filter
+    edges = (np.arange(-30 * m, 30 * m + 1) / m - 0.5).astype(np.float32)
+    vals = [edges]
+    for d in (1, 2, 3):
+        up, dn = edges.copy(), edges.copy()
+        for _ in range(d):
+            up = np.nextafter(up, np.float32(np.inf))
+            dn = np.nextafter(dn, np.float32(-np.inf))
+        vals += [up, dn]
+    tiny = np.array([2.0 ** -60, 2.0 ** -30, 2.0 ** -18, 2.0 ** -17, 2.0 ** -16, 1e-6, 0.0], np.float32)
+    t17 = np.float32(2.0 ** -17)
+    tiny = np.concatenate([tiny, -tiny, [np.nextafter(t17, np.float32(0)), np.nextafter(t17, np.float32(1)),
+                                         -np.nextafter(t17, np.float32(0)), -np.nextafter(t17, np.float32(1)),
+                                         np.float32(-0.0)]]).astype(np.float32)
+    x = np.concatenate(vals + [tiny]).astype(np.float32)
+    n = x.size
+    rng = np.random.default_rng(m)
+    y = rng.permutation(x)
+    state = np.zeros((5, n), np.float32)
+    state[0], state[1], state[4] = x, y, 50.0
+    w = synth.preset("tiny", H=64, W=64, n=(n,), m=(m, m, 1), proc_sigma=(0.0, 0.0, 0.0, 0.0, 0.0))
+    cfg = _cfg(w, seed=3, lik_mode=1)
+    f = Filter(cfg, torch.from_numpy(state).cuda())
+    f.set_debug(True)
+    frame = torch.full((64, 64), 10.0, dtype=torch.float32, device="cuda")
+    log(f"case cell_index_adversarial m={m} n={n}")
+    f.pcsir_step(frame, 1)
+    prop = f.dump("propagated").cpu().numpy()
+    keys = f.dump("keys").cpu().numpy()
+    f.close()
+    np.testing.assert_array_equal(prop[0], x + np.float32(0.0))
+    np.testing.assert_array_equal(keys[0], oracle.bin_key(prop[0], m))
+    np.testing.assert_array_equal(keys[1], oracle.bin_key(prop[1], m))
