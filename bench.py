@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--h", type=float, default=0.5)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--train-rows", type=int, default=1_000_000)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--check", type=float, default=0.01, help="share of dummies checked exactly per frame")
     ap.add_argument("--tol", type=float, default=2.0, help="surrogate fallback threshold (nats)")
     ap.add_argument("--no-cpu", action="store_true")

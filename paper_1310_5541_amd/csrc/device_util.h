@@ -92,6 +92,16 @@ __device__ __forceinline__ int32_t cell_index(float xf, int32_t m) {
   return (m >> 1) - (((m & 1) == 0 && x < 0.0f) ? 1 : 0);
 }
 
+// Order-preserving map of doubles to unsigned integers (for atomic max); 0
+// is below every mapped value.
+__device__ __forceinline__ unsigned long long ordered_bits(double d) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_ordered_bits(unsigned long long u) {
+  return __longlong_as_double((long long)((u >> 63) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u));
+}
+
 __device__ __forceinline__ int32_t floor_div(int32_t a, int32_t m) {
   int32_t q = a / m;
   if ((a % m) != 0 && (a < 0)) q -= 1;

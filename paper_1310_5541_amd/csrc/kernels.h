@@ -32,6 +32,8 @@ enum {
   META_MAXERR = 7,    // surrogate: largest |l_surrogate - l_exact| seen (float bits)
   META_FALLBACK = 8,  // surrogate: target-frames recomputed exactly (cumulative)
   META_L = 9,         // length of this frame's list of distinct (tile, cell) keys
+  META_NCHK = 10,     // surrogate: dummies picked for the exact check this frame
+  META_NFB = 11,      // surrogate: dummies of fallback targets this frame
   META_N = 12
 };
 constexpr int MAX_DIGIT_BITS = 11;  // radix digit of at most 2048 buckets (LDS histogram)
@@ -90,7 +92,6 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
                                                    int32_t *__restrict__ bbox_part, unsigned long long *__restrict__ acc,
                                                    const uint64_t *__restrict__ meta) {
   constexpr int D = 2 * DIM + 1;
-  __shared__ int32_t red[TPB / WAVE];
   const Tile tl = tiles[blockIdx.x];
   const int t = tl.t;
   const uint32_t base = off[t];
@@ -134,14 +135,28 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
     }
   }
   if (KEYS) {
+    // per-wave extremes, then one barrier and a combine of the block's waves
+    __shared__ int32_t wbox[TPB / WAVE][6];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      const int32_t lo = block_min<TPB>(kmin[a], red);
-      const int32_t hi = block_max<TPB>(kmax[a], red);
-      if (threadIdx.x == 0) {
-        bbox_part[(size_t)blockIdx.x * 6 + a] = lo;
-        bbox_part[(size_t)blockIdx.x * 6 + 3 + a] = hi;
+      const int32_t lo = wave_min(kmin[a]);
+      const int32_t hi = wave_max(kmax[a]);
+      if (lane_id() == 0) {
+        wbox[wave_id()][a] = lo;
+        wbox[wave_id()][3 + a] = hi;
       }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * DIM) {
+      const int a = threadIdx.x % DIM;
+      const bool mx = threadIdx.x >= DIM;
+      int32_t v = wbox[0][mx ? 3 + a : a];
+#pragma unroll
+      for (int w = 1; w < TPB / WAVE; ++w) {
+        const int32_t u = wbox[w][mx ? 3 + a : a];
+        v = mx ? max(v, u) : min(v, u);
+      }
+      bbox_part[(size_t)blockIdx.x * 6 + (mx ? 3 : 0) + a] = v;
     }
   }
 }
@@ -215,6 +230,8 @@ __global__ __launch_bounds__(TPB) void k_bbox_scan(int T, const unsigned long lo
     meta[META_PASSES] = (uint64_t)passes;
     meta[META_DIGIT] = (uint64_t)width;
     meta[META_L] = 0;
+    meta[META_NCHK] = 0;
+    meta[META_NFB] = 0;
   }
 }
 
@@ -812,34 +829,102 @@ __device__ __forceinline__ float scaled_sq(float u, float kh, float kl) {
 __device__ __forceinline__ float sub_offset(int a, int q) { return (float)(2 * a + 1 - q) / (float)(2 * q); }
 
 // Evaluation sets of k_lik: every dummy / particle; the dummies picked for
-// the surrogate's exact check (a counter-based uniform below the check
-// fraction: counter (dummy, k, target, 2)); the dummies of targets whose
-// check failed (exact recomputation, the surrogate's fallback).
+// the surrogate's exact check (list, see k_surr_pick); the dummies of targets
+// whose check failed (list, see k_surr_fallback_list).
 enum { LIK_ALL = 0, LIK_CHECK = 1, LIK_FALLBACK = 2 };
 struct SurrCheck {
   float fraction;            // share of dummies checked per frame
   float tol;                 // largest accepted |l_surrogate - l_exact| (nats)
   int32_t *tfallback;        // [T] per-target fallback flag of this frame
+  const uint32_t *list;      // dummies to evaluate (CHECK / FALLBACK)
+  const unsigned long long *tmax;  // [T] largest surrogate l of each target (ordered bits)
+  float *err;                // CHECK: |l_surrogate - l_exact| of list entry i
 };
+// A checked dummy counts only when its exact or surrogate log-likelihood is
+// within this many nats of its target's largest surrogate value: below, its
+// weight relative to the target's best dummy is under e^-40 whatever the error.
+constexpr double SURR_RELEVANT_NATS = 40.0;
 
+// A dummy is checked when the uniform of counter (dummy, k, target, 2) is
+// below the check fraction.
 __device__ __forceinline__ bool surr_checked(uint64_t seed, uint32_t e, int64_t k, int t, float fraction) {
   const U64x4 b = philox4x64_10(e, (uint64_t)k, (uint64_t)t, 2, seed, 0);
   return (double)(b.v[0] >> 11) * 0x1p-53 < (double)fraction;
 }
 
+// Append e to a list where `take` holds: one ballot and one atomic per wave.
+// The list's order depends on the order of the waves' atomics; every use of
+// it is independent of that order.
+__device__ __forceinline__ void wave_append(bool take, uint32_t e, uint32_t *__restrict__ list,
+                                            uint64_t *__restrict__ count) {
+  const unsigned long long m = __ballot(take);
+  if (m == 0ull) return;
+  const int lane = lane_id();
+  uint32_t base = 0;
+  if (lane == __ffsll((long long)m) - 1) base = (uint32_t)atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(m));
+  base = __shfl(base, __ffsll((long long)m) - 1, WAVE);
+  if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = e;
+}
+// Dummies picked for this frame's exact check.
+__global__ __launch_bounds__(TPB) void k_surr_pick(Params p, const uint64_t *__restrict__ meta,
+                                                   const StepDesc *__restrict__ desc,
+                                                   const int32_t *__restrict__ seg_t, float fraction,
+                                                   uint32_t *__restrict__ list, uint64_t *__restrict__ count) {
+  const uint32_t B = (uint32_t)meta[META_B];
+  const int64_t k = desc->k;
+  for (uint32_t e0 = blockIdx.x * TPB; e0 < B; e0 += gridDim.x * TPB) {
+    const uint32_t e = e0 + threadIdx.x;
+    const bool take = e < B && surr_checked(p.seed, e, k, seg_t[e], fraction);
+    wave_append(take, e, list, count);
+  }
+}
+
+// Zero fill (a kernel, so that captured graphs hold no memset nodes).
+__global__ __launch_bounds__(TPB) void k_clear_u64(unsigned long long *__restrict__ a, uint32_t n) {
+  const uint32_t i = blockIdx.x * TPB + threadIdx.x;
+  if (i < n) a[i] = 0ull;
+}
+
+// Check statistics of the frame: dummies checked, largest error (one block).
+__global__ __launch_bounds__(TPB) void k_surr_stats(const float *__restrict__ err, uint64_t *__restrict__ meta) {
+  __shared__ float lds[TPB / WAVE];
+  const uint32_t n = (uint32_t)meta[META_NCHK];
+  float mx = 0.0f;
+  for (uint32_t i = threadIdx.x; i < n; i += TPB) mx = fmaxf(mx, err[i]);
+  mx = block_max<TPB, float>(mx, lds);
+  if (threadIdx.x == 0) {
+    meta[META_CHECKED] += n;
+    const uint64_t b = (uint64_t)__float_as_uint(mx);
+    if (b > meta[META_MAXERR]) meta[META_MAXERR] = b;
+  }
+}
+
+// Dummies of the targets whose check failed.
+__global__ __launch_bounds__(TPB) void k_surr_fallback_list(const uint64_t *__restrict__ meta,
+                                                            const int32_t *__restrict__ seg_t,
+                                                            const int32_t *__restrict__ tfallback,
+                                                            uint32_t *__restrict__ list, uint64_t *__restrict__ count) {
+  const uint32_t B = (uint32_t)meta[META_B];
+  for (uint32_t e0 = blockIdx.x * TPB; e0 < B; e0 += gridDim.x * TPB) {
+    const uint32_t e = e0 + threadIdx.x;
+    const bool take = e < B && tfallback[seg_t[e]] != 0;
+    wave_append(take, e, list, count);
+  }
+}
+
 template <int DIM, bool SIR, bool SEP, int Q, int MODE = LIK_ALL>
 __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64_t *__restrict__ meta,
                                              const StepDesc *__restrict__ desc, double *__restrict__ ll,
-                                             SurrCheck chk = SurrCheck{0.0f, 0.0f, nullptr},
+                                             SurrCheck chk = SurrCheck{0.0f, 0.0f, nullptr, nullptr, nullptr, nullptr},
                                              uint64_t *__restrict__ stats = nullptr) {
   const float *__restrict__ frame = desc->frame;
-  const uint32_t E = SIR ? p.NT : (uint32_t)meta[META_B];
+  const uint32_t E = SIR ? p.NT
+                         : (uint32_t)meta[MODE == LIK_CHECK ? META_NCHK : (MODE == LIK_FALLBACK ? META_NFB : META_B)];
   const int lane = lane_id();
   const int P = p.P, R = p.R, P2 = P * P;
   const int q = Q ? Q : p.q;
-  for (uint32_t e = blockIdx.x * LIK_WAVES + wave_id(); e < E; e += gridDim.x * LIK_WAVES) {
-    if (MODE == LIK_CHECK && !surr_checked(p.seed, e, desc->k, in.seg_t[e], chk.fraction)) continue;
-    if (MODE == LIK_FALLBACK && !chk.tfallback[in.seg_t[e]]) continue;
+  for (uint32_t idx = blockIdx.x * LIK_WAVES + wave_id(); idx < E; idx += gridDim.x * LIK_WAVES) {
+    const uint32_t e = MODE == LIK_ALL ? idx : chk.list[idx];
     int t;
     int32_t c0, r0;
     float dx, dy, I0, zpos = 0.0f;
@@ -871,9 +956,27 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
     const ExpScale ks = psf_scale(p, zpos);
     const float Iq = I0 / (float)(q * q);
     const float *fr = frame + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
+    // SEPARABLE: the 2 P per-axis sums over q sub-samples are spread over the
+    // wave, H = 64 / (2P) lanes per sum, each adding every H-th sub-sample; the
+    // sum of (axis, pixel c) ends up in lane (axis P + c) H. With 2P > 64, lanes
+    // below P form both axes' sums of their pixel.
+    const int H = WAVE / (2 * P);  // SEPARABLE only
     float gxl = 0.0f, gyl = 0.0f;
     if (SEP) {
-      if (lane < P) {
+      if (H >= 1) {
+        if (lane < 2 * P * H) {
+          const int axis = lane / (P * H);
+          const int rem = lane - axis * P * H;
+          const int pixel = rem / H, part = rem - pixel * H;
+          const float cc = (float)(pixel - R);
+          const float d = axis ? dy : dx;
+          const float kh = axis ? ks.yh : ks.xh, kl = axis ? ks.yl : ks.xl;
+          for (int a = part; a < q; a += H) gxl += exp2_neg(scaled_sq((cc + sub_offset(a, q)) - d, kh, kl));
+        }
+        float tot = gxl;
+        for (int h = 1; h < H; ++h) tot += __shfl(gxl, (lane + h) & (WAVE - 1), WAVE);
+        gxl = tot;
+      } else if (lane < P) {
         const float cc = (float)(lane - R);
         for (int a = 0; a < q; ++a) {
           const float o = sub_offset(a, q);
@@ -888,8 +991,9 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       const int pc = pix % P, pr = pix / P;
       float g = 0.0f;
       if (SEP) {
-        const float gx = __shfl(gxl, pc < P ? pc : 0, WAVE);
-        const float gy = __shfl(gyl, pr < P ? pr : 0, WAVE);
+        const int pcs = pc < P ? pc : 0, prs = pr < P ? pr : 0;
+        const float gx = H >= 1 ? __shfl(gxl, pcs * H, WAVE) : __shfl(gxl, pcs, WAVE);
+        const float gy = H >= 1 ? __shfl(gxl, (P + prs) * H, WAVE) : __shfl(gyl, prs, WAVE);
         g = gx * gy;
       } else if (pix < P2) {
         const float cc = (float)(pc - R), rr = (float)(pr - R);
@@ -935,13 +1039,13 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
     double hi, lo;
     wave_sum_pair(ssd, err, hi, lo);
     const double lx = -(hi + lo) * p.inv2sxi2;
-    if (MODE == LIK_CHECK) {
-      if (lane == 0) {
-        const float d = (float)fabs(lx - ll[e]);
-        atomicAdd((unsigned long long *)&stats[META_CHECKED], 1ull);
-        atomicMax((unsigned long long *)&stats[META_MAXERR], (unsigned long long)__float_as_uint(d));
-        if (!(d <= chk.tol)) atomicOr(&chk.tfallback[t], 1);
-      }
+    if (MODE == LIK_CHECK && lane == 0) {
+      const double ls = ll[e];
+      const float d = (float)fabs(lx - ls);
+      const double top = from_ordered_bits(chk.tmax[t]);
+      const bool relevant = fmax(lx, ls) >= top - SURR_RELEVANT_NATS || !(top == top);
+      if (relevant && !(d <= chk.tol)) chk.tfallback[t] = 1;  // every writer stores 1
+      chk.err[idx] = d != d ? INFINITY : d;
     }
     if (lane == 0) ll[e] = lx;
   }
@@ -1015,7 +1119,7 @@ __global__ __launch_bounds__(TPB) void k_norm_part(Params p, const Tile *__restr
   const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
   double mx = -INFINITY;
   for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    const uint32_t i = tl.i0 + it * TPB + threadIdx.x;
     if (i < n) mx = fmax(mx, ll[base + i]);
   }
   const double M = block_max<TPB, double>(mx, lds);
@@ -1023,7 +1127,7 @@ __global__ __launch_bounds__(TPB) void k_norm_part(Params p, const Tile *__restr
 #pragma unroll
   for (int d = 0; d < D; ++d) X[d] = 0.0;
   for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    const uint32_t i = tl.i0 + it * TPB + threadIdx.x;
     if (i < n) {
       const uint32_t g = base + i;
       const double e = exp(ll[g] - M);
@@ -1114,7 +1218,7 @@ __global__ __launch_bounds__(TPB) void k_cdf_sum(const Tile *__restrict__ tiles,
   const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
   double acc = 0.0;
   for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    const uint32_t i = tl.i0 + it * TPB + threadIdx.x;  // coalesced
     if (i < n) acc += particle_weight<SIR>(ws, tl.t, base + i);
   }
   const double tot = block_sum<TPB, double>(acc, lds);
@@ -1169,6 +1273,11 @@ __device__ __forceinline__ uint32_t count_below(double c, double u, uint32_t n) 
 // are then dealt to the threads in interleaved order (coalesced writes, and
 // no thread serialises the many offspring of a heavy particle); each finds its
 // parent by binary search over the tile's cumulative weights in LDS.
+// Weights are loaded coalesced into LDS first, then each thread takes its
+// SCAN_ITEMS consecutive ones; the LDS array has one pad slot per
+// SCAN_ITEMS entries so that those strided reads do not collide in banks.
+__device__ __forceinline__ uint32_t cpad(uint32_t l) { return l + l / SCAN_ITEMS; }
+
 template <bool SIR>
 __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
                                                       const uint32_t *__restrict__ tile_last,
@@ -1177,18 +1286,24 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
                                                       double *__restrict__ cdf_dbg) {
   __shared__ double lds[TPB / WAVE];
   __shared__ double bound[TPB + 1];
-  __shared__ double cl[SCAN_TILE];
+  __shared__ double cl[SCAN_TILE + SCAN_TILE / SCAN_ITEMS];
   const Tile tl = tiles[blockIdx.x];
   const int t = tl.t;
   const uint32_t base = off[t], n = off[t + 1] - base;
   const uint32_t m = min((uint32_t)SCAN_TILE, n - tl.i0);  // particles in this tile
   const double u = ws.tgt[t * 4 + 3];
+#pragma unroll
+  for (int it = 0; it < SCAN_ITEMS; ++it) {
+    const uint32_t li = it * TPB + threadIdx.x;
+    const uint32_t i = tl.i0 + li;
+    cl[cpad(li)] = i < n ? particle_weight<SIR>(ws, t, base + i) : 0.0;
+  }
+  __syncthreads();
   double w[SCAN_ITEMS];
   double loc = 0.0;
 #pragma unroll
   for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
-    w[it] = i < n ? particle_weight<SIR>(ws, t, base + i) : 0.0;
+    w[it] = cl[cpad(threadIdx.x * SCAN_ITEMS + it)];
     loc += w[it];
   }
   double tot;
@@ -1202,7 +1317,7 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
     bound[threadIdx.x] = b < tile_end ? b : tile_end;
   }
   if (threadIdx.x == 0) bound[TPB] = tile_end;
-  __syncthreads();
+  __syncthreads();  // also: every thread has read its weights from cl
   if (tflag[t]) {
     // non-finite normalisation: keep the particles (identity resampling)
 #pragma unroll
@@ -1228,12 +1343,12 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
       c = pre + (ex + run);  // the target's total
       c = c < cprev ? cprev : c;
       if (cdf_dbg) cdf_dbg[base + i] = c;
-      cl[li] = INFINITY;     // the last particle takes every j left over
+      cl[cpad(li)] = INFINITY;  // the last particle takes every j left over
     } else {
       c = (it == SCAN_ITEMS - 1) ? end : pre + (ex + run);
       c = c < cprev ? cprev : (c > end ? end : c);
       if (cdf_dbg) cdf_dbg[base + i] = c;
-      cl[li] = c;
+      cl[cpad(li)] = c;
     }
     cprev = c;
   }
@@ -1246,14 +1361,14 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
     const double theta = ((double)j + u) / dn;
     // smallest l >= prev with cl[l] > theta (cl[m-1] > theta for every j < jhi)
     uint32_t lo = prev, step = 1, hi = prev;
-    while (hi < m - 1 && !(cl[hi] > theta)) {
+    while (hi < m - 1 && !(cl[cpad(hi)] > theta)) {
       lo = hi + 1;
       hi = min(hi + step, m - 1);
       step *= 2;
     }
     while (lo < hi) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (cl[mid] > theta) hi = mid;
+      if (cl[cpad(mid)] > theta) hi = mid;
       else lo = mid + 1;
     }
     prev = lo;

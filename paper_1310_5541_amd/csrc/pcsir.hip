@@ -24,7 +24,7 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
-      ll, wbin, desc, dvel, surr, tfb, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
+      ll, wbin, desc, dvel, surr, tfb, tmax, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
@@ -138,6 +138,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.desc = take(sizeof(StepDesc));
   L.surr = c->lik_mode >= PCSIR_LIK_SURR_BF16 ? take(SURR_BYTES) : 0;  // surrogate weights
   L.tfb = take(4 * T);
+  L.tmax = take(8 * T);
   L.seg_first = take(4 * (T + 1));
   L.bbox_part = take(4 * 6 * (size_t)L.n256);
   L.range = take(8 * T);
@@ -302,31 +303,43 @@ void launch_surrogate(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   const uint64_t *meta = c->at<uint64_t>(L.meta);
   const StepDesc *desc = c->at<StepDesc>(L.desc);
   double *ll = c->at<double>(L.ll);
-  const uint32_t grid = grid_stride_blocks(c, c->p.NT, SURR_ROWS);
+  const bool fp8 = c->cfg.lik_mode == PCSIR_LIK_SURR_FP8;
+  const uint32_t grid = grid_stride_blocks(c, c->p.NT, fp8 ? SurrRows<true>::N : SurrRows<false>::N);
+  unsigned long long *tmax = c->at<unsigned long long>(L.tmax);
+  k_clear_u64<<<(c->p.T + TPB - 1) / TPB, TPB, 0, st>>>(tmax, (uint32_t)c->p.T);
   if (c->cfg.lik_mode == PCSIR_LIK_SURR_FP8)
-    k_surr_infer<DIM, true><<<grid, 256, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll);
+    k_surr_infer<DIM, true><<<grid, 256, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
   else
-    k_surr_infer<DIM, false><<<grid, 256, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll);
+    k_surr_infer<DIM, false><<<grid, 256, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
+  // exact check of the picked dummies, then exact recomputation of the targets
+  // that failed it; the lists reuse the sort buffers, free at this point
+  uint32_t *list_chk = c->at<uint32_t>(L.kA), *list_fb = c->at<uint32_t>(L.kB);
+  uint64_t *meta_w = c->at<uint64_t>(L.meta);
+  int32_t *tfb = c->at<int32_t>(L.tfb);
+  const uint32_t pg = grid_stride_blocks(c, c->p.NT, TPB);
   SurrCheck chk;
   chk.fraction = c->surr_fraction;
   chk.tol = c->surr_tol;
-  chk.tfallback = c->at<int32_t>(L.tfb);
-  uint64_t *stats = c->at<uint64_t>(L.meta);
+  chk.tfallback = tfb;
+  chk.list = list_chk;
+  chk.tmax = tmax;
+  chk.err = (float *)c->at<double>(L.wbin);  // bin weights are formed after the check
   const uint32_t lg = grid_stride_blocks(c, c->p.NT, LIK_WAVES);
   const Params &p = c->p;
   mark(c, "surr_check");
-  switch (p.q) {
-    case 8:
-      k_lik<DIM, false, false, 8, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, stats);
-      mark(c, "surr_fallback");
-      k_lik<DIM, false, false, 8, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, stats);
-      break;
-    default:
-      k_lik<DIM, false, false, 0, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, stats);
-      mark(c, "surr_fallback");
-      k_lik<DIM, false, false, 0, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, stats);
-      break;
-  }
+  k_surr_pick<<<pg, TPB, 0, st>>>(p, meta, desc, in.seg_t, c->surr_fraction, list_chk, meta_w + META_NCHK);
+  if (p.q == 8)
+    k_lik<DIM, false, false, 8, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
+  else
+    k_lik<DIM, false, false, 0, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
+  k_surr_stats<<<1, TPB, 0, st>>>(chk.err, meta_w);
+  mark(c, "surr_fallback");
+  k_surr_fallback_list<<<pg, TPB, 0, st>>>(meta, in.seg_t, tfb, list_fb, meta_w + META_NFB);
+  chk.list = list_fb;
+  if (p.q == 8)
+    k_lik<DIM, false, false, 8, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
+  else
+    k_lik<DIM, false, false, 0, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
 }
 
 template <int DIM, bool SEP>
@@ -872,7 +885,8 @@ pcsir_status pcsir_surr_rows(const void *surr_dev, const uint16_t *X_dev, int32_
   if (n == 0) return PCSIR_OK;
   const hipStream_t st = (hipStream_t)hip_stream;
   const SurrWeights sw = surr_view((void *)surr_dev);
-  const int grid = std::min((n + SURR_ROWS - 1) / SURR_ROWS, 8192);
+  const int rows = fp8 ? SurrRows<true>::N : SurrRows<false>::N;
+  const int grid = std::min((n + rows - 1) / rows, 8192);
   if (fp8)
     k_surr_rows<true><<<grid, 256, 0, st>>>(n, X_dev, sw, f_dev, (unsigned int *)absmax_dev);
   else

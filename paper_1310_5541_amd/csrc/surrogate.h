@@ -2,7 +2,9 @@
 // rows, for tests and calibration): features -> three MFMA layers with exact
 // GELU -> output unit -> l = 100 f - A(z). BF16 or FP8 (E4M3, per-tensor
 // scales) operands, FP32 accumulation. One block of four waves per 64 rows;
-// each wave owns 64 of the 256 output units of a layer.
+// each wave owns 64 of the 256 output units of a layer, so every weight read
+// from L2 serves all the block's rows. (128 rows per block halve the weight
+// traffic but need 288 registers per lane: one wave per SIMD, slower.)
 #pragma once
 #include "device_util.h"
 #include "kernels.h"
@@ -10,7 +12,12 @@
 
 namespace pcsir {
 
-constexpr int SURR_ROWS = 64;
+constexpr int SURR_ROWS = 64;       // rows per block, FP8
+constexpr int SURR_ROWS_BF16 = 64;  // rows per block, BF16
+template <bool FP8>
+struct SurrRows {
+  static constexpr int N = FP8 ? SURR_ROWS : SURR_ROWS_BF16;
+};
 constexpr int SURR_LD = MLP_F + 8;      // LDS row stride (bf16 elements)
 constexpr int SURR_LD8 = MLP_F + 16;    // LDS row stride (fp8 bytes)
 constexpr float FP8_MAX = 448.0f;       // largest finite E4M3 value
@@ -106,18 +113,20 @@ __device__ __forceinline__ double dummy_data_term(const Params &p, const DummyVi
 template <bool FP8>
 __device__ __forceinline__ void surr_layers(const SurrWeights &sw, uint16_t (*X)[SURR_LD], uint8_t (*X8)[SURR_LD8],
                                             float *fout, unsigned int *absmax = nullptr) {
+  constexpr int ROWS = SurrRows<FP8>::N;
+  constexpr int RT = ROWS / 32;  // 32-row MFMA tiles
   const int lane = lane_id(), w = wave_id(), tid = threadIdx.x;
   for (int l = 0; l < 3; ++l) {
     if (absmax) {
       float mx = 0.0f;
-      for (int e = tid; e < SURR_ROWS * MLP_F; e += 256) mx = fmaxf(mx, fabsf(bf2f(X[e / MLP_F][e % MLP_F])));
+      for (int e = tid; e < ROWS * MLP_F; e += 256) mx = fmaxf(mx, fabsf(bf2f(X[e / MLP_F][e % MLP_F])));
       mx = wave_max(mx);
       if (lane == 0) atomicMax(&absmax[l], __float_as_uint(mx));
     }
     if (FP8) {
       // quantize this layer's input with its per-tensor scale
       const float inv = 1.0f / sw.scale_x[l];
-      for (int e = tid; e < SURR_ROWS * (MLP_F / 2); e += 256) {
+      for (int e = tid; e < ROWS * (MLP_F / 2); e += 256) {
         const int m = e / (MLP_F / 2), k = 2 * (e % (MLP_F / 2));
         const float a = fminf(fmaxf(bf2f(X[m][k]) * inv, -FP8_MAX), FP8_MAX);
         const float b = fminf(fmaxf(bf2f(X[m][k + 1]) * inv, -FP8_MAX), FP8_MAX);
@@ -127,9 +136,9 @@ __device__ __forceinline__ void surr_layers(const SurrWeights &sw, uint16_t (*X)
       }
       __syncthreads();
     }
-    f32x16 acc[2][2];
+    f32x16 acc[RT][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -140,35 +149,35 @@ __device__ __forceinline__ void surr_layers(const SurrWeights &sw, uint16_t (*X)
 #pragma unroll 4
       for (int kk = 0; kk < MLP_F; kk += 16) {
         const int k = kk + mfma_k0(lane);
-        const uint2 a0 = *reinterpret_cast<const uint2 *>(&X8[mfma_col(lane)][k]);
-        const uint2 a1 = *reinterpret_cast<const uint2 *>(&X8[32 + mfma_col(lane)][k]);
         const uint2 b0 = *reinterpret_cast<const uint2 *>(W8 + (size_t)(nb + mfma_col(lane)) * MLP_F + k);
         const uint2 b1 = *reinterpret_cast<const uint2 *>(W8 + (size_t)(nb + 32 + mfma_col(lane)) * MLP_F + k);
-        acc[0][0] = mfma_fp8(a0, b0, acc[0][0]);
-        acc[0][1] = mfma_fp8(a0, b1, acc[0][1]);
-        acc[1][0] = mfma_fp8(a1, b0, acc[1][0]);
-        acc[1][1] = mfma_fp8(a1, b1, acc[1][1]);
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          const uint2 a = *reinterpret_cast<const uint2 *>(&X8[32 * i + mfma_col(lane)][k]);
+          acc[i][0] = mfma_fp8(a, b0, acc[i][0]);
+          acc[i][1] = mfma_fp8(a, b1, acc[i][1]);
+        }
       }
     } else {
       const uint16_t *Wt = sw.wt + (size_t)l * MLP_H * MLP_F;
-#pragma unroll 4
+#pragma unroll 2
       for (int kk = 0; kk < MLP_F; kk += 16) {
         const int k = kk + mfma_k0(lane);
-        const uint4 a0 = *reinterpret_cast<const uint4 *>(&X[mfma_col(lane)][k]);
-        const uint4 a1 = *reinterpret_cast<const uint4 *>(&X[32 + mfma_col(lane)][k]);
         const uint4 b0 = *reinterpret_cast<const uint4 *>(Wt + (size_t)(nb + mfma_col(lane)) * MLP_F + k);
         const uint4 b1 = *reinterpret_cast<const uint4 *>(Wt + (size_t)(nb + 32 + mfma_col(lane)) * MLP_F + k);
-        acc[0][0] = mfma_bf16(a0, b0, acc[0][0]);
-        acc[0][1] = mfma_bf16(a0, b1, acc[0][1]);
-        acc[1][0] = mfma_bf16(a1, b0, acc[1][0]);
-        acc[1][1] = mfma_bf16(a1, b1, acc[1][1]);
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          const uint4 a = *reinterpret_cast<const uint4 *>(&X[32 * i + mfma_col(lane)][k]);
+          acc[i][0] = mfma_bf16(a, b0, acc[i][0]);
+          acc[i][1] = mfma_bf16(a, b1, acc[i][1]);
+        }
       }
     }
     __syncthreads();  // every wave has read this layer's input
     const float sc = FP8 ? sw.scale_x[l] * sw.scale_w[l] : 1.0f;
     const float *bias = sw.bias + l * MLP_H;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -179,7 +188,7 @@ __device__ __forceinline__ void surr_layers(const SurrWeights &sw, uint16_t (*X)
         }
     __syncthreads();
   }
-  if (tid < SURR_ROWS) {
+  if (tid < ROWS) {
     float f = sw.b4[0];
     for (int n = 0; n < MLP_H; ++n) f = fmaf(bf2f(X[tid][n]), sw.w4[n], f);
     fout[tid] = f;
@@ -187,33 +196,48 @@ __device__ __forceinline__ void surr_layers(const SurrWeights &sw, uint16_t (*X)
   __syncthreads();
 }
 
-// Surrogate log-likelihood of every dummy of the step: ll[s] = 100 f - A(z).
+// Surrogate log-likelihood of every dummy of the step: ll[s] = 100 f - A(z),
+// and every target's largest surrogate value (tmax, ordered bits, atomic max;
+// dummies are sorted by target, so a block's rows span consecutive targets).
 template <int DIM, bool FP8>
 __global__ __launch_bounds__(256) void k_surr_infer(Params p, DummyView dv, const uint64_t *__restrict__ meta,
                                                     const StepDesc *__restrict__ desc, SurrWeights sw,
-                                                    double *__restrict__ ll) {
-  __shared__ __attribute__((aligned(16))) uint16_t X[SURR_ROWS][SURR_LD];
+                                                    double *__restrict__ ll, unsigned long long *__restrict__ tmax) {
+  constexpr int ROWS = SurrRows<FP8>::N;
+  __shared__ __attribute__((aligned(16))) uint16_t X[ROWS][SURR_LD];
   __shared__ __attribute__((aligned(16))) uint8_t X8[FP8 ? SURR_ROWS : 1][SURR_LD8];
-  __shared__ float fout[SURR_ROWS];
-  __shared__ double az[SURR_ROWS];
+  __shared__ float fout[ROWS];
+  __shared__ double az[ROWS];
   const uint32_t B = (uint32_t)meta[META_B];
   const float *frame = desc->frame;
-  for (uint32_t s0 = blockIdx.x * SURR_ROWS; s0 < B; s0 += gridDim.x * SURR_ROWS) {
-    for (int e = threadIdx.x; e < SURR_ROWS * MLP_F; e += 256) {
+  for (uint32_t s0 = blockIdx.x * ROWS; s0 < B; s0 += gridDim.x * ROWS) {
+    for (int e = threadIdx.x; e < ROWS * MLP_F; e += 256) {
       const int m = e / MLP_F, f = e % MLP_F;
       const uint32_t s = s0 + m;
       X[m][f] = f2bf(s < B ? dummy_feature<DIM>(p, dv, frame, s, f) : 0.0f);
     }
-    if (threadIdx.x < SURR_ROWS) {
+    if (threadIdx.x < ROWS) {
       const uint32_t s = s0 + threadIdx.x;
       az[threadIdx.x] = s < B ? dummy_data_term<DIM>(p, dv, frame, s) : 0.0;
     }
     __syncthreads();
     surr_layers<FP8>(sw, X, X8, fout);
-    if (threadIdx.x < SURR_ROWS) {
+    // tmx[j]: largest value among rows of target t_first + j (at most ROWS targets)
+    __shared__ unsigned long long tmx[ROWS];
+    if (threadIdx.x < ROWS) tmx[threadIdx.x] = 0ull;
+    __syncthreads();
+    const int t_first = dv.seg_t[s0];
+    if (threadIdx.x < ROWS) {
       const uint32_t s = s0 + threadIdx.x;
-      if (s < B) ll[s] = (double)MLP_OUT_SCALE * (double)fout[threadIdx.x] - az[threadIdx.x];
+      if (s < B) {
+        const double v = (double)MLP_OUT_SCALE * (double)fout[threadIdx.x] - az[threadIdx.x];
+        ll[s] = v;
+        atomicMax(&tmx[dv.seg_t[s] - t_first], ordered_bits(v));
+      }
     }
+    __syncthreads();
+    if (threadIdx.x < ROWS && tmx[threadIdx.x] != 0ull)
+      atomicMax(&tmax[t_first + threadIdx.x], tmx[threadIdx.x]);
     __syncthreads();
   }
 }
@@ -222,17 +246,18 @@ __global__ __launch_bounds__(256) void k_surr_infer(Params p, DummyView dv, cons
 template <bool FP8>
 __global__ __launch_bounds__(256) void k_surr_rows(int n, const uint16_t *__restrict__ Xg, SurrWeights sw,
                                                    float *__restrict__ f_out, unsigned int *__restrict__ absmax) {
-  __shared__ __attribute__((aligned(16))) uint16_t X[SURR_ROWS][SURR_LD];
+  constexpr int ROWS = SurrRows<FP8>::N;
+  __shared__ __attribute__((aligned(16))) uint16_t X[ROWS][SURR_LD];
   __shared__ __attribute__((aligned(16))) uint8_t X8[FP8 ? SURR_ROWS : 1][SURR_LD8];
-  __shared__ float fout[SURR_ROWS];
-  for (int r0 = blockIdx.x * SURR_ROWS; r0 < n; r0 += gridDim.x * SURR_ROWS) {
-    for (int e = threadIdx.x; e < SURR_ROWS * MLP_F; e += 256) {
+  __shared__ float fout[ROWS];
+  for (int r0 = blockIdx.x * ROWS; r0 < n; r0 += gridDim.x * ROWS) {
+    for (int e = threadIdx.x; e < ROWS * MLP_F; e += 256) {
       const int m = e / MLP_F, f = e % MLP_F;
       X[m][f] = r0 + m < n ? Xg[(size_t)(r0 + m) * MLP_F + f] : (uint16_t)0;
     }
     __syncthreads();
     surr_layers<FP8>(sw, X, X8, fout, absmax);
-    if (threadIdx.x < SURR_ROWS && r0 + threadIdx.x < n) f_out[r0 + threadIdx.x] = fout[threadIdx.x];
+    if (threadIdx.x < ROWS && r0 + threadIdx.x < n) f_out[r0 + threadIdx.x] = fout[threadIdx.x];
     __syncthreads();
   }
 }
