@@ -59,12 +59,14 @@ def parse():
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--check", type=float, default=0.01, help="share of dummies checked exactly per frame")
     ap.add_argument("--tol", type=float, default=2.0, help="surrogate fallback threshold (nats)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many exact pcSIR steps (--lik) and exit (for rocprofv3)")
     ap.add_argument("--lik", type=int, default=LIK_SEP, help="profile mode: 0 direct, 1 separable")
     ap.add_argument("--no-graphs", action="store_true", help="profile mode: launch kernels one by one")
+    ap.add_argument("--tuning", default="", help="profile mode: launch shapes as JSON (pcsir_tuning fields)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="if > 0: only copy this many bytes device to device 3 times and exit "
                          "(calibration of the HBM byte counters)")
@@ -90,6 +92,26 @@ def bytes_per_particle(D: int) -> dict:
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def counter_traffic(workload: str, h: float, likelihood: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size), or None when
+    the summary is for another configuration or the kernel sources have changed."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("workload") != workload or abs(rec.get("h", -1) - h) > 1e-9 or rec.get("likelihood") != likelihood:
+        return None
+    hsh = hashlib.sha256()
+    for f in rec["sources"]:
+        hsh.update(open(os.path.join(ROOT, f), "rb").read())
+    if hsh.hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    k = rec["per_launch"].get(kernel)
+    return None if k is None else round(k["traffic_bytes"], 0)
 
 
 def main():
@@ -143,6 +165,8 @@ def main():
         # the timed region's frames: W warm-up frames, then the profiled ones
         f = make(w, init, args.h, args.lik)
         f.set_graphs(not args.no_graphs)
+        if args.tuning:
+            f.set_tuning(**json.loads(args.tuning))
         for k in range(1, args.warmup + args.profile_steps + 1):
             f.pcsir_step(frame(k), k)
         torch.cuda.synchronize()
@@ -241,12 +265,22 @@ def main():
                 "checks_fallbacks": {"bf16": st_b, "fp8": st_8}}
 
     # ---- 3. timed regions
-    def timed(sir, h, lik, with_events):
+    tuned = {}
+
+    def timed(sir, h, lik, with_events, autotune=False):
         f = make(w, init, h, lik)
         if lik >= LIK_SURR_BF16:
             f.set_surrogate(params, scales if lik == LIK_SURR_FP8 else None, args.check, args.tol)
+        if not sir and "shapes" in tuned:
+            f.set_tuning(**tuned["shapes"])
         for k in range(1, args.warmup + 1):
             f.step(frame(k), k, sir=sir)
+        if autotune and not args.no_autotune:
+            # launch shapes searched on the next frame; the particles are left as they were
+            t0 = time.perf_counter()
+            best, ms, n = f.autotune(frame(args.warmup + 1), args.warmup + 1, reps=3)
+            tuned.update(shapes=best, ms_per_step=round(ms, 4), trials=n, seconds=round(time.perf_counter() - t0, 2))
+            log(f"autotune: {best} ({ms:.4f} ms/step, {n} trials)")
         state = f.get_particles()
         torch.cuda.synchronize()
         t_start = time.perf_counter()
@@ -277,7 +311,7 @@ def main():
 
     steps = args.steps
     runs = {}
-    runs["pcsir_sep"] = timed(False, h_match, LIK_SEP, True)
+    runs["pcsir_sep"] = timed(False, h_match, LIK_SEP, True, autotune=True)
     runs["pcsir_direct"] = timed(False, h_match, LIK_DIRECT, True)
     runs["sir_sep"] = timed(True, h_match, LIK_SEP, True)
     runs["sir_direct"] = timed(True, h_match, LIK_DIRECT, True)
@@ -303,8 +337,12 @@ def main():
     launches = passes if dom.startswith("sort") else 1
     nb = bpp[dom] * units[dom] * launches
     achieved = nb / (k_pc[dom] * 1e-3) / 1e9
+    traffic = counter_traffic(w.name, h_match, "separable", dom)
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_unit": bpp[dom],
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_note": "HBM bytes per launch, rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a copy kernel "
+                            "(profiles/hbm_traffic.json); null if the kernels changed since",
+            "algorithmic_bytes_per_launch": nb / max(launches, 1), "bytes_per_unit": bpp[dom],
             "units_per_launch": units[dom], "launches_per_step": launches,
             "avg_launch_ms": round(k_pc[dom] / max(launches, 1), 5)}
     hbm = {}
@@ -344,17 +382,20 @@ def main():
                            sigma_psf=w.sigma_psf, astig_gamma=w.astig_gamma, astig_d=w.astig_d, i_bg=w.i_bg,
                            sigma_xi=w.sigma_xi, proc_sigma=w.proc_sigma, seed=w.seed + 500)
         st = synth.initial_particles(w, tr[0], counts)
+        off = np.concatenate([[0], np.cumsum(counts)])
+        # frame 1, whole targets one after another until the time budget is used
         t1 = time.perf_counter()
-        kk = ps = 0
-        while time.perf_counter() - t1 < args.cpu_seconds and kk < w.K:
-            kk += 1
-            fr_k = frames_np[kk - 1:kk]
-            st = oracle.track(mdl, fr_k, counts, st, k0=kk)[0]
-            ps += NT
+        nt = ps = 0
+        while nt < T and (nt == 0 or time.perf_counter() - t1 < args.cpu_seconds):
+            a, b = off[nt], off[nt + 1]
+            fr_t = frames_np[0:1, nt:nt + 1] if w.per_target_frames else frames_np[0:1]
+            oracle.track(mdl, fr_t, counts[nt:nt + 1], st[:, a:b], k0=1, per_target=w.per_target_frames)
+            ps += int(b - a)
+            nt += 1
         el_cpu = time.perf_counter() - t1
         cpu = {"value": ps / el_cpu, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"exact pcSIR h={h_match}: {kk} frame(s) of the full workload ({NT} particles), "
-                         f"FP64, one thread"}
+               "sample": f"exact pcSIR h={h_match}, first frame, targets 0..{nt - 1} ({ps} particles, "
+                         f"{el_cpu:.1f} s), FP64, one thread"}
 
     out = {
         "metric": METRIC,
@@ -382,6 +423,7 @@ def main():
         "hbm_gbs_per_kernel": hbm,
         "kernel_ms_per_step": {k: {n: round(v, 5) for n, v in r["per"].items()} for k, r in runs.items()},
         "sir_likelihood": sir_lik,
+        "autotune": tuned or None,
         "surrogate": surr,
         "cpu_baseline": cpu,
         "input_generation_s": round(gen_s, 2),

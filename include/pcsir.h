@@ -203,6 +203,43 @@ pcsir_status pcsir_set_debug(pcsir_ctx *ctx, int32_t on);
 pcsir_status pcsir_set_timing(pcsir_ctx *ctx, int32_t on);
 pcsir_status pcsir_kernel_times(pcsir_ctx *ctx, const char **names, float *ms, int32_t cap, int32_t *count);
 
+/* Launch shapes of the pcSIR step. None of them changes any result: bins
+ * are the sorted distinct cell keys whatever the tile size, bin sums are exact
+ * integers, and no reduction depends on the grid. */
+typedef struct {
+  int32_t bin_tile;     /* particles per work item of the key deduplication and the bin
+                           sums: 1024, 2048 or 4096 (default 4096) */
+  int32_t list_blocks;  /* workgroups of the sort and segment passes over the list of
+                           distinct keys: 64 .. 2048 (default 1024) */
+  int32_t digit_bits;   /* widest digit of the radix sort, 6 .. 11 (default 11); the
+                           width actually used is the narrowest that keeps the fewest passes */
+  int32_t grid_per_cu;  /* workgroups per compute unit of the grid-stride kernels
+                           (likelihood, surrogate, dummies): 4 .. 64 (default 32) */
+} pcsir_tuning;
+
+/* Current launch shapes. */
+pcsir_status pcsir_get_tuning(const pcsir_ctx *ctx, pcsir_tuning *out);
+
+/* Set the launch shapes (validated; E_INVAL when out of range). Synchronises the
+ * context's stream and drops captured graphs, which are captured again on the
+ * next step. */
+pcsir_status pcsir_set_tuning(pcsir_ctx *ctx, const pcsir_tuning *tuning);
+
+/* Self-tuning of the launch shapes on the caller's data: a coordinate search,
+ * one field at a time in the order above, over bin_tile {1024, 2048, 4096},
+ * list_blocks {256, 512, 1024, 2048}, digit_bits {8, 9, 10, 11} and
+ * grid_per_cu {8, 16, 32, 64}, keeping the best setting of each field before
+ * moving to the next. A trial restores the particles, runs one untimed
+ * pcsir_step on `frame_dev` with frame index k (graph capture), restores them
+ * again and times `reps` steps with HIP events on the context's stream.
+ * state_scratch_dev: caller buffer of D * sum(N_t) floats that receives the
+ * current particles first; the particles are restored from it at the end
+ * (no step has then run: pcsir_estimate needs a new step). The best setting is
+ * applied to ctx and written to *best (may be NULL), its time per step in ms to
+ * *best_ms (may be NULL), the number of trials to *trials (may be NULL). */
+pcsir_status pcsir_autotune(pcsir_ctx *ctx, const float *frame_dev, int32_t H, int32_t W, int64_t k, int32_t reps,
+                            float *state_scratch_dev, pcsir_tuning *best, float *best_ms, int32_t *trials);
+
 #ifdef __cplusplus
 }
 #endif

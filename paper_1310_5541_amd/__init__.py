@@ -5,6 +5,6 @@ resample) runs entirely in ``libpcsir.so``. This package is argument
 marshalling only: torch supplies device memory and the stream.
 """
 from ._lib import (  # noqa: F401
-    DUMP, Config, Filter, LibraryMissing, MLPTrainer, PcsirError, SurrogateNet, gemm_bf16, lib, lib_path,
-    mlp_param_count,
+    DUMP, Config, Filter, LibraryMissing, MLPTrainer, PcsirError, SurrogateNet, Tuning, gemm_bf16, lib,
+    lib_path, mlp_param_count,
 )

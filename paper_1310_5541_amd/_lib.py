@@ -49,6 +49,15 @@ class _Cfg(C.Structure):
 _lib = None
 
 
+class Tuning(C.Structure):
+    """Python mirror of ``pcsir_tuning`` (launch shapes; results do not depend on them)."""
+    _fields_ = [("bin_tile", C.c_int32), ("list_blocks", C.c_int32), ("digit_bits", C.c_int32),
+                ("grid_per_cu", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 def lib_path() -> str:
     return _LIB
 
@@ -85,6 +94,10 @@ def lib():
     L.pcsir_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, i32, vp, sz, vp, vp, vp]
     L.pcsir_mlp_forward_train_path.argtypes = [vp, vp, i32, vp, vp, sz, vp]
     L.pcsir_mlp_gemm_bf16.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp]
+    L.pcsir_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.pcsir_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.pcsir_autotune.argtypes = [vp, vp, i32, i32, i64, i32, vp, C.POINTER(Tuning), C.POINTER(C.c_float),
+                                 C.POINTER(i32)]
     L.pcsir_surr_bytes.argtypes = []
     L.pcsir_surr_bytes.restype = sz
     L.pcsir_surr_prepare.argtypes = [vp, vp, vp, sz, vp]
@@ -93,7 +106,8 @@ def lib():
     L.pcsir_surrogate_features.argtypes = [vp, vp, vp, i32, C.POINTER(i32)]
     L.pcsir_surrogate_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_float), i32]
     for f in ("pcsir_mlp_train_step", "pcsir_mlp_forward_train_path", "pcsir_mlp_gemm_bf16", "pcsir_surr_prepare",
-              "pcsir_surr_rows", "pcsir_set_surrogate", "pcsir_surrogate_features", "pcsir_surrogate_stats"):
+              "pcsir_surr_rows", "pcsir_set_surrogate", "pcsir_surrogate_features", "pcsir_surrogate_stats",
+              "pcsir_get_tuning", "pcsir_set_tuning", "pcsir_autotune"):
         getattr(L, f).restype = i32
     for f in ("pcsir_init", "pcsir_step", "sir_step", "pcsir_estimate", "pcsir_destroy", "pcsir_get_particles",
               "pcsir_set_particles", "pcsir_debug_dump", "pcsir_set_debug", "pcsir_set_graphs", "pcsir_set_timing",
@@ -243,6 +257,27 @@ class Filter:
 
     def set_debug(self, on: bool = True):
         self._check(lib().pcsir_set_debug(self._ctx, 1 if on else 0))
+
+    # -- launch shapes
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(lib().pcsir_get_tuning(self._ctx, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{**self.get_tuning(), **kw})
+        self._check(lib().pcsir_set_tuning(self._ctx, C.byref(t)))
+
+    def autotune(self, frame, k: int, reps: int = 3):
+        """Search the launch shapes on `frame` (pcsir_autotune); returns (tuning, ms per step, trials).
+        The particles are left as they were."""
+        fp, H, W = self._frame(frame)
+        scratch = self._torch.empty((self.cfg.D, self.cfg.NT), dtype=self._torch.float32, device=self.device)
+        best, ms, n = Tuning(), C.c_float(0.0), C.c_int32(0)
+        self._check(lib().pcsir_autotune(self._ctx, fp, H, W, int(k), int(reps), _ptr(scratch), C.byref(best),
+                                         C.byref(ms), C.byref(n)))
+        self._hold = scratch
+        return best.as_dict(), float(ms.value), int(n.value)
 
     # -- learned surrogate (lik_mode 2 / 3)
     def set_surrogate(self, params, act_scale=None, check_fraction: float = 0.01, tol_nats: float = 1.0):

@@ -8,7 +8,7 @@
 namespace pcsir {
 
 constexpr int TPB = 256;            // threads per block of the streaming kernels
-constexpr int LIST_BLOCKS = 1024;   // workgroups of the sort / segment passes over the key list
+constexpr int LIST_BLOCKS_MAX = 2048;  // most workgroups of the sort / segment passes over the key list
 constexpr int SCAN_ITEMS = 4;       // particles per thread in the weight scan
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 constexpr int LIK_WAVES = 4;        // likelihood evaluations per block (one per wave)
@@ -203,7 +203,8 @@ __global__ __launch_bounds__(TPB) void k_bbox_reduce(int dim, const uint32_t *__
 // total range, and the radix digit width and number of sort passes it needs;
 // also resets the length of the frame's key list. One block.
 __global__ __launch_bounds__(TPB) void k_bbox_scan(int T, const unsigned long long *__restrict__ range,
-                                                   uint32_t *__restrict__ kbase, uint64_t *__restrict__ meta) {
+                                                   uint32_t *__restrict__ kbase, uint64_t *__restrict__ meta,
+                                                   int max_bits) {
   __shared__ unsigned long long lds[TPB / WAVE];
   unsigned long long carry = 0;
   for (int t0 = 0; t0 < T; t0 += TPB) {
@@ -224,8 +225,8 @@ __global__ __launch_bounds__(TPB) void k_bbox_scan(int T, const unsigned long lo
       meta[META_ERR] |= ERR_KEY_RANGE;
       bits = 32;
     }
-    // fewest passes of at most MAX_DIGIT_BITS bits, digits as narrow as that allows
-    const int passes = (bits + MAX_DIGIT_BITS - 1) / MAX_DIGIT_BITS;
+    // fewest passes of at most max_bits bits, digits as narrow as that allows
+    const int passes = (bits + max_bits - 1) / max_bits;
     const int width = passes ? (bits + passes - 1) / passes : 1;
     meta[META_PASSES] = (uint64_t)passes;
     meta[META_DIGIT] = (uint64_t)width;

@@ -73,6 +73,17 @@ bool valid_config(const pcsir_config *c, std::string *why) {
   return true;
 }
 
+constexpr int BIN_TILE_MIN = 1024, BIN_TILE_MAX = BIN_TILES * SCAN_TILE;
+constexpr int DIGIT_BITS_MIN = 6;
+
+void build_bin_tiles(const pcsir_config *c, uint32_t tile, std::vector<BinTile> &tB) {
+  tB.clear();
+  for (int t = 0; t < c->n_targets; ++t) {
+    const uint32_t n = (uint32_t)c->n_particles[t];
+    for (uint32_t i0 = 0; i0 < n; i0 += tile) tB.push_back(BinTile{t, i0, std::min<uint32_t>(n, i0 + tile)});
+  }
+}
+
 void build_tables(const pcsir_config *c, Tables &tb) {
   const int T = c->n_targets;
   tb.off.assign(T + 1, 0);
@@ -92,24 +103,27 @@ void build_tables(const pcsir_config *c, Tables &tb) {
       tb.tS.push_back(Tile{t, i0});
       tb.tile_last.push_back(i0 + SCAN_TILE >= n ? 1u : 0u);
     }
-    for (uint32_t i0 = 0; i0 < n; i0 += BIN_TILES * SCAN_TILE)
-      tb.tB.push_back(BinTile{t, i0, std::min<uint32_t>(n, i0 + BIN_TILES * SCAN_TILE)});
   }
+  build_bin_tiles(c, BIN_TILE_MAX, tb.tB);
   tb.tfirst[T] = (uint32_t)tb.tS.size();
   tb.t256_first[T] = (uint32_t)tb.t256.size();
 }
 
-constexpr int MAX_PASSES = (32 + MAX_DIGIT_BITS - 1) / MAX_DIGIT_BITS;
 
 Layout plan(const pcsir_config *c, const Tables &tb) {
   Layout L;
   const size_t NT = tb.off.back();
   const size_t T = c->n_targets;
   const size_t dim = c->dim, D = 2 * dim + 1;
-  L.G = (uint32_t)std::max<size_t>(1, std::min<size_t>(LIST_BLOCKS, (NT + TPB - 1) / TPB));
+  L.G = (uint32_t)std::max<size_t>(1, std::min<size_t>(LIST_BLOCKS_MAX, (NT + TPB - 1) / TPB));
   L.n256 = (uint32_t)tb.t256.size();
   L.nS = (uint32_t)tb.tS.size();
-  L.nB = (uint32_t)tb.tB.size();
+  {
+    // bin-tile table sized for the smallest tile the tuning allows
+    std::vector<BinTile> most;
+    build_bin_tiles(c, BIN_TILE_MIN, most);
+    L.nB = (uint32_t)most.size();
+  }
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -192,6 +206,8 @@ struct pcsir_ctx {
   float surr_fraction = 0.01f, surr_tol = 1.0f;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2][2][2] = {};
+  pcsir_tuning tune{BIN_TILE_MAX, 1024, MAX_DIGIT_BITS, 32};
+  uint32_t nB = 0;  // bin tiles of the current tile size
 
   template <typename T>
   T *at(size_t off) const {
@@ -265,7 +281,7 @@ WeightSrc weight_src(const pcsir_ctx *c) {
 
 uint32_t grid_stride_blocks(const pcsir_ctx *c, uint32_t work, uint32_t per_block) {
   const uint32_t need = (work + per_block - 1) / per_block;
-  const uint32_t cap = (uint32_t)c->num_cus * 32;
+  const uint32_t cap = (uint32_t)c->num_cus * (uint32_t)c->tune.grid_per_cu;
   return std::max(1u, std::min(need, cap));
 }
 
@@ -362,36 +378,39 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   k_bbox_reduce<<<p.T, TPB, 0, st>>>(p.dim, c->at<uint32_t>(L.t256_first), c->at<int32_t>(L.bbox_part),
                                      c->at<int32_t>(L.bbox_cur), c->at<unsigned long long>(L.range),
                                      c->at<int32_t>(L.tfb));
-  k_bbox_scan<<<1, TPB, 0, st>>>(p.T, c->at<unsigned long long>(L.range), c->at<uint32_t>(L.kbase), meta);
+  k_bbox_scan<<<1, TPB, 0, st>>>(p.T, c->at<unsigned long long>(L.range), c->at<uint32_t>(L.kbase), meta,
+                                 c->tune.digit_bits);
   mark(c, "keys");
-  k_keys<DIM><<<L.nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+  k_keys<DIM><<<c->nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                     c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.key), meta);
   SortBufs sb = sort_bufs(c);
   uint32_t *hist = c->at<uint32_t>(L.hist);
   uint32_t *dtot = c->at<uint32_t>(L.dtot);
-  for (int pass = 0; pass < MAX_PASSES; ++pass) {
+  const uint32_t G = std::min<uint32_t>(L.G, (uint32_t)c->tune.list_blocks);
+  const int max_passes = (32 + c->tune.digit_bits - 1) / c->tune.digit_bits;
+  for (int pass = 0; pass < max_passes; ++pass) {
     const uint32_t *kin = pass == 0 ? sb.key_store : ((pass & 1) ? sb.kB : sb.kA);
     uint32_t *kout = (uint32_t *)((pass & 1) ? sb.kA : sb.kB);
     mark(c, "sort_hist");
-    k_sort_hist<<<L.G, TPB, 0, st>>>(pass, kin, hist, L.G, meta);
+    k_sort_hist<<<G, TPB, 0, st>>>(pass, kin, hist, G, meta);
     mark(c, "sort_scan");
-    k_sort_scan<<<MAX_BUCKETS, TPB, 0, st>>>(pass, hist, L.G, dtot, meta);
+    k_sort_scan<<<MAX_BUCKETS, TPB, 0, st>>>(pass, hist, G, dtot, meta);
     mark(c, "sort_scatter");
-    k_sort_scatter<<<L.G, TPB, 0, st>>>(pass, kin, kout, hist, L.G, dtot, meta);
+    k_sort_scatter<<<G, TPB, 0, st>>>(pass, kin, kout, hist, G, dtot, meta);
   }
   uint32_t *chunk = c->at<uint32_t>(L.chunk_heads);
   unsigned long long *acc = c->at<unsigned long long>(L.acc);
   mark(c, "seg_count");
-  k_seg_count<<<L.G, TPB, 0, st>>>(L.G, sb, meta, chunk);
+  k_seg_count<<<G, TPB, 0, st>>>(G, sb, meta, chunk);
   mark(c, "seg_scan");
-  k_seg_scan<<<1, TPB, 0, st>>>(p.T, chunk, L.G, meta, c->at<uint32_t>(L.seg_first));
+  k_seg_scan<<<1, TPB, 0, st>>>(p.T, chunk, G, meta, c->at<uint32_t>(L.seg_first));
   mark(c, "seg_mark");
-  k_seg_mark<<<L.G, TPB, 0, st>>>(p, L.G, sb, meta, chunk, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
+  k_seg_mark<<<G, TPB, 0, st>>>(p, G, sb, meta, chunk, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                   c->at<int32_t>(L.seg_t));
   k_seg_first<<<(p.T + 1 + TPB - 1) / TPB, TPB, 0, st>>>(p.T, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                                          meta, c->at<uint32_t>(L.seg_first));
   mark(c, "bin_sums");
-  k_bin_sums<DIM><<<L.nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+  k_bin_sums<DIM><<<c->nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta);
   mark(c, "dummy");
@@ -623,6 +642,7 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   c->ws = (char *)workspace_dev;
   c->stream = (hipStream_t)hip_stream;
   c->NT = c->tb.off.back();
+  c->nB = (uint32_t)c->tb.tB.size();
   c->p = make_params(&c->cfg, c->NT);
   c->p.bbox_cur = c->at<int32_t>(c->L.bbox_cur);
   int dev = 0;
@@ -865,6 +885,99 @@ pcsir_status pcsir_kernel_times(pcsir_ctx *c, const char **names, float *ms, int
   *count = n;
   c->ev_used = 0;
   return PCSIR_OK;
+}
+
+pcsir_status pcsir_get_tuning(const pcsir_ctx *c, pcsir_tuning *out) {
+  if (!c || !out) return PCSIR_E_INVAL;
+  *out = c->tune;
+  return PCSIR_OK;
+}
+
+pcsir_status pcsir_set_tuning(pcsir_ctx *c, const pcsir_tuning *t) {
+  if (!c || !t) return PCSIR_E_INVAL;
+  if (t->bin_tile != 1024 && t->bin_tile != 2048 && t->bin_tile != BIN_TILE_MAX)
+    return fail(c, PCSIR_E_INVAL, "bin_tile must be 1024, 2048 or 4096");
+  if (t->list_blocks < 64 || t->list_blocks > LIST_BLOCKS_MAX)
+    return fail(c, PCSIR_E_INVAL, "list_blocks must lie in [64, 2048]");
+  if (t->digit_bits < DIGIT_BITS_MIN || t->digit_bits > MAX_DIGIT_BITS)
+    return fail(c, PCSIR_E_INVAL, "digit_bits must lie in [6, 11]");
+  if (t->grid_per_cu < 4 || t->grid_per_cu > 64) return fail(c, PCSIR_E_INVAL, "grid_per_cu must lie in [4, 64]");
+  drop_graphs(c);  // captured graphs hold the launch shapes
+  if (t->bin_tile != c->tune.bin_tile) {
+    std::vector<BinTile> tB;
+    build_bin_tiles(&c->cfg, (uint32_t)t->bin_tile, tB);
+    hipError_t e = hipMemcpyAsync(c->ws + c->L.tilesB, tB.data(), sizeof(BinTile) * tB.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return check_hip(c, e, "pcsir_set_tuning");
+    c->nB = (uint32_t)tB.size();
+  }
+  c->tune = *t;
+  return PCSIR_OK;
+}
+
+pcsir_status pcsir_autotune(pcsir_ctx *c, const float *frame_dev, int32_t H, int32_t W, int64_t k, int32_t reps,
+                            float *state_scratch_dev, pcsir_tuning *best_out, float *best_ms_out,
+                            int32_t *trials_out) {
+  if (!c) return PCSIR_E_INVAL;
+  if (!frame_dev || !state_scratch_dev) return fail(c, PCSIR_E_INVAL, "frame_dev and state_scratch_dev are required");
+  if (reps < 1) return fail(c, PCSIR_E_INVAL, "reps must be >= 1");
+  if (k < 1) return fail(c, PCSIR_E_INVAL, "frame index k must be >= 1");
+  pcsir_status s = pcsir_get_particles(c, state_scratch_dev);
+  if (s != PCSIR_OK) return s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return check_hip(c, e, "pcsir_autotune");
+  int trials = 0;
+  auto trial = [&](const pcsir_tuning &t, float *ms) -> pcsir_status {
+    pcsir_status r = pcsir_set_tuning(c, &t);
+    if (r == PCSIR_OK) r = pcsir_set_particles(c, state_scratch_dev);
+    if (r == PCSIR_OK) r = run_step(c, frame_dev, H, W, k, false);  // untimed: graph capture
+    if (r == PCSIR_OK) r = pcsir_set_particles(c, state_scratch_dev);
+    if (r != PCSIR_OK) return r;
+    hipError_t he = hipEventRecord(e0, c->stream);
+    for (int i = 0; i < reps && r == PCSIR_OK; ++i) r = run_step(c, frame_dev, H, W, k + i, false);
+    if (he == hipSuccess) he = hipEventRecord(e1, c->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(ms, e0, e1);
+    if (r != PCSIR_OK) return r;
+    if (he != hipSuccess) return check_hip(c, he, "pcsir_autotune");
+    *ms /= (float)reps;
+    ++trials;
+    return pull_device_status(c);
+  };
+  pcsir_tuning best = c->tune;
+  float best_ms = 0.0f;
+  s = trial(best, &best_ms);
+  const int tiles[] = {1024, 2048, BIN_TILE_MAX}, blocks[] = {256, 512, 1024, 2048}, bits[] = {8, 9, 10, 11},
+            grids[] = {8, 16, 32, 64};
+  const int *cands[4] = {tiles, blocks, bits, grids};
+  const int ncand[4] = {3, 4, 4, 4};
+  for (int f = 0; f < 4 && s == PCSIR_OK; ++f) {
+    for (int i = 0; i < ncand[f] && s == PCSIR_OK; ++i) {
+      pcsir_tuning t = best;
+      int32_t *field = f == 0 ? &t.bin_tile : f == 1 ? &t.list_blocks : f == 2 ? &t.digit_bits : &t.grid_per_cu;
+      if (*field == cands[f][i]) continue;
+      *field = cands[f][i];
+      float ms = 0.0f;
+      s = trial(t, &ms);
+      if (s == PCSIR_OK && ms < best_ms) {
+        best = t;
+        best_ms = ms;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != PCSIR_OK) return s;
+  s = pcsir_set_tuning(c, &best);
+  if (s == PCSIR_OK) s = pcsir_set_particles(c, state_scratch_dev);
+  if (s != PCSIR_OK) return s;
+  if (best_out) *best_out = best;
+  if (best_ms_out) *best_ms_out = best_ms;
+  if (trials_out) *trials_out = trials;
+  return check_hip(c, hipStreamSynchronize(c->stream), "pcsir_autotune");
 }
 
 size_t pcsir_surr_bytes(void) { return SURR_BYTES; }

@@ -88,7 +88,7 @@ def preset(name: str, **kw) -> Workload:
         "train-2d-512": Workload(name="train-2d-512", H=512, W=512, K=60, T=250, n_rule="loguniform", n_lo=3.0,
                                  n_hi=4.0, m=(2, 2, 1), patch=15, quad=8, i0=(20.0, 100.0), speed=(2.0, 4.0),
                                  mid_lo=50.0, mid_hi=462.0, seed=7000),
-        "train-3d": Workload(name="train-3d", dim=3, H=256, W=256, K=20, T=100, n=(5_000,), m=(4, 4, 4), patch=15,
+        "train-3d": Workload(name="train-3d", dim=3, H=256, W=256, K=20, T=40, n=(50_000,), m=(4, 4, 4), patch=15,
                              quad=8, i0=(20.0, 100.0), speed=(2.0, 4.0),
                              proc_sigma=(0.5, 0.5, 0.5, 0.1, 0.1, 0.1, 2.0), per_target_frames=True, seed=8000),
         "3d-astig": Workload(name="3d-astig", dim=3, H=256, W=256, K=20, T=200, n=(50_000,), m=(4, 4, 4),

@@ -325,3 +325,53 @@ def test_cell_index_at_adversarial_positions(m):
     np.testing.assert_array_equal(prop[0], x + np.float32(0.0))
     np.testing.assert_array_equal(keys[0], oracle.bin_key(prop[0], m))
     np.testing.assert_array_equal(keys[1], oracle.bin_key(prop[1], m))
+
+
+def test_launch_shapes_do_not_change_results_and_autotune_restores_particles():
+    """Every pcsir_tuning setting gives bit-identical steps (bins are the sorted
+    distinct keys, sums are exact integers, no reduction depends on the grid);
+    the autotuner returns a valid setting and leaves the particles as they were."""
+    import torch
+
+    from paper_1310_5541_amd import Filter
+    counts = (1, 255, 2049, 5000, 9000)
+    w = synth.preset("tiny", H=128, W=128, T=len(counts), n=counts, m=(4, 4, 1), K=4, i0=(20.0, 100.0),
+                     speed=(0.5, 1.0), patch=15, quad=4)
+    tr = synth.truth(w, seed=12)
+    mids = _separated_mids(len(counts), 15.0, 113.0, 25.0, 12)
+    tr[:, :, :2] += (mids - tr[1, :, :2])[None]
+    fr = torch.from_numpy(synth.frames(w, tr, seed=12)).cuda()
+    cloud = torch.from_numpy(_clouds(w, counts, [tr[1, t] for t in range(len(counts))], 1.2, 5)).cuda()
+    cfg = _cfg(w, seed=13, lik_mode=1)
+    shapes = [None, dict(bin_tile=1024, list_blocks=64, digit_bits=6, grid_per_cu=4),
+              dict(bin_tile=2048, list_blocks=512, digit_bits=8, grid_per_cu=16)]
+    outs = []
+    for sh in shapes:
+        log(f"case launch_shapes {sh}")
+        f = Filter(cfg, cloud)
+        f.set_debug(True)
+        if sh:
+            f.set_tuning(**sh)
+            assert f.get_tuning() == sh
+        for k in range(1, 4):
+            f.pcsir_step(fr[k], k)
+        outs.append({n: f.dump(n).cpu().numpy() for n in ("loglik", "weights", "resample", "bin_key", "bin_n")}
+                    | {"after": f.get_particles().cpu().numpy(), "passes": int(f.dump("counts")[1].item())})
+        f.close()
+    for o in outs[1:]:
+        for n in ("loglik", "weights", "resample", "bin_key", "bin_n", "after"):
+            assert np.array_equal(o[n], outs[0][n]), n
+    log(f"  sort passes per shape: {[o['passes'] for o in outs]}")
+    # autotune
+    f = Filter(cfg, cloud)
+    f.pcsir_step(fr[1], 1)
+    before = f.get_particles().cpu().numpy()
+    best, ms, n = f.autotune(fr[2], 2, reps=2)
+    log(f"  autotune: {best}, {ms:.4f} ms/step, {n} trials")
+    assert n >= 12 and ms > 0
+    assert best["bin_tile"] in (1024, 2048, 4096) and 8 <= best["digit_bits"] <= 11
+    assert f.get_tuning() == best
+    assert np.array_equal(f.get_particles().cpu().numpy(), before)
+    f.pcsir_step(fr[2], 2)
+    f.estimate()
+    f.close()
