@@ -58,11 +58,12 @@ __device__ __forceinline__ void normals8(uint64_t seed, uint64_t i, uint64_t k, 
   for (int p = 0; p < 4; ++p) {
     const float u1 = u01_hi(b.v[p]);
     const float u2 = u01_lo(b.v[p]);
-    const float r = sqrtf(-2.0f * logf(u1));
-    float s, c;
-    sincospif(2.0f * u2, &s, &c);
-    z[2 * p] = r * c;
-    z[2 * p + 1] = r * s;
+    // hardware log2, and sine / cosine of 2 pi u2 (the instructions take the
+    // angle in turns); about one ulp each, far inside the tolerance of the
+    // propagated states
+    const float r = sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u1));
+    z[2 * p] = r * __builtin_amdgcn_cosf(u2);
+    z[2 * p + 1] = r * __builtin_amdgcn_sinf(u2);
   }
 }
 

@@ -257,9 +257,12 @@ __device__ __forceinline__ uint32_t particle_key(const float *__restrict__ s, ui
 
 // Distinct cell keys of one bin-sum tile (at most BIN_TILES * SCAN_TILE
 // particles of one target), found with an open-addressing hash set in LDS of
-// twice that many slots (so it never fills), appended to the frame's key list.
-// The list holds every occupied cell at least once; its order depends on the
-// order in which workgroups append, which the sort that follows removes.
+// twice that many slots (so it never fills). A tile has at most as many
+// distinct keys as particles, so it writes them into its own particle range
+// of `sparse` (global index of its first particle on), and its count to
+// tcount[tile]; k_list_offsets and k_list_compact then pack the tiles' keys
+// into one list, in tile order, without atomics. The list holds every
+// occupied cell at least once.
 constexpr int DEDUP_SLOTS = 2 * BIN_TILES * SCAN_TILE;
 constexpr int DEDUP_SHIFT = 32 - 13;
 static_assert(DEDUP_SLOTS == 1 << 13, "hash slots");
@@ -269,12 +272,11 @@ template <int DIM>
 __global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restrict__ tiles,
                                               const uint32_t *__restrict__ off, const float *__restrict__ s,
                                               const int32_t *__restrict__ bbox_cur, const uint32_t *__restrict__ kbase,
-                                              uint32_t *__restrict__ list, uint64_t *__restrict__ meta) {
-  constexpr int R = 4;
+                                              uint32_t *__restrict__ sparse, uint32_t *__restrict__ tcount) {
+  constexpr int R = BIN_TILES * SCAN_TILE / TPB;  // all of a thread's positions are loaded before use
   constexpr int PER = DEDUP_SLOTS / TPB;
   __shared__ uint32_t tab[DEDUP_SLOTS];
   __shared__ uint32_t lds[TPB / WAVE];
-  __shared__ uint32_t sbase;
   const BinTile tl = tiles[blockIdx.x];
   const int t = tl.t;
   const uint32_t base = off[t];
@@ -285,11 +287,14 @@ __global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restric
   for (int i = threadIdx.x; i < DEDUP_SLOTS; i += TPB) tab[i] = KEY_EMPTY;
   __syncthreads();
   for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * TPB) {
+    // loads from clamped indices, issued together, then masked (a load under a
+    // bounds branch would be waited for before the next one is issued)
     uint32_t kk[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const uint32_t i = r0 + q * TPB + threadIdx.x;
-      kk[q] = i < tl.i1 ? particle_key<DIM>(s, p.NT, base + i, p.m, bb, kb) : KEY_EMPTY;
+      const uint32_t k = particle_key<DIM>(s, p.NT, base + min(i, tl.i1 - 1), p.m, bb, kb);
+      kk[q] = i < tl.i1 ? k : KEY_EMPTY;
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -312,15 +317,42 @@ __global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restric
 #pragma unroll
   for (int j = 0; j < PER; ++j) c += tab[threadIdx.x * PER + j] != KEY_EMPTY ? 1u : 0u;
   uint32_t tot;
-  uint32_t o = block_excl_scan<TPB, uint32_t>(c, lds, &tot);
-  if (threadIdx.x == 0) sbase = (uint32_t)atomicAdd((unsigned long long *)&meta[META_L], (unsigned long long)tot);
-  __syncthreads();
-  o += sbase;
+  uint32_t o = base + tl.i0 + block_excl_scan<TPB, uint32_t>(c, lds, &tot);
+  if (threadIdx.x == 0) tcount[blockIdx.x] = tot;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const uint32_t v = tab[threadIdx.x * PER + j];
-    if (v != KEY_EMPTY) list[o++] = v;
+    if (v != KEY_EMPTY) sparse[o++] = v;
   }
+}
+
+// Exclusive scan of the tiles' key counts (one block); meta[META_L] = total.
+__global__ __launch_bounds__(TPB) void k_list_offsets(uint32_t ntiles, uint32_t *__restrict__ tcount,
+                                                      uint64_t *__restrict__ meta) {
+  __shared__ uint32_t lds[TPB / WAVE];
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < ntiles; b0 += TPB) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t v = b < ntiles ? tcount[b] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<TPB, uint32_t>(v, lds, &tot);
+    if (b < ntiles) tcount[b] = carry + ex;  // becomes the tile's offset in the list
+    carry += tot;
+  }
+  if (threadIdx.x == 0) meta[META_L] = carry;
+}
+
+// Pack each tile's keys to its offset in the list (one block per tile).
+__global__ __launch_bounds__(TPB) void k_list_compact(const BinTile *__restrict__ tiles,
+                                                      const uint32_t *__restrict__ off,
+                                                      const uint32_t *__restrict__ toff, uint32_t ntiles,
+                                                      const uint64_t *__restrict__ meta,
+                                                      const uint32_t *__restrict__ sparse, uint32_t *__restrict__ list) {
+  const BinTile tl = tiles[blockIdx.x];
+  const uint32_t src = off[tl.t] + tl.i0;
+  const uint32_t o = toff[blockIdx.x];
+  const uint32_t end = blockIdx.x + 1 < ntiles ? toff[blockIdx.x + 1] : (uint32_t)meta[META_L];
+  for (uint32_t i = threadIdx.x; i < end - o; i += TPB) list[o + i] = sparse[src + i];
 }
 
 // Contiguous share of a device-sized list for block b of G.
@@ -622,7 +654,7 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
   constexpr int D = 2 * DIM + 1;
   constexpr int NC = BinLds<DIM>::NC;
   constexpr int BINS = BinLds<DIM>::BINS;
-  constexpr int R = 4;  // particles per thread per round, loaded together
+  constexpr int R = 8;  // particles per thread per round, loaded together
   __shared__ uint32_t bkey[BINS];
   __shared__ unsigned long long bacc[NC][BINS];
   const uint32_t NT = p.NT;
@@ -654,11 +686,9 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
       float x[R][D];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const uint32_t i = r0 + q * TPB + threadIdx.x;
-        if (i < tl.i1) {
+        const uint32_t i = min(r0 + q * TPB + threadIdx.x, tl.i1 - 1);  // clamped: unconditional loads
 #pragma unroll
-          for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + base + i];
-        }
+        for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + base + i];
       }
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -986,8 +1016,19 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
         }
       }
     }
+    // window pixels of the first ZPRE rounds loaded up front (clamped
+    // coordinates, unconditional loads, masked afterwards)
+    constexpr int ZPRE = 4;
+    float zpre[ZPRE];
+#pragma unroll
+    for (int it = 0; it < ZPRE; ++it) {
+      const int pix = it * WAVE + lane;
+      const int c = c0 + pix % P - R, r = r0 + pix / P - R;
+      const float v = fr[(size_t)min(max(r, 0), p.H - 1) * p.W + min(max(c, 0), p.W - 1)];
+      zpre[it] = (pix < P2 && c >= 0 && c < p.W && r >= 0 && r < p.H) ? v - p.i_bg : 0.0f;
+    }
     float ssd = 0.0f, err = 0.0f;
-    for (int pix0 = 0; pix0 < P2; pix0 += WAVE) {
+    for (int pix0 = 0, it = 0; pix0 < P2; pix0 += WAVE, ++it) {
       const int pix = pix0 + lane;
       const int pc = pix % P, pr = pix / P;
       float g = 0.0f;
@@ -1019,7 +1060,13 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       if (pix < P2) {
         const int c = c0 + pc - R, r = r0 + pr - R;
         float zb = 0.0f;
-        if (c >= 0 && c < p.W && r >= 0 && r < p.H) zb = fr[(size_t)r * p.W + c] - p.i_bg;
+        if (it < ZPRE) {
+#pragma unroll
+          for (int u = 0; u < ZPRE; ++u)
+            if (u == it) zb = zpre[u];
+        } else if (c >= 0 && c < p.W && r >= 0 && r < p.H) {
+          zb = fr[(size_t)r * p.W + c] - p.i_bg;
+        }
         // residual d = zb - Iq g and its square as FP32 (hi, lo) pairs: a residual
         // of ~100 (a spot the model lacks) would otherwise lose 1e-5 of l per particle
         const float mg = Iq * g;
@@ -1218,10 +1265,15 @@ __global__ __launch_bounds__(TPB) void k_cdf_sum(const Tile *__restrict__ tiles,
   const Tile tl = tiles[blockIdx.x];
   const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
   double acc = 0.0;
+  double w[SCAN_ITEMS];
+#pragma unroll
   for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t i = tl.i0 + it * TPB + threadIdx.x;  // coalesced
-    if (i < n) acc += particle_weight<SIR>(ws, tl.t, base + i);
+    const uint32_t i = tl.i0 + it * TPB + threadIdx.x;  // coalesced; clamped, unconditional loads
+    w[it] = particle_weight<SIR>(ws, tl.t, base + min(i, n - 1));
   }
+#pragma unroll
+  for (int it = 0; it < SCAN_ITEMS; ++it)
+    if (tl.i0 + it * TPB + threadIdx.x < n) acc += w[it];
   const double tot = block_sum<TPB, double>(acc, lds);
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
 }
@@ -1271,9 +1323,10 @@ __device__ __forceinline__ uint32_t count_below(double c, double u, uint32_t n) 
 // (block scan), with every boundary taken from one source (the next thread's
 // or tile's start, made non-decreasing), so consecutive tiles partition the
 // new particles. The tile's new particles [count(tile start), count(tile end))
-// are then dealt to the threads in interleaved order (coalesced writes, and
-// no thread serialises the many offspring of a heavy particle); each finds its
-// parent by binary search over the tile's cumulative weights in LDS.
+// are then split into equal contiguous ranges, one per thread (no thread
+// serialises the many offspring of a heavy particle); the thread finds the
+// parent of its first new particle by galloping search over the tile's
+// cumulative weights in LDS, then of each next one from the previous parent.
 // Weights are loaded coalesced into LDS first, then each thread takes its
 // SCAN_ITEMS consecutive ones; the LDS array has one pad slot per
 // SCAN_ITEMS entries so that those strided reads do not collide in banks.
@@ -1293,11 +1346,16 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
   const uint32_t base = off[t], n = off[t + 1] - base;
   const uint32_t m = min((uint32_t)SCAN_TILE, n - tl.i0);  // particles in this tile
   const double u = ws.tgt[t * 4 + 3];
+  {
+    double wl[SCAN_ITEMS];
 #pragma unroll
-  for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t li = it * TPB + threadIdx.x;
-    const uint32_t i = tl.i0 + li;
-    cl[cpad(li)] = i < n ? particle_weight<SIR>(ws, t, base + i) : 0.0;
+    for (int it = 0; it < SCAN_ITEMS; ++it)
+      wl[it] = particle_weight<SIR>(ws, t, base + min(tl.i0 + it * TPB + threadIdx.x, n - 1));
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+      const uint32_t li = it * TPB + threadIdx.x;
+      cl[cpad(li)] = tl.i0 + li < n ? wl[it] : 0.0;
+    }
   }
   __syncthreads();
   double w[SCAN_ITEMS];
@@ -1358,7 +1416,9 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
   const uint32_t jhi = last_tile ? n : count_below(tile_end, u, n);
   const double dn = (double)n;
   uint32_t prev = 0;  // parents are non-decreasing in j: search forward from the last one
-  for (uint32_t j = jlo + threadIdx.x; j < jhi; j += TPB) {
+  const uint32_t per = (jhi - jlo + TPB - 1) / TPB;
+  const uint32_t ja = jlo + min(jhi - jlo, threadIdx.x * per), jb = min(jhi, ja + per);
+  for (uint32_t j = ja; j < jb; ++j) {
     const double theta = ((double)j + u) / dn;
     // smallest l >= prev with cl[l] > theta (cl[m-1] > theta for every j < jhi)
     uint32_t lo = prev, step = 1, hi = prev;

@@ -24,7 +24,7 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
-      ll, wbin, desc, dvel, surr, tfb, tmax, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
+      ll, wbin, desc, dvel, surr, tfb, tmax, tcount, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
@@ -169,6 +169,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.tiles256 = take(sizeof(Tile) * (size_t)L.n256);
   L.tilesS = take(sizeof(Tile) * (size_t)L.nS);
   L.tilesB = take(sizeof(BinTile) * (size_t)L.nB);
+  L.tcount = take(4 * (size_t)L.nB);
   L.tile_last = take(4 * (size_t)L.nS);
   L.tfirst = take(4 * (T + 1));
   L.t256_first = take(4 * (T + 1));
@@ -381,8 +382,12 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   k_bbox_scan<<<1, TPB, 0, st>>>(p.T, c->at<unsigned long long>(L.range), c->at<uint32_t>(L.kbase), meta,
                                  c->tune.digit_bits);
   mark(c, "keys");
+  // distinct keys per tile into the tile's own range of kA, then packed into key (the sort's input)
   k_keys<DIM><<<c->nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
-                                    c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.key), meta);
+                                    c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.kA), c->at<uint32_t>(L.tcount));
+  k_list_offsets<<<1, TPB, 0, st>>>(c->nB, c->at<uint32_t>(L.tcount), meta);
+  k_list_compact<<<c->nB, TPB, 0, st>>>(c->at<BinTile>(L.tilesB), off, c->at<uint32_t>(L.tcount), c->nB, meta,
+                                        c->at<uint32_t>(L.kA), c->at<uint32_t>(L.key));
   SortBufs sb = sort_bufs(c);
   uint32_t *hist = c->at<uint32_t>(L.hist);
   uint32_t *dtot = c->at<uint32_t>(L.dtot);
