@@ -93,10 +93,13 @@ pcsir_status pcsir_surr_rows(const void *surr_dev, const uint16_t *X_dev, int32_
  * PCSIR_LIK_SURR_FP8 (required before its first pcsir_step; may be called
  * again to replace the weights). Per frame, each dummy is checked against its
  * exact log-likelihood with probability check_fraction (a counter-based
- * uniform of (dummy index, frame, target)); a target with any checked dummy
- * off by more than tol_nats has all its dummies evaluated exactly in that
- * frame. Checked dummies keep their exact value. act_scale_host as in
- * pcsir_surr_prepare, required for FP8. Synchronises the filter's stream. */
+ * uniform of (dummy index, frame, target)). A checked dummy is relevant when
+ * its exact or surrogate value lies within 40 nats of its target's largest
+ * surrogate value (below that its weight is under e^-40 of the best one's); a
+ * target whose relevant checked dummies have a root-mean-square error above
+ * tol_nats has all its dummies evaluated exactly in that frame. Checked
+ * dummies keep their exact value. act_scale_host as in pcsir_surr_prepare,
+ * required for FP8. Synchronises the filter's stream. */
 pcsir_status pcsir_set_surrogate(pcsir_ctx *ctx, const float *params_dev, const float *act_scale_host,
                                  float check_fraction, float tol_nats);
 

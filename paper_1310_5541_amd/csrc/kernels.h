@@ -870,7 +870,11 @@ struct SurrCheck {
   const uint32_t *list;      // dummies to evaluate (CHECK / FALLBACK)
   const unsigned long long *tmax;  // [T] largest surrogate l of each target (ordered bits)
   float *err;                // CHECK: |l_surrogate - l_exact| of list entry i
+  unsigned long long *tsse;  // [T] squared errors of relevant checked dummies, fixed point 2^16
+  unsigned int *tcnt;        // [T] number of relevant checked dummies
 };
+constexpr double SSE_FX = 65536.0;      // fixed-point scale of the squared errors (nats^2)
+constexpr double SSE_CLAMP = 1.0e9;     // a squared error counts at most this much
 // A checked dummy counts only when its exact or surrogate log-likelihood is
 // within this many nats of its target's largest surrogate value: below, its
 // weight relative to the target's best dummy is under e^-40 whatever the error.
@@ -930,6 +934,20 @@ __global__ __launch_bounds__(TPB) void k_surr_stats(const float *__restrict__ er
   }
 }
 
+// Per-target decision after the check: fall back when the mean squared
+// error of the target's relevant checked dummies exceeds tol^2; the sums are
+// cleared for the next frame.
+__global__ __launch_bounds__(TPB) void k_surr_decide(int T, float tol, unsigned long long *__restrict__ tsse,
+                                                     unsigned int *__restrict__ tcnt, int32_t *__restrict__ tfallback) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= T) return;
+  const unsigned int n = tcnt[t];
+  const double mse = n ? (double)tsse[t] / SSE_FX / (double)n : 0.0;
+  tfallback[t] = n && !(mse <= (double)tol * (double)tol) ? 1 : 0;
+  tsse[t] = 0ull;
+  tcnt[t] = 0u;
+}
+
 // Dummies of the targets whose check failed.
 __global__ __launch_bounds__(TPB) void k_surr_fallback_list(const uint64_t *__restrict__ meta,
                                                             const int32_t *__restrict__ seg_t,
@@ -946,7 +964,8 @@ __global__ __launch_bounds__(TPB) void k_surr_fallback_list(const uint64_t *__re
 template <int DIM, bool SIR, bool SEP, int Q, int MODE = LIK_ALL>
 __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64_t *__restrict__ meta,
                                              const StepDesc *__restrict__ desc, double *__restrict__ ll,
-                                             SurrCheck chk = SurrCheck{0.0f, 0.0f, nullptr, nullptr, nullptr, nullptr},
+                                             SurrCheck chk = SurrCheck{0.0f, 0.0f, nullptr, nullptr, nullptr, nullptr,
+                                                                       nullptr, nullptr},
                                              uint64_t *__restrict__ stats = nullptr) {
   const float *__restrict__ frame = desc->frame;
   const uint32_t E = SIR ? p.NT
@@ -1092,7 +1111,12 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       const float d = (float)fabs(lx - ls);
       const double top = from_ordered_bits(chk.tmax[t]);
       const bool relevant = fmax(lx, ls) >= top - SURR_RELEVANT_NATS || !(top == top);
-      if (relevant && !(d <= chk.tol)) chk.tfallback[t] = 1;  // every writer stores 1
+      if (relevant) {
+        // integer sums: the per-target decision does not depend on the order of the atomics
+        const double d2 = d == d ? fmin((double)d * (double)d, SSE_CLAMP) : SSE_CLAMP;
+        atomicAdd(&chk.tsse[t], (unsigned long long)(d2 * SSE_FX));
+        atomicAdd(&chk.tcnt[t], 1u);
+      }
       chk.err[idx] = d != d ? INFINITY : d;
     }
     if (lane == 0) ll[e] = lx;

@@ -24,7 +24,7 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
-      ll, wbin, desc, dvel, surr, tfb, tmax, tcount, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
+      ll, wbin, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
@@ -153,6 +153,8 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.surr = c->lik_mode >= PCSIR_LIK_SURR_BF16 ? take(SURR_BYTES) : 0;  // surrogate weights
   L.tfb = take(4 * T);
   L.tmax = take(8 * T);
+  L.tsse = take(8 * T);
+  L.tcnt = take(4 * T);
   L.seg_first = take(4 * (T + 1));
   L.bbox_part = take(4 * 6 * (size_t)L.n256);
   L.range = take(8 * T);
@@ -341,6 +343,8 @@ void launch_surrogate(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   chk.list = list_chk;
   chk.tmax = tmax;
   chk.err = (float *)c->at<double>(L.wbin);  // bin weights are formed after the check
+  chk.tsse = c->at<unsigned long long>(L.tsse);
+  chk.tcnt = c->at<unsigned int>(L.tcnt);
   const uint32_t lg = grid_stride_blocks(c, c->p.NT, LIK_WAVES);
   const Params &p = c->p;
   mark(c, "surr_check");
@@ -350,6 +354,7 @@ void launch_surrogate(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   else
     k_lik<DIM, false, false, 0, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
   k_surr_stats<<<1, TPB, 0, st>>>(chk.err, meta_w);
+  k_surr_decide<<<(p.T + TPB - 1) / TPB, TPB, 0, st>>>(p.T, chk.tol, chk.tsse, chk.tcnt, tfb);
   mark(c, "surr_fallback");
   k_surr_fallback_list<<<pg, TPB, 0, st>>>(meta, in.seg_t, tfb, list_fb, meta_w + META_NFB);
   chk.list = list_fb;
@@ -672,6 +677,8 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   h2d(L.t256_first, c->tb.t256_first.data(), 4 * c->tb.t256_first.size());
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.meta, 0, 8 * META_N, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tflag, 0, 4 * (size_t)T, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tsse, 0, 8 * (size_t)T, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tcnt, 0, 4 * (size_t)T, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.acc, 0, 8 * (size_t)(1 + D) * c->NT, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->state(0), init_state_dev, 4 * (size_t)D * c->NT, hipMemcpyDeviceToDevice, c->stream);

@@ -13,9 +13,10 @@
 * The surrogate inside the step: with no exact check, l = 100 f - A(z) of the
   fused kernel; with every dummy checked and tolerance 0, every target falls
   back and the step has full oracle parity; with a small check fraction, the
-  checked set follows the counter-based draw exactly, and a target falls back
-  when one of its checked dummies is relevant (within 40 nats of the target's
-  largest surrogate value).
+  checked set follows the counter-based draw exactly, and with tolerance 0 a
+  target falls back when one of its checked dummies is relevant (within 40
+  nats of the target's largest surrogate value): the root-mean-square error of
+  its relevant checked dummies is then above 0.
 """
 import math
 
