@@ -287,14 +287,22 @@ __global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restric
   for (int i = threadIdx.x; i < DEDUP_SLOTS; i += TPB) tab[i] = KEY_EMPTY;
   __syncthreads();
   for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * TPB) {
-    // loads from clamped indices, issued together, then masked (a load under a
-    // bounds branch would be waited for before the next one is issued)
+    // all positions loaded first, from clamped indices (a load under a bounds
+    // branch would be waited for before the next one is issued), then keyed
+    float xs[DIM][R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const uint32_t g = base + min(r0 + q * TPB + threadIdx.x, tl.i1 - 1);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) xs[a][q] = s[(size_t)a * p.NT + g];
+    }
     uint32_t kk[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const uint32_t i = r0 + q * TPB + threadIdx.x;
-      const uint32_t k = particle_key<DIM>(s, p.NT, base + min(i, tl.i1 - 1), p.m, bb, kb);
-      kk[q] = i < tl.i1 ? k : KEY_EMPTY;
+      int32_t c[3];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) c[a] = cell_index(xs[a][q], p.m[a]);
+      kk[q] = r0 + q * TPB + threadIdx.x < tl.i1 ? compact_key<DIM>(c, bb, kb) : KEY_EMPTY;
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -583,7 +591,9 @@ __device__ __forceinline__ int key_target(uint32_t key, int T, const uint32_t *_
 __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs sb, const uint64_t *__restrict__ meta,
                                                   const uint32_t *__restrict__ chunk_base,
                                                   const uint32_t *__restrict__ kbase, uint32_t *__restrict__ seg_key,
-                                                  int32_t *__restrict__ seg_t) {
+                                                  int32_t *__restrict__ seg_t, uint32_t *__restrict__ lut,
+                                                  uint64_t lut_cap) {
+  const bool use_lut = meta[META_RANGE] <= lut_cap;
   __shared__ uint32_t lds[TPB / WAVE];
   const uint32_t *K = sorted_keys(sb, meta[META_PASSES]);
   uint32_t j0, j1;
@@ -598,6 +608,7 @@ __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs
       const uint32_t kj = K[j];
       seg_key[heads + ex] = kj;
       seg_t[heads + ex] = key_target(kj, p.T, kbase);
+      if (use_lut) lut[kj] = heads + ex;  // bin of every occupied cell key
     }
     heads += tot;
   }
@@ -650,9 +661,13 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
                                                   const uint32_t *__restrict__ seg_key,
                                                   const uint32_t *__restrict__ seg_first,
                                                   unsigned long long *__restrict__ acc, uint32_t *__restrict__ segid,
-                                                  uint64_t *__restrict__ meta) {
+                                                  uint64_t *__restrict__ meta, const uint32_t *__restrict__ lut,
+                                                  uint64_t lut_cap) {
   constexpr int D = 2 * DIM + 1;
   constexpr int NC = BinLds<DIM>::NC;
+  // with the cell -> bin table of this frame (total key range within its
+  // capacity) a particle's bin is one load; otherwise a binary search
+  const bool use_lut = meta[META_RANGE] <= lut_cap;
   constexpr int BINS = BinLds<DIM>::BINS;
   constexpr int R = 8;  // particles per thread per round, loaded together
   __shared__ uint32_t bkey[BINS];
@@ -699,17 +714,25 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
 #pragma unroll
         for (int a = 0; a < DIM; ++a) cc[a] = cell_index(x[q][a], p.m[a]);
         const uint32_t k = compact_key<DIM>(cc, bb, kb);
-        if (k < klo || k > khi) {
+        uint32_t lo;
+        if (use_lut) {
+          lo = lut[k] - (s0 + c0);  // wraps above cn for bins of other chunks
+        } else if (k < klo || k > khi) {
+          lo = 0xFFFFFFFFu;
+        } else {
+          uint32_t l0 = 0, h0 = cn - 1;
+          while (l0 < h0) {
+            const uint32_t mid = (l0 + h0) >> 1;
+            if (bkey[mid] < k) l0 = mid + 1;
+            else h0 = mid;
+          }
+          lo = l0;
+        }
+        if (lo >= cn) {
           // a bin of another chunk; the first chunk gives every particle a
           // valid bin number, which the particle's own chunk overwrites
           if (first && !last) segid[g] = s0;
           continue;
-        }
-        uint32_t lo = 0, hi = cn - 1;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (bkey[mid] < k) lo = mid + 1;
-          else hi = mid;
         }
         segid[g] = s0 + c0 + lo;
         long long val[NC];
@@ -973,6 +996,7 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
   const int lane = lane_id();
   const int P = p.P, R = p.R, P2 = P * P;
   const int q = Q ? Q : p.q;
+  const ExpScale ks_flat = psf_scale(p, 0.0f);  // the scale of a z-independent PSF, formed once
   for (uint32_t idx = blockIdx.x * LIK_WAVES + wave_id(); idx < E; idx += gridDim.x * LIK_WAVES) {
     const uint32_t e = MODE == LIK_ALL ? idx : chk.list[idx];
     int t;
@@ -1003,7 +1027,7 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       if (DIM == 3) zpos = (float)in.dpix[(size_t)2 * p.NT + e] + in.doff[(size_t)2 * p.NT + e];
       I0 = in.dint[e];
     }
-    const ExpScale ks = psf_scale(p, zpos);
+    const ExpScale ks = (DIM == 3 && p.psf == 1) ? psf_scale(p, zpos) : ks_flat;
     const float Iq = I0 / (float)(q * q);
     const float *fr = frame + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
     // SEPARABLE: the 2 P per-axis sums over q sub-samples are spread over the

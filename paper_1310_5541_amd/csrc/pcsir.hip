@@ -24,11 +24,12 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
-      ll, wbin, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
+      ll, wbin, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
   uint32_t n256; // propagate tiles
+  uint64_t lut_cap;  // entries of the cell -> bin table
   uint32_t nS;   // scan tiles
   uint32_t nB;   // bin-sum tiles
 };
@@ -172,6 +173,10 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.tilesS = take(sizeof(Tile) * (size_t)L.nS);
   L.tilesB = take(sizeof(BinTile) * (size_t)L.nB);
   L.tcount = take(4 * (size_t)L.nB);
+  // cell -> bin table: 8 entries per particle, between 2^16 and 2^25 (128 MB)
+  L.lut_cap = 1ull << 16;
+  while (L.lut_cap < 8 * NT && L.lut_cap < (1ull << 25)) L.lut_cap <<= 1;
+  L.lut = take(4 * L.lut_cap);
   L.tile_last = take(4 * (size_t)L.nS);
   L.tfirst = take(4 * (T + 1));
   L.t256_first = take(4 * (T + 1));
@@ -416,13 +421,14 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   k_seg_scan<<<1, TPB, 0, st>>>(p.T, chunk, G, meta, c->at<uint32_t>(L.seg_first));
   mark(c, "seg_mark");
   k_seg_mark<<<G, TPB, 0, st>>>(p, G, sb, meta, chunk, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
-                                  c->at<int32_t>(L.seg_t));
+                                  c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.lut), L.lut_cap);
   k_seg_first<<<(p.T + 1 + TPB - 1) / TPB, TPB, 0, st>>>(p.T, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                                          meta, c->at<uint32_t>(L.seg_first));
   mark(c, "bin_sums");
   k_bin_sums<DIM><<<c->nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
-                                        c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta);
+                                        c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
+                                        c->at<uint32_t>(L.lut), L.lut_cap);
   mark(c, "dummy");
   k_dummy<DIM><<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(
       p, meta, acc, c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.kbase),
