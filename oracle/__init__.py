@@ -111,6 +111,9 @@ def lib():
         L.orc_weigh.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_void_p,
                                 C.c_void_p, C.c_int32, C.c_void_p]
         L.orc_weigh.restype = C.c_int64
+        L.orc_step_thr.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_int32), C.c_int64, C.c_int64, C.c_int32, C.c_double, C.c_void_p,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.orc_resample.argtypes = [C.c_int64, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
         L.orc_step.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_void_p,
                                C.c_int64, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]
@@ -216,6 +219,25 @@ def step(model: Model, frame: np.ndarray, state: np.ndarray, k: int, t: int = 0,
     mc = model._c()
     lib().orc_step(C.byref(mc), _p(fr), H, W, N, _p(s), k, t, 1 if sir else 0, _p(est), _p(neff))
     return s, est, float(neff[0])
+
+
+def step_thr(model: Model, frame: np.ndarray, state: np.ndarray, logw, uniform: bool, k: int, t: int = 0,
+             sir: bool = False, neff_frac: float = float("inf")):
+    """One step with a resampling threshold (orc_step_thr). Returns
+    (state, logw, uniform, est [D], neff, resampled)."""
+    fr = np.ascontiguousarray(frame, dtype=np.float32)
+    H, W = fr.shape
+    s = np.ascontiguousarray(state, dtype=np.float32).copy()
+    D, N = s.shape
+    lw = np.ascontiguousarray(np.zeros(N) if logw is None else logw, dtype=np.float64).copy()
+    uni = C.c_int32(1 if uniform else 0)
+    est = np.zeros(D, np.float64)
+    neff = C.c_double(0.0)
+    res = C.c_int32(0)
+    mc = model._c()
+    lib().orc_step_thr(C.byref(mc), _p(fr), H, W, N, _p(s), _p(lw), C.byref(uni), int(k), int(t), 1 if sir else 0,
+                       float(neff_frac), _p(est), C.byref(neff), C.byref(res))
+    return s, lw, bool(uni.value), est, float(neff.value), bool(res.value)
 
 
 def track(model: Model, frames: np.ndarray, n_per_target, state: np.ndarray, k0: int = 1,

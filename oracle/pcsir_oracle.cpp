@@ -257,7 +257,12 @@ double orc_loglik(const orc_model *mdl, const float *frame, int32_t H, int32_t W
  *           the likelihood is evaluated on the dummy only and its value is
  *           copied to every member.
  * The log-weight of particle i is logw_prev[i] + its likelihood term
- * (logw_prev NULL: uniform previous weights, which cancel). Normalisation
+ * (logw_prev NULL: uniform previous weights, which cancel). With previous
+ * weights the dummy is the centre of mass of its members weighted by them
+ * (Sec. 4: the dummy's state is formed from the members' states and
+ * weights), sum_i w_i x_i / sum_i w_i, w_i = exp(logw_prev[i] - max over the
+ * bin); without them, or when they are equal, it is the plain mean of
+ * Alg. pcSIR. Normalisation
  * (Alg. SIR, normalise; applied in Alg. pcSIR as well) divides by the sum,
  * after a shift by the maximum log-weight that cancels in exact arithmetic.
  * N_eff = 1 / sum w^2 (both algorithms). The estimate is the posterior mean
@@ -302,10 +307,22 @@ int64_t orc_weigh(const orc_model *mdl, const float *frame, int32_t H, int32_t W
       out->bin_key[1 * N + B] = std::get<1>(kv.first);
       out->bin_key[2 * N + B] = std::get<0>(kv.first);
       out->bin_n[B] = (int64_t)mem.size();
-      for (int d = 0; d < D; ++d) {
-        double s = 0.0;
-        for (int64_t i : mem) s += (double)state[(int64_t)d * N + i];
-        out->bin_mean[(int64_t)d * N + B] = s / (double)mem.size();
+      if (logw_prev) {
+        double mx = -INFINITY;
+        for (int64_t i : mem) mx = logw_prev[i] > mx ? logw_prev[i] : mx;
+        double ws = 0.0;
+        for (int64_t i : mem) ws += std::exp(logw_prev[i] - mx);
+        for (int d = 0; d < D; ++d) {
+          double s = 0.0;
+          for (int64_t i : mem) s += std::exp(logw_prev[i] - mx) * (double)state[(int64_t)d * N + i];
+          out->bin_mean[(int64_t)d * N + B] = s / ws;
+        }
+      } else {
+        for (int d = 0; d < D; ++d) {
+          double s = 0.0;
+          for (int64_t i : mem) s += (double)state[(int64_t)d * N + i];
+          out->bin_mean[(int64_t)d * N + B] = s / (double)mem.size();
+        }
       }
       if (mdl->dummy_mode == 1) {
         for (int a = 0; a < dim; ++a) {
@@ -395,6 +412,43 @@ void orc_step(const orc_model *mdl, const float *frame, int32_t H, int32_t W, in
   std::vector<float> old(state, state + (size_t)D * N);
   for (int d = 0; d < D; ++d)
     for (int64_t j = 0; j < N; ++j) state[(int64_t)d * N + j] = old[(int64_t)d * N + s[j]];
+}
+
+/* One step of one target with a resampling threshold (Alg. SIR / Alg.
+ * pcSIR: resample only when N_eff falls below it). logw [N] holds the
+ * normalised log-weights kept from the previous frame; *uniform != 0 means
+ * they are all equal (after resampling or at the start), which is weighed
+ * exactly as without previous weights. The target resamples when
+ * N_eff < neff_frac * N; it then takes the resampled set and *uniform = 1.
+ * Otherwise the propagated particles stay in place, logw[i] = log w_i and
+ * *uniform = 0. *resampled reports which happened. neff_frac = +inf gives
+ * orc_step. */
+void orc_step_thr(const orc_model *mdl, const float *frame, int32_t H, int32_t W, int64_t N, float *state,
+                  double *logw, int32_t *uniform, int64_t k, int64_t t, int32_t sir, double neff_frac, double *est,
+                  double *neff, int32_t *resampled) {
+  const int D = 2 * mdl->dim + 1;
+  orc_propagate(mdl, N, state, k, t);
+  std::vector<int32_t> keys(3 * N), bin_key(3 * N);
+  std::vector<int64_t> bin_of(N), bin_n(N), s(N);
+  std::vector<double> bin_mean((size_t)D * N), ll(N), w(N);
+  double scal[3];
+  orc_weigh_out o = {keys.data(), bin_of.data(), bin_key.data(), bin_n.data(), bin_mean.data(),
+                     ll.data(),   w.data(),      scal,           est};
+  orc_weigh(mdl, frame, H, W, N, state, *uniform ? nullptr : logw, sir, &o);
+  *neff = scal[2];
+  if (scal[2] < neff_frac * (double)N) {
+    double u = orc_resample_u(mdl->seed, (uint64_t)k, (uint64_t)t);
+    orc_resample(N, w.data(), u, nullptr, s.data());
+    std::vector<float> old(state, state + (size_t)D * N);
+    for (int d = 0; d < D; ++d)
+      for (int64_t j = 0; j < N; ++j) state[(int64_t)d * N + j] = old[(int64_t)d * N + s[j]];
+    *uniform = 1;
+    *resampled = 1;
+  } else {
+    for (int64_t i = 0; i < N; ++i) logw[i] = std::log(w[i]);
+    *uniform = 0;
+    *resampled = 0;
+  }
 }
 
 /* Several targets over several frames: targets t = 0..T-1 with particle
