@@ -420,8 +420,9 @@ void orc_step(const orc_model *mdl, const float *frame, int32_t H, int32_t W, in
  * they are all equal (after resampling or at the start), which is weighed
  * exactly as without previous weights. The target resamples when
  * N_eff < neff_frac * N; it then takes the resampled set and *uniform = 1.
- * Otherwise the propagated particles stay in place, logw[i] = log w_i and
- * *uniform = 0. *resampled reports which happened. neff_frac = +inf gives
+ * Otherwise the propagated particles stay in place, logw[i] = log w_i,
+ * formed in the log domain (previous logw_i + l_i - M - log S) so that it
+ * stays finite where w_i underflows binary64, and *uniform = 0. *resampled reports which happened. neff_frac = +inf gives
  * orc_step. */
 void orc_step_thr(const orc_model *mdl, const float *frame, int32_t H, int32_t W, int64_t N, float *state,
                   double *logw, int32_t *uniform, int64_t k, int64_t t, int32_t sir, double neff_frac, double *est,
@@ -445,7 +446,10 @@ void orc_step_thr(const orc_model *mdl, const float *frame, int32_t H, int32_t W
     *uniform = 1;
     *resampled = 1;
   } else {
-    for (int64_t i = 0; i < N; ++i) logw[i] = std::log(w[i]);
+    /* normalised log-weights, kept in the log domain: log w_i = logw_i - M - log S,
+       finite even where w_i itself underflows binary64 */
+    const double lnorm = scal[0] + std::log(scal[1]);
+    for (int64_t i = 0; i < N; ++i) logw[i] = (*uniform ? 0.0 : logw[i]) + ll[bin_of[i]] - lnorm;
     *uniform = 0;
     *resampled = 0;
   }

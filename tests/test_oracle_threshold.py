@@ -123,5 +123,29 @@ def test_threshold_decision_and_kept_weights(orc, scene, sir):
     prop = orc.propagate(mdl, cloud, 1, 0).astype(np.float32)
     assert np.array_equal(below[0], prop)
     r = orc.weigh(mdl, fr[1], prop, sir=sir)
-    np.testing.assert_array_equal(below[1], np.log(r["w"]))
+    np.testing.assert_array_equal(below[1], r["ll"][r["bin_of"]] - (r["M"] + math.log(r["S"])))
+    np.testing.assert_allclose(np.exp(below[1]), r["w"], rtol=1e-13, atol=0)
     assert abs(np.exp(below[1]).sum() - 1.0) < 1e-12
+
+
+def test_kept_log_weights_stay_finite_where_weights_underflow(orc, scene):
+    """pcSIR without resampling over several frames: normalised weights fall
+    below the smallest binary64 value (exp underflows to 0), yet the kept
+    log-weights stay finite and equal the running sum of each particle's
+    dummy log-likelihoods minus its log-sum-exp, recomputed here frame by
+    frame from the dummies the oracle reports; every N_eff stays finite."""
+    w = synth.preset("tiny", H=96, W=96, T=1, n=(1500,), K=5, i0=(40.0, 100.0))
+    tr = synth.truth(w, seed=3)
+    fr = np.concatenate([np.zeros((1, 96, 96), np.float32), synth.frames(w, tr, seed=3)])  # fr[k]: frame k
+    mdl = _mdl()
+    x, lw, uni = synth.random_cloud(w, tr[0, 0], 1500, 3.0, seed=22), None, True
+    acc = np.zeros(x.shape[1])
+    for k in range(1, 6):
+        prev = None if uni else lw.copy()
+        x, lw, uni, est, neff, res = orc.step_thr(mdl, fr[k], x, lw, uni, k, 0, False, 0.0)
+        assert not res and np.isfinite(neff) and np.all(np.isfinite(lw))
+        r = orc.weigh(mdl, fr[k], x, sir=False, logw_prev=prev)
+        acc += r["ll"][r["bin_of"]]
+        mx = acc.max()
+        np.testing.assert_allclose(lw, acc - (mx + math.log(np.exp(acc - mx).sum())), rtol=1e-12, atol=1e-9)
+    assert lw.min() < -746.0   # the weights themselves underflow
