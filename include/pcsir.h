@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define PCSIR_ABI_VERSION 1
+#define PCSIR_ABI_VERSION 2
 
 typedef struct pcsir_ctx pcsir_ctx; /* opaque; host memory owned by the library */
 
@@ -98,6 +98,15 @@ typedef struct {
   float sigma_xi;              /* likelihood width sigma_xi > 0 */
   float proc_sigma[7];         /* process-noise standard deviation per state component and frame */
   uint64_t seed;               /* Philox4x64-10 key word 0 */
+  double neff_threshold;       /* resampling threshold as a fraction of N_t (Alg. SIR and Alg. pcSIR
+                                  resample when N_eff falls below a threshold). Above 1 (e.g.
+                                  +inf): resample every frame, the default. In [0, 1]: a target
+                                  resamples only when N_eff < neff_threshold * N_t; otherwise its
+                                  particles stay and carry their normalised log-weights into the
+                                  next frame, where each pcSIR dummy is the centre of mass of its
+                                  members weighted by them (Sec. 4). Weighted sums use float64
+                                  atomics, so results with kept weights are reproducible to
+                                  rounding, not bit for bit. NaN or < 0: invalid. */
 } pcsir_config;
 
 /* Bytes of device workspace that a context with this config needs (0 if the
@@ -119,7 +128,9 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
  * and the posterior-mean estimate, and resample (systematic scheme, every
  * frame). frame_dev: float32 [H][W], or [T][H][W] with per_target_frames;
  * it must stay valid until the stream has passed this step. k >= 1 is the
- * frame index; it is part of the random-number counter. Asynchronous. */
+ * frame index; it is part of the random-number counter. With neff_threshold
+ * in [0, 1] a target resamples only when its N_eff is below the threshold.
+ * Asynchronous. */
 pcsir_status pcsir_step(pcsir_ctx *ctx, const float *frame_dev, int32_t H, int32_t W, int64_t k);
 
 /* One frame of classical SIR (Alg. SIR): as pcsir_step, but the likelihood
@@ -158,13 +169,18 @@ pcsir_status pcsir_set_particles(pcsir_ctx *ctx, const float *src_dev);
  *  BIN_TARGET  int32   [B]          target of every bin; bins in ascending (target, kz, ky, kx)
  *  BIN_KEY     int32   [3][B]       cell index of every bin
  *  BIN_N       int64   [B]          members per bin
- *  BIN_MEAN    float64 [D][B]       mean state of the members of every bin (exact sums)
+ *  BIN_MEAN    float64 [D][B]       mean state of the members of every bin (exact sums); with kept
+ *                                   weights, the weighted mean the dummy used (CoM positions)
  *  LOGLIK      float64 [B] (pcSIR) or [sum N] (SIR)  log-likelihood per bin or particle
  *  WEIGHTS     float64 [sum N]      normalised weights, storage order
  *  TARGET      float64 [T][4]       per target: max log-weight M, S = sum exp(logw - M),
  *                                   N_eff, resampling uniform u
  *  CDF         float64 [sum N]      cumulative weights per target, storage order
- *  RESAMPLE    int32   [sum N]      s(j): parent of new particle j, index within its target */
+ *  RESAMPLE    int32   [sum N]      s(j): parent of new particle j, index within its target
+ *                                   (the identity for a target that did not resample)
+ *  LOGW        float64 [sum N]      log-weight every current particle carries into the next frame:
+ *                                   -log N_t for a target that resampled (or always, with
+ *                                   neff_threshold above 1), else its normalised log-weight */
 typedef enum {
   PCSIR_DUMP_PROPAGATED = 0,
   PCSIR_DUMP_KEYS = 1,
@@ -177,7 +193,8 @@ typedef enum {
   PCSIR_DUMP_WEIGHTS = 8,
   PCSIR_DUMP_TARGET = 9,
   PCSIR_DUMP_CDF = 10,
-  PCSIR_DUMP_RESAMPLE = 11
+  PCSIR_DUMP_RESAMPLE = 11,
+  PCSIR_DUMP_LOGW = 12
 } pcsir_dump;
 
 pcsir_status pcsir_debug_dump(pcsir_ctx *ctx, int32_t what, void *dst_dev, size_t bytes);

@@ -16,10 +16,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libpcsir.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 DUMP = dict(propagated=0, keys=1, counts=2, bin_target=3, bin_key=4, bin_n=5, bin_mean=6, loglik=7,
-            weights=8, target=9, cdf=10, resample=11)
+            weights=8, target=9, cdf=10, resample=11, logw=12)
 
 _STATUS = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP", -4: "E_STATE", -5: "E_NUMERIC",
            -6: "E_UNSUPPORTED"}
@@ -43,6 +43,7 @@ class _Cfg(C.Structure):
         ("per_target_frames", C.c_int32), ("frame_h", C.c_int32), ("frame_w", C.c_int32),
         ("sigma_psf", C.c_float), ("astig_gamma", C.c_float), ("astig_d", C.c_float), ("i_bg", C.c_float),
         ("sigma_xi", C.c_float), ("proc_sigma", C.c_float * 7), ("seed", C.c_uint64),
+        ("neff_threshold", C.c_double),
     ]
 
 
@@ -138,6 +139,7 @@ class Config:
     sigma_xi: float = 10.0
     proc_sigma: tuple = (0.5, 0.5, 0.1, 0.1, 2.0)
     seed: int = 1
+    neff_threshold: float = float("inf")   # <= 1: resample only when N_eff < fraction * N
 
     @property
     def D(self) -> int:
@@ -170,6 +172,7 @@ class Config:
         for d in range(7):
             c.proc_sigma[d] = float(ps[d])
         c.seed = int(self.seed) & (2**64 - 1)
+        c.neff_threshold = float(self.neff_threshold)
         return c, n  # keep n alive while c is used
 
     @classmethod
@@ -315,7 +318,7 @@ class Filter:
             B = int(self.dump("counts")[0].item())
         shapes = dict(propagated=((D, NT), t.float32), keys=((3, NT), t.int32), counts=((3,), t.int64),
                       weights=((NT,), t.float64), target=((T, 4), t.float64), cdf=((NT,), t.float64),
-                      resample=((NT,), t.int32))
+                      resample=((NT,), t.int32), logw=((NT,), t.float64))
         if what in shapes:
             shape, dt = shapes[what]
         elif what == "bin_target":

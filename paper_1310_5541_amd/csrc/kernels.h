@@ -775,6 +775,69 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
   if (sat) atomicOr((unsigned long long *)&meta[META_ERR], (unsigned long long)ERR_FIXED_SAT);
 }
 
+// Weighted member sums of every bin for targets with kept (non-uniform)
+// weights: sum w, sum w (x - pixel) per position axis, sum w v, sum w I, with
+// w = exp(log-weight - the largest log-weight in the bin), so the bin's
+// largest member has w = 1 however small the bin's share of the target's
+// weight. wacc [2 + D][NT]: rows 0..D the sums (FP64 atomics), row D + 1 the
+// bin's largest log-weight as ordered bits (atomic max). One thread per
+// particle over the propagate tiles; the rows are cleared first.
+__global__ __launch_bounds__(TPB) void k_wsum_clear(uint32_t NT, int D, const uint64_t *__restrict__ meta,
+                                                    double *__restrict__ wacc) {
+  const uint32_t B = (uint32_t)meta[META_B];
+  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < B; i += gridDim.x * TPB)
+    for (int c = 0; c <= D + 1; ++c) wacc[(size_t)c * NT + i] = 0.0;  // row D + 1: below every ordered value
+}
+
+__global__ __launch_bounds__(TPB) void k_bin_wmax(Params p, const Tile *__restrict__ tiles,
+                                                  const uint32_t *__restrict__ off, const uint32_t *__restrict__ segid,
+                                                  const double *__restrict__ lw, const int32_t *__restrict__ tuni,
+                                                  double *__restrict__ wacc) {
+  const Tile tl = tiles[blockIdx.x];
+  if (tuni[tl.t]) return;
+  const uint32_t base = off[tl.t];
+  const uint32_t i = tl.i0 + threadIdx.x;
+  if (i >= off[tl.t + 1] - base) return;
+  unsigned long long *mx = (unsigned long long *)(wacc + (size_t)(1 + p.D) * p.NT);
+  atomicMax(&mx[segid[base + i]], ordered_bits(lw[base + i]));
+}
+
+template <int DIM>
+__global__ __launch_bounds__(TPB) void k_bin_wsums(Params p, const Tile *__restrict__ tiles,
+                                                   const uint32_t *__restrict__ off, const float *__restrict__ s,
+                                                   const uint32_t *__restrict__ segid, const double *__restrict__ lw,
+                                                   const int32_t *__restrict__ tuni, double *__restrict__ wacc) {
+  constexpr int D = 2 * DIM + 1;
+  const Tile tl = tiles[blockIdx.x];
+  const int t = tl.t;
+  if (tuni[t]) return;
+  const uint32_t base = off[t];
+  const uint32_t i = tl.i0 + threadIdx.x;
+  if (i >= off[t + 1] - base) return;
+  const uint32_t g = base + i, NT = p.NT;
+  const uint32_t b = segid[g];
+  const unsigned long long *mx = (const unsigned long long *)(wacc + (size_t)(1 + D) * NT);
+  const double w = exp(lw[g] - from_ordered_bits(mx[b]));
+  atomicAdd(&wacc[b], w);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const float x = s[(size_t)a * NT + g];
+    atomicAdd(&wacc[(size_t)(1 + a) * NT + b], w * (double)(x - (float)cell_index(x, 1)));  // x - pixel exact
+  }
+#pragma unroll
+  for (int d = DIM; d < D; ++d) atomicAdd(&wacc[(size_t)(1 + d) * NT + b], w * (double)s[(size_t)d * NT + g]);
+}
+
+__global__ __launch_bounds__(TPB) void k_copy_i32(int32_t *__restrict__ dst, const int32_t *__restrict__ src,
+                                                  uint32_t n) {
+  const uint32_t i = blockIdx.x * TPB + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+__global__ __launch_bounds__(TPB) void k_fill_i32(int32_t *__restrict__ dst, int32_t v, uint32_t n) {
+  const uint32_t i = blockIdx.x * TPB + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+
 // Dummy particle of every bin: mean of the members (CoM) or the cell centre
 // (CoC) for the positions, mean of the other components. Positions are kept
 // as (pixel of the cell, offset from it) so the likelihood never subtracts
@@ -784,7 +847,8 @@ __global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsig
                         const uint32_t *__restrict__ seg_key, const int32_t *__restrict__ seg_t,
                         const uint32_t *__restrict__ kbase, const int32_t *__restrict__ bbox_cur,
                         int32_t *__restrict__ dpix, float *__restrict__ doff, float *__restrict__ dint,
-                        float *__restrict__ dvel) {
+                        float *__restrict__ dvel, const double *__restrict__ wacc,
+                        const int32_t *__restrict__ tuni) {
   const uint32_t B = (uint32_t)meta[META_B];
   const uint32_t NT = p.NT;
   for (uint32_t sidx = blockIdx.x * blockDim.x + threadIdx.x; sidx < B; sidx += gridDim.x * blockDim.x) {
@@ -792,6 +856,9 @@ __global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsig
     int32_t cell[3];
     decode_key<DIM>(seg_key[sidx], p.T, kbase, bbox_cur, t, cell);
     const double n = (double)(long long)acc[sidx];
+    // kept (non-uniform) weights: the members' centre of mass weighted by them
+    const bool wt = wacc && !tuni[t] && wacc[sidx] > 0.0;
+    const double wsum = wt ? wacc[sidx] : 1.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       const int32_t c0 = floor_div(cell[a], p.m[a]);
@@ -800,15 +867,20 @@ __global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsig
       if (p.dummy_mode == 1) {
         const int32_t r = cell[a] - c0 * p.m[a];  // cell within its pixel, 0..m-1
         off = (float)(((double)r + 0.5) / (double)p.m[a] - 0.5);
+      } else if (wt) {
+        off = (float)(wacc[(size_t)(1 + a) * NT + sidx] / wsum);
       } else {
         off = (float)((double)(long long)acc[(size_t)(1 + a) * NT + sidx] / (double)FX_POS / n);
       }
       doff[(size_t)a * NT + sidx] = off;
     }
-    dint[sidx] = (float)((double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + sidx] / (double)FX_INT / n);
+    dint[sidx] = wt ? (float)(wacc[(size_t)(1 + 2 * DIM) * NT + sidx] / wsum)
+                    : (float)((double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + sidx] / (double)FX_INT / n);
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
-      dvel[(size_t)a * NT + sidx] = (float)((double)(long long)acc[(size_t)(1 + DIM + a) * NT + sidx] / (double)FX_VEL / n);
+      dvel[(size_t)a * NT + sidx] =
+          wt ? (float)(wacc[(size_t)(1 + DIM + a) * NT + sidx] / wsum)
+             : (float)((double)(long long)acc[(size_t)(1 + DIM + a) * NT + sidx] / (double)FX_VEL / n);
   }
 }
 
@@ -1204,10 +1276,44 @@ __global__ __launch_bounds__(TPB) void k_norm_bins(Params p, const uint32_t *__r
   }
 }
 
-// SIR: per-tile partials (max, S, Q, X[D]) over particles, then a per-target combine.
-template <int DIM>
+// Weight of particle g (target t) in storage order. pcSIR: the weight of the
+// bin that holds it (binary search of its key among the target's sorted bin
+// keys); SIR: e^{l_g - M} / S.
+struct WeightSrc {
+  const uint32_t *segid;     // pcSIR: bin of every particle, storage order
+  const double *wbin;        // pcSIR: [B]
+  const double *ll;          // SIR: [NT]; pcSIR: [B]
+  const double *tgt;         // [T][4]
+  // kept weights (resampling threshold below 1; null otherwise): normalised
+  // log-weights of the previous frame, and per target whether they are uniform
+  double *lw;                // [NT]
+  const int32_t *tuni;       // [T]
+};
+// Log-weight of particle g before normalisation: its previous log-weight
+// (0 when the target's weights are uniform) plus its likelihood term.
+template <bool SIR>
+__device__ __forceinline__ double particle_logv(const WeightSrc &ws, int t, uint32_t g) {
+  const double l = SIR ? ws.ll[g] : ws.ll[ws.segid[g]];
+  return (ws.tuni[t] ? 0.0 : ws.lw[g]) + l;
+}
+template <bool SIR>
+__device__ __forceinline__ double particle_weight(const WeightSrc &ws, int t, uint32_t g) {
+  if (ws.lw) return exp(particle_logv<SIR>(ws, t, g) - ws.tgt[t * 4]) / ws.tgt[t * 4 + 1];
+  if (SIR) return exp(ws.ll[g] - ws.tgt[t * 4]) / ws.tgt[t * 4 + 1];
+  return ws.wbin[ws.segid[g]];
+}
+
+// Per-particle normalisation: per-tile partials (max, S, Q, X[D]) over the
+// particles, then a per-target combine.
+template <int DIM, bool SIR>
+__device__ __forceinline__ double norm_value(const WeightSrc &ws, int t, uint32_t g) {
+  return ws.lw ? particle_logv<SIR>(ws, t, g) : ws.ll[g];
+}
+
+// SIR, and pcSIR with kept weights.
+template <int DIM, bool SIR>
 __global__ __launch_bounds__(TPB) void k_norm_part(Params p, const Tile *__restrict__ tiles,
-                                                   const uint32_t *__restrict__ off, const double *__restrict__ ll,
+                                                   const uint32_t *__restrict__ off, WeightSrc ws,
                                                    const float *__restrict__ s, double *__restrict__ part) {
   constexpr int D = 2 * DIM + 1;
   __shared__ double lds[TPB / WAVE];
@@ -1216,7 +1322,7 @@ __global__ __launch_bounds__(TPB) void k_norm_part(Params p, const Tile *__restr
   double mx = -INFINITY;
   for (int it = 0; it < SCAN_ITEMS; ++it) {
     const uint32_t i = tl.i0 + it * TPB + threadIdx.x;
-    if (i < n) mx = fmax(mx, ll[base + i]);
+    if (i < n) mx = fmax(mx, norm_value<DIM, SIR>(ws, tl.t, base + i));
   }
   const double M = block_max<TPB, double>(mx, lds);
   double S = 0.0, Q = 0.0, X[D];
@@ -1226,7 +1332,7 @@ __global__ __launch_bounds__(TPB) void k_norm_part(Params p, const Tile *__restr
     const uint32_t i = tl.i0 + it * TPB + threadIdx.x;
     if (i < n) {
       const uint32_t g = base + i;
-      const double e = exp(ll[g] - M);
+      const double e = exp(norm_value<DIM, SIR>(ws, tl.t, g) - M);
       S += e;
       Q += e * e;
 #pragma unroll
@@ -1251,7 +1357,8 @@ template <int DIM>
 __global__ __launch_bounds__(TPB) void k_norm_comb(Params p, const uint32_t *__restrict__ tfirst,
                                                    const double *__restrict__ part, const StepDesc *__restrict__ desc,
                                                    double *__restrict__ tgt, double *__restrict__ est,
-                                                   int32_t *__restrict__ tflag, uint64_t *__restrict__ meta) {
+                                                   int32_t *__restrict__ tflag, uint64_t *__restrict__ meta,
+                                                   const int32_t *__restrict__ tfallback) {
   constexpr int D = 2 * DIM + 1;
   constexpr int W = 3 + D;
   __shared__ double lds[TPB / WAVE];
@@ -1287,25 +1394,11 @@ __global__ __launch_bounds__(TPB) void k_norm_comb(Params p, const uint32_t *__r
     for (int d = 0; d < D; ++d) est[t * D + d] = X[d] / S;
     tflag[t] = ok ? 0 : 1;
     if (!ok) atomicOr((unsigned long long *)&meta[META_ERR], (unsigned long long)ERR_NONFINITE);
+    if (tfallback && tfallback[t]) atomicAdd((unsigned long long *)&meta[META_FALLBACK], 1ull);
   }
 }
 
 // ---------------------------------------------------------------- weights, CDF, resampling
-// Weight of particle g (target t) in storage order. pcSIR: the weight of the
-// bin that holds it (binary search of its key among the target's sorted bin
-// keys); SIR: e^{l_g - M} / S.
-struct WeightSrc {
-  const uint32_t *segid;     // pcSIR: bin of every particle, storage order
-  const double *wbin;        // pcSIR: [B]
-  const double *ll;          // SIR: [NT]
-  const double *tgt;         // [T][4]
-};
-template <bool SIR>
-__device__ __forceinline__ double particle_weight(const WeightSrc &ws, int t, uint32_t g) {
-  if (SIR) return exp(ws.ll[g] - ws.tgt[t * 4]) / ws.tgt[t * 4 + 1];
-  return ws.wbin[ws.segid[g]];
-}
-
 template <bool SIR>
 __global__ __launch_bounds__(TPB) void k_cdf_sum(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
                                                  WeightSrc ws, double *__restrict__ tile_sum) {
@@ -1385,7 +1478,8 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
                                                       const uint32_t *__restrict__ tile_last,
                                                       WeightSrc ws, const double *__restrict__ tile_pre,
                                                       const int32_t *__restrict__ tflag, uint32_t *__restrict__ anc,
-                                                      double *__restrict__ cdf_dbg) {
+                                                      double *__restrict__ cdf_dbg, double neff_frac,
+                                                      int32_t *__restrict__ tuni_next) {
   __shared__ double lds[TPB / WAVE];
   __shared__ double bound[TPB + 1];
   __shared__ double cl[SCAN_TILE + SCAN_TILE / SCAN_ITEMS];
@@ -1425,12 +1519,21 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
   }
   if (threadIdx.x == 0) bound[TPB] = tile_end;
   __syncthreads();  // also: every thread has read its weights from cl
-  if (tflag[t]) {
-    // non-finite normalisation: keep the particles (identity resampling)
+  // kept weights: a target resamples only when N_eff < neff_frac * N
+  const bool keep = ws.lw && !tflag[t] && !(ws.tgt[t * 4 + 2] < neff_frac * (double)n);
+  if (tuni_next && tl.i0 == 0 && threadIdx.x == 0) tuni_next[t] = keep ? 0 : 1;
+  if (tflag[t] || keep) {
+    // the particles stay (identity resampling): after a non-finite
+    // normalisation, or when N_eff is above the threshold; then they keep
+    // their normalised log-weights for the next frame
+    const double lnorm = ws.tgt[t * 4] + log(ws.tgt[t * 4 + 1]);
 #pragma unroll
     for (int it = 0; it < SCAN_ITEMS; ++it) {
       const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
-      if (i < n) anc[base + i] = i;
+      if (i < n) {
+        anc[base + i] = i;
+        if (keep) ws.lw[base + i] = particle_logv<SIR>(ws, t, base + i) - lnorm;
+      }
     }
     return;
   }
@@ -1518,7 +1621,8 @@ __global__ void k_dbg_keys(int dim, uint32_t NT, int m0, int m1, int m2, const f
 template <int DIM>
 __global__ void k_dbg_bins(Params p, const uint64_t *__restrict__ meta, const unsigned long long *__restrict__ acc,
                            const uint32_t *__restrict__ seg_key, const uint32_t *__restrict__ kbase,
-                           const int32_t *__restrict__ bbox_cur, int what, void *__restrict__ out) {
+                           const int32_t *__restrict__ bbox_cur, int what, void *__restrict__ out,
+                           const double *__restrict__ wacc, const int32_t *__restrict__ tuni) {
   constexpr int D = 2 * DIM + 1;
   const uint32_t B = (uint32_t)meta[META_B];
   const uint32_t NT = p.NT;
@@ -1531,7 +1635,14 @@ __global__ void k_dbg_bins(Params p, const uint64_t *__restrict__ meta, const un
     if (what == 4)
       for (int a = 0; a < 3; ++a) ((int32_t *)out)[(size_t)a * B + s] = cell[a];
     if (what == 5) ((long long *)out)[s] = (long long)acc[s];
-    if (what == 6) {
+    if (what == 6 && wacc && !tuni[t] && wacc[s] > 0.0) {
+      // kept weights: the weighted mean the dummy was formed from
+      double *o = (double *)out;
+      const double ws = wacc[s];
+      for (int a = 0; a < DIM; ++a)
+        o[(size_t)a * B + s] = (double)floor_div(cell[a], p.m[a]) + wacc[(size_t)(1 + a) * NT + s] / ws;
+      for (int d = DIM; d < D; ++d) o[(size_t)d * B + s] = wacc[(size_t)(1 + d) * NT + s] / ws;
+    } else if (what == 6) {
       double *o = (double *)out;
       for (int a = 0; a < DIM; ++a) {
         const double c0 = (double)floor_div(cell[a], p.m[a]);
@@ -1540,19 +1651,32 @@ __global__ void k_dbg_bins(Params p, const uint64_t *__restrict__ meta, const un
       for (int a = 0; a < DIM; ++a)
         o[(size_t)(DIM + a) * B + s] = (double)(long long)acc[(size_t)(1 + DIM + a) * NT + s] / (double)FX_VEL / n;
       o[(size_t)(2 * DIM) * B + s] = (double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + s] / (double)FX_INT / n;
-      (void)D;
     }
   }
 }
 
+// Normalised weights of the last step. A target that kept its weights
+// (tuni_next 0) already holds log w in lw, in place of the step's input.
 template <bool SIR>
 __global__ __launch_bounds__(TPB) void k_dbg_weights(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
-                                                     WeightSrc ws, double *__restrict__ out) {
+                                                     WeightSrc ws, const int32_t *__restrict__ tuni_next,
+                                                     double *__restrict__ out) {
   const Tile tl = tiles[blockIdx.x];
   const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
   const uint32_t i = tl.i0 + threadIdx.x;
   if (i >= n) return;
-  out[base + i] = particle_weight<SIR>(ws, tl.t, base + i);
+  out[base + i] = (ws.lw && !tuni_next[tl.t]) ? exp(ws.lw[base + i]) : particle_weight<SIR>(ws, tl.t, base + i);
+}
+
+// Log-weight each particle carries into the next frame (uniform targets: -log N_t).
+__global__ __launch_bounds__(TPB) void k_dbg_logw(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
+                                                  const double *__restrict__ lw, const int32_t *__restrict__ tuni,
+                                                  double *__restrict__ out) {
+  const Tile tl = tiles[blockIdx.x];
+  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t i = tl.i0 + threadIdx.x;
+  if (i >= n) return;
+  out[base + i] = (!lw || tuni[tl.t]) ? -log((double)n) : lw[base + i];
 }
 
 }  // namespace pcsir

@@ -24,7 +24,8 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
-      ll, wbin, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first, bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
+      ll, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
+      bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
@@ -71,6 +72,7 @@ bool valid_config(const pcsir_config *c, std::string *why) {
   if (c->psf == PCSIR_PSF_ASTIG3D && !(c->astig_d > 0.0f)) return bad("astig_d must be > 0");
   for (int d = 0; d < 2 * c->dim + 1; ++d)
     if (!(c->proc_sigma[d] >= 0.0f)) return bad("proc_sigma must be >= 0");
+  if (!(c->neff_threshold >= 0.0)) return bad("neff_threshold must be >= 0 (above 1: resample every frame)");
   return true;
 }
 
@@ -111,8 +113,11 @@ void build_tables(const pcsir_config *c, Tables &tb) {
 }
 
 
+// A resampling threshold in [0, 1] keeps weights across frames.
+bool keeps_weights(const pcsir_config *c) { return c->neff_threshold <= 1.0; }
+
 Layout plan(const pcsir_config *c, const Tables &tb) {
-  Layout L;
+  Layout L{};
   const size_t NT = tb.off.back();
   const size_t T = c->n_targets;
   const size_t dim = c->dim, D = 2 * dim + 1;
@@ -150,6 +155,12 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.dvel = take(4 * dim * NT);
   L.ll = take(8 * NT);
   L.wbin = take(8 * NT);
+  if (keeps_weights(c)) {
+    L.lw = take(8 * NT);
+    L.wacc = take(8 * (2 + D) * NT);
+    L.tuni = take(4 * T);
+    L.tuni_next = take(4 * T);
+  }
   L.desc = take(sizeof(StepDesc));
   L.surr = c->lik_mode >= PCSIR_LIK_SURR_BF16 ? take(SURR_BYTES) : 0;  // surrogate weights
   L.tfb = take(4 * T);
@@ -284,6 +295,9 @@ WeightSrc weight_src(const pcsir_ctx *c) {
   w.wbin = c->at<double>(c->L.wbin);
   w.ll = c->at<double>(c->L.ll);
   w.tgt = c->at<double>(c->L.tgt);
+  const bool keep = keeps_weights(&c->cfg);
+  w.lw = keep ? c->at<double>(c->L.lw) : nullptr;
+  w.tuni = keep ? c->at<int32_t>(c->L.tuni) : nullptr;
   return w;
 }
 
@@ -382,6 +396,11 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   uint32_t *anc = c->at<uint32_t>(L.anc);
   uint64_t *meta = c->at<uint64_t>(L.meta);
 
+  const bool keep = keeps_weights(&c->cfg);
+  int32_t *tuni = keep ? c->at<int32_t>(L.tuni) : nullptr;
+  double *wacc = keep ? c->at<double>(L.wacc) : nullptr;
+  // the previous frame's resampling decisions become this frame's
+  if (keep) k_copy_i32<<<(p.T + TPB - 1) / TPB, TPB, 0, st>>>(tuni, c->at<int32_t>(L.tuni_next), (uint32_t)p.T);
   mark(c, "propagate");
   k_propagate<DIM, true><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc,
                                                  c->at<int32_t>(L.bbox_part), c->at<unsigned long long>(L.acc), meta);
@@ -429,11 +448,18 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
                                         c->at<uint32_t>(L.lut), L.lut_cap);
+  if (keep) {
+    mark(c, "bin_wsums");
+    k_wsum_clear<<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(p.NT, p.D, meta, wacc);
+    k_bin_wmax<<<L.n256, TPB, 0, st>>>(p, t256, off, c->at<uint32_t>(L.segid), c->at<double>(L.lw), tuni, wacc);
+    k_bin_wsums<DIM><<<L.n256, TPB, 0, st>>>(p, t256, off, sout, c->at<uint32_t>(L.segid), c->at<double>(L.lw),
+                                             tuni, wacc);
+  }
   mark(c, "dummy");
   k_dummy<DIM><<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(
       p, meta, acc, c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.kbase),
       c->at<int32_t>(L.bbox_cur), c->at<int32_t>(L.dpix), c->at<float>(L.doff), c->at<float>(L.dint),
-      c->at<float>(L.dvel));
+      c->at<float>(L.dvel), wacc, tuni);
   LikInput in;
   in.dpix = c->at<int32_t>(L.dpix);
   in.doff = c->at<float>(L.doff);
@@ -448,11 +474,19 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
     launch_lik<DIM, false, SEP>(c, in, st);
   }
   mark(c, "normalise");
-  k_norm_bins<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.seg_first), c->at<double>(L.ll), acc,
-                                        c->at<int32_t>(L.dpix), desc, c->at<double>(L.wbin), c->at<double>(L.tgt),
-                                        c->at<double>(L.est), c->at<int32_t>(L.tflag), meta,
-                                        c->at<int32_t>(L.tfb));
   WeightSrc ws = weight_src(c);
+  const int32_t *tfb = c->cfg.lik_mode >= PCSIR_LIK_SURR_BF16 ? c->at<int32_t>(L.tfb) : nullptr;
+  if (keep) {
+    // kept weights differ within a bin: normalise over the particles
+    k_norm_part<DIM, false><<<L.nS, TPB, 0, st>>>(p, tS, off, ws, sout, c->at<double>(L.part));
+    k_norm_comb<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.tfirst), c->at<double>(L.part), desc,
+                                          c->at<double>(L.tgt), c->at<double>(L.est), c->at<int32_t>(L.tflag), meta,
+                                          tfb);
+  } else {
+    k_norm_bins<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.seg_first), c->at<double>(L.ll), acc,
+                                          c->at<int32_t>(L.dpix), desc, c->at<double>(L.wbin), c->at<double>(L.tgt),
+                                          c->at<double>(L.est), c->at<int32_t>(L.tflag), meta, tfb);
+  }
   mark(c, "cdf_sum");
   k_cdf_sum<false><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.tile_sum));
   mark(c, "cdf_prefix");
@@ -461,7 +495,8 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   mark(c, "resample");
   k_cdf_resample<false><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
                                               c->at<int32_t>(L.tflag), anc,
-                                              c->debug ? c->at<double>(L.cdf) : nullptr);
+                                              c->debug ? c->at<double>(L.cdf) : nullptr, c->cfg.neff_threshold,
+                                              keep ? c->at<int32_t>(L.tuni_next) : nullptr);
   mark(c, "end");
 }
 
@@ -477,6 +512,10 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
   float *sout = c->state(1 - c->cur);
   uint32_t *anc = c->at<uint32_t>(L.anc);
   uint64_t *meta = c->at<uint64_t>(L.meta);
+  const bool keep = keeps_weights(&c->cfg);
+  if (keep)
+    k_copy_i32<<<(p.T + TPB - 1) / TPB, TPB, 0, st>>>(c->at<int32_t>(L.tuni), c->at<int32_t>(L.tuni_next),
+                                                      (uint32_t)p.T);
   mark(c, "propagate");
   k_propagate<DIM, false><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc, nullptr, nullptr,
                                                   meta);
@@ -486,11 +525,12 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
   in.off = off;
   mark(c, "likelihood");
   launch_lik<DIM, true, SEP>(c, in, st);
-  mark(c, "normalise");
-  k_norm_part<DIM><<<L.nS, TPB, 0, st>>>(p, tS, off, c->at<double>(L.ll), sout, c->at<double>(L.part));
-  k_norm_comb<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.tfirst), c->at<double>(L.part), desc,
-                                        c->at<double>(L.tgt), c->at<double>(L.est), c->at<int32_t>(L.tflag), meta);
   WeightSrc ws = weight_src(c);
+  mark(c, "normalise");
+  k_norm_part<DIM, true><<<L.nS, TPB, 0, st>>>(p, tS, off, ws, sout, c->at<double>(L.part));
+  k_norm_comb<DIM><<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.tfirst), c->at<double>(L.part), desc,
+                                        c->at<double>(L.tgt), c->at<double>(L.est), c->at<int32_t>(L.tflag), meta,
+                                        nullptr);
   mark(c, "cdf_sum");
   k_cdf_sum<true><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.tile_sum));
   mark(c, "cdf_prefix");
@@ -498,7 +538,8 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
                                     c->at<double>(L.tile_pre));
   mark(c, "resample");
   k_cdf_resample<true><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
-                                             c->at<int32_t>(L.tflag), anc, c->debug ? c->at<double>(L.cdf) : nullptr);
+                                             c->at<int32_t>(L.tflag), anc, c->debug ? c->at<double>(L.cdf) : nullptr,
+                                             c->cfg.neff_threshold, keep ? c->at<int32_t>(L.tuni_next) : nullptr);
   mark(c, "end");
 }
 
@@ -605,6 +646,16 @@ bool valid_act_scales(const float *s) {
   return true;
 }
 
+// Uniform weights for every target (kept-weight mode): the next step starts
+// from the resampled state.
+hipError_t reset_weights(pcsir_ctx *c) {
+  if (!keeps_weights(&c->cfg)) return hipSuccess;
+  const uint32_t T = (uint32_t)c->cfg.n_targets;
+  k_fill_i32<<<(T + TPB - 1) / TPB, TPB, 0, c->stream>>>(c->at<int32_t>(c->L.tuni_next), 1, T);
+  k_fill_i32<<<(T + TPB - 1) / TPB, TPB, 0, c->stream>>>(c->at<int32_t>(c->L.tuni), 1, T);
+  return hipGetLastError();
+}
+
 pcsir_status pull_device_status(pcsir_ctx *c) {
   uint64_t meta[META_N];
   hipError_t e = hipMemcpyAsync(meta, c->at<uint64_t>(c->L.meta), sizeof(meta), hipMemcpyDeviceToHost, c->stream);
@@ -692,6 +743,7 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
     k_identity<<<L.n256, TPB, 0, c->stream>>>(c->at<Tile>(L.tiles256), c->at<uint32_t>(L.off), c->at<uint32_t>(L.anc));
     e = hipGetLastError();
   }
+  if (e == hipSuccess) e = reset_weights(c);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     fprintf(stderr, "pcsir_init: %s\n", hipGetErrorString(e));
@@ -754,8 +806,9 @@ pcsir_status pcsir_get_particles(pcsir_ctx *c, float *dst_dev) {
 
 pcsir_status pcsir_set_particles(pcsir_ctx *c, const float *src_dev) {
   if (!c || !src_dev) return PCSIR_E_INVAL;
-  const hipError_t e = hipMemcpyAsync(c->state(c->cur), src_dev, 4 * (size_t)c->p.D * c->NT, hipMemcpyDeviceToDevice,
-                                      c->stream);
+  hipError_t e = hipMemcpyAsync(c->state(c->cur), src_dev, 4 * (size_t)c->p.D * c->NT, hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e == hipSuccess) e = reset_weights(c);
   c->pending = 0;
   c->stepped = 0;
   return check_hip(c, e, "pcsir_set_particles");
@@ -783,6 +836,7 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *c, int32_t what, void *dst, size_t byte
   // the propagated states of the last step sit in the current buffer
   const float *prop = c->state(c->cur);
   uint64_t B = 0;
+  const bool keep = keeps_weights(&c->cfg);
   if (what >= PCSIR_DUMP_COUNTS && what <= PCSIR_DUMP_BIN_MEAN) {
     uint64_t meta[META_N];
     hipError_t e = hipMemcpyAsync(meta, c->at<uint64_t>(L.meta), sizeof(meta), hipMemcpyDeviceToHost, st);
@@ -822,11 +876,13 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *c, int32_t what, void *dst, size_t byte
       if (c->p.dim == 2)
         k_dbg_bins<2><<<gb, TPB, 0, st>>>(c->p, c->at<uint64_t>(L.meta), c->at<unsigned long long>(L.acc),
                                           c->at<uint32_t>(L.seg_key), c->at<uint32_t>(L.kbase),
-                                          c->at<int32_t>(L.bbox_cur), what, dst);
+                                          c->at<int32_t>(L.bbox_cur), what, dst, keep ? c->at<double>(L.wacc) : nullptr,
+                                          keep ? c->at<int32_t>(L.tuni) : nullptr);
       else
         k_dbg_bins<3><<<gb, TPB, 0, st>>>(c->p, c->at<uint64_t>(L.meta), c->at<unsigned long long>(L.acc),
                                           c->at<uint32_t>(L.seg_key), c->at<uint32_t>(L.kbase),
-                                          c->at<int32_t>(L.bbox_cur), what, dst);
+                                          c->at<int32_t>(L.bbox_cur), what, dst, keep ? c->at<double>(L.wacc) : nullptr,
+                                          keep ? c->at<int32_t>(L.tuni) : nullptr);
       break;
     }
     case PCSIR_DUMP_LOGLIK: {
@@ -845,10 +901,10 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *c, int32_t what, void *dst, size_t byte
       if (!need(8 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
       if (c->last_sir)
         k_dbg_weights<true><<<L.n256, TPB, 0, st>>>(c->at<Tile>(L.tiles256), c->at<uint32_t>(L.off), weight_src(c),
-                                                    (double *)dst);
+                                                    keep ? c->at<int32_t>(L.tuni_next) : nullptr, (double *)dst);
       else
         k_dbg_weights<false><<<L.n256, TPB, 0, st>>>(c->at<Tile>(L.tiles256), c->at<uint32_t>(L.off), weight_src(c),
-                                                     (double *)dst);
+                                                     keep ? c->at<int32_t>(L.tuni_next) : nullptr, (double *)dst);
       break;
     case PCSIR_DUMP_TARGET:
       if (!need(8 * 4 * T)) return fail(c, PCSIR_E_INVAL, "buffer too small");
@@ -862,6 +918,12 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *c, int32_t what, void *dst, size_t byte
     case PCSIR_DUMP_RESAMPLE:
       if (!need(4 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
       e = hipMemcpyAsync(dst, c->at<uint32_t>(L.anc), 4 * NT, hipMemcpyDeviceToDevice, st);
+      break;
+    case PCSIR_DUMP_LOGW:
+      if (!need(8 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      k_dbg_logw<<<L.n256, TPB, 0, st>>>(c->at<Tile>(L.tiles256), c->at<uint32_t>(L.off),
+                                         keep ? c->at<double>(L.lw) : nullptr,
+                                         keep ? c->at<int32_t>(L.tuni_next) : nullptr, (double *)dst);
       break;
     default:
       return fail(c, PCSIR_E_INVAL, "unknown dump");
