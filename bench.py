@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--check", type=float, default=0.01, help="share of dummies checked exactly per frame")
     ap.add_argument("--tol", type=float, default=2.0, help="surrogate fallback threshold (nats)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--neff-threshold", type=float, default=0.5,
+                    help="the extra kept-weight mode: resample when N_eff < this fraction of N (negative: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -154,8 +156,9 @@ def main():
         m = int(round(1.0 / h))
         return (m, m, m if dim == 3 else 1)
 
-    def make(wk, init_state, h, lik, seed_off=500):
-        cfg = Config.from_workload(wk, bins_per_px=bins(h), lik_mode=lik, seed=wk.seed + seed_off)
+    def make(wk, init_state, h, lik, seed_off=500, thr=float("inf")):
+        cfg = Config.from_workload(wk, bins_per_px=bins(h), lik_mode=lik, seed=wk.seed + seed_off,
+                                   neff_threshold=thr)
         return Filter(cfg, init_state)
 
     def frame(k):
@@ -187,10 +190,10 @@ def main():
         initr = torch.from_numpy(synth.initial_particles(wr, trr[0], wr.counts())).to(dev)
         seqs.append((wr, trr, frr, initr))
 
-    def track_rmse(mode_sir, h, lik, params=None, scales=None, stats=None):
+    def track_rmse(mode_sir, h, lik, params=None, scales=None, stats=None, thr=float("inf")):
         out = []
         for wr, trr, frr, initr in seqs:
-            f = make(wr, initr, h, lik)
+            f = make(wr, initr, h, lik, thr=thr)
             if params is not None:
                 f.set_surrogate(params, scales, args.check, args.tol)
             est = np.zeros((Kmatch, T, D))
@@ -267,8 +270,8 @@ def main():
     # ---- 3. timed regions
     tuned = {}
 
-    def timed(sir, h, lik, with_events, autotune=False):
-        f = make(w, init, h, lik)
+    def timed(sir, h, lik, with_events, autotune=False, thr=float("inf")):
+        f = make(w, init, h, lik, thr=thr)
         if lik >= LIK_SURR_BF16:
             f.set_surrogate(params, scales if lik == LIK_SURR_FP8 else None, args.check, args.tol)
         if not sir and "shapes" in tuned:
@@ -315,6 +318,12 @@ def main():
     runs["pcsir_direct"] = timed(False, h_match, LIK_DIRECT, True)
     runs["sir_sep"] = timed(True, h_match, LIK_SEP, True)
     runs["sir_direct"] = timed(True, h_match, LIK_DIRECT, True)
+    thr = args.neff_threshold
+    if thr >= 0:
+        runs["pcsir_sep_thr"] = timed(False, h_match, LIK_SEP, True, thr=thr)
+        if not args.no_match:
+            rmse[f"h={h_match},neff<{thr}N"] = track_rmse(False, h_match, LIK_SEP, thr=thr)
+            log(f"rmse h={h_match} with N_eff threshold {thr}: {rmse[f'h={h_match},neff<{thr}N']:.4f}")
     if params is not None:
         runs["surr_bf16"] = timed(False, h_match, LIK_SURR_BF16, True)
         runs["surr_fp8"] = timed(False, h_match, LIK_SURR_FP8, True)
