@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--neff-threshold", type=float, default=0.5,
                     help="the extra kept-weight mode: resample when N_eff < this fraction of N (negative: skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--large-seqs", type=int, default=20,
+                    help="sequences of the large-object section (0: skip it)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many exact pcSIR steps (--lik) and exit (for rocprofv3)")
@@ -114,6 +116,70 @@ def counter_traffic(workload: str, h: float, likelihood: str, kernel: str):
         return None
     k = rec["per_launch"].get(kernel)
     return None if k is None else round(k["traffic_bytes"], 0)
+
+
+def large_object(args, dev):
+    """The large-object case of Sec. 5: sigma_PSF = 13, a 65 x 65 likelihood
+    support, 12 800 particles per sequence, 50 frames of 512 x 512 (synthetic,
+    seeded). S sequences run batched as S targets with their own frames: an
+    untimed pass tracks every frame from the truth for the RMSE, then the same
+    50 frames are timed (device-synchronised). One sequence alone (the paper's
+    own setting) is timed as well."""
+    import torch
+
+    import synth
+    from paper_1310_5541_amd import Config, Filter
+    S = args.large_seqs
+    w = synth.preset("large-2d-512", T=S, per_target_frames=True)
+    t0 = time.time()
+    tr = synth.truth(w, seed=4242)
+    fr = torch.from_numpy(synth.frames(w, tr, seed=4242)).to(dev)   # [K, S, H, W]
+    init = torch.from_numpy(synth.initial_particles(w, tr[0], w.counts())).to(dev)
+    gen = time.time() - t0
+    K, dim = w.K, w.dim
+    modes = {"sir_direct": (True, 1, LIK_DIRECT), "sir_sep": (True, 1, LIK_SEP),
+             "pcsir_1x1_direct": (False, 1, LIK_DIRECT), "pcsir_1x1_sep": (False, 1, LIK_SEP),
+             "pcsir_2x2_direct": (False, 2, LIK_DIRECT), "pcsir_2x2_sep": (False, 2, LIK_SEP)}
+    out = {}
+    for name, (sir, m, lik) in modes.items():
+        res = {}
+        for seqs in (S, 1):
+            wk = synth.preset("large-2d-512", T=seqs, per_target_frames=True)
+            cfg = Config.from_workload(wk, bins_per_px=(m, m, 1), lik_mode=lik, seed=77)
+            st = init[:, :int(wk.counts().sum())].contiguous()
+            frs = fr[:, :seqs].contiguous()
+            f = Filter(cfg, st)
+            if seqs == S:
+                est = np.zeros((K, seqs, w.D))
+                for k in range(1, K + 1):
+                    f.step(frs[k - 1], k, sir=sir)
+                    est[k - 1] = f.estimate()[0]
+                per_seq = synth.rmse(est, tr[:, :seqs], dim)
+                res["rmse_px"] = round(float(np.mean(per_seq)), 4)
+                res["rmse_px_stderr"] = round(float(np.std(per_seq, ddof=1) / np.sqrt(seqs)), 4)
+                f.set_particles(st)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for k in range(1, K + 1):
+                f.step(frs[k - 1], k, sir=sir)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t1) / K
+            f.close()
+            res["ms_per_frame" if seqs == S else "ms_per_frame_one_sequence"] = round(ms, 4)
+        out[name] = res
+        log(f"large object {name}: {res}")
+    sp = {}
+    for form in ("direct", "sep"):
+        for b in ("1x1", "2x2"):
+            pc, sr = out[f"pcsir_{b}_{form}"], out[f"sir_{form}"]
+            sp[f"pcsir_{b}_{form}"] = {"batched": round(sr["ms_per_frame"] / pc["ms_per_frame"], 2),
+                                       "one_sequence": round(sr["ms_per_frame_one_sequence"] /
+                                                             pc["ms_per_frame_one_sequence"], 2)}
+    return {"sequences": S, "particles_per_sequence": int(w.counts()[0]), "frames": K, "frame": [w.H, w.W],
+            "patch": w.patch, "quad": w.quad, "sigma_psf": w.sigma_psf, "sigma_xi": w.sigma_xi,
+            "input_generation_s": round(gen, 2), "modes": out, "speedup_over_sir": sp,
+            "paper_context": "50-frame sequence with 12 800 particles on one CPU core (Java, FP64): SIR 5 min, "
+                             "pcSIR-1x1 2.3 s, pcSIR-2x2 5.3 s; another machine, context only"}
 
 
 def main():
@@ -437,6 +503,10 @@ def main():
         "cpu_baseline": cpu,
         "input_generation_s": round(gen_s, 2),
     }
+    if args.large_seqs > 0:
+        del frames, init
+        torch.cuda.empty_cache()
+        out["large_object"] = large_object(args, dev)
     print(json.dumps(out))
 
 

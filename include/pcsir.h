@@ -85,7 +85,8 @@ typedef struct {
   int32_t bins_per_px[3];      /* m_x, m_y, m_z in [1, 4096]: cells of edge h = 1/m, edges at
                                   j/m - 1/2, so every pixel is a union of cells (Sec. 4.2:
                                   m = 1 is pcSIR-1x1, m = 2 is pcSIR-2x2). m_z used in 3D only. */
-  int32_t patch;               /* P: side of the likelihood window, odd, 1..63 */
+  int32_t patch;               /* P: side of the likelihood window, odd, 1..127 (65 for the
+                                  large-object support of Sec. 5) */
   int32_t quad;                /* q: midpoint sub-samples per pixel axis, 1..16 */
   int32_t psf;                 /* pcsir_psf; ASTIG3D requires dim == 3 */
   int32_t dummy_mode;          /* pcsir_dummy */

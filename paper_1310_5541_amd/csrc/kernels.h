@@ -1104,10 +1104,10 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
     const float *fr = frame + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
     // SEPARABLE: the 2 P per-axis sums over q sub-samples are spread over the
     // wave, H = 64 / (2P) lanes per sum, each adding every H-th sub-sample; the
-    // sum of (axis, pixel c) ends up in lane (axis P + c) H. With 2P > 64, lanes
-    // below P form both axes' sums of their pixel.
+    // sum of (axis, pixel c) ends up in lane (axis P + c) H. With 2P > 64, lane
+    // j forms both axes' sums of pixel j and, for P > 64, of pixel j + 64.
     const int H = WAVE / (2 * P);  // SEPARABLE only
-    float gxl = 0.0f, gyl = 0.0f;
+    float gxl = 0.0f, gyl = 0.0f, gxh = 0.0f, gyh = 0.0f;
     if (SEP) {
       if (H >= 1) {
         if (lane < 2 * P * H) {
@@ -1122,12 +1122,22 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
         float tot = gxl;
         for (int h = 1; h < H; ++h) tot += __shfl(gxl, (lane + h) & (WAVE - 1), WAVE);
         gxl = tot;
-      } else if (lane < P) {
-        const float cc = (float)(lane - R);
-        for (int a = 0; a < q; ++a) {
-          const float o = sub_offset(a, q);
-          gxl += exp2_neg(scaled_sq((cc + o) - dx, ks.xh, ks.xl));
-          gyl += exp2_neg(scaled_sq((cc + o) - dy, ks.yh, ks.yl));
+      } else {
+        if (lane < P) {
+          const float cc = (float)(lane - R);
+          for (int a = 0; a < q; ++a) {
+            const float o = sub_offset(a, q);
+            gxl += exp2_neg(scaled_sq((cc + o) - dx, ks.xh, ks.xl));
+            gyl += exp2_neg(scaled_sq((cc + o) - dy, ks.yh, ks.yl));
+          }
+        }
+        if (lane + WAVE < P) {
+          const float cc = (float)(lane + WAVE - R);
+          for (int a = 0; a < q; ++a) {
+            const float o = sub_offset(a, q);
+            gxh += exp2_neg(scaled_sq((cc + o) - dx, ks.xh, ks.xl));
+            gyh += exp2_neg(scaled_sq((cc + o) - dy, ks.yh, ks.yl));
+          }
         }
       }
     }
@@ -1149,8 +1159,20 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       float g = 0.0f;
       if (SEP) {
         const int pcs = pc < P ? pc : 0, prs = pr < P ? pr : 0;
-        const float gx = H >= 1 ? __shfl(gxl, pcs * H, WAVE) : __shfl(gxl, pcs, WAVE);
-        const float gy = H >= 1 ? __shfl(gxl, (P + prs) * H, WAVE) : __shfl(gyl, prs, WAVE);
+        float gx, gy;
+        if (H >= 1) {
+          gx = __shfl(gxl, pcs * H, WAVE);
+          gy = __shfl(gxl, (P + prs) * H, WAVE);
+        } else if (P <= WAVE) {
+          gx = __shfl(gxl, pcs, WAVE);
+          gy = __shfl(gyl, prs, WAVE);
+        } else {
+          // every lane takes part in all four shuffles; each keeps the slot of its pixel
+          const float xa = __shfl(gxl, pcs & (WAVE - 1), WAVE), xb = __shfl(gxh, pcs & (WAVE - 1), WAVE);
+          const float ya = __shfl(gyl, prs & (WAVE - 1), WAVE), yb = __shfl(gyh, prs & (WAVE - 1), WAVE);
+          gx = pcs < WAVE ? xa : xb;
+          gy = prs < WAVE ? ya : yb;
+        }
         g = gx * gy;
       } else if (pix < P2) {
         const float cc = (float)(pc - R), rr = (float)(pr - R);

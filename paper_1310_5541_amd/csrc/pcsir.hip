@@ -59,7 +59,7 @@ bool valid_config(const pcsir_config *c, std::string *why) {
   }
   for (int a = 0; a < c->dim; ++a)
     if (c->bins_per_px[a] < 1 || c->bins_per_px[a] > 4096) return bad("bins_per_px must lie in [1, 4096]");
-  if (c->patch < 1 || c->patch > 63 || (c->patch % 2) == 0) return bad("patch must be odd and in [1, 63]");
+  if (c->patch < 1 || c->patch > 127 || (c->patch % 2) == 0) return bad("patch must be odd and in [1, 127]");
   if (c->quad < 1 || c->quad > 16) return bad("quad must lie in [1, 16]");
   if (c->psf != PCSIR_PSF_GAUSS2D && c->psf != PCSIR_PSF_ASTIG3D) return bad("unknown psf");
   if (c->psf == PCSIR_PSF_ASTIG3D && c->dim != 3) return bad("astigmatic PSF needs dim == 3");

@@ -70,6 +70,11 @@ class Workload:
         return np.floor(10.0 ** rng.uniform(self.n_lo, self.n_hi, size=self.T)).astype(np.int64)
 
 
+# Peak intensity above a background of 10 at SNR 2, with the Poisson SNR read
+# as I0 / sqrt(I0 + I_bg): I0 = 2 + sqrt(4 + 4 I_bg).
+SNR2_I0 = 2.0 + math.sqrt(44.0)
+
+
 def preset(name: str, **kw) -> Workload:
     """Named workloads. 'single-2d-64' .. '3d-astig' follow the configurations the
     benchmark is quoted on; 'tiny' is a fast case for tests."""
@@ -91,6 +96,13 @@ def preset(name: str, **kw) -> Workload:
         "train-3d": Workload(name="train-3d", dim=3, H=256, W=256, K=20, T=40, n=(50_000,), m=(4, 4, 4), patch=15,
                              quad=8, i0=(20.0, 100.0), speed=(2.0, 4.0),
                              proc_sigma=(0.5, 0.5, 0.5, 0.1, 0.1, 0.1, 2.0), per_target_frames=True, seed=8000),
+        # large objects (Sec. 5): sigma_PSF = 13, a 65 x 65 likelihood support,
+        # speeds U[2, 7], SNR 2 (peak I0 with I0 / sqrt(I0 + I_bg) = 2), 12 800
+        # particles per sequence; sigma_xi = 30 as for the large-object kernels
+        # of the likelihood figure; the pixel value is point-sampled (q = 1)
+        "large-2d-512": Workload(name="large-2d-512", H=512, W=512, K=50, n=(12_800,), m=(1, 1, 1), patch=65,
+                                 quad=1, sigma_psf=13.0, i_bg=10.0, i0=(SNR2_I0, SNR2_I0), sigma_xi=30.0,
+                                 speed=(2.0, 7.0), mid_lo=128.0, mid_hi=384.0),
         "3d-astig": Workload(name="3d-astig", dim=3, H=256, W=256, K=20, T=200, n=(50_000,), m=(4, 4, 4),
                              patch=15, quad=8, i0=(20.0, 100.0), speed=(2.0, 4.0),
                              proc_sigma=(0.5, 0.5, 0.5, 0.1, 0.1, 0.1, 2.0), per_target_frames=True),

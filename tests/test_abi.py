@@ -64,7 +64,7 @@ def test_workspace_bytes_and_validation(L):
     b2 = L.pcsir_workspace_bytes(C.byref(c2))
     assert 50 * b < b2 < 150 * b
     bad = [dict(dim=4), dict(n_particles=(0,)), dict(bins_per_px=(0, 2, 1)), dict(bins_per_px=(5000, 2, 1)),
-           dict(patch=10), dict(patch=65), dict(quad=0), dict(quad=17), dict(psf=1), dict(lik_mode=7),
+           dict(patch=10), dict(patch=129), dict(quad=0), dict(quad=17), dict(psf=1), dict(lik_mode=7),
            dict(sigma_xi=0.0), dict(sigma_psf=-1.0), dict(frame_h=0), dict(dummy_mode=3),
            dict(proc_sigma=(-1, 0, 0, 0, 0))]
     for kw in bad:
