@@ -219,3 +219,50 @@ def rmse(est: np.ndarray, tr: np.ndarray, dim: int) -> np.ndarray:
     """Per-target tracking RMSE over frames 1..K of the positions: est [K, T, D], truth [K+1, T, D]."""
     d = est[:, :, :dim] - tr[1:, :, :dim]
     return np.sqrt(np.mean(np.sum(d * d, axis=2), axis=0))
+
+
+# ---------------------------------------------------------------- pseudo-tracking
+# Sec. 5.3's convergence experiment: the prior p(x_k | Z^{k-1}) is fixed (a
+# uniform square of 3 or 5 pixels, or an isotropic Gaussian of sigma 0.5 or
+# 0.8 px), the object is one spot of sigma_PSF = 1.16 at SNR 2, and the
+# likelihood has sigma_xi = 20. Readings: the prior is centred on the object;
+# one noisy frame is drawn and kept, and the repetitions differ in the particle
+# draws only, so the RMSE over repetitions measures the estimator's error
+# against the exact posterior mean of that frame.
+PSEUDO_PRIORS = (("uniform", 3.0), ("uniform", 5.0), ("gauss", 0.5), ("gauss", 0.8))
+
+
+def pseudo_workload(reps: int, n: int, m: int = 1) -> Workload:
+    """Model constants of the pseudo-tracking experiment: `reps` repetitions of
+    n particles as targets sharing one 32 x 32 frame; no motion (velocity 0 and
+    no process noise, so a step weighs the prior draws as they are)."""
+    return Workload(name="pseudo-2d-32", H=32, W=32, K=1, T=reps, n=(n,), m=(m, m, 1), patch=9, quad=2,
+                    sigma_psf=1.16, i_bg=10.0, i0=(SNR2_I0, SNR2_I0), sigma_xi=20.0,
+                    proc_sigma=(0.0, 0.0, 0.0, 0.0, 0.0))
+
+
+def pseudo_frame(seed: int = 11) -> tuple:
+    """(frame [32, 32] float32, object position (x, y)): the object uniformly
+    placed in the central pixel's area, Poisson noise."""
+    w = pseudo_workload(1, 1)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xy = np.array([15.0, 15.0]) + rng.uniform(-0.5, 0.5, 2)
+    st = np.array([[xy[0], xy[1], 0.0, 0.0, w.i0[0]]])
+    mu = expected_image(w, st, w.H, w.W)
+    return rng.poisson(mu).astype(np.float32), xy
+
+
+def pseudo_particles(kind: str, par: float, centre, reps: int, n: int, seed: int) -> np.ndarray:
+    """Prior draws [5, reps * n] float32 (repetition after repetition): positions
+    uniform on the par x par square or Gaussian with sigma par around centre,
+    velocity 0, intensity the object's."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    N = reps * n
+    out = np.zeros((5, N), np.float64)
+    for a in range(2):
+        if kind == "uniform":
+            out[a] = centre[a] + rng.uniform(-par / 2.0, par / 2.0, N)
+        else:
+            out[a] = centre[a] + par * rng.standard_normal(N)
+    out[4] = SNR2_I0
+    return out.astype(np.float32)
