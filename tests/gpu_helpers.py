@@ -15,13 +15,10 @@ Tolerances (derived in the design notes from the FP32 arithmetic of the path):
                  error grows with S (about 2.5 FP32 ulp of l). Near the weight
                  maximum |l| is small and the bound stays below the 1e-5 that
                  the weights allow; far from it the weights are negligible.
-  weights        |dw| <= 1e-5 w + 1e-10 max w; for windows that hold spots the
-                 one-spot model lacks (|l| of several hundred), the FP32 sum of
-                 squares has a relative precision of a few 1e-8, and the bound
-                 becomes (1e-5 + 4e-8 |l|) w + 1e-10 max w. The 1e-5 is for
-                 windows up to 15 x 15: each window pixel adds an independent
-                 rounding error of the model value to l, so for a P x P window
-                 it scales as P / 15 (w_rel)
+  weights        inherited from l: w_i = exp(l_i - M) / S, so to first order
+                 dw_i / w_i = dl_i - sum_j w_j dl_j, and with the bound tol(l) of
+                 the log-likelihood row, |dw_i| <= 1.01 (tol(l_i) + sum_j w_j
+                 tol(l_j)) w_i + 1e-12 max w
   estimates      rel 1e-5 (abs 1e-5); N_eff rel 1e-5
   resampling u   bit-exact
   s(j)           bit-exact except where the oracle's cumulative weight lies
@@ -59,8 +56,13 @@ def exempt_mask(cdf, s, theta, eps):
     return (np.abs(hi - theta) <= eps) | (np.abs(lo - theta) <= eps)
 
 
-def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, w_cond=0.0, surrogate=None,
-                    on_filter=None):
+def weight_bound(ll_of_particle, wo):
+    """Largest |w_gpu - w_oracle| per particle that the log-likelihood tolerance allows."""
+    tl = LL_ATOL + LL_RTOL * np.abs(ll_of_particle)
+    return 1.01 * (tl + np.sum(wo * tl)) * wo + 1e-12 * wo.max()
+
+
+def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, surrogate=None, on_filter=None):
     """cloud: [D, NT] float32 (host); frames: [H, W] or [T, H, W] float32 (host).
     Runs one GPU step from `cloud` and checks every stage against the oracle.
     surrogate: (params, act_scale, check_fraction, tol) installed before the step
@@ -72,7 +74,6 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, w_
     from paper_1310_5541_amd import Filter
 
     T, D, dim = cfg.T, cfg.D, cfg.dim
-    w_rel = 1e-5 * max(1.0, cfg.patch / 15.0)
     n = np.asarray(cfg.n_particles, dtype=np.int64)
     off = np.concatenate([[0], np.cumsum(n)])
     mdl = oracle_model(cfg)
@@ -145,9 +146,7 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, w_
         dev["ll"] = max(dev["ll"], float(d_ll.max()))
         dev["ll_rel"] = max(dev.get("ll_rel", 0.0), float(np.max(d_ll / np.maximum(np.abs(ll_o), 1.0))))
         wg, wo = w_gpu[a:b], r["w"]
-        # w_cond > 0 widens the bound by the FP32 conditioning of a large sum of
-        # squares (|l| in the hundreds: a window holding a spot the model lacks)
-        e_w = np.abs(wg - wo) - ((w_rel + w_cond * np.abs(r["ll"][r["bin_of"]])) * wo + 1e-10 * wo.max())
+        e_w = np.abs(wg - wo) - weight_bound(r["ll"][r["bin_of"]], wo)
         worst = int(np.argmax(e_w))
         assert np.all(e_w <= 0), (f"target {t}: weights off, worst excess {e_w[worst]} at w = {wo[worst]} "
                                   f"(GPU {wg[worst]}), l = {r['ll'][r['bin_of'][worst]]}, max w = {wo.max()}")
