@@ -97,11 +97,13 @@ def lib():
             build()
         L = C.CDLL(_LIB_PATH)
         L.orc_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_uniform.argtypes = [C.c_uint64, C.c_int32]
+        L.orc_uniform.argtypes = [C.c_uint32]
         L.orc_uniform.restype = C.c_double
         L.orc_normals.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p]
         L.orc_resample_u.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
         L.orc_resample_u.restype = C.c_double
+        L.orc_check_u.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64]
+        L.orc_check_u.restype = C.c_double
         L.orc_bin_key.argtypes = [C.c_float, C.c_int32]
         L.orc_bin_key.restype = C.c_int32
         L.orc_propagate.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int64]
@@ -129,15 +131,16 @@ def _p(a: np.ndarray):
 
 
 def philox(ctr, key) -> np.ndarray:
-    c = np.asarray(ctr, dtype=np.uint64)
-    k = np.asarray(key, dtype=np.uint64)
-    out = np.zeros(4, dtype=np.uint64)
+    """Philox4x32-10 block: four 32-bit counter words, two key words."""
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
     lib().orc_philox(_p(c), _p(k), _p(out))
     return out
 
 
-def uniform(word: int, low_field: bool = False) -> float:
-    return lib().orc_uniform(C.c_uint64(int(word)), 1 if low_field else 0)
+def uniform(word: int) -> float:
+    return lib().orc_uniform(C.c_uint32(int(word)))
 
 
 def normals(seed: int, i: int, k: int, t: int) -> np.ndarray:
@@ -148,6 +151,10 @@ def normals(seed: int, i: int, k: int, t: int) -> np.ndarray:
 
 def resample_u(seed: int, k: int, t: int) -> float:
     return lib().orc_resample_u(seed, k, t)
+
+
+def check_u(seed: int, dummy: int, k: int, t: int) -> float:
+    return lib().orc_check_u(seed, dummy, k, t)
 
 
 def bin_key(x, m: int) -> np.ndarray:

@@ -29,29 +29,27 @@
 
 namespace {
 
-/* ---------------- Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) ------
+/* ---------------- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ------
  * Counter-based generator. Not from the paper (the paper names no RNG); it
  * is used so that the oracle and the GPU draw the same uniforms from the
- * same (counter, key). Round: two 64x64->128 products of words 0 and 2 with
+ * same (counter, key). Round: two 32x32->64 products of words 0 and 2 with
  * the published multipliers, words permuted and xored with the key; the key
  * is bumped by the published Weyl constants between rounds. */
-const uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ULL;
-const uint64_t PHILOX_M1 = 0xCA5A826395121157ULL;
-const uint64_t PHILOX_W0 = 0x9E3779B97F4A7C15ULL;
-const uint64_t PHILOX_W1 = 0xBB67AE8584CAA73BULL;
+const uint32_t PHILOX_M0 = 0xD2511F53u;
+const uint32_t PHILOX_M1 = 0xCD9E8D57u;
+const uint32_t PHILOX_W0 = 0x9E3779B9u;
+const uint32_t PHILOX_W1 = 0xBB67AE85u;
 
-void philox4x64_10(const uint64_t in_ctr[4], const uint64_t in_key[2], uint64_t out[4]) {
-  uint64_t c0 = in_ctr[0], c1 = in_ctr[1], c2 = in_ctr[2], c3 = in_ctr[3];
-  uint64_t k0 = in_key[0], k1 = in_key[1];
+void philox4x32_10(const uint32_t in_ctr[4], const uint32_t in_key[2], uint32_t out[4]) {
+  uint32_t c0 = in_ctr[0], c1 = in_ctr[1], c2 = in_ctr[2], c3 = in_ctr[3];
+  uint32_t k0 = in_key[0], k1 = in_key[1];
   for (int round = 0; round < 10; ++round) {
-    unsigned __int128 p0 = (unsigned __int128)PHILOX_M0 * c0;
-    unsigned __int128 p1 = (unsigned __int128)PHILOX_M1 * c2;
-    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
-    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
-    uint64_t n0 = hi1 ^ c1 ^ k0;
-    uint64_t n1 = lo1;
-    uint64_t n2 = hi0 ^ c3 ^ k1;
-    uint64_t n3 = lo0;
+    const uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
+    const uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n1 = (uint32_t)p1;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n3 = (uint32_t)p0;
     c0 = n0; c1 = n1; c2 = n2; c3 = n3;
     k0 += PHILOX_W0;
     k1 += PHILOX_W1;
@@ -59,12 +57,23 @@ void philox4x64_10(const uint64_t in_ctr[4], const uint64_t in_key[2], uint64_t 
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Uniforms on (0,1) from one 64-bit word: two disjoint 23-bit fields
- * (bits 41..63 and bits 9..31), each plus one half, scaled by 2^-23. The
- * values are dyadic rationals with 24 significant bits, so they are exact in
- * binary32 as well as binary64. */
-double uniform_hi(uint64_t w) { return ((double)(w >> 41) + 0.5) * 0x1p-23; }
-double uniform_lo(uint64_t w) { return ((double)((w >> 9) & 0x7FFFFFULL) + 0.5) * 0x1p-23; }
+/* The key of every draw: the 64-bit seed as (low word, high word). A counter
+ * word that holds the frame index k takes k modulo 2^32. */
+void philox_draw(uint64_t seed, uint32_t c0, uint64_t k, uint32_t c2, uint32_t c3, uint32_t out[4]) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  const uint32_t ctr[4] = {c0, (uint32_t)k, c2, c3};
+  philox4x32_10(ctr, key, out);
+}
+
+/* Uniform on (0,1) from one word: its top 23 bits plus one half, scaled by
+ * 2^-23. The values are dyadic rationals with 24 significant bits, so they
+ * are exact in binary32 as well as binary64. */
+double uniform23(uint32_t w) { return ((double)(w >> 9) + 0.5) * 0x1p-23; }
+
+/* [0, 1) with 53 random bits from two words: (w1 2^32 + w0) >> 11, times 2^-53. */
+double uniform53(uint32_t w0, uint32_t w1) {
+  return (double)((((uint64_t)w1 << 32) | (uint64_t)w0) >> 11) * 0x1p-53;
+}
 
 const double TWO_PI = 6.283185307179586476925286766559;
 
@@ -103,39 +112,41 @@ typedef struct {
   double *est;        /* [D] posterior-mean estimate sum_i w_i x_i */
 } orc_weigh_out;
 
-void orc_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
-  philox4x64_10(ctr, key, out);
-}
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) { philox4x32_10(ctr, key, out); }
 
-double orc_uniform(uint64_t w, int32_t low_field) { return low_field ? uniform_lo(w) : uniform_hi(w); }
+double orc_uniform(uint32_t w) { return uniform23(w); }
 
-/* Eight standard normals for particle i of target t at frame k: one Philox
- * block with counter (i, k, t, 0) and key (seed, 0); word p gives the pair
- * (u1, u2) = (high field, low field), mapped by Box-Muller,
- * (z_2p, z_2p+1) = sqrt(-2 ln u1) * (cos 2 pi u2, sin 2 pi u2). */
+/* Eight standard normals for particle i of target t at frame k: Philox
+ * blocks with counters (i, k, t, 0) and (i, k, t, 1); pair p takes
+ * (u1, u2) from words 2p and 2p + 1 of their eight words and maps them by
+ * Box-Muller, (z_2p, z_2p+1) = sqrt(-2 ln u1) * (cos 2 pi u2, sin 2 pi u2). */
 void orc_normals(uint64_t seed, uint64_t i, uint64_t k, uint64_t t, double z[8]) {
-  const uint64_t key[2] = {seed, 0};
-  const uint64_t ctr[4] = {i, k, t, 0};
-  uint64_t out[4];
-  philox4x64_10(ctr, key, out);
+  uint32_t w[8];
+  philox_draw(seed, (uint32_t)i, k, (uint32_t)t, 0, w);
+  philox_draw(seed, (uint32_t)i, k, (uint32_t)t, 1, w + 4);
   for (int p = 0; p < 4; ++p) {
-    double u1 = uniform_hi(out[p]);
-    double u2 = uniform_lo(out[p]);
+    double u1 = uniform23(w[2 * p]);
+    double u2 = uniform23(w[2 * p + 1]);
     double r = std::sqrt(-2.0 * std::log(u1));
     z[2 * p] = r * std::cos(TWO_PI * u2);
     z[2 * p + 1] = r * std::sin(TWO_PI * u2);
   }
 }
 
-/* The one uniform of systematic resampling for target t at frame k:
- * word 0 of the Philox block with counter (0, k, t, 1), as (w >> 11) 2^-53,
- * a value in [0, 1). */
+/* The one uniform of systematic resampling for target t at frame k: words 0
+ * and 1 of the Philox block with counter (0, k, t, 2), a value in [0, 1). */
 double orc_resample_u(uint64_t seed, uint64_t k, uint64_t t) {
-  const uint64_t key[2] = {seed, 0};
-  const uint64_t ctr[4] = {0, k, t, 1};
-  uint64_t out[4];
-  philox4x64_10(ctr, key, out);
-  return (double)(out[0] >> 11) * 0x1p-53;
+  uint32_t w[4];
+  philox_draw(seed, 0, k, (uint32_t)t, 2, w);
+  return uniform53(w[0], w[1]);
+}
+
+/* The draw that picks a dummy for the surrogate's exact check: words 0 and 1
+ * of the block with counter (dummy, k, t, 3). */
+double orc_check_u(uint64_t seed, uint64_t dummy, uint64_t k, uint64_t t) {
+  uint32_t w[4];
+  philox_draw(seed, (uint32_t)dummy, k, (uint32_t)t, 3, w);
+  return uniform53(w[0], w[1]);
 }
 
 /* Cell index of coordinate x on the grid of "B bins of equal size" (Alg.

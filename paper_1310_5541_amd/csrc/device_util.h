@@ -9,24 +9,25 @@ namespace pcsir {
 
 constexpr int WAVE = 64;
 
-// ---------------------------------------------------------------- Philox4x64-10
+// ---------------------------------------------------------------- Philox4x32-10
 // Counter-based generator of Salmon et al. (SC'11): ten rounds of two
-// 64x64->128 products (multipliers 0xD2E7470EE14C6C93, 0xCA5A826395121157)
-// with a Weyl key schedule (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B).
-struct U64x4 {
-  uint64_t v[4];
+// 32x32->64 products (multipliers 0xD2511F53, 0xCD9E8D57) with a Weyl key
+// schedule (0x9E3779B9, 0xBB67AE85). The 32-bit variant runs on the native
+// 32-bit multiplier; the 64-bit one needs four partial products per multiply.
+struct U32x4 {
+  uint32_t v[4];
 };
 
-__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                               uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+__device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                               uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint64_t lo0 = c0 * M0, hi0 = __umul64hi(c0, M0);
-    const uint64_t lo1 = c2 * M1, hi1 = __umul64hi(c2, M1);
-    const uint64_t n0 = hi1 ^ c1 ^ k0;
-    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    const uint32_t lo0 = c0 * M0, hi0 = __umulhi(c0, M0);
+    const uint32_t lo1 = c2 * M1, hi1 = __umulhi(c2, M1);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
     c1 = lo1;
     c2 = n2;
@@ -34,7 +35,7 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
     k0 += W0;
     k1 += W1;
   }
-  U64x4 o;
+  U32x4 o;
   o.v[0] = c0;
   o.v[1] = c1;
   o.v[2] = c2;
@@ -42,22 +43,38 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   return o;
 }
 
-// Two uniforms on (0,1) from one word: 23-bit fields at bits 41..63 and
-// 9..31, plus one half, times 2^-23. Both are exact in binary32.
-__device__ __forceinline__ float u01_hi(uint64_t w) {
-  return ((float)(uint32_t)(w >> 41) + 0.5f) * 0x1p-23f;
-}
-__device__ __forceinline__ float u01_lo(uint64_t w) {
-  return ((float)((uint32_t)(w >> 9) & 0x7FFFFFu) + 0.5f) * 0x1p-23f;
+// Key of every draw: the 64-bit seed as two words.
+__device__ __forceinline__ uint32_t seed_lo(uint64_t seed) { return (uint32_t)seed; }
+__device__ __forceinline__ uint32_t seed_hi(uint64_t seed) { return (uint32_t)(seed >> 32); }
+
+// A uniform on (0,1) from one word: its top 23 bits plus one half, times
+// 2^-23; exact in binary32.
+__device__ __forceinline__ float u01(uint32_t w) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
+
+// [0, 1) with 53 random bits from two words: (w1 2^32 + w0) >> 11, times 2^-53.
+__device__ __forceinline__ double u01_53(uint32_t w0, uint32_t w1) {
+  return (double)((((uint64_t)w1 << 32) | (uint64_t)w0) >> 11) * 0x1p-53;
 }
 
-// Eight N(0,1) draws (binary32 Box-Muller) for counter (i, k, t, 0), key (seed, 0).
-__device__ __forceinline__ void normals8(uint64_t seed, uint64_t i, uint64_t k, uint64_t t, float z[8]) {
-  const U64x4 b = philox4x64_10(i, k, t, 0, seed, 0);
+// NPAIRS pairs of N(0,1) draws (binary32 Box-Muller) for particle i of target
+// t at frame k: blocks with counters (i, k, t, 0) and (i, k, t, 1); pair p
+// takes (u1, u2) from words 2p and 2p + 1 of the eight. k enters modulo 2^32.
+template <int NPAIRS>
+__device__ __forceinline__ void normal_pairs(uint64_t seed, uint32_t i, uint64_t k, uint32_t t, float *z) {
+  static_assert(NPAIRS >= 1 && NPAIRS <= 4, "two blocks give at most four pairs");
+  uint32_t w[8];
+  const U32x4 a = philox4x32_10(i, (uint32_t)k, t, 0u, seed_lo(seed), seed_hi(seed));
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const float u1 = u01_hi(b.v[p]);
-    const float u2 = u01_lo(b.v[p]);
+  for (int q = 0; q < 4; ++q) w[q] = a.v[q];
+  if (NPAIRS > 2) {
+    const U32x4 b = philox4x32_10(i, (uint32_t)k, t, 1u, seed_lo(seed), seed_hi(seed));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[4 + q] = b.v[q];
+  }
+#pragma unroll
+  for (int p = 0; p < NPAIRS; ++p) {
+    const float u1 = u01(w[2 * p]);
+    const float u2 = u01(w[2 * p + 1]);
     // hardware log2, and sine / cosine of 2 pi u2 (the instructions take the
     // angle in turns); about one ulp each, far inside the tolerance of the
     // propagated states
@@ -67,11 +84,11 @@ __device__ __forceinline__ void normals8(uint64_t seed, uint64_t i, uint64_t k, 
   }
 }
 
-// Resampling uniform of target t at frame k: counter (0, k, t, 1), word 0,
-// (w >> 11) * 2^-53 in [0, 1).
+// Resampling uniform of target t at frame k: counter (0, k, t, 2), words 0
+// and 1, in [0, 1).
 __device__ __forceinline__ double resample_uniform(uint64_t seed, uint64_t k, uint64_t t) {
-  const U64x4 b = philox4x64_10(0, k, t, 1, seed, 0);
-  return (double)(b.v[0] >> 11) * 0x1p-53;
+  const U32x4 b = philox4x32_10(0u, (uint32_t)k, (uint32_t)t, 2u, seed_lo(seed), seed_hi(seed));
+  return u01_53(b.v[0], b.v[1]);
 }
 
 // ---------------------------------------------------------------- exact cell index

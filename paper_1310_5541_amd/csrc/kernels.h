@@ -110,8 +110,8 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
     float x[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) x[d] = sin[(size_t)d * p.NT + src];
-    float z[8];
-    normals8(p.seed, i, (uint64_t)desc->k, (uint64_t)t, z);
+    float z[2 * ((D + 1) / 2)];
+    normal_pairs<(D + 1) / 2>(p.seed, i, (uint64_t)desc->k, (uint32_t)t, z);
     float nx[D];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) nx[a] = fmaf(p.proc_sigma[a], z[a], x[a] + x[DIM + a]);
@@ -975,11 +975,11 @@ constexpr double SSE_CLAMP = 1.0e9;     // a squared error counts at most this m
 // weight relative to the target's best dummy is under e^-40 whatever the error.
 constexpr double SURR_RELEVANT_NATS = 40.0;
 
-// A dummy is checked when the uniform of counter (dummy, k, target, 2) is
+// A dummy is checked when the uniform of counter (dummy, k, target, 3) is
 // below the check fraction.
 __device__ __forceinline__ bool surr_checked(uint64_t seed, uint32_t e, int64_t k, int t, float fraction) {
-  const U64x4 b = philox4x64_10(e, (uint64_t)k, (uint64_t)t, 2, seed, 0);
-  return (double)(b.v[0] >> 11) * 0x1p-53 < (double)fraction;
+  const U32x4 b = philox4x32_10(e, (uint32_t)k, (uint32_t)t, 3u, seed_lo(seed), seed_hi(seed));
+  return u01_53(b.v[0], b.v[1]) < (double)fraction;
 }
 
 // Append e to a list where `take` holds: one ballot and one atomic per wave.

@@ -320,9 +320,8 @@ def test_surrogate_partial_check_follows_the_draw():
     feats, A, ll_o, tgt = _oracle_rows(cfg, fr[1], prop, off)
     fo = SurrogateNet(pt).rows(X.contiguous()).cpu().numpy().astype(np.float64)
     surr = 100.0 * fo - A
-    # the draw: uniform of counter (dummy, k, target, 2) below the fraction
-    pick = np.array([(int(oracle.philox([e, k, int(tgt[e]), 2], [cfg.seed, 0])[0]) >> 11) * 2.0 ** -53
-                     < float(np.float32(frac)) for e in range(B)])
+    # the draw: uniform of counter (dummy, k, target, 3) below the fraction
+    pick = np.array([oracle.check_u(cfg.seed, e, k, int(tgt[e])) < float(np.float32(frac)) for e in range(B)])
     # a picked dummy fails the check (tolerance 0) when it is relevant: its exact or
     # surrogate value within 40 nats of its target's largest surrogate value
     top = np.array([surr[tgt == t].max() for t in range(len(counts))])

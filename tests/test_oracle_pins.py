@@ -1,7 +1,7 @@
 """Pins of the FP64 oracle against what the paper and mathematics fix (CPU only).
 
-Each test checks the oracle against something other than itself: a library
-generator (numpy's Philox), exact rational arithmetic, closed forms (Poisson
+Each test checks the oracle against something other than itself: the
+generator's published known-answer vectors, exact rational arithmetic, closed forms (Poisson
 summation of Gaussian sums, constant frames), brute force on small inputs at 50
 digits, invariants stated by the paper (one particle per cell recovers SIR,
 Sec. 4.2; all members of a bin share the dummy's weight, Alg. pcSIR), and the
@@ -19,34 +19,29 @@ import synth
 # --------------------------------------------------------------------------- RNG
 
 
-def _numpy_philox_block(ctr, key):
-    """numpy's Philox starts by incrementing its counter, so its first block is at ctr."""
-    c = int(ctr[0]) | (int(ctr[1]) << 64) | (int(ctr[2]) << 128) | (int(ctr[3]) << 192)
-    c -= 1
-    words = [(c >> (64 * i)) & (2**64 - 1) for i in range(4)]
-    g = np.random.Philox(counter=np.array(words, dtype=np.uint64),
-                         key=np.array([int(key[0]), int(key[1])], dtype=np.uint64))
-    return g.random_raw(4)
+# Known-answer vectors published with the generator (Salmon et al., SC'11,
+# Random123 distribution) for Philox4x32 with 10 rounds: (counter, key, output).
+PHILOX4X32_10_KAT = [
+    ((0x00000000, 0x00000000, 0x00000000, 0x00000000), (0x00000000, 0x00000000),
+     (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+    ((0xffffffff, 0xffffffff, 0xffffffff, 0xffffffff), (0xffffffff, 0xffffffff),
+     (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+    ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+]
 
 
-@pytest.mark.parametrize("ctr,key", [
-    ((1, 0, 0, 0), (123, 456)),
-    ((0, 7, 3, 1), (2**64 - 1, 0)),
-    ((12345, 99, 999, 0), (42, 0)),
-    ((2**63 + 5, 2**40, 17, 2), (0xDEADBEEF, 0)),
-])
-def test_philox_matches_numpy(orc, ctr, key):
-    assert np.array_equal(orc.philox(ctr, key), _numpy_philox_block(ctr, key))
+@pytest.mark.parametrize("ctr,key,want", PHILOX4X32_10_KAT)
+def test_philox_known_answers(orc, ctr, key, want):
+    assert [int(v) for v in orc.philox(ctr, key)] == list(want)
 
 
 def test_uniform_open_interval_and_exact_in_binary32(orc):
-    for wd in (0, 1, 2**41 - 1, 2**41, 2**63, 2**64 - 1, 0x0123456789ABCDEF, 0xFFFFFE00, 0x1FF):
-        for low in (False, True):
-            u = orc.uniform(wd, low)
-            assert 0.0 < u < 1.0
-            assert float(np.float32(u)) == u  # 24 significant bits at most
-            field = ((wd >> 9) & (2**23 - 1)) if low else (wd >> 41)
-            assert u == float(Fraction(2 * field + 1, 2**24))
+    for wd in (0, 1, 2**9 - 1, 2**9, 2**31, 2**32 - 1, 0x01234567, 0xFFFFFE00, 0x1FF):
+        u = orc.uniform(wd)
+        assert 0.0 < u < 1.0
+        assert float(np.float32(u)) == u  # 24 significant bits at most
+        assert u == float(Fraction(2 * (wd >> 9) + 1, 2**24))
 
 
 def test_box_muller_invariant_and_moments(orc):
@@ -55,10 +50,10 @@ def test_box_muller_invariant_and_moments(orc):
     # and atan2(z1, z0) = 2 pi u2 (mod 2 pi)
     for i in range(50):
         z = orc.normals(seed, i, 3, 1)
-        blk = orc.philox((i, 3, 1, 0), (seed, 0))
+        words = np.concatenate([orc.philox((i, 3, 1, 0), (seed, 0)), orc.philox((i, 3, 1, 1), (seed, 0))])
         for p in range(4):
-            u1 = orc.uniform(int(blk[p]), False)
-            u2 = orc.uniform(int(blk[p]), True)
+            u1 = orc.uniform(int(words[2 * p]))
+            u2 = orc.uniform(int(words[2 * p + 1]))
             assert z[2 * p] ** 2 + z[2 * p + 1] ** 2 == pytest.approx(-2.0 * math.log(u1), rel=1e-12)
             ang = math.atan2(z[2 * p + 1], z[2 * p]) % (2 * math.pi)
             assert min(abs(ang - 2 * math.pi * u2), 2 * math.pi - abs(ang - 2 * math.pi * u2)) < 1e-9
@@ -398,9 +393,14 @@ def test_systematic_resampling_marginals(orc):
     assert np.all(np.abs(freq - wts) < 4 * np.sqrt(wts / (R * N)) + 1e-4)
 
 
-def test_resample_uniform_counter(orc):
-    blk = orc.philox((0, 4, 9, 1), (31, 0))
-    assert orc.resample_u(31, 4, 9) == float(Fraction(int(blk[0]) >> 11, 2**53))
+def test_resample_and_check_uniform_counters(orc):
+    seed = (7 << 32) | 31   # both key words in use
+    blk = orc.philox((0, 4, 9, 2), (31, 7))
+    assert orc.resample_u(seed, 4, 9) == float(Fraction(((int(blk[1]) << 32) | int(blk[0])) >> 11, 2**53))
+    blk = orc.philox((12, 4, 9, 3), (31, 7))
+    assert orc.check_u(seed, 12, 4, 9) == float(Fraction(((int(blk[1]) << 32) | int(blk[0])) >> 11, 2**53))
+    # the frame index enters modulo 2^32
+    assert orc.resample_u(seed, 4 + 2**32, 9) == orc.resample_u(seed, 4, 9)
 
 
 # --------------------------------------------------------------------------- bin size
