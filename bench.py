@@ -90,7 +90,8 @@ def bytes_per_particle(D: int) -> dict:
         "seg_mark": 4,                     # per list entry: sorted key in
         "bin_sums": 4 * D + 4,             # state in (key recomputed), bin number out
         "cdf_sum": 4,                      # bin number in
-        "resample": 4 + 4,                 # bin number in, parent index out
+        "cdf_scan": 4 + 8,                 # bin number in, cumulative weight out
+        "resample": 8 + 4,                 # cumulative weight in, parent index out
     }
 
 

@@ -66,14 +66,17 @@ __global__ void k_set_desc(StepDesc *__restrict__ d, const float *frame, int64_t
 }
 
 struct Tile {
-  int32_t t;   // target
-  uint32_t i0; // first particle of the tile, index within the target
+  int32_t t;     // target
+  uint32_t i0;   // first particle of the tile, index within the target
+  uint32_t base; // the target's first particle in storage
+  uint32_t n;    // the target's particle count
 };
 
 // Bin-sum work item: up to BIN_TILES * SCAN_TILE consecutive particles of one target.
 struct BinTile {
   int32_t t;
   uint32_t i0, i1;  // particles [i0, i1) of target t
+  uint32_t base;    // the target's first particle in storage
 };
 
 // ---------------------------------------------------------------- propagation
@@ -94,8 +97,8 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
   constexpr int D = 2 * DIM + 1;
   const Tile tl = tiles[blockIdx.x];
   const int t = tl.t;
-  const uint32_t base = off[t];
-  const uint32_t n = off[t + 1] - base;
+  const uint32_t base = tl.base;
+  const uint32_t n = tl.n;
   const uint32_t i = tl.i0 + threadIdx.x;
   const bool valid = i < n;
   int32_t kmin[DIM], kmax[DIM];
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restric
   __shared__ uint32_t lds[TPB / WAVE];
   const BinTile tl = tiles[blockIdx.x];
   const int t = tl.t;
-  const uint32_t base = off[t];
+  const uint32_t base = tl.base;
   int32_t bb[6];
 #pragma unroll
   for (int a = 0; a < 6; ++a) bb[a] = bbox_cur[t * 6 + a];
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(TPB) void k_list_compact(const BinTile *__restrict_
                                                       const uint64_t *__restrict__ meta,
                                                       const uint32_t *__restrict__ sparse, uint32_t *__restrict__ list) {
   const BinTile tl = tiles[blockIdx.x];
-  const uint32_t src = off[tl.t] + tl.i0;
+  const uint32_t src = tl.base + tl.i0;
   const uint32_t o = toff[blockIdx.x];
   const uint32_t end = blockIdx.x + 1 < ntiles ? toff[blockIdx.x + 1] : (uint32_t)meta[META_L];
   for (uint32_t i = threadIdx.x; i < end - o; i += TPB) list[o + i] = sparse[src + i];
@@ -675,7 +678,7 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
   const uint32_t NT = p.NT;
   const BinTile tl = tiles[blockIdx.x];
   const int t = tl.t;
-  const uint32_t base = off[t];
+  const uint32_t base = tl.base;
   const uint32_t s0 = seg_first[t], nb = seg_first[t + 1] - s0;
   int32_t bb[6];
 #pragma unroll
@@ -795,9 +798,9 @@ __global__ __launch_bounds__(TPB) void k_bin_wmax(Params p, const Tile *__restri
                                                   double *__restrict__ wacc) {
   const Tile tl = tiles[blockIdx.x];
   if (tuni[tl.t]) return;
-  const uint32_t base = off[tl.t];
+  const uint32_t base = tl.base;
   const uint32_t i = tl.i0 + threadIdx.x;
-  if (i >= off[tl.t + 1] - base) return;
+  if (i >= tl.n) return;
   unsigned long long *mx = (unsigned long long *)(wacc + (size_t)(1 + p.D) * p.NT);
   atomicMax(&mx[segid[base + i]], ordered_bits(lw[base + i]));
 }
@@ -811,9 +814,9 @@ __global__ __launch_bounds__(TPB) void k_bin_wsums(Params p, const Tile *__restr
   const Tile tl = tiles[blockIdx.x];
   const int t = tl.t;
   if (tuni[t]) return;
-  const uint32_t base = off[t];
+  const uint32_t base = tl.base;
   const uint32_t i = tl.i0 + threadIdx.x;
-  if (i >= off[t + 1] - base) return;
+  if (i >= tl.n) return;
   const uint32_t g = base + i, NT = p.NT;
   const uint32_t b = segid[g];
   const unsigned long long *mx = (const unsigned long long *)(wacc + (size_t)(1 + D) * NT);
@@ -1340,7 +1343,7 @@ __global__ __launch_bounds__(TPB) void k_norm_part(Params p, const Tile *__restr
   constexpr int D = 2 * DIM + 1;
   __shared__ double lds[TPB / WAVE];
   const Tile tl = tiles[blockIdx.x];
-  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t base = tl.base, n = tl.n;
   double mx = -INFINITY;
   for (int it = 0; it < SCAN_ITEMS; ++it) {
     const uint32_t i = tl.i0 + it * TPB + threadIdx.x;
@@ -1426,7 +1429,7 @@ __global__ __launch_bounds__(TPB) void k_cdf_sum(const Tile *__restrict__ tiles,
                                                  WeightSrc ws, double *__restrict__ tile_sum) {
   __shared__ double lds[TPB / WAVE];
   const Tile tl = tiles[blockIdx.x];
-  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t base = tl.base, n = tl.n;
   double acc = 0.0;
   double w[SCAN_ITEMS];
 #pragma unroll
@@ -1479,37 +1482,35 @@ __device__ __forceinline__ uint32_t count_below(double c, double u, uint32_t n) 
   return j;
 }
 
-// Systematic resampling fused with the cumulative-weight scan. The new
-// particle j takes the parent s(j) = min{ l : C_l > theta_j }, theta_j =
-// (j + u) / n; the last particle also takes any j left above C_{n-1} by
-// rounding. Each tile first forms the cumulative weights of its particles
-// (block scan), with every boundary taken from one source (the next thread's
-// or tile's start, made non-decreasing), so consecutive tiles partition the
-// new particles. The tile's new particles [count(tile start), count(tile end))
-// are then split into equal contiguous ranges, one per thread (no thread
-// serialises the many offspring of a heavy particle); the thread finds the
-// parent of its first new particle by galloping search over the tile's
-// cumulative weights in LDS, then of each next one from the previous parent.
-// Weights are loaded coalesced into LDS first, then each thread takes its
-// SCAN_ITEMS consecutive ones; the LDS array has one pad slot per
-// SCAN_ITEMS entries so that those strided reads do not collide in banks.
+// Cumulative weights of systematic resampling: each tile forms those of its
+// particles (block scan), with every boundary taken from one source (the next
+// thread's or tile's start, made non-decreasing), so that C is non-decreasing
+// across the whole target, and writes them (C_l, storage order). Weights are
+// loaded coalesced into LDS first, then each thread takes its SCAN_ITEMS
+// consecutive ones; the LDS array has one pad slot per SCAN_ITEMS entries so
+// that those strided reads do not collide in banks. A target that keeps its
+// particles (non-finite normalisation, or N_eff at or above the threshold)
+// gets identity ancestors and, with kept weights, its normalised log-weights.
+// The new particles whose parents lie in the tile are those with
+// theta_j in [tile start, next tile's start); for every multiple of SCAN_TILE
+// among them, the start of a block of the search below, the tile also records
+// that j's parent (chunk_par), from its cumulative weights in LDS.
 __device__ __forceinline__ uint32_t cpad(uint32_t l) { return l + l / SCAN_ITEMS; }
 
 template <bool SIR>
-__global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
-                                                      const uint32_t *__restrict__ tile_last,
-                                                      WeightSrc ws, const double *__restrict__ tile_pre,
-                                                      const int32_t *__restrict__ tflag, uint32_t *__restrict__ anc,
-                                                      double *__restrict__ cdf_dbg, double neff_frac,
-                                                      int32_t *__restrict__ tuni_next) {
+__global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
+                                                  const uint32_t *__restrict__ tile_last,
+                                                  WeightSrc ws, const double *__restrict__ tile_pre,
+                                                  const int32_t *__restrict__ tflag, uint32_t *__restrict__ anc,
+                                                  double *__restrict__ cdf, double neff_frac,
+                                                  int32_t *__restrict__ tuni_next, uint32_t *__restrict__ chunk_par) {
   __shared__ double lds[TPB / WAVE];
   __shared__ double bound[TPB + 1];
   __shared__ double cl[SCAN_TILE + SCAN_TILE / SCAN_ITEMS];
   const Tile tl = tiles[blockIdx.x];
   const int t = tl.t;
-  const uint32_t base = off[t], n = off[t + 1] - base;
+  const uint32_t base = tl.base, n = tl.n;
   const uint32_t m = min((uint32_t)SCAN_TILE, n - tl.i0);  // particles in this tile
-  const double u = ws.tgt[t * 4 + 3];
   {
     double wl[SCAN_ITEMS];
 #pragma unroll
@@ -1564,49 +1565,122 @@ __global__ __launch_bounds__(TPB) void k_cdf_resample(const Tile *__restrict__ t
   if (end < start) end = start;
   double run = 0.0;
   double cprev = start;
+  double c[SCAN_ITEMS];
 #pragma unroll
   for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t li = threadIdx.x * SCAN_ITEMS + it;
-    const uint32_t i = tl.i0 + li;
-    if (i >= n) break;
+    const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
     run += w[it];
-    double c;
+    double ci;
     if (i + 1 == n) {
-      c = pre + (ex + run);  // the target's total
-      c = c < cprev ? cprev : c;
-      if (cdf_dbg) cdf_dbg[base + i] = c;
-      cl[cpad(li)] = INFINITY;  // the last particle takes every j left over
+      ci = pre + (ex + run);  // the target's total
+      ci = ci < cprev ? cprev : ci;
     } else {
-      c = (it == SCAN_ITEMS - 1) ? end : pre + (ex + run);
-      c = c < cprev ? cprev : (c > end ? end : c);
-      if (cdf_dbg) cdf_dbg[base + i] = c;
-      cl[cpad(li)] = c;
+      ci = (it == SCAN_ITEMS - 1) ? end : pre + (ex + run);
+      ci = ci < cprev ? cprev : (ci > end ? end : ci);
     }
-    cprev = c;
+    c[it] = ci;
+    cprev = ci;
   }
+  // through LDS, so that the stores to global memory are coalesced
+#pragma unroll
+  for (int it = 0; it < SCAN_ITEMS; ++it) cl[cpad(threadIdx.x * SCAN_ITEMS + it)] = c[it];
   __syncthreads();
+#pragma unroll
+  for (int it = 0; it < SCAN_ITEMS; ++it) {
+    const uint32_t li = it * TPB + threadIdx.x;
+    if (li < m) cdf[base + tl.i0 + li] = cl[cpad(li)];
+  }
+  // parents of the search blocks' first new particles that fall in this tile
+  const double u = ws.tgt[t * 4 + 3];
   const uint32_t jlo = count_below(pre, u, n);
   const uint32_t jhi = last_tile ? n : count_below(tile_end, u, n);
+  const uint32_t first_tile = blockIdx.x - tl.i0 / SCAN_TILE;  // this target's tiles are consecutive
   const double dn = (double)n;
-  uint32_t prev = 0;  // parents are non-decreasing in j: search forward from the last one
-  const uint32_t per = (jhi - jlo + TPB - 1) / TPB;
-  const uint32_t ja = jlo + min(jhi - jlo, threadIdx.x * per), jb = min(jhi, ja + per);
-  for (uint32_t j = ja; j < jb; ++j) {
+  for (uint32_t q = (jlo + SCAN_TILE - 1) / SCAN_TILE + threadIdx.x; q * SCAN_TILE < jhi; q += TPB) {
+    const double theta = ((double)(q * SCAN_TILE) + u) / dn;
+    // smallest li with C > theta; the tile's last particle qualifies (its C is
+    // the next tile's start, or the target's last particle)
+    uint32_t a = 0, b = m - 1;
+    while (a < b) {
+      const uint32_t mid = (a + b) >> 1;
+      if (cl[cpad(mid)] > theta) b = mid;
+      else a = mid + 1;
+    }
+    chunk_par[first_tile + q] = tl.i0 + a;
+  }
+}
+
+// Systematic resampling proper, one block per SCAN_TILE new particles of a
+// target (the same tiles as the particles), so that the work does not follow
+// the weights: a tile holding most of a target's weight has as many parents
+// to find as it has offspring, which one block per particle tile would
+// serialise. The new particle j takes the parent s(j) = min{ l : C_l > theta_j },
+// theta_j = (j + u) / n, over the cumulative weights C (non-decreasing
+// across the whole target); the last particle also takes any j left above
+// C_{n-1} by rounding. The block's parents lie between the parents of its
+// first j and of the next block's first j (chunk_par); when that range fits,
+// its C values are staged in LDS. Each thread takes SCAN_ITEMS consecutive j:
+// a binary search for the first, galloping forward from the previous parent
+// for the next ones.
+constexpr uint32_t SEARCH_LDS = 1024;
+
+template <bool SIR>
+__global__ __launch_bounds__(TPB) void k_resample_search(const Tile *__restrict__ tiles,
+                                                         const uint32_t *__restrict__ off, WeightSrc ws,
+                                                         const double *__restrict__ cdf,
+                                                         const uint32_t *__restrict__ chunk_par,
+                                                         const int32_t *__restrict__ tflag, uint32_t *__restrict__ anc,
+                                                         double neff_frac) {
+  __shared__ double cs[SEARCH_LDS];
+  const Tile tl = tiles[blockIdx.x];
+  const int t = tl.t;
+  const uint32_t base = tl.base, n = tl.n;
+  // the loads that do not depend on each other are issued together
+  const uint32_t p0 = chunk_par[blockIdx.x];
+  const uint32_t p1 = tl.i0 + SCAN_TILE < n ? chunk_par[blockIdx.x + 1] : n - 1;  // inclusive
+  const double u = ws.tgt[t * 4 + 3];
+  // targets that keep their particles were written by the scan
+  if (tflag[t] || (ws.lw && !(ws.tgt[t * 4 + 2] < neff_frac * (double)n))) return;
+  const double dn = (double)n;
+  const double *__restrict__ C = cdf + base;
+  // every stride-th C of the range in LDS (all of them when it fits); a
+  // search then takes the LDS samples, then at most stride - 1 values
+  const uint32_t span = p1 - p0 + 1;
+  const uint32_t stride = (span + SEARCH_LDS - 1) / SEARCH_LDS;
+  const uint32_t ns = (span + stride - 1) / stride;
+  for (uint32_t k = threadIdx.x; k < ns; k += TPB) {
+    const uint32_t l = p0 + k * stride;
+    cs[k] = l + 1 >= n ? INFINITY : C[l];  // the last particle stands for +infinity
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < SCAN_ITEMS; ++it) {
+    const uint32_t j = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    if (j >= n) break;
     const double theta = ((double)j + u) / dn;
-    // smallest l >= prev with cl[l] > theta (cl[m-1] > theta for every j < jhi)
-    uint32_t lo = prev, step = 1, hi = prev;
-    while (hi < m - 1 && !(cl[cpad(hi)] > theta)) {
-      lo = hi + 1;
-      hi = min(hi + step, m - 1);
-      step *= 2;
+    // first sample above theta (ns if none: the answer is then in the last
+    // segment, whose end p1 is above theta)
+    uint32_t a = 0, b = ns;
+    while (a < b) {
+      const uint32_t mid = (a + b) >> 1;
+      if (cs[mid] > theta) b = mid;
+      else a = mid + 1;
     }
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (cl[cpad(mid)] > theta) hi = mid;
-      else lo = mid + 1;
+    uint32_t par;
+    if (stride == 1) {
+      par = p0 + min(a, ns - 1);
+    } else {
+      // the answer lies in (sample a-1, sample a]
+      uint32_t lo = a == 0 ? p0 : p0 + (a - 1) * stride + 1;
+      uint32_t hi = a == ns ? p1 : p0 + a * stride;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (mid + 1 >= n || C[mid] > theta) hi = mid;
+        else lo = mid + 1;
+      }
+      par = lo;
     }
-    prev = lo;
-    anc[base + j] = tl.i0 + lo;
+    anc[base + j] = par;
   }
 }
 
@@ -1616,7 +1690,7 @@ __global__ __launch_bounds__(TPB) void k_gather(int D, uint32_t NT, const Tile *
                                                 const uint32_t *__restrict__ off, const float *__restrict__ s,
                                                 const uint32_t *__restrict__ anc, int pending, float *__restrict__ dst) {
   const Tile tl = tiles[blockIdx.x];
-  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t base = tl.base, n = tl.n;
   const uint32_t i = tl.i0 + threadIdx.x;
   if (i >= n) return;
   const uint32_t g = base + i;
@@ -1628,7 +1702,7 @@ __global__ __launch_bounds__(TPB) void k_gather(int D, uint32_t NT, const Tile *
 __global__ __launch_bounds__(TPB) void k_identity(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
                                                   uint32_t *__restrict__ anc) {
   const Tile tl = tiles[blockIdx.x];
-  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t base = tl.base, n = tl.n;
   const uint32_t i = tl.i0 + threadIdx.x;
   if (i < n) anc[base + i] = i;
 }
@@ -1684,7 +1758,7 @@ __global__ __launch_bounds__(TPB) void k_dbg_weights(const Tile *__restrict__ ti
                                                      WeightSrc ws, const int32_t *__restrict__ tuni_next,
                                                      double *__restrict__ out) {
   const Tile tl = tiles[blockIdx.x];
-  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t base = tl.base, n = tl.n;
   const uint32_t i = tl.i0 + threadIdx.x;
   if (i >= n) return;
   out[base + i] = (ws.lw && !tuni_next[tl.t]) ? exp(ws.lw[base + i]) : particle_weight<SIR>(ws, tl.t, base + i);
@@ -1695,7 +1769,7 @@ __global__ __launch_bounds__(TPB) void k_dbg_logw(const Tile *__restrict__ tiles
                                                   const double *__restrict__ lw, const int32_t *__restrict__ tuni,
                                                   double *__restrict__ out) {
   const Tile tl = tiles[blockIdx.x];
-  const uint32_t base = off[tl.t], n = off[tl.t + 1] - base;
+  const uint32_t base = tl.base, n = tl.n;
   const uint32_t i = tl.i0 + threadIdx.x;
   if (i >= n) return;
   out[base + i] = (!lw || tuni[tl.t]) ? -log((double)n) : lw[base + i];

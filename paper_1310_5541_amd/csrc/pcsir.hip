@@ -26,7 +26,7 @@ struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
       ll, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
       bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
-      tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off;
+      tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off, chunk_par;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
   uint32_t n256; // propagate tiles
@@ -81,9 +81,11 @@ constexpr int DIGIT_BITS_MIN = 6;
 
 void build_bin_tiles(const pcsir_config *c, uint32_t tile, std::vector<BinTile> &tB) {
   tB.clear();
+  uint32_t base = 0;
   for (int t = 0; t < c->n_targets; ++t) {
     const uint32_t n = (uint32_t)c->n_particles[t];
-    for (uint32_t i0 = 0; i0 < n; i0 += tile) tB.push_back(BinTile{t, i0, std::min<uint32_t>(n, i0 + tile)});
+    for (uint32_t i0 = 0; i0 < n; i0 += tile) tB.push_back(BinTile{t, i0, std::min<uint32_t>(n, i0 + tile), base});
+    base += n;
   }
 }
 
@@ -100,10 +102,10 @@ void build_tables(const pcsir_config *c, Tables &tb) {
     const uint32_t n = (uint32_t)c->n_particles[t];
     tb.off[t + 1] = tb.off[t] + n;
     tb.t256_first[t] = (uint32_t)tb.t256.size();
-    for (uint32_t i0 = 0; i0 < n; i0 += TPB) tb.t256.push_back(Tile{t, i0});
+    for (uint32_t i0 = 0; i0 < n; i0 += TPB) tb.t256.push_back(Tile{t, i0, tb.off[t], n});
     tb.tfirst[t] = (uint32_t)tb.tS.size();
     for (uint32_t i0 = 0; i0 < n; i0 += SCAN_TILE) {
-      tb.tS.push_back(Tile{t, i0});
+      tb.tS.push_back(Tile{t, i0, tb.off[t], n});
       tb.tile_last.push_back(i0 + SCAN_TILE >= n ? 1u : 0u);
     }
   }
@@ -180,6 +182,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.tile_sum = take(8 * (size_t)L.nS);
   L.tile_pre = take(8 * (size_t)L.nS);
   L.cdf = take(8 * NT);
+  L.chunk_par = take(4 * (size_t)L.nS);
   L.tiles256 = take(sizeof(Tile) * (size_t)L.n256);
   L.tilesS = take(sizeof(Tile) * (size_t)L.nS);
   L.tilesB = take(sizeof(BinTile) * (size_t)L.nB);
@@ -492,11 +495,13 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   mark(c, "cdf_prefix");
   k_cdf_prefix<<<p.T, TPB, 0, st>>>(c->at<uint32_t>(L.tfirst), c->at<double>(L.tile_sum),
                                     c->at<double>(L.tile_pre));
+  mark(c, "cdf_scan");
+  k_cdf_scan<false><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
+                                          c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
+                                          keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par));
   mark(c, "resample");
-  k_cdf_resample<false><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
-                                              c->at<int32_t>(L.tflag), anc,
-                                              c->debug ? c->at<double>(L.cdf) : nullptr, c->cfg.neff_threshold,
-                                              keep ? c->at<int32_t>(L.tuni_next) : nullptr);
+  k_resample_search<false><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
+                                                 c->at<int32_t>(L.tflag), anc, c->cfg.neff_threshold);
   mark(c, "end");
 }
 
@@ -536,10 +541,13 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
   mark(c, "cdf_prefix");
   k_cdf_prefix<<<p.T, TPB, 0, st>>>(c->at<uint32_t>(L.tfirst), c->at<double>(L.tile_sum),
                                     c->at<double>(L.tile_pre));
+  mark(c, "cdf_scan");
+  k_cdf_scan<true><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
+                                         c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
+                                         keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par));
   mark(c, "resample");
-  k_cdf_resample<true><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
-                                             c->at<int32_t>(L.tflag), anc, c->debug ? c->at<double>(L.cdf) : nullptr,
-                                             c->cfg.neff_threshold, keep ? c->at<int32_t>(L.tuni_next) : nullptr);
+  k_resample_search<true><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
+                                                c->at<int32_t>(L.tflag), anc, c->cfg.neff_threshold);
   mark(c, "end");
 }
 
