@@ -208,9 +208,9 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *ctx, int32_t what, void *dst_dev, size_
  * kernels one by one while timing is on. */
 pcsir_status pcsir_set_graphs(pcsir_ctx *ctx, int32_t on);
 
-/* Keep the per-particle cumulative weights of later steps for
- * PCSIR_DUMP_CDF (on != 0). Off by default: it adds 8 bytes of HBM writes per
- * particle and step. */
+/* Allow PCSIR_DUMP_CDF (on != 0; off by default). The step always stores the
+ * per-particle cumulative weights, which its resampling search reads; the
+ * switch only gates the view of them. */
 pcsir_status pcsir_set_debug(pcsir_ctx *ctx, int32_t on);
 
 /* Per-kernel times, in milliseconds, of every launch since timing was turned

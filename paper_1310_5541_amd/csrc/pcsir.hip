@@ -830,7 +830,6 @@ pcsir_status pcsir_set_graphs(pcsir_ctx *c, int32_t on) {
 
 pcsir_status pcsir_set_debug(pcsir_ctx *c, int32_t on) {
   if (!c) return PCSIR_E_INVAL;
-  if (c->debug != (on ? 1 : 0)) drop_graphs(c);  // captured graphs hold the debug pointers
   c->debug = on ? 1 : 0;
   return PCSIR_OK;
 }
@@ -919,7 +918,7 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *c, int32_t what, void *dst, size_t byte
       e = hipMemcpyAsync(dst, c->at<double>(L.tgt), 8 * 4 * T, hipMemcpyDeviceToDevice, st);
       break;
     case PCSIR_DUMP_CDF:
-      if (!c->debug) return fail(c, PCSIR_E_STATE, "cumulative weights are kept only with pcsir_set_debug(ctx, 1)");
+      if (!c->debug) return fail(c, PCSIR_E_STATE, "the cumulative-weight view needs pcsir_set_debug(ctx, 1)");
       if (!need(8 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
       e = hipMemcpyAsync(dst, c->at<double>(L.cdf), 8 * NT, hipMemcpyDeviceToDevice, st);
       break;
