@@ -10,7 +10,10 @@ and "3d-astig" (200 targets x 5e4, D = 7) are selectable.
 
 1. Matching pass (untimed): SIR and pcSIR at h in {1, 0.5, 0.25, 0.1, 0.05}
    track every frame from the truth on R seeded sequences; the matched pcSIR
-   operating point is the largest h whose mean RMSE is at most 1.05x SIR's.
+   operating point is the largest h whose median per-target RMSE is at most
+   1.05x SIR's and whose share of lost targets (RMSE > 2 px) is at most 2
+   points above SIR's. The mean RMSE and the h the mean alone would give are
+   reported beside it.
 2. Surrogate (untimed, reported separately): training rows from exact pcSIR
    steps at the matched h on 512x512 training sequences (other seeds, the same
    spot density), GPU training with the library's MFMA kernels, FP8 scale
@@ -51,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched-2d-1024")
-    ap.add_argument("--reps", type=int, default=2, help="sequences of the RMSE matching pass")
+    ap.add_argument("--reps", type=int, default=4, help="sequences of the RMSE matching pass")
     ap.add_argument("--no-match", action="store_true", help="skip the RMSE matching pass (use --h)")
     ap.add_argument("--h", type=float, default=0.5)
     ap.add_argument("--no-surrogate", action="store_true")
@@ -270,17 +273,33 @@ def main():
             if stats is not None:
                 stats.append(f.surrogate_stats())
             f.close()
-            out.append(float(np.mean(synth.rmse(est, trr[:Kmatch + 1], dim))))
-        return float(np.mean(out))
+            out.append(synth.rmse(est, trr[:Kmatch + 1], dim))
+        return np.concatenate(out)   # per-target RMSE, all sequences
 
-    rmse = {}
+    LOST_PX = 2.0
+
+    def summary(a):
+        return {"mean": round(float(np.mean(a)), 4), "median": round(float(np.median(a)), 4),
+                "lost_frac": round(float(np.mean(a > LOST_PX)), 4)}
+
+    rmse, rmse_stats = {}, {}
+    h_mean_rule = None
     if not args.no_match:
-        rmse["sir"] = track_rmse(True, 0.5, LIK_SEP)
+        a = track_rmse(True, 0.5, LIK_SEP)
+        rmse["sir"], rmse_stats["sir"] = float(np.mean(a)), summary(a)
         for h in hs:
-            rmse[f"h={h}"] = track_rmse(False, h, LIK_SEP)
-            log(f"rmse h={h}: {rmse[f'h={h}']:.4f} (SIR {rmse['sir']:.4f})")
-        ok = [h for h in hs if rmse[f"h={h}"] <= 1.05 * rmse["sir"]]
+            a = track_rmse(False, h, LIK_SEP)
+            rmse[f"h={h}"], rmse_stats[f"h={h}"] = float(np.mean(a)), summary(a)
+            log(f"rmse h={h}: {rmse_stats[f'h={h}']} (SIR {rmse_stats['sir']})")
+        # matched: the median per-target RMSE within 5% of SIR's and at most 2
+        # points more lost targets (RMSE > 2 px); on crowded frames a quarter of
+        # even SIR's tracks are lost, and the mean is dominated by which ones
+        sm, sl = rmse_stats["sir"]["median"], rmse_stats["sir"]["lost_frac"]
+        ok = [h for h in hs if rmse_stats[f"h={h}"]["median"] <= 1.05 * sm
+              and rmse_stats[f"h={h}"]["lost_frac"] <= sl + 0.02]
         h_match = max(ok) if ok else min(hs)
+        okm = [h for h in hs if rmse[f"h={h}"] <= 1.05 * rmse["sir"]]
+        h_mean_rule = max(okm) if okm else min(hs)
     else:
         h_match = args.h
 
@@ -322,8 +341,10 @@ def main():
         del Xe, ye
         log(f"surrogate error (nats) bf16 {err_bf16}\n  fp8 {err_fp8}")
         st_b, st_8 = [], []
-        r_b = track_rmse(False, h_match, LIK_SURR_BF16, params, None, st_b) if not args.no_match else None
-        r_8 = track_rmse(False, h_match, LIK_SURR_FP8, params, scales, st_8) if not args.no_match else None
+        a_b = track_rmse(False, h_match, LIK_SURR_BF16, params, None, st_b) if not args.no_match else None
+        a_8 = track_rmse(False, h_match, LIK_SURR_FP8, params, scales, st_8) if not args.no_match else None
+        r_b = None if a_b is None else float(np.mean(a_b))
+        r_8 = None if a_8 is None else float(np.mean(a_8))
         surr = {"train": {"rows": n_rows, "sequences": seq, "workload": wt.name, "row_generation_s":
                           round(gen_rows_s, 2), "train_s": round(hist["train_s"], 2), "epochs": args.epochs,
                           "batch": hist["batch"], "steps": hist["steps"],
@@ -332,6 +353,8 @@ def main():
                                         "rows_from": f"exact pcSIR dummies, first {min(Kmatch, 10)} frames"},
                 "fp8_scales": [float(s) for s in scales], "check_fraction": args.check, "tol_nats": args.tol,
                 "rmse_px": {"bf16": r_b, "fp8": r_8},
+                "rmse_stats": {"bf16": None if a_b is None else summary(a_b),
+                               "fp8": None if a_8 is None else summary(a_8)},
                 "checks_fallbacks": {"bf16": st_b, "fp8": st_8}}
 
     # ---- 3. timed regions
@@ -389,8 +412,10 @@ def main():
     if thr >= 0:
         runs["pcsir_sep_thr"] = timed(False, h_match, LIK_SEP, True, thr=thr)
         if not args.no_match:
-            rmse[f"h={h_match},neff<{thr}N"] = track_rmse(False, h_match, LIK_SEP, thr=thr)
-            log(f"rmse h={h_match} with N_eff threshold {thr}: {rmse[f'h={h_match},neff<{thr}N']:.4f}")
+            a = track_rmse(False, h_match, LIK_SEP, thr=thr)
+            key = f"h={h_match},neff<{thr}N"
+            rmse[key], rmse_stats[key] = float(np.mean(a)), summary(a)
+            log(f"rmse h={h_match} with N_eff threshold {thr}: {rmse_stats[key]}")
     if params is not None:
         runs["surr_bf16"] = timed(False, h_match, LIK_SURR_BF16, True)
         runs["surr_fp8"] = timed(False, h_match, LIK_SURR_FP8, True)
@@ -449,6 +474,9 @@ def main():
         if surr["rmse_px"]["bf16"] is not None and f"h={h_match}" in rmse:
             surr["rmse_vs_exact_pcsir"] = {m: round(surr["rmse_px"][m] / rmse[f"h={h_match}"], 4)
                                            for m in ("bf16", "fp8")}
+            surr["median_rmse_vs_exact_pcsir"] = {
+                m: round(surr["rmse_stats"][m]["median"] / rmse_stats[f"h={h_match}"]["median"], 4)
+                for m in ("bf16", "fp8")}
 
     # ---- 4. CPU baseline: the oracle on a bounded sample
     cpu = None
@@ -495,6 +523,10 @@ def main():
         "speedup_pcsir_over_sir": {"separable": round(val["pcsir_sep"] / val["sir_sep"], 2),
                                    "direct": round(val["pcsir_direct"] / val["sir_direct"], 2)},
         "rmse_px": rmse,
+        "rmse_stats": rmse_stats,
+        "matching": {"rule": "largest h with median per-target RMSE <= 1.05 x SIR's and lost-target share "
+                             "(RMSE > 2 px) <= SIR's + 0.02", "sequences": args.reps, "h_matched": h_match,
+                     "h_by_mean_rmse_rule": h_mean_rule},
         "roofline": roof,
         "hbm_gbs_per_kernel": hbm,
         "kernel_ms_per_step": {k: {n: round(v, 5) for n, v in r["per"].items()} for k, r in runs.items()},
