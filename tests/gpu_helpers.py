@@ -62,11 +62,13 @@ def weight_bound(ll_of_particle, wo):
     return 1.01 * (tl + np.sum(wo * tl)) * wo + 1e-12 * wo.max()
 
 
-def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, surrogate=None, on_filter=None):
+def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, surrogate=None, on_filter=None,
+                    targets=None, tuning=None):
     """cloud: [D, NT] float32 (host); frames: [H, W] or [T, H, W] float32 (host).
     Runs one GPU step from `cloud` and checks every stage against the oracle.
     surrogate: (params, act_scale, check_fraction, tol) installed before the step
     (a surrogate lik_mode); on_filter(f) runs after the dumps, before close.
+    targets: the targets to check (all by default); tuning: launch shapes.
     Returns a dict of the largest deviations."""
     import torch
 
@@ -79,6 +81,8 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
     mdl = oracle_model(cfg)
     f = Filter(cfg, torch.from_numpy(np.ascontiguousarray(cloud)).cuda())
     f.set_debug(True)
+    if tuning is not None:
+        f.set_tuning(**tuning)
     if surrogate is not None:
         f.set_surrogate(*surrogate)
     fr_t = torch.from_numpy(np.ascontiguousarray(frames)).cuda()
@@ -104,8 +108,12 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
 
     dev = dict(prop=0.0, mean_pos=0.0, mean_vel=0.0, mean_int=0.0, ll=0.0, w=0.0, est=0.0, neff=0.0,
                exempt=0, mismatch=0, B=0)
-    bofs = 0
-    for t in range(T):
+    check = range(T) if targets is None else sorted(set(int(t) for t in targets))
+    if not sir:
+        # bins are ordered by target: each target's first bin
+        bfirst = np.searchsorted(b_t, np.arange(T + 1), side="left")
+        assert np.all(np.diff(b_t) >= 0), "bins not ordered by target"
+    for t in check:
         a, b = off[t], off[t + 1]
         fr = frames[t] if cfg.per_target_frames else frames
         if check_prop:
@@ -121,7 +129,8 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
             ll_o = r["ll"]
             ll_g = ll_gpu[a:b].astype(np.float64)
         else:
-            gsl = slice(bofs, bofs + B)
+            gsl = slice(int(bfirst[t]), int(bfirst[t + 1]))
+            assert bfirst[t + 1] - bfirst[t] == B, f"target {t}: {bfirst[t + 1] - bfirst[t]} bins, oracle {B}"
             assert np.all(b_t[gsl] == t), f"target {t}: bin targets"
             assert np.array_equal(b_key[:dim, gsl], r["bin_key"][:dim]), f"target {t}: bin keys"
             assert np.array_equal(b_n[gsl], r["bin_n"]), f"target {t}: bin counts"
@@ -137,7 +146,6 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
             dev["mean_int"] = max(dev["mean_int"], float(e_int))
             ll_o = r["ll"]
             ll_g = ll_gpu[gsl].astype(np.float64)
-            bofs += B
             dev["B"] += B
         d_ll = np.abs(ll_g - ll_o)
         bad = d_ll > LL_ATOL + LL_RTOL * np.abs(ll_o)
@@ -181,7 +189,9 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
         # the resampled set is the gather of the propagated states
         assert np.array_equal(after[:, a:b], prop[:, a:b][:, sg])
     if not sir:
-        assert int(counts[0]) == dev["B"]
+        assert int(counts[0]) == b_t.size
+        if targets is None:
+            assert int(counts[0]) == dev["B"]
     if report is not None:
         report.update(dev)
     return dev, after

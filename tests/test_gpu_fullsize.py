@@ -1,0 +1,92 @@
+"""GPU parity at the full sizes the benchmark runs, in its launch configuration.
+
+The single target (10^6 particles, 512 x 512, 15 x 15 window, 8 x 8
+quadrature), the batched workload (1000 targets, 21 654 239 particles,
+1024 x 1024) and the 3D workload (200 targets x 5 x 10^4 particles, D = 7)
+step from a state three frames into tracking, at h = 0.25, with the separable
+likelihood, graph launches and the launch shapes the benchmark's autotuner
+picks. The oracle checks every stage (propagation, keys, bins, bin means,
+log-likelihoods, weights, estimates, N_eff, resampling) for the whole single
+target and for sampled targets of the others (smallest, largest and spread
+sizes), to the tolerances of gpu_helpers; the remaining targets are checked
+through properties that hold at any size: bins ordered by target, member
+counts summing to N_t, weights summing to 1 and non-decreasing parents.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import log, run_step_parity
+
+pytestmark = pytest.mark.gpu
+
+TUNING = dict(bin_tile=4096, list_blocks=512, digit_bits=11, grid_per_cu=32)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1310_5541_amd import lib
+    lib()
+
+
+def _start(w, cfg, frames, k0):
+    """The particle set after k0 - 1 frames of tracking from the truth."""
+    import torch
+
+    from paper_1310_5541_amd import Filter
+    tr = synth.truth(w)
+    f = Filter(cfg, torch.from_numpy(synth.initial_particles(w, tr[0], w.counts())).cuda())
+    f.set_tuning(**TUNING)
+    fr = torch.from_numpy(frames).cuda()
+    for k in range(1, k0):
+        f.step(fr[k - 1], k)
+    st = f.get_particles().cpu().numpy()
+    f.close()
+    return st
+
+
+def _properties(cfg, frames, start, k):
+    """Size-independent properties of one step over every target."""
+    import torch
+
+    from paper_1310_5541_amd import Filter
+    n = np.asarray(cfg.n_particles, dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(n)])
+    f = Filter(cfg, torch.from_numpy(start).cuda())
+    f.set_tuning(**TUNING)
+    f.step(torch.from_numpy(frames).cuda(), k)
+    f.estimate()
+    b_t = f.dump("bin_target").cpu().numpy()
+    b_n = f.dump("bin_n").cpu().numpy()
+    w = f.dump("weights").cpu().numpy()
+    s = f.dump("resample").cpu().numpy().astype(np.int64)
+    f.close()
+    assert np.all(np.diff(b_t) >= 0)
+    assert np.array_equal(np.bincount(b_t, weights=b_n, minlength=len(n)).astype(np.int64), n)
+    sums = np.add.reduceat(w, off[:-1])
+    assert np.all(np.abs(sums - 1.0) < 1e-12), np.abs(sums - 1.0).max()
+    for t in range(len(n)):
+        st = s[off[t]:off[t + 1]]
+        assert st.min() >= 0 and st.max() < n[t] and np.all(np.diff(st) >= 0), t
+
+
+@pytest.mark.parametrize("workload", ["single-2d-512", "batched-2d-1024", "3d-astig"])
+def test_full_size_step(workload):
+    from paper_1310_5541_amd import Config
+    w = synth.preset(workload, K=4)
+    frames = synth.frames(w, synth.truth(w))
+    m = 4
+    cfg = Config.from_workload(w, bins_per_px=(m, m, m if w.dim == 3 else 1), lik_mode=1, seed=w.seed + 500)
+    start = _start(w, cfg, frames, 4)
+    n = w.counts()
+    order = np.argsort(n, kind="stable")
+    T = len(n)
+    pos = np.clip([0, 1, T // 4, T // 2, (3 * T) // 4, T - 2, T - 1], 0, T - 1)
+    sample = sorted(set(order[pos].tolist()))
+    log(f"case full_size {workload}: {int(n.sum())} particles, {len(n)} targets, checked {sample}")
+    _properties(cfg, frames[3], start, 4)
+    dev, _ = run_step_parity(cfg, start, frames[3], 4, False, targets=sample, tuning=TUNING)
+    log(f"  deviations {dev}")
