@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define PCSIR_ABI_VERSION 2
+#define PCSIR_ABI_VERSION 3
 
 typedef struct pcsir_ctx pcsir_ctx; /* opaque; host memory owned by the library */
 
@@ -108,6 +108,14 @@ typedef struct {
                                   members weighted by them (Sec. 4). Weighted sums use float64
                                   atomics, so results with kept weights are reproducible to
                                   rounding, not bit for bit. NaN or < 0: invalid. */
+  double bins_per_sigma;       /* 0: every target uses bins_per_px. > 0: adaptive bin size (the paper
+                                  names adaptive bins as future work): per frame, target and spatial
+                                  axis, m = ceil(bins_per_sigma / sd) cells per pixel, clamped to
+                                  [1, bins_max], where sd is the standard deviation of the target's
+                                  propagated positions on that axis (population variance
+                                  S2/n - (S1/n)^2 in binary64; bins_max when sd = 0). Cells keep
+                                  their edges at j/m - 1/2. Must be finite. */
+  int32_t bins_max;            /* adaptive bins: largest m, 1..4096 */
 } pcsir_config;
 
 /* Bytes of device workspace that a context with this config needs (0 if the
@@ -179,6 +187,7 @@ pcsir_status pcsir_set_particles(pcsir_ctx *ctx, const float *src_dev);
  *  CDF         float64 [sum N]      cumulative weights per target, storage order
  *  RESAMPLE    int32   [sum N]      s(j): parent of new particle j, index within its target
  *                                   (the identity for a target that did not resample)
+ *  BINS_PER_PX int32   [T][3]       cells per pixel m of every target and axis in the last pcsir_step
  *  LOGW        float64 [sum N]      log-weight every current particle carries into the next frame:
  *                                   -log N_t for a target that resampled (or always, with
  *                                   neff_threshold above 1), else its normalised log-weight */
@@ -195,7 +204,8 @@ typedef enum {
   PCSIR_DUMP_TARGET = 9,
   PCSIR_DUMP_CDF = 10,
   PCSIR_DUMP_RESAMPLE = 11,
-  PCSIR_DUMP_LOGW = 12
+  PCSIR_DUMP_LOGW = 12,
+  PCSIR_DUMP_BINS_PER_PX = 13
 } pcsir_dump;
 
 pcsir_status pcsir_debug_dump(pcsir_ctx *ctx, int32_t what, void *dst_dev, size_t bytes);

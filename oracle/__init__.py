@@ -12,6 +12,7 @@ the tracking-RMSE level is "parity unpinned" (no data from the paper).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -307,3 +308,28 @@ def posterior_mean(model: Model, frame: np.ndarray, kind: str, par: float, centr
     st[model.D - 1] = I0
     r = weigh(model, frame, st, sir=True, logw_prev=np.log(P))
     return r["est"][:2]
+
+
+def adaptive_bins(state: np.ndarray, dim: int, bins_per_sigma: float, bins_max: int):
+    """Cells per pixel of one target with adaptive bins. The paper names
+    adaptive bin sizes as future work without a rule; the rule here: per
+    spatial axis, m = ceil(bins_per_sigma / sd) clamped to [1, bins_max]
+    (bins_max when sd = 0), sd the population standard deviation of the
+    target's positions, S2/n - (S1/n)^2 in binary64 with each sum correctly
+    rounded, positions taken through the clamp of the cell index (NaN -> 2^24,
+    then into [-2^24, 2^24]). Returns (m [3] with 1 for unused axes, variances [dim])."""
+    m = [1, 1, 1]
+    var = []
+    for a in range(dim):
+        x = np.asarray(state[a], dtype=np.float32).astype(np.float64)
+        x = np.where(np.isnan(x), 2.0 ** 24, np.clip(x, -(2.0 ** 24), 2.0 ** 24))
+        n = x.size
+        s1 = math.fsum(x.tolist())
+        s2 = math.fsum((x * x).tolist())   # squares of binary32 values are exact in binary64
+        mean = s1 / n
+        v = max(s2 / n - mean * mean, 0.0)
+        var.append(v)
+        sd = math.sqrt(v)
+        q = bins_per_sigma / sd if sd > 0.0 else math.inf
+        m[a] = int(bins_max) if not q < bins_max else max(1, int(math.ceil(q)))
+    return tuple(m), var

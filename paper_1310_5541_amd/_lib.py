@@ -16,10 +16,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libpcsir.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 DUMP = dict(propagated=0, keys=1, counts=2, bin_target=3, bin_key=4, bin_n=5, bin_mean=6, loglik=7,
-            weights=8, target=9, cdf=10, resample=11, logw=12)
+            weights=8, target=9, cdf=10, resample=11, logw=12, bins_per_px=13)
 
 _STATUS = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP", -4: "E_STATE", -5: "E_NUMERIC",
            -6: "E_UNSUPPORTED"}
@@ -43,7 +43,7 @@ class _Cfg(C.Structure):
         ("per_target_frames", C.c_int32), ("frame_h", C.c_int32), ("frame_w", C.c_int32),
         ("sigma_psf", C.c_float), ("astig_gamma", C.c_float), ("astig_d", C.c_float), ("i_bg", C.c_float),
         ("sigma_xi", C.c_float), ("proc_sigma", C.c_float * 7), ("seed", C.c_uint64),
-        ("neff_threshold", C.c_double),
+        ("neff_threshold", C.c_double), ("bins_per_sigma", C.c_double), ("bins_max", C.c_int32),
     ]
 
 
@@ -140,6 +140,8 @@ class Config:
     proc_sigma: tuple = (0.5, 0.5, 0.1, 0.1, 2.0)
     seed: int = 1
     neff_threshold: float = float("inf")   # <= 1: resample only when N_eff < fraction * N
+    bins_per_sigma: float = 0.0            # > 0: adaptive bins, about this many per standard deviation
+    bins_max: int = 8                      # adaptive bins: largest cells per pixel
 
     @property
     def D(self) -> int:
@@ -173,6 +175,8 @@ class Config:
             c.proc_sigma[d] = float(ps[d])
         c.seed = int(self.seed) & (2**64 - 1)
         c.neff_threshold = float(self.neff_threshold)
+        c.bins_per_sigma = float(self.bins_per_sigma)
+        c.bins_max = int(self.bins_max)
         return c, n  # keep n alive while c is used
 
     @classmethod
@@ -318,7 +322,7 @@ class Filter:
             B = int(self.dump("counts")[0].item())
         shapes = dict(propagated=((D, NT), t.float32), keys=((3, NT), t.int32), counts=((3,), t.int64),
                       weights=((NT,), t.float64), target=((T, 4), t.float64), cdf=((NT,), t.float64),
-                      resample=((NT,), t.int32), logw=((NT,), t.float64))
+                      resample=((NT,), t.int32), logw=((NT,), t.float64), bins_per_px=((T, 3), t.int32))
         if what in shapes:
             shape, dt = shapes[what]
         elif what == "bin_target":

@@ -98,10 +98,15 @@ __device__ __forceinline__ double resample_uniform(uint64_t seed, uint64_t k, ui
 // 13, so (x + 1/2) m is exact in binary64 and so is its floor. Below, |x m|
 // < 2^-5 and the floor is m/2 rounded down, less one when m is even and
 // x < 0 (x in (-2^-17, 0) pushes (x + 1/2) m just below m/2).
-__device__ __forceinline__ int32_t cell_index(float xf, int32_t m) {
+// The clamp of cell_index: NaN -> 2^24, then into [-2^24, 2^24].
+__device__ __forceinline__ float clamp_position(float xf) {
   float x = xf;
   if (x != x) x = 16777216.0f;
-  x = fminf(fmaxf(x, -16777216.0f), 16777216.0f);
+  return fminf(fmaxf(x, -16777216.0f), 16777216.0f);
+}
+
+__device__ __forceinline__ int32_t cell_index(float xf, int32_t m) {
+  const float x = clamp_position(xf);
   if (fabsf(x) >= 0x1p-17f) {
     double v = floor(((double)x + 0.5) * (double)m);
     v = fmin(fmax(v, -1073741824.0), 1073741824.0);

@@ -42,7 +42,10 @@ constexpr int MAX_BUCKETS = 1 << MAX_DIGIT_BITS;
 struct Params {
   int dim, D, T;
   uint32_t NT;
-  int m[3];
+  int m[3];                 // configured cells per pixel (fixed bin size)
+  double bins_per_sigma;    // > 0: adaptive bin size, about this many bins per standard deviation
+  int bins_max;             // adaptive: at most this many cells per pixel
+  const int32_t *tm;        // [T][3] cells per pixel of every target in the current frame
   int P, R, q;
   int psf, dummy_mode, per_target_frames, H, W;
   float sigma_psf, astig_gamma, astig_d, i_bg;
@@ -92,7 +95,8 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
                                                    const uint32_t *__restrict__ off, const float *__restrict__ sin,
                                                    float *__restrict__ sout, const uint32_t *__restrict__ anc,
                                                    int pending, const StepDesc *__restrict__ desc,
-                                                   int32_t *__restrict__ bbox_part, unsigned long long *__restrict__ acc,
+                                                   float *__restrict__ bbox_part, double *__restrict__ mom_part,
+                                                   unsigned long long *__restrict__ acc,
                                                    const uint64_t *__restrict__ meta) {
   constexpr int D = 2 * DIM + 1;
   const Tile tl = tiles[blockIdx.x];
@@ -101,11 +105,14 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
   const uint32_t n = tl.n;
   const uint32_t i = tl.i0 + threadIdx.x;
   const bool valid = i < n;
-  int32_t kmin[DIM], kmax[DIM];
+  // extremes of the positions as cell_index clamps them (the cell index is
+  // non-decreasing in the clamped value, so the extremes give the cell
+  // range for any bin size), and with adaptive bins their sums and squares
+  float kmin[DIM], kmax[DIM];
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    kmin[a] = 0x7FFFFFFF;
-    kmax[a] = -0x7FFFFFFF - 1;
+    kmin[a] = INFINITY;
+    kmax[a] = -INFINITY;
   }
   if (valid) {
     const uint32_t g = base + i;
@@ -126,9 +133,9 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
     if (KEYS) {
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        const int32_t c = cell_index(nx[a], p.m[a]);
-        kmin[a] = c;
-        kmax[a] = c;
+        const float xc = clamp_position(nx[a]);
+        kmin[a] = xc;
+        kmax[a] = xc;
       }
       const uint32_t dirty = (uint32_t)meta[META_DIRTY];
       if (g < dirty) {
@@ -138,53 +145,100 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
     }
   }
   if (KEYS) {
-    // per-wave extremes, then one barrier and a combine of the block's waves
-    __shared__ int32_t wbox[TPB / WAVE][6];
+    // per-wave extremes (and sums), then one barrier and a combine of the block's waves
+    __shared__ float wbox[TPB / WAVE][6];
+    __shared__ double wmom[TPB / WAVE][6];
+    const bool adaptive = p.bins_per_sigma > 0.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      const int32_t lo = wave_min(kmin[a]);
-      const int32_t hi = wave_max(kmax[a]);
+      const float lo = wave_min(kmin[a]);
+      const float hi = wave_max(kmax[a]);
       if (lane_id() == 0) {
         wbox[wave_id()][a] = lo;
         wbox[wave_id()][3 + a] = hi;
+      }
+      if (adaptive) {
+        const double xd = valid ? (double)kmin[a] : 0.0;  // the particle's clamped position
+        const double s1 = wave_sum(xd);
+        const double s2 = wave_sum(xd * xd);
+        if (lane_id() == 0) {
+          wmom[wave_id()][a] = s1;
+          wmom[wave_id()][3 + a] = s2;
+        }
       }
     }
     __syncthreads();
     if (threadIdx.x < 2 * DIM) {
       const int a = threadIdx.x % DIM;
       const bool mx = threadIdx.x >= DIM;
-      int32_t v = wbox[0][mx ? 3 + a : a];
+      float v = wbox[0][mx ? 3 + a : a];
+      double sm = wmom[0][mx ? 3 + a : a];
 #pragma unroll
       for (int w = 1; w < TPB / WAVE; ++w) {
-        const int32_t u = wbox[w][mx ? 3 + a : a];
-        v = mx ? max(v, u) : min(v, u);
+        const float u = wbox[w][mx ? 3 + a : a];
+        v = mx ? fmaxf(v, u) : fminf(v, u);
+        if (adaptive) sm += wmom[w][mx ? 3 + a : a];
       }
       bbox_part[(size_t)blockIdx.x * 6 + (mx ? 3 : 0) + a] = v;
+      if (adaptive) mom_part[(size_t)blockIdx.x * 6 + (mx ? 3 : 0) + a] = sm;
     }
   }
 }
 
-// Per-target cell range from the propagate tiles' partial bounding boxes
-// (tiles of target t: t256_first[t] .. t256_first[t+1]-1). One block per target.
-__global__ __launch_bounds__(TPB) void k_bbox_reduce(int dim, const uint32_t *__restrict__ t256_first,
-                                                     const int32_t *__restrict__ bbox_part,
+// Cells per pixel of a target on one axis with adaptive bins: about
+// bins_per_sigma cells per standard deviation of its positions,
+// m = ceil(bins_per_sigma / sigma) in [1, bins_max] (bins_max for sigma = 0),
+// from the population variance S2/n - (S1/n)^2 in binary64.
+__device__ __forceinline__ int32_t adaptive_m(double s1, double s2, double n, double c, int32_t m_max) {
+  const double mean = s1 / n;
+  double var = s2 / n - mean * mean;
+  var = var > 0.0 ? var : 0.0;
+  const double sd = sqrt(var);
+  const double q = c / sd;  // +inf for sd = 0
+  if (!(q < (double)m_max)) return m_max;
+  const double mc = ceil(q);
+  return mc < 1.0 ? 1 : (int32_t)mc;
+}
+
+// Per-target cells per pixel and cell range from the propagate tiles' partial
+// extremes (tiles of target t: t256_first[t] .. t256_first[t+1]-1). One
+// block per target.
+__global__ __launch_bounds__(TPB) void k_bbox_reduce(Params p, const uint32_t *__restrict__ t256_first,
+                                                     const uint32_t *__restrict__ off,
+                                                     const float *__restrict__ bbox_part,
+                                                     const double *__restrict__ mom_part, int32_t *__restrict__ tm,
                                                      int32_t *__restrict__ bbox_cur,
                                                      unsigned long long *__restrict__ range,
                                                      int32_t *__restrict__ tfallback) {
-  __shared__ int32_t red[TPB / WAVE];
+  __shared__ float redf[TPB / WAVE];
+  __shared__ double redd[TPB / WAVE];
   const int t = blockIdx.x;
   const uint32_t a0 = t256_first[t], a1 = t256_first[t + 1];
+  const double n = (double)(off[t + 1] - off[t]);
   unsigned long long r = 1;
   for (int a = 0; a < 3; ++a) {
-    int32_t lo = 0, wdt = 1;
-    if (a < dim) {
-      int32_t mn = 0x7FFFFFFF, mx = -0x7FFFFFFF - 1;
+    int32_t lo = 0, wdt = 1, m = 1;
+    if (a < p.dim) {
+      float mn = INFINITY, mx = -INFINITY;
+      double s1 = 0.0, s2 = 0.0;
       for (uint32_t b = a0 + threadIdx.x; b < a1; b += TPB) {
-        mn = min(mn, bbox_part[(size_t)b * 6 + a]);
-        mx = max(mx, bbox_part[(size_t)b * 6 + 3 + a]);
+        mn = fminf(mn, bbox_part[(size_t)b * 6 + a]);
+        mx = fmaxf(mx, bbox_part[(size_t)b * 6 + 3 + a]);
+        if (p.bins_per_sigma > 0.0) {
+          s1 += mom_part[(size_t)b * 6 + a];
+          s2 += mom_part[(size_t)b * 6 + 3 + a];
+        }
       }
-      lo = block_min<TPB>(mn, red);
-      const int32_t hi = block_max<TPB>(mx, red);
+      const float fl = block_min<TPB>(mn, redf);
+      const float fh = block_max<TPB>(mx, redf);
+      m = p.m[a];
+      if (p.bins_per_sigma > 0.0) {
+        const double S1 = block_sum<TPB>(s1, redd);
+        const double S2 = block_sum<TPB>(s2, redd);
+        m = adaptive_m(S1, S2, n, p.bins_per_sigma, p.bins_max);
+      }
+      lo = cell_index(fl, m);
+      const int32_t hi = cell_index(fh, m);
       long long w64 = (long long)hi - (long long)lo + 1;
       w64 = w64 < 1 ? 1 : (w64 > 0x7FFFFFFFLL ? 0x7FFFFFFFLL : w64);  // flagged by the scan if too wide
       wdt = (int32_t)w64;
@@ -192,6 +246,7 @@ __global__ __launch_bounds__(TPB) void k_bbox_reduce(int dim, const uint32_t *__
     if (threadIdx.x == 0) {
       bbox_cur[t * 6 + a] = lo;
       bbox_cur[t * 6 + 3 + a] = wdt;
+      tm[t * 3 + a] = m;
     }
     r *= (unsigned long long)(uint32_t)wdt;
     if (r > (1ull << 40)) r = (1ull << 40);
@@ -304,7 +359,7 @@ __global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restric
     for (int q = 0; q < R; ++q) {
       int32_t c[3];
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) c[a] = cell_index(xs[a][q], p.m[a]);
+      for (int a = 0; a < DIM; ++a) c[a] = cell_index(xs[a][q], p.tm[t * 3 + a]);
       kk[q] = r0 + q * TPB + threadIdx.x < tl.i1 ? compact_key<DIM>(c, bb, kb) : KEY_EMPTY;
     }
 #pragma unroll
@@ -715,7 +770,7 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
         const uint32_t g = base + i;
         int32_t cc[3];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) cc[a] = cell_index(x[q][a], p.m[a]);
+        for (int a = 0; a < DIM; ++a) cc[a] = cell_index(x[q][a], p.tm[t * 3 + a]);
         const uint32_t k = compact_key<DIM>(cc, bb, kb);
         uint32_t lo;
         if (use_lut) {
@@ -864,12 +919,13 @@ __global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsig
     const double wsum = wt ? wacc[sidx] : 1.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      const int32_t c0 = floor_div(cell[a], p.m[a]);
+      const int32_t ma = p.tm[t * 3 + a];
+      const int32_t c0 = floor_div(cell[a], ma);
       dpix[(size_t)a * NT + sidx] = c0;
       float off;
       if (p.dummy_mode == 1) {
-        const int32_t r = cell[a] - c0 * p.m[a];  // cell within its pixel, 0..m-1
-        off = (float)(((double)r + 0.5) / (double)p.m[a] - 0.5);
+        const int32_t r = cell[a] - c0 * ma;  // cell within its pixel, 0..m-1
+        off = (float)(((double)r + 0.5) / (double)ma - 0.5);
       } else if (wt) {
         off = (float)(wacc[(size_t)(1 + a) * NT + sidx] / wsum);
       } else {
@@ -1707,11 +1763,17 @@ __global__ __launch_bounds__(TPB) void k_identity(const Tile *__restrict__ tiles
   if (i < n) anc[base + i] = i;
 }
 
-__global__ void k_dbg_keys(int dim, uint32_t NT, int m0, int m1, int m2, const float *__restrict__ s,
-                           int32_t *__restrict__ out) {
-  const int m[3] = {m0, m1, m2};
-  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < NT; g += gridDim.x * blockDim.x)
-    for (int a = 0; a < 3; ++a) out[(size_t)a * NT + g] = a < dim ? cell_index(s[(size_t)a * NT + g], m[a]) : 0;
+// Cell index of every particle with its target's cells per pixel (tm null:
+// pixels, m = 1).
+__global__ __launch_bounds__(TPB) void k_dbg_keys(int dim, uint32_t NT, const Tile *__restrict__ tiles,
+                                                  const int32_t *__restrict__ tm, const float *__restrict__ s,
+                                                  int32_t *__restrict__ out) {
+  const Tile tl = tiles[blockIdx.x];
+  const uint32_t i = tl.i0 + threadIdx.x;
+  if (i >= tl.n) return;
+  const uint32_t g = tl.base + i;
+  for (int a = 0; a < 3; ++a)
+    out[(size_t)a * NT + g] = a < dim ? cell_index(s[(size_t)a * NT + g], tm ? tm[tl.t * 3 + a] : 1) : 0;
 }
 
 template <int DIM>
@@ -1736,12 +1798,12 @@ __global__ void k_dbg_bins(Params p, const uint64_t *__restrict__ meta, const un
       double *o = (double *)out;
       const double ws = wacc[s];
       for (int a = 0; a < DIM; ++a)
-        o[(size_t)a * B + s] = (double)floor_div(cell[a], p.m[a]) + wacc[(size_t)(1 + a) * NT + s] / ws;
+        o[(size_t)a * B + s] = (double)floor_div(cell[a], p.tm[t * 3 + a]) + wacc[(size_t)(1 + a) * NT + s] / ws;
       for (int d = DIM; d < D; ++d) o[(size_t)d * B + s] = wacc[(size_t)(1 + d) * NT + s] / ws;
     } else if (what == 6) {
       double *o = (double *)out;
       for (int a = 0; a < DIM; ++a) {
-        const double c0 = (double)floor_div(cell[a], p.m[a]);
+        const double c0 = (double)floor_div(cell[a], p.tm[t * 3 + a]);
         o[(size_t)a * B + s] = c0 + (double)(long long)acc[(size_t)(1 + a) * NT + s] / (double)FX_POS / n;
       }
       for (int a = 0; a < DIM; ++a)

@@ -25,7 +25,7 @@ constexpr size_t ALIGN = 256;
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
       ll, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
-      bbox_part, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
+      bbox_part, mom_part, tm, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off, chunk_par;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
@@ -73,6 +73,9 @@ bool valid_config(const pcsir_config *c, std::string *why) {
   for (int d = 0; d < 2 * c->dim + 1; ++d)
     if (!(c->proc_sigma[d] >= 0.0f)) return bad("proc_sigma must be >= 0");
   if (!(c->neff_threshold >= 0.0)) return bad("neff_threshold must be >= 0 (above 1: resample every frame)");
+  if (!(c->bins_per_sigma >= 0.0) || !std::isfinite(c->bins_per_sigma))
+    return bad("bins_per_sigma must be finite and >= 0 (0: the fixed bins_per_px)");
+  if (c->bins_per_sigma > 0.0 && (c->bins_max < 1 || c->bins_max > 4096)) return bad("bins_max must lie in [1, 4096]");
   return true;
 }
 
@@ -171,6 +174,8 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.tcnt = take(4 * T);
   L.seg_first = take(4 * (T + 1));
   L.bbox_part = take(4 * 6 * (size_t)L.n256);
+  L.mom_part = take(8 * 6 * (size_t)L.n256);
+  L.tm = take(4 * 3 * T);
   L.range = take(8 * T);
   L.bbox_cur = take(4 * 6 * T);
   L.kbase = take(4 * (T + 1));
@@ -266,6 +271,8 @@ Params make_params(const pcsir_config *c, uint32_t NT) {
   p.T = c->n_targets;
   p.NT = NT;
   for (int a = 0; a < 3; ++a) p.m[a] = a < c->dim ? c->bins_per_px[a] : 1;
+  p.bins_per_sigma = c->bins_per_sigma;
+  p.bins_max = c->bins_max;
   p.P = c->patch;
   p.R = (c->patch - 1) / 2;
   p.q = c->quad;
@@ -406,11 +413,12 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   if (keep) k_copy_i32<<<(p.T + TPB - 1) / TPB, TPB, 0, st>>>(tuni, c->at<int32_t>(L.tuni_next), (uint32_t)p.T);
   mark(c, "propagate");
   k_propagate<DIM, true><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc,
-                                                 c->at<int32_t>(L.bbox_part), c->at<unsigned long long>(L.acc), meta);
+                                                 c->at<float>(L.bbox_part), c->at<double>(L.mom_part),
+                                                 c->at<unsigned long long>(L.acc), meta);
   mark(c, "bbox");
-  k_bbox_reduce<<<p.T, TPB, 0, st>>>(p.dim, c->at<uint32_t>(L.t256_first), c->at<int32_t>(L.bbox_part),
-                                     c->at<int32_t>(L.bbox_cur), c->at<unsigned long long>(L.range),
-                                     c->at<int32_t>(L.tfb));
+  k_bbox_reduce<<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.t256_first), off, c->at<float>(L.bbox_part),
+                                     c->at<double>(L.mom_part), c->at<int32_t>(L.tm), c->at<int32_t>(L.bbox_cur),
+                                     c->at<unsigned long long>(L.range), c->at<int32_t>(L.tfb));
   k_bbox_scan<<<1, TPB, 0, st>>>(p.T, c->at<unsigned long long>(L.range), c->at<uint32_t>(L.kbase), meta,
                                  c->tune.digit_bits);
   mark(c, "keys");
@@ -523,7 +531,7 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
                                                       (uint32_t)p.T);
   mark(c, "propagate");
   k_propagate<DIM, false><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc, nullptr, nullptr,
-                                                  meta);
+                                                  nullptr, meta);
   LikInput in;
   memset(&in, 0, sizeof(in));
   in.state = sout;
@@ -720,6 +728,7 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   c->nB = (uint32_t)c->tb.tB.size();
   c->p = make_params(&c->cfg, c->NT);
   c->p.bbox_cur = c->at<int32_t>(c->L.bbox_cur);
+  c->p.tm = c->at<int32_t>(c->L.tm);
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) {
     int cus = 0;
@@ -869,10 +878,15 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *c, int32_t what, void *dst, size_t byte
     case PCSIR_DUMP_KEYS: {
       if (!need(4 * 3 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
       // SIR: the pixel index (cells with m = 1) that centres each particle's window
-      const int m0 = c->last_sir ? 1 : c->p.m[0], m1 = c->last_sir ? 1 : c->p.m[1], m2 = c->last_sir ? 1 : c->p.m[2];
-      k_dbg_keys<<<gb, TPB, 0, st>>>(c->p.dim, (uint32_t)NT, m0, m1, m2, prop, (int32_t *)dst);
+      k_dbg_keys<<<L.n256, TPB, 0, st>>>(c->p.dim, (uint32_t)NT, c->at<Tile>(L.tiles256),
+                                         c->last_sir ? nullptr : c->at<int32_t>(L.tm), prop, (int32_t *)dst);
       break;
     }
+    case PCSIR_DUMP_BINS_PER_PX:
+      if (c->last_sir) return fail(c, PCSIR_E_STATE, "bins exist only after pcsir_step");
+      if (!need(4 * 3 * T)) return fail(c, PCSIR_E_INVAL, "buffer too small");
+      e = hipMemcpyAsync(dst, c->at<int32_t>(L.tm), 4 * 3 * T, hipMemcpyDeviceToDevice, st);
+      break;
     case PCSIR_DUMP_BIN_TARGET:
     case PCSIR_DUMP_BIN_KEY:
     case PCSIR_DUMP_BIN_N:

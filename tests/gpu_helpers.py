@@ -27,6 +27,8 @@ Tolerances (derived in the design notes from the FP32 arithmetic of the path):
 """
 from __future__ import annotations
 
+import dataclasses
+import math
 import sys
 
 import numpy as np
@@ -96,6 +98,7 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
     cdf_gpu = f.dump("cdf").cpu().numpy()
     s_gpu = f.dump("resample").cpu().numpy().astype(np.int64)
     if not sir:
+        m_gpu = f.dump("bins_per_px").cpu().numpy()
         counts = f.dump("counts").cpu().numpy()
         b_t = f.dump("bin_target").cpu().numpy()
         b_key = f.dump("bin_key").cpu().numpy()
@@ -122,7 +125,19 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
             tol = 1e-6 * np.abs(op.astype(np.float64)) + 2e-6
             assert np.all(err <= tol), f"target {t}: propagate off by {err.max()}"
             dev["prop"] = max(dev["prop"], float(err.max()))
-        r = oracle.weigh(mdl, fr, prop[:, a:b], sir=sir)
+        mdl_t = mdl
+        if not sir and cfg.bins_per_sigma > 0:
+            # adaptive bins: the GPU's cells per pixel against the rule; a
+            # variance within rounding of a step of the rule may go either way
+            m_o, var = oracle.adaptive_bins(prop[:, a:b], dim, cfg.bins_per_sigma, cfg.bins_max)
+            for ax in range(dim):
+                if m_gpu[t, ax] != m_o[ax]:
+                    sd = math.sqrt(var[ax])
+                    step = cfg.bins_per_sigma / min(m_gpu[t, ax], m_o[ax])
+                    assert abs(sd - step) <= 1e-6 * step, f"target {t} axis {ax}: m {m_gpu[t, ax]} vs {m_o[ax]}"
+            dev["adaptive_m"] = dev.get("adaptive_m", []) + [tuple(int(v) for v in m_gpu[t])]
+            mdl_t = dataclasses.replace(mdl, m=tuple(int(v) for v in m_gpu[t]))
+        r = oracle.weigh(mdl_t, fr, prop[:, a:b], sir=sir)
         assert np.array_equal(keys[:dim, a:b], r["keys"][:dim]), f"target {t}: keys differ"
         B = r["B"]
         if sir:
