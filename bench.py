@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--check", type=float, default=0.01, help="share of dummies checked exactly per frame")
     ap.add_argument("--tol", type=float, default=2.0, help="surrogate fallback threshold (nats)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--bins-per-sigma", type=float, default=2.0,
+                    help="the extra adaptive-bin mode: about this many bins per standard deviation (0: skip)")
+    ap.add_argument("--bins-max", type=int, default=8, help="adaptive bins: largest cells per pixel")
     ap.add_argument("--neff-threshold", type=float, default=0.5,
                     help="the extra kept-weight mode: resample when N_eff < this fraction of N (negative: skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -226,9 +229,9 @@ def main():
         m = int(round(1.0 / h))
         return (m, m, m if dim == 3 else 1)
 
-    def make(wk, init_state, h, lik, seed_off=500, thr=float("inf")):
+    def make(wk, init_state, h, lik, seed_off=500, thr=float("inf"), **kw):
         cfg = Config.from_workload(wk, bins_per_px=bins(h), lik_mode=lik, seed=wk.seed + seed_off,
-                                   neff_threshold=thr)
+                                   neff_threshold=thr, **kw)
         return Filter(cfg, init_state)
 
     def frame(k):
@@ -260,10 +263,10 @@ def main():
         initr = torch.from_numpy(synth.initial_particles(wr, trr[0], wr.counts())).to(dev)
         seqs.append((wr, trr, frr, initr))
 
-    def track_rmse(mode_sir, h, lik, params=None, scales=None, stats=None, thr=float("inf")):
+    def track_rmse(mode_sir, h, lik, params=None, scales=None, stats=None, thr=float("inf"), **kw):
         out = []
         for wr, trr, frr, initr in seqs:
-            f = make(wr, initr, h, lik, thr=thr)
+            f = make(wr, initr, h, lik, thr=thr, **kw)
             if params is not None:
                 f.set_surrogate(params, scales, args.check, args.tol)
             est = np.zeros((Kmatch, T, D))
@@ -360,8 +363,8 @@ def main():
     # ---- 3. timed regions
     tuned = {}
 
-    def timed(sir, h, lik, with_events, autotune=False, thr=float("inf")):
-        f = make(w, init, h, lik, thr=thr)
+    def timed(sir, h, lik, with_events, autotune=False, thr=float("inf"), **kw):
+        f = make(w, init, h, lik, thr=thr, **kw)
         if lik >= LIK_SURR_BF16:
             f.set_surrogate(params, scales if lik == LIK_SURR_FP8 else None, args.check, args.tol)
         if not sir and "shapes" in tuned:
@@ -416,6 +419,14 @@ def main():
             key = f"h={h_match},neff<{thr}N"
             rmse[key], rmse_stats[key] = float(np.mean(a)), summary(a)
             log(f"rmse h={h_match} with N_eff threshold {thr}: {rmse_stats[key]}")
+    if args.bins_per_sigma > 0:
+        ad = dict(bins_per_sigma=args.bins_per_sigma, bins_max=args.bins_max)
+        runs["pcsir_sep_adaptive"] = timed(False, h_match, LIK_SEP, True, **ad)
+        if not args.no_match:
+            a = track_rmse(False, h_match, LIK_SEP, **ad)
+            key = f"adaptive,{args.bins_per_sigma}/sd,max{args.bins_max}"
+            rmse[key], rmse_stats[key] = float(np.mean(a)), summary(a)
+            log(f"rmse with adaptive bins: {rmse_stats[key]}")
     if params is not None:
         runs["surr_bf16"] = timed(False, h_match, LIK_SURR_BF16, True)
         runs["surr_fp8"] = timed(False, h_match, LIK_SURR_FP8, True)
