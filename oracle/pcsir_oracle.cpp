@@ -88,7 +88,8 @@ typedef struct {
   int32_t patch;      /* P: side of the square likelihood window, odd */
   int32_t quad;       /* q: midpoint sub-samples per pixel axis */
   int32_t psf;        /* 0: Gaussian PSF (Eq. object); 1: astigmatic PSF, sigma_x(z), sigma_y(z) */
-  int32_t dummy_mode; /* 0: centre of mass of the bin (pcSIR-CoM); 1: geometric bin centre (CoC) */
+  int32_t dummy_mode; /* 0: centre of mass of the bin (pcSIR-CoM); 1: geometric bin centre (CoC);
+                         2: CoM with the members' position covariance (second order, 2D) */
   double sigma_psf;   /* PSF sigma in pixels (3D: sigma at focus) */
   double astig_gamma; /* 3D: focal offset of the two axes (pixels) */
   double astig_d;     /* 3D: depth scale (pixels) */
@@ -264,7 +265,9 @@ double orc_loglik(const orc_model *mdl, const float *frame, int32_t H, int32_t W
  *  sir = 1: classical SIR (Alg. SIR): every particle is evaluated.
  *  sir = 0: pcSIR (Alg. pcSIR): particles are assigned to bins; each occupied
  *           bin gets one dummy whose state is the mean state of its members
- *           (CoM; or, with dummy_mode 1, the bin centre for the positions);
+ *           (CoM; or, with dummy_mode 1, the bin centre for the positions;
+ *           dummy_mode 2 adds the second-order term of the members' position
+ *           covariance to the dummy's log-likelihood, see below);
  *           the likelihood is evaluated on the dummy only and its value is
  *           copied to every member.
  * The log-weight of particle i is logw_prev[i] + its likelihood term
@@ -287,6 +290,7 @@ int64_t orc_weigh(const orc_model *mdl, const float *frame, int32_t H, int32_t W
   const int D = 2 * dim + 1;
   const int32_t m1[3] = {1, 1, 1};
   const int32_t *mm = sir ? m1 : mdl->m;
+  std::vector<double> cov;  /* second-order dummies: position covariance per bin (xx, yy, xy) */
 
   for (int64_t i = 0; i < N; ++i) {
     for (int a = 0; a < 3; ++a) {
@@ -308,6 +312,7 @@ int64_t orc_weigh(const orc_model *mdl, const float *frame, int32_t H, int32_t W
   } else {
     /* Bins ordered by (kz, ky, kx). */
     std::map<std::tuple<int32_t, int32_t, int32_t>, std::vector<int64_t>> bins;
+    if (mdl->dummy_mode == 2) cov.assign(3 * (size_t)N, 0.0);
     for (int64_t i = 0; i < N; ++i) {
       auto key = std::make_tuple(out->keys[2 * N + i], out->keys[1 * N + i], out->keys[0 * N + i]);
       bins[key].push_back(i);
@@ -341,6 +346,26 @@ int64_t orc_weigh(const orc_model *mdl, const float *frame, int32_t H, int32_t W
           out->bin_mean[(int64_t)a * N + B] = (kk + 0.5) / (double)mdl->m[a] - 0.5;
         }
       }
+      if (mdl->dummy_mode == 2) {
+        /* covariance of the members' positions about the dummy, weighted
+           as the mean is: xx, yy, xy */
+        double mx = -INFINITY;
+        if (logw_prev)
+          for (int64_t i : mem) mx = logw_prev[i] > mx ? logw_prev[i] : mx;
+        double ws = 0.0, sxx = 0.0, syy = 0.0, sxy = 0.0;
+        const double ux = out->bin_mean[0 * N + B], uy = out->bin_mean[1 * N + B];
+        for (int64_t i : mem) {
+          const double wi = logw_prev ? std::exp(logw_prev[i] - mx) : 1.0;
+          const double ddx = (double)state[0 * N + i] - ux, ddy = (double)state[1 * N + i] - uy;
+          ws += wi;
+          sxx += wi * ddx * ddx;
+          syy += wi * ddy * ddy;
+          sxy += wi * ddx * ddy;
+        }
+        cov[3 * (size_t)B + 0] = sxx / ws;
+        cov[3 * (size_t)B + 1] = syy / ws;
+        cov[3 * (size_t)B + 2] = sxy / ws;
+      }
       for (int64_t i : mem) out->bin_of[i] = B;
       ++B;
     }
@@ -351,8 +376,29 @@ int64_t orc_weigh(const orc_model *mdl, const float *frame, int32_t H, int32_t W
     int64_t c0 = floor_div(out->bin_key[0 * N + b], mm[0]);
     int64_t r0 = floor_div(out->bin_key[1 * N + b], mm[1]);
     double zh = dim == 3 ? out->bin_mean[2 * N + b] : 0.0;
-    out->ll[b] = orc_loglik(mdl, frame, H, W, c0, r0, out->bin_mean[0 * N + b], out->bin_mean[1 * N + b],
-                            zh, out->bin_mean[(int64_t)(2 * dim) * N + b]);
+    const double ux = out->bin_mean[0 * N + b], uy = out->bin_mean[1 * N + b];
+    const double I0 = out->bin_mean[(int64_t)(2 * dim) * N + b];
+    out->ll[b] = orc_loglik(mdl, frame, H, W, c0, r0, ux, uy, zh, I0);
+    if (!sir && mdl->dummy_mode == 2) {
+      /* second order: the bin's log-likelihood is the log of the members'
+         mean likelihood to second order in their spread, ell(mu) +
+         tr(H S)/2 + g'Sg/2, with g and H the gradient and Hessian of the
+         log-likelihood in the bin's (fixed) window, by central differences
+         of half a cell */
+      const double dx = 0.5 / (double)mm[0], dy = 0.5 / (double)mm[1];
+      auto L = [&](double sx, double sy) {
+        return orc_loglik(mdl, frame, H, W, c0, r0, ux + sx * dx, uy + sy * dy, zh, I0);
+      };
+      const double l0 = out->ll[b];
+      const double lxp = L(1, 0), lxm = L(-1, 0), lyp = L(0, 1), lym = L(0, -1);
+      const double lpp = L(1, 1), lpm = L(1, -1), lmp = L(-1, 1), lmm = L(-1, -1);
+      const double gx = (lxp - lxm) / (2.0 * dx), gy = (lyp - lym) / (2.0 * dy);
+      const double hxx = (lxp - 2.0 * l0 + lxm) / (dx * dx), hyy = (lyp - 2.0 * l0 + lym) / (dy * dy);
+      const double hxy = (lpp - lpm - lmp + lmm) / (4.0 * dx * dy);
+      const double sxx = cov[3 * (size_t)b], syy = cov[3 * (size_t)b + 1], sxy = cov[3 * (size_t)b + 2];
+      out->ll[b] = l0 + 0.5 * (hxx * sxx + hyy * syy + 2.0 * hxy * sxy) +
+                   0.5 * (gx * gx * sxx + gy * gy * syy + 2.0 * gx * gy * sxy);
+    }
   }
 
   /* Weights: copy of the bin's likelihood to every member, then normalise. */
