@@ -74,8 +74,14 @@ typedef enum {
 typedef enum { PCSIR_PSF_GAUSS2D = 0, PCSIR_PSF_ASTIG3D = 1 } pcsir_psf;
 
 /* Dummy particle of a bin (Alg. pcSIR: mean state of the members; Sec. 5.5
- * also uses the geometric cell centre, "CoC", for the positions). */
-typedef enum { PCSIR_DUMMY_COM = 0, PCSIR_DUMMY_COC = 1 } pcsir_dummy;
+ * also uses the geometric cell centre, "CoC", for the positions).
+ * COM2: the CoM dummy also carries its members' position covariance S (Sec. 4
+ * notes that a dummy could store higher moments): the bin's log-likelihood
+ * is ell(mu) + tr(H S)/2 + g'S g/2, the log of the members' mean likelihood
+ * to second order in their spread, with g and H from nine evaluations of
+ * the dummy's window at shifts of half a cell (central differences). 2D,
+ * exact likelihood modes and every-frame resampling only. */
+typedef enum { PCSIR_DUMMY_COM = 0, PCSIR_DUMMY_COC = 1, PCSIR_DUMMY_COM2 = 2 } pcsir_dummy;
 
 typedef struct {
   uint32_t abi_version;        /* must equal PCSIR_ABI_VERSION */
@@ -119,7 +125,7 @@ typedef struct {
 } pcsir_config;
 
 /* Bytes of device workspace that a context with this config needs (0 if the
- * config is invalid). Grows linearly with sum N_t (about 150 B per particle
+ * config is invalid). Grows linearly with sum N_t (about 175 B per particle
  * in 2D) and with T. */
 size_t pcsir_workspace_bytes(const pcsir_config *cfg);
 

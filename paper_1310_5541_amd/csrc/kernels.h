@@ -18,6 +18,7 @@ constexpr int BIN_TILES = 4;        // scan tiles of one target per block of the
 constexpr float FX_POS = 4294967296.0f;  // 2^32: offsets from the cell's pixel, |d| <= 1/2
 constexpr float FX_VEL = 16777216.0f;    // 2^24: velocities, |v| < 2^7
 constexpr float FX_INT = 1048576.0f;     // 2^20: intensity, |I| < 2^15
+constexpr double FX_SQ = 4294967296.0;   // 2^32: second moments of the offsets, (d 2^16)^2 rounded
 constexpr float LIM_VEL = 128.0f;
 constexpr float LIM_INT = 32768.0f;
 
@@ -46,6 +47,7 @@ struct Params {
   double bins_per_sigma;    // > 0: adaptive bin size, about this many bins per standard deviation
   int bins_max;             // adaptive: at most this many cells per pixel
   const int32_t *tm;        // [T][3] cells per pixel of every target in the current frame
+  int acc_rows;             // rows of the bin sums (1 + D, plus 3 second moments for second-order dummies)
   int P, R, q;
   int psf, dummy_mode, per_target_frames, H, W;
   float sigma_psf, astig_gamma, astig_d, i_bg;
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
       const uint32_t dirty = (uint32_t)meta[META_DIRTY];
       if (g < dirty) {
 #pragma unroll
-        for (int c = 0; c < 1 + D; ++c) acc[(size_t)c * p.NT + g] = 0ull;
+        for (int c = 0; c < p.acc_rows; ++c) acc[(size_t)c * p.NT + g] = 0ull;
       }
     }
   }
@@ -705,13 +707,15 @@ __global__ __launch_bounds__(TPB) void k_seg_first(int T, const uint32_t *__rest
 // search and accumulate in LDS with 64-bit integer atomics, then each bin of
 // the chunk is flushed to HBM once. Integer sums are exact, so the result
 // does not depend on order. Also writes every particle's bin number.
-template <int DIM>
+// MOM2 (second-order dummies, 2D) adds the second moments of the offsets:
+// (dx 2^16)^2, (dy 2^16)^2 and (dx 2^16)(dy 2^16), each rounded to an integer.
+template <int DIM, bool MOM2 = false>
 struct BinLds {
-  static constexpr int NC = 2 + 2 * DIM;                // count + D components
-  static constexpr int BINS = DIM == 2 ? 1024 : 896;    // table fits in 64 KB with the keys
+  static constexpr int NC = 2 + 2 * DIM + (MOM2 ? 3 : 0);                // count + D components (+ 3)
+  static constexpr int BINS = MOM2 ? 768 : (DIM == 2 ? 1024 : 896);      // table fits in 64 KB with the keys
 };
 
-template <int DIM>
+template <int DIM, bool MOM2 = false>
 __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__restrict__ tiles,
                                                   const uint32_t *__restrict__ off, const float *__restrict__ s,
                                                   const int32_t *__restrict__ bbox_cur,
@@ -722,11 +726,12 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
                                                   uint64_t *__restrict__ meta, const uint32_t *__restrict__ lut,
                                                   uint64_t lut_cap) {
   constexpr int D = 2 * DIM + 1;
-  constexpr int NC = BinLds<DIM>::NC;
+  constexpr int NC = BinLds<DIM, MOM2>::NC;
+  static_assert(!MOM2 || DIM == 2, "second moments in 2D only");
   // with the cell -> bin table of this frame (total key range within its
   // capacity) a particle's bin is one load; otherwise a binary search
   const bool use_lut = meta[META_RANGE] <= lut_cap;
-  constexpr int BINS = BinLds<DIM>::BINS;
+  constexpr int BINS = BinLds<DIM, MOM2>::BINS;
   constexpr int R = 8;  // particles per thread per round, loaded together
   __shared__ uint32_t bkey[BINS];
   __shared__ unsigned long long bacc[NC][BINS];
@@ -795,11 +800,20 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
         segid[g] = s0 + c0 + lo;
         long long val[NC];
         val[0] = 1;
+        float dpos[DIM];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
           // x - pix is exact and in [-1/2, 1/2), so the scaled value is in [-2^31, 2^31)
           const float pix = (float)cell_index(x[q][a], 1);
-          val[1 + a] = (long long)__float2int_rn((x[q][a] - pix) * FX_POS);
+          dpos[a] = x[q][a] - pix;
+          val[1 + a] = (long long)__float2int_rn(dpos[a] * FX_POS);
+        }
+        if (MOM2) {
+          // d 2^16 is exact; products of two such values are within 2^30
+          const double ux = (double)(dpos[0] * 65536.0f), uy = (double)(dpos[1 % DIM] * 65536.0f);
+          val[NC - 3] = __double2ll_rn(ux * ux);
+          val[NC - 2] = __double2ll_rn(uy * uy);
+          val[NC - 1] = __double2ll_rn(ux * uy);
         }
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -1016,7 +1030,10 @@ __device__ __forceinline__ float sub_offset(int a, int q) { return (float)(2 * a
 // Evaluation sets of k_lik: every dummy / particle; the dummies picked for
 // the surrogate's exact check (list, see k_surr_pick); the dummies of targets
 // whose check failed (list, see k_surr_fallback_list).
-enum { LIK_ALL = 0, LIK_CHECK = 1, LIK_FALLBACK = 2 };
+// LIK_STENCIL: second-order dummies; entry 9 b + s evaluates dummy b at the
+// position shifted by (s % 3 - 1, s / 3 - 1) half cells, in the dummy's
+// window, into ll[s NT + b].
+enum { LIK_ALL = 0, LIK_CHECK = 1, LIK_FALLBACK = 2, LIK_STENCIL = 3 };
 struct SurrCheck {
   float fraction;            // share of dummies checked per frame
   float tol;                 // largest accepted |l_surrogate - l_exact| (nats)
@@ -1123,13 +1140,14 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
                                              uint64_t *__restrict__ stats = nullptr) {
   const float *__restrict__ frame = desc->frame;
   const uint32_t E = SIR ? p.NT
-                         : (uint32_t)meta[MODE == LIK_CHECK ? META_NCHK : (MODE == LIK_FALLBACK ? META_NFB : META_B)];
+                         : (uint32_t)meta[MODE == LIK_CHECK ? META_NCHK : (MODE == LIK_FALLBACK ? META_NFB : META_B)] *
+                               (MODE == LIK_STENCIL ? 9u : 1u);
   const int lane = lane_id();
   const int P = p.P, R = p.R, P2 = P * P;
   const int q = Q ? Q : p.q;
   const ExpScale ks_flat = psf_scale(p, 0.0f);  // the scale of a z-independent PSF, formed once
   for (uint32_t idx = blockIdx.x * LIK_WAVES + wave_id(); idx < E; idx += gridDim.x * LIK_WAVES) {
-    const uint32_t e = MODE == LIK_ALL ? idx : chk.list[idx];
+    const uint32_t e = MODE == LIK_ALL ? idx : (MODE == LIK_STENCIL ? idx / 9u : chk.list[idx]);
     int t;
     int32_t c0, r0;
     float dx, dy, I0, zpos = 0.0f;
@@ -1157,6 +1175,12 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       dy = in.doff[(size_t)p.NT + e];
       if (DIM == 3) zpos = (float)in.dpix[(size_t)2 * p.NT + e] + in.doff[(size_t)2 * p.NT + e];
       I0 = in.dint[e];
+      if (MODE == LIK_STENCIL) {
+        // the shifted position, formed in binary64 and rounded once
+        const int sidx = (int)(idx - 9u * e);
+        dx = (float)((double)dx + (double)(sidx % 3 - 1) * (0.5 / (double)p.tm[t * 3 + 0]));
+        dy = (float)((double)dy + (double)(sidx / 3 - 1) * (0.5 / (double)p.tm[t * 3 + 1]));
+      }
     }
     const ExpScale ks = (DIM == 3 && p.psf == 1) ? psf_scale(p, zpos) : ks_flat;
     const float Iq = I0 / (float)(q * q);
@@ -1296,7 +1320,38 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       }
       chk.err[idx] = d != d ? INFINITY : d;
     }
-    if (lane == 0) ll[e] = lx;
+    if (lane == 0) ll[MODE == LIK_STENCIL ? (size_t)(idx - 9u * e) * p.NT + e : (size_t)e] = lx;
+  }
+}
+
+// Second-order dummies: each bin's log-likelihood from the nine stencil
+// values (ll9[s][b], s = 3 (sy + 1) + (sx + 1) for shifts of half a cell)
+// and the members' position covariance from the fixed-point bin sums:
+// ell(mu) + tr(H S)/2 + g'S g/2 with central differences for g and H.
+__global__ __launch_bounds__(TPB) void k_second_order(Params p, const uint64_t *__restrict__ meta,
+                                                      const unsigned long long *__restrict__ acc,
+                                                      const int32_t *__restrict__ seg_t,
+                                                      const double *__restrict__ ll9, double *__restrict__ ll) {
+  const uint32_t B = (uint32_t)meta[META_B];
+  const uint32_t NT = p.NT;
+  for (uint32_t b = blockIdx.x * TPB + threadIdx.x; b < B; b += gridDim.x * TPB) {
+    const int t = seg_t[b];
+    const double dx = 0.5 / (double)p.tm[t * 3 + 0], dy = 0.5 / (double)p.tm[t * 3 + 1];
+    double l[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) l[s] = ll9[(size_t)s * NT + b];
+    const double gx = (l[5] - l[3]) / (2.0 * dx), gy = (l[7] - l[1]) / (2.0 * dy);
+    const double hxx = (l[5] - 2.0 * l[4] + l[3]) / (dx * dx), hyy = (l[7] - 2.0 * l[4] + l[1]) / (dy * dy);
+    const double hxy = (l[8] - l[6] - l[2] + l[0]) / (4.0 * dx * dy);
+    // covariance: second moments of x - pixel (scale 2^32) minus the square of the mean offset
+    const double n = (double)(long long)acc[b];
+    const double mx = (double)(long long)acc[(size_t)1 * NT + b] / (double)FX_POS / n;
+    const double my = (double)(long long)acc[(size_t)2 * NT + b] / (double)FX_POS / n;
+    const double sxx = (double)(long long)acc[(size_t)6 * NT + b] / (double)FX_SQ / n - mx * mx;
+    const double syy = (double)(long long)acc[(size_t)7 * NT + b] / (double)FX_SQ / n - my * my;
+    const double sxy = (double)(long long)acc[(size_t)8 * NT + b] / (double)FX_SQ / n - mx * my;
+    ll[b] = l[4] + 0.5 * (hxx * sxx + hyy * syy + 2.0 * hxy * sxy) +
+            0.5 * (gx * gx * sxx + gy * gy * syy + 2.0 * gx * gy * sxy);
   }
 }
 

@@ -24,7 +24,7 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
-      ll, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
+      ll, ll9, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
       bbox_part, mom_part, tm, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off, chunk_par;
   size_t total;
@@ -63,7 +63,8 @@ bool valid_config(const pcsir_config *c, std::string *why) {
   if (c->quad < 1 || c->quad > 16) return bad("quad must lie in [1, 16]");
   if (c->psf != PCSIR_PSF_GAUSS2D && c->psf != PCSIR_PSF_ASTIG3D) return bad("unknown psf");
   if (c->psf == PCSIR_PSF_ASTIG3D && c->dim != 3) return bad("astigmatic PSF needs dim == 3");
-  if (c->dummy_mode != PCSIR_DUMMY_COM && c->dummy_mode != PCSIR_DUMMY_COC) return bad("unknown dummy_mode");
+  if (c->dummy_mode != PCSIR_DUMMY_COM && c->dummy_mode != PCSIR_DUMMY_COC && c->dummy_mode != PCSIR_DUMMY_COM2)
+    return bad("unknown dummy_mode");
   if (c->lik_mode < PCSIR_LIK_DIRECT || c->lik_mode > PCSIR_LIK_SURR_FP8) return bad("unknown lik_mode");
   if (c->lik_mode >= PCSIR_LIK_SURR_BF16 && c->patch * c->patch + 2 * c->dim + 1 > MLP_F)
     return bad("surrogate features (patch^2 + 2 dim + 1) exceed 256");
@@ -73,6 +74,9 @@ bool valid_config(const pcsir_config *c, std::string *why) {
   for (int d = 0; d < 2 * c->dim + 1; ++d)
     if (!(c->proc_sigma[d] >= 0.0f)) return bad("proc_sigma must be >= 0");
   if (!(c->neff_threshold >= 0.0)) return bad("neff_threshold must be >= 0 (above 1: resample every frame)");
+  if (c->dummy_mode == PCSIR_DUMMY_COM2 &&
+      (c->dim != 2 || c->lik_mode > PCSIR_LIK_SEPARABLE || c->neff_threshold <= 1.0))
+    return bad("second-order dummies need dim 2, an exact likelihood and resampling every frame");
   if (!(c->bins_per_sigma >= 0.0) || !std::isfinite(c->bins_per_sigma))
     return bad("bins_per_sigma must be finite and >= 0 (0: the fixed bins_per_px)");
   if (c->bins_per_sigma > 0.0 && (c->bins_max < 1 || c->bins_max > 4096)) return bad("bins_max must lie in [1, 4096]");
@@ -150,7 +154,9 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.hist = take(4 * (size_t)MAX_BUCKETS * (size_t)L.G);
   L.dtot = take(4 * (size_t)MAX_BUCKETS);
   L.chunk_heads = take(4 * (size_t)L.G);
-  L.acc = take(8 * (1 + D) * NT);
+  const size_t acc_rows = 1 + D + (c->dummy_mode == PCSIR_DUMMY_COM2 ? 3 : 0);
+  L.acc = take(8 * acc_rows * NT);
+  L.ll9 = c->dummy_mode == PCSIR_DUMMY_COM2 ? take(8 * 9 * NT) : 0;
   L.seg_key = take(4 * NT);
   L.seg_t = take(4 * NT);
   L.segid = take(4 * NT);
@@ -272,6 +278,7 @@ Params make_params(const pcsir_config *c, uint32_t NT) {
   p.NT = NT;
   for (int a = 0; a < 3; ++a) p.m[a] = a < c->dim ? c->bins_per_px[a] : 1;
   p.bins_per_sigma = c->bins_per_sigma;
+  p.acc_rows = 1 + p.D + (c->dummy_mode == PCSIR_DUMMY_COM2 ? 3 : 0);
   p.bins_max = c->bins_max;
   p.P = c->patch;
   p.R = (c->patch - 1) / 2;
@@ -455,10 +462,23 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   k_seg_first<<<(p.T + 1 + TPB - 1) / TPB, TPB, 0, st>>>(p.T, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                                          meta, c->at<uint32_t>(L.seg_first));
   mark(c, "bin_sums");
-  k_bin_sums<DIM><<<c->nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+  if constexpr (DIM == 2) {
+    if (c->cfg.dummy_mode == PCSIR_DUMMY_COM2)
+      k_bin_sums<DIM, true><<<c->nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
                                         c->at<uint32_t>(L.lut), L.lut_cap);
+    else
+      k_bin_sums<DIM><<<c->nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+                                        c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
+                                        c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
+                                        c->at<uint32_t>(L.lut), L.lut_cap);
+  } else {
+    k_bin_sums<DIM><<<c->nB, TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+                                        c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
+                                        c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
+                                        c->at<uint32_t>(L.lut), L.lut_cap);
+  }
   if (keep) {
     mark(c, "bin_wsums");
     k_wsum_clear<<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(p.NT, p.D, meta, wacc);
@@ -482,7 +502,19 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   if (c->cfg.lik_mode >= PCSIR_LIK_SURR_BF16) {
     launch_surrogate<DIM>(c, in, st);
   } else {
-    launch_lik<DIM, false, SEP>(c, in, st);
+    if (c->cfg.dummy_mode == PCSIR_DUMMY_COM2) {
+      // nine shifted evaluations per dummy, then the second-order combination
+      const uint32_t grid = grid_stride_blocks(c, 9 * p.NT, LIK_WAVES);
+      double *ll9 = c->at<double>(L.ll9);
+      if (SEP)
+        k_lik<DIM, false, true, 0, LIK_STENCIL><<<grid, TPB, 0, st>>>(p, in, meta, desc, ll9);
+      else
+        k_lik<DIM, false, false, 0, LIK_STENCIL><<<grid, TPB, 0, st>>>(p, in, meta, desc, ll9);
+      k_second_order<<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(p, meta, acc, in.seg_t, ll9,
+                                                                      c->at<double>(L.ll));
+    } else {
+      launch_lik<DIM, false, SEP>(c, in, st);
+    }
   }
   mark(c, "normalise");
   WeightSrc ws = weight_src(c);
@@ -753,7 +785,7 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tflag, 0, 4 * (size_t)T, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tsse, 0, 8 * (size_t)T, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tcnt, 0, 4 * (size_t)T, c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.acc, 0, 8 * (size_t)(1 + D) * c->NT, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.acc, 0, 8 * (size_t)c->p.acc_rows * c->NT, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->state(0), init_state_dev, 4 * (size_t)D * c->NT, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) {

@@ -58,9 +58,11 @@ def exempt_mask(cdf, s, theta, eps):
     return (np.abs(hi - theta) <= eps) | (np.abs(lo - theta) <= eps)
 
 
-def weight_bound(ll_of_particle, wo):
-    """Largest |w_gpu - w_oracle| per particle that the log-likelihood tolerance allows."""
-    tl = LL_ATOL + LL_RTOL * np.abs(ll_of_particle)
+def weight_bound(ll_of_particle, wo, tl=None):
+    """Largest |w_gpu - w_oracle| per particle that the log-likelihood tolerance
+    (tl per particle; by default that of the log-likelihood row) allows."""
+    if tl is None:
+        tl = LL_ATOL + LL_RTOL * np.abs(ll_of_particle)
     return 1.01 * (tl + np.sum(wo * tl)) * wo + 1e-12 * wo.max()
 
 
@@ -163,13 +165,30 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
             ll_g = ll_gpu[gsl].astype(np.float64)
             dev["B"] += B
         d_ll = np.abs(ll_g - ll_o)
-        bad = d_ll > LL_ATOL + LL_RTOL * np.abs(ll_o)
+        tol_ll = LL_ATOL + LL_RTOL * np.abs(ll_o)
+        if not sir and cfg.dummy_mode == 2:
+            # second-order dummies: nine evaluations, each within tol, enter through
+            # central differences of step delta = half a cell, with |S| <= delta^2:
+            # |error| <= 6 tol + 2 tol delta (|g_x| + |g_y|); g from the oracle's stencil
+            mx, my = mdl_t.m[0], mdl_t.m[1]
+            gsum = np.zeros(B)
+            for bi in range(B):
+                c0, r0 = int(r["bin_key"][0, bi]) // mx, int(r["bin_key"][1, bi]) // my
+                ux, uy = float(r["bin_mean"][0, bi]), float(r["bin_mean"][1, bi])
+                I0 = float(r["bin_mean"][2 * dim, bi])
+                dx, dy = 0.5 / mx, 0.5 / my
+                lx = [oracle.loglik(mdl_t, fr, c0, r0, ux + sx * dx, uy, 0.0, I0) for sx in (-1, 1)]
+                ly = [oracle.loglik(mdl_t, fr, c0, r0, ux, uy + sy * dy, 0.0, I0) for sy in (-1, 1)]
+                gsum[bi] = abs(lx[1] - lx[0]) / 2.0 + abs(ly[1] - ly[0]) / 2.0   # delta (|g_x| + |g_y|)
+            tol_ll = 1.2 * (6.0 * tol_ll + 2.0 * tol_ll * gsum)
+        bad = d_ll > tol_ll
         assert not np.any(bad), (f"target {t}: log-likelihood off by {d_ll[bad].max()} at l = "
                                  f"{ll_o[bad][np.argmax(d_ll[bad])]}")
         dev["ll"] = max(dev["ll"], float(d_ll.max()))
         dev["ll_rel"] = max(dev.get("ll_rel", 0.0), float(np.max(d_ll / np.maximum(np.abs(ll_o), 1.0))))
         wg, wo = w_gpu[a:b], r["w"]
-        e_w = np.abs(wg - wo) - weight_bound(r["ll"][r["bin_of"]], wo)
+        tl_p = tol_ll[r["bin_of"]] if (not sir and cfg.dummy_mode == 2) else None
+        e_w = np.abs(wg - wo) - weight_bound(r["ll"][r["bin_of"]], wo, tl_p)
         worst = int(np.argmax(e_w))
         assert np.all(e_w <= 0), (f"target {t}: weights off, worst excess {e_w[worst]} at w = {wo[worst]} "
                                   f"(GPU {wg[worst]}), l = {r['ll'][r['bin_of'][worst]]}, max w = {wo.max()}")

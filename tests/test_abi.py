@@ -66,13 +66,19 @@ def test_workspace_bytes_and_validation(L):
     bad = [dict(dim=4), dict(n_particles=(0,)), dict(bins_per_px=(0, 2, 1)), dict(bins_per_px=(5000, 2, 1)),
            dict(patch=10), dict(patch=129), dict(quad=0), dict(quad=17), dict(psf=1), dict(lik_mode=7),
            dict(sigma_xi=0.0), dict(sigma_psf=-1.0), dict(frame_h=0), dict(dummy_mode=3),
-           dict(proc_sigma=(-1, 0, 0, 0, 0))]
+           dict(proc_sigma=(-1, 0, 0, 0, 0)), dict(neff_threshold=float("nan")), dict(neff_threshold=-1.0),
+           dict(bins_per_sigma=-1.0), dict(bins_per_sigma=float("inf")), dict(bins_per_sigma=2.0, bins_max=0),
+           dict(dummy_mode=2, neff_threshold=0.5), dict(dummy_mode=2, lik_mode=2),
+           dict(dummy_mode=2, dim=3, psf=1, bins_per_px=(4, 4, 4), proc_sigma=(0.5,) * 7)]
     for kw in bad:
         cb, kb = _cfg(**kw)._c()
         assert L.pcsir_workspace_bytes(C.byref(cb)) == 0, kw
     cb, kb = _cfg()._c()
     cb.abi_version = 99
     assert L.pcsir_workspace_bytes(C.byref(cb)) == 0
+    for kw in (dict(dummy_mode=2), dict(bins_per_sigma=2.0, bins_max=8), dict(neff_threshold=0.3)):
+        cg, kg = _cfg(**kw)._c()
+        assert L.pcsir_workspace_bytes(C.byref(cg)) > 0, kw
     # 3D with the astigmatic PSF is valid
     c3, k3 = _cfg(dim=3, psf=1, bins_per_px=(4, 4, 4), proc_sigma=(0.5,) * 7)._c()
     assert L.pcsir_workspace_bytes(C.byref(c3)) > 0

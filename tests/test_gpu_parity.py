@@ -375,3 +375,18 @@ def test_launch_shapes_do_not_change_results_and_autotune_restores_particles():
     f.pcsir_step(fr[2], 2)
     f.estimate()
     f.close()
+
+
+@pytest.mark.parametrize("lik", [0, 1])
+def test_second_order_dummies(lik):
+    """Dummies that carry their members' position covariance: nine shifted
+    evaluations per dummy, combined to second order (tolerance in gpu_helpers)."""
+    counts = (4000, 1, 1500)
+    w = synth.preset("tiny", H=96, W=96, T=3, n=counts, K=2, mid_lo=20.0, mid_hi=76.0, m=(2, 2, 1),
+                     sigma_xi=40.0)
+    tr, fr = _scene(w, seed=6)
+    cfg = _cfg(w, seed=23, lik_mode=lik, dummy_mode=2)
+    cloud = _clouds(w, counts, [tr[1, t] for t in range(3)], 0.8, 31)
+    log(f"case second_order_dummies lik={lik}")
+    dev, _ = run_step_parity(cfg, cloud, fr[1], 2, False)
+    log(f"  deviations {dev}")
