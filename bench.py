@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--bins-per-sigma", type=float, default=2.0,
                     help="the extra adaptive-bin mode: about this many bins per standard deviation (0: skip)")
     ap.add_argument("--bins-max", type=int, default=8, help="adaptive bins: largest cells per pixel")
+    ap.add_argument("--no-second-order", action="store_true", help="skip the second-order-dummy mode")
     ap.add_argument("--neff-threshold", type=float, default=0.5,
                     help="the extra kept-weight mode: resample when N_eff < this fraction of N (negative: skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -419,6 +420,15 @@ def main():
             key = f"h={h_match},neff<{thr}N"
             rmse[key], rmse_stats[key] = float(np.mean(a)), summary(a)
             log(f"rmse h={h_match} with N_eff threshold {thr}: {rmse_stats[key]}")
+    if dim == 2 and not args.no_second_order:
+        # second-order dummies at the coarser bin size h = 2 h_match (a quarter of the dummies)
+        h2 = min(1.0, 2 * h_match)
+        runs["pcsir_sep_second_order"] = timed(False, h2, LIK_SEP, True, dummy_mode=2)
+        if not args.no_match:
+            a = track_rmse(False, h2, LIK_SEP, dummy_mode=2)
+            key = f"h={h2},second_order"
+            rmse[key], rmse_stats[key] = float(np.mean(a)), summary(a)
+            log(f"rmse with second-order dummies at h={h2}: {rmse_stats[key]}")
     if args.bins_per_sigma > 0:
         ad = dict(bins_per_sigma=args.bins_per_sigma, bins_max=args.bins_max)
         runs["pcsir_sep_adaptive"] = timed(False, h_match, LIK_SEP, True, **ad)
