@@ -104,7 +104,7 @@ typedef struct {
   float i_bg;                  /* background intensity; also the value of pixels outside the frame */
   float sigma_xi;              /* likelihood width sigma_xi > 0 */
   float proc_sigma[7];         /* process-noise standard deviation per state component and frame */
-  uint64_t seed;               /* Philox4x64-10 key word 0 */
+  uint64_t seed;               /* Philox4x32-10 key: (low 32 bits, high 32 bits) */
   double neff_threshold;       /* resampling threshold as a fraction of N_t (Alg. SIR and Alg. pcSIR
                                   resample when N_eff falls below a threshold). Above 1 (e.g.
                                   +inf): resample every frame, the default. In [0, 1]: a target

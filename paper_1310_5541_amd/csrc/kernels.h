@@ -1413,8 +1413,8 @@ __global__ __launch_bounds__(TPB) void k_norm_bins(Params p, const uint32_t *__r
 }
 
 // Weight of particle g (target t) in storage order. pcSIR: the weight of the
-// bin that holds it (binary search of its key among the target's sorted bin
-// keys); SIR: e^{l_g - M} / S.
+// bin that holds it (its bin number, from the bin sums); SIR: e^{l_g - M} / S;
+// with kept weights, e^{previous log-weight + l - M} / S.
 struct WeightSrc {
   const uint32_t *segid;     // pcSIR: bin of every particle, storage order
   const double *wbin;        // pcSIR: [B]
