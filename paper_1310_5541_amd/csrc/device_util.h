@@ -9,6 +9,15 @@ namespace pcsir {
 
 constexpr int WAVE = 64;
 
+// ---------------------------------------------------------------- address spaces
+// A pointer read from memory (rather than passed as a kernel argument) is
+// generic to the compiler, and loads through it become flat loads, which are
+// counted with the LDS operations as well: every wait for a lane shuffle then
+// also waits for them. Pointers known to address device memory are cast to
+// the global address space before use.
+typedef const float __attribute__((address_space(1))) gfloat;
+__device__ __forceinline__ const gfloat *as_global(const float *ptr) { return (const gfloat *)ptr; }
+
 // ---------------------------------------------------------------- Philox4x32-10
 // Counter-based generator of Salmon et al. (SC'11): ten rounds of two
 // 32x32->64 products (multipliers 0xD2511F53, 0xCD9E8D57) with a Weyl key

@@ -8,6 +8,8 @@
 namespace pcsir {
 
 constexpr int TPB = 256;            // threads per block of the streaming kernels
+constexpr int KEYS_TPB = 512;       // threads per block of the key dedup (k_keys)
+constexpr int BINS_TPB = 512;       // threads per block of the bin sums (k_bin_sums)
 constexpr int LIST_BLOCKS_MAX = 2048;  // most workgroups of the sort / segment passes over the key list
 constexpr int SCAN_ITEMS = 4;       // particles per thread in the weight scan
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
@@ -329,14 +331,14 @@ static_assert(DEDUP_SLOTS == 1 << 13, "hash slots");
 constexpr uint32_t KEY_EMPTY = 0xFFFFFFFFu;  // compacted keys are < 2^32 - 1 (checked range)
 
 template <int DIM>
-__global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restrict__ tiles,
+__global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__restrict__ tiles,
                                               const uint32_t *__restrict__ off, const float *__restrict__ s,
                                               const int32_t *__restrict__ bbox_cur, const uint32_t *__restrict__ kbase,
                                               uint32_t *__restrict__ sparse, uint32_t *__restrict__ tcount) {
-  constexpr int R = BIN_TILES * SCAN_TILE / TPB;  // all of a thread's positions are loaded before use
-  constexpr int PER = DEDUP_SLOTS / TPB;
+  constexpr int R = BIN_TILES * SCAN_TILE / KEYS_TPB;  // all of a thread's positions are loaded before use
+  constexpr int PER = DEDUP_SLOTS / KEYS_TPB;
   __shared__ uint32_t tab[DEDUP_SLOTS];
-  __shared__ uint32_t lds[TPB / WAVE];
+  __shared__ uint32_t lds[KEYS_TPB / WAVE];
   const BinTile tl = tiles[blockIdx.x];
   const int t = tl.t;
   const uint32_t base = tl.base;
@@ -344,15 +346,15 @@ __global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restric
 #pragma unroll
   for (int a = 0; a < 6; ++a) bb[a] = bbox_cur[t * 6 + a];
   const uint32_t kb = kbase[t];
-  for (int i = threadIdx.x; i < DEDUP_SLOTS; i += TPB) tab[i] = KEY_EMPTY;
+  for (int i = threadIdx.x; i < DEDUP_SLOTS; i += KEYS_TPB) tab[i] = KEY_EMPTY;
   __syncthreads();
-  for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * TPB) {
+  for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * KEYS_TPB) {
     // all positions loaded first, from clamped indices (a load under a bounds
     // branch would be waited for before the next one is issued), then keyed
     float xs[DIM][R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const uint32_t g = base + min(r0 + q * TPB + threadIdx.x, tl.i1 - 1);
+      const uint32_t g = base + min(r0 + q * KEYS_TPB + threadIdx.x, tl.i1 - 1);
 #pragma unroll
       for (int a = 0; a < DIM; ++a) xs[a][q] = s[(size_t)a * p.NT + g];
     }
@@ -362,34 +364,40 @@ __global__ __launch_bounds__(TPB) void k_keys(Params p, const BinTile *__restric
       int32_t c[3];
 #pragma unroll
       for (int a = 0; a < DIM; ++a) c[a] = cell_index(xs[a][q], p.tm[t * 3 + a]);
-      kk[q] = r0 + q * TPB + threadIdx.x < tl.i1 ? compact_key<DIM>(c, bb, kb) : KEY_EMPTY;
+      kk[q] = r0 + q * KEYS_TPB + threadIdx.x < tl.i1 ? compact_key<DIM>(c, bb, kb) : KEY_EMPTY;
+    }
+    // the compare-and-swap of every key at its home slot at once (R atomics
+    // in flight instead of R round trips): it inserts the key or returns what
+    // the slot holds; a slot, once filled, never changes, so only a slot
+    // holding another key sends the key on to the next slots
+    uint32_t hh[R], vv[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      hh[q] = (kk[q] * 0x9E3779B1u) >> DEDUP_SHIFT;  // Fibonacci hashing: top bits of the product
+      vv[q] = kk[q] == KEY_EMPTY ? KEY_EMPTY : atomicCAS(&tab[hh[q]], KEY_EMPTY, kk[q]);
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const uint32_t k = kk[q];
       if (k == KEY_EMPTY) continue;
-      uint32_t h = (k * 0x9E3779B1u) >> DEDUP_SHIFT;  // Fibonacci hashing: top bits of the product
-      while (true) {
-        uint32_t v = tab[h];
-        if (v == k) break;
-        if (v == KEY_EMPTY) {
-          v = atomicCAS(&tab[h], KEY_EMPTY, k);
-          if (v == KEY_EMPTY || v == k) break;
-        }
+      uint32_t h = hh[q], v = vv[q];
+      while (v != KEY_EMPTY && v != k) {
         h = (h + 1) & (DEDUP_SLOTS - 1);
+        v = atomicCAS(&tab[h], KEY_EMPTY, k);
       }
     }
   }
   __syncthreads();
+  // thread t reads slots t, t + KEYS_TPB, ...: consecutive lanes, consecutive banks
   uint32_t c = 0;
 #pragma unroll
-  for (int j = 0; j < PER; ++j) c += tab[threadIdx.x * PER + j] != KEY_EMPTY ? 1u : 0u;
+  for (int j = 0; j < PER; ++j) c += tab[j * KEYS_TPB + threadIdx.x] != KEY_EMPTY ? 1u : 0u;
   uint32_t tot;
-  uint32_t o = base + tl.i0 + block_excl_scan<TPB, uint32_t>(c, lds, &tot);
+  uint32_t o = base + tl.i0 + block_excl_scan<KEYS_TPB, uint32_t>(c, lds, &tot);
   if (threadIdx.x == 0) tcount[blockIdx.x] = tot;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const uint32_t v = tab[threadIdx.x * PER + j];
+    const uint32_t v = tab[j * KEYS_TPB + threadIdx.x];
     if (v != KEY_EMPTY) sparse[o++] = v;
   }
 }
@@ -715,8 +723,47 @@ struct BinLds {
   static constexpr int BINS = MOM2 ? 768 : (DIM == 2 ? 1024 : 896);      // table fits in 64 KB with the keys
 };
 
+// One member's fixed-point contributions: count, offsets from its pixel
+// (x - pixel is exact, |.| <= 1/2), velocities, intensity, and with MOM2 the
+// second moments of the offsets; sets sat where a value is outside its range.
+template <int DIM, bool MOM2>
+__device__ __forceinline__ void member_values(const float *xq, long long *val, bool &sat) {
+  constexpr int NC = BinLds<DIM, MOM2>::NC;
+  val[0] = 1;
+  float dpos[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    // x - pix is exact and in [-1/2, 1/2), so the scaled value is in [-2^31, 2^31)
+    const float pix = (float)cell_index(xq[a], 1);
+    dpos[a] = xq[a] - pix;
+    val[1 + a] = (long long)__float2int_rn(dpos[a] * FX_POS);
+  }
+  if (MOM2) {
+    // d 2^16 is exact; products of two such values are within 2^30
+    const double ux = (double)(dpos[0] * 65536.0f), uy = (double)(dpos[1 % DIM] * 65536.0f);
+    val[NC - 3] = __double2ll_rn(ux * ux);
+    val[NC - 2] = __double2ll_rn(uy * uy);
+    val[NC - 1] = __double2ll_rn(ux * uy);
+  }
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    float vel = xq[DIM + a];
+    if (!(fabsf(vel) < LIM_VEL)) {
+      sat = true;
+      vel = 0.0f;
+    }
+    val[1 + DIM + a] = (long long)__float2int_rn(vel * FX_VEL);  // |v 2^24| < 2^31
+  }
+  float in = xq[2 * DIM];
+  if (!(fabsf(in) < LIM_INT)) {
+    sat = true;
+    in = 0.0f;
+  }
+  val[1 + 2 * DIM] = __float2ll_rn(in * FX_INT);
+}
+
 template <int DIM, bool MOM2 = false>
-__global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__restrict__ tiles,
+__global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *__restrict__ tiles,
                                                   const uint32_t *__restrict__ off, const float *__restrict__ s,
                                                   const int32_t *__restrict__ bbox_cur,
                                                   const uint32_t *__restrict__ kbase,
@@ -746,13 +793,13 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
   const uint32_t kb = kbase[t];
   if (nb == 0) {
     // only when the frame's key range overflowed (reported): keep segid in range
-    for (uint32_t i = tl.i0 + threadIdx.x; i < tl.i1; i += TPB) segid[base + i] = 0;
+    for (uint32_t i = tl.i0 + threadIdx.x; i < tl.i1; i += BINS_TPB) segid[base + i] = 0;
     return;
   }
   bool sat = false;
   for (uint32_t c0 = 0; c0 < nb; c0 += BINS) {
     const uint32_t cn = min((uint32_t)BINS, nb - c0);
-    for (uint32_t b = threadIdx.x; b < cn; b += TPB) {
+    for (uint32_t b = threadIdx.x; b < cn; b += BINS_TPB) {
       bkey[b] = seg_key[s0 + c0 + b];
 #pragma unroll
       for (int c = 0; c < NC; ++c) bacc[c][b] = 0ull;
@@ -760,37 +807,50 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
     __syncthreads();
     const uint32_t klo = bkey[0], khi = bkey[cn - 1];
     const bool first = c0 == 0, last = c0 + cn == nb;
-    for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * TPB) {
+    for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * BINS_TPB) {
       float x[R][D];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const uint32_t i = min(r0 + q * TPB + threadIdx.x, tl.i1 - 1);  // clamped: unconditional loads
+        const uint32_t i = min(r0 + q * BINS_TPB + threadIdx.x, tl.i1 - 1);  // clamped: unconditional loads
 #pragma unroll
         for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + base + i];
       }
+      // the bins of all R particles first, so that the R table loads are in
+      // flight together (clamped indices: every key is a valid table index)
+      uint32_t lob[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const uint32_t i = r0 + q * TPB + threadIdx.x;
-        if (i >= tl.i1) continue;
-        const uint32_t g = base + i;
         int32_t cc[3];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) cc[a] = cell_index(x[q][a], p.tm[t * 3 + a]);
-        const uint32_t k = compact_key<DIM>(cc, bb, kb);
-        uint32_t lo;
-        if (use_lut) {
-          lo = lut[k] - (s0 + c0);  // wraps above cn for bins of other chunks
-        } else if (k < klo || k > khi) {
-          lo = 0xFFFFFFFFu;
-        } else {
-          uint32_t l0 = 0, h0 = cn - 1;
-          while (l0 < h0) {
-            const uint32_t mid = (l0 + h0) >> 1;
-            if (bkey[mid] < k) l0 = mid + 1;
-            else h0 = mid;
+        lob[q] = compact_key<DIM>(cc, bb, kb);
+      }
+      if (use_lut) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) lob[q] = lut[lob[q]] - (s0 + c0);  // wraps above cn for bins of other chunks
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const uint32_t k = lob[q];
+          if (k < klo || k > khi) {
+            lob[q] = 0xFFFFFFFFu;
+          } else {
+            uint32_t l0 = 0, h0 = cn - 1;
+            while (l0 < h0) {
+              const uint32_t mid = (l0 + h0) >> 1;
+              if (bkey[mid] < k) l0 = mid + 1;
+              else h0 = mid;
+            }
+            lob[q] = l0;
           }
-          lo = l0;
         }
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint32_t i = r0 + q * BINS_TPB + threadIdx.x;
+        if (i >= tl.i1) continue;
+        const uint32_t g = base + i;
+        const uint32_t lo = lob[q];
         if (lo >= cn) {
           // a bin of another chunk; the first chunk gives every particle a
           // valid bin number, which the particle's own chunk overwrites
@@ -799,45 +859,13 @@ __global__ __launch_bounds__(TPB) void k_bin_sums(Params p, const BinTile *__res
         }
         segid[g] = s0 + c0 + lo;
         long long val[NC];
-        val[0] = 1;
-        float dpos[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          // x - pix is exact and in [-1/2, 1/2), so the scaled value is in [-2^31, 2^31)
-          const float pix = (float)cell_index(x[q][a], 1);
-          dpos[a] = x[q][a] - pix;
-          val[1 + a] = (long long)__float2int_rn(dpos[a] * FX_POS);
-        }
-        if (MOM2) {
-          // d 2^16 is exact; products of two such values are within 2^30
-          const double ux = (double)(dpos[0] * 65536.0f), uy = (double)(dpos[1 % DIM] * 65536.0f);
-          val[NC - 3] = __double2ll_rn(ux * ux);
-          val[NC - 2] = __double2ll_rn(uy * uy);
-          val[NC - 1] = __double2ll_rn(ux * uy);
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          float vel = x[q][DIM + a];
-          if (!(fabsf(vel) < LIM_VEL)) {
-            sat = true;
-            vel = 0.0f;
-          }
-          val[1 + DIM + a] = (long long)__float2int_rn(vel * FX_VEL);  // |v 2^24| < 2^31
-        }
-        {
-          float in = x[q][2 * DIM];
-          if (!(fabsf(in) < LIM_INT)) {
-            sat = true;
-            in = 0.0f;
-          }
-          val[1 + 2 * DIM] = __float2ll_rn(in * FX_INT);
-        }
+        member_values<DIM, MOM2>(x[q], val, sat);
 #pragma unroll
         for (int c = 0; c < NC; ++c) atomicAdd(&bacc[c][lo], (unsigned long long)val[c]);
       }
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < cn; b += TPB) {
+    for (uint32_t b = threadIdx.x; b < cn; b += BINS_TPB) {
       if (bacc[0][b] == 0ull) continue;
 #pragma unroll
       for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + s0 + c0 + b], bacc[c][b]);
@@ -1184,7 +1212,21 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
     }
     const ExpScale ks = (DIM == 3 && p.psf == 1) ? psf_scale(p, zpos) : ks_flat;
     const float Iq = I0 / (float)(q * q);
-    const float *fr = frame + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
+    const gfloat *fr = as_global(frame) + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
+    // window pixels of the first ZPRE rounds loaded before the model is
+    // formed, so that their latency overlaps it: clamped coordinates, and a
+    // 0 / 1 factor instead of a select, so that every value is used and no
+    // load is moved under a branch that waits for it (pixel values are
+    // finite, so a masked pixel is +-0, which acts as 0 below)
+    constexpr int ZPRE = 4;
+    float zpre[ZPRE];
+#pragma unroll
+    for (int it = 0; it < ZPRE; ++it) {
+      const int pix = it * WAVE + lane;
+      const int c = c0 + pix % P - R, r = r0 + pix / P - R;
+      const float v = fr[(size_t)min(max(r, 0), p.H - 1) * p.W + min(max(c, 0), p.W - 1)];
+      zpre[it] = (v - p.i_bg) * ((pix < P2 && c >= 0 && c < p.W && r >= 0 && r < p.H) ? 1.0f : 0.0f);
+    }
     // SEPARABLE: the 2 P per-axis sums over q sub-samples are spread over the
     // wave, H = 64 / (2P) lanes per sum, each adding every H-th sub-sample; the
     // sum of (axis, pixel c) ends up in lane (axis P + c) H. With 2P > 64, lane
@@ -1223,17 +1265,6 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
           }
         }
       }
-    }
-    // window pixels of the first ZPRE rounds loaded up front (clamped
-    // coordinates, unconditional loads, masked afterwards)
-    constexpr int ZPRE = 4;
-    float zpre[ZPRE];
-#pragma unroll
-    for (int it = 0; it < ZPRE; ++it) {
-      const int pix = it * WAVE + lane;
-      const int c = c0 + pix % P - R, r = r0 + pix / P - R;
-      const float v = fr[(size_t)min(max(r, 0), p.H - 1) * p.W + min(max(c, 0), p.W - 1)];
-      zpre[it] = (pix < P2 && c >= 0 && c < p.W && r >= 0 && r < p.H) ? v - p.i_bg : 0.0f;
     }
     float ssd = 0.0f, err = 0.0f;
     for (int pix0 = 0, it = 0; pix0 < P2; pix0 += WAVE, ++it) {

@@ -74,7 +74,7 @@ __device__ __forceinline__ float dummy_feature(const Params &p, const DummyView 
   const uint32_t NT = p.NT;
   if (f < P2) {
     const int t = dv.seg_t[s];
-    const float *fr = frame + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
+    const gfloat *fr = as_global(frame) + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
     const int c = dv.dpix[s] + f % p.P - p.R;
     const int r = dv.dpix[(size_t)NT + s] + f / p.P - p.R;
     const float zb = (c >= 0 && c < p.W && r >= 0 && r < p.H) ? fr[(size_t)r * p.W + c] - p.i_bg : 0.0f;
@@ -94,7 +94,7 @@ __device__ __forceinline__ float dummy_feature(const Params &p, const DummyView 
 template <int DIM>
 __device__ __forceinline__ double dummy_data_term(const Params &p, const DummyView &dv, const float *frame, uint32_t s) {
   const int t = dv.seg_t[s];
-  const float *fr = frame + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
+  const gfloat *fr = as_global(frame) + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
   const int c0 = dv.dpix[s], r0 = dv.dpix[(size_t)p.NT + s];
   double a = 0.0;
   for (int r = r0 - p.R; r <= r0 + p.R; ++r)
