@@ -13,6 +13,7 @@ constexpr int BINS_TPB = 512;       // threads per block of the bin sums (k_bin_
 constexpr int LIST_BLOCKS_MAX = 2048;  // most workgroups of the sort / segment passes over the key list
 constexpr int SCAN_ITEMS = 4;       // particles per thread in the weight scan
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+constexpr int MAX_QUAD = 16;        // largest number of sub-samples per pixel axis
 constexpr int LIK_WAVES = 4;        // likelihood evaluations per block (one per wave)
 constexpr int BIN_TILES = 4;        // scan tiles of one target per block of the key dedup and bin sums
 
@@ -1174,6 +1175,24 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
   const int P = p.P, R = p.R, P2 = P * P;
   const int q = Q ? Q : p.q;
   const ExpScale ks_flat = psf_scale(p, 0.0f);  // the scale of a z-independent PSF, formed once
+  // window column and row of this lane's pixel in round 0; each round of 64
+  // pixels then advances them by (64 mod P, 64 div P) with one wrap, instead
+  // of an integer division per round
+  const int pc_first = lane % P, pr_first = lane / P;
+  const int dpc = WAVE % P, dpr = WAVE / P;
+  // sub-sample offsets (a + 1/2) / q - 1/2, a < q, formed once per block
+  __shared__ float soff[MAX_QUAD];
+  if (threadIdx.x < MAX_QUAD) soff[threadIdx.x] = (int)threadIdx.x < q ? sub_offset((int)threadIdx.x, q) : 0.0f;
+  __syncthreads();
+  // SEPARABLE with H = 64 / (2P) >= 1 lanes per per-axis sum: this lane's
+  // (axis, pixel, first sub-sample), fixed for the launch
+  const int H = WAVE / (2 * P);
+  const bool s_on = H >= 1 && lane < 2 * P * H;
+  const int s_axis = s_on ? lane / (P * H) : 0;
+  const int s_rem = lane - s_axis * P * H;
+  const int s_pixel = H >= 1 ? s_rem / H : 0;
+  const int s_part = s_rem - s_pixel * H;
+  const float s_cc = (float)(s_pixel - R);
   for (uint32_t idx = blockIdx.x * LIK_WAVES + wave_id(); idx < E; idx += gridDim.x * LIK_WAVES) {
     const uint32_t e = MODE == LIK_ALL ? idx : (MODE == LIK_STENCIL ? idx / 9u : chk.list[idx]);
     int t;
@@ -1220,29 +1239,33 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
     // finite, so a masked pixel is +-0, which acts as 0 below)
     constexpr int ZPRE = 4;
     float zpre[ZPRE];
+    {
+      int pc = pc_first, pr = pr_first;
 #pragma unroll
-    for (int it = 0; it < ZPRE; ++it) {
-      const int pix = it * WAVE + lane;
-      const int c = c0 + pix % P - R, r = r0 + pix / P - R;
-      const float v = fr[(size_t)min(max(r, 0), p.H - 1) * p.W + min(max(c, 0), p.W - 1)];
-      zpre[it] = (v - p.i_bg) * ((pix < P2 && c >= 0 && c < p.W && r >= 0 && r < p.H) ? 1.0f : 0.0f);
+      for (int it = 0; it < ZPRE; ++it) {
+        const int pix = it * WAVE + lane;
+        const int c = c0 + pc - R, r = r0 + pr - R;
+        const float v = fr[(size_t)min(max(r, 0), p.H - 1) * p.W + min(max(c, 0), p.W - 1)];
+        zpre[it] = (v - p.i_bg) * ((pix < P2 && c >= 0 && c < p.W && r >= 0 && r < p.H) ? 1.0f : 0.0f);
+        pc += dpc;
+        pr += dpr;
+        if (pc >= P) {
+          pc -= P;
+          ++pr;
+        }
+      }
     }
     // SEPARABLE: the 2 P per-axis sums over q sub-samples are spread over the
     // wave, H = 64 / (2P) lanes per sum, each adding every H-th sub-sample; the
     // sum of (axis, pixel c) ends up in lane (axis P + c) H. With 2P > 64, lane
     // j forms both axes' sums of pixel j and, for P > 64, of pixel j + 64.
-    const int H = WAVE / (2 * P);  // SEPARABLE only
     float gxl = 0.0f, gyl = 0.0f, gxh = 0.0f, gyh = 0.0f;
     if (SEP) {
       if (H >= 1) {
-        if (lane < 2 * P * H) {
-          const int axis = lane / (P * H);
-          const int rem = lane - axis * P * H;
-          const int pixel = rem / H, part = rem - pixel * H;
-          const float cc = (float)(pixel - R);
-          const float d = axis ? dy : dx;
-          const float kh = axis ? ks.yh : ks.xh, kl = axis ? ks.yl : ks.xl;
-          for (int a = part; a < q; a += H) gxl += exp2_neg(scaled_sq((cc + sub_offset(a, q)) - d, kh, kl));
+        if (s_on) {
+          const float d = s_axis ? dy : dx;
+          const float kh = s_axis ? ks.yh : ks.xh, kl = s_axis ? ks.yl : ks.xl;
+          for (int a = s_part; a < q; a += H) gxl += exp2_neg(scaled_sq((s_cc + soff[a]) - d, kh, kl));
         }
         float tot = gxl;
         for (int h = 1; h < H; ++h) tot += __shfl(gxl, (lane + h) & (WAVE - 1), WAVE);
@@ -1251,7 +1274,7 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
         if (lane < P) {
           const float cc = (float)(lane - R);
           for (int a = 0; a < q; ++a) {
-            const float o = sub_offset(a, q);
+            const float o = soff[a];
             gxl += exp2_neg(scaled_sq((cc + o) - dx, ks.xh, ks.xl));
             gyl += exp2_neg(scaled_sq((cc + o) - dy, ks.yh, ks.yl));
           }
@@ -1259,7 +1282,7 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
         if (lane + WAVE < P) {
           const float cc = (float)(lane + WAVE - R);
           for (int a = 0; a < q; ++a) {
-            const float o = sub_offset(a, q);
+            const float o = soff[a];
             gxh += exp2_neg(scaled_sq((cc + o) - dx, ks.xh, ks.xl));
             gyh += exp2_neg(scaled_sq((cc + o) - dy, ks.yh, ks.yl));
           }
@@ -1267,9 +1290,9 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       }
     }
     float ssd = 0.0f, err = 0.0f;
+    int pc = pc_first, pr = pr_first;
     for (int pix0 = 0, it = 0; pix0 < P2; pix0 += WAVE, ++it) {
       const int pix = pix0 + lane;
-      const int pc = pix % P, pr = pix / P;
       float g = 0.0f;
       if (SEP) {
         const int pcs = pc < P ? pc : 0, prs = pr < P ? pr : 0;
@@ -1331,6 +1354,12 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
         const float bp = tsum - ssd;
         err += ((ssd - (tsum - bp)) + (sq - bp)) + sqe;
         ssd = tsum;
+      }
+      pc += dpc;
+      pr += dpr;
+      if (pc >= P) {
+        pc -= P;
+        ++pr;
       }
     }
     // compensated wave sum; the (hi, lo) result is combined and scaled in FP64,
