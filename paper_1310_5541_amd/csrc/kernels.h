@@ -646,7 +646,8 @@ __device__ __forceinline__ void decode_key(uint32_t key, int T, const uint32_t *
   }
 }
 
-__device__ __forceinline__ int key_target(uint32_t key, int T, const uint32_t *__restrict__ kbase) {
+template <typename KB>
+__device__ __forceinline__ int key_target(uint32_t key, int T, KB kbase) {
   int lo = 0, hi = T - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -656,6 +657,9 @@ __device__ __forceinline__ int key_target(uint32_t key, int T, const uint32_t *_
   return lo;
 }
 
+// Targets whose key bases k_seg_mark stages in LDS for its searches.
+constexpr int KBASE_LDS = 4096;
+
 // Record every bin: its key and its target.
 __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs sb, const uint64_t *__restrict__ meta,
                                                   const uint32_t *__restrict__ chunk_base,
@@ -664,6 +668,11 @@ __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs
                                                   uint64_t lut_cap) {
   const bool use_lut = meta[META_RANGE] <= lut_cap;
   __shared__ uint32_t lds[TPB / WAVE];
+  __shared__ uint32_t kb_lds[KBASE_LDS];
+  const bool kb_in_lds = p.T <= KBASE_LDS;
+  if (kb_in_lds)
+    for (int t = threadIdx.x; t < p.T; t += TPB) kb_lds[t] = kbase[t];
+  __syncthreads();
   const uint32_t *K = sorted_keys(sb, meta[META_PASSES]);
   uint32_t j0, j1;
   list_range((uint32_t)meta[META_L], G, blockIdx.x, j0, j1);
@@ -676,7 +685,7 @@ __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs
     if (h) {
       const uint32_t kj = K[j];
       seg_key[heads + ex] = kj;
-      seg_t[heads + ex] = key_target(kj, p.T, kbase);
+      seg_t[heads + ex] = kb_in_lds ? key_target(kj, p.T, (const uint32_t *)kb_lds) : key_target(kj, p.T, kbase);
       if (use_lut) lut[kj] = heads + ex;  // bin of every occupied cell key
     }
     heads += tot;
