@@ -1604,24 +1604,56 @@ __global__ __launch_bounds__(TPB) void k_norm_comb(Params p, const uint32_t *__r
 }
 
 // ---------------------------------------------------------------- weights, CDF, resampling
+// Sum of the broadcast weights of every scan tile. A block takes
+// CDF_SUM_TILES consecutive tiles, so that all of their loads (for pcSIR the
+// bin numbers, then the bin weights they index) are in flight together; each
+// tile's sum is formed in the same order as a block of its own would form it
+// (per thread over its items, then the waves in order).
+constexpr int CDF_SUM_TILES = 4;
+
 template <bool SIR>
-__global__ __launch_bounds__(TPB) void k_cdf_sum(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
-                                                 WeightSrc ws, double *__restrict__ tile_sum) {
-  __shared__ double lds[TPB / WAVE];
-  const Tile tl = tiles[blockIdx.x];
-  const uint32_t base = tl.base, n = tl.n;
-  double acc = 0.0;
-  double w[SCAN_ITEMS];
+__global__ __launch_bounds__(TPB) void k_cdf_sum(const Tile *__restrict__ tiles, uint32_t ntiles,
+                                                 const uint32_t *__restrict__ off, WeightSrc ws,
+                                                 double *__restrict__ tile_sum) {
+  __shared__ double lds[CDF_SUM_TILES][TPB / WAVE];
+  Tile tl[CDF_SUM_TILES];
 #pragma unroll
-  for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t i = tl.i0 + it * TPB + threadIdx.x;  // coalesced; clamped, unconditional loads
-    w[it] = particle_weight<SIR>(ws, tl.t, base + min(i, n - 1));
+  for (int k = 0; k < CDF_SUM_TILES; ++k) tl[k] = tiles[min(blockIdx.x * CDF_SUM_TILES + k, ntiles - 1)];
+  double w[CDF_SUM_TILES][SCAN_ITEMS];
+  if (!SIR && !ws.lw) {
+    uint32_t b[CDF_SUM_TILES][SCAN_ITEMS];
+#pragma unroll
+    for (int k = 0; k < CDF_SUM_TILES; ++k)
+#pragma unroll
+      for (int it = 0; it < SCAN_ITEMS; ++it)  // coalesced; clamped, unconditional loads
+        b[k][it] = ws.segid[tl[k].base + min(tl[k].i0 + it * TPB + threadIdx.x, tl[k].n - 1)];
+#pragma unroll
+    for (int k = 0; k < CDF_SUM_TILES; ++k)
+#pragma unroll
+      for (int it = 0; it < SCAN_ITEMS; ++it) w[k][it] = ws.wbin[b[k][it]];
+  } else {
+#pragma unroll
+    for (int k = 0; k < CDF_SUM_TILES; ++k)
+#pragma unroll
+      for (int it = 0; it < SCAN_ITEMS; ++it)
+        w[k][it] = particle_weight<SIR>(ws, tl[k].t, tl[k].base + min(tl[k].i0 + it * TPB + threadIdx.x, tl[k].n - 1));
   }
 #pragma unroll
-  for (int it = 0; it < SCAN_ITEMS; ++it)
-    if (tl.i0 + it * TPB + threadIdx.x < n) acc += w[it];
-  const double tot = block_sum<TPB, double>(acc, lds);
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+  for (int k = 0; k < CDF_SUM_TILES; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it)
+      if (tl[k].i0 + it * TPB + threadIdx.x < tl[k].n) acc += w[k][it];
+    acc = wave_sum(acc);
+    if (lane_id() == 0) lds[k][wave_id()] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < CDF_SUM_TILES && blockIdx.x * CDF_SUM_TILES + threadIdx.x < ntiles) {
+    double r = lds[threadIdx.x][0];
+#pragma unroll
+    for (int v = 1; v < TPB / WAVE; ++v) r += lds[threadIdx.x][v];
+    tile_sum[blockIdx.x * CDF_SUM_TILES + threadIdx.x] = r;
+  }
 }
 
 // Per target: exclusive, non-decreasing scan of its tiles' sums.
@@ -1799,9 +1831,8 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
 // across the whole target); the last particle also takes any j left above
 // C_{n-1} by rounding. The block's parents lie between the parents of its
 // first j and of the next block's first j (chunk_par); when that range fits,
-// its C values are staged in LDS. Each thread takes SCAN_ITEMS consecutive j:
-// a binary search for the first, galloping forward from the previous parent
-// for the next ones.
+// its C values are staged in LDS. Each thread takes SCAN_ITEMS consecutive j,
+// one binary search each.
 constexpr uint32_t SEARCH_LDS = 1024;
 
 template <bool SIR>

@@ -531,7 +531,8 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
                                           c->at<double>(L.est), c->at<int32_t>(L.tflag), meta, tfb);
   }
   mark(c, "cdf_sum");
-  k_cdf_sum<false><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.tile_sum));
+  k_cdf_sum<false><<<(L.nS + CDF_SUM_TILES - 1) / CDF_SUM_TILES, TPB, 0, st>>>(tS, L.nS, off, ws,
+                                                                             c->at<double>(L.tile_sum));
   mark(c, "cdf_prefix");
   k_cdf_prefix<<<p.T, TPB, 0, st>>>(c->at<uint32_t>(L.tfirst), c->at<double>(L.tile_sum),
                                     c->at<double>(L.tile_pre));
@@ -577,7 +578,8 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
                                         c->at<double>(L.tgt), c->at<double>(L.est), c->at<int32_t>(L.tflag), meta,
                                         nullptr);
   mark(c, "cdf_sum");
-  k_cdf_sum<true><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.tile_sum));
+  k_cdf_sum<true><<<(L.nS + CDF_SUM_TILES - 1) / CDF_SUM_TILES, TPB, 0, st>>>(tS, L.nS, off, ws,
+                                                                             c->at<double>(L.tile_sum));
   mark(c, "cdf_prefix");
   k_cdf_prefix<<<p.T, TPB, 0, st>>>(c->at<uint32_t>(L.tfirst), c->at<double>(L.tile_sum),
                                     c->at<double>(L.tile_pre));
