@@ -14,6 +14,7 @@ constexpr int LIST_BLOCKS_MAX = 2048;  // most workgroups of the sort / segment 
 constexpr int SCAN_ITEMS = 4;       // particles per thread in the weight scan
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 constexpr int MAX_QUAD = 16;        // largest number of sub-samples per pixel axis
+constexpr int PROP_TILES = 2;       // propagate tiles (TPB particles each) per block
 constexpr int LIK_WAVES = 4;        // likelihood evaluations per block (one per wave)
 constexpr int BIN_TILES = 4;        // scan tiles of one target per block of the key dedup and bin sums
 
@@ -90,13 +91,14 @@ struct BinTile {
 // ---------------------------------------------------------------- propagation
 // Alg. SIR / Alg. pcSIR "draw a sample from pi": bootstrap proposal with the
 // nearly-constant-velocity dynamics of Sec. 5.1. The gather x_j <- x~_{s(j)}
-// of the previous frame's resampling is fused into the load. With KEYS, the
-// exact cell indices of the new positions are reduced to a per-target
-// bounding box (integer atomics).
-// With KEYS (pcSIR) it also clears the bin accumulators that the previous
-// frame used (meta[META_DIRTY] of them).
+// of the previous frame's resampling is fused into the load. With KEYS
+// (pcSIR), each tile of TPB particles writes the extremes of its new
+// positions as the cell index clamps them (and, with adaptive bins, their
+// sums and squares) for k_bbox_reduce, and the bin accumulators that the
+// previous frame used (meta[META_DIRTY] of them) are cleared. A block takes
+// PROP_TILES tiles, so that their loads are in flight together.
 template <int DIM, bool KEYS>
-__global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restrict__ tiles,
+__global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restrict__ tiles, uint32_t ntiles,
                                                    const uint32_t *__restrict__ off, const float *__restrict__ sin,
                                                    float *__restrict__ sout, const uint32_t *__restrict__ anc,
                                                    int pending, const StepDesc *__restrict__ desc,
@@ -104,88 +106,114 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
                                                    unsigned long long *__restrict__ acc,
                                                    const uint64_t *__restrict__ meta) {
   constexpr int D = 2 * DIM + 1;
-  const Tile tl = tiles[blockIdx.x];
-  const int t = tl.t;
-  const uint32_t base = tl.base;
-  const uint32_t n = tl.n;
-  const uint32_t i = tl.i0 + threadIdx.x;
-  const bool valid = i < n;
+  constexpr int K = PROP_TILES;
+  // the block's K tiles: their ancestor loads, then their state loads, are
+  // issued together (a duplicate of the last tile pads the last block and
+  // writes nothing)
+  Tile tl[K];
+  bool valid[K];
+  uint32_t src[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t tb = blockIdx.x * K + k;
+    tl[k] = tiles[min(tb, ntiles - 1)];
+    const uint32_t i = tl[k].i0 + threadIdx.x;
+    valid[k] = tb < ntiles && i < tl[k].n;
+    src[k] = tl[k].base + min(i, tl[k].n - 1);
+  }
+  if (pending) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) src[k] = tl[k].base + min(anc[src[k]], tl[k].n - 1);
+  }
+  float x[K][D];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[k][d] = sin[(size_t)d * p.NT + src[k]];
+  const uint32_t dirty = KEYS ? (uint32_t)meta[META_DIRTY] : 0u;
   // extremes of the positions as cell_index clamps them (the cell index is
   // non-decreasing in the clamped value, so the extremes give the cell
   // range for any bin size), and with adaptive bins their sums and squares
-  float kmin[DIM], kmax[DIM];
+  float kmin[K][DIM], kmax[K][DIM];
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    kmin[a] = INFINITY;
-    kmax[a] = -INFINITY;
-  }
-  if (valid) {
-    const uint32_t g = base + i;
-    const uint32_t src = pending ? base + min(anc[g], n - 1) : g;
-    float x[D];
+  for (int k = 0; k < K; ++k) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) x[d] = sin[(size_t)d * p.NT + src];
-    float z[2 * ((D + 1) / 2)];
-    normal_pairs<(D + 1) / 2>(p.seed, i, (uint64_t)desc->k, (uint32_t)t, z);
-    float nx[D];
+    for (int a = 0; a < DIM; ++a) {
+      kmin[k][a] = INFINITY;
+      kmax[k][a] = -INFINITY;
+    }
+    if (valid[k]) {
+      const uint32_t i = tl[k].i0 + threadIdx.x;
+      const uint32_t g = tl[k].base + i;
+      float z[2 * ((D + 1) / 2)];
+      normal_pairs<(D + 1) / 2>(p.seed, i, (uint64_t)desc->k, (uint32_t)tl[k].t, z);
+      float nx[D];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) nx[a] = fmaf(p.proc_sigma[a], z[a], x[a] + x[DIM + a]);
+      for (int a = 0; a < DIM; ++a) nx[a] = fmaf(p.proc_sigma[a], z[a], x[k][a] + x[k][DIM + a]);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) nx[DIM + a] = fmaf(p.proc_sigma[DIM + a], z[DIM + a], x[DIM + a]);
-    nx[2 * DIM] = fmaf(p.proc_sigma[2 * DIM], z[2 * DIM], x[2 * DIM]);
+      for (int a = 0; a < DIM; ++a) nx[DIM + a] = fmaf(p.proc_sigma[DIM + a], z[DIM + a], x[k][DIM + a]);
+      nx[2 * DIM] = fmaf(p.proc_sigma[2 * DIM], z[2 * DIM], x[k][2 * DIM]);
 #pragma unroll
-    for (int d = 0; d < D; ++d) sout[(size_t)d * p.NT + g] = nx[d];
-    if (KEYS) {
+      for (int d = 0; d < D; ++d) sout[(size_t)d * p.NT + g] = nx[d];
+      if (KEYS) {
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const float xc = clamp_position(nx[a]);
-        kmin[a] = xc;
-        kmax[a] = xc;
-      }
-      const uint32_t dirty = (uint32_t)meta[META_DIRTY];
-      if (g < dirty) {
+        for (int a = 0; a < DIM; ++a) {
+          const float xc = clamp_position(nx[a]);
+          kmin[k][a] = xc;
+          kmax[k][a] = xc;
+        }
+        if (g < dirty) {
 #pragma unroll
-        for (int c = 0; c < p.acc_rows; ++c) acc[(size_t)c * p.NT + g] = 0ull;
+          for (int c = 0; c < p.acc_rows; ++c) acc[(size_t)c * p.NT + g] = 0ull;
+        }
       }
     }
   }
   if (KEYS) {
-    // per-wave extremes (and sums), then one barrier and a combine of the block's waves
-    __shared__ float wbox[TPB / WAVE][6];
-    __shared__ double wmom[TPB / WAVE][6];
+    // per tile: per-wave extremes (and sums), then one barrier and a combine of the block's waves
+    __shared__ float wbox[K][TPB / WAVE][6];
+    __shared__ double wmom[K][TPB / WAVE][6];
     const bool adaptive = p.bins_per_sigma > 0.0;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const float lo = wave_min(kmin[a]);
-      const float hi = wave_max(kmax[a]);
-      if (lane_id() == 0) {
-        wbox[wave_id()][a] = lo;
-        wbox[wave_id()][3 + a] = hi;
-      }
-      if (adaptive) {
-        const double xd = valid ? (double)kmin[a] : 0.0;  // the particle's clamped position
-        const double s1 = wave_sum(xd);
-        const double s2 = wave_sum(xd * xd);
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const float lo = wave_min(kmin[k][a]);
+        const float hi = wave_max(kmax[k][a]);
         if (lane_id() == 0) {
-          wmom[wave_id()][a] = s1;
-          wmom[wave_id()][3 + a] = s2;
+          wbox[k][wave_id()][a] = lo;
+          wbox[k][wave_id()][3 + a] = hi;
+        }
+        if (adaptive) {
+          const double xd = valid[k] ? (double)kmin[k][a] : 0.0;  // the particle's clamped position
+          const double s1 = wave_sum(xd);
+          const double s2 = wave_sum(xd * xd);
+          if (lane_id() == 0) {
+            wmom[k][wave_id()][a] = s1;
+            wmom[k][wave_id()][3 + a] = s2;
+          }
         }
       }
     }
     __syncthreads();
-    if (threadIdx.x < 2 * DIM) {
-      const int a = threadIdx.x % DIM;
-      const bool mx = threadIdx.x >= DIM;
-      float v = wbox[0][mx ? 3 + a : a];
-      double sm = wmom[0][mx ? 3 + a : a];
+    if (threadIdx.x < K * 2 * DIM) {
+      const int k = threadIdx.x / (2 * DIM);
+      const int r = threadIdx.x - k * 2 * DIM;
+      const int a = r % DIM;
+      const bool mx = r >= DIM;
+      const uint32_t tb = blockIdx.x * K + k;
+      float v = wbox[k][0][mx ? 3 + a : a];
+      double sm = wmom[k][0][mx ? 3 + a : a];
 #pragma unroll
       for (int w = 1; w < TPB / WAVE; ++w) {
-        const float u = wbox[w][mx ? 3 + a : a];
+        const float u = wbox[k][w][mx ? 3 + a : a];
         v = mx ? fmaxf(v, u) : fminf(v, u);
-        if (adaptive) sm += wmom[w][mx ? 3 + a : a];
+        if (adaptive) sm += wmom[k][w][mx ? 3 + a : a];
       }
-      bbox_part[(size_t)blockIdx.x * 6 + (mx ? 3 : 0) + a] = v;
-      if (adaptive) mom_part[(size_t)blockIdx.x * 6 + (mx ? 3 : 0) + a] = sm;
+      if (tb < ntiles) {
+        bbox_part[(size_t)tb * 6 + (mx ? 3 : 0) + a] = v;
+        if (adaptive) mom_part[(size_t)tb * 6 + (mx ? 3 : 0) + a] = sm;
+      }
     }
   }
 }

@@ -419,9 +419,9 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   // the previous frame's resampling decisions become this frame's
   if (keep) k_copy_i32<<<(p.T + TPB - 1) / TPB, TPB, 0, st>>>(tuni, c->at<int32_t>(L.tuni_next), (uint32_t)p.T);
   mark(c, "propagate");
-  k_propagate<DIM, true><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc,
-                                                 c->at<float>(L.bbox_part), c->at<double>(L.mom_part),
-                                                 c->at<unsigned long long>(L.acc), meta);
+  k_propagate<DIM, true><<<(L.n256 + PROP_TILES - 1) / PROP_TILES, TPB, 0, st>>>(
+      p, t256, L.n256, off, sin, sout, anc, c->pending, desc, c->at<float>(L.bbox_part), c->at<double>(L.mom_part),
+      c->at<unsigned long long>(L.acc), meta);
   mark(c, "bbox");
   k_bbox_reduce<<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.t256_first), off, c->at<float>(L.bbox_part),
                                      c->at<double>(L.mom_part), c->at<int32_t>(L.tm), c->at<int32_t>(L.bbox_cur),
@@ -563,8 +563,8 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
     k_copy_i32<<<(p.T + TPB - 1) / TPB, TPB, 0, st>>>(c->at<int32_t>(L.tuni), c->at<int32_t>(L.tuni_next),
                                                       (uint32_t)p.T);
   mark(c, "propagate");
-  k_propagate<DIM, false><<<L.n256, TPB, 0, st>>>(p, t256, off, sin, sout, anc, c->pending, desc, nullptr, nullptr,
-                                                  nullptr, meta);
+  k_propagate<DIM, false><<<(L.n256 + PROP_TILES - 1) / PROP_TILES, TPB, 0, st>>>(
+      p, t256, L.n256, off, sin, sout, anc, c->pending, desc, nullptr, nullptr, nullptr, meta);
   LikInput in;
   memset(&in, 0, sizeof(in));
   in.state = sout;
