@@ -748,11 +748,14 @@ __global__ __launch_bounds__(TPB) void k_seg_first(int T, const uint32_t *__rest
 // pixel of each member, so x - pixel is exact and |.| <= 1/2), velocities and
 // intensity. Particles are read in storage order (coalesced); a block holds
 // one target's tile and recomputes each particle's cell key. The target's
-// sorted bin keys are staged in LDS in chunks of BINS: for each chunk, the
-// tile's particles whose key falls in the chunk find their bin by binary
-// search and accumulate in LDS with 64-bit integer atomics, then each bin of
-// the chunk is flushed to HBM once. Integer sums are exact, so the result
-// does not depend on order. Also writes every particle's bin number.
+// bins are taken in LDS chunks of BINS: for each chunk, the tile's particles
+// whose bin falls in it accumulate in LDS with 64-bit integer atomics, then
+// each bin of the chunk is flushed to HBM once. A particle's bin is one load
+// from this frame's cell -> bin table when the frame's key range fits it
+// (then the tile is loaded once for all chunks); otherwise a binary search
+// over the chunk's keys, staged in LDS, with the tile read once per chunk.
+// Integer sums are exact, so the result does not depend on order. Also
+// writes every particle's bin number.
 // MOM2 (second-order dummies, 2D) adds the second moments of the offsets:
 // (dx 2^16)^2, (dy 2^16)^2 and (dx 2^16)(dy 2^16), each rounded to an integer.
 template <int DIM, bool MOM2 = false>
@@ -835,6 +838,60 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
     return;
   }
   bool sat = false;
+  if (use_lut) {
+    // a tile is one round (at most R BINS_TPB particles): each particle is
+    // loaded and its bin looked up once, and each LDS chunk of the target's
+    // bins then takes the particles whose bin it holds
+    static_assert(BIN_TILES * SCAN_TILE <= R * BINS_TPB, "one round per bin-sum tile");
+    float x[R][D];
+    uint32_t bin[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const uint32_t i = min(tl.i0 + q * BINS_TPB + threadIdx.x, tl.i1 - 1);  // clamped: unconditional loads
+#pragma unroll
+      for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + base + i];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      int32_t cc[3];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) cc[a] = cell_index(x[q][a], p.tm[t * 3 + a]);
+      bin[q] = compact_key<DIM>(cc, bb, kb);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) bin[q] = lut[bin[q]];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const uint32_t i = tl.i0 + q * BINS_TPB + threadIdx.x;
+      if (i < tl.i1) segid[base + i] = bin[q];
+    }
+    for (uint32_t c0 = 0; c0 < nb; c0 += BINS) {
+      const uint32_t cn = min((uint32_t)BINS, nb - c0);
+      for (uint32_t b = threadIdx.x; b < cn; b += BINS_TPB) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) bacc[c][b] = 0ull;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint32_t lo = bin[q] - (s0 + c0);  // wraps above cn for bins of other chunks
+        if (tl.i0 + q * BINS_TPB + threadIdx.x >= tl.i1 || lo >= cn) continue;
+        long long val[NC];
+        member_values<DIM, MOM2>(x[q], val, sat);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) atomicAdd(&bacc[c][lo], (unsigned long long)val[c]);
+      }
+      __syncthreads();
+      for (uint32_t b = threadIdx.x; b < cn; b += BINS_TPB) {
+        if (bacc[0][b] == 0ull) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + s0 + c0 + b], bacc[c][b]);
+      }
+      __syncthreads();
+    }
+    if (sat) atomicOr((unsigned long long *)&meta[META_ERR], (unsigned long long)ERR_FIXED_SAT);
+    return;
+  }
   for (uint32_t c0 = 0; c0 < nb; c0 += BINS) {
     const uint32_t cn = min((uint32_t)BINS, nb - c0);
     for (uint32_t b = threadIdx.x; b < cn; b += BINS_TPB) {
@@ -853,34 +910,24 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
 #pragma unroll
         for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + base + i];
       }
-      // the bins of all R particles first, so that the R table loads are in
-      // flight together (clamped indices: every key is a valid table index)
+      // each particle's bin within the chunk, by binary search over its keys
       uint32_t lob[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         int32_t cc[3];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) cc[a] = cell_index(x[q][a], p.tm[t * 3 + a]);
-        lob[q] = compact_key<DIM>(cc, bb, kb);
-      }
-      if (use_lut) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) lob[q] = lut[lob[q]] - (s0 + c0);  // wraps above cn for bins of other chunks
-      } else {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const uint32_t k = lob[q];
-          if (k < klo || k > khi) {
-            lob[q] = 0xFFFFFFFFu;
-          } else {
-            uint32_t l0 = 0, h0 = cn - 1;
-            while (l0 < h0) {
-              const uint32_t mid = (l0 + h0) >> 1;
-              if (bkey[mid] < k) l0 = mid + 1;
-              else h0 = mid;
-            }
-            lob[q] = l0;
+        const uint32_t k = compact_key<DIM>(cc, bb, kb);
+        if (k < klo || k > khi) {
+          lob[q] = 0xFFFFFFFFu;
+        } else {
+          uint32_t l0 = 0, h0 = cn - 1;
+          while (l0 < h0) {
+            const uint32_t mid = (l0 + h0) >> 1;
+            if (bkey[mid] < k) l0 = mid + 1;
+            else h0 = mid;
           }
+          lob[q] = l0;
         }
       }
 #pragma unroll
