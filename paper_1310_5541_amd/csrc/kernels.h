@@ -762,6 +762,11 @@ template <int DIM, bool MOM2 = false>
 struct BinLds {
   static constexpr int NC = 2 + 2 * DIM + (MOM2 ? 3 : 0);                // count + D components (+ 3)
   static constexpr int BINS = MOM2 ? 768 : (DIM == 2 ? 1024 : 896);      // table fits in 64 KB with the keys
+  // threads per block: more components per particle take 1024 threads with
+  // 4 particles each (instead of 512 with 8), which keeps the registers of a
+  // thread within what four waves per SIMD allow
+  static constexpr int NTH = (DIM == 3 || MOM2) ? 1024 : BINS_TPB;
+  static constexpr int R = BIN_TILES * SCAN_TILE / NTH;  // particles per thread and round, loaded together
 };
 
 // One member's fixed-point contributions: count, offsets from its pixel
@@ -804,7 +809,7 @@ __device__ __forceinline__ void member_values(const float *xq, long long *val, b
 }
 
 template <int DIM, bool MOM2 = false>
-__global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *__restrict__ tiles,
+__global__ __launch_bounds__((BinLds<DIM, MOM2>::NTH)) void k_bin_sums(Params p, const BinTile *__restrict__ tiles,
                                                   const uint32_t *__restrict__ off, const float *__restrict__ s,
                                                   const int32_t *__restrict__ bbox_cur,
                                                   const uint32_t *__restrict__ kbase,
@@ -820,7 +825,8 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
   // capacity) a particle's bin is one load; otherwise a binary search
   const bool use_lut = meta[META_RANGE] <= lut_cap;
   constexpr int BINS = BinLds<DIM, MOM2>::BINS;
-  constexpr int R = 8;  // particles per thread per round, loaded together
+  constexpr int R = BinLds<DIM, MOM2>::R;
+  constexpr int NTH = BinLds<DIM, MOM2>::NTH;
   __shared__ uint32_t bkey[BINS];
   __shared__ unsigned long long bacc[NC][BINS];
   const uint32_t NT = p.NT;
@@ -834,20 +840,20 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
   const uint32_t kb = kbase[t];
   if (nb == 0) {
     // only when the frame's key range overflowed (reported): keep segid in range
-    for (uint32_t i = tl.i0 + threadIdx.x; i < tl.i1; i += BINS_TPB) segid[base + i] = 0;
+    for (uint32_t i = tl.i0 + threadIdx.x; i < tl.i1; i += NTH) segid[base + i] = 0;
     return;
   }
   bool sat = false;
   if (use_lut) {
-    // a tile is one round (at most R BINS_TPB particles): each particle is
+    // a tile is one round (at most R NTH particles): each particle is
     // loaded and its bin looked up once, and each LDS chunk of the target's
     // bins then takes the particles whose bin it holds
-    static_assert(BIN_TILES * SCAN_TILE <= R * BINS_TPB, "one round per bin-sum tile");
+    static_assert(BIN_TILES * SCAN_TILE <= R * NTH, "one round per bin-sum tile");
     float x[R][D];
     uint32_t bin[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const uint32_t i = min(tl.i0 + q * BINS_TPB + threadIdx.x, tl.i1 - 1);  // clamped: unconditional loads
+      const uint32_t i = min(tl.i0 + q * NTH + threadIdx.x, tl.i1 - 1);  // clamped: unconditional loads
 #pragma unroll
       for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + base + i];
     }
@@ -862,12 +868,12 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
     for (int q = 0; q < R; ++q) bin[q] = lut[bin[q]];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const uint32_t i = tl.i0 + q * BINS_TPB + threadIdx.x;
+      const uint32_t i = tl.i0 + q * NTH + threadIdx.x;
       if (i < tl.i1) segid[base + i] = bin[q];
     }
     for (uint32_t c0 = 0; c0 < nb; c0 += BINS) {
       const uint32_t cn = min((uint32_t)BINS, nb - c0);
-      for (uint32_t b = threadIdx.x; b < cn; b += BINS_TPB) {
+      for (uint32_t b = threadIdx.x; b < cn; b += NTH) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) bacc[c][b] = 0ull;
       }
@@ -875,14 +881,14 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const uint32_t lo = bin[q] - (s0 + c0);  // wraps above cn for bins of other chunks
-        if (tl.i0 + q * BINS_TPB + threadIdx.x >= tl.i1 || lo >= cn) continue;
+        if (tl.i0 + q * NTH + threadIdx.x >= tl.i1 || lo >= cn) continue;
         long long val[NC];
         member_values<DIM, MOM2>(x[q], val, sat);
 #pragma unroll
         for (int c = 0; c < NC; ++c) atomicAdd(&bacc[c][lo], (unsigned long long)val[c]);
       }
       __syncthreads();
-      for (uint32_t b = threadIdx.x; b < cn; b += BINS_TPB) {
+      for (uint32_t b = threadIdx.x; b < cn; b += NTH) {
         if (bacc[0][b] == 0ull) continue;
 #pragma unroll
         for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + s0 + c0 + b], bacc[c][b]);
@@ -894,7 +900,7 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
   }
   for (uint32_t c0 = 0; c0 < nb; c0 += BINS) {
     const uint32_t cn = min((uint32_t)BINS, nb - c0);
-    for (uint32_t b = threadIdx.x; b < cn; b += BINS_TPB) {
+    for (uint32_t b = threadIdx.x; b < cn; b += NTH) {
       bkey[b] = seg_key[s0 + c0 + b];
 #pragma unroll
       for (int c = 0; c < NC; ++c) bacc[c][b] = 0ull;
@@ -902,11 +908,11 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
     __syncthreads();
     const uint32_t klo = bkey[0], khi = bkey[cn - 1];
     const bool first = c0 == 0, last = c0 + cn == nb;
-    for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * BINS_TPB) {
+    for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * NTH) {
       float x[R][D];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const uint32_t i = min(r0 + q * BINS_TPB + threadIdx.x, tl.i1 - 1);  // clamped: unconditional loads
+        const uint32_t i = min(r0 + q * NTH + threadIdx.x, tl.i1 - 1);  // clamped: unconditional loads
 #pragma unroll
         for (int d = 0; d < D; ++d) x[q][d] = s[(size_t)d * NT + base + i];
       }
@@ -932,7 +938,7 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
       }
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const uint32_t i = r0 + q * BINS_TPB + threadIdx.x;
+        const uint32_t i = r0 + q * NTH + threadIdx.x;
         if (i >= tl.i1) continue;
         const uint32_t g = base + i;
         const uint32_t lo = lob[q];
@@ -950,7 +956,7 @@ __global__ __launch_bounds__(BINS_TPB) void k_bin_sums(Params p, const BinTile *
       }
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < cn; b += BINS_TPB) {
+    for (uint32_t b = threadIdx.x; b < cn; b += NTH) {
       if (bacc[0][b] == 0ull) continue;
 #pragma unroll
       for (int c = 0; c < NC; ++c) atomicAdd(&acc[(size_t)c * NT + s0 + c0 + b], bacc[c][b]);

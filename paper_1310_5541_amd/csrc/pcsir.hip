@@ -464,17 +464,17 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   mark(c, "bin_sums");
   if constexpr (DIM == 2) {
     if (c->cfg.dummy_mode == PCSIR_DUMMY_COM2)
-      k_bin_sums<DIM, true><<<c->nB, BINS_TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+      k_bin_sums<DIM, true><<<c->nB, BinLds<DIM, true>::NTH, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
                                         c->at<uint32_t>(L.lut), L.lut_cap);
     else
-      k_bin_sums<DIM><<<c->nB, BINS_TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+      k_bin_sums<DIM><<<c->nB, BinLds<DIM>::NTH, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
                                         c->at<uint32_t>(L.lut), L.lut_cap);
   } else {
-    k_bin_sums<DIM><<<c->nB, BINS_TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
+    k_bin_sums<DIM><<<c->nB, BinLds<DIM>::NTH, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
                                         c->at<uint32_t>(L.lut), L.lut_cap);
