@@ -9,6 +9,7 @@ namespace pcsir {
 
 constexpr int TPB = 256;            // threads per block of the streaming kernels
 constexpr int KEYS_TPB = 512;       // threads per block of the key dedup (k_keys)
+constexpr int KEYS_TILE = 8192;     // particles of one target per tile of the key dedup
 constexpr int BINS_TPB = 512;       // threads per block of the bin sums (k_bin_sums)
 constexpr int LIST_BLOCKS_MAX = 2048;  // most workgroups of the sort / segment passes over the key list
 constexpr int SCAN_ITEMS = 4;       // particles per thread in the weight scan
@@ -346,17 +347,19 @@ __device__ __forceinline__ uint32_t particle_key(const float *__restrict__ s, ui
   return compact_key<DIM>(c, bb, kb);
 }
 
-// Distinct cell keys of one bin-sum tile (at most BIN_TILES * SCAN_TILE
-// particles of one target), found with an open-addressing hash set in LDS of
-// twice that many slots (so it never fills). A tile has at most as many
+// Distinct cell keys of one key tile (at most KEYS_TILE particles of one
+// target), found with an open-addressing hash set in LDS of twice that many
+// slots (so it never fills). Larger tiles than the bin sums' repeat a cell in
+// fewer tiles, so the list to sort is shorter. A tile has at most as many
 // distinct keys as particles, so it writes them into its own particle range
 // of `sparse` (global index of its first particle on), and its count to
 // tcount[tile]; k_list_offsets and k_list_compact then pack the tiles' keys
 // into one list, in tile order, without atomics. The list holds every
 // occupied cell at least once.
-constexpr int DEDUP_SLOTS = 2 * BIN_TILES * SCAN_TILE;
-constexpr int DEDUP_SHIFT = 32 - 13;
-static_assert(DEDUP_SLOTS == 1 << 13, "hash slots");
+constexpr int DEDUP_LOG2 = 14;
+constexpr int DEDUP_SLOTS = 2 * KEYS_TILE;
+constexpr int DEDUP_SHIFT = 32 - DEDUP_LOG2;
+static_assert(DEDUP_SLOTS == 1 << DEDUP_LOG2, "hash slots");
 constexpr uint32_t KEY_EMPTY = 0xFFFFFFFFu;  // compacted keys are < 2^32 - 1 (checked range)
 
 template <int DIM>
@@ -364,7 +367,7 @@ __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__re
                                               const uint32_t *__restrict__ off, const float *__restrict__ s,
                                               const int32_t *__restrict__ bbox_cur, const uint32_t *__restrict__ kbase,
                                               uint32_t *__restrict__ sparse, uint32_t *__restrict__ tcount) {
-  constexpr int R = BIN_TILES * SCAN_TILE / KEYS_TPB;  // all of a thread's positions are loaded before use
+  constexpr int R = KEYS_TILE / KEYS_TPB;  // all of a thread's positions are loaded before use
   constexpr int PER = DEDUP_SLOTS / KEYS_TPB;
   __shared__ uint32_t tab[DEDUP_SLOTS];
   __shared__ uint32_t lds[KEYS_TPB / WAVE];

@@ -26,18 +26,19 @@ struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
       ll, ll9, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
       bbox_part, mom_part, tm, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
-      tiles256, tilesS, tilesB, tile_last, tfirst, t256_first, off, chunk_par;
+      tiles256, tilesS, tilesB, tilesK, tile_last, tfirst, t256_first, off, chunk_par;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
   uint32_t n256; // propagate tiles
   uint64_t lut_cap;  // entries of the cell -> bin table
   uint32_t nS;   // scan tiles
   uint32_t nB;   // bin-sum tiles
+  uint32_t nK;   // key tiles
 };
 
 struct Tables {
   std::vector<Tile> t256, tS;
-  std::vector<BinTile> tB;
+  std::vector<BinTile> tB, tK;
   std::vector<uint32_t> tile_last, tfirst, t256_first, off;
 };
 
@@ -117,6 +118,7 @@ void build_tables(const pcsir_config *c, Tables &tb) {
     }
   }
   build_bin_tiles(c, BIN_TILE_MAX, tb.tB);
+  build_bin_tiles(c, KEYS_TILE, tb.tK);
   tb.tfirst[T] = (uint32_t)tb.tS.size();
   tb.t256_first[T] = (uint32_t)tb.t256.size();
 }
@@ -197,7 +199,9 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.tiles256 = take(sizeof(Tile) * (size_t)L.n256);
   L.tilesS = take(sizeof(Tile) * (size_t)L.nS);
   L.tilesB = take(sizeof(BinTile) * (size_t)L.nB);
-  L.tcount = take(4 * (size_t)L.nB);
+  L.nK = (uint32_t)tb.tK.size();
+  L.tilesK = take(sizeof(BinTile) * (size_t)L.nK);
+  L.tcount = take(4 * (size_t)L.nK);
   // cell -> bin table: 8 entries per particle, between 2^16 and 2^25 (128 MB)
   L.lut_cap = 1ull << 16;
   while (L.lut_cap < 8 * NT && L.lut_cap < (1ull << 25)) L.lut_cap <<= 1;
@@ -430,10 +434,10 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
                                  c->tune.digit_bits);
   mark(c, "keys");
   // distinct keys per tile into the tile's own range of kA, then packed into key (the sort's input)
-  k_keys<DIM><<<c->nB, KEYS_TPB, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
-                                    c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.kA), c->at<uint32_t>(L.tcount));
-  k_list_offsets<<<1, TPB, 0, st>>>(c->nB, c->at<uint32_t>(L.tcount), meta);
-  k_list_compact<<<c->nB, TPB, 0, st>>>(c->at<BinTile>(L.tilesB), off, c->at<uint32_t>(L.tcount), c->nB, meta,
+  k_keys<DIM><<<L.nK, KEYS_TPB, 0, st>>>(p, c->at<BinTile>(L.tilesK), off, sout, c->at<int32_t>(L.bbox_cur),
+                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.kA), c->at<uint32_t>(L.tcount));
+  k_list_offsets<<<1, TPB, 0, st>>>(L.nK, c->at<uint32_t>(L.tcount), meta);
+  k_list_compact<<<L.nK, TPB, 0, st>>>(c->at<BinTile>(L.tilesK), off, c->at<uint32_t>(L.tcount), L.nK, meta,
                                         c->at<uint32_t>(L.kA), c->at<uint32_t>(L.key));
   SortBufs sb = sort_bufs(c);
   uint32_t *hist = c->at<uint32_t>(L.hist);
@@ -779,6 +783,7 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   h2d(L.tiles256, c->tb.t256.data(), sizeof(Tile) * c->tb.t256.size());
   h2d(L.tilesS, c->tb.tS.data(), sizeof(Tile) * c->tb.tS.size());
   h2d(L.tilesB, c->tb.tB.data(), sizeof(BinTile) * c->tb.tB.size());
+  h2d(L.tilesK, c->tb.tK.data(), sizeof(BinTile) * c->tb.tK.size());
   h2d(L.tile_last, c->tb.tile_last.data(), 4 * c->tb.tile_last.size());
   h2d(L.tfirst, c->tb.tfirst.data(), 4 * c->tb.tfirst.size());
   h2d(L.off, c->tb.off.data(), 4 * c->tb.off.size());
