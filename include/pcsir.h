@@ -241,8 +241,8 @@ pcsir_status pcsir_kernel_times(pcsir_ctx *ctx, const char **names, float *ms, i
  * are the sorted distinct cell keys whatever the tile size, bin sums are exact
  * integers, and no reduction depends on the grid. */
 typedef struct {
-  int32_t bin_tile;     /* particles per work item of the key deduplication and the bin
-                           sums: 1024, 2048 or 4096 (default 4096) */
+  int32_t bin_tile;     /* particles per work item of the bin sums: 1024, 2048 or 4096
+                           (default 4096); the key deduplication takes 8192 */
   int32_t list_blocks;  /* workgroups of the sort and segment passes over the list of
                            distinct keys: 64 .. 2048 (default 1024) */
   int32_t digit_bits;   /* widest digit of the radix sort, 6 .. 11 (default 11); the

@@ -17,7 +17,7 @@ constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 constexpr int MAX_QUAD = 16;        // largest number of sub-samples per pixel axis
 constexpr int PROP_TILES = 2;       // propagate tiles (TPB particles each) per block
 constexpr int LIK_WAVES = 4;        // likelihood evaluations per block (one per wave)
-constexpr int BIN_TILES = 4;        // scan tiles of one target per block of the key dedup and bin sums
+constexpr int BIN_TILES = 4;        // largest bin-sum tile, in scan tiles of one target
 
 // Fixed-point scales of the bin sums (integer sums are exact and order-free).
 constexpr float FX_POS = 4294967296.0f;  // 2^32: offsets from the cell's pixel, |d| <= 1/2
