@@ -1807,6 +1807,14 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
   const int t = tl.t;
   const uint32_t base = tl.base, n = tl.n;
   const uint32_t m = min((uint32_t)SCAN_TILE, n - tl.i0);  // particles in this tile
+  // per-tile and per-target values, loaded before the first barrier so that
+  // their latency overlaps the weights' (loads are not moved across barriers)
+  const double pre = tile_pre[blockIdx.x];
+  const bool last_tile = tile_last[blockIdx.x] != 0;
+  const double tile_end = last_tile ? INFINITY : tile_pre[blockIdx.x + 1];
+  const int32_t flag = tflag[t];
+  const double neff = ws.tgt[t * 4 + 2];
+  const double u = ws.tgt[t * 4 + 3];
   {
     double wl[SCAN_ITEMS];
 #pragma unroll
@@ -1828,9 +1836,6 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
   }
   double tot;
   const double ex = block_excl_scan_monotone<TPB>(loc, lds, &tot);
-  const double pre = tile_pre[blockIdx.x];
-  const bool last_tile = tile_last[blockIdx.x] != 0;
-  const double tile_end = last_tile ? INFINITY : tile_pre[blockIdx.x + 1];
   // thread boundaries: non-decreasing, within [this tile's start, next tile's start]
   {
     const double b = pre + ex;
@@ -1839,9 +1844,9 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
   if (threadIdx.x == 0) bound[TPB] = tile_end;
   __syncthreads();  // also: every thread has read its weights from cl
   // kept weights: a target resamples only when N_eff < neff_frac * N
-  const bool keep = ws.lw && !tflag[t] && !(ws.tgt[t * 4 + 2] < neff_frac * (double)n);
+  const bool keep = ws.lw && !flag && !(neff < neff_frac * (double)n);
   if (tuni_next && tl.i0 == 0 && threadIdx.x == 0) tuni_next[t] = keep ? 0 : 1;
-  if (tflag[t] || keep) {
+  if (flag || keep) {
     // the particles stay (identity resampling): after a non-finite
     // normalisation, or when N_eff is above the threshold; then they keep
     // their normalised log-weights for the next frame
@@ -1887,7 +1892,6 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
     if (li < m) cdf[base + tl.i0 + li] = cl[cpad(li)];
   }
   // parents of the search blocks' first new particles that fall in this tile
-  const double u = ws.tgt[t * 4 + 3];
   const uint32_t jlo = count_below(pre, u, n);
   const uint32_t jhi = last_tile ? n : count_below(tile_end, u, n);
   const uint32_t first_tile = blockIdx.x - tl.i0 / SCAN_TILE;  // this target's tiles are consecutive
