@@ -1923,86 +1923,63 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
 // one binary search each.
 constexpr uint32_t SEARCH_LDS = 1024;
 
-constexpr int SEARCH_TILES = 2;  // search blocks (tiles of new particles) per workgroup
-
 template <bool SIR>
-__global__ __launch_bounds__(TPB) void k_resample_search(const Tile *__restrict__ tiles, uint32_t ntiles,
+__global__ __launch_bounds__(TPB) void k_resample_search(const Tile *__restrict__ tiles,
                                                          const uint32_t *__restrict__ off, WeightSrc ws,
                                                          const double *__restrict__ cdf,
                                                          const uint32_t *__restrict__ chunk_par,
                                                          const int32_t *__restrict__ tflag, uint32_t *__restrict__ anc,
                                                          double neff_frac) {
-  constexpr int K = SEARCH_TILES;
-  __shared__ double cs[K][SEARCH_LDS];
-  // the workgroup takes K consecutive tiles, so that their independent loads
-  // (range ends, then the staged cumulative weights) are in flight together
-  Tile tl[K];
-  uint32_t p0[K], p1[K];
-  double u[K];
-  bool skip[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const uint32_t tb = blockIdx.x * K + k;
-    tl[k] = tiles[min(tb, ntiles - 1)];
-    const uint32_t n = tl[k].n;
-    p0[k] = chunk_par[min(tb, ntiles - 1)];
-    p1[k] = tl[k].i0 + SCAN_TILE < n ? chunk_par[tb + 1] : n - 1;  // inclusive
-    u[k] = ws.tgt[tl[k].t * 4 + 3];
-    // targets that keep their particles were written by the scan
-    skip[k] = tb >= ntiles || tflag[tl[k].t] || (ws.lw && !(ws.tgt[tl[k].t * 4 + 2] < neff_frac * (double)n));
-  }
+  __shared__ double cs[SEARCH_LDS];
+  const Tile tl = tiles[blockIdx.x];
+  const int t = tl.t;
+  const uint32_t base = tl.base, n = tl.n;
+  // the loads that do not depend on each other are issued together
+  const uint32_t p0 = chunk_par[blockIdx.x];
+  const uint32_t p1 = tl.i0 + SCAN_TILE < n ? chunk_par[blockIdx.x + 1] : n - 1;  // inclusive
+  const double u = ws.tgt[t * 4 + 3];
+  // targets that keep their particles were written by the scan
+  if (tflag[t] || (ws.lw && !(ws.tgt[t * 4 + 2] < neff_frac * (double)n))) return;
+  const double dn = (double)n;
+  const double *__restrict__ C = cdf + base;
   // every stride-th C of the range in LDS (all of them when it fits); a
   // search then takes the LDS samples, then at most stride - 1 values
-  uint32_t stride[K], ns[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    stride[k] = ns[k] = 1;
-    if (skip[k]) continue;  // its range ends were not written this frame
-    const uint32_t span = p1[k] - p0[k] + 1;
-    stride[k] = (span + SEARCH_LDS - 1) / SEARCH_LDS;
-    ns[k] = (span + stride[k] - 1) / stride[k];
-    const double *__restrict__ C = cdf + tl[k].base;
-    for (uint32_t q = threadIdx.x; q < ns[k]; q += TPB) {
-      const uint32_t l = p0[k] + q * stride[k];
-      cs[k][q] = l + 1 >= tl[k].n ? INFINITY : C[l];  // the last particle stands for +infinity
-    }
+  const uint32_t span = p1 - p0 + 1;
+  const uint32_t stride = (span + SEARCH_LDS - 1) / SEARCH_LDS;
+  const uint32_t ns = (span + stride - 1) / stride;
+  for (uint32_t k = threadIdx.x; k < ns; k += TPB) {
+    const uint32_t l = p0 + k * stride;
+    cs[k] = l + 1 >= n ? INFINITY : C[l];  // the last particle stands for +infinity
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    if (skip[k]) continue;
-    const uint32_t base = tl[k].base, n = tl[k].n;
-    const double dn = (double)n;
-    const double *__restrict__ C = cdf + base;
-#pragma unroll
-    for (int it = 0; it < SCAN_ITEMS; ++it) {
-      const uint32_t j = tl[k].i0 + threadIdx.x * SCAN_ITEMS + it;
-      if (j >= n) break;
-      const double theta = ((double)j + u[k]) / dn;
-      // first sample above theta (ns if none: the answer is then in the last
-      // segment, whose end p1 is above theta)
-      uint32_t a = 0, b = ns[k];
-      while (a < b) {
-        const uint32_t mid = (a + b) >> 1;
-        if (cs[k][mid] > theta) b = mid;
-        else a = mid + 1;
-      }
-      uint32_t par;
-      if (stride[k] == 1) {
-        par = p0[k] + min(a, ns[k] - 1);
-      } else {
-        // the answer lies in (sample a-1, sample a]
-        uint32_t lo = a == 0 ? p0[k] : p0[k] + (a - 1) * stride[k] + 1;
-        uint32_t hi = a == ns[k] ? p1[k] : p0[k] + a * stride[k];
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (mid + 1 >= n || C[mid] > theta) hi = mid;
-          else lo = mid + 1;
-        }
-        par = lo;
-      }
-      anc[base + j] = par;
+  for (int it = 0; it < SCAN_ITEMS; ++it) {
+    const uint32_t j = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+    if (j >= n) break;
+    const double theta = ((double)j + u) / dn;
+    // first sample above theta (ns if none: the answer is then in the last
+    // segment, whose end p1 is above theta)
+    uint32_t a = 0, b = ns;
+    while (a < b) {
+      const uint32_t mid = (a + b) >> 1;
+      if (cs[mid] > theta) b = mid;
+      else a = mid + 1;
     }
+    uint32_t par;
+    if (stride == 1) {
+      par = p0 + min(a, ns - 1);
+    } else {
+      // the answer lies in (sample a-1, sample a]
+      uint32_t lo = a == 0 ? p0 : p0 + (a - 1) * stride + 1;
+      uint32_t hi = a == ns ? p1 : p0 + a * stride;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (mid + 1 >= n || C[mid] > theta) hi = mid;
+        else lo = mid + 1;
+      }
+      par = lo;
+    }
+    anc[base + j] = par;
   }
 }
 

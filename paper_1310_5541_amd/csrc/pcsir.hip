@@ -545,9 +545,8 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
                                           c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
                                           keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par));
   mark(c, "resample");
-  k_resample_search<false><<<(L.nS + SEARCH_TILES - 1) / SEARCH_TILES, TPB, 0, st>>>(
-      tS, L.nS, off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par), c->at<int32_t>(L.tflag), anc,
-      c->cfg.neff_threshold);
+  k_resample_search<false><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
+                                                 c->at<int32_t>(L.tflag), anc, c->cfg.neff_threshold);
   mark(c, "end");
 }
 
@@ -593,9 +592,8 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
                                          c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
                                          keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par));
   mark(c, "resample");
-  k_resample_search<true><<<(L.nS + SEARCH_TILES - 1) / SEARCH_TILES, TPB, 0, st>>>(
-      tS, L.nS, off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par), c->at<int32_t>(L.tflag), anc,
-      c->cfg.neff_threshold);
+  k_resample_search<true><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
+                                                c->at<int32_t>(L.tflag), anc, c->cfg.neff_threshold);
   mark(c, "end");
 }
 
