@@ -207,10 +207,18 @@ def main():
     if args.copy_bytes > 0:
         a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
-        for _ in range(3):
+        # three copies (the counter calibration counts them), each bracketed
+        # by HIP events: the fastest gives the bandwidth a plain copy reaches
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        for i in range(3):
             b.copy_(a)
+            ev[i + 1].record()
         torch.cuda.synchronize()
-        print(json.dumps({"copied_bytes": a.numel() * 4, "times": 3}))
+        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+        nbytes = a.numel() * 4
+        print(json.dumps({"copied_bytes": nbytes, "times": 3, "ms": [round(x, 4) for x in ms],
+                          "read_plus_write_gbs": round(2 * nbytes / (min(ms) * 1e-3) / 1e9, 1)}))
         return
     w0 = synth.preset(args.workload)
     K_total = max(w0.K, args.warmup + args.steps)
