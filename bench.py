@@ -219,7 +219,7 @@ def large_object(args, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (sharding over several GPUs "
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 (sharding over several GPUs "
                                    "is a design, not built)"}))
         sys.exit(2)
     import torch
