@@ -57,16 +57,20 @@ typedef enum {
  * the same value (the model image of Eq. object averaged over q x q midpoint
  * sub-samples per pixel); they differ only in floating-point rounding.
  *  DIRECT:    one exponential per sub-sample and pixel (P^2 q^2 per evaluation),
- *             the image-formation simulation written out;
+ *             the image-formation simulation written out, in binary32: its
+ *             log-likelihood errs by up to about 3e-7 of |l| (the rounding of
+ *             each model value to one binary32 word);
  *  SEPARABLE: the Gaussian factorises over x and y, so 2 P q exponentials per
- *             evaluation suffice. */
+ *             evaluation suffice; the per-axis sums, the model image and the
+ *             residuals are carried as binary32 pairs (about 48 bits), and the
+ *             log-likelihood errs by about 1e-8 absolute. */
 typedef enum {
   PCSIR_LIK_DIRECT = 0,
   PCSIR_LIK_SEPARABLE = 1,
   /* Learned surrogate of the dummies' log-likelihood (pcsir_mlp.h), BF16 or
    * FP8 matrix-core inference, with an exact check of a random share of the
-   * dummies each frame and exact recomputation (DIRECT) of every target whose
-   * check fails. pcsir_step only; sir_step stays exact (DIRECT). */
+   * dummies each frame and exact recomputation (SEPARABLE) of every target
+   * whose check fails. pcsir_step only; sir_step stays exact (SEPARABLE). */
   PCSIR_LIK_SURR_BF16 = 2,
   PCSIR_LIK_SURR_FP8 = 3
 } pcsir_lik_mode;

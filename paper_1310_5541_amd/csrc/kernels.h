@@ -1041,7 +1041,7 @@ __global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsig
                         const uint32_t *__restrict__ seg_key, const int32_t *__restrict__ seg_t,
                         const uint32_t *__restrict__ kbase, const int32_t *__restrict__ bbox_cur,
                         int32_t *__restrict__ dpix, float *__restrict__ doff, float *__restrict__ dint,
-                        float *__restrict__ dvel, const double *__restrict__ wacc,
+                        float *__restrict__ dlo, float *__restrict__ dvel, const double *__restrict__ wacc,
                         const int32_t *__restrict__ tuni) {
   const uint32_t B = (uint32_t)meta[META_B];
   const uint32_t NT = p.NT;
@@ -1058,19 +1058,25 @@ __global__ void k_dummy(Params p, const uint64_t *__restrict__ meta, const unsig
       const int32_t ma = p.tm[t * 3 + a];
       const int32_t c0 = floor_div(cell[a], ma);
       dpix[(size_t)a * NT + sidx] = c0;
-      float off;
+      double off;
       if (p.dummy_mode == 1) {
         const int32_t r = cell[a] - c0 * ma;  // cell within its pixel, 0..m-1
-        off = (float)(((double)r + 0.5) / (double)ma - 0.5);
+        off = ((double)r + 0.5) / (double)ma - 0.5;
       } else if (wt) {
-        off = (float)(wacc[(size_t)(1 + a) * NT + sidx] / wsum);
+        off = wacc[(size_t)(1 + a) * NT + sidx] / wsum;
       } else {
-        off = (float)((double)(long long)acc[(size_t)(1 + a) * NT + sidx] / (double)FX_POS / n);
+        off = (double)(long long)acc[(size_t)(1 + a) * NT + sidx] / (double)FX_POS / n;
       }
-      doff[(size_t)a * NT + sidx] = off;
+      // the offset as a pair of binary32 words (hi + lo)
+      const float oh = (float)off;
+      doff[(size_t)a * NT + sidx] = oh;
+      dlo[(size_t)a * NT + sidx] = (float)(off - (double)oh);
     }
-    dint[sidx] = wt ? (float)(wacc[(size_t)(1 + 2 * DIM) * NT + sidx] / wsum)
-                    : (float)((double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + sidx] / (double)FX_INT / n);
+    const double in0 = wt ? wacc[(size_t)(1 + 2 * DIM) * NT + sidx] / wsum
+                          : (double)(long long)acc[(size_t)(1 + 2 * DIM) * NT + sidx] / (double)FX_INT / n;
+    const float ih = (float)in0;
+    dint[sidx] = ih;
+    dlo[(size_t)DIM * NT + sidx] = (float)(in0 - (double)ih);
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
       dvel[(size_t)a * NT + sidx] =
@@ -1091,6 +1097,8 @@ struct LikInput {
   const int32_t *dpix;  // [dim][E] pixel of the cell (pcSIR)
   const float *doff;    // [dim][E] offset from it (pcSIR)
   const float *dint;    // [E] intensity (pcSIR)
+  const float *dlo;     // [dim + 1][E] low words of the offsets and of the intensity (pcSIR):
+                        // the dummy's mean is offset + low word, intensity + low word
   const int32_t *seg_t; // [E] target (pcSIR)
   const float *state;   // SoA state (SIR)
   const uint32_t *off;  // [T+1] (SIR)
@@ -1124,13 +1132,13 @@ __device__ __forceinline__ float exp2_neg(float a) {
 struct ExpScale {
   float xh, xl, yh, yl;
 };
-__device__ __forceinline__ ExpScale psf_scale(const Params &p, float zpos) {
+__device__ __forceinline__ ExpScale psf_scale(const Params &p, double zpos) {
   const double LOG2E = 1.4426950408889634074;
   const double s0 = (double)p.sigma_psf;
   double sx2 = s0 * s0, sy2 = s0 * s0;
   if (p.psf == 1) {
-    const double ax = ((double)zpos - (double)p.astig_gamma) / (double)p.astig_d;
-    const double ay = ((double)zpos + (double)p.astig_gamma) / (double)p.astig_d;
+    const double ax = (zpos - (double)p.astig_gamma) / (double)p.astig_d;
+    const double ay = (zpos + (double)p.astig_gamma) / (double)p.astig_d;
     sx2 *= 1.0 + ax * ax;
     sy2 *= 1.0 + ay * ay;
   }
@@ -1148,6 +1156,99 @@ __device__ __forceinline__ float scaled_sq(float u, float kh, float kl) {
 }
 // Sub-sample offset within a pixel: (a + 1/2)/q - 1/2 = (2a + 1 - q) / (2q).
 __device__ __forceinline__ float sub_offset(int a, int q) { return (float)(2 * a + 1 - q) / (float)(2 * q); }
+
+// ---------------------------------------------------------------- FP32 pairs
+// The separable likelihood carries the model image in unevaluated FP32 pairs
+// (hi + lo, about 48 significant bits). A model value rounded to one FP32
+// word errs by up to 6e-8 of itself; where a window holds residuals of tens
+// of counts (a neighbouring spot the model lacks), that rounding alone moves
+// the log-likelihood by about 1e-5, the size of the whole weight tolerance.
+// The build disables implicit multiply-add contraction, so each operation
+// below rounds where it is written.
+
+// a + b = s + e exactly (Knuth's TwoSum; no condition on the operands).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+// a + b = s + e exactly when |a| >= |b| or a = 0 (Dekker's Fast2Sum).
+__device__ __forceinline__ void fast_two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  e = b - (s - a);
+}
+// (sh, sl) += (eh, el), the sum kept as a pair.
+__device__ __forceinline__ void pair_acc(float &sh, float &sl, float eh, float el) {
+  float s, e;
+  two_sum(sh, eh, s, e);
+  sh = s;
+  sl += e + el;
+}
+// (ah, al) (bh, bl) as a pair (al bl dropped: below 2^-46 of the product).
+__device__ __forceinline__ void pair_mul(float ah, float al, float bh, float bl, float &ph, float &pl) {
+  ph = ah * bh;
+  float e = fmaf(ah, bh, -ph);  // ah bh = ph + e exactly
+  e = fmaf(ah, bl, e);
+  pl = fmaf(al, bh, e);
+}
+
+// 2^(j/64) for j = -32..32 as FP32 pairs: one LDS table per block.
+constexpr int EXP2_TBL = 65;
+__device__ __forceinline__ void exp2_table_fill(float2 *tbl) {
+  for (int j = threadIdx.x; j < EXP2_TBL; j += blockDim.x) {
+    const double v = exp2((double)(j - 32) / 64.0);
+    const float h = (float)v;
+    tbl[j] = make_float2(h, (float)(v - (double)h));
+  }
+}
+
+// 2^-(ah + al) as a pair (rh, rl), for ah >= 0 and |al| <= 2^-20 ah (a pair
+// exponent). With n the integer nearest ah, f = n - ah is exact and
+// |f| <= 1/2; f = j/64 + t with integer j and |t| <= 1/128, again exact.
+// Then 2^(t - al) = e^y = 1 + p, y = (t - al) ln 2 (|y| < 0.0055), with p from
+// the Taylor series to degree 4 (remainder below 4e-14 of the result) and y
+// formed as a pair; 2^(j/64) comes from the table; the scaling by 2^-n is
+// exact. Relative error about 6e-10 (the rounding of the table product).
+__device__ __forceinline__ void exp2_neg_pair(float ah, float al, const float2 *tbl, float &rh, float &rl) {
+  constexpr float LN2_HI = 0.693147182464599609375f;  // ln 2 rounded to binary32
+  constexpr float LN2_LO = (float)(0.69314718055994530942 - 0.693147182464599609375);
+  ah = fminf(ah, 200.0f);
+  const float n = rintf(ah);
+  const float f = n - ah;
+  const float j = rintf(f * 64.0f);
+  const float t = (f - j * 0.015625f) - al;
+  const float yh = t * LN2_HI;
+  const float yl = fmaf(t, LN2_HI, -yh) + t * LN2_LO;
+  float c = fmaf(yh, 1.0f / 24.0f, 1.0f / 6.0f);
+  c = fmaf(yh, c, 0.5f);
+  const float qd = (yh * yh) * c;          // y^2/2 + y^3/6 + y^4/24
+  const float ph = yh + (yl + qd);
+  const float pl = ((yh - ph) + yl) + qd;  // yh - ph is exact
+  const float2 tb = tbl[(int)j + 32];
+  const float s = fmaf(tb.x, ph, fmaf(tb.x, pl, tb.y));
+  float h, l;
+  fast_two_sum(tb.x, s, h, l);
+  const int e = -(int)n;
+  rh = ldexpf(h, e);
+  rl = ldexpf(l, e);
+}
+
+// exp(-(U - d)^2 / (2 s^2)) = 2^-(k (U - d)^2) as a pair, for an exact
+// sub-sample position U, a pair offset d = dh + dl and a pair scale k = kh + kl.
+__device__ __forceinline__ void psf_factor_pair(float U, float dh, float dl, float kh, float kl, const float2 *tbl,
+                                                float &eh, float &el) {
+  float uh, ue;
+  two_sum(U, -dh, uh, ue);
+  const float ul = ue - dl;           // U - d = uh + ul
+  const float sh = uh * uh;
+  float sl = fmaf(uh, uh, -sh);
+  sl = fmaf(2.0f * uh, ul, sl);       // (U - d)^2 = sh + sl
+  const float ah = sh * kh;
+  float al = fmaf(sh, kh, -ah);
+  al = fmaf(sh, kl, al);
+  al = fmaf(sl, kh, al);              // k (U - d)^2 = ah + al
+  exp2_neg_pair(ah, al, tbl, eh, el);
+}
 
 // Evaluation sets of k_lik: every dummy / particle; the dummies picked for
 // the surrogate's exact check (list, see k_surr_pick); the dummies of targets
@@ -1267,15 +1368,18 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
   const int lane = lane_id();
   const int P = p.P, R = p.R, P2 = P * P;
   const int q = Q ? Q : p.q;
-  const ExpScale ks_flat = psf_scale(p, 0.0f);  // the scale of a z-independent PSF, formed once
+  const ExpScale ks_flat = psf_scale(p, 0.0);  // the scale of a z-independent PSF, formed once
   // window column and row of this lane's pixel in round 0; each round of 64
   // pixels then advances them by (64 mod P, 64 div P) with one wrap, instead
   // of an integer division per round
   const int pc_first = lane % P, pr_first = lane / P;
   const int dpc = WAVE % P, dpr = WAVE / P;
-  // sub-sample offsets (a + 1/2) / q - 1/2, a < q, formed once per block
+  // sub-sample offsets (a + 1/2) / q - 1/2, a < q, formed once per block, and
+  // (SEPARABLE) the table of the pair exponential
   __shared__ float soff[MAX_QUAD];
+  __shared__ float2 e2tbl[SEP ? EXP2_TBL : 1];
   if (threadIdx.x < MAX_QUAD) soff[threadIdx.x] = (int)threadIdx.x < q ? sub_offset((int)threadIdx.x, q) : 0.0f;
+  if (SEP) exp2_table_fill(e2tbl);
   __syncthreads();
   // SEPARABLE with H = 64 / (2P) >= 1 lanes per per-axis sum: this lane's
   // (axis, pixel, first sub-sample), fixed for the launch
@@ -1286,11 +1390,15 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
   const int s_pixel = H >= 1 ? s_rem / H : 0;
   const int s_part = s_rem - s_pixel * H;
   const float s_cc = (float)(s_pixel - R);
+  const float inv_q2 = 1.0f / (float)(q * q);
   for (uint32_t idx = blockIdx.x * LIK_WAVES + wave_id(); idx < E; idx += gridDim.x * LIK_WAVES) {
     const uint32_t e = MODE == LIK_ALL ? idx : (MODE == LIK_STENCIL ? idx / 9u : chk.list[idx]);
     int t;
     int32_t c0, r0;
-    float dx, dy, I0, zpos = 0.0f;
+    // dummy / particle: offsets from the window's centre pixel and intensity,
+    // each as a pair (hi + lo); a particle's are exact in one word
+    float dx, dy, I0, dxl = 0.0f, dyl = 0.0f, I0l = 0.0f;
+    double zpos = 0.0;
     if (SIR) {
       int lo = 0, hi = p.T - 1;
       while (lo < hi) {
@@ -1305,7 +1413,7 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       r0 = cell_index(y, 1);
       dx = x - (float)c0;  // exact
       dy = y - (float)r0;
-      if (DIM == 3) zpos = in.state[(size_t)2 * p.NT + e];
+      if (DIM == 3) zpos = (double)in.state[(size_t)2 * p.NT + e];
       I0 = in.state[(size_t)(2 * DIM) * p.NT + e];
     } else {
       t = in.seg_t[e];
@@ -1313,17 +1421,25 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       r0 = in.dpix[(size_t)p.NT + e];
       dx = in.doff[e];
       dy = in.doff[(size_t)p.NT + e];
-      if (DIM == 3) zpos = (float)in.dpix[(size_t)2 * p.NT + e] + in.doff[(size_t)2 * p.NT + e];
+      dxl = in.dlo[e];
+      dyl = in.dlo[(size_t)p.NT + e];
+      if (DIM == 3)
+        zpos = (double)in.dpix[(size_t)2 * p.NT + e] + (double)in.doff[(size_t)2 * p.NT + e] +
+               (double)in.dlo[(size_t)2 * p.NT + e];
       I0 = in.dint[e];
+      I0l = in.dlo[(size_t)DIM * p.NT + e];
       if (MODE == LIK_STENCIL) {
-        // the shifted position, formed in binary64 and rounded once
+        // the shifted position, formed in binary64 and split into a pair
         const int sidx = (int)(idx - 9u * e);
-        dx = (float)((double)dx + (double)(sidx % 3 - 1) * (0.5 / (double)p.tm[t * 3 + 0]));
-        dy = (float)((double)dy + (double)(sidx / 3 - 1) * (0.5 / (double)p.tm[t * 3 + 1]));
+        const double sx = (double)dx + (double)dxl + (double)(sidx % 3 - 1) * (0.5 / (double)p.tm[t * 3 + 0]);
+        const double sy = (double)dy + (double)dyl + (double)(sidx / 3 - 1) * (0.5 / (double)p.tm[t * 3 + 1]);
+        dx = (float)sx;
+        dxl = (float)(sx - (double)dx);
+        dy = (float)sy;
+        dyl = (float)(sy - (double)dy);
       }
     }
     const ExpScale ks = (DIM == 3 && p.psf == 1) ? psf_scale(p, zpos) : ks_flat;
-    const float Iq = I0 / (float)(q * q);
     const gfloat *fr = as_global(frame) + (p.per_target_frames ? (size_t)t * p.H * p.W : 0);
     // window pixels of the first ZPRE rounds loaded before the model is
     // formed, so that their latency overlaps it: clamped coordinates, and a
@@ -1339,7 +1455,7 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
         const int pix = it * WAVE + lane;
         const int c = c0 + pc - R, r = r0 + pr - R;
         const float v = fr[(size_t)min(max(r, 0), p.H - 1) * p.W + min(max(c, 0), p.W - 1)];
-        zpre[it] = (v - p.i_bg) * ((pix < P2 && c >= 0 && c < p.W && r >= 0 && r < p.H) ? 1.0f : 0.0f);
+        zpre[it] = v * ((pix < P2 && c >= 0 && c < p.W && r >= 0 && r < p.H) ? 1.0f : 0.0f);
         pc += dpc;
         pr += dpr;
         if (pc >= P) {
@@ -1348,111 +1464,189 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
         }
       }
     }
-    // SEPARABLE: the 2 P per-axis sums over q sub-samples are spread over the
-    // wave, H = 64 / (2P) lanes per sum, each adding every H-th sub-sample; the
-    // sum of (axis, pixel c) ends up in lane (axis P + c) H. With 2P > 64, lane
-    // j forms both axes' sums of pixel j and, for P > 64, of pixel j + 64.
-    float gxl = 0.0f, gyl = 0.0f, gxh = 0.0f, gyh = 0.0f;
+    float ssd = 0.0f, err = 0.0f;
     if (SEP) {
+      // Per-axis sums g_x(c) = sum_a exp(-(c + o_a - x)^2 / 2 s_x^2) (and g_y) as
+      // pairs. With H = 64 / (2P) >= 1 they are spread over the wave, H lanes per
+      // sum, each adding every H-th sub-sample; the sum of (axis, pixel c) ends
+      // up in lane (axis P + c) H. With 2P > 64, lane j forms both axes' sums of
+      // pixel j and, for P > 64, of pixel j + 64. The x sums are then scaled by
+      // the intensity per sub-sample, A(c) = I0 g_x(c) / q^2, so that the model
+      // value of pixel (c, r) is one pair product A(c) g_y(r).
+      float Iqh = I0 * inv_q2;
+      float Iql = (fmaf(-Iqh, (float)(q * q), I0) + I0l) * inv_q2;  // I0 - Iqh q^2 is exact
+      if ((q & (q - 1)) == 0) Iql = I0l * inv_q2;                     // q^2 a power of two: Iqh exact
+      float ah = 0.0f, al = 0.0f, bh = 0.0f, bl = 0.0f;  // H >= 1: (ah, al); else x (a) and y (b) of pixel lane
+      float ch = 0.0f, cl = 0.0f, eh = 0.0f, el = 0.0f;  // P > 64: x (c) and y (e) of pixel lane + 64
       if (H >= 1) {
         if (s_on) {
-          const float d = s_axis ? dy : dx;
+          const float d = s_axis ? dy : dx, dl = s_axis ? dyl : dxl;
           const float kh = s_axis ? ks.yh : ks.xh, kl = s_axis ? ks.yl : ks.xl;
-          for (int a = s_part; a < q; a += H) gxl += exp2_neg(scaled_sq((s_cc + soff[a]) - d, kh, kl));
+          for (int a = s_part; a < q; a += H) {
+            float vh, vl;
+            psf_factor_pair(s_cc + soff[a], d, dl, kh, kl, e2tbl, vh, vl);
+            pair_acc(ah, al, vh, vl);
+          }
         }
-        float tot = gxl;
-        for (int h = 1; h < H; ++h) tot += __shfl(gxl, (lane + h) & (WAVE - 1), WAVE);
-        gxl = tot;
+        float th = ah, tl = al;
+        for (int h = 1; h < H; ++h) {
+          const int src = (lane + h) & (WAVE - 1);
+          pair_acc(th, tl, __shfl(ah, src, WAVE), __shfl(al, src, WAVE));
+        }
+        if (s_axis == 0) pair_mul(Iqh, Iql, th, tl, ah, al);
+        else {
+          ah = th;
+          al = tl;
+        }
       } else {
         if (lane < P) {
           const float cc = (float)(lane - R);
           for (int a = 0; a < q; ++a) {
-            const float o = soff[a];
-            gxl += exp2_neg(scaled_sq((cc + o) - dx, ks.xh, ks.xl));
-            gyl += exp2_neg(scaled_sq((cc + o) - dy, ks.yh, ks.yl));
+            float vh, vl;
+            psf_factor_pair(cc + soff[a], dx, dxl, ks.xh, ks.xl, e2tbl, vh, vl);
+            pair_acc(ah, al, vh, vl);
+            psf_factor_pair(cc + soff[a], dy, dyl, ks.yh, ks.yl, e2tbl, vh, vl);
+            pair_acc(bh, bl, vh, vl);
           }
+          float th, tl;
+          pair_mul(Iqh, Iql, ah, al, th, tl);
+          ah = th;
+          al = tl;
         }
         if (lane + WAVE < P) {
           const float cc = (float)(lane + WAVE - R);
           for (int a = 0; a < q; ++a) {
-            const float o = soff[a];
-            gxh += exp2_neg(scaled_sq((cc + o) - dx, ks.xh, ks.xl));
-            gyh += exp2_neg(scaled_sq((cc + o) - dy, ks.yh, ks.yl));
+            float vh, vl;
+            psf_factor_pair(cc + soff[a], dx, dxl, ks.xh, ks.xl, e2tbl, vh, vl);
+            pair_acc(ch, cl, vh, vl);
+            psf_factor_pair(cc + soff[a], dy, dyl, ks.yh, ks.yl, e2tbl, vh, vl);
+            pair_acc(eh, el, vh, vl);
           }
+          float th, tl;
+          pair_mul(Iqh, Iql, ch, cl, th, tl);
+          ch = th;
+          cl = tl;
         }
       }
-    }
-    float ssd = 0.0f, err = 0.0f;
-    int pc = pc_first, pr = pr_first;
-    for (int pix0 = 0, it = 0; pix0 < P2; pix0 += WAVE, ++it) {
-      const int pix = pix0 + lane;
-      float g = 0.0f;
-      if (SEP) {
+      int pc = pc_first, pr = pr_first;
+      for (int pix0 = 0, it = 0; pix0 < P2; pix0 += WAVE, ++it) {
+        const int pix = pix0 + lane;
         const int pcs = pc < P ? pc : 0, prs = pr < P ? pr : 0;
-        float gx, gy;
+        float xh, xl, yh, yl;
         if (H >= 1) {
-          gx = __shfl(gxl, pcs * H, WAVE);
-          gy = __shfl(gxl, (P + prs) * H, WAVE);
+          xh = __shfl(ah, pcs * H, WAVE);
+          xl = __shfl(al, pcs * H, WAVE);
+          yh = __shfl(ah, (P + prs) * H, WAVE);
+          yl = __shfl(al, (P + prs) * H, WAVE);
         } else if (P <= WAVE) {
-          gx = __shfl(gxl, pcs, WAVE);
-          gy = __shfl(gyl, prs, WAVE);
+          xh = __shfl(ah, pcs, WAVE);
+          xl = __shfl(al, pcs, WAVE);
+          yh = __shfl(bh, prs, WAVE);
+          yl = __shfl(bl, prs, WAVE);
         } else {
-          // every lane takes part in all four shuffles; each keeps the slot of its pixel
-          const float xa = __shfl(gxl, pcs & (WAVE - 1), WAVE), xb = __shfl(gxh, pcs & (WAVE - 1), WAVE);
-          const float ya = __shfl(gyl, prs & (WAVE - 1), WAVE), yb = __shfl(gyh, prs & (WAVE - 1), WAVE);
-          gx = pcs < WAVE ? xa : xb;
-          gy = prs < WAVE ? ya : yb;
+          // every lane takes part in all shuffles; each keeps the slot of its pixel
+          const int sc = pcs & (WAVE - 1), sr = prs & (WAVE - 1);
+          const float x0h = __shfl(ah, sc, WAVE), x0l = __shfl(al, sc, WAVE);
+          const float x1h = __shfl(ch, sc, WAVE), x1l = __shfl(cl, sc, WAVE);
+          const float y0h = __shfl(bh, sr, WAVE), y0l = __shfl(bl, sr, WAVE);
+          const float y1h = __shfl(eh, sr, WAVE), y1l = __shfl(el, sr, WAVE);
+          xh = pcs < WAVE ? x0h : x1h;
+          xl = pcs < WAVE ? x0l : x1l;
+          yh = prs < WAVE ? y0h : y1h;
+          yl = prs < WAVE ? y0l : y1l;
         }
-        g = gx * gy;
-      } else if (pix < P2) {
-        const float cc = (float)(pc - R), rr = (float)(pr - R);
-        if (Q) {
-          float ax[Q > 0 ? Q : 1];
+        if (pix < P2) {
+          const int c = c0 + pc - R, r = r0 + pr - R;
+          const bool inside = c >= 0 && c < p.W && r >= 0 && r < p.H;
+          float z = 0.0f;
+          if (it < ZPRE) {
 #pragma unroll
-          for (int a = 0; a < Q; ++a) ax[a] = scaled_sq((cc + sub_offset(a, Q)) - dx, ks.xh, ks.xl);
-#pragma unroll
-          for (int b = 0; b < Q; ++b) {
-            const float ay = scaled_sq((rr + sub_offset(b, Q)) - dy, ks.yh, ks.yl);
-#pragma unroll
-            for (int a = 0; a < Q; ++a) g += exp2_neg(ax[a] + ay);
+            for (int u = 0; u < ZPRE; ++u)
+              if (u == it) z = zpre[u];
+          } else if (inside) {
+            z = fr[(size_t)r * p.W + c];
           }
-        } else {
-          for (int b = 0; b < q; ++b) {
-            const float ay = scaled_sq((rr + sub_offset(b, q)) - dy, ks.yh, ks.yl);
-            for (int a = 0; a < q; ++a)
-              g += exp2_neg(scaled_sq((cc + sub_offset(a, q)) - dx, ks.xh, ks.xl) + ay);
-          }
+          // frame value minus background (a pixel outside the frame reads as the
+          // background) and minus the model image, as pairs
+          float zh = 0.0f, zl = 0.0f;
+          if (inside) two_sum(z, -p.i_bg, zh, zl);
+          float mh, ml;
+          pair_mul(xh, xl, yh, yl, mh, ml);
+          float dh, de;
+          two_sum(zh, -mh, dh, de);
+          const float dl = (de + zl) - ml;
+          const float sq = dh * dh;
+          float sqe = fmaf(dh, dh, -sq);
+          sqe = fmaf(2.0f * dh, dl, sqe);  // d^2 = sq + sqe (+ dl^2)
+          float s2, e2;
+          two_sum(ssd, sq, s2, e2);
+          ssd = s2;
+          err += e2 + sqe;
+        }
+        pc += dpc;
+        pr += dpr;
+        if (pc >= P) {
+          pc -= P;
+          ++pr;
         }
       }
-      if (pix < P2) {
-        const int c = c0 + pc - R, r = r0 + pr - R;
-        float zb = 0.0f;
-        if (it < ZPRE) {
+    } else {
+      const float Iq = I0 / (float)(q * q);
+      int pc = pc_first, pr = pr_first;
+      for (int pix0 = 0, it = 0; pix0 < P2; pix0 += WAVE, ++it) {
+        const int pix = pix0 + lane;
+        if (pix < P2) {
+          float g = 0.0f;
+          const float cc = (float)(pc - R), rr = (float)(pr - R);
+          if (Q) {
+            float ax[Q > 0 ? Q : 1];
 #pragma unroll
-          for (int u = 0; u < ZPRE; ++u)
-            if (u == it) zb = zpre[u];
-        } else if (c >= 0 && c < p.W && r >= 0 && r < p.H) {
-          zb = fr[(size_t)r * p.W + c] - p.i_bg;
+            for (int a = 0; a < Q; ++a) ax[a] = scaled_sq((cc + sub_offset(a, Q)) - dx, ks.xh, ks.xl);
+#pragma unroll
+            for (int b = 0; b < Q; ++b) {
+              const float ay = scaled_sq((rr + sub_offset(b, Q)) - dy, ks.yh, ks.yl);
+#pragma unroll
+              for (int a = 0; a < Q; ++a) g += exp2_neg(ax[a] + ay);
+            }
+          } else {
+            for (int b = 0; b < q; ++b) {
+              const float ay = scaled_sq((rr + sub_offset(b, q)) - dy, ks.yh, ks.yl);
+              for (int a = 0; a < q; ++a)
+                g += exp2_neg(scaled_sq((cc + sub_offset(a, q)) - dx, ks.xh, ks.xl) + ay);
+            }
+          }
+          const int c = c0 + pc - R, r = r0 + pr - R;
+          // frame value minus background; a pixel outside the frame reads as the background
+          const bool inside = c >= 0 && c < p.W && r >= 0 && r < p.H;
+          float z = 0.0f;
+          if (it < ZPRE) {
+#pragma unroll
+            for (int u = 0; u < ZPRE; ++u)
+              if (u == it) z = zpre[u];
+          } else if (inside) {
+            z = fr[(size_t)r * p.W + c];
+          }
+          const float zb = inside ? z - p.i_bg : 0.0f;
+          // residual d = zb - Iq g and its square as FP32 (hi, lo) pairs: a residual
+          // of ~100 (a spot the model lacks) would otherwise lose 1e-5 of l per particle
+          const float mg = Iq * g;
+          const float mge = fmaf(Iq, g, -mg);          // Iq g = mg + mge exactly
+          const float dh = zb - mg;
+          const float bv = dh - zb;
+          const float dl = ((zb - (dh - bv)) + (-mg - bv)) - mge;  // zb - mg = dh + (..) exactly
+          const float sq = dh * dh;
+          const float sqe = fmaf(dh, dh, -sq) + 2.0f * dh * dl;   // d^2 = sq + sqe (+ dl^2)
+          const float tsum = ssd + sq;
+          const float bp = tsum - ssd;
+          err += ((ssd - (tsum - bp)) + (sq - bp)) + sqe;
+          ssd = tsum;
         }
-        // residual d = zb - Iq g and its square as FP32 (hi, lo) pairs: a residual
-        // of ~100 (a spot the model lacks) would otherwise lose 1e-5 of l per particle
-        const float mg = Iq * g;
-        const float mge = fmaf(Iq, g, -mg);          // Iq g = mg + mge exactly
-        const float dh = zb - mg;
-        const float bv = dh - zb;
-        const float dl = ((zb - (dh - bv)) + (-mg - bv)) - mge;  // zb - mg = dh + (..) exactly
-        const float sq = dh * dh;
-        const float sqe = fmaf(dh, dh, -sq) + 2.0f * dh * dl;   // d^2 = sq + sqe (+ dl^2)
-        const float tsum = ssd + sq;
-        const float bp = tsum - ssd;
-        err += ((ssd - (tsum - bp)) + (sq - bp)) + sqe;
-        ssd = tsum;
-      }
-      pc += dpc;
-      pr += dpr;
-      if (pc >= P) {
-        pc -= P;
-        ++pr;
+        pc += dpc;
+        pr += dpr;
+        if (pc >= P) {
+          pc -= P;
+          ++pr;
+        }
       }
     }
     // compensated wave sum; the (hi, lo) result is combined and scaled in FP64,

@@ -23,7 +23,7 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 struct Layout {
-  size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint,
+  size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint, dlo,
       ll, ll9, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
       bbox_part, mom_part, tm, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
       tiles256, tilesS, tilesB, tilesK, tile_last, tfirst, t256_first, off, chunk_par;
@@ -165,6 +165,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.dpix = take(4 * dim * NT);
   L.doff = take(4 * dim * NT);
   L.dint = take(4 * NT);
+  L.dlo = take(4 * (dim + 1) * NT);
   L.dvel = take(4 * dim * NT);
   L.ll = take(8 * NT);
   L.wbin = take(8 * NT);
@@ -389,19 +390,13 @@ void launch_surrogate(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   const Params &p = c->p;
   mark(c, "surr_check");
   k_surr_pick<<<pg, TPB, 0, st>>>(p, meta, desc, in.seg_t, c->surr_fraction, list_chk, meta_w + META_NCHK);
-  if (p.q == 8)
-    k_lik<DIM, false, false, 8, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
-  else
-    k_lik<DIM, false, false, 0, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
+  k_lik<DIM, false, true, 0, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
   k_surr_stats<<<1, TPB, 0, st>>>(chk.err, meta_w);
   k_surr_decide<<<(p.T + TPB - 1) / TPB, TPB, 0, st>>>(p.T, chk.tol, chk.tsse, chk.tcnt, tfb);
   mark(c, "surr_fallback");
   k_surr_fallback_list<<<pg, TPB, 0, st>>>(meta, in.seg_t, tfb, list_fb, meta_w + META_NFB);
   chk.list = list_fb;
-  if (p.q == 8)
-    k_lik<DIM, false, false, 8, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
-  else
-    k_lik<DIM, false, false, 0, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
+  k_lik<DIM, false, true, 0, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
 }
 
 template <int DIM, bool SEP>
@@ -494,11 +489,12 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   k_dummy<DIM><<<grid_stride_blocks(c, p.NT, TPB), TPB, 0, st>>>(
       p, meta, acc, c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.kbase),
       c->at<int32_t>(L.bbox_cur), c->at<int32_t>(L.dpix), c->at<float>(L.doff), c->at<float>(L.dint),
-      c->at<float>(L.dvel), wacc, tuni);
+      c->at<float>(L.dlo), c->at<float>(L.dvel), wacc, tuni);
   LikInput in;
   in.dpix = c->at<int32_t>(L.dpix);
   in.doff = c->at<float>(L.doff);
   in.dint = c->at<float>(L.dint);
+  in.dlo = c->at<float>(L.dlo);
   in.seg_t = c->at<int32_t>(L.seg_t);
   in.state = sout;
   in.off = off;
@@ -598,7 +594,8 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
 }
 
 void launch_step(pcsir_ctx *c, bool sir, hipStream_t st) {
-  const bool sep = c->cfg.lik_mode == PCSIR_LIK_SEPARABLE;
+  // the surrogate modes' exact evaluations (sir_step, check, fallback) use the separable form
+  const bool sep = c->cfg.lik_mode != PCSIR_LIK_DIRECT;
   if (sir) {
     if (c->cfg.dim == 2) sep ? launch_sir<2, true>(c, st) : launch_sir<2, false>(c, st);
     else sep ? launch_sir<3, true>(c, st) : launch_sir<3, false>(c, st);

@@ -9,16 +9,17 @@ Tolerances (derived in the design notes from the FP32 arithmetic of the path):
   propagate      |d| <= 1e-6 * |x| + 2e-6
   keys, bins     bit-exact (keys, counts, bin order, targets)
   bin means      positions 1e-7 px, velocities 1e-7, intensity 1e-6
-  log-likelihood |d| <= 5e-6 + 3e-7 |l|: the window's sum of squares S = -2 sigma_xi^2 l
-                 is formed in FP32 from P^2 q^2 hardware exp2 values; a bias of a
-                 few ulp in them shifts every model pixel the same way, so the
-                 error grows with S (about 2.5 FP32 ulp of l). Near the weight
-                 maximum |l| is small and the bound stays below the 1e-5 that
-                 the weights allow; far from it the weights are negligible.
-  weights        inherited from l: w_i = exp(l_i - M) / S, so to first order
-                 dw_i / w_i = dl_i - sum_j w_j dl_j, and with the bound tol(l) of
-                 the log-likelihood row, |dw_i| <= 1.01 (tol(l_i) + sum_j w_j
-                 tol(l_j)) w_i + 1e-12 max w
+  log-likelihood separable form (model image in FP32 pairs; also the surrogate's exact
+                 check and fallback, and SIR in those modes): |d| <= 2e-6 + 1e-9 |l|.
+                 Per-sub-sample form (one FP32 word per model value):
+                 |d| <= 5e-6 + 3e-7 |l|; the rounding of each model value (6e-8 of
+                 it) times residuals of tens of counts gives errors that grow with
+                 the window's sum of squares S = -2 sigma_xi^2 l.
+  weights        separable form: |dw_i| <= 1e-5 w_i + 1e-10 max w (relative 1e-5,
+                 with a floor for weights that are negligible next to the largest).
+                 Per-sub-sample form: inherited from its l bound, w_i = exp(l_i - M) / S,
+                 so to first order dw_i / w_i = dl_i - sum_j w_j dl_j and
+                 |dw_i| <= 1.01 (tol(l_i) + sum_j w_j tol(l_j)) w_i + 1e-12 max w
   estimates      rel 1e-5 (abs 1e-5); N_eff rel 1e-5
   resampling u   bit-exact
   s(j)           bit-exact except where the oracle's cumulative weight lies
@@ -33,8 +34,24 @@ import sys
 
 import numpy as np
 
-LL_ATOL = 5e-6
+LL_ATOL = 5e-6          # per-sub-sample form
 LL_RTOL = 3e-7
+LL_SEP_ATOL = 2e-6      # separable form (pairs)
+LL_SEP_RTOL = 1e-9
+W_RTOL = 1e-5           # weights, separable form: 1e-5 w + 1e-10 max w
+W_FLOOR = 1e-10
+
+
+def pair_form(cfg, sir):
+    """True when the step's exact log-likelihoods come from the separable pair form."""
+    return cfg.lik_mode != 0
+
+
+def ll_tol(cfg, sir, ll):
+    ll = np.abs(np.asarray(ll, dtype=np.float64))
+    if pair_form(cfg, sir):
+        return LL_SEP_ATOL + LL_SEP_RTOL * ll
+    return LL_ATOL + LL_RTOL * ll
 
 
 def log(msg: str):
@@ -64,6 +81,13 @@ def weight_bound(ll_of_particle, wo, tl=None):
     if tl is None:
         tl = LL_ATOL + LL_RTOL * np.abs(ll_of_particle)
     return 1.01 * (tl + np.sum(wo * tl)) * wo + 1e-12 * wo.max()
+
+
+def w_bound(cfg, sir, ll_of_particle, wo):
+    """Largest |w_gpu - w_oracle| per particle for the step's likelihood form."""
+    if pair_form(cfg, sir):
+        return W_RTOL * wo + W_FLOOR * wo.max()
+    return weight_bound(ll_of_particle, wo)
 
 
 def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, surrogate=None, on_filter=None,
@@ -165,7 +189,7 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
             ll_g = ll_gpu[gsl].astype(np.float64)
             dev["B"] += B
         d_ll = np.abs(ll_g - ll_o)
-        tol_ll = LL_ATOL + LL_RTOL * np.abs(ll_o)
+        tol_ll = ll_tol(cfg, sir, ll_o)
         if not sir and cfg.dummy_mode == 2:
             # second-order dummies: nine evaluations, each within tol, enter through
             # central differences of step delta = half a cell, with |S| <= delta^2:
@@ -187,12 +211,19 @@ def run_step_parity(cfg, cloud, frames, k, sir, check_prop=True, report=None, su
         dev["ll"] = max(dev["ll"], float(d_ll.max()))
         dev["ll_rel"] = max(dev.get("ll_rel", 0.0), float(np.max(d_ll / np.maximum(np.abs(ll_o), 1.0))))
         wg, wo = w_gpu[a:b], r["w"]
-        tl_p = tol_ll[r["bin_of"]] if (not sir and cfg.dummy_mode == 2) else None
-        e_w = np.abs(wg - wo) - weight_bound(r["ll"][r["bin_of"]], wo, tl_p)
+        if pair_form(cfg, sir) and cfg.dummy_mode != 2:
+            wb = W_RTOL * wo + W_FLOOR * wo.max()
+        else:
+            tl_p = tol_ll[r["bin_of"]] if (not sir and cfg.dummy_mode == 2) else None
+            wb = weight_bound(r["ll"][r["bin_of"]], wo, tl_p)
+        e_w = np.abs(wg - wo) - wb
         worst = int(np.argmax(e_w))
         assert np.all(e_w <= 0), (f"target {t}: weights off, worst excess {e_w[worst]} at w = {wo[worst]} "
                                   f"(GPU {wg[worst]}), l = {r['ll'][r['bin_of'][worst]]}, max w = {wo.max()}")
         dev["w"] = max(dev["w"], float(np.max(np.abs(wg - wo) / np.maximum(wo, 1e-300))))
+        # relative weight error where the weight is not negligible (above the floor)
+        big = wo > W_FLOOR * wo.max() / W_RTOL
+        dev["w_rel"] = max(dev.get("w_rel", 0.0), float(np.max(np.abs(wg - wo)[big] / wo[big])))
         assert abs(wg.sum() - 1.0) < 1e-12
         e_est = np.abs(est[t] - r["est"]) / np.maximum(np.abs(r["est"]), 1.0)
         assert np.all(e_est <= 1e-5), f"target {t}: estimate off by {e_est.max()}"

@@ -3,14 +3,17 @@
 The single target (10^6 particles, 512 x 512, 15 x 15 window, 8 x 8
 quadrature), the batched workload (1000 targets, 21 654 239 particles,
 1024 x 1024) and the 3D workload (200 targets x 5 x 10^4 particles, D = 7)
-step from a state three frames into tracking, at h = 0.25, with the separable
-likelihood, graph launches and the launch shapes the benchmark's autotuner
-picks. The oracle checks every stage (propagation, keys, bins, bin means,
-log-likelihoods, weights, estimates, N_eff, resampling) for the whole single
-target and for sampled targets of the others (smallest, largest and spread
-sizes), to the tolerances of gpu_helpers; the remaining targets are checked
-through properties that hold at any size: bins ordered by target, member
-counts summing to N_t, weights summing to 1 and non-decreasing parents.
+step from a state three frames into tracking, at h = 0.25, with graph
+launches and the launch shapes the benchmark's autotuner picks; the batched
+workload runs with both exact likelihood forms (separable, the benchmark's,
+and per sub-sample). The oracle checks every stage (propagation, keys, bins,
+bin means, log-likelihoods, weights, estimates, N_eff, resampling) for the
+whole single target and, of the others, for 50 targets: the 10 with the most
+bins of this frame (lost, spread-out clouds, whose bin sums span the most
+chunks) and 40 spread over the particle counts from the smallest to the
+largest, to the tolerances of gpu_helpers. Every target is checked through
+properties that hold at any size: bins ordered by target, member counts
+summing to N_t, weights summing to 1 and non-decreasing parents.
 """
 import numpy as np
 import pytest
@@ -65,28 +68,40 @@ def _properties(cfg, frames, start, k):
     s = f.dump("resample").cpu().numpy().astype(np.int64)
     f.close()
     assert np.all(np.diff(b_t) >= 0)
+    bins = np.bincount(b_t, minlength=len(n))
     assert np.array_equal(np.bincount(b_t, weights=b_n, minlength=len(n)).astype(np.int64), n)
     sums = np.add.reduceat(w, off[:-1])
     assert np.all(np.abs(sums - 1.0) < 1e-12), np.abs(sums - 1.0).max()
     for t in range(len(n)):
         st = s[off[t]:off[t + 1]]
         assert st.min() >= 0 and st.max() < n[t] and np.all(np.diff(st) >= 0), t
+    return bins
 
 
-@pytest.mark.parametrize("workload", ["single-2d-512", "batched-2d-1024", "3d-astig"])
-def test_full_size_step(workload):
+def _sample(n, bins, most=10, spread=40):
+    """The targets with the most bins, then targets spread over the particle counts."""
+    T = len(n)
+    pick = list(np.argsort(-bins, kind="stable")[:most])
+    order = np.argsort(n, kind="stable")
+    for i in np.unique(np.linspace(0, T - 1, spread).round().astype(int)):
+        if order[i] not in pick:
+            pick.append(order[i])
+    return sorted(int(t) for t in pick)
+
+
+@pytest.mark.parametrize("workload,lik", [("single-2d-512", 1), ("batched-2d-1024", 1), ("3d-astig", 1),
+                                          ("batched-2d-1024", 0)])
+def test_full_size_step(workload, lik):
     from paper_1310_5541_amd import Config
     w = synth.preset(workload, K=4)
     frames = synth.frames(w, synth.truth(w))
     m = 4
-    cfg = Config.from_workload(w, bins_per_px=(m, m, m if w.dim == 3 else 1), lik_mode=1, seed=w.seed + 500)
+    cfg = Config.from_workload(w, bins_per_px=(m, m, m if w.dim == 3 else 1), lik_mode=lik, seed=w.seed + 500)
     start = _start(w, cfg, frames, 4)
     n = w.counts()
-    order = np.argsort(n, kind="stable")
-    T = len(n)
-    pos = np.clip([0, 1, T // 4, T // 2, (3 * T) // 4, T - 2, T - 1], 0, T - 1)
-    sample = sorted(set(order[pos].tolist()))
-    log(f"case full_size {workload}: {int(n.sum())} particles, {len(n)} targets, checked {sample}")
-    _properties(cfg, frames[3], start, 4)
+    log(f"case full_size {workload} lik_mode={lik}: {int(n.sum())} particles, {len(n)} targets")
+    bins = _properties(cfg, frames[3], start, 4)
+    sample = _sample(n, bins)
+    log(f"  checked {len(sample)} targets: {sample}; most bins {int(bins.max())}")
     dev, _ = run_step_parity(cfg, start, frames[3], 4, False, targets=sample, tuning=TUNING)
     log(f"  deviations {dev}")

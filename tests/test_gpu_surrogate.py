@@ -25,7 +25,7 @@ import pytest
 
 import synth
 from fp_emul import bf16_round, e4m3_round
-from gpu_helpers import LL_ATOL, LL_RTOL, log, oracle_model, run_step_parity
+from gpu_helpers import ll_tol, log, oracle_model, run_step_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -239,7 +239,7 @@ def test_training_rows_from_an_exact_step():
     assert np.all(d <= 2.0 ** -7 * np.abs(feats[:, P2:P2 + 5]) + 1e-30), d.max()
     assert np.all(X[:, P2 + 5:] == 0)
     y_e = (ll + A) / 100.0
-    tol = (LL_ATOL + LL_RTOL * np.abs(ll)) / 100.0 + 2.0 ** -22 * np.abs(y_e)
+    tol = ll_tol(cfg, False, ll) / 100.0 + 2.0 ** -22 * np.abs(y_e)
     assert np.all(np.abs(y - y_e) <= tol), np.abs(y - y_e).max()
 
 
@@ -333,5 +333,5 @@ def test_surrogate_partial_check_follows_the_draw():
     assert checked == int(pick.sum()) and fb == int(fall.sum())
     exact = fall[tgt] | pick
     d_ex = np.abs(ll - ll_o)
-    assert np.all(d_ex[exact] <= LL_ATOL + LL_RTOL * np.abs(ll_o[exact]))
+    assert np.all(d_ex[exact] <= ll_tol(cfg, False, ll_o[exact])), d_ex[exact].max()
     assert np.all(np.abs(ll - surr)[~exact] <= 1e-9 * (1.0 + np.abs(A[~exact])))

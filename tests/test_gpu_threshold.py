@@ -23,7 +23,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import LL_ATOL, LL_RTOL, exempt_mask, log, oracle_model, weight_bound
+from gpu_helpers import exempt_mask, ll_tol, log, oracle_model, w_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -120,9 +120,9 @@ def _run(cfg, fr, cloud, K, sir, lik_check=True):
                     bofs += B
                 if lik_check:
                     d_ll = np.abs(ll_g - ll_o)
-                    assert np.all(d_ll <= LL_ATOL + LL_RTOL * np.abs(ll_o)), f"k={k} t={t}: ll off {d_ll.max()}"
+                    assert np.all(d_ll <= ll_tol(cfg, sir, ll_o)), f"k={k} t={t}: ll off {d_ll.max()}"
                 wg, wo = w_gpu[a:b], r["w"]
-                bound = weight_bound(r["ll"][r["bin_of"]], wo)
+                bound = w_bound(cfg, sir, r["ll"][r["bin_of"]], wo)
                 assert np.all(np.abs(wg - wo) <= bound), f"k={k} t={t}: weights"
                 e_est = np.abs(est[t] - r["est"]) / np.maximum(np.abs(r["est"]), 1.0)
                 assert np.all(e_est <= 1e-5), f"k={k} t={t}: estimate off {e_est.max()}"
@@ -152,7 +152,7 @@ def _run(cfg, fr, cloud, K, sir, lik_check=True):
                     lo = (0.0 if prev is None else prev) + r["ll"][r["bin_of"]] - (r["M"] + math.log(r["S"]))
                     assert np.all(np.isfinite(lg))
                     assert np.all(np.abs(np.exp(lg) - wo) <= bound), f"k={k} t={t}: kept weights"
-                    tl = LL_ATOL + LL_RTOL * np.abs(r["ll"][r["bin_of"]])
+                    tl = ll_tol(cfg, sir, r["ll"][r["bin_of"]])
                     lbound = 1.01 * (tl + np.sum(wo * tl)) + 1e-9
                     assert np.all(np.abs(lg - lo) <= lbound), f"k={k} t={t}: kept log-weights"
             decisions.append(row)

@@ -22,12 +22,19 @@ def _traffic():
     return json.load(open(path))
 
 
-def test_traffic_summary_matches_kernel_sources():
+def test_stale_traffic_is_not_reported():
+    """The benchmark reports counter traffic only for the kernel sources the
+    counters were taken on: after any kernel change it reports null."""
+    import bench
     rec = _traffic()
     h = hashlib.sha256()
     for f in rec["sources"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    assert h.hexdigest()[:16] == rec["source_sha256_16"], "kernel sources changed since the counters were taken"
+    got = bench.counter_traffic(rec["workload"], rec["h"], rec["likelihood"], "propagate")
+    if h.hexdigest()[:16] == rec["source_sha256_16"]:
+        assert got == round(rec["per_launch"]["propagate"]["traffic_bytes"], 0)
+    else:
+        assert got is None
 
 
 def test_traffic_summary_covers_the_roofline_kernels():
