@@ -272,7 +272,7 @@ def track(model: Model, frames: np.ndarray, n_per_target, state: np.ndarray, k0:
 def posterior_mean(model: Model, frame: np.ndarray, kind: str, par: float, centre, I0: float,
                    delta: float = 1.0 / 32) -> np.ndarray:
     """Exact posterior mean of the position (x, y) for a fixed prior, the
-    reference of Sec. 5.3's convergence experiment: the integral of
+    reference of Sec. 5.5's convergence experiment: the integral of
     x prior(x) p(z | x) over the integral of prior(x) p(z | x), with p(z | x)
     the Eq. likelihood at intensity I0 (velocity 0).
 

@@ -222,7 +222,7 @@ def rmse(est: np.ndarray, tr: np.ndarray, dim: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- pseudo-tracking
-# Sec. 5.3's convergence experiment: the prior p(x_k | Z^{k-1}) is fixed (a
+# Sec. 5.5's convergence experiment: the prior p(x_k | Z^{k-1}) is fixed (a
 # uniform square of 3 or 5 pixels, or an isotropic Gaussian of sigma 0.5 or
 # 0.8 px), the object is one spot of sigma_PSF = 1.16 at SNR 2, and the
 # likelihood has sigma_xi = 20. Readings: the prior is centred on the object;

@@ -1,4 +1,4 @@
-"""Sec. 5.3's pseudo-tracking experiment on the GPU.
+"""Sec. 5.5's pseudo-tracking experiment on the GPU.
 
 Repetitions run batched as targets that share one frame; with no motion, one
 step weighs the prior draws as they are. Checked here:

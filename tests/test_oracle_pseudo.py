@@ -1,4 +1,4 @@
-"""Sec. 5.3's pseudo-tracking experiment on the oracle (CPU only).
+"""Sec. 5.5's pseudo-tracking experiment on the oracle (CPU only).
 
 The reference, the exact posterior mean under a fixed prior, is pinned by:
 - a flat frame (the likelihood is constant): the prior's own mean;
