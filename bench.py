@@ -126,30 +126,51 @@ def counter_traffic(workload: str, h: float, likelihood: str, kernel: str):
     return None if k is None else round(k["traffic_bytes"], 0)
 
 
-def cpu_oracle_rate(oracle, mdl, w, frames_np, counts, state, seconds):
-    """The oracle's pcSIR rate on a bounded sample of the workload: whole
-    targets one after another, frame after frame from frame 1 (each target
-    tracked from where its previous step left it), until about `seconds` of
-    one CPU thread are used."""
+def cpu_info():
+    """Host CPU model and the logical CPUs the OS reports."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def cpu_subset(T, stride):
+    """Targets of the CPU sample: every `stride`-th target (all when T <= stride)."""
+    return np.arange(0, T, stride if T > stride else 1)
+
+
+def cpu_oracle_rate(oracle, mdl, w, frames_np, counts, state, seconds, threads=1, stride=10):
+    """The oracle's pcSIR rate on a bounded sample of the workload: every
+    `stride`-th target (counts drawn independently of the index, so the
+    subset spans the particle counts), tracked frame after frame from frame 1
+    with all subset targets per frame, until about `seconds` are used (at
+    least one frame; at most every frame). `threads` OpenMP threads run the
+    subset's targets in parallel; the per-target arithmetic is the same."""
     T = len(counts)
+    sub = cpu_subset(T, stride)
     off = np.concatenate([[0], np.cumsum(counts)])
-    st = np.array(state, dtype=np.float32, copy=True)
+    st = np.ascontiguousarray(np.concatenate([state[:, off[t]:off[t + 1]] for t in sub], axis=1), dtype=np.float32)
+    n_sub = np.ascontiguousarray(np.asarray(counts)[sub], dtype=np.int64)
+    used = oracle.set_threads(threads)
     t1 = time.perf_counter()
-    k, nt, units, ps = 1, 0, 0, 0
-    while k <= frames_np.shape[0] and (units == 0 or time.perf_counter() - t1 < seconds):
-        a, b = off[nt], off[nt + 1]
-        fr_t = frames_np[k - 1:k, nt:nt + 1] if w.per_target_frames else frames_np[k - 1:k]
-        s_new, _, _ = oracle.track(mdl, fr_t, counts[nt:nt + 1], st[:, a:b], k0=k, per_target=w.per_target_frames)
-        st[:, a:b] = s_new
-        ps += int(b - a)
-        units += 1
-        nt += 1
-        if nt == T:
-            nt, k = 0, k + 1
+    k, ps = 1, 0
+    try:
+        while k <= frames_np.shape[0] and (k == 1 or time.perf_counter() - t1 < seconds):
+            fr_t = frames_np[k - 1:k][:, sub] if w.per_target_frames else frames_np[k - 1:k]
+            st, _, _ = oracle.track(mdl, fr_t, n_sub, st, k0=k, per_target=w.per_target_frames)
+            ps += int(n_sub.sum())
+            k += 1
+    finally:
+        oracle.set_threads(os.cpu_count() or 1)
     el = time.perf_counter() - t1
-    last = k if nt else k - 1
-    return {"value": ps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{units} target-steps over frames 1..{last} ({ps} particle-steps, {el:.1f} s), FP64, one thread"}
+    return {"value": ps / el, "unit": "particle-steps/s", "cores": used, "kind": "oracle",
+            "sample": f"{len(sub)} of {T} targets (every {stride if T > stride else 1}th), frames 1..{k - 1} "
+                      f"({ps} particle-steps, {el:.1f} s), FP64, {used} thread{'s' if used > 1 else ''}"}
 
 
 def large_object(args, dev):
@@ -541,8 +562,14 @@ def main():
                            sigma_psf=w.sigma_psf, astig_gamma=w.astig_gamma, astig_d=w.astig_d, i_bg=w.i_bg,
                            sigma_xi=w.sigma_xi, proc_sigma=w.proc_sigma, seed=w.seed + 500)
         st = synth.initial_particles(w, tr[0], counts)
-        cpu = cpu_oracle_rate(oracle, mdl, w, frames_np, counts, st, args.cpu_seconds)
+        # all host cores the process may use (OMP_NUM_THREADS when set), then one core
+        cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        cpu = cpu_oracle_rate(oracle, mdl, w, frames_np, counts, st, args.cpu_seconds, threads=cores)
         cpu["sample"] = f"exact pcSIR h={h_match}, " + cpu["sample"]
+        one = cpu_oracle_rate(oracle, mdl, w, frames_np, counts, st, args.cpu_seconds, threads=1)
+        one["sample"] = f"exact pcSIR h={h_match}, " + one["sample"]
+        cpu["single_thread"] = one
+        cpu.update(cpu_info())
 
     out = {
         "metric": METRIC,

@@ -25,8 +25,9 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 
 def build() -> str:
-    """Compile the oracle with g++ (plain -O2, IEEE semantics, no fast-math)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
+    """Compile the oracle with g++ (plain -O2, IEEE semantics, no fast-math;
+    OpenMP only for the loop over independent targets in orc_track)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
            "-o", _LIB_PATH + ".tmp", _SRC]
     subprocess.run(cmd, check=True)
     os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
@@ -123,8 +124,16 @@ def lib():
         L.orc_track.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
                                 C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
                                 C.c_void_p]
+        L.orc_set_threads.argtypes = [C.c_int32]
+        L.orc_set_threads.restype = C.c_int32
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of :func:`track` (targets in parallel; 1 = one core). Returns the
+    count in effect; n <= 0 only queries it."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def _p(a: np.ndarray):

@@ -26,6 +26,9 @@
 #include <map>
 #include <tuple>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -516,28 +519,42 @@ void orc_step_thr(const orc_model *mdl, const float *frame, int32_t H, int32_t W
  * counts n[t], stored one after another in a SoA array [D][sum n]; frames
  * k = k0 .. k0+K-1 read frame index k - k0 from frames (shared by all
  * targets, [K][H][W]) or, with per_target != 0, from [K][T][H][W]. Writes the
- * per-frame estimates [K][T][D] and N_eff [K][T]. */
+ * per-frame estimates [K][T][D] and N_eff [K][T]. Targets are independent
+ * (every step of both algorithms is per target), so within a frame they run
+ * on the OpenMP threads that orc_set_threads chose, each on its own copy of
+ * its particles; the results do not depend on the thread count. */
 void orc_track(const orc_model *mdl, const float *frames, int32_t H, int32_t W, int32_t per_target,
                int64_t T, const int64_t *n, float *state, int64_t k0, int64_t K, int32_t sir, double *est,
                double *neff) {
   const int D = 2 * mdl->dim + 1;
-  int64_t total = 0;
-  for (int64_t t = 0; t < T; ++t) total += n[t];
-  std::vector<float> tmp;
+  std::vector<int64_t> off((size_t)T + 1, 0);
+  for (int64_t t = 0; t < T; ++t) off[(size_t)t + 1] = off[(size_t)t] + n[t];
+  const int64_t total = off[(size_t)T];
   for (int64_t kk = 0; kk < K; ++kk) {
-    int64_t off = 0;
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < T; ++t) {
-      const int64_t Nt = n[t];
-      tmp.assign((size_t)D * Nt, 0.0f);
+      const int64_t Nt = n[t], o = off[(size_t)t];
+      std::vector<float> tmp((size_t)D * Nt);
       for (int d = 0; d < D; ++d)
-        for (int64_t i = 0; i < Nt; ++i) tmp[(size_t)d * Nt + i] = state[(int64_t)d * total + off + i];
+        for (int64_t i = 0; i < Nt; ++i) tmp[(size_t)d * Nt + i] = state[(int64_t)d * total + o + i];
       const float *fr = per_target ? frames + ((kk * T + t) * (int64_t)H * W) : frames + kk * (int64_t)H * W;
       orc_step(mdl, fr, H, W, Nt, tmp.data(), k0 + kk, t, sir, est + (kk * T + t) * D, neff + kk * T + t);
       for (int d = 0; d < D; ++d)
-        for (int64_t i = 0; i < Nt; ++i) state[(int64_t)d * total + off + i] = tmp[(size_t)d * Nt + i];
-      off += Nt;
+        for (int64_t i = 0; i < Nt; ++i) state[(int64_t)d * total + o + i] = tmp[(size_t)d * Nt + i];
     }
   }
+}
+
+/* Threads of orc_track (1 = the paper's single-core setting); returns the
+ * count now in effect. n <= 0 leaves it unchanged. */
+int32_t orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return (int32_t)omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 }  /* extern "C" */
