@@ -152,6 +152,38 @@ def test_fused_fp8_matches_emulation_and_calibration():
     assert rel < 0.1
 
 
+@pytest.mark.parametrize("seed", [11, 61])
+def test_inference_error_against_the_fp64_oracle(seed):
+    """Error of the fused kernel against the FP64 network (oracle/mlp.py) on the
+    same rows and FP32 parameters, stated per result. Each row's error is
+    measured against its output scale s = sum_n |w4_n h3_n|: BF16 (unit
+    roundoff 2^-9) must stay within 2^-7 s, FP8 E4M3 (unit roundoff 2^-4)
+    within 2^-4 s; the relative RMS over rows within 0.5% (BF16) and 8% (FP8).
+    The numpy emulation of the same arithmetic reaches 2^-9 s and 0.25% (BF16),
+    0.026 s and 3.9% (FP8) on these rows."""
+    import torch
+
+    from oracle import mlp
+    from paper_1310_5541_amd import SurrogateNet
+    th = _params(seed)
+    X = _rows(64 * 40 + 17, seed + 1)
+    f64, _ = mlp.forward(th.astype(np.float64), X.astype(np.float64))
+    _, scale, am = _emulate(th, X)
+    pt = torch.from_numpy(th).cuda()
+    Xt = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    scales = [a / 448.0 for a in am]
+    rms64 = np.sqrt(np.mean(f64 ** 2))
+    for name, net, fp8, tol, rel in (("bf16", SurrogateNet(pt), False, 2.0 ** -7, 0.005),
+                                     ("fp8", SurrogateNet(pt, act_scale=scales), True, 2.0 ** -4, 0.08)):
+        f = net.rows(Xt, fp8=fp8).cpu().numpy().astype(np.float64)
+        e = np.abs(f - f64)
+        r = np.sqrt(np.mean(e ** 2)) / rms64
+        log(f"case inference_vs_fp64 seed={seed} {name}: max |f - f64| / s {np.max(e / scale):.3e}, "
+            f"relative RMS {r:.3e}, max |f - f64| {e.max():.3e}")
+        assert np.all(e <= tol * scale), np.max(e / scale)
+        assert r <= rel
+
+
 # ------------------------------------------------------------------ in the step
 def _scene(counts, seed=9, H=96, m=4, patch=11):
     w = synth.preset("tiny", H=H, W=H, T=len(counts), n=counts, m=(m, m, 1), K=2, i0=(20.0, 100.0),
@@ -169,17 +201,28 @@ def _scene(counts, seed=9, H=96, m=4, patch=11):
     return w, tr, fr, np.ascontiguousarray(np.concatenate(parts, axis=1))
 
 
+def _scene3d(counts, seed=9, H=48, m=2, patch=15):
+    """3D astigmatic targets, each at the centre of its own H x H region (per-target frames)."""
+    w = synth.preset("3d-astig", H=H, W=H, T=len(counts), n=counts, m=(m, m, m), K=2, patch=patch)
+    tr = synth.truth(w, seed=seed)
+    fr = synth.frames(w, tr, seed=seed)
+    parts = [synth.random_cloud(w, tr[1, t], int(n), 0.6, 11 + t) for t, n in enumerate(counts)]
+    return w, tr, fr, np.ascontiguousarray(np.concatenate(parts, axis=1))
+
+
 def _oracle_rows(cfg, frame, prop, off):
-    """Expected features (float32, before BF16 rounding), A(z) and the oracle's l per dummy, all targets."""
+    """Expected features (float32, before BF16 rounding), A(z) and the oracle's l per dummy,
+    all targets. frame: [H, W], or [T, H, W] with per-target frames."""
     import oracle
     mdl = oracle_model(cfg)
-    P, R = cfg.patch, cfg.patch // 2
+    P, R, dim = cfg.patch, cfg.patch // 2, cfg.dim
     Hh, Ww = cfg.frame_h, cfg.frame_w
     ibg = np.float32(cfg.i_bg)
     feats, A, ll, tgt = [], [], [], []
     for t in range(cfg.T):
         a, b = off[t], off[t + 1]
-        r = oracle.weigh(mdl, frame, prop[:, a:b], sir=False)
+        fr_t = frame[t] if cfg.per_target_frames else frame
+        r = oracle.weigh(mdl, fr_t, prop[:, a:b], sir=False)
         for j in range(r["B"]):
             cx, cy = int(r["bin_key"][0, j]), int(r["bin_key"][1, j])
             c0, r0 = cx // cfg.bins_per_px[0], cy // cfg.bins_per_px[1]
@@ -189,20 +232,27 @@ def _oracle_rows(cfg, frame, prop, off):
                 for dx in range(P):
                     c, rr = c0 + dx - R, r0 + dy - R
                     if 0 <= c < Ww and 0 <= rr < Hh:
-                        zb = np.float32(np.float32(frame[rr, c]) - ibg)
+                        zb = np.float32(np.float32(fr_t[rr, c]) - ibg)
                         row[dy * P + dx] = zb * np.float32(0.01)
-                        s += (float(frame[rr, c]) - float(cfg.i_bg)) ** 2
+                        s += (float(fr_t[rr, c]) - float(cfg.i_bg)) ** 2
             mean = r["bin_mean"][:, j]
             row[P * P] = mean[0] - c0
             row[P * P + 1] = mean[1] - r0
-            row[P * P + 2] = np.float32(mean[2]) * np.float32(0.1)
-            row[P * P + 3] = np.float32(mean[3]) * np.float32(0.1)
-            row[P * P + 4] = np.float32(mean[4]) * np.float32(0.01)
+            if dim == 3:
+                row[P * P + 2] = np.float32(mean[2]) * np.float32(0.1)   # depth in full, / 10
+            for d in range(dim):                                         # velocities / 10
+                row[P * P + dim + d] = np.float32(mean[dim + d]) * np.float32(0.1)
+            row[P * P + 2 * dim] = np.float32(mean[2 * dim]) * np.float32(0.01)
             feats.append(row)
             A.append(s / (2.0 * cfg.sigma_xi ** 2))
             ll.append(r["ll"][j])
             tgt.append(t)
     return np.array(feats), np.array(A), np.array(ll), np.array(tgt)
+
+
+def _scene_for(dim, counts, seed, m=4, patch=15):
+    return _scene(counts, seed=seed, m=m, patch=patch) if dim == 2 else _scene3d(counts, seed=seed, m=m // 2 or 1,
+                                                                                   patch=patch)
 
 
 def _cfg(w, **kw):
@@ -243,19 +293,19 @@ def test_training_rows_from_an_exact_step():
     assert np.all(np.abs(y - y_e) <= tol), np.abs(y - y_e).max()
 
 
-@pytest.mark.parametrize("mode", [2, 3])
-def test_surrogate_step_without_check_is_the_fused_network(mode):
+@pytest.mark.parametrize("dim,mode", [(2, 2), (2, 3), (3, 2), (3, 3)])
+def test_surrogate_step_without_check_is_the_fused_network(dim, mode):
     import torch
 
     from paper_1310_5541_amd import Filter, SurrogateNet
     counts = (300, 2049, 4097)
-    w, tr, fr, cloud = _scene(counts, seed=4, patch=15)
+    w, tr, fr, cloud = _scene_for(dim, counts, seed=4)
     cfg = _cfg(w, seed=6, lik_mode=mode)
     off = np.concatenate([[0], np.cumsum(counts)])
-    th = _params(31)
+    th = _params(31, n_in=225 + 2 * dim + 1)
     pt = torch.from_numpy(th).cuda()
     scales = [0.02, 0.01, 0.01] if mode == 3 else None
-    log(f"case surrogate_step_without_check mode={mode}")
+    log(f"case surrogate_step_without_check dim={dim} mode={mode}")
     f = Filter(cfg, torch.from_numpy(cloud).cuda())
     f.set_debug(True)
     f.set_surrogate(pt, scales, check_fraction=0.0, tol_nats=float("inf"))
@@ -267,49 +317,60 @@ def test_surrogate_step_without_check_is_the_fused_network(mode):
     checked, fb, _ = f.surrogate_stats()
     f.close()
     assert checked == 0 and fb == 0 and B == ll.shape[0]
+    feats, A, _, _ = _oracle_rows(cfg, fr[1], prop, off)
+    # the step's features are the oracle's bins' (window bit-exact, state within one BF16 step)
+    Xn = X.float().cpu().numpy()
+    P2 = cfg.patch ** 2
+    np.testing.assert_array_equal(Xn[:, :P2], bf16_round(feats[:, :P2]))
+    nst = 3 * dim
+    d = np.abs(Xn[:, P2:P2 + nst] - bf16_round(feats[:, P2:P2 + nst]))
+    assert np.all(d <= 2.0 ** -7 * np.abs(feats[:, P2:P2 + nst]) + 1e-30), d.max()
     net = SurrogateNet(pt, act_scale=scales)
     fo = net.rows(X.contiguous(), fp8=(mode == 3)).cpu().numpy().astype(np.float64)
-    _, A, _, _ = _oracle_rows(cfg, fr[1], prop, off)
     exp = 100.0 * fo - A
     assert np.all(np.abs(ll - exp) <= 1e-9 * (1.0 + np.abs(A))), np.abs(ll - exp).max()
 
 
-def test_surrogate_full_check_falls_back_to_exact_parity():
+@pytest.mark.parametrize("dim,mode", [(2, 2), (2, 3), (3, 2), (3, 3)])
+def test_surrogate_full_check_falls_back_to_exact_parity(dim, mode):
     import torch
     counts = (1, 255, 256, 2049, 5000)
-    w, tr, fr, cloud = _scene(counts, seed=7)
-    cfg = _cfg(w, seed=8, lik_mode=2)
-    pt = torch.from_numpy(_params(41)).cuda()
+    w, tr, fr, cloud = _scene_for(dim, counts, seed=7)
+    cfg = _cfg(w, seed=8, lik_mode=mode)
+    pt = torch.from_numpy(_params(41, n_in=225 + 2 * dim + 1)).cuda()
+    scales = [0.02, 0.01, 0.01] if mode == 3 else None
     st = {}
 
     def grab(f):
         st["stats"] = f.surrogate_stats()
         st["B"] = f.dump("counts").cpu().numpy()[0]
 
-    log("case surrogate_full_check_falls_back")
-    dev, _ = run_step_parity(cfg, cloud, fr[1], 3, False, surrogate=(pt, None, 1.0, 0.0), on_filter=grab)
+    log(f"case surrogate_full_check_falls_back dim={dim} mode={mode}")
+    dev, _ = run_step_parity(cfg, cloud, fr[1], 3, False, surrogate=(pt, scales, 1.0, 0.0), on_filter=grab)
     checked, fb, mx = st["stats"]
     log(f"  deviations {dev}; stats {st['stats']}")
     assert checked == int(st["B"]) and fb == len(counts) and mx > 0
 
 
-def test_surrogate_partial_check_follows_the_draw():
+@pytest.mark.parametrize("dim,mode", [(2, 2), (2, 3), (3, 2), (3, 3)])
+def test_surrogate_partial_check_follows_the_draw(dim, mode):
     import torch
 
     import oracle
     from paper_1310_5541_amd import Filter, SurrogateNet
     counts = (1, 3, 40, 255, 2047, 5000)
-    w, tr, fr, cloud = _scene(counts, seed=3, m=2)
+    w, tr, fr, cloud = _scene_for(dim, counts, seed=3, m=2)
     frac = 0.02
-    cfg = _cfg(w, seed=9, lik_mode=2)
+    cfg = _cfg(w, seed=9, lik_mode=mode)
     off = np.concatenate([[0], np.cumsum(counts)])
-    th = _params(51)
+    th = _params(51, n_in=225 + 2 * dim + 1)
     pt = torch.from_numpy(th).cuda()
+    scales = [0.02, 0.01, 0.01] if mode == 3 else None
     k = 3
-    log("case surrogate_partial_check")
+    log(f"case surrogate_partial_check dim={dim} mode={mode}")
     f = Filter(cfg, torch.from_numpy(cloud).cuda())
     f.set_debug(True)
-    f.set_surrogate(pt, None, check_fraction=frac, tol_nats=0.0)
+    f.set_surrogate(pt, scales, check_fraction=frac, tol_nats=0.0)
     frame = torch.from_numpy(fr[1]).cuda()
     f.step(frame, k)
     ll = f.dump("loglik").cpu().numpy()
@@ -318,7 +379,7 @@ def test_surrogate_partial_check_follows_the_draw():
     checked, fb, _ = f.surrogate_stats()
     f.close()
     feats, A, ll_o, tgt = _oracle_rows(cfg, fr[1], prop, off)
-    fo = SurrogateNet(pt).rows(X.contiguous()).cpu().numpy().astype(np.float64)
+    fo = SurrogateNet(pt, act_scale=scales).rows(X.contiguous(), fp8=(mode == 3)).cpu().numpy().astype(np.float64)
     surr = 100.0 * fo - A
     # the draw: uniform of counter (dummy, k, target, 3) below the fraction
     pick = np.array([oracle.check_u(cfg.seed, e, k, int(tgt[e])) < float(np.float32(frac)) for e in range(B)])
