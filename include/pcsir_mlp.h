@@ -52,6 +52,26 @@ pcsir_status pcsir_mlp_train_step(float *params_dev, float *adam_m_dev, float *a
                                   const float *y_dev, int32_t batch, float lr, int32_t t, void *workspace_dev,
                                   size_t workspace_bytes, void *hip_stream, float *loss_dev, float *grad_dev);
 
+/* Largest batch of pcsir_mlp_train_step_static. */
+#define PCSIR_MLP_STATIC_MAX_BATCH 1024
+
+/* pcsir_mlp_train_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight training loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the workspace taken from a
+ * device array inside the library, sized for PCSIR_MLP_STATIC_MAX_BATCH rows
+ * (6.4 MiB, held on every GPU the library runs on until the process ends).
+ * No hipMalloc, hipFree or other allocation happens in the call. Returns
+ * PCSIR_E_NOMEM when batch exceeds PCSIR_MLP_STATIC_MAX_BATCH, PCSIR_E_INVAL
+ * for the argument errors of pcsir_mlp_train_step or when hip_stream does not
+ * belong to the current device. On its first call on a device the library
+ * looks up the array's address there (no allocation); calls on one GPU share
+ * the array, so calls that overlap on one GPU (concurrent streams or host
+ * threads) race and must be serialised by the caller. Every byte the step
+ * reads from the array is written earlier in the same call. */
+pcsir_status pcsir_mlp_train_step_static(float *params_dev, float *adam_m_dev, float *adam_v_dev,
+                                         const uint16_t *X_dev, const float *y_dev, int32_t batch, float lr,
+                                         int32_t t, void *hip_stream, float *loss_dev, float *grad_dev);
+
 /* Network outputs f [n] for BF16 feature rows X [n][256] through the training
  * path (the same GEMMs as pcsir_mlp_train_step). n a multiple of 64. */
 pcsir_status pcsir_mlp_forward_train_path(const float *params_dev, const uint16_t *X_dev, int32_t n, float *f_dev,

@@ -93,6 +93,7 @@ def lib():
     L.pcsir_mlp_train_bytes.argtypes = [i32]
     L.pcsir_mlp_train_bytes.restype = sz
     L.pcsir_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, i32, vp, sz, vp, vp, vp]
+    L.pcsir_mlp_train_step_static.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, i32, vp, vp, vp]
     L.pcsir_mlp_forward_train_path.argtypes = [vp, vp, i32, vp, vp, sz, vp]
     L.pcsir_mlp_gemm_bf16.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp]
     L.pcsir_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
@@ -106,7 +107,7 @@ def lib():
     L.pcsir_set_surrogate.argtypes = [vp, vp, vp, C.c_float, C.c_float]
     L.pcsir_surrogate_features.argtypes = [vp, vp, vp, i32, C.POINTER(i32)]
     L.pcsir_surrogate_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_float), i32]
-    for f in ("pcsir_mlp_train_step", "pcsir_mlp_forward_train_path", "pcsir_mlp_gemm_bf16", "pcsir_surr_prepare",
+    for f in ("pcsir_mlp_train_step", "pcsir_mlp_train_step_static", "pcsir_mlp_forward_train_path", "pcsir_mlp_gemm_bf16", "pcsir_surr_prepare",
               "pcsir_surr_rows", "pcsir_set_surrogate", "pcsir_surrogate_features", "pcsir_surrogate_stats",
               "pcsir_get_tuning", "pcsir_set_tuning", "pcsir_autotune"):
         getattr(L, f).restype = i32
@@ -437,6 +438,16 @@ class MLPTrainer:
         """One Adam step on a batch; returns the loss tensor (device, before the step)."""
         self._run(X, y, lr, True)
         return self.loss
+
+    def step_static(self, X, y, lr: float):
+        """One Adam step through pcsir_mlp_train_step_static (no workspace; batch
+        rows up to PCSIR_MLP_STATIC_MAX_BATCH, any multiple of 64); returns the status."""
+        assert X.dtype == self._torch.bfloat16 and X.dim() == 2 and X.shape[1] == 256 and X.is_contiguous()
+        assert y.dtype == self._torch.float32 and y.shape == (X.shape[0],)
+        self.t += 1
+        return lib().pcsir_mlp_train_step_static(_ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(X), _ptr(y),
+                                                 int(X.shape[0]), float(lr), self.t, _stream(X.device),
+                                                 _ptr(self.loss), _ptr(self.grad))
 
     def gradients(self, X, y):
         """Gradient of the batch loss without updating the parameters."""

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/pcsir_mlp.h"
@@ -150,10 +151,10 @@ struct TrainLayout {
   size_t wb[3], Z[3], Hh[3], dZ[3], f, df, loss_part, total;
 };
 
-TrainLayout train_layout(int B) {
-  TrainLayout L;
+constexpr TrainLayout train_layout(int B) {
+  TrainLayout L{};
   size_t o = 0;
-  auto take = [&](size_t bytes) {
+  auto take = [&o](size_t bytes) {
     const size_t at = o;
     o += (bytes + 255) / 256 * 256;
     return at;
@@ -169,6 +170,40 @@ TrainLayout train_layout(int B) {
   return L;
 }
 
+}  // namespace
+
+// Workspace of the no-allocation training step: a file-scope device array
+// sized for the largest batch it accepts (6.4 MiB). Each GPU holds its own
+// copy from module load until the process ends. Host code never passes the
+// array's name to a kernel: it is a host-side stand-in there, and the device
+// address comes from hipGetSymbolAddress, taken once per device.
+constexpr size_t MLP_STATIC_BYTES = train_layout(PCSIR_MLP_STATIC_MAX_BATCH).total;
+static __device__ __align__(256) unsigned char scratch[MLP_STATIC_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the device that owns `stream` (which must be
+// the current device), looked up on the first call for that device.
+pcsir_status scratch_address(void *stream, void **out) {
+  int cur = -1, dev = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return PCSIR_E_HIP;
+  if (hipStreamGetDevice((hipStream_t)stream, &dev) != hipSuccess) return PCSIR_E_HIP;
+  if (dev != cur || cur < 0 || cur >= MAX_DEVICES) return PCSIR_E_INVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[cur]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return PCSIR_E_HIP;
+    g_scratch_dev[cur] = p;
+  }
+  *out = g_scratch_dev[cur];
+  return PCSIR_OK;
+}
+
 template <int EPI>
 void gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int lda, int a_t, const uint16_t *B, int ldb, int b_t,
           const float *bias, const float *Zin, float *Zout, uint16_t *Hout, float *Cout, int ldc) {
@@ -176,25 +211,11 @@ void gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int lda, int a
   k_gemm<EPI><<<grid, 256, 0, st>>>(M, N, K, A, lda, a_t, B, ldb, b_t, bias, Zin, Zout, Hout, Cout, ldc);
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t pcsir_mlp_param_count(void) { return (size_t)MLP_N_PARAMS; }
-
-size_t pcsir_mlp_train_bytes(int32_t batch) {
-  if (batch < 64 || batch % 64) return 0;
-  return train_layout(batch).total;
-}
-
-pcsir_status pcsir_mlp_train_step(float *params, float *adam_m, float *adam_v, const uint16_t *X, const float *y,
-                                  int32_t batch, float lr, int32_t t, void *ws, size_t ws_bytes, void *stream,
-                                  float *loss_dev, float *grad_dev) {
-  if (!params || !X || !y || !ws || batch < 64 || batch % 64) return PCSIR_E_INVAL;
-  if (!grad_dev && (!adam_m || !adam_v || t < 1)) return PCSIR_E_INVAL;
+// The training step of pcsir_mlp_train_step in a workspace at `ws` (device
+// memory of at least train_layout(batch).total bytes); arguments validated.
+pcsir_status train_step(float *params, float *adam_m, float *adam_v, const uint16_t *X, const float *y, int32_t batch,
+                        float lr, int32_t t, void *ws, void *stream, float *loss_dev, float *grad_dev) {
   const TrainLayout L = train_layout(batch);
-  if (ws_bytes < L.total) return PCSIR_E_NOMEM;
-  if (!grad_dev) return PCSIR_E_INVAL;  // the caller provides the gradient buffer (used for Adam too)
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   auto at16 = [&](size_t o) { return (uint16_t *)(w + o); };
@@ -235,6 +256,38 @@ pcsir_status pcsir_mlp_train_step(float *params, float *adam_m, float *adam_v, c
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? PCSIR_OK : PCSIR_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pcsir_mlp_param_count(void) { return (size_t)MLP_N_PARAMS; }
+
+size_t pcsir_mlp_train_bytes(int32_t batch) {
+  if (batch < 64 || batch % 64) return 0;
+  return train_layout(batch).total;
+}
+
+pcsir_status pcsir_mlp_train_step(float *params, float *adam_m, float *adam_v, const uint16_t *X, const float *y,
+                                  int32_t batch, float lr, int32_t t, void *ws, size_t ws_bytes, void *stream,
+                                  float *loss_dev, float *grad_dev) {
+  if (!params || !X || !y || !ws || batch < 64 || batch % 64) return PCSIR_E_INVAL;
+  // the caller provides the gradient buffer (used for Adam too)
+  if (!grad_dev) return PCSIR_E_INVAL;
+  if (ws_bytes < train_layout(batch).total) return PCSIR_E_NOMEM;
+  return train_step(params, adam_m, adam_v, X, y, batch, lr, t, ws, stream, loss_dev, grad_dev);
+}
+
+pcsir_status pcsir_mlp_train_step_static(float *params, float *adam_m, float *adam_v, const uint16_t *X,
+                                         const float *y, int32_t batch, float lr, int32_t t, void *stream,
+                                         float *loss_dev, float *grad_dev) {
+  if (!params || !X || !y || !grad_dev || batch < 64 || batch % 64) return PCSIR_E_INVAL;
+  if (batch > PCSIR_MLP_STATIC_MAX_BATCH) return PCSIR_E_NOMEM;
+  void *ws = nullptr;
+  const pcsir_status s = scratch_address(stream, &ws);
+  if (s != PCSIR_OK) return s;
+  return train_step(params, adam_m, adam_v, X, y, batch, lr, t, ws, stream, loss_dev, grad_dev);
 }
 
 pcsir_status pcsir_mlp_forward_train_path(const float *params, const uint16_t *X, int32_t n, float *f_out, void *ws,
