@@ -364,13 +364,13 @@ void launch_surrogate(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   const StepDesc *desc = c->at<StepDesc>(L.desc);
   double *ll = c->at<double>(L.ll);
   const bool fp8 = c->cfg.lik_mode == PCSIR_LIK_SURR_FP8;
-  const uint32_t grid = grid_stride_blocks(c, c->p.NT, fp8 ? SurrRows<true>::N : SurrRows<false>::N);
+  const uint32_t grid = grid_stride_blocks(c, c->p.NT, SURR_ROWS);
   unsigned long long *tmax = c->at<unsigned long long>(L.tmax);
   k_clear_u64<<<(c->p.T + TPB - 1) / TPB, TPB, 0, st>>>(tmax, (uint32_t)c->p.T);
   if (c->cfg.lik_mode == PCSIR_LIK_SURR_FP8)
-    k_surr_infer<DIM, true><<<grid, 256, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
+    k_surr_infer<DIM, true><<<grid, SURR_TPB, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
   else
-    k_surr_infer<DIM, false><<<grid, 256, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
+    k_surr_infer<DIM, false><<<grid, SURR_TPB, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
   // exact check of the picked dummies, then exact recomputation of the targets
   // that failed it; the lists reuse the sort buffers, free at this point
   uint32_t *list_chk = c->at<uint32_t>(L.kA), *list_fb = c->at<uint32_t>(L.kB);
@@ -1135,12 +1135,11 @@ pcsir_status pcsir_surr_rows(const void *surr_dev, const uint16_t *X_dev, int32_
   if (n == 0) return PCSIR_OK;
   const hipStream_t st = (hipStream_t)hip_stream;
   const SurrWeights sw = surr_view((void *)surr_dev);
-  const int rows = fp8 ? SurrRows<true>::N : SurrRows<false>::N;
-  const int grid = std::min((n + rows - 1) / rows, 8192);
+  const int grid = std::min((n + SURR_ROWS - 1) / SURR_ROWS, 8192);
   if (fp8)
-    k_surr_rows<true><<<grid, 256, 0, st>>>(n, X_dev, sw, f_dev, (unsigned int *)absmax_dev);
+    k_surr_rows<true><<<grid, SURR_TPB, 0, st>>>(n, X_dev, sw, f_dev, (unsigned int *)absmax_dev);
   else
-    k_surr_rows<false><<<grid, 256, 0, st>>>(n, X_dev, sw, f_dev, (unsigned int *)absmax_dev);
+    k_surr_rows<false><<<grid, SURR_TPB, 0, st>>>(n, X_dev, sw, f_dev, (unsigned int *)absmax_dev);
   return hipGetLastError() == hipSuccess ? PCSIR_OK : PCSIR_E_HIP;
 }
 

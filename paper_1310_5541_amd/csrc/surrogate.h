@@ -1,10 +1,17 @@
 // Fused surrogate inference for the dummies of a pcSIR step (and for feature
-// rows, for tests and calibration): features -> three MFMA layers with exact
-// GELU -> output unit -> l = 100 f - A(z). BF16 or FP8 (E4M3, per-tensor
-// scales) operands, FP32 accumulation. One block of four waves per 64 rows;
-// each wave owns 64 of the 256 output units of a layer, so every weight read
-// from L2 serves all the block's rows. (128 rows per block halve the weight
-// traffic but need 288 registers per lane: one wave per SIMD, slower.)
+// rows, for tests and calibration): features -> three MFMA layers with GELU
+// -> output unit -> l = 100 f - A(z). BF16 or FP8 (E4M3, per-tensor scales)
+// operands, FP32 accumulation.
+//
+// One block of eight waves takes SURR_ROWS = 128 rows at a time; wave w owns
+// units [32 w, 32 w + 32) of every layer, so each weight read from L2 serves
+// all 128 rows, and two blocks per compute unit (four waves per SIMD) let one
+// wave's matrix products run while another evaluates its GELUs. The product is formed transposed, C^T = W^T X^T: the MFMA's
+// first operand is the weights (k contiguous in the inference layout), the
+// second the activations in LDS, and each lane's accumulators then hold four
+// consecutive units of one row, which the epilogue (bias, GELU, rounding)
+// stores as one 8-byte (BF16) or 4-byte (FP8) LDS write. The last layer's
+// epilogue forms the output unit directly from registers.
 #pragma once
 #include "device_util.h"
 #include "kernels.h"
@@ -12,15 +19,38 @@
 
 namespace pcsir {
 
-constexpr int SURR_ROWS = 64;       // rows per block, FP8
-constexpr int SURR_ROWS_BF16 = 64;  // rows per block, BF16
+constexpr int SURR_NW = 8;                // waves per block
+constexpr int SURR_WU = MLP_H / SURR_NW;  // units per wave (a multiple of 32)
+constexpr int SURR_NJ = SURR_WU / 32;     // 32-unit MFMA tiles per wave
+constexpr int SURR_TPB = 64 * SURR_NW;
+constexpr int SURR_ROWS = 128;            // rows per block
+constexpr int SURR_RT = SURR_ROWS / 32;   // 32-row MFMA tiles
+constexpr int SURR_LD = MLP_F + 8;        // LDS row stride (bf16 elements)
+constexpr int SURR_LD8 = MLP_F + 16;      // LDS row stride (fp8 bytes)
+constexpr float FP8_MAX = 448.0f;         // largest finite E4M3 value
+
+// LDS bytes of the activations of SURR_ROWS rows
 template <bool FP8>
-struct SurrRows {
-  static constexpr int N = FP8 ? SURR_ROWS : SURR_ROWS_BF16;
+struct SurrAct {
+  static constexpr int BYTES = FP8 ? SURR_ROWS * SURR_LD8 : SURR_ROWS * SURR_LD * 2;
 };
-constexpr int SURR_LD = MLP_F + 8;      // LDS row stride (bf16 elements)
-constexpr int SURR_LD8 = MLP_F + 16;    // LDS row stride (fp8 bytes)
-constexpr float FP8_MAX = 448.0f;       // largest finite E4M3 value
+
+// Loads through global-address-space pointers (see as_global).
+typedef uint32_t u32v4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32v2 __attribute__((ext_vector_type(2)));
+typedef float f32v4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 gload_u4(const void *ptr) {
+  const u32v4 v = *(const __attribute__((address_space(1))) u32v4 *)ptr;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint2 gload_u2(const void *ptr) {
+  const u32v2 v = *(const __attribute__((address_space(1))) u32v2 *)ptr;
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ float4 gload_f4(const float *ptr) {
+  const f32v4 v = *(const __attribute__((address_space(1))) f32v4 *)ptr;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
 
 // Weights in inference layout, prepared on the device from the FP32 master
 // vector: WT[l][n][k] (k contiguous, so a lane's 8 k values are one load).
@@ -106,158 +136,337 @@ __device__ __forceinline__ double dummy_data_term(const Params &p, const DummyVi
   return a * p.inv2sxi2;
 }
 
-// Three hidden layers on the 64 rows held in LDS (X: bf16 activations; X8:
-// fp8 copy when FP8), then the output unit; f of row m goes to fout[m].
-// With `absmax`, the largest |input| of each layer is max-accumulated into it
-// (FP8 scale calibration).
+// One layer's product for this wave's SURR_WU units and the block's SURR_ROWS
+// rows: acc[j][i] is the 32-unit tile j (units SURR_WU w + 32 j + ...) of row
+// tile i (rows 32 i + ...), transposed: lane l holds units
+// 8 (r / 4) + 4 (l / 32) + r % 4 of row l % 32. Weights stream from L2 three
+// k-steps ahead of the MFMAs; activations come from LDS.
 template <bool FP8>
-__device__ __forceinline__ void surr_layers(const SurrWeights &sw, uint16_t (*X)[SURR_LD], uint8_t (*X8)[SURR_LD8],
-                                            float *fout, unsigned int *absmax = nullptr) {
-  constexpr int ROWS = SurrRows<FP8>::N;
-  constexpr int RT = ROWS / 32;  // 32-row MFMA tiles
-  const int lane = lane_id(), w = wave_id(), tid = threadIdx.x;
-  for (int l = 0; l < 3; ++l) {
-    if (absmax) {
-      float mx = 0.0f;
-      for (int e = tid; e < ROWS * MLP_F; e += 256) mx = fmaxf(mx, fabsf(bf2f(X[e / MLP_F][e % MLP_F])));
-      mx = wave_max(mx);
-      if (lane == 0) atomicMax(&absmax[l], __float_as_uint(mx));
-    }
-    if (FP8) {
-      // quantize this layer's input with its per-tensor scale
-      const float inv = 1.0f / sw.scale_x[l];
-      for (int e = tid; e < ROWS * (MLP_F / 2); e += 256) {
-        const int m = e / (MLP_F / 2), k = 2 * (e % (MLP_F / 2));
-        const float a = fminf(fmaxf(bf2f(X[m][k]) * inv, -FP8_MAX), FP8_MAX);
-        const float b = fminf(fmaxf(bf2f(X[m][k + 1]) * inv, -FP8_MAX), FP8_MAX);
-        const uint32_t pk = f2fp8x2(a, b);
-        X8[m][k] = (uint8_t)(pk & 0xFF);
-        X8[m][k + 1] = (uint8_t)(pk >> 8);
+__device__ __forceinline__ void surr_gemm(const SurrWeights &sw, int l, const uint8_t *act,
+                                          f32x16 (&acc)[SURR_NJ][SURR_RT]) {
+  const int lane = lane_id(), w = wave_id();
+#pragma unroll
+  for (int j = 0; j < SURR_NJ; ++j)
+#pragma unroll
+    for (int i = 0; i < SURR_RT; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[j][i][r] = 0.0f;
+  constexpr int KS = MLP_F / 16;  // k-steps of 16
+  constexpr int PF = 3;           // weight k-steps in flight
+  const size_t wrow = (size_t)(SURR_WU * w + mfma_col(lane)) * MLP_F + mfma_k0(lane);
+  if (!FP8) {
+    const uint16_t *W = sw.wt + (size_t)l * MLP_H * MLP_F + wrow;
+    const uint16_t *X = (const uint16_t *)act + mfma_col(lane) * SURR_LD + mfma_k0(lane);
+    uint4 wq[PF][SURR_NJ];
+#pragma unroll
+    for (int s = 0; s < PF; ++s)
+#pragma unroll
+      for (int j = 0; j < SURR_NJ; ++j) wq[s][j] = gload_u4(W + 32 * j * MLP_F + 16 * s);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      uint4 a[SURR_NJ];
+#pragma unroll
+      for (int j = 0; j < SURR_NJ; ++j) {
+        a[j] = wq[ks % PF][j];
+        if (ks + PF < KS) wq[ks % PF][j] = gload_u4(W + 32 * j * MLP_F + 16 * (ks + PF));
       }
-      __syncthreads();
-    }
-    f32x16 acc[RT][2];
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+      for (int i = 0; i < SURR_RT; ++i) {
+        const uint4 xb = *reinterpret_cast<const uint4 *>(X + 32 * i * SURR_LD + 16 * ks);
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    const int nb = 64 * w;
-    if (FP8) {
-      const uint8_t *W8 = sw.wt8 + (size_t)l * MLP_H * MLP_F;
-#pragma unroll 4
-      for (int kk = 0; kk < MLP_F; kk += 16) {
-        const int k = kk + mfma_k0(lane);
-        const uint2 b0 = *reinterpret_cast<const uint2 *>(W8 + (size_t)(nb + mfma_col(lane)) * MLP_F + k);
-        const uint2 b1 = *reinterpret_cast<const uint2 *>(W8 + (size_t)(nb + 32 + mfma_col(lane)) * MLP_F + k);
-#pragma unroll
-        for (int i = 0; i < RT; ++i) {
-          const uint2 a = *reinterpret_cast<const uint2 *>(&X8[32 * i + mfma_col(lane)][k]);
-          acc[i][0] = mfma_fp8(a, b0, acc[i][0]);
-          acc[i][1] = mfma_fp8(a, b1, acc[i][1]);
-        }
-      }
-    } else {
-      const uint16_t *Wt = sw.wt + (size_t)l * MLP_H * MLP_F;
-#pragma unroll 2
-      for (int kk = 0; kk < MLP_F; kk += 16) {
-        const int k = kk + mfma_k0(lane);
-        const uint4 b0 = *reinterpret_cast<const uint4 *>(Wt + (size_t)(nb + mfma_col(lane)) * MLP_F + k);
-        const uint4 b1 = *reinterpret_cast<const uint4 *>(Wt + (size_t)(nb + 32 + mfma_col(lane)) * MLP_F + k);
-#pragma unroll
-        for (int i = 0; i < RT; ++i) {
-          const uint4 a = *reinterpret_cast<const uint4 *>(&X[32 * i + mfma_col(lane)][k]);
-          acc[i][0] = mfma_bf16(a, b0, acc[i][0]);
-          acc[i][1] = mfma_bf16(a, b1, acc[i][1]);
-        }
+        for (int j = 0; j < SURR_NJ; ++j) acc[j][i] = mfma_bf16(a[j], xb, acc[j][i]);
       }
     }
-    __syncthreads();  // every wave has read this layer's input
-    const float sc = FP8 ? sw.scale_x[l] * sw.scale_w[l] : 1.0f;
-    const float *bias = sw.bias + l * MLP_H;
+  } else {
+    // K = 64 per instruction: lane l takes k = 64 ks + 32 (l / 32) + 0..31
+    constexpr int KS8 = MLP_F / 64, PF8 = 2;
+    const size_t w8row = (size_t)(SURR_WU * w + mfma_col(lane)) * MLP_F + 32 * (lane >> 5);
+    const uint8_t *W = sw.wt8 + (size_t)l * MLP_H * MLP_F + w8row;
+    const uint8_t *X = act + mfma_col(lane) * SURR_LD8 + 32 * (lane >> 5);
+    uint4 wq[PF8][SURR_NJ][2];
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+    for (int s = 0; s < PF8; ++s)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < SURR_NJ; ++j) {
+        wq[s][j][0] = gload_u4(W + 32 * j * MLP_F + 64 * s);
+        wq[s][j][1] = gload_u4(W + 32 * j * MLP_F + 64 * s + 16);
+      }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = 32 * i + mfma_row(lane, r);
-          const int n = nb + 32 * j + mfma_col(lane);
-          X[m][n] = f2bf(gelu(fmaf(acc[i][j][r], sc, bias[n])));
+    for (int ks = 0; ks < KS8; ++ks) {
+      uint4 a[SURR_NJ][2];
+#pragma unroll
+      for (int j = 0; j < SURR_NJ; ++j) {
+        a[j][0] = wq[ks % PF8][j][0];
+        a[j][1] = wq[ks % PF8][j][1];
+        if (ks + PF8 < KS8) {
+          wq[ks % PF8][j][0] = gload_u4(W + 32 * j * MLP_F + 64 * (ks + PF8));
+          wq[ks % PF8][j][1] = gload_u4(W + 32 * j * MLP_F + 64 * (ks + PF8) + 16);
         }
-    __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < SURR_RT; ++i) {
+        const uint4 x0 = *reinterpret_cast<const uint4 *>(X + 32 * i * SURR_LD8 + 64 * ks);
+        const uint4 x1 = *reinterpret_cast<const uint4 *>(X + 32 * i * SURR_LD8 + 64 * ks + 16);
+#pragma unroll
+        for (int j = 0; j < SURR_NJ; ++j) acc[j][i] = mfma_fp8_k64(a[j][0], a[j][1], x0, x1, acc[j][i]);
+      }
+    }
   }
-  if (tid < ROWS) {
-    float f = sw.b4[0];
-    for (int n = 0; n < MLP_H; ++n) f = fmaf(bf2f(X[tid][n]), sw.w4[n], f);
-    fout[tid] = f;
+}
+
+// Pre-activation of the lane's unit n (bias b) from accumulator value a.
+template <bool FP8>
+__device__ __forceinline__ float surr_pre(float a, float sc, float b) {
+  return fmaf(a, FP8 ? sc : 1.0f, b);
+}
+
+// Epilogue of hidden layer l < 2: g = gelu(acc * scale + bias) into the
+// activations for layer l + 1, rounded to BF16, or (FP8) quantised directly
+// with that layer's input scale, fp8(clamp(g / s_{l+1})). With `absmax`
+// (BF16), the largest |bf16(g)| is max-accumulated into absmax[l + 1].
+template <bool FP8>
+__device__ __forceinline__ void surr_store(const SurrWeights &sw, int l, const f32x16 (&acc)[SURR_NJ][SURR_RT],
+                                           uint8_t *act, unsigned int *absmax) {
+  const int lane = lane_id(), w = wave_id();
+  const float sc = FP8 ? sw.scale_x[l] * sw.scale_w[l] : 1.0f;
+  const float inv = FP8 ? 1.0f / sw.scale_x[l + 1] : 1.0f;
+  const float *bias = sw.bias + l * MLP_H;
+  float mx = 0.0f;
+#pragma unroll
+  for (int j = 0; j < SURR_NJ; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = SURR_WU * w + 32 * j + 8 * q + 4 * (lane >> 5);
+      const float4 b = gload_f4(bias + n);
+#pragma unroll
+      for (int i = 0; i < SURR_RT; ++i) {
+        const int m = 32 * i + mfma_col(lane);
+        const float g0 = gelu(surr_pre<FP8>(acc[j][i][4 * q + 0], sc, b.x));
+        const float g1 = gelu(surr_pre<FP8>(acc[j][i][4 * q + 1], sc, b.y));
+        const float g2 = gelu(surr_pre<FP8>(acc[j][i][4 * q + 2], sc, b.z));
+        const float g3 = gelu(surr_pre<FP8>(acc[j][i][4 * q + 3], sc, b.w));
+        if (FP8) {
+          const float q0 = fminf(fmaxf(g0 * inv, -FP8_MAX), FP8_MAX);
+          const float q1 = fminf(fmaxf(g1 * inv, -FP8_MAX), FP8_MAX);
+          const float q2 = fminf(fmaxf(g2 * inv, -FP8_MAX), FP8_MAX);
+          const float q3 = fminf(fmaxf(g3 * inv, -FP8_MAX), FP8_MAX);
+          *reinterpret_cast<uint32_t *>(act + m * SURR_LD8 + n) = f2fp8x2(q0, q1) | (f2fp8x2(q2, q3) << 16);
+        } else {
+          uint2 v;
+          v.x = f2bf2(g0, g1);
+          v.y = f2bf2(g2, g3);
+          if (absmax)
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(__uint_as_float(v.x << 16)), fabsf(__uint_as_float(v.x & 0xFFFF0000u))),
+                                 fmaxf(fabsf(__uint_as_float(v.y << 16)), fabsf(__uint_as_float(v.y & 0xFFFF0000u)))));
+          *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(act) + m * SURR_LD + n) = v;
+        }
+      }
+    }
+  if (!FP8 && absmax) {
+    mx = wave_max(mx);
+    if (lane == 0) atomicMax(&absmax[l + 1], __float_as_uint(mx));
+  }
+}
+
+// Epilogue of the last hidden layer fused with the output unit: this wave's
+// share sum_n bf16(gelu(z_n)) w4_n of every row into fpart[w][row].
+template <bool FP8>
+__device__ __forceinline__ void surr_head(const SurrWeights &sw, const f32x16 (&acc)[SURR_NJ][SURR_RT],
+                                          float (*fpart)[SURR_ROWS]) {
+  const int lane = lane_id(), w = wave_id();
+  const float sc = FP8 ? sw.scale_x[2] * sw.scale_w[2] : 1.0f;
+  const float *bias = sw.bias + 2 * MLP_H;
+  float part[SURR_RT];
+#pragma unroll
+  for (int i = 0; i < SURR_RT; ++i) part[i] = 0.0f;
+#pragma unroll
+  for (int j = 0; j < SURR_NJ; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = SURR_WU * w + 32 * j + 8 * q + 4 * (lane >> 5);
+      const float4 b = gload_f4(bias + n);
+      const float4 v = gload_f4(sw.w4 + n);
+#pragma unroll
+      for (int i = 0; i < SURR_RT; ++i) {
+        const uint32_t h01 = f2bf2(gelu(surr_pre<FP8>(acc[j][i][4 * q + 0], sc, b.x)),
+                                   gelu(surr_pre<FP8>(acc[j][i][4 * q + 1], sc, b.y)));
+        const uint32_t h23 = f2bf2(gelu(surr_pre<FP8>(acc[j][i][4 * q + 2], sc, b.z)),
+                                   gelu(surr_pre<FP8>(acc[j][i][4 * q + 3], sc, b.w)));
+        part[i] = fmaf(__uint_as_float(h01 << 16), v.x, part[i]);
+        part[i] = fmaf(__uint_as_float(h01 & 0xFFFF0000u), v.y, part[i]);
+        part[i] = fmaf(__uint_as_float(h23 << 16), v.z, part[i]);
+        part[i] = fmaf(__uint_as_float(h23 & 0xFFFF0000u), v.w, part[i]);
+      }
+    }
+#pragma unroll
+  for (int i = 0; i < SURR_RT; ++i) {
+    // lanes l and l + 32 hold the two halves of the wave's units of row l % 32
+    const float both = part[i] + __shfl_xor(part[i], 32, WAVE);
+    if (lane < 32) fpart[w][32 * i + lane] = both;
+  }
+}
+
+// The three layers and the output unit on the block's rows in `act`; the
+// network output of row m is sw.b4 + sum_w fpart[w][m] (fixed order).
+template <bool FP8>
+__device__ __forceinline__ void surr_layers(const SurrWeights &sw, uint8_t *act, float (*fpart)[SURR_ROWS],
+                                            unsigned int *absmax) {
+  f32x16 acc[SURR_NJ][SURR_RT];
+  for (int l = 0; l < 3; ++l) {
+    surr_gemm<FP8>(sw, l, act, acc);
+    __syncthreads();  // every wave has read this layer's input
+    if (l < 2) {
+      surr_store<FP8>(sw, l, acc, act, absmax);
+      __syncthreads();
+    } else {
+      surr_head<FP8>(sw, acc, fpart);
+    }
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ float surr_out(const SurrWeights &sw, const float (*fpart)[SURR_ROWS], int m) {
+  float f = sw.b4[0];
+#pragma unroll
+  for (int w = 0; w < SURR_NW; ++w) f += fpart[w][m];
+  return f;
+}
+
+// One feature value into the activations (BF16, or FP8 with layer 0's scale).
+template <bool FP8>
+__device__ __forceinline__ void surr_put(uint8_t *act, int m, int f, float v, float inv0) {
+  const uint16_t h = f2bf(v);
+  if (FP8)
+    act[m * SURR_LD8 + f] = (uint8_t)(f2fp8x2(fminf(fmaxf(bf2f(h) * inv0, -FP8_MAX), FP8_MAX), 0.0f) & 0xFF);
+  else
+    reinterpret_cast<uint16_t *>(act)[m * SURR_LD + f] = h;
 }
 
 // Surrogate log-likelihood of every dummy of the step: ll[s] = 100 f - A(z),
 // and every target's largest surrogate value (tmax, ordered bits, atomic max;
 // dummies are sorted by target, so a block's rows span consecutive targets).
+// Features: threads take (row m = tid % SURR_ROWS, window rows g, g + G, ...),
+// G = 256 / SURR_ROWS, and load the window's pixels row by row, adding their
+// squared residuals for A(z) in binary64; the G partial sums of a row are
+// added in a fixed order.
 template <int DIM, bool FP8>
-__global__ __launch_bounds__(256) void k_surr_infer(Params p, DummyView dv, const uint64_t *__restrict__ meta,
-                                                    const StepDesc *__restrict__ desc, SurrWeights sw,
-                                                    double *__restrict__ ll, unsigned long long *__restrict__ tmax) {
-  constexpr int ROWS = SurrRows<FP8>::N;
-  __shared__ __attribute__((aligned(16))) uint16_t X[ROWS][SURR_LD];
-  __shared__ __attribute__((aligned(16))) uint8_t X8[FP8 ? SURR_ROWS : 1][SURR_LD8];
-  __shared__ float fout[ROWS];
-  __shared__ double az[ROWS];
+__global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) void k_surr_infer(Params p, DummyView dv, const uint64_t *__restrict__ meta,
+                                                            const StepDesc *__restrict__ desc, SurrWeights sw,
+                                                            double *__restrict__ ll,
+                                                            unsigned long long *__restrict__ tmax) {
+  constexpr int G = SURR_TPB / SURR_ROWS;
+  static_assert(G * SURR_ROWS == SURR_TPB, "rows must divide the block");
+  __shared__ __attribute__((aligned(16))) uint8_t act[SurrAct<FP8>::BYTES];
+  __shared__ float fpart[SURR_NW][SURR_ROWS];
+  __shared__ double apart[G > 1 ? G - 1 : 1][SURR_ROWS];
+  __shared__ int rinfo[4][SURR_ROWS];  // frame offset, c0, r0, valid
+  __shared__ unsigned long long tmx[SURR_ROWS];
   const uint32_t B = (uint32_t)meta[META_B];
-  const float *frame = desc->frame;
-  for (uint32_t s0 = blockIdx.x * ROWS; s0 < B; s0 += gridDim.x * ROWS) {
-    for (int e = threadIdx.x; e < ROWS * MLP_F; e += 256) {
-      const int m = e / MLP_F, f = e % MLP_F;
-      const uint32_t s = s0 + m;
-      X[m][f] = f2bf(s < B ? dummy_feature<DIM>(p, dv, frame, s, f) : 0.0f);
-    }
-    if (threadIdx.x < ROWS) {
-      const uint32_t s = s0 + threadIdx.x;
-      az[threadIdx.x] = s < B ? dummy_data_term<DIM>(p, dv, frame, s) : 0.0;
+  const uint32_t NT = p.NT;
+  const gfloat *frame = as_global(desc->frame);
+  const int tid = threadIdx.x, P = p.P, R = p.R, P2 = P * P, NF = P2 + 2 * DIM + 1;
+  const float inv0 = FP8 ? 1.0f / sw.scale_x[0] : 1.0f;
+  for (uint32_t s0 = blockIdx.x * SURR_ROWS; s0 < B; s0 += gridDim.x * SURR_ROWS) {
+    if (tid < SURR_ROWS) {
+      const uint32_t s = s0 + tid;
+      const bool valid = s < B;
+      const int t = valid ? dv.seg_t[s] : 0;
+      rinfo[0][tid] = p.per_target_frames ? t * p.H * p.W : 0;
+      rinfo[1][tid] = valid ? dv.dpix[s] : 0;
+      rinfo[2][tid] = valid ? dv.dpix[(size_t)NT + s] : 0;
+      rinfo[3][tid] = valid;
+      // state features: offsets from the pixel (in-plane), the axial
+      // coordinate in full / 10 (3D), velocities / 10, intensity / 100
+      float st[2 * DIM + 1];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) st[a] = valid ? dv.doff[(size_t)a * NT + s] : 0.0f;
+      if (DIM == 3)
+        st[2] = valid ? ((float)dv.dpix[2 * (size_t)NT + s] + dv.doff[2 * (size_t)NT + s]) * MLP_VEL_SCALE : 0.0f;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) st[DIM + a] = valid ? dv.dvel[(size_t)a * NT + s] * MLP_VEL_SCALE : 0.0f;
+      st[2 * DIM] = valid ? dv.dint[s] * MLP_IN_SCALE : 0.0f;
+#pragma unroll
+      for (int a = 0; a < 2 * DIM + 1; ++a) surr_put<FP8>(act, tid, P2 + a, st[a], inv0);
+      for (int f = NF; f < MLP_F; ++f) surr_put<FP8>(act, tid, f, 0.0f, inv0);
     }
     __syncthreads();
-    surr_layers<FP8>(sw, X, X8, fout);
-    // tmx[j]: largest value among rows of target t_first + j (at most ROWS targets)
-    __shared__ unsigned long long tmx[ROWS];
-    if (threadIdx.x < ROWS) tmx[threadIdx.x] = 0ull;
+    const int m = tid % SURR_ROWS, g = tid / SURR_ROWS;
+    double a = 0.0;
+    {
+      const int base = rinfo[0][m], c0 = rinfo[1][m], r0 = rinfo[2][m];
+      const bool valid = rinfo[3][m] != 0;
+      for (int dy = g; dy < P; dy += G) {
+        const int r = r0 + dy - R;
+        const bool rok = valid && r >= 0 && r < p.H;
+        const gfloat *fr = frame + base + (ptrdiff_t)(rok ? r : 0) * p.W;
+        for (int dx = 0; dx < P; ++dx) {
+          const int c = c0 + dx - R;
+          const bool ok = rok && c >= 0 && c < p.W;
+          const float z = ok ? fr[c] : p.i_bg;
+          surr_put<FP8>(act, m, dy * P + dx, (z - p.i_bg) * MLP_IN_SCALE, inv0);
+          if (ok) {
+            const double zb = (double)z - (double)p.i_bg;
+            a += zb * zb;
+          }
+        }
+      }
+    }
+    if (G > 1 && g > 0) apart[g - 1][m] = a;
+    __syncthreads();
+    double az = 0.0;
+    if (tid < SURR_ROWS) {
+      for (int gg = 1; gg < G; ++gg) a += apart[gg - 1][tid];
+      az = a * p.inv2sxi2;
+    }
+    surr_layers<FP8>(sw, act, fpart, nullptr);
+    if (tid < SURR_ROWS) tmx[tid] = 0ull;
     __syncthreads();
     const int t_first = dv.seg_t[s0];
-    if (threadIdx.x < ROWS) {
-      const uint32_t s = s0 + threadIdx.x;
+    if (tid < SURR_ROWS) {
+      const uint32_t s = s0 + tid;
       if (s < B) {
-        const double v = (double)MLP_OUT_SCALE * (double)fout[threadIdx.x] - az[threadIdx.x];
+        const double v = (double)MLP_OUT_SCALE * (double)surr_out(sw, fpart, tid) - az;
         ll[s] = v;
         atomicMax(&tmx[dv.seg_t[s] - t_first], ordered_bits(v));
       }
     }
     __syncthreads();
-    if (threadIdx.x < ROWS && tmx[threadIdx.x] != 0ull)
-      atomicMax(&tmax[t_first + threadIdx.x], tmx[threadIdx.x]);
+    if (tid < SURR_ROWS && tmx[tid] != 0ull) atomicMax(&tmax[t_first + tid], tmx[tid]);
     __syncthreads();
   }
 }
 
 // Network outputs f for BF16 feature rows X [n][256] (tests, calibration, evaluation).
 template <bool FP8>
-__global__ __launch_bounds__(256) void k_surr_rows(int n, const uint16_t *__restrict__ Xg, SurrWeights sw,
-                                                   float *__restrict__ f_out, unsigned int *__restrict__ absmax) {
-  constexpr int ROWS = SurrRows<FP8>::N;
-  __shared__ __attribute__((aligned(16))) uint16_t X[ROWS][SURR_LD];
-  __shared__ __attribute__((aligned(16))) uint8_t X8[FP8 ? SURR_ROWS : 1][SURR_LD8];
-  __shared__ float fout[ROWS];
-  for (int r0 = blockIdx.x * ROWS; r0 < n; r0 += gridDim.x * ROWS) {
-    for (int e = threadIdx.x; e < ROWS * MLP_F; e += 256) {
-      const int m = e / MLP_F, f = e % MLP_F;
-      X[m][f] = r0 + m < n ? Xg[(size_t)(r0 + m) * MLP_F + f] : (uint16_t)0;
+__global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) void k_surr_rows(int n, const uint16_t *__restrict__ Xg, SurrWeights sw,
+                                                           float *__restrict__ f_out,
+                                                           unsigned int *__restrict__ absmax) {
+  __shared__ __attribute__((aligned(16))) uint8_t act[SurrAct<FP8>::BYTES];
+  __shared__ float fpart[SURR_NW][SURR_ROWS];
+  const int tid = threadIdx.x;
+  const float inv0 = FP8 ? 1.0f / sw.scale_x[0] : 1.0f;
+  for (int r0 = blockIdx.x * SURR_ROWS; r0 < n; r0 += gridDim.x * SURR_ROWS) {
+    float mx = 0.0f;
+    for (int e = tid; e < SURR_ROWS * (MLP_F / 8); e += SURR_TPB) {
+      const int m = e / (MLP_F / 8), k = 8 * (e % (MLP_F / 8));
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (r0 + m < n) v = gload_u4(Xg + (size_t)(r0 + m) * MLP_F + k);
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint16_t lo = (uint16_t)(wv[u] & 0xFFFF), hi = (uint16_t)(wv[u] >> 16);
+        mx = fmaxf(mx, fmaxf(fabsf(bf2f(lo)), fabsf(bf2f(hi))));
+        surr_put<FP8>(act, m, k + 2 * u, bf2f(lo), inv0);
+        surr_put<FP8>(act, m, k + 2 * u + 1, bf2f(hi), inv0);
+      }
+    }
+    if (absmax) {
+      mx = wave_max(mx);
+      if (lane_id() == 0) atomicMax(&absmax[0], __float_as_uint(mx));
     }
     __syncthreads();
-    surr_layers<FP8>(sw, X, X8, fout, absmax);
-    if (threadIdx.x < ROWS && r0 + threadIdx.x < n) f_out[r0 + threadIdx.x] = fout[threadIdx.x];
+    surr_layers<FP8>(sw, act, fpart, absmax);
+    if (tid < SURR_ROWS && r0 + tid < n) f_out[r0 + tid] = surr_out(sw, fpart, tid);
     __syncthreads();
   }
 }

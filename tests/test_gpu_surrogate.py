@@ -3,9 +3,11 @@
 * Fused inference kernel (BF16 and FP8 E4M3 operands) against a numpy
   emulation of the same arithmetic (tests/fp_emul.py, pinned on the CPU): the
   kernel rounds each hidden activation to BF16, and FP8 mode quantises each
-  layer's input and weights; a rounding boundary crossed differently under a
-  different FP32 summation order moves a hidden unit by one BF16 (or E4M3)
-  step, so the bound on f is one BF16 step of every last-layer unit:
+  layer's input (the FP32 activation) and weights; its GELU takes Phi from
+  a formula within 3e-7 of the exact one (the emulation's). A rounding
+  boundary crossed differently under a different FP32 summation order (or
+  that GELU) moves a hidden unit by one BF16 (or E4M3) step, so the bound on
+  f is one BF16 step of every last-layer unit:
   2^-8 sum_n |w4_n h3_n| (FP8: 98% of rows within it, all within 2^-4 of it).
 * Training rows from an exact pcSIR step against features built from the
   oracle's bins (window features bit-exact, state features within one BF16
@@ -65,7 +67,10 @@ def _gelu32(z):
 
 
 def _emulate(th32, X, fp8=False, act_scale=None):
-    """f [n], |w4| |h3| row sums, per-layer input absmax."""
+    """f [n], |w4| |h3| row sums, per-layer input absmax. BF16: every hidden
+    activation is rounded to BF16. FP8: a hidden layer's output is quantised
+    directly, fp8(clamp(g / s)), as the next layer's input; the features are
+    BF16 before their quantisation; the output unit reads BF16 activations."""
     from oracle import mlp
     p = mlp.unpack(th32.astype(np.float64))
     h = X.astype(np.float32)
@@ -85,7 +90,9 @@ def _emulate(th32, X, fp8=False, act_scale=None):
         else:
             acc = h.astype(np.float64) @ bf16_round(W32).astype(np.float64)
             z = (acc.astype(np.float32) + b32).astype(np.float32)
-        h = bf16_round(_gelu32(z))
+        g = _gelu32(z)
+        h = g if fp8 else bf16_round(g)
+    h = bf16_round(g)
     w4 = p["w4"].astype(np.float64)
     f = h.astype(np.float64) @ w4 + p["b4"][0]
     scale = np.abs(h.astype(np.float64)) @ np.abs(w4)
