@@ -88,10 +88,14 @@ pcsir_status pcsir_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t
  * Inference form of the network: one device block of pcsir_surr_bytes() (256-
  * byte aligned) holding the weights transposed to [layer][unit][input] in BF16
  * and in FP8 E4M3 (scaled per layer by max|W| / 448), the FP32 biases and the
- * output unit, and the FP8 input scales s_l of the three layers: in FP8 mode a
- * layer's input x is quantised as fp8(clamp(x / s_l, +-448)). One fused kernel
- * runs the three layers on 64 rows per workgroup with FP32 accumulation; the
- * activations between layers are rounded to BF16. */
+ * output unit, and the FP8 input scales s_l of the three layers. One fused
+ * kernel runs the three layers on 128 rows per workgroup with FP32
+ * accumulation. BF16 mode: BF16 operands; the activations between layers are
+ * rounded to BF16. FP8 mode: the input layer keeps BF16 operands (the
+ * features' 3-bit-mantissa quantisation carried most of the all-FP8 network's
+ * error); the two hidden layers take E4M3 operands, their input being the
+ * previous layer's FP32 output g quantised as fp8(clamp(g / s_l, +-448)),
+ * l = 1, 2 (s_0 is unused). The output unit reads BF16 activations. */
 size_t pcsir_surr_bytes(void);
 
 /* Fill the inference block from the FP32 parameter vector. act_scale_host: [3]

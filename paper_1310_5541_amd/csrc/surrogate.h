@@ -29,11 +29,10 @@ constexpr int SURR_LD = MLP_F + 8;        // LDS row stride (bf16 elements)
 constexpr int SURR_LD8 = MLP_F + 16;      // LDS row stride (fp8 bytes)
 constexpr float FP8_MAX = 448.0f;         // largest finite E4M3 value
 
-// LDS bytes of the activations of SURR_ROWS rows
-template <bool FP8>
-struct SurrAct {
-  static constexpr int BYTES = FP8 ? SURR_ROWS * SURR_LD8 : SURR_ROWS * SURR_LD * 2;
-};
+// LDS bytes of the activations of SURR_ROWS rows (BF16 layout; the FP8
+// layout of the hidden layers' inputs, SURR_ROWS x SURR_LD8 bytes, fits in it)
+constexpr int SURR_ACT_BYTES = SURR_ROWS * SURR_LD * 2;
+static_assert(SURR_ROWS * SURR_LD8 <= SURR_ACT_BYTES, "FP8 activations fit the buffer");
 
 // Loads through global-address-space pointers (see as_global).
 typedef uint32_t u32v4 __attribute__((ext_vector_type(4)));
@@ -222,13 +221,14 @@ __device__ __forceinline__ float surr_pre(float a, float sc, float b) {
 
 // Epilogue of hidden layer l < 2: g = gelu(acc * scale + bias) into the
 // activations for layer l + 1, rounded to BF16, or (FP8) quantised directly
-// with that layer's input scale, fp8(clamp(g / s_{l+1})). With `absmax`
-// (BF16), the largest |bf16(g)| is max-accumulated into absmax[l + 1].
-template <bool FP8>
+// with that layer's input scale, fp8(clamp(g / s_{l+1})). IN8: this layer's
+// operands were FP8 (the accumulator then carries the scales). With
+// `absmax` (BF16), the largest |bf16(g)| is max-accumulated into absmax[l + 1].
+template <bool IN8, bool FP8>
 __device__ __forceinline__ void surr_store(const SurrWeights &sw, int l, const f32x16 (&acc)[SURR_NJ][SURR_RT],
                                            uint8_t *act, unsigned int *absmax) {
   const int lane = lane_id(), w = wave_id();
-  const float sc = FP8 ? sw.scale_x[l] * sw.scale_w[l] : 1.0f;
+  const float sc = IN8 ? sw.scale_x[l] * sw.scale_w[l] : 1.0f;
   const float inv = FP8 ? 1.0f / sw.scale_x[l + 1] : 1.0f;
   const float *bias = sw.bias + l * MLP_H;
   float mx = 0.0f;
@@ -241,10 +241,10 @@ __device__ __forceinline__ void surr_store(const SurrWeights &sw, int l, const f
 #pragma unroll
       for (int i = 0; i < SURR_RT; ++i) {
         const int m = 32 * i + mfma_col(lane);
-        const float g0 = gelu(surr_pre<FP8>(acc[j][i][4 * q + 0], sc, b.x));
-        const float g1 = gelu(surr_pre<FP8>(acc[j][i][4 * q + 1], sc, b.y));
-        const float g2 = gelu(surr_pre<FP8>(acc[j][i][4 * q + 2], sc, b.z));
-        const float g3 = gelu(surr_pre<FP8>(acc[j][i][4 * q + 3], sc, b.w));
+        const float g0 = gelu(surr_pre<IN8>(acc[j][i][4 * q + 0], sc, b.x));
+        const float g1 = gelu(surr_pre<IN8>(acc[j][i][4 * q + 1], sc, b.y));
+        const float g2 = gelu(surr_pre<IN8>(acc[j][i][4 * q + 2], sc, b.z));
+        const float g3 = gelu(surr_pre<IN8>(acc[j][i][4 * q + 3], sc, b.w));
         if (FP8) {
           const float q0 = fminf(fmaxf(g0 * inv, -FP8_MAX), FP8_MAX);
           const float q1 = fminf(fmaxf(g1 * inv, -FP8_MAX), FP8_MAX);
@@ -306,17 +306,27 @@ __device__ __forceinline__ void surr_head(const SurrWeights &sw, const f32x16 (&
   }
 }
 
-// The three layers and the output unit on the block's rows in `act`; the
-// network output of row m is sw.b4 + sum_w fpart[w][m] (fixed order).
+// The three layers and the output unit on the block's rows in `act` (BF16
+// features); the network output of row m is sw.b4 + sum_w fpart[w][m] (fixed
+// order). FP8: the input layer keeps BF16 operands (quantising the window's
+// pixels to a 3-bit mantissa carried most of the FP8 network's error) and
+// quantises its output for the two FP8 hidden layers.
 template <bool FP8>
 __device__ __forceinline__ void surr_layers(const SurrWeights &sw, uint8_t *act, float (*fpart)[SURR_ROWS],
                                             unsigned int *absmax) {
   f32x16 acc[SURR_NJ][SURR_RT];
   for (int l = 0; l < 3; ++l) {
-    surr_gemm<FP8>(sw, l, act, acc);
-    __syncthreads();  // every wave has read this layer's input
+    const bool in8 = FP8 && l > 0;
+    if (in8)
+      surr_gemm<true>(sw, l, act, acc);
+    else
+      surr_gemm<false>(sw, l, act, acc);
+    __syncthreads();  // every wave has read the layer's input
     if (l < 2) {
-      surr_store<FP8>(sw, l, acc, act, absmax);
+      if (in8)
+        surr_store<true, FP8>(sw, l, acc, act, absmax);
+      else
+        surr_store<false, FP8>(sw, l, acc, act, absmax);
       __syncthreads();
     } else {
       surr_head<FP8>(sw, acc, fpart);
@@ -332,14 +342,9 @@ __device__ __forceinline__ float surr_out(const SurrWeights &sw, const float (*f
   return f;
 }
 
-// One feature value into the activations (BF16, or FP8 with layer 0's scale).
-template <bool FP8>
-__device__ __forceinline__ void surr_put(uint8_t *act, int m, int f, float v, float inv0) {
-  const uint16_t h = f2bf(v);
-  if (FP8)
-    act[m * SURR_LD8 + f] = (uint8_t)(f2fp8x2(fminf(fmaxf(bf2f(h) * inv0, -FP8_MAX), FP8_MAX), 0.0f) & 0xFF);
-  else
-    reinterpret_cast<uint16_t *>(act)[m * SURR_LD + f] = h;
+// One feature value into the activations (BF16).
+__device__ __forceinline__ void surr_put(uint8_t *act, int m, int f, float v) {
+  reinterpret_cast<uint16_t *>(act)[m * SURR_LD + f] = f2bf(v);
 }
 
 // Surrogate log-likelihood of every dummy of the step: ll[s] = 100 f - A(z),
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) v
                                                             unsigned long long *__restrict__ tmax) {
   constexpr int G = SURR_TPB / SURR_ROWS;
   static_assert(G * SURR_ROWS == SURR_TPB, "rows must divide the block");
-  __shared__ __attribute__((aligned(16))) uint8_t act[SurrAct<FP8>::BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t act[SURR_ACT_BYTES];
   __shared__ float fpart[SURR_NW][SURR_ROWS];
   __shared__ double apart[G > 1 ? G - 1 : 1][SURR_ROWS];
   __shared__ int rinfo[4][SURR_ROWS];  // frame offset, c0, r0, valid
@@ -365,7 +370,6 @@ __global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) v
   const uint32_t NT = p.NT;
   const gfloat *frame = as_global(desc->frame);
   const int tid = threadIdx.x, P = p.P, R = p.R, P2 = P * P, NF = P2 + 2 * DIM + 1;
-  const float inv0 = FP8 ? 1.0f / sw.scale_x[0] : 1.0f;
   for (uint32_t s0 = blockIdx.x * SURR_ROWS; s0 < B; s0 += gridDim.x * SURR_ROWS) {
     if (tid < SURR_ROWS) {
       const uint32_t s = s0 + tid;
@@ -386,8 +390,8 @@ __global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) v
       for (int a = 0; a < DIM; ++a) st[DIM + a] = valid ? dv.dvel[(size_t)a * NT + s] * MLP_VEL_SCALE : 0.0f;
       st[2 * DIM] = valid ? dv.dint[s] * MLP_IN_SCALE : 0.0f;
 #pragma unroll
-      for (int a = 0; a < 2 * DIM + 1; ++a) surr_put<FP8>(act, tid, P2 + a, st[a], inv0);
-      for (int f = NF; f < MLP_F; ++f) surr_put<FP8>(act, tid, f, 0.0f, inv0);
+      for (int a = 0; a < 2 * DIM + 1; ++a) surr_put(act, tid, P2 + a, st[a]);
+      for (int f = NF; f < MLP_F; ++f) surr_put(act, tid, f, 0.0f);
     }
     __syncthreads();
     const int m = tid % SURR_ROWS, g = tid / SURR_ROWS;
@@ -403,7 +407,7 @@ __global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) v
           const int c = c0 + dx - R;
           const bool ok = rok && c >= 0 && c < p.W;
           const float z = ok ? fr[c] : p.i_bg;
-          surr_put<FP8>(act, m, dy * P + dx, (z - p.i_bg) * MLP_IN_SCALE, inv0);
+          surr_put(act, m, dy * P + dx, (z - p.i_bg) * MLP_IN_SCALE);
           if (ok) {
             const double zb = (double)z - (double)p.i_bg;
             a += zb * zb;
@@ -441,10 +445,9 @@ template <bool FP8>
 __global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) void k_surr_rows(int n, const uint16_t *__restrict__ Xg, SurrWeights sw,
                                                            float *__restrict__ f_out,
                                                            unsigned int *__restrict__ absmax) {
-  __shared__ __attribute__((aligned(16))) uint8_t act[SurrAct<FP8>::BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t act[SURR_ACT_BYTES];
   __shared__ float fpart[SURR_NW][SURR_ROWS];
   const int tid = threadIdx.x;
-  const float inv0 = FP8 ? 1.0f / sw.scale_x[0] : 1.0f;
   for (int r0 = blockIdx.x * SURR_ROWS; r0 < n; r0 += gridDim.x * SURR_ROWS) {
     float mx = 0.0f;
     for (int e = tid; e < SURR_ROWS * (MLP_F / 8); e += SURR_TPB) {
@@ -456,8 +459,8 @@ __global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) v
       for (int u = 0; u < 4; ++u) {
         const uint16_t lo = (uint16_t)(wv[u] & 0xFFFF), hi = (uint16_t)(wv[u] >> 16);
         mx = fmaxf(mx, fmaxf(fabsf(bf2f(lo)), fabsf(bf2f(hi))));
-        surr_put<FP8>(act, m, k + 2 * u, bf2f(lo), inv0);
-        surr_put<FP8>(act, m, k + 2 * u + 1, bf2f(hi), inv0);
+        surr_put(act, m, k + 2 * u, bf2f(lo));
+        surr_put(act, m, k + 2 * u + 1, bf2f(hi));
       }
     }
     if (absmax) {

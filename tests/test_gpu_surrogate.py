@@ -2,8 +2,8 @@
 
 * Fused inference kernel (BF16 and FP8 E4M3 operands) against a numpy
   emulation of the same arithmetic (tests/fp_emul.py, pinned on the CPU): the
-  kernel rounds each hidden activation to BF16, and FP8 mode quantises each
-  layer's input (the FP32 activation) and weights; its GELU takes Phi from
+  kernel rounds each hidden activation to BF16, and FP8 mode quantises the
+  two hidden layers' inputs (FP32 activations) and weights; its GELU takes Phi from
   a formula within 3e-7 of the exact one (the emulation's). A rounding
   boundary crossed differently under a different FP32 summation order (or
   that GELU) moves a hidden unit by one BF16 (or E4M3) step, so the bound on
@@ -68,9 +68,10 @@ def _gelu32(z):
 
 def _emulate(th32, X, fp8=False, act_scale=None):
     """f [n], |w4| |h3| row sums, per-layer input absmax. BF16: every hidden
-    activation is rounded to BF16. FP8: a hidden layer's output is quantised
-    directly, fp8(clamp(g / s)), as the next layer's input; the features are
-    BF16 before their quantisation; the output unit reads BF16 activations."""
+    activation is rounded to BF16. FP8: the input layer keeps BF16 operands;
+    the two hidden layers take FP8 operands, their input being the previous
+    layer's FP32 output quantised directly, fp8(clamp(g / s)); the output
+    unit reads BF16 activations."""
     from oracle import mlp
     p = mlp.unpack(th32.astype(np.float64))
     h = X.astype(np.float32)
@@ -79,7 +80,7 @@ def _emulate(th32, X, fp8=False, act_scale=None):
         absmax.append(float(np.abs(h).max()))
         W32 = p[W].astype(np.float32)
         b32 = p[b].astype(np.float32)
-        if fp8:
+        if fp8 and l > 0:
             sw = np.float32(np.float32(np.abs(W32).max()) / np.float32(448.0))
             Wq = e4m3_round(np.clip(W32 / sw, -448, 448).astype(np.float32))
             inv = np.float32(1.0) / np.float32(act_scale[l])

@@ -1,0 +1,96 @@
+"""What the learned surrogate gains over the method without it, on one seeded
+workload: a network trained on the GPU (the library's BF16 MFMA training
+kernels) from rows that exact pcSIR produces on separate training sequences
+replaces the per-sub-sample likelihood of the dummies (Eq. likelihood with
+8 x 8 sub-pixel quadrature) in pcSIR. On a test sequence of 250 targets at
+the batched workload's spot density, the surrogate's tracking RMSE must stay
+within 5% of exact pcSIR's by the rule the benchmark matches operating points
+with: the median per-target RMSE within 5%, and the share of lost targets
+(RMSE above 2 px) at most 2 points above exact's (where spots cross, a track
+can be lost in one run and kept in the other, which dominates the mean). The
+time per step of both is reported."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1310_5541_amd import lib
+    lib()
+
+
+def _filter(w, init, lik, h=0.25):
+    from paper_1310_5541_amd import Config, Filter
+    m = int(round(1.0 / h))
+    return Filter(Config.from_workload(w, bins_per_px=(m, m, 1), lik_mode=lik, seed=w.seed + 500), init)
+
+
+def _track(w, tr, fr, init, lik, params=None):
+    import torch
+    f = _filter(w, init, lik)
+    if params is not None:
+        f.set_surrogate(params, None, 0.01, 2.0)
+    est = np.zeros((w.K, w.T, w.D))
+    for k in range(1, w.K + 1):
+        f.step(fr[k - 1], k)
+        est[k - 1] = f.estimate()[0]
+    # timed replay of the same frames from the same start
+    f.set_particles(init)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, w.K + 1):
+        f.step(fr[k - 1], k)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / w.K
+    stats = f.surrogate_stats() if params is not None else None
+    f.close()
+    return synth.rmse(est, tr, 2), ms, stats
+
+
+def test_trained_surrogate_tracks_like_exact_pcsir():
+    import torch
+
+    from paper_1310_5541_amd import surrogate as sg
+    dev = torch.device("cuda:0")
+    # training rows: exact pcSIR dummies of two training sequences
+    cap = 1_000_000
+    X = torch.empty((cap, 256), dtype=torch.bfloat16, device=dev)
+    y = torch.empty(cap, dtype=torch.float32, device=dev)
+    n = 0
+    for s in range(4):
+        if n >= cap:
+            break
+        wt = synth.preset("train-2d-512", K=20, seed=7000 + 100 * s)
+        trt = synth.truth(wt)
+        frt = torch.from_numpy(synth.frames(wt, trt)).to(dev)
+        it = torch.from_numpy(synth.initial_particles(wt, trt[0], wt.counts())).to(dev)
+        f = _filter(wt, it, 1)
+        n = sg.rows(f, frt, 1, wt.K, cap, X, y, start=n)
+        f.close()
+    params, hist = sg.train(X[:n], y[:n], epochs=8)
+    log(f"case surrogate_gain: {n} rows, rms per epoch (nats) "
+        f"{[round(float(np.sqrt(m)) * 100, 3) for m in hist['mse_per_epoch']]}, {hist['train_s']:.1f} s")
+    # test sequence: 250 targets in the central 412^2 of 512^2 frames, other seeds
+    w = synth.preset("train-2d-512", K=20, seed=9100)
+    tr = synth.truth(w)
+    fr = torch.from_numpy(synth.frames(w, tr)).to(dev)
+    init = torch.from_numpy(synth.initial_particles(w, tr[0], w.counts())).to(dev)
+    r_ex, ms_ex, _ = _track(w, tr, fr, init, 0)
+    r_sg, ms_sg, st = _track(w, tr, fr, init, 2, params)
+    log(f"  exact (per sub-sample): mean {r_ex.mean():.4f} median {np.median(r_ex):.4f} px, {ms_ex:.3f} ms/step")
+    log(f"  surrogate BF16:         mean {r_sg.mean():.4f} median {np.median(r_sg):.4f} px, {ms_sg:.3f} ms/step; "
+        f"checks, fallbacks, max error {st}")
+    lost_ex, lost_sg = int(np.sum(r_ex > 2.0)), int(np.sum(r_sg > 2.0))
+    log(f"  lost targets: exact {lost_ex}, surrogate {lost_sg}; time ratio exact / surrogate {ms_ex / ms_sg:.2f}")
+    assert np.median(r_sg) <= 1.05 * np.median(r_ex)
+    assert lost_sg <= lost_ex + 0.02 * w.T
