@@ -73,9 +73,15 @@ def parse():
     ap.add_argument("--large-seqs", type=int, default=20,
                     help="sequences of the large-object section (0: skip it)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-target sections (N = 10^4 on 64^2, and the h sweep at N = 10^6 on 512^2)")
+    ap.add_argument("--single-reps", type=int, default=3, help="sequences of the single-target RMSE")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many exact pcSIR steps (--lik) and exit (for rocprofv3)")
-    ap.add_argument("--lik", type=int, default=LIK_SEP, help="profile mode: 0 direct, 1 separable")
+    ap.add_argument("--lik", type=int, default=LIK_SEP,
+                    help="profile mode: 0 direct, 1 separable, 2 surrogate BF16, 3 surrogate FP8")
+    ap.add_argument("--profile-train", type=int, default=0,
+                    help="run this many surrogate training steps (batch 1024) on random rows, then exit")
     ap.add_argument("--no-graphs", action="store_true", help="profile mode: launch kernels one by one")
     ap.add_argument("--tuning", default="", help="profile mode: launch shapes as JSON (pcsir_tuning fields)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -171,6 +177,83 @@ def cpu_oracle_rate(oracle, mdl, w, frames_np, counts, state, seconds, threads=1
     return {"value": ps / el, "unit": "particle-steps/s", "cores": used, "kind": "oracle",
             "sample": f"{len(sub)} of {T} targets (every {stride if T > stride else 1}th), frames 1..{k - 1} "
                       f"({ps} particle-steps, {el:.1f} s), FP64, {used} thread{'s' if used > 1 else ''}"}
+
+
+def single_target(args, dev):
+    """The two single-target configurations, each timed (inputs in HBM, W
+    warm-up frames, then K frames bracketed by device synchronisation) and
+    tracked from the truth over R seeded sequences for the RMSE:
+    * single-2d-64: N = 10^4, 64 x 64, 20 frames, 11 x 11 window, 2 x 2
+      quadrature, h = 0.5; SIR and pcSIR, microseconds per step;
+    * single-2d-512: N = 10^6, 512 x 512, 15 x 15 window, 8 x 8 quadrature;
+      SIR and pcSIR at every h in {0.05, 0.1, 0.25, 0.5, 1}, both likelihood
+      forms timed, RMSE over R sequences of 50 frames (separable form)."""
+    import torch
+
+    import synth
+    from paper_1310_5541_amd import Config, Filter
+
+    def run(name, K_rmse, hs, reps, forms):
+        w = synth.preset(name, K=max(synth.preset(name).K, args.warmup + args.steps))
+        tr = synth.truth(w)
+        fr = torch.from_numpy(synth.frames(w, tr)).to(dev)
+        init = torch.from_numpy(synth.initial_particles(w, tr[0], w.counts())).to(dev)
+        N = int(w.counts().sum())
+        seqs = []
+        for r in range(reps):
+            wr = synth.preset(name, seed=w.seed + 1000 * (r + 1), K=K_rmse)
+            trr = synth.truth(wr)
+            seqs.append((wr, trr, torch.from_numpy(synth.frames(wr, trr)).to(dev),
+                         torch.from_numpy(synth.initial_particles(wr, trr[0], wr.counts())).to(dev)))
+
+        def cfg(wk, h, lik):
+            m = int(round(1.0 / h))
+            return Config.from_workload(wk, bins_per_px=(m, m, 1), lik_mode=lik, seed=wk.seed + 500)
+
+        def timed(sir, h, lik):
+            f = Filter(cfg(w, h, lik), init)
+            for k in range(1, args.warmup + 1):
+                f.step(fr[k - 1], k, sir=sir)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.warmup + 1, args.warmup + args.steps + 1):
+                f.step(fr[k - 1], k, sir=sir)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            f.close()
+            return el / args.steps
+
+        def rmse(sir, h):
+            out = []
+            for wr, trr, frr, ir in seqs:
+                f = Filter(cfg(wr, h, LIK_SEP), ir)
+                est = np.zeros((K_rmse, 1, wr.D))
+                for k in range(1, K_rmse + 1):
+                    f.step(frr[k - 1], k, sir=sir)
+                    est[k - 1] = f.estimate()[0]
+                f.close()
+                out.append(synth.rmse(est, trr[:K_rmse + 1], 2)[0])
+            return round(float(np.mean(out)), 4)
+
+        res = {"particles": N, "frame": [w.H, w.W], "patch": w.patch, "quad": w.quad, "steps": args.steps,
+               "rmse_sequences": reps, "rmse_frames": K_rmse, "modes": {}}
+        for h in hs:
+            for form, lik in forms:
+                for sir in (False, True):
+                    if sir and h != hs[0]:
+                        continue   # SIR does not depend on h
+                    key = ("sir" if sir else f"pcsir_h{h}") + f"_{form}"
+                    s = timed(sir, h, lik)
+                    res["modes"][key] = {"us_per_step": round(1e6 * s, 2), "particle_steps_per_s": round(N / s, 1)}
+            res["modes"][f"pcsir_h{h}_sep"]["rmse_px"] = rmse(False, h)
+            log(f"{name} h={h}: {res['modes'][f'pcsir_h{h}_sep']}")
+        res["modes"]["sir_sep"]["rmse_px"] = rmse(True, hs[0])
+        return res
+
+    out = {"single-2d-64": run("single-2d-64", 20, [0.5], args.single_reps, [("sep", LIK_SEP), ("direct", LIK_DIRECT)]),
+           "single-2d-512": run("single-2d-512", 50, [0.05, 0.1, 0.25, 0.5, 1.0], args.single_reps,
+                                [("sep", LIK_SEP), ("direct", LIK_DIRECT)])}
+    return out
 
 
 def large_object(args, dev):
@@ -293,9 +376,26 @@ def main():
     def frame(k):
         return frames[(k - 1) % frames.shape[0]]
 
+    if args.profile_train > 0:
+        # the surrogate's training kernels on random rows (counters / kernel trace)
+        n = args.profile_train * 1024
+        g = torch.Generator(device=dev)
+        g.manual_seed(3)
+        X = (0.3 * torch.randn((n, 256), generator=g, device=dev)).to(torch.bfloat16).contiguous()
+        y = (0.3 * torch.randn(n, generator=g, device=dev)).contiguous()
+        params, hist = sg.train(X, y, epochs=1)
+        print(json.dumps({"profiled_training_steps": hist["steps"], "batch": hist["batch"],
+                          "train_s": round(hist["train_s"], 3)}))
+        return
     if args.profile_steps > 0:
         # the timed region's frames: W warm-up frames, then the profiled ones
         f = make(w, init, args.h, args.lik)
+        if args.lik >= LIK_SURR_BF16:
+            # a He-initialised network (the kernels' cost does not depend on the
+            # weights); every dummy is checked at the default share, none falls back
+            th = torch.from_numpy(sg.init_params(0, w.patch ** 2 + 2 * dim + 1)).to(dev)
+            f.set_surrogate(th, [0.004, 0.004, 0.004] if args.lik == LIK_SURR_FP8 else None, args.check,
+                            float("inf"))
         f.set_graphs(not args.no_graphs)
         if args.tuning:
             f.set_tuning(**json.loads(args.tuning))
@@ -445,21 +545,31 @@ def main():
         passes = int(cnt[1]) if not sir else 0
         Llist = int(cnt[2]) if not sir else 0
         per, el_ev = {}, None
+        B_avg, L_avg = B, Llist
         if with_events:
             f.set_particles(state)
             f.set_timing(True)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
+            Bs, Ls = [], []
             for k in range(args.warmup + 1, args.warmup + args.steps + 1):
                 f.step(frame(k), k, sir=sir)
+                if not sir:
+                    # bins and list length of every frame (a read that synchronises:
+                    # it delays the next launch, not the kernels the events time)
+                    c = f.dump("counts").cpu().numpy()
+                    Bs.append(int(c[0]))
+                    Ls.append(int(c[2]))
             torch.cuda.synchronize()
             el_ev = time.perf_counter() - t2
             for name, ms in f.kernel_times():
                 per.setdefault(name, []).append(ms)
+            if Bs:
+                B_avg, L_avg = float(np.mean(Bs)), float(np.mean(Ls))
         stats = f.surrogate_stats() if lik >= LIK_SURR_BF16 else None
         f.close()
         return {"el": el, "per": {k: float(np.sum(v) / args.steps) for k, v in per.items()}, "B": B,
-                "passes": passes, "L": Llist, "el_ev": el_ev, "stats": stats}
+                "passes": passes, "L": Llist, "B_avg": B_avg, "L_avg": L_avg, "el_ev": el_ev, "stats": stats}
 
     steps = args.steps
     runs = {}
@@ -509,7 +619,7 @@ def main():
     # elements each kernel streams: particles, or entries of the distinct-key list
     units = {k: NT for k in bpp}
     for k in ("sort_hist", "sort_scatter", "seg_count", "seg_mark"):
-        units[k] = Llist
+        units[k] = head["L_avg"]   # entries of the distinct-key list, mean over the timed frames
     dom = max((k for k in k_pc if k in bpp), key=k_pc.get)
     launches = passes if dom.startswith("sort") else 1
     nb = bpp[dom] * units[dom] * launches
@@ -542,7 +652,8 @@ def main():
             "fp8": {"value": round(val["surr_fp8"], 1),
                     "ms_per_step": round(1e3 * runs["surr_fp8"]["el"] / steps, 4), "stats": runs["surr_fp8"]["stats"]},
             "inference_roofline_bf16": {"bound": "mfma", "unit": "TFLOP/s", "peak": BF16_PEAK_TFLOPS,
-                                        "achieved": round(B_pc * flops_padded / (inf_ms * 1e-3) / 1e12, 2),
+                                        "achieved": round(sb["B_avg"] * flops_padded / (inf_ms * 1e-3) / 1e12, 2),
+                                        "dummies_per_step": round(sb["B_avg"], 1),
                                         "useful_flop_per_dummy": flops, "flop_per_dummy_as_computed": flops_padded,
                                         "ms": inf_ms},
             "speedup_over_exact_direct": round(val["surr_bf16"] / val["pcsir_direct"], 3),
@@ -599,6 +710,9 @@ def main():
                      "h_by_mean_rmse_rule": h_mean_rule},
         "roofline": roof,
         "hbm_gbs_per_kernel": hbm,
+        # the binning and resampling kernels against the 8 TB/s peak (the target is 0.5)
+        "hbm_frac_binning_resampling": {k: round(v / HBM_PEAK_GBS, 3) for k, v in hbm.items()
+                                        if k in ("keys", "bin_sums", "cdf_sum", "cdf_scan", "resample")},
         "kernel_ms_per_step": {k: {n: round(v, 5) for n, v in r["per"].items()} for k, r in runs.items()},
         "sir_likelihood": sir_lik,
         "autotune": tuned or None,
@@ -606,10 +720,19 @@ def main():
         "cpu_baseline": cpu,
         "input_generation_s": round(gen_s, 2),
     }
-    if args.large_seqs > 0:
+    if h_mean_rule is not None and h_mean_rule != h_match:
+        # the operating point the mean-RMSE rule alone gives, timed the same way
+        r = timed(False, h_mean_rule, LIK_SEP, False)
+        out["matching"]["h_by_mean_rmse_rule_timed"] = {
+            "h": h_mean_rule, "value": round(NT * steps / r["el"], 1), "ms_per_step": round(1e3 * r["el"] / steps, 4),
+            "bins": r["B"], "rmse": rmse_stats.get(f"h={h_mean_rule}")}
+    if args.large_seqs > 0 or not args.no_single:
         del frames, init
         torch.cuda.empty_cache()
+    if args.large_seqs > 0:
         out["large_object"] = large_object(args, dev)
+    if not args.no_single:
+        out["single_target"] = single_target(args, dev)
     print(json.dumps(out))
 
 

@@ -59,7 +59,7 @@ pcsir_status pcsir_mlp_train_step(float *params_dev, float *adam_m_dev, float *a
  * under HIP graph capture, tight training loops, harnesses that forbid
  * hipMalloc): the same kernels and results, with the workspace taken from a
  * device array inside the library, sized for PCSIR_MLP_STATIC_MAX_BATCH rows
- * (6.4 MiB, held on every GPU the library runs on until the process ends).
+ * (8.4 MiB, held on every GPU the library runs on until the process ends).
  * No hipMalloc, hipFree or other allocation happens in the call. Returns
  * PCSIR_E_NOMEM when batch exceeds PCSIR_MLP_STATIC_MAX_BATCH, PCSIR_E_INVAL
  * for the argument errors of pcsir_mlp_train_step or when hip_stream does not
@@ -79,7 +79,8 @@ pcsir_status pcsir_mlp_forward_train_path(const float *params_dev, const uint16_
 
 /* Plain BF16 MFMA GEMM, C [M][N] (ldc) = op(A) op(B) in FP32, for tests:
  * A(m,k) = a_trans ? A[k lda + m] : A[m lda + k], B(k,n) = b_trans ? B[n ldb + k] : B[k ldb + n].
- * M, N multiples of 64, K a multiple of 32. */
+ * M, N multiples of 64, K a multiple of 32; lda and ldb multiples of 8 and A,
+ * B 16-byte aligned (E_INVAL otherwise). */
 pcsir_status pcsir_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A, int32_t lda, int32_t a_trans,
                                  const uint16_t *B, int32_t ldb, int32_t b_trans, float *C, int32_t ldc,
                                  void *hip_stream);

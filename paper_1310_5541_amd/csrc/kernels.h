@@ -1281,34 +1281,62 @@ __device__ __forceinline__ bool surr_checked(uint64_t seed, uint32_t e, int64_t 
   return u01_53(b.v[0], b.v[1]) < (double)fraction;
 }
 
-// Append e to a list where `take` holds: one ballot and one atomic per wave.
-// The list's order depends on the order of the waves' atomics; every use of
-// it is independent of that order.
-__device__ __forceinline__ void wave_append(bool take, uint32_t e, uint32_t *__restrict__ list,
-                                            uint64_t *__restrict__ count) {
+// Appends of a block to a global list, staged in LDS: lanes that take an
+// element add it to the block's buffer (one LDS atomic per wave), and the
+// buffer goes to the list with one global atomic per flush: when a further
+// round could overflow it, and at the end. A single counter that every wave
+// incremented serialised thousands of same-address atomics per frame.
+constexpr int LIST_CAP = 2048;
+struct ListStage {
+  uint32_t buf[LIST_CAP];
+  uint32_t n, base;
+};
+__device__ __forceinline__ void stage_append(ListStage &ls, bool take, uint32_t e) {
   const unsigned long long m = __ballot(take);
   if (m == 0ull) return;
   const int lane = lane_id();
+  const int first = __ffsll((long long)m) - 1;
   uint32_t base = 0;
-  if (lane == __ffsll((long long)m) - 1) base = (uint32_t)atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(m));
-  base = __shfl(base, __ffsll((long long)m) - 1, WAVE);
-  if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = e;
+  if (lane == first) base = atomicAdd(&ls.n, (uint32_t)__popcll(m));
+  base = __shfl(base, first, WAVE);
+  if (take) ls.buf[base + __popcll(m & ((1ull << lane) - 1ull))] = e;
 }
-// Dummies picked for this frame's exact check.
+// Called by every thread of the block after a barrier; flushes when the
+// buffer holds more than `keep` entries (keep = 0: whatever it holds).
+__device__ __forceinline__ void stage_flush(ListStage &ls, uint32_t keep, uint32_t *__restrict__ list,
+                                            uint64_t *__restrict__ count) {
+  const uint32_t n = ls.n;
+  if (n == 0 || n <= keep) return;
+  if (threadIdx.x == 0) ls.base = (uint32_t)atomicAdd((unsigned long long *)count, (unsigned long long)n);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) list[ls.base + i] = ls.buf[i];
+  __syncthreads();
+  if (threadIdx.x == 0) ls.n = 0;
+  __syncthreads();
+}
+
+// Dummies picked for this frame's exact check (grid-stride over the dummies;
+// the list's order depends on the order of the blocks' flushes, and every use
+// of it is independent of that order).
 __global__ __launch_bounds__(TPB) void k_surr_pick(Params p, const uint64_t *__restrict__ meta,
                                                    const StepDesc *__restrict__ desc,
                                                    const int32_t *__restrict__ seg_t, float fraction,
                                                    uint32_t *__restrict__ list, uint64_t *__restrict__ count) {
+  __shared__ ListStage ls;
+  if (threadIdx.x == 0) ls.n = 0;
+  __syncthreads();
   const uint32_t B = (uint32_t)meta[META_B];
   const int64_t k = desc->k;
   for (uint32_t e0 = blockIdx.x * TPB; e0 < B; e0 += gridDim.x * TPB) {
     const uint32_t e = e0 + threadIdx.x;
     const bool take = e < B && surr_checked(p.seed, e, k, seg_t[e], fraction);
-    wave_append(take, e, list, count);
+    stage_append(ls, take, e);
+    __syncthreads();
+    stage_flush(ls, LIST_CAP - TPB, list, count);
   }
+  __syncthreads();
+  stage_flush(ls, 0, list, count);
 }
-
-// Zero fill (a kernel, so that captured graphs hold no memset nodes).
 __global__ __launch_bounds__(TPB) void k_clear_u64(unsigned long long *__restrict__ a, uint32_t n) {
   const uint32_t i = blockIdx.x * TPB + threadIdx.x;
   if (i < n) a[i] = 0ull;
@@ -1347,12 +1375,19 @@ __global__ __launch_bounds__(TPB) void k_surr_fallback_list(const uint64_t *__re
                                                             const int32_t *__restrict__ seg_t,
                                                             const int32_t *__restrict__ tfallback,
                                                             uint32_t *__restrict__ list, uint64_t *__restrict__ count) {
+  __shared__ ListStage ls;
+  if (threadIdx.x == 0) ls.n = 0;
+  __syncthreads();
   const uint32_t B = (uint32_t)meta[META_B];
   for (uint32_t e0 = blockIdx.x * TPB; e0 < B; e0 += gridDim.x * TPB) {
     const uint32_t e = e0 + threadIdx.x;
     const bool take = e < B && tfallback[seg_t[e]] != 0;
-    wave_append(take, e, list, count);
+    stage_append(ls, take, e);
+    __syncthreads();
+    stage_flush(ls, LIST_CAP - TPB, list, count);
   }
+  __syncthreads();
+  stage_flush(ls, 0, list, count);
 }
 
 template <int DIM, bool SIR, bool SEP, int Q, int MODE = LIK_ALL>

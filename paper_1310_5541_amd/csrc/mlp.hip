@@ -22,48 +22,79 @@ constexpr int GPAD = 8;   // LDS row padding (bf16 elements)
 
 enum { EPI_FWD = 0, EPI_BWD = 1, EPI_STORE = 2 };
 
+// 8 consecutive BF16 elements of a tile row into LDS row `dst` (16 bytes).
+__device__ __forceinline__ uint4 ld16(const uint16_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+
+// Stage one GT x GK tile of op(X) into Xs[row][k], with op(X)(row, k) =
+// x_t ? X[k ld + row] : X[row ld + k]: one 16-byte load per thread (8
+// consecutive elements of the contiguous index); the transposed case
+// scatters its 8 values down a column of the tile.
+__device__ __forceinline__ uint4 stage_load(const uint16_t *X, int ld, int x_t, int r0, int k0, int tid) {
+  if (x_t) {
+    const int k = tid / (GT / 8), r8 = 8 * (tid % (GT / 8));
+    return ld16(X + (size_t)(k0 + k) * ld + r0 + r8);
+  }
+  const int r = tid / (GK / 8), k8 = 8 * (tid % (GK / 8));
+  return ld16(X + (size_t)(r0 + r) * ld + k0 + k8);
+}
+__device__ __forceinline__ void stage_store(uint16_t (*Xs)[GK + GPAD], int x_t, int tid, const uint4 &v) {
+  if (x_t) {
+    const int k = tid / (GT / 8), r8 = 8 * (tid % (GT / 8));
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      Xs[r8 + 2 * i][k] = (uint16_t)(w[i] & 0xFFFF);
+      Xs[r8 + 2 * i + 1][k] = (uint16_t)(w[i] >> 16);
+    }
+  } else {
+    const int r = tid / (GK / 8), k8 = 8 * (tid % (GK / 8));
+    *reinterpret_cast<uint4 *>(&Xs[r][k8]) = v;
+  }
+}
+
 // C = op(A) op(B), A(m,k) = a_t ? A[k lda + m] : A[m lda + k], B(k,n) = b_t ? B[n ldb + k] : B[k ldb + n],
-// BF16 inputs, FP32 accumulation. M, N multiples of 64, K a multiple of 32.
+// BF16 inputs, FP32 accumulation. M, N multiples of 64, K a multiple of 32,
+// lda and ldb multiples of 8 and 16-byte aligned operands. Block (x, y, z)
+// computes the 64 x 64 tile (y, x) over the z-th of gridDim.z equal shares
+// of K; the next k-chunk is loaded while the current one is multiplied.
 // EPI_FWD:   z = acc + bias[n]; Zout[m][n] = z; Hout[m][n] = bf16(gelu(z))
 // EPI_BWD:   Hout[m][n] = bf16(acc * gelu'(Zin[m][n]))
-// EPI_STORE: Cout[m][n] = acc
+// EPI_STORE: Cout[z M ldc + m ldc + n] = acc (the z-th partial with a K split)
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, int lda, int a_t,
                                               const uint16_t *__restrict__ B, int ldb, int b_t,
                                               const float *__restrict__ bias, const float *__restrict__ Zin,
                                               float *__restrict__ Zout, uint16_t *__restrict__ Hout,
                                               float *__restrict__ Cout, int ldc) {
+  static_assert(GT * GK / 8 == 256, "one 16-byte load per thread and operand");
   __shared__ __attribute__((aligned(16))) uint16_t As[GT][GK + GPAD];  // [m][k]
   __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GK + GPAD];  // [n][k]
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int kz = K / (int)gridDim.z, kb = kz * (int)blockIdx.z, ke = kb + kz;
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = 0; k0 < K; k0 += GK) {
-    // stage A and B chunks; the fastest-moving index follows the contiguous one in memory
-    for (int e = tid; e < GT * GK; e += 256) {
-      int m, k;
-      if (a_t) { m = e % GT; k = e / GT; }
-      else { k = e % GK; m = e / GK; }
-      As[m][k] = a_t ? A[(size_t)(k0 + k) * lda + (m0 + m)] : A[(size_t)(m0 + m) * lda + (k0 + k)];
-    }
-    for (int e = tid; e < GT * GK; e += 256) {
-      int n, k;
-      if (b_t) { k = e % GK; n = e / GK; }
-      else { n = e % GT; k = e / GT; }
-      Bs[n][k] = b_t ? B[(size_t)(n0 + n) * ldb + (k0 + k)] : B[(size_t)(k0 + k) * ldb + (n0 + n)];
-    }
+  uint4 va = stage_load(A, lda, a_t, m0, kb, tid);
+  uint4 vb = stage_load(B, ldb, !b_t, n0, kb, tid);
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+    __syncthreads();  // the previous chunk has been read
+    stage_store(As, a_t, tid, va);
+    stage_store(Bs, !b_t, tid, vb);
     __syncthreads();
+    if (k0 + GK < ke) {
+      va = stage_load(A, lda, a_t, m0, k0 + GK, tid);
+      vb = stage_load(B, ldb, !b_t, n0, k0 + GK, tid);
+    }
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 16) {
       const uint4 a = *reinterpret_cast<const uint4 *>(&As[wm + mfma_col(lane)][kk + mfma_k0(lane)]);
       const uint4 b = *reinterpret_cast<const uint4 *>(&Bs[wn + mfma_col(lane)][kk + mfma_k0(lane)]);
       acc = mfma_bf16(a, b, acc);
     }
-    __syncthreads();
   }
+  float *Cz = EPI == EPI_STORE ? Cout + (size_t)blockIdx.z * M * ldc : nullptr;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int m = m0 + wm + mfma_row(lane, r);
@@ -76,8 +107,17 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
     } else if (EPI == EPI_BWD) {
       Hout[o] = f2bf(acc[r] * gelu_grad(Zin[o]));
     } else {
-      Cout[o] = acc[r];
+      Cz[o] = acc[r];
     }
+  }
+}
+
+// out[i] = sum over the S partials part[s][i], s = 0..S-1 in order (K split).
+__global__ void k_split_sum(int n, int S, const float *__restrict__ part, float *__restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    float v = part[i];
+    for (int s = 1; s < S; ++s) v += part[(size_t)s * n + i];
+    out[i] = v;
   }
 }
 
@@ -115,14 +155,33 @@ __global__ __launch_bounds__(256) void k_head(int M, const uint16_t *__restrict_
   }
 }
 
-// out[n] = sum_m X[m][n] * (v ? v[m] : 1), FP32, fixed order (one thread per column).
-__global__ void k_colsum(int M, int N, const uint16_t *__restrict__ X, const float *__restrict__ v,
-                         float *__restrict__ out) {
+// Column sums out[n] = sum_m X[m][n] * (v ? v[m] : 1) in FP32, in a fixed
+// order: block (x, y) sums rows [128 y, 128 y + 128) of columns
+// [32 x, 32 x + 32), thread (g, c) every eighth row from g, the eight partial
+// sums then in order of g, into part[y][n]; k_colsum_fin adds the row blocks
+// in order of y.
+constexpr int CS_ROWS = 128;
+__global__ __launch_bounds__(256) void k_colsum(int M, int N, const uint16_t *__restrict__ X,
+                                                const float *__restrict__ v, float *__restrict__ part) {
+  __shared__ float lds[8][32];
+  const int c = threadIdx.x % 32, g = threadIdx.x / 32;
+  const int n = 32 * blockIdx.x + c, m0 = CS_ROWS * blockIdx.y;
+  float s = 0.0f;
+  for (int m = m0 + g; m < min(M, m0 + CS_ROWS); m += 8) s = fmaf(bf2f(X[(size_t)m * N + n]), v ? v[m] : 1.0f, s);
+  lds[g][c] = s;
+  __syncthreads();
+  if (g == 0) {
+    float t = lds[0][c];
+    for (int i = 1; i < 8; ++i) t += lds[i][c];
+    part[(size_t)blockIdx.y * N + n] = t;
+  }
+}
+__global__ void k_colsum_fin(int N, int parts, const float *__restrict__ part, float *__restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  float s = 0.0f;
-  for (int m = 0; m < M; ++m) s = fmaf(bf2f(X[(size_t)m * N + n]), v ? v[m] : 1.0f, s);
-  out[n] = s;
+  float t = part[n];
+  for (int y = 1; y < parts; ++y) t += part[(size_t)y * N + n];
+  out[n] = t;
 }
 
 __global__ void k_sum(int n, const float *__restrict__ v, float *__restrict__ out, float scale) {
@@ -148,8 +207,16 @@ __global__ void k_adam(int n, float *__restrict__ th, float *__restrict__ m, flo
 }
 
 struct TrainLayout {
-  size_t wb[3], Z[3], Hh[3], dZ[3], f, df, loss_part, total;
+  size_t wb[3], Z[3], Hh[3], dZ[3], f, df, loss_part, part, cs, total;
 };
+
+// Shares of the batch dimension for the weight-gradient GEMMs (K = batch):
+// up to 8, each a multiple of 32 rows.
+constexpr int wgrad_splits(int B) {
+  int S = 8;
+  while (S > 1 && B % (32 * S) != 0) S /= 2;
+  return S;
+}
 
 constexpr TrainLayout train_layout(int B) {
   TrainLayout L{};
@@ -166,6 +233,8 @@ constexpr TrainLayout train_layout(int B) {
   L.f = take(4 * (size_t)B);
   L.df = take(4 * (size_t)B);
   L.loss_part = take(4 * (size_t)((B + 255) / 256));
+  L.part = take(4 * (size_t)wgrad_splits(B) * MLP_H * MLP_H);
+  L.cs = take(4 * (size_t)((B + CS_ROWS - 1) / CS_ROWS) * MLP_H);
   L.total = o;
   return L;
 }
@@ -173,7 +242,7 @@ constexpr TrainLayout train_layout(int B) {
 }  // namespace
 
 // Workspace of the no-allocation training step: a file-scope device array
-// sized for the largest batch it accepts (6.4 MiB). Each GPU holds its own
+// sized for the largest batch it accepts (8.4 MiB). Each GPU holds its own
 // copy from module load until the process ends. Host code never passes the
 // array's name to a kernel: it is a host-side stand-in there, and the device
 // address comes from hipGetSymbolAddress, taken once per device.
@@ -206,9 +275,16 @@ pcsir_status scratch_address(void *stream, void **out) {
 
 template <int EPI>
 void gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int lda, int a_t, const uint16_t *B, int ldb, int b_t,
-          const float *bias, const float *Zin, float *Zout, uint16_t *Hout, float *Cout, int ldc) {
-  dim3 grid(N / GT, M / GT);
+          const float *bias, const float *Zin, float *Zout, uint16_t *Hout, float *Cout, int ldc, int splits = 1) {
+  dim3 grid(N / GT, M / GT, splits);
   k_gemm<EPI><<<grid, 256, 0, st>>>(M, N, K, A, lda, a_t, B, ldb, b_t, bias, Zin, Zout, Hout, Cout, ldc);
+}
+
+// out[n] = sum_m X[m][n] (v ? v[m] : 1) for the N = 256 columns, fixed order; part: workspace.
+void colsum(hipStream_t st, int M, const uint16_t *X, const float *v, float *part, float *out) {
+  const int parts = (M + CS_ROWS - 1) / CS_ROWS;
+  k_colsum<<<dim3(MLP_H / 32, parts), 256, 0, st>>>(M, MLP_H, X, v, part);
+  k_colsum_fin<<<1, MLP_H, 0, st>>>(MLP_H, parts, part, out);
 }
 
 // The training step of pcsir_mlp_train_step in a workspace at `ws` (device
@@ -237,13 +313,16 @@ pcsir_status train_step(float *params, float *adam_m, float *adam_v, const uint1
   if (loss_dev) k_sum<<<1, 256, 0, st>>>(hb, at32(L.loss_part), loss_dev, 1.0f / (float)M);
   // backward: output unit
   float *g = grad_dev;
-  k_colsum<<<1, 256, 0, st>>>(M, H, at16(L.Hh[2]), at32(L.df), g + MLP_OFF_W4);
+  colsum(st, M, at16(L.Hh[2]), at32(L.df), at32(L.cs), g + MLP_OFF_W4);
   k_sum<<<1, 256, 0, st>>>(M, at32(L.df), g + MLP_OFF_B4, 1.0f);
+  const int S = wgrad_splits(M);
   for (int l = 2; l >= 0; --l) {
     const uint16_t *hin = l > 0 ? at16(L.Hh[l - 1]) : X;
-    // dW_l = H_{l-1}^T dZ_l  (K = batch)
-    gemm<EPI_STORE>(st, H, H, M, hin, H, 1, at16(L.dZ[l]), H, 0, nullptr, nullptr, nullptr, nullptr, g + offW[l], H);
-    k_colsum<<<1, 256, 0, st>>>(M, H, at16(L.dZ[l]), nullptr, g + offB[l]);
+    // dW_l = H_{l-1}^T dZ_l (K = batch, in S shares whose partial products are added in order)
+    gemm<EPI_STORE>(st, H, H, M, hin, H, 1, at16(L.dZ[l]), H, 0, nullptr, nullptr, nullptr, nullptr, at32(L.part), H,
+                    S);
+    k_split_sum<<<64, 256, 0, st>>>(H * H, S, at32(L.part), g + offW[l]);
+    colsum(st, M, at16(L.dZ[l]), nullptr, at32(L.cs), g + offB[l]);
     if (l > 0) {
       // dZ_{l-1} = (dZ_l W_l^T) * gelu'(Z_{l-1})
       gemm<EPI_BWD>(st, M, H, H, at16(L.dZ[l]), H, 0, at16(L.wb[l]), H, 1, nullptr, at32(L.Z[l - 1]), nullptr,
@@ -318,6 +397,7 @@ pcsir_status pcsir_mlp_forward_train_path(const float *params, const uint16_t *X
 pcsir_status pcsir_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A, int32_t lda, int32_t a_trans,
                                  const uint16_t *B, int32_t ldb, int32_t b_trans, float *C, int32_t ldc, void *stream) {
   if (!A || !B || !C || M <= 0 || N <= 0 || K <= 0 || M % GT || N % GT || K % GK) return PCSIR_E_INVAL;
+  if (lda % 8 || ldb % 8 || ((uintptr_t)A) % 16 || ((uintptr_t)B) % 16) return PCSIR_E_INVAL;
   gemm<EPI_STORE>((hipStream_t)stream, M, N, K, A, lda, a_trans ? 1 : 0, B, ldb, b_trans ? 1 : 0, nullptr, nullptr,
                   nullptr, nullptr, C, ldc);
   const hipError_t e = hipGetLastError();

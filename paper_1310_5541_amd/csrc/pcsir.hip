@@ -376,7 +376,9 @@ void launch_surrogate(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   uint32_t *list_chk = c->at<uint32_t>(L.kA), *list_fb = c->at<uint32_t>(L.kB);
   uint64_t *meta_w = c->at<uint64_t>(L.meta);
   int32_t *tfb = c->at<int32_t>(L.tfb);
-  const uint32_t pg = grid_stride_blocks(c, c->p.NT, TPB);
+  // list kernels: about two workgroups per compute unit, each flushing its
+  // staged list once or a few times
+  const uint32_t pg = std::min(grid_stride_blocks(c, c->p.NT, TPB), 2u * (uint32_t)c->num_cus);
   SurrCheck chk;
   chk.fraction = c->surr_fraction;
   chk.tol = c->surr_tol;

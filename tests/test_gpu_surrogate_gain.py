@@ -2,8 +2,8 @@
 workload: a network trained on the GPU (the library's BF16 MFMA training
 kernels) from rows that exact pcSIR produces on separate training sequences
 replaces the per-sub-sample likelihood of the dummies (Eq. likelihood with
-8 x 8 sub-pixel quadrature) in pcSIR. On a test sequence of 250 targets at
-the batched workload's spot density, the surrogate's tracking RMSE must stay
+8 x 8 sub-pixel quadrature) in pcSIR. On two test sequences of 250 targets
+at the batched workload's spot density (per-target RMSE pooled), the surrogate's tracking RMSE must stay
 within 5% of exact pcSIR's by the rule the benchmark matches operating points
 with: the median per-target RMSE within 5%, and the share of lost targets
 (RMSE above 2 px) at most 2 points above exact's (where spots cross, a track
@@ -62,12 +62,12 @@ def test_trained_surrogate_tracks_like_exact_pcsir():
 
     from paper_1310_5541_amd import surrogate as sg
     dev = torch.device("cuda:0")
-    # training rows: exact pcSIR dummies of two training sequences
-    cap = 1_000_000
+    # training rows: exact pcSIR dummies of training sequences (seeds apart from the test)
+    cap = 1_500_000
     X = torch.empty((cap, 256), dtype=torch.bfloat16, device=dev)
     y = torch.empty(cap, dtype=torch.float32, device=dev)
     n = 0
-    for s in range(4):
+    for s in range(8):
         if n >= cap:
             break
         wt = synth.preset("train-2d-512", K=20, seed=7000 + 100 * s)
@@ -77,20 +77,27 @@ def test_trained_surrogate_tracks_like_exact_pcsir():
         f = _filter(wt, it, 1)
         n = sg.rows(f, frt, 1, wt.K, cap, X, y, start=n)
         f.close()
-    params, hist = sg.train(X[:n], y[:n], epochs=8)
+    params, hist = sg.train(X[:n], y[:n], epochs=12)
     log(f"case surrogate_gain: {n} rows, rms per epoch (nats) "
         f"{[round(float(np.sqrt(m)) * 100, 3) for m in hist['mse_per_epoch']]}, {hist['train_s']:.1f} s")
-    # test sequence: 250 targets in the central 412^2 of 512^2 frames, other seeds
-    w = synth.preset("train-2d-512", K=20, seed=9100)
-    tr = synth.truth(w)
-    fr = torch.from_numpy(synth.frames(w, tr)).to(dev)
-    init = torch.from_numpy(synth.initial_particles(w, tr[0], w.counts())).to(dev)
-    r_ex, ms_ex, _ = _track(w, tr, fr, init, 0)
-    r_sg, ms_sg, st = _track(w, tr, fr, init, 2, params)
+    # test sequences: 250 targets each in the central 412^2 of 512^2 frames, other seeds
+    r_ex, r_sg, ms_ex, ms_sg, st = [], [], 0.0, 0.0, None
+    for seed in (9100, 9200):
+        w = synth.preset("train-2d-512", K=20, seed=seed)
+        tr = synth.truth(w)
+        fr = torch.from_numpy(synth.frames(w, tr)).to(dev)
+        init = torch.from_numpy(synth.initial_particles(w, tr[0], w.counts())).to(dev)
+        a, t_ex, _ = _track(w, tr, fr, init, 0)
+        b, t_sg, st = _track(w, tr, fr, init, 2, params)
+        r_ex.append(a)
+        r_sg.append(b)
+        ms_ex += t_ex / 2
+        ms_sg += t_sg / 2
+    r_ex, r_sg = np.concatenate(r_ex), np.concatenate(r_sg)
     log(f"  exact (per sub-sample): mean {r_ex.mean():.4f} median {np.median(r_ex):.4f} px, {ms_ex:.3f} ms/step")
     log(f"  surrogate BF16:         mean {r_sg.mean():.4f} median {np.median(r_sg):.4f} px, {ms_sg:.3f} ms/step; "
         f"checks, fallbacks, max error {st}")
     lost_ex, lost_sg = int(np.sum(r_ex > 2.0)), int(np.sum(r_sg > 2.0))
     log(f"  lost targets: exact {lost_ex}, surrogate {lost_sg}; time ratio exact / surrogate {ms_ex / ms_sg:.2f}")
     assert np.median(r_sg) <= 1.05 * np.median(r_ex)
-    assert lost_sg <= lost_ex + 0.02 * w.T
+    assert lost_sg <= lost_ex + 0.02 * r_ex.size
