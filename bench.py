@@ -97,8 +97,8 @@ def bytes_per_particle(D: int) -> dict:
     return {
         "propagate": 4 * D + 4 + 4 * D,   # parent state + ancestor index in, new state out
         "keys": 4 * 2,                     # x, y in (3D: + z); distinct keys out (per list entry, small)
-        "sort_hist": 4,                    # per list entry: key in
-        "sort_scatter": 4 + 4,             # per list entry: key in, key out
+        "sort_hist": 4,                    # per list entry and pass: key in
+        "sort_scatter": 4 + 4,             # per list entry and pass: key in, key out
         "seg_count": 4,                    # per list entry: sorted key in
         "seg_mark": 4,                     # per list entry: sorted key in
         "bin_sums": 4 * D + 4,             # state in (key recomputed), bin number out

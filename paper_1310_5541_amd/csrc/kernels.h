@@ -40,9 +40,54 @@ enum {
   META_L = 9,         // length of this frame's list of distinct (tile, cell) keys
   META_NCHK = 10,     // surrogate: dummies picked for the exact check this frame
   META_NFB = 11,      // surrogate: dummies of fallback targets this frame
-  META_N = 12
+  // arrival counters of kernels whose last workgroup finishes a reduction of
+  // all workgroups' results (back to 0 at the end of every launch)
+  META_ARRIVE_BBOX = 12, META_ARRIVE_KEYS = 13, META_ARRIVE_SEG = 14,
+  META_N = 15
 };
+
+// Values one workgroup hands to another within a launch go through memory,
+// not through the XCD's own L2 (which the other workgroup's XCD does not
+// see): an agent-scope store writes through, and once the storing thread's
+// memory counter has drained (stores_done) the value is visible to an
+// agent-scope load on any XCD. Only the handed-over values take this path;
+// an agent-scope fence instead would write back the XCD's whole L2.
+template <typename T>
+__device__ __forceinline__ void store_agent(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T load_agent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stores_done() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Whether this workgroup is the last of its launch to get here: true in
+// exactly one workgroup, which may then read with load_agent what every
+// workgroup stored with store_agent before its call (the storing threads
+// call stores_done first; the workgroup's count follows its barrier). Every
+// workgroup calls it once, with all its threads; the last one resets the
+// counter for the next launch. This fuses a reduction over all workgroups
+// into the kernel that produces its inputs, instead of a separate
+// one-workgroup launch.
+__device__ __forceinline__ bool last_block(uint64_t *counter) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long n =
+        __hip_atomic_fetch_add((unsigned long long *)counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = n + 1ull == (unsigned long long)gridDim.x * gridDim.y * gridDim.z;
+    if (last) store_agent((unsigned long long *)counter, 0ull);
+  }
+  __syncthreads();
+  return last != 0;
+}
 constexpr int MAX_DIGIT_BITS = 11;  // radix digit of at most 2048 buckets (LDS histogram)
+constexpr int MIN_DIGIT_BITS = 6;
 constexpr int MAX_BUCKETS = 1 << MAX_DIGIT_BITS;
 
 struct Params {
@@ -234,6 +279,43 @@ __device__ __forceinline__ int32_t adaptive_m(double s1, double s2, double n, do
   return mc < 1.0 ? 1 : (int32_t)mc;
 }
 
+// Exclusive scan of the per-target cell ranges -> compacted key bases, the
+// total range, and the radix digit width and number of sort passes it needs;
+// also resets the length of the frame's key list. Run by one workgroup of TPB
+// threads: the last one of k_bbox_reduce.
+__device__ __forceinline__ void bbox_scan(int T, const unsigned long long *__restrict__ range,
+                                          uint32_t *__restrict__ kbase, uint64_t *__restrict__ meta, int max_bits) {
+  __shared__ unsigned long long lds[TPB / WAVE];
+  unsigned long long carry = 0;
+  for (int t0 = 0; t0 < T; t0 += TPB) {
+    const int t = t0 + threadIdx.x;
+    const unsigned long long r = t < T ? load_agent(&range[t]) : 0ull;
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan<TPB, unsigned long long>(r, lds, &tot);
+    if (t < T) kbase[t] = (uint32_t)(carry + ex);
+    carry += tot;
+    if (carry > (1ull << 40)) carry = (1ull << 40);
+  }
+  if (threadIdx.x == 0) {
+    kbase[T] = (uint32_t)carry;
+    meta[META_RANGE] = carry;
+    int bits = 0;
+    if (carry > 1) bits = 64 - __clzll((long long)(carry - 1));
+    if (carry > 0xFFFFFFFFull) {
+      meta[META_ERR] |= ERR_KEY_RANGE;
+      bits = 32;
+    }
+    // fewest passes of at most max_bits bits, digits as narrow as that allows
+    const int passes = (bits + max_bits - 1) / max_bits;
+    const int width = passes ? (bits + passes - 1) / passes : 1;
+    meta[META_PASSES] = (uint64_t)passes;
+    meta[META_DIGIT] = (uint64_t)width;
+    meta[META_L] = 0;
+    meta[META_NCHK] = 0;
+    meta[META_NFB] = 0;
+  }
+}
+
 // Per-target cells per pixel and cell range from the propagate tiles' partial
 // extremes (tiles of target t: t256_first[t] .. t256_first[t+1]-1). One
 // block per target.
@@ -243,7 +325,8 @@ __global__ __launch_bounds__(TPB) void k_bbox_reduce(Params p, const uint32_t *_
                                                      const double *__restrict__ mom_part, int32_t *__restrict__ tm,
                                                      int32_t *__restrict__ bbox_cur,
                                                      unsigned long long *__restrict__ range,
-                                                     int32_t *__restrict__ tfallback) {
+                                                     int32_t *__restrict__ tfallback, uint32_t *__restrict__ kbase,
+                                                     uint64_t *__restrict__ meta, int max_bits) {
   __shared__ float redf[TPB / WAVE];
   __shared__ double redd[TPB / WAVE];
   const int t = blockIdx.x;
@@ -286,46 +369,11 @@ __global__ __launch_bounds__(TPB) void k_bbox_reduce(Params p, const uint32_t *_
     if (r > (1ull << 40)) r = (1ull << 40);
   }
   if (threadIdx.x == 0) {
-    range[t] = r;
+    store_agent(&range[t], r);
+    stores_done();
     tfallback[t] = 0;
   }
-}
-
-// Exclusive scan of the per-target cell ranges -> compacted key bases, the
-// total range, and the radix digit width and number of sort passes it needs;
-// also resets the length of the frame's key list. One block.
-__global__ __launch_bounds__(TPB) void k_bbox_scan(int T, const unsigned long long *__restrict__ range,
-                                                   uint32_t *__restrict__ kbase, uint64_t *__restrict__ meta,
-                                                   int max_bits) {
-  __shared__ unsigned long long lds[TPB / WAVE];
-  unsigned long long carry = 0;
-  for (int t0 = 0; t0 < T; t0 += TPB) {
-    const int t = t0 + threadIdx.x;
-    const unsigned long long r = t < T ? range[t] : 0ull;
-    unsigned long long tot;
-    const unsigned long long ex = block_excl_scan<TPB, unsigned long long>(r, lds, &tot);
-    if (t < T) kbase[t] = (uint32_t)(carry + ex);
-    carry += tot;
-    if (carry > (1ull << 40)) carry = (1ull << 40);
-  }
-  if (threadIdx.x == 0) {
-    kbase[T] = (uint32_t)carry;
-    meta[META_RANGE] = carry;
-    int bits = 0;
-    if (carry > 1) bits = 64 - __clzll((long long)(carry - 1));
-    if (carry > 0xFFFFFFFFull) {
-      meta[META_ERR] |= ERR_KEY_RANGE;
-      bits = 32;
-    }
-    // fewest passes of at most max_bits bits, digits as narrow as that allows
-    const int passes = (bits + max_bits - 1) / max_bits;
-    const int width = passes ? (bits + passes - 1) / passes : 1;
-    meta[META_PASSES] = (uint64_t)passes;
-    meta[META_DIGIT] = (uint64_t)width;
-    meta[META_L] = 0;
-    meta[META_NCHK] = 0;
-    meta[META_NFB] = 0;
-  }
+  if (last_block(&meta[META_ARRIVE_BBOX])) bbox_scan(p.T, range, kbase, meta, max_bits);
 }
 
 template <int DIM>
@@ -353,9 +401,9 @@ __device__ __forceinline__ uint32_t particle_key(const float *__restrict__ s, ui
 // fewer tiles, so the list to sort is shorter. A tile has at most as many
 // distinct keys as particles, so it writes them into its own particle range
 // of `sparse` (global index of its first particle on), and its count to
-// tcount[tile]; k_list_offsets and k_list_compact then pack the tiles' keys
-// into one list, in tile order, without atomics. The list holds every
-// occupied cell at least once.
+// tcount[tile]; the last workgroup turns the counts into offsets, and
+// k_list_compact packs the tiles' keys into one list, in tile order, without
+// atomics. The list holds every occupied cell at least once.
 constexpr int DEDUP_LOG2 = 14;
 constexpr int DEDUP_SLOTS = 2 * KEYS_TILE;
 constexpr int DEDUP_SHIFT = 32 - DEDUP_LOG2;
@@ -366,10 +414,11 @@ template <int DIM>
 __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__restrict__ tiles,
                                               const uint32_t *__restrict__ off, const float *__restrict__ s,
                                               const int32_t *__restrict__ bbox_cur, const uint32_t *__restrict__ kbase,
-                                              uint32_t *__restrict__ sparse, uint32_t *__restrict__ tcount) {
+                                              uint32_t *__restrict__ sparse, uint32_t *__restrict__ tcount,
+                                              uint64_t *__restrict__ meta) {
   constexpr int R = KEYS_TILE / KEYS_TPB;  // all of a thread's positions are loaded before use
   constexpr int PER = DEDUP_SLOTS / KEYS_TPB;
-  __shared__ uint32_t tab[DEDUP_SLOTS];
+  __shared__ __attribute__((aligned(16))) uint32_t tab[DEDUP_SLOTS];
   __shared__ uint32_t lds[KEYS_TPB / WAVE];
   const BinTile tl = tiles[blockIdx.x];
   const int t = tl.t;
@@ -378,7 +427,8 @@ __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__re
 #pragma unroll
   for (int a = 0; a < 6; ++a) bb[a] = bbox_cur[t * 6 + a];
   const uint32_t kb = kbase[t];
-  for (int i = threadIdx.x; i < DEDUP_SLOTS; i += KEYS_TPB) tab[i] = KEY_EMPTY;
+  for (int i = threadIdx.x; i < DEDUP_SLOTS / 4; i += KEYS_TPB)
+    reinterpret_cast<uint4 *>(tab)[i] = make_uint4(KEY_EMPTY, KEY_EMPTY, KEY_EMPTY, KEY_EMPTY);
   __syncthreads();
   for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * KEYS_TPB) {
     // all positions loaded first, from clamped indices (a load under a bounds
@@ -420,34 +470,42 @@ __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__re
     }
   }
   __syncthreads();
-  // thread t reads slots t, t + KEYS_TPB, ...: consecutive lanes, consecutive banks
+  // thread t reads 16-byte groups t, t + KEYS_TPB, ... of slots (consecutive
+  // lanes, consecutive banks), once, and keeps them for the write
+  uint4 sl[PER / 4];
   uint32_t c = 0;
 #pragma unroll
-  for (int j = 0; j < PER; ++j) c += tab[j * KEYS_TPB + threadIdx.x] != KEY_EMPTY ? 1u : 0u;
+  for (int j = 0; j < PER / 4; ++j) {
+    sl[j] = reinterpret_cast<const uint4 *>(tab)[j * KEYS_TPB + threadIdx.x];
+    c += (sl[j].x != KEY_EMPTY) + (sl[j].y != KEY_EMPTY) + (sl[j].z != KEY_EMPTY) + (sl[j].w != KEY_EMPTY);
+  }
   uint32_t tot;
   uint32_t o = base + tl.i0 + block_excl_scan<KEYS_TPB, uint32_t>(c, lds, &tot);
-  if (threadIdx.x == 0) tcount[blockIdx.x] = tot;
+  if (threadIdx.x == 0) {
+    store_agent(&tcount[blockIdx.x], tot);
+    stores_done();
+  }
 #pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const uint32_t v = tab[j * KEYS_TPB + threadIdx.x];
-    if (v != KEY_EMPTY) sparse[o++] = v;
+  for (int j = 0; j < PER / 4; ++j) {
+    if (sl[j].x != KEY_EMPTY) sparse[o++] = sl[j].x;
+    if (sl[j].y != KEY_EMPTY) sparse[o++] = sl[j].y;
+    if (sl[j].z != KEY_EMPTY) sparse[o++] = sl[j].z;
+    if (sl[j].w != KEY_EMPTY) sparse[o++] = sl[j].w;
   }
-}
-
-// Exclusive scan of the tiles' key counts (one block); meta[META_L] = total.
-__global__ __launch_bounds__(TPB) void k_list_offsets(uint32_t ntiles, uint32_t *__restrict__ tcount,
-                                                      uint64_t *__restrict__ meta) {
-  __shared__ uint32_t lds[TPB / WAVE];
-  uint32_t carry = 0;
-  for (uint32_t b0 = 0; b0 < ntiles; b0 += TPB) {
-    const uint32_t b = b0 + threadIdx.x;
-    const uint32_t v = b < ntiles ? tcount[b] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<TPB, uint32_t>(v, lds, &tot);
-    if (b < ntiles) tcount[b] = carry + ex;  // becomes the tile's offset in the list
-    carry += tot;
+  // the last workgroup turns the tiles' key counts into their offsets in the
+  // packed list (exclusive scan, in tile order) and sets the list's length
+  if (last_block(&meta[META_ARRIVE_KEYS])) {
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < gridDim.x; b0 += KEYS_TPB) {
+      const uint32_t b = b0 + threadIdx.x;
+      const uint32_t v = b < gridDim.x ? load_agent(&tcount[b]) : 0u;
+      uint32_t t2;
+      const uint32_t ex = block_excl_scan<KEYS_TPB, uint32_t>(v, lds, &t2);
+      if (b < gridDim.x) tcount[b] = carry + ex;
+      carry += t2;
+    }
+    if (threadIdx.x == 0) meta[META_L] = carry;
   }
-  if (threadIdx.x == 0) meta[META_L] = carry;
 }
 
 // Pack each tile's keys to its offset in the list (one block per tile).
@@ -486,8 +544,16 @@ __device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d
   return peers;
 }
 
-// Per-block digit histograms of pass `pass`; the digit width comes from the
-// device (meta[META_DIGIT]) and the pass runs only if the key range needs it.
+// Each pass: per-workgroup digit counts (k_sort_hist), their scan per digit
+// across workgroups (k_sort_scan), and the stable scatter (k_sort_scatter).
+// A workgroup takes its share of the list in rounds of SORT_ITEMS keys per
+// thread, all loaded before use.
+constexpr int SORT_ITEMS = 8;
+
+// Per-block digit histograms of pass `pass` over that pass's input order (the
+// scatter ranks each block's share of its own input, so the counts must come
+// from the same keys in the same order); the digit width comes from the device
+// (meta[META_DIGIT]) and the pass runs only if the key range needs it.
 __global__ __launch_bounds__(TPB) void k_sort_hist(int pass, const uint32_t *__restrict__ key,
                                                    uint32_t *__restrict__ hist, uint32_t G,
                                                    const uint64_t *__restrict__ meta) {
@@ -501,12 +567,20 @@ __global__ __launch_bounds__(TPB) void k_sort_hist(int pass, const uint32_t *__r
   list_range((uint32_t)meta[META_L], G, blockIdx.x, j0, j1);
   const int sh = width * pass;
   const unsigned long long below = (1ull << lane_id()) - 1ull;
-  for (uint32_t r0 = j0; r0 < j1; r0 += TPB) {
-    const uint32_t j = r0 + threadIdx.x;
-    const bool valid = j < j1;
-    const uint32_t d = valid ? (key[j] >> sh) & mask : (uint32_t)MAX_BUCKETS;
-    const unsigned long long peers = digit_peers(valid, d, width);
-    if (valid && (peers & below) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+  for (uint32_t r0 = j0; r0 < j1; r0 += SORT_ITEMS * TPB) {
+    uint32_t kk[SORT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+      const uint32_t j = r0 + i * TPB + threadIdx.x;
+      kk[i] = j < j1 ? key[j] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+      const bool valid = r0 + i * TPB + threadIdx.x < j1;
+      const uint32_t d = valid ? (kk[i] >> sh) & mask : (uint32_t)MAX_BUCKETS;
+      const unsigned long long peers = digit_peers(valid, d, width);
+      if (valid && (peers & below) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+    }
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < nb; d += TPB) hist[(size_t)d * G + blockIdx.x] = cnt[d];
@@ -532,10 +606,12 @@ __global__ __launch_bounds__(TPB) void k_sort_scan(int pass, uint32_t *__restric
   if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
-// Stable scatter of pass `pass`: slots in (round, wave, lane) order; within a
-// round each wave ranks its lanes by digit with ballots, waves are ordered
-// through per-wave digit counts in LDS, and a per-digit running offset
-// carries the order across rounds.
+// Stable scatter of pass `pass`: slots in (round, item, wave, lane) order,
+// where an item is TPB consecutive keys of the list; within an item each wave
+// ranks its lanes by digit with ballots, waves are ordered through per-wave
+// digit counts in LDS, and a per-digit running offset carries the order
+// across items. Item i's per-wave counts use wcnt[i & 1], which item i clears
+// after its slots are taken and item i + 2 refills (two barriers per item).
 __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, const uint32_t *__restrict__ key_in,
                                                       uint32_t *__restrict__ key_out,
                                                       const uint32_t *__restrict__ hist, uint32_t G,
@@ -546,7 +622,7 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, const uint32_t *
   const uint32_t nb = 1u << width, mask = nb - 1u;
   constexpr int PER = MAX_BUCKETS / TPB;
   __shared__ uint32_t run[MAX_BUCKETS];
-  __shared__ uint32_t wcnt[TPB / WAVE][MAX_BUCKETS];
+  __shared__ uint32_t wcnt[2][TPB / WAVE][MAX_BUCKETS];
   __shared__ uint32_t lds[TPB / WAVE];
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
   {
@@ -565,7 +641,7 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, const uint32_t *
       const uint32_t d = (uint32_t)(tid * PER + i);
       if (d < nb) run[d] = ex + hist[(size_t)d * G + blockIdx.x];
       ex += loc[i];
-      for (int ww = 0; ww < TPB / WAVE; ++ww) wcnt[ww][d] = 0;
+      for (int ww = 0; ww < TPB / WAVE; ++ww) wcnt[0][ww][d] = wcnt[1][ww][d] = 0;
     }
   }
   __syncthreads();
@@ -573,37 +649,40 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(int pass, const uint32_t *
   list_range((uint32_t)meta[META_L], G, blockIdx.x, j0, j1);
   const int sh = width * pass;
   const unsigned long long below = (1ull << lane) - 1ull;
-  for (uint32_t r0 = j0; r0 < j1; r0 += TPB) {
-    const uint32_t j = r0 + tid;
-    const bool valid = j < j1;
-    uint32_t kk = 0, d = (uint32_t)MAX_BUCKETS;
-    if (valid) {
-      kk = key_in[j];
-      d = (kk >> sh) & mask;
+  int par = 0;
+  for (uint32_t r0 = j0; r0 < j1; r0 += SORT_ITEMS * TPB) {
+    uint32_t kk[SORT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+      const uint32_t j = r0 + i * TPB + tid;
+      kk[i] = j < j1 ? key_in[j] : 0u;
     }
-    const unsigned long long peers = digit_peers(valid, d, width);
-    const uint32_t rank = (uint32_t)__popcll(peers & below);
-    const bool leader = valid && rank == 0;
-    const uint32_t cnt = (uint32_t)__popcll(peers);
-    if (leader) wcnt[w][d] = cnt;
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[d] + rank;
-      for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][d];
-      key_out[pos] = kk;
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+      if (r0 + i * TPB >= j1) break;  // the same for the whole workgroup
+      const bool valid = r0 + i * TPB + tid < j1;
+      const uint32_t d = valid ? (kk[i] >> sh) & mask : (uint32_t)MAX_BUCKETS;
+      const unsigned long long peers = digit_peers(valid, d, width);
+      const uint32_t rank = (uint32_t)__popcll(peers & below);
+      const bool leader = valid && rank == 0;
+      const uint32_t cnt = (uint32_t)__popcll(peers);
+      if (leader) wcnt[par][w][d] = cnt;
+      __syncthreads();
+      if (valid) {
+        uint32_t pos = run[d] + rank;
+        for (int ww = 0; ww < w; ++ww) pos += wcnt[par][ww][d];
+        key_out[pos] = kk[i];
+      }
+      __syncthreads();
+      if (leader) {
+        atomicAdd(&run[d], cnt);
+        wcnt[par][w][d] = 0;
+      }
+      par ^= 1;
     }
-    __syncthreads();
-    if (leader) {
-      atomicAdd(&run[d], cnt);
-      wcnt[w][d] = 0;
-    }
-    __syncthreads();
   }
 }
 
-// Sorted buffers chosen on the device from the number of passes that ran.
-// Only keys are sorted: a bin needs nothing but its key; the members' sums
-// are formed afterwards in storage order (k_bin_sums).
 struct SortBufs {
   const uint32_t *key_store;  // the unsorted list (0 passes: a single key value)
   const uint32_t *kA, *kB;
@@ -620,8 +699,11 @@ __device__ __forceinline__ bool seg_head(const uint32_t *__restrict__ K, uint32_
   return j == 0 || K[j] != K[j - 1];
 }
 
-__global__ __launch_bounds__(TPB) void k_seg_count(uint32_t G, SortBufs sb, const uint64_t *__restrict__ meta,
-                                                   uint32_t *__restrict__ chunk_heads) {
+// Per-block head counts; the last workgroup scans them (exclusive, in block
+// order) into each block's first bin and writes the bin count B.
+__global__ __launch_bounds__(TPB) void k_seg_count(uint32_t G, int T, SortBufs sb, uint64_t *__restrict__ meta,
+                                                   uint32_t *__restrict__ chunk_heads,
+                                                   uint32_t *__restrict__ seg_first) {
   __shared__ uint32_t lds[TPB / WAVE];
   const uint32_t *K = sorted_keys(sb, meta[META_PASSES]);
   uint32_t j0, j1;
@@ -630,17 +712,15 @@ __global__ __launch_bounds__(TPB) void k_seg_count(uint32_t G, SortBufs sb, cons
   for (uint32_t j = j0 + threadIdx.x; j < j1; j += TPB)
     if (seg_head(K, j)) ++c;
   const uint32_t s = block_sum<TPB, uint32_t>(c, lds);
-  if (threadIdx.x == 0) chunk_heads[blockIdx.x] = s;
-}
-
-// Exclusive scan of chunk head counts (one block); writes the bin count B.
-__global__ __launch_bounds__(TPB) void k_seg_scan(int T, uint32_t *__restrict__ chunk_heads, uint32_t G,
-                                                  uint64_t *__restrict__ meta, uint32_t *__restrict__ seg_first) {
-  __shared__ uint32_t lds[TPB / WAVE];
+  if (threadIdx.x == 0) {
+    store_agent(&chunk_heads[blockIdx.x], s);
+    stores_done();
+  }
+  if (!last_block(&meta[META_ARRIVE_SEG])) return;
   uint32_t carry = 0;
   for (uint32_t b0 = 0; b0 < G; b0 += TPB) {
     const uint32_t b = b0 + threadIdx.x;
-    const uint32_t v = b < G ? chunk_heads[b] : 0u;
+    const uint32_t v = b < G ? load_agent(&chunk_heads[b]) : 0u;
     uint32_t tot;
     const uint32_t ex = block_excl_scan<TPB, uint32_t>(v, lds, &tot);
     if (b < G) chunk_heads[b] = carry + ex;
@@ -649,8 +729,11 @@ __global__ __launch_bounds__(TPB) void k_seg_scan(int T, uint32_t *__restrict__ 
   if (threadIdx.x == 0) {
     meta[META_B] = carry;
     meta[META_DIRTY] = carry;  // accumulators [0, B) are written this frame
-    seg_first[T] = carry;
   }
+  // an empty list has no bins: every target's first bin is 0 (k_seg_mark
+  // writes seg_first otherwise)
+  if (carry == 0)
+    for (int t = threadIdx.x; t <= T; t += TPB) seg_first[t] = 0;
 }
 
 template <int DIM>
@@ -691,12 +774,19 @@ __device__ __forceinline__ int key_target(uint32_t key, int T, KB kbase) {
 // Targets whose key bases k_seg_mark stages in LDS for its searches.
 constexpr int KBASE_LDS = 4096;
 
-// Record every bin: its key and its target.
-__global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs sb, const uint64_t *__restrict__ meta,
+// Record every bin: its key and its target, and every target's first bin:
+// seg_first[t] is the first bin whose key is >= kbase[t] (bins are sorted by
+// key and targets own consecutive key ranges), seg_first[T] = B. A bin whose
+// target tb differs from that of the bin before it (target tp, or -1 for the
+// first bin) is the first bin of every target in (tp, tb], so it writes those
+// entries, and the list's last key writes B into those after its target:
+// every entry is written once, with no search over the bins. (B = 0 is
+// handled by k_seg_count.)
+__global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs sb, uint64_t *__restrict__ meta,
                                                   const uint32_t *__restrict__ chunk_base,
                                                   const uint32_t *__restrict__ kbase, uint32_t *__restrict__ seg_key,
                                                   int32_t *__restrict__ seg_t, uint32_t *__restrict__ lut,
-                                                  uint64_t lut_cap) {
+                                                  uint64_t lut_cap, uint32_t *__restrict__ seg_first) {
   const bool use_lut = meta[META_RANGE] <= lut_cap;
   __shared__ uint32_t lds[TPB / WAVE];
   __shared__ uint32_t kb_lds[KBASE_LDS];
@@ -705,8 +795,9 @@ __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs
     for (int t = threadIdx.x; t < p.T; t += TPB) kb_lds[t] = kbase[t];
   __syncthreads();
   const uint32_t *K = sorted_keys(sb, meta[META_PASSES]);
+  const uint32_t L = (uint32_t)meta[META_L];
   uint32_t j0, j1;
-  list_range((uint32_t)meta[META_L], G, blockIdx.x, j0, j1);
+  list_range(L, G, blockIdx.x, j0, j1);
   uint32_t heads = chunk_base[blockIdx.x];
   for (uint32_t r0 = j0; r0 < j1; r0 += TPB) {
     const uint32_t j = r0 + threadIdx.x;
@@ -715,35 +806,25 @@ __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs
     const uint32_t ex = block_excl_scan<TPB, uint32_t>(h ? 1u : 0u, lds, &tot);
     if (h) {
       const uint32_t kj = K[j];
+      const int tb = kb_in_lds ? key_target(kj, p.T, (const uint32_t *)kb_lds) : key_target(kj, p.T, kbase);
       seg_key[heads + ex] = kj;
-      seg_t[heads + ex] = kb_in_lds ? key_target(kj, p.T, (const uint32_t *)kb_lds) : key_target(kj, p.T, kbase);
+      seg_t[heads + ex] = tb;
       if (use_lut) lut[kj] = heads + ex;  // bin of every occupied cell key
+      // previous bin's target: below tb only if its key is below tb's base
+      int tp = tb;
+      if (j == 0) tp = -1;
+      else if (K[j - 1] < kbase[tb])
+        tp = kb_in_lds ? key_target(K[j - 1], p.T, (const uint32_t *)kb_lds) : key_target(K[j - 1], p.T, kbase);
+      for (int t = tp + 1; t <= tb; ++t) seg_first[t] = heads + ex;
+    }
+    if (j + 1 == L && j < j1) {
+      const uint32_t kl = K[j];
+      const int tl = kb_in_lds ? key_target(kl, p.T, (const uint32_t *)kb_lds) : key_target(kl, p.T, kbase);
+      const uint32_t B = (uint32_t)meta[META_B];
+      for (int t = tl + 1; t <= p.T; ++t) seg_first[t] = B;
     }
     heads += tot;
   }
-}
-
-// First bin of every target: the first bin whose key is >= the target's key
-// base (bins are sorted by key and targets own consecutive key ranges);
-// seg_first[T] = B. Defined for every target whatever the keys hold.
-__global__ __launch_bounds__(TPB) void k_seg_first(int T, const uint32_t *__restrict__ kbase,
-                                                   const uint32_t *__restrict__ seg_key,
-                                                   const uint64_t *__restrict__ meta, uint32_t *__restrict__ seg_first) {
-  const int t = blockIdx.x * TPB + threadIdx.x;
-  if (t > T) return;
-  const uint32_t B = (uint32_t)meta[META_B];
-  if (t == T) {
-    seg_first[T] = B;
-    return;
-  }
-  const uint32_t kb = kbase[t];
-  uint32_t lo = 0, hi = B;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (seg_key[mid] < kb) lo = mid + 1;
-    else hi = mid;
-  }
-  seg_first[t] = lo;
 }
 
 // Members' sums of every bin as exact fixed-point integers: count, offsets of

@@ -85,7 +85,6 @@ bool valid_config(const pcsir_config *c, std::string *why) {
 }
 
 constexpr int BIN_TILE_MIN = 1024, BIN_TILE_MAX = BIN_TILES * SCAN_TILE;
-constexpr int DIGIT_BITS_MIN = 6;
 
 void build_bin_tiles(const pcsir_config *c, uint32_t tile, std::vector<BinTile> &tB) {
   tB.clear();
@@ -426,14 +425,13 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   mark(c, "bbox");
   k_bbox_reduce<<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.t256_first), off, c->at<float>(L.bbox_part),
                                      c->at<double>(L.mom_part), c->at<int32_t>(L.tm), c->at<int32_t>(L.bbox_cur),
-                                     c->at<unsigned long long>(L.range), c->at<int32_t>(L.tfb));
-  k_bbox_scan<<<1, TPB, 0, st>>>(p.T, c->at<unsigned long long>(L.range), c->at<uint32_t>(L.kbase), meta,
-                                 c->tune.digit_bits);
+                                     c->at<unsigned long long>(L.range), c->at<int32_t>(L.tfb),
+                                     c->at<uint32_t>(L.kbase), meta, c->tune.digit_bits);
   mark(c, "keys");
   // distinct keys per tile into the tile's own range of kA, then packed into key (the sort's input)
   k_keys<DIM><<<L.nK, KEYS_TPB, 0, st>>>(p, c->at<BinTile>(L.tilesK), off, sout, c->at<int32_t>(L.bbox_cur),
-                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.kA), c->at<uint32_t>(L.tcount));
-  k_list_offsets<<<1, TPB, 0, st>>>(L.nK, c->at<uint32_t>(L.tcount), meta);
+                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.kA), c->at<uint32_t>(L.tcount),
+                                         meta);
   k_list_compact<<<L.nK, TPB, 0, st>>>(c->at<BinTile>(L.tilesK), off, c->at<uint32_t>(L.tcount), L.nK, meta,
                                         c->at<uint32_t>(L.kA), c->at<uint32_t>(L.key));
   SortBufs sb = sort_bufs(c);
@@ -454,14 +452,11 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   uint32_t *chunk = c->at<uint32_t>(L.chunk_heads);
   unsigned long long *acc = c->at<unsigned long long>(L.acc);
   mark(c, "seg_count");
-  k_seg_count<<<G, TPB, 0, st>>>(G, sb, meta, chunk);
-  mark(c, "seg_scan");
-  k_seg_scan<<<1, TPB, 0, st>>>(p.T, chunk, G, meta, c->at<uint32_t>(L.seg_first));
+  k_seg_count<<<G, TPB, 0, st>>>(G, p.T, sb, meta, chunk, c->at<uint32_t>(L.seg_first));
   mark(c, "seg_mark");
   k_seg_mark<<<G, TPB, 0, st>>>(p, G, sb, meta, chunk, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
-                                  c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.lut), L.lut_cap);
-  k_seg_first<<<(p.T + 1 + TPB - 1) / TPB, TPB, 0, st>>>(p.T, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
-                                                         meta, c->at<uint32_t>(L.seg_first));
+                                  c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.lut), L.lut_cap,
+                                  c->at<uint32_t>(L.seg_first));
   mark(c, "bin_sums");
   if constexpr (DIM == 2) {
     if (c->cfg.dummy_mode == PCSIR_DUMMY_COM2)
@@ -1038,7 +1033,7 @@ pcsir_status pcsir_set_tuning(pcsir_ctx *c, const pcsir_tuning *t) {
     return fail(c, PCSIR_E_INVAL, "bin_tile must be 1024, 2048 or 4096");
   if (t->list_blocks < 64 || t->list_blocks > LIST_BLOCKS_MAX)
     return fail(c, PCSIR_E_INVAL, "list_blocks must lie in [64, 2048]");
-  if (t->digit_bits < DIGIT_BITS_MIN || t->digit_bits > MAX_DIGIT_BITS)
+  if (t->digit_bits < MIN_DIGIT_BITS || t->digit_bits > MAX_DIGIT_BITS)
     return fail(c, PCSIR_E_INVAL, "digit_bits must lie in [6, 11]");
   if (t->grid_per_cu < 4 || t->grid_per_cu > 64) return fail(c, PCSIR_E_INVAL, "grid_per_cu must lie in [4, 64]");
   drop_graphs(c);  // captured graphs hold the launch shapes
