@@ -12,12 +12,14 @@ constexpr int KEYS_TPB = 512;       // threads per block of the key dedup (k_key
 constexpr int KEYS_TILE = 8192;     // particles of one target per tile of the key dedup
 constexpr int BINS_TPB = 512;       // threads per block of the bin sums (k_bin_sums)
 constexpr int LIST_BLOCKS_MAX = 2048;  // most workgroups of the sort / segment passes over the key list
-constexpr int SCAN_ITEMS = 4;       // particles per thread in the weight scan
+constexpr int SCAN_ITEMS = 8;       // particles per thread in the weight scan and resampling
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+constexpr int RS_ITEMS = 4;         // new particles per thread in the resampling search
+constexpr int RS_TILE = TPB * RS_ITEMS;
 constexpr int MAX_QUAD = 16;        // largest number of sub-samples per pixel axis
 constexpr int PROP_TILES = 2;       // propagate tiles (TPB particles each) per block
 constexpr int LIK_WAVES = 4;        // likelihood evaluations per block (one per wave)
-constexpr int BIN_TILES = 4;        // largest bin-sum tile, in scan tiles of one target
+constexpr int BIN_TILE_MAX = 4096;   // largest bin-sum tile: consecutive particles of one target
 
 // Fixed-point scales of the bin sums (integer sums are exact and order-free).
 constexpr float FX_POS = 4294967296.0f;  // 2^32: offsets from the cell's pixel, |d| <= 1/2
@@ -127,7 +129,7 @@ struct Tile {
   uint32_t n;    // the target's particle count
 };
 
-// Bin-sum work item: up to BIN_TILES * SCAN_TILE consecutive particles of one target.
+// Bin-sum work item: up to BIN_TILE_MAX consecutive particles of one target.
 struct BinTile {
   int32_t t;
   uint32_t i0, i1;  // particles [i0, i1) of target t
@@ -850,7 +852,7 @@ struct BinLds {
   // 4 particles each (instead of 512 with 8), which keeps the registers of a
   // thread within what four waves per SIMD allow
   static constexpr int NTH = (DIM == 3 || MOM2) ? 1024 : BINS_TPB;
-  static constexpr int R = BIN_TILES * SCAN_TILE / NTH;  // particles per thread and round, loaded together
+  static constexpr int R = BIN_TILE_MAX / NTH;  // particles per thread and round, loaded together
 };
 
 // One member's fixed-point contributions: count, offsets from its pixel
@@ -932,7 +934,7 @@ __global__ __launch_bounds__((BinLds<DIM, MOM2>::NTH)) void k_bin_sums(Params p,
     // a tile is one round (at most R NTH particles): each particle is
     // loaded and its bin looked up once, and each LDS chunk of the target's
     // bins then takes the particles whose bin it holds
-    static_assert(BIN_TILES * SCAN_TILE <= R * NTH, "one round per bin-sum tile");
+    static_assert(BIN_TILE_MAX <= R * NTH, "one round per bin-sum tile");
     float x[R][D];
     uint32_t bin[R];
 #pragma unroll
@@ -2003,7 +2005,7 @@ __global__ __launch_bounds__(TPB) void k_norm_comb(Params p, const uint32_t *__r
 // bin numbers, then the bin weights they index) are in flight together; each
 // tile's sum is formed in the same order as a block of its own would form it
 // (per thread over its items, then the waves in order).
-constexpr int CDF_SUM_TILES = 4;
+constexpr int CDF_SUM_TILES = 2;
 
 template <bool SIR>
 __global__ __launch_bounds__(TPB) void k_cdf_sum(const Tile *__restrict__ tiles, uint32_t ntiles,
@@ -2109,7 +2111,8 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
                                                   WeightSrc ws, const double *__restrict__ tile_pre,
                                                   const int32_t *__restrict__ tflag, uint32_t *__restrict__ anc,
                                                   double *__restrict__ cdf, double neff_frac,
-                                                  int32_t *__restrict__ tuni_next, uint32_t *__restrict__ chunk_par) {
+                                                  int32_t *__restrict__ tuni_next, uint32_t *__restrict__ chunk_par,
+                                                  const uint32_t *__restrict__ tfirstR) {
   __shared__ double lds[TPB / WAVE];
   __shared__ double bound[TPB + 1];
   __shared__ double cl[SCAN_TILE + SCAN_TILE / SCAN_ITEMS];
@@ -2204,10 +2207,10 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
   // parents of the search blocks' first new particles that fall in this tile
   const uint32_t jlo = count_below(pre, u, n);
   const uint32_t jhi = last_tile ? n : count_below(tile_end, u, n);
-  const uint32_t first_tile = blockIdx.x - tl.i0 / SCAN_TILE;  // this target's tiles are consecutive
+  const uint32_t first_rtile = tfirstR[t];  // the target's first search block
   const double dn = (double)n;
-  for (uint32_t q = (jlo + SCAN_TILE - 1) / SCAN_TILE + threadIdx.x; q * SCAN_TILE < jhi; q += TPB) {
-    const double theta = ((double)(q * SCAN_TILE) + u) / dn;
+  for (uint32_t q = (jlo + RS_TILE - 1) / RS_TILE + threadIdx.x; q * RS_TILE < jhi; q += TPB) {
+    const double theta = ((double)(q * RS_TILE) + u) / dn;
     // smallest li with C > theta; the tile's last particle qualifies (its C is
     // the next tile's start, or the target's last particle)
     uint32_t a = 0, b = m - 1;
@@ -2216,22 +2219,23 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
       if (cl[cpad(mid)] > theta) b = mid;
       else a = mid + 1;
     }
-    chunk_par[first_tile + q] = tl.i0 + a;
+    chunk_par[first_rtile + q] = tl.i0 + a;
   }
 }
 
-// Systematic resampling proper, one block per SCAN_TILE new particles of a
-// target (the same tiles as the particles), so that the work does not follow
+// Systematic resampling proper, one block per RS_TILE new particles of a
+// target, so that the work does not follow
 // the weights: a tile holding most of a target's weight has as many parents
 // to find as it has offspring, which one block per particle tile would
 // serialise. The new particle j takes the parent s(j) = min{ l : C_l > theta_j },
 // theta_j = (j + u) / n, over the cumulative weights C (non-decreasing
 // across the whole target); the last particle also takes any j left above
 // C_{n-1} by rounding. The block's parents lie between the parents of its
-// first j and of the next block's first j (chunk_par); when that range fits,
-// its C values are staged in LDS. Each thread takes SCAN_ITEMS consecutive j,
-// one binary search each.
-constexpr uint32_t SEARCH_LDS = 1024;
+// first j and of the next block's first j (chunk_par); when that range fits
+// (up to twice the tile: weights need not be even), its C values are staged
+// in LDS, otherwise every stride-th of them. Each thread takes RS_ITEMS
+// j, TPB apart, one binary search each.
+constexpr uint32_t SEARCH_LDS = 2 * RS_TILE;
 
 template <bool SIR>
 __global__ __launch_bounds__(TPB) void k_resample_search(const Tile *__restrict__ tiles,
@@ -2246,7 +2250,7 @@ __global__ __launch_bounds__(TPB) void k_resample_search(const Tile *__restrict_
   const uint32_t base = tl.base, n = tl.n;
   // the loads that do not depend on each other are issued together
   const uint32_t p0 = chunk_par[blockIdx.x];
-  const uint32_t p1 = tl.i0 + SCAN_TILE < n ? chunk_par[blockIdx.x + 1] : n - 1;  // inclusive
+  const uint32_t p1 = tl.i0 + RS_TILE < n ? chunk_par[blockIdx.x + 1] : n - 1;  // inclusive
   const double u = ws.tgt[t * 4 + 3];
   // targets that keep their particles were written by the scan
   if (tflag[t] || (ws.lw && !(ws.tgt[t * 4 + 2] < neff_frac * (double)n))) return;
@@ -2257,34 +2261,54 @@ __global__ __launch_bounds__(TPB) void k_resample_search(const Tile *__restrict_
   const uint32_t span = p1 - p0 + 1;
   const uint32_t stride = (span + SEARCH_LDS - 1) / SEARCH_LDS;
   const uint32_t ns = (span + stride - 1) / stride;
-  for (uint32_t k = threadIdx.x; k < ns; k += TPB) {
-    const uint32_t l = p0 + k * stride;
-    cs[k] = l + 1 >= n ? INFINITY : C[l];  // the last particle stands for +infinity
+  {
+    // every load is issued before the first is used
+    constexpr int PER = SEARCH_LDS / TPB;
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t k = q * TPB + threadIdx.x;
+      const uint32_t l = p0 + k * stride;
+      v[q] = k < ns && l + 1 < n ? C[l] : INFINITY;  // the last particle stands for +infinity
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t k = q * TPB + threadIdx.x;
+      if (k < ns) cs[k] = v[q];
+    }
   }
   __syncthreads();
+  // new particle j = i0 + it TPB + thread (each store instruction covers
+  // consecutive slots); the RS_ITEMS searches of a thread advance together,
+  // one halving step at a time, so that their LDS reads overlap
+  double theta[RS_ITEMS];
+  uint32_t a[RS_ITEMS];
 #pragma unroll
-  for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t j = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+  for (int it = 0; it < RS_ITEMS; ++it) {
+    theta[it] = ((double)(tl.i0 + it * TPB + threadIdx.x) + u) / dn;
+    a[it] = 0;
+  }
+  // a = number of samples <= theta: the first sample above theta (ns if
+  // none: the answer is then in the last segment, whose end p1 is above theta)
+  for (uint32_t step = 1u << (31 - __clz(ns)); step > 0; step >>= 1) {
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it)
+      if (a[it] + step <= ns && cs[a[it] + step - 1] <= theta[it]) a[it] += step;
+  }
+#pragma unroll
+  for (int it = 0; it < RS_ITEMS; ++it) {
+    const uint32_t j = tl.i0 + it * TPB + threadIdx.x;
     if (j >= n) break;
-    const double theta = ((double)j + u) / dn;
-    // first sample above theta (ns if none: the answer is then in the last
-    // segment, whose end p1 is above theta)
-    uint32_t a = 0, b = ns;
-    while (a < b) {
-      const uint32_t mid = (a + b) >> 1;
-      if (cs[mid] > theta) b = mid;
-      else a = mid + 1;
-    }
     uint32_t par;
     if (stride == 1) {
-      par = p0 + min(a, ns - 1);
+      par = p0 + min(a[it], ns - 1);
     } else {
       // the answer lies in (sample a-1, sample a]
-      uint32_t lo = a == 0 ? p0 : p0 + (a - 1) * stride + 1;
-      uint32_t hi = a == ns ? p1 : p0 + a * stride;
+      uint32_t lo = a[it] == 0 ? p0 : p0 + (a[it] - 1) * stride + 1;
+      uint32_t hi = a[it] == ns ? p1 : p0 + a[it] * stride;
       while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (mid + 1 >= n || C[mid] > theta) hi = mid;
+        if (mid + 1 >= n || C[mid] > theta[it]) hi = mid;
         else lo = mid + 1;
       }
       par = lo;

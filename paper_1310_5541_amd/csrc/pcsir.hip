@@ -26,20 +26,21 @@ struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint, dlo,
       ll, ll9, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
       bbox_part, mom_part, tm, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
-      tiles256, tilesS, tilesB, tilesK, tile_last, tfirst, t256_first, off, chunk_par;
+      tiles256, tilesS, tilesR, tilesB, tilesK, tile_last, tfirst, tfirstR, t256_first, off, chunk_par;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
   uint32_t n256; // propagate tiles
   uint64_t lut_cap;  // entries of the cell -> bin table
   uint32_t nS;   // scan tiles
+  uint32_t nR;   // resampling search tiles
   uint32_t nB;   // bin-sum tiles
   uint32_t nK;   // key tiles
 };
 
 struct Tables {
-  std::vector<Tile> t256, tS;
+  std::vector<Tile> t256, tS, tR;
   std::vector<BinTile> tB, tK;
-  std::vector<uint32_t> tile_last, tfirst, t256_first, off;
+  std::vector<uint32_t> tile_last, tfirst, tfirstR, t256_first, off;
 };
 
 bool valid_config(const pcsir_config *c, std::string *why) {
@@ -84,7 +85,7 @@ bool valid_config(const pcsir_config *c, std::string *why) {
   return true;
 }
 
-constexpr int BIN_TILE_MIN = 1024, BIN_TILE_MAX = BIN_TILES * SCAN_TILE;
+constexpr int BIN_TILE_MIN = 1024;
 
 void build_bin_tiles(const pcsir_config *c, uint32_t tile, std::vector<BinTile> &tB) {
   tB.clear();
@@ -100,6 +101,8 @@ void build_tables(const pcsir_config *c, Tables &tb) {
   const int T = c->n_targets;
   tb.off.assign(T + 1, 0);
   tb.tfirst.assign(T + 1, 0);
+  tb.tfirstR.assign(T + 1, 0);
+  tb.tR.clear();
   tb.t256_first.assign(T + 1, 0);
   tb.t256.clear();
   tb.tS.clear();
@@ -115,10 +118,13 @@ void build_tables(const pcsir_config *c, Tables &tb) {
       tb.tS.push_back(Tile{t, i0, tb.off[t], n});
       tb.tile_last.push_back(i0 + SCAN_TILE >= n ? 1u : 0u);
     }
+    tb.tfirstR[t] = (uint32_t)tb.tR.size();
+    for (uint32_t i0 = 0; i0 < n; i0 += RS_TILE) tb.tR.push_back(Tile{t, i0, tb.off[t], n});
   }
   build_bin_tiles(c, BIN_TILE_MAX, tb.tB);
   build_bin_tiles(c, KEYS_TILE, tb.tK);
   tb.tfirst[T] = (uint32_t)tb.tS.size();
+  tb.tfirstR[T] = (uint32_t)tb.tR.size();
   tb.t256_first[T] = (uint32_t)tb.t256.size();
 }
 
@@ -134,6 +140,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.G = (uint32_t)std::max<size_t>(1, std::min<size_t>(LIST_BLOCKS_MAX, (NT + TPB - 1) / TPB));
   L.n256 = (uint32_t)tb.t256.size();
   L.nS = (uint32_t)tb.tS.size();
+  L.nR = (uint32_t)tb.tR.size();
   {
     // bin-tile table sized for the smallest tile the tuning allows
     std::vector<BinTile> most;
@@ -195,9 +202,10 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.tile_sum = take(8 * (size_t)L.nS);
   L.tile_pre = take(8 * (size_t)L.nS);
   L.cdf = take(8 * NT);
-  L.chunk_par = take(4 * (size_t)L.nS);
+  L.chunk_par = take(4 * (size_t)L.nR);
   L.tiles256 = take(sizeof(Tile) * (size_t)L.n256);
   L.tilesS = take(sizeof(Tile) * (size_t)L.nS);
+  L.tilesR = take(sizeof(Tile) * (size_t)L.nR);
   L.tilesB = take(sizeof(BinTile) * (size_t)L.nB);
   L.nK = (uint32_t)tb.tK.size();
   L.tilesK = take(sizeof(BinTile) * (size_t)L.nK);
@@ -208,6 +216,7 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.lut = take(4 * L.lut_cap);
   L.tile_last = take(4 * (size_t)L.nS);
   L.tfirst = take(4 * (T + 1));
+  L.tfirstR = take(4 * (T + 1));
   L.t256_first = take(4 * (T + 1));
   L.off = take(4 * (T + 1));
   L.total = o;
@@ -536,9 +545,10 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   mark(c, "cdf_scan");
   k_cdf_scan<false><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
                                           c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
-                                          keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par));
+                                          keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par),
+                                          c->at<uint32_t>(L.tfirstR));
   mark(c, "resample");
-  k_resample_search<false><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
+  k_resample_search<false><<<L.nR, TPB, 0, st>>>(c->at<Tile>(L.tilesR), off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
                                                  c->at<int32_t>(L.tflag), anc, c->cfg.neff_threshold);
   mark(c, "end");
 }
@@ -583,9 +593,10 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
   mark(c, "cdf_scan");
   k_cdf_scan<true><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
                                          c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
-                                         keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par));
+                                         keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par),
+                                          c->at<uint32_t>(L.tfirstR));
   mark(c, "resample");
-  k_resample_search<true><<<L.nS, TPB, 0, st>>>(tS, off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
+  k_resample_search<true><<<L.nR, TPB, 0, st>>>(c->at<Tile>(L.tilesR), off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
                                                 c->at<int32_t>(L.tflag), anc, c->cfg.neff_threshold);
   mark(c, "end");
 }
@@ -776,6 +787,8 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   };
   h2d(L.tiles256, c->tb.t256.data(), sizeof(Tile) * c->tb.t256.size());
   h2d(L.tilesS, c->tb.tS.data(), sizeof(Tile) * c->tb.tS.size());
+  h2d(L.tilesR, c->tb.tR.data(), sizeof(Tile) * c->tb.tR.size());
+  h2d(L.tfirstR, c->tb.tfirstR.data(), 4 * c->tb.tfirstR.size());
   h2d(L.tilesB, c->tb.tB.data(), sizeof(BinTile) * c->tb.tB.size());
   h2d(L.tilesK, c->tb.tK.data(), sizeof(BinTile) * c->tb.tK.size());
   h2d(L.tile_last, c->tb.tile_last.data(), 4 * c->tb.tile_last.size());
