@@ -23,9 +23,21 @@ __device__ __forceinline__ const gfloat *as_global(const float *ptr) { return (c
 // 32x32->64 products (multipliers 0xD2511F53, 0xCD9E8D57) with a Weyl key
 // schedule (0x9E3779B9, 0xBB67AE85). The 32-bit variant runs on the native
 // 32-bit multiplier; the 64-bit one needs four partial products per multiply.
+// The key (k0, k1) must be the same in every lane of a wave (here always the
+// seed, a kernel argument): it enters the rounds from scalar registers.
 struct U32x4 {
   uint32_t v[4];
 };
+
+// a ^ b ^ k in one instruction (the compiler emits two XORs for it): the
+// three-input bitwise operation with truth table 0x96 (bit 4a + 2b + c of the
+// table is a ^ b ^ c), for a key k that is the same in every lane of the wave
+// (held in a scalar register)
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
 
 __device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                                uint32_t k1) {
@@ -33,14 +45,14 @@ __device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
   const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = c0 * M0, hi0 = __umulhi(c0, M0);
-    const uint32_t lo1 = c2 * M1, hi1 = __umulhi(c2, M1);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    // each 64-bit product is one multiply instruction giving both halves
+    const uint64_t p0 = (uint64_t)c0 * M0, p1 = (uint64_t)c2 * M1;
+    const uint32_t n0 = xor3_key((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3_key((uint32_t)(p0 >> 32), c3, k1);
     c0 = n0;
-    c1 = lo1;
+    c1 = (uint32_t)p1;
     c2 = n2;
-    c3 = lo0;
+    c3 = (uint32_t)p0;
     k0 += W0;
     k1 += W1;
   }
