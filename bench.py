@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--train-rows", type=int, default=1_000_000)
     ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--qat-epochs", type=int, default=2,
+                    help="FP8-aware epochs after the BF16 ones (their scales serve the FP8 mode)")
     ap.add_argument("--check", type=float, default=0.01, help="share of dummies checked exactly per frame")
     ap.add_argument("--tol", type=float, default=2.0, help="surrogate fallback threshold (nats)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
@@ -484,8 +486,9 @@ def main():
         gen_rows_s = time.perf_counter() - t1
         log(f"surrogate: {n_rows} training rows from {seq} sequences in {gen_rows_s:.1f} s")
         n_in = w.patch ** 2 + 2 * dim + 1
-        params, hist = sg.train(X[:n_rows], y[:n_rows], epochs=args.epochs, n_in=n_in, log=log)
-        scales = sg.calibrate(params, X[:n_rows])
+        params, hist = sg.train(X[:n_rows], y[:n_rows], epochs=args.epochs, n_in=n_in, log=log,
+                                qat_epochs=args.qat_epochs)
+        scales = hist["fp8_scales"] if args.qat_epochs > 0 else sg.calibrate(params, X[:n_rows])
         del X, y
         # held-out rows: exact pcSIR dummies of this workload (matching sequence 0)
         wr, trr, frr, initr = seqs[0]
@@ -506,6 +509,9 @@ def main():
         r_8 = None if a_8 is None else float(np.mean(a_8))
         surr = {"train": {"rows": n_rows, "sequences": seq, "workload": wt.name, "row_generation_s":
                           round(gen_rows_s, 2), "train_s": round(hist["train_s"], 2), "epochs": args.epochs,
+                          "fp8_aware_epochs": args.qat_epochs,
+                          "rms_nats_per_fp8_aware_epoch": [round(float(np.sqrt(m)) * 100, 4)
+                                                           for m in hist.get("qat_mse_per_epoch", [])],
                           "batch": hist["batch"], "steps": hist["steps"],
                           "rms_nats_per_epoch": [round(float(np.sqrt(m)) * 100, 4) for m in hist["mse_per_epoch"]]},
                 "error_nats_vs_exact": {"bf16": err_bf16, "fp8": err_fp8, "rows": n_ev,

@@ -52,6 +52,22 @@ pcsir_status pcsir_mlp_train_step(float *params_dev, float *adam_m_dev, float *a
                                   const float *y_dev, int32_t batch, float lr, int32_t t, void *workspace_dev,
                                   size_t workspace_bytes, void *hip_stream, float *loss_dev, float *grad_dev);
 
+/* pcsir_mlp_train_step with the FP8 quantisation of the inference kernel in
+ * the forward pass (quantisation-aware training, an extension for the FP8
+ * surrogate mode): the two hidden layers take E4M3 operands, their inputs
+ * quantised as fp8(clamp(g / s, +-448)) with s = act_scale_dev[1] and
+ * act_scale_dev[2] (device, three FP32 values as for pcsir_set_surrogate;
+ * [0] unused), their weights as fp8(W / s_w) with s_w = max|W| / 448 per
+ * tensor, and the accumulators scaled by s s_w. The backward pass takes each
+ * quantiser as the identity where it does not clamp and as zero where it
+ * does (straight-through gradients onto the FP32 master weights). The input
+ * layer and the output unit are as in pcsir_mlp_train_step. Same workspace,
+ * arguments and errors as pcsir_mlp_train_step; act_scale_dev is required. */
+pcsir_status pcsir_mlp_train_step_fp8(float *params_dev, float *adam_m_dev, float *adam_v_dev, const uint16_t *X_dev,
+                                      const float *y_dev, int32_t batch, float lr, int32_t t,
+                                      const float *act_scale_dev, void *workspace_dev, size_t workspace_bytes,
+                                      void *hip_stream, float *loss_dev, float *grad_dev);
+
 /* Largest batch of pcsir_mlp_train_step_static. */
 #define PCSIR_MLP_STATIC_MAX_BATCH 1024
 

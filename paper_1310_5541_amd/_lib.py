@@ -94,6 +94,7 @@ def lib():
     L.pcsir_mlp_train_bytes.restype = sz
     L.pcsir_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, i32, vp, sz, vp, vp, vp]
     L.pcsir_mlp_train_step_static.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, i32, vp, vp, vp]
+    L.pcsir_mlp_train_step_fp8.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, i32, vp, vp, sz, vp, vp, vp]
     L.pcsir_mlp_forward_train_path.argtypes = [vp, vp, i32, vp, vp, sz, vp]
     L.pcsir_mlp_gemm_bf16.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp]
     L.pcsir_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
@@ -107,7 +108,8 @@ def lib():
     L.pcsir_set_surrogate.argtypes = [vp, vp, vp, C.c_float, C.c_float]
     L.pcsir_surrogate_features.argtypes = [vp, vp, vp, i32, C.POINTER(i32)]
     L.pcsir_surrogate_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_float), i32]
-    for f in ("pcsir_mlp_train_step", "pcsir_mlp_train_step_static", "pcsir_mlp_forward_train_path", "pcsir_mlp_gemm_bf16", "pcsir_surr_prepare",
+    for f in ("pcsir_mlp_train_step", "pcsir_mlp_train_step_static", "pcsir_mlp_train_step_fp8",
+              "pcsir_mlp_forward_train_path", "pcsir_mlp_gemm_bf16", "pcsir_surr_prepare",
               "pcsir_surr_rows", "pcsir_set_surrogate", "pcsir_surrogate_features", "pcsir_surrogate_stats",
               "pcsir_get_tuning", "pcsir_set_tuning", "pcsir_autotune"):
         getattr(L, f).restype = i32
@@ -422,21 +424,29 @@ class MLPTrainer:
         self.loss = torch.zeros(1, dtype=torch.float32, device=self.params.device)
         self.t = 0
 
-    def _run(self, X, y, lr, adam: bool):
+    def _run(self, X, y, lr, adam: bool, act_scale=None):
         assert X.dtype == self._torch.bfloat16 and X.shape == (self.batch, 256) and X.is_contiguous()
         assert y.dtype == self._torch.float32 and y.shape == (self.batch,)
         if adam:
             self.t += 1
-        st = lib().pcsir_mlp_train_step(_ptr(self.params), _ptr(self.m) if adam else None,
-                                        _ptr(self.v) if adam else None, _ptr(X), _ptr(y), self.batch,
-                                        float(lr), self.t if adam else 0, _ptr(self.ws), self.ws.numel(),
-                                        _stream(X.device), _ptr(self.loss), _ptr(self.grad))
+        common = (_ptr(self.params), _ptr(self.m) if adam else None, _ptr(self.v) if adam else None, _ptr(X),
+                  _ptr(y), self.batch, float(lr), self.t if adam else 0)
+        tail = (_ptr(self.ws), self.ws.numel(), _stream(X.device), _ptr(self.loss), _ptr(self.grad))
+        if act_scale is None:
+            st = lib().pcsir_mlp_train_step(*common, *tail)
+            name = "pcsir_mlp_train_step"
+        else:
+            assert act_scale.dtype == self._torch.float32 and act_scale.numel() == 3 and act_scale.is_cuda
+            st = lib().pcsir_mlp_train_step_fp8(*common, _ptr(act_scale), *tail)
+            name = "pcsir_mlp_train_step_fp8"
         if st != 0:
-            raise PcsirError(st, "pcsir_mlp_train_step")
+            raise PcsirError(st, name)
 
-    def step(self, X, y, lr: float):
-        """One Adam step on a batch; returns the loss tensor (device, before the step)."""
-        self._run(X, y, lr, True)
+    def step(self, X, y, lr: float, act_scale=None):
+        """One Adam step on a batch; returns the loss tensor (device, before the step).
+        act_scale (device FP32 [3]): quantisation-aware step with the FP8 inference's
+        quantisers (pcsir_mlp_train_step_fp8)."""
+        self._run(X, y, lr, True, act_scale)
         return self.loss
 
     def step_static(self, X, y, lr: float):
@@ -449,9 +459,10 @@ class MLPTrainer:
                                                  int(X.shape[0]), float(lr), self.t, _stream(X.device),
                                                  _ptr(self.loss), _ptr(self.grad))
 
-    def gradients(self, X, y):
-        """Gradient of the batch loss without updating the parameters."""
-        self._run(X, y, 0.0, False)
+    def gradients(self, X, y, act_scale=None):
+        """Gradient of the batch loss without updating the parameters (act_scale:
+        of the quantisation-aware forward pass, as in step)."""
+        self._run(X, y, 0.0, False, act_scale)
         return self.grad.clone(), float(self.loss.item())
 
     def forward(self, X, params=None):

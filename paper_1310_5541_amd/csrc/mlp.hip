@@ -60,12 +60,18 @@ __device__ __forceinline__ void stage_store(uint16_t (*Xs)[GK + GPAD], int x_t, 
 // EPI_FWD:   z = acc + bias[n]; Zout[m][n] = z; Hout[m][n] = bf16(gelu(z))
 // EPI_BWD:   Hout[m][n] = bf16(acc * gelu'(Zin[m][n]))
 // EPI_STORE: Cout[z M ldc + m ldc + n] = acc (the z-th partial with a K split)
+// With FP8 quantisation in the forward pass (qs, two device floats, else null):
+// EPI_FWD:   z = acc qs[0] + bias[n] (operands holding E4M3 values of scaled
+//            tensors); with qs[1] > 0, Hout = the E4M3 value of
+//            clamp(gelu(z) / qs[1]) (the next layer's quantised input)
+// EPI_BWD:   Hout = bf16(acc qs[0] gelu'(z) [|gelu(z) / qs[1]| <= FP8_MAX])
+//            (the straight-through gradient of the quantiser, zero where it clamps)
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, int lda, int a_t,
                                               const uint16_t *__restrict__ B, int ldb, int b_t,
                                               const float *__restrict__ bias, const float *__restrict__ Zin,
                                               float *__restrict__ Zout, uint16_t *__restrict__ Hout,
-                                              float *__restrict__ Cout, int ldc) {
+                                              float *__restrict__ Cout, int ldc, const float *__restrict__ qs) {
   static_assert(GT * GK / 8 == 256, "one 16-byte load per thread and operand");
   __shared__ __attribute__((aligned(16))) uint16_t As[GT][GK + GPAD];  // [m][k]
   __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GK + GPAD];  // [n][k]
@@ -95,30 +101,80 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
     }
   }
   float *Cz = EPI == EPI_STORE ? Cout + (size_t)blockIdx.z * M * ldc : nullptr;
+  // quantisation: the accumulator's scale, and the output quantiser's scale
+  // and reciprocal (the inference kernel's form, g * (1 / s))
+  const float qa = qs ? qs[0] : 1.0f, qo = qs ? qs[1] : 0.0f;
+  const float qinv = qo > 0.0f ? 1.0f / qo : 0.0f;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int m = m0 + wm + mfma_row(lane, r);
     const int n = n0 + wn + mfma_col(lane);
     const size_t o = (size_t)m * ldc + n;
     if (EPI == EPI_FWD) {
-      const float z = acc[r] + bias[n];
+      const float z = fmaf(acc[r], qa, bias[n]);
       Zout[o] = z;
-      Hout[o] = f2bf(gelu(z));
+      const float g = gelu(z);
+      Hout[o] = f2bf(qo > 0.0f ? fp8_value(g * qinv) : g);
     } else if (EPI == EPI_BWD) {
-      Hout[o] = f2bf(acc[r] * gelu_grad(Zin[o]));
+      const float z = Zin[o];
+      float d = acc[r] * qa * gelu_grad(z);
+      if (qo > 0.0f && !(fabsf(gelu(z) * qinv) <= FP8_MAX)) d = 0.0f;
+      Hout[o] = f2bf(d);
     } else {
       Cz[o] = acc[r];
     }
   }
 }
 
-// out[i] = sum over the S partials part[s][i], s = 0..S-1 in order (K split).
-__global__ void k_split_sum(int n, int S, const float *__restrict__ part, float *__restrict__ out) {
+// out[i] = sum over the S partials part[s][i], s = 0..S-1 in order (K split),
+// times *scale when scale is not null.
+__global__ void k_split_sum(int n, int S, const float *__restrict__ part, float *__restrict__ out,
+                            const float *__restrict__ scale) {
+  const float sc = scale ? *scale : 1.0f;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     float v = part[i];
     for (int s = 1; s < S; ++s) v += part[(size_t)s * n + i];
-    out[i] = v;
+    out[i] = scale ? v * sc : v;
   }
+}
+
+// FP8 quantisation of the hidden layers for training (quantisation-aware):
+// block l - 1 (l = 1, 2) scales W_l per tensor as the inference kernel does,
+// sw = max|W_l| / FP8_MAX, and writes the E4M3 values of W_l / sw as BF16
+// into wq[l - 1]; sw into q[6 + l - 1].
+__global__ __launch_bounds__(256) void k_qat_weights(const float *__restrict__ params, uint16_t *__restrict__ wq1,
+                                                     uint16_t *__restrict__ wq2, float *__restrict__ q) {
+  __shared__ float lds[4];
+  const int l = blockIdx.x + 1;
+  const float *W = params + (l == 1 ? MLP_OFF_W2 : MLP_OFF_W3);
+  uint16_t *out = l == 1 ? wq1 : wq2;
+  float mx = 0.0f;
+  for (int i = threadIdx.x; i < MLP_H * MLP_H; i += 256) mx = fmaxf(mx, fabsf(W[i]));
+  mx = block_max<256, float>(mx, lds);
+  const float sw = mx > 0.0f ? mx / FP8_MAX : 1.0f;
+  for (int i = threadIdx.x; i < MLP_H * MLP_H; i += 256) out[i] = f2bf(fp8_value(W[i] / sw));
+  if (threadIdx.x == 0) q[6 + l - 1] = sw;
+}
+// The per-GEMM factors from the activation scales sx (sx[1], sx[2]: inputs of
+// hidden layers 1 and 2) and the weight scales q[6], q[7]:
+// forward l = 0, 1, 2 at q[2l] (accumulator scale, output quantiser scale),
+// backward through W_1, W_2 at q[8], q[10] (weight scale, quantiser scale),
+// weight gradients of W_1, W_2 at q[12], q[13].
+__global__ void k_qat_factors(const float *__restrict__ sx, float *__restrict__ q) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const float s1 = sx[1], s2 = sx[2], w1 = q[6], w2 = q[7];
+  q[0] = 1.0f;
+  q[1] = s1;
+  q[2] = s1 * w1;
+  q[3] = s2;
+  q[4] = s2 * w2;
+  q[5] = 0.0f;
+  q[8] = w1;
+  q[9] = s1;
+  q[10] = w2;
+  q[11] = s2;
+  q[12] = s1;
+  q[13] = s2;
 }
 
 __global__ void k_f32_to_bf16(int n, const float *__restrict__ src, uint16_t *__restrict__ dst) {
@@ -207,7 +263,7 @@ __global__ void k_adam(int n, float *__restrict__ th, float *__restrict__ m, flo
 }
 
 struct TrainLayout {
-  size_t wb[3], Z[3], Hh[3], dZ[3], f, df, loss_part, part, cs, total;
+  size_t wb[3], Z[3], Hh[3], dZ[3], f, df, loss_part, part, cs, q, total;
 };
 
 // Shares of the batch dimension for the weight-gradient GEMMs (K = batch):
@@ -235,6 +291,7 @@ constexpr TrainLayout train_layout(int B) {
   L.loss_part = take(4 * (size_t)((B + 255) / 256));
   L.part = take(4 * (size_t)wgrad_splits(B) * MLP_H * MLP_H);
   L.cs = take(4 * (size_t)((B + CS_ROWS - 1) / CS_ROWS) * MLP_H);
+  L.q = take(4 * 16);  // FP8 quantisation factors (quantisation-aware step)
   L.total = o;
   return L;
 }
@@ -275,9 +332,10 @@ pcsir_status scratch_address(void *stream, void **out) {
 
 template <int EPI>
 void gemm(hipStream_t st, int M, int N, int K, const uint16_t *A, int lda, int a_t, const uint16_t *B, int ldb, int b_t,
-          const float *bias, const float *Zin, float *Zout, uint16_t *Hout, float *Cout, int ldc, int splits = 1) {
+          const float *bias, const float *Zin, float *Zout, uint16_t *Hout, float *Cout, int ldc, int splits = 1,
+          const float *qs = nullptr) {
   dim3 grid(N / GT, M / GT, splits);
-  k_gemm<EPI><<<grid, 256, 0, st>>>(M, N, K, A, lda, a_t, B, ldb, b_t, bias, Zin, Zout, Hout, Cout, ldc);
+  k_gemm<EPI><<<grid, 256, 0, st>>>(M, N, K, A, lda, a_t, B, ldb, b_t, bias, Zin, Zout, Hout, Cout, ldc, qs);
 }
 
 // out[n] = sum_m X[m][n] (v ? v[m] : 1) for the N = 256 columns, fixed order; part: workspace.
@@ -289,8 +347,13 @@ void colsum(hipStream_t st, int M, const uint16_t *X, const float *v, float *par
 
 // The training step of pcsir_mlp_train_step in a workspace at `ws` (device
 // memory of at least train_layout(batch).total bytes); arguments validated.
+// act_scale (device, three floats, or null): the forward pass quantises the
+// two hidden layers as the FP8 inference does, with these input scales
+// (act_scale[1], act_scale[2]) and per-tensor weight scales, and the
+// backward pass takes the quantisers as the identity where they do not clamp.
 pcsir_status train_step(float *params, float *adam_m, float *adam_v, const uint16_t *X, const float *y, int32_t batch,
-                        float lr, int32_t t, void *ws, void *stream, float *loss_dev, float *grad_dev) {
+                        float lr, int32_t t, void *ws, void *stream, float *loss_dev, float *grad_dev,
+                        const float *act_scale = nullptr) {
   const TrainLayout L = train_layout(batch);
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
@@ -299,12 +362,18 @@ pcsir_status train_step(float *params, float *adam_m, float *adam_v, const uint1
   const int H = MLP_H, M = batch;
   const int offW[3] = {MLP_OFF_W1, MLP_OFF_W2, MLP_OFF_W3};
   const int offB[3] = {MLP_OFF_B1, MLP_OFF_B2, MLP_OFF_B3};
-  for (int l = 0; l < 3; ++l) k_f32_to_bf16<<<64, 256, 0, st>>>(H * H, params + offW[l], at16(L.wb[l]));
+  const bool q8 = act_scale != nullptr;
+  float *q = at32(L.q);
+  for (int l = 0; l < (q8 ? 1 : 3); ++l) k_f32_to_bf16<<<64, 256, 0, st>>>(H * H, params + offW[l], at16(L.wb[l]));
+  if (q8) {
+    k_qat_weights<<<2, 256, 0, st>>>(params, at16(L.wb[1]), at16(L.wb[2]), q);
+    k_qat_factors<<<1, 64, 0, st>>>(act_scale, q);
+  }
   // forward
   const uint16_t *in = X;
   for (int l = 0; l < 3; ++l) {
     gemm<EPI_FWD>(st, M, H, H, in, H, 0, at16(L.wb[l]), H, 0, params + offB[l], nullptr, at32(L.Z[l]),
-                  at16(L.Hh[l]), nullptr, H);
+                  at16(L.Hh[l]), nullptr, H, 1, q8 ? q + 2 * l : nullptr);
     in = at16(L.Hh[l]);
   }
   const int hb = (M + 255) / 256;
@@ -321,12 +390,13 @@ pcsir_status train_step(float *params, float *adam_m, float *adam_v, const uint1
     // dW_l = H_{l-1}^T dZ_l (K = batch, in S shares whose partial products are added in order)
     gemm<EPI_STORE>(st, H, H, M, hin, H, 1, at16(L.dZ[l]), H, 0, nullptr, nullptr, nullptr, nullptr, at32(L.part), H,
                     S);
-    k_split_sum<<<64, 256, 0, st>>>(H * H, S, at32(L.part), g + offW[l]);
+    // (quantised: the activations hold E4M3 values of H_{l-1} / s_l)
+    k_split_sum<<<64, 256, 0, st>>>(H * H, S, at32(L.part), g + offW[l], q8 && l > 0 ? q + 11 + l : nullptr);
     colsum(st, M, at16(L.dZ[l]), nullptr, at32(L.cs), g + offB[l]);
     if (l > 0) {
       // dZ_{l-1} = (dZ_l W_l^T) * gelu'(Z_{l-1})
       gemm<EPI_BWD>(st, M, H, H, at16(L.dZ[l]), H, 0, at16(L.wb[l]), H, 1, nullptr, at32(L.Z[l - 1]), nullptr,
-                    at16(L.dZ[l - 1]), nullptr, H);
+                    at16(L.dZ[l - 1]), nullptr, H, 1, q8 ? q + 6 + 2 * l : nullptr);
     }
   }
   if (adam_m && adam_v && t >= 1) {
@@ -358,6 +428,15 @@ pcsir_status pcsir_mlp_train_step(float *params, float *adam_m, float *adam_v, c
   return train_step(params, adam_m, adam_v, X, y, batch, lr, t, ws, stream, loss_dev, grad_dev);
 }
 
+pcsir_status pcsir_mlp_train_step_fp8(float *params, float *adam_m, float *adam_v, const uint16_t *X, const float *y,
+                                      int32_t batch, float lr, int32_t t, const float *act_scale_dev, void *ws,
+                                      size_t ws_bytes, void *stream, float *loss_dev, float *grad_dev) {
+  if (!params || !X || !y || !ws || !act_scale_dev || batch < 64 || batch % 64) return PCSIR_E_INVAL;
+  if (!grad_dev) return PCSIR_E_INVAL;
+  if (ws_bytes < train_layout(batch).total) return PCSIR_E_NOMEM;
+  return train_step(params, adam_m, adam_v, X, y, batch, lr, t, ws, stream, loss_dev, grad_dev, act_scale_dev);
+}
+
 pcsir_status pcsir_mlp_train_step_static(float *params, float *adam_m, float *adam_v, const uint16_t *X,
                                          const float *y, int32_t batch, float lr, int32_t t, void *stream,
                                          float *loss_dev, float *grad_dev) {
@@ -385,7 +464,7 @@ pcsir_status pcsir_mlp_forward_train_path(const float *params, const uint16_t *X
   const uint16_t *in = X;
   for (int l = 0; l < 3; ++l) {
     gemm<EPI_FWD>(st, n, H, H, in, H, 0, at16(L.wb[l]), H, 0, params + offB[l], nullptr, at32(L.Z[l]),
-                  at16(L.Hh[l]), nullptr, H);
+                  at16(L.Hh[l]), nullptr, H, 1);
     in = at16(L.Hh[l]);
   }
   k_head<<<(n + 255) / 256, 256, 0, st>>>(n, at16(L.Hh[2]), at32(L.Z[2]), params, nullptr, f_out, nullptr, nullptr,

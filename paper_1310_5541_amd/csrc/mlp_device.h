@@ -106,5 +106,13 @@ __device__ __forceinline__ f32x16 mfma_fp8_k64(const uint4 &a0, const uint4 &a1,
 __device__ __forceinline__ uint32_t f2fp8x2(float a, float b) {
   return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xFFFFu;
 }
+constexpr float FP8_MAX = 448.0f;  // largest finite E4M3 value
+
+// v rounded to E4M3 (after the clamp to +-FP8_MAX that the FP8 paths apply),
+// as a float: every E4M3 value is exact in binary32 and in BF16.
+__device__ __forceinline__ float fp8_value(float v) {
+  const float q = fminf(fmaxf(v, -FP8_MAX), FP8_MAX);
+  return __builtin_amdgcn_cvt_f32_fp8((int)f2fp8x2(q, 0.0f), 0);
+}
 
 }  // namespace pcsir

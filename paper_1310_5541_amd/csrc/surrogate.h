@@ -27,7 +27,6 @@ constexpr int SURR_ROWS = 128;            // rows per block
 constexpr int SURR_RT = SURR_ROWS / 32;   // 32-row MFMA tiles
 constexpr int SURR_LD = MLP_F + 8;        // LDS row stride (bf16 elements)
 constexpr int SURR_LD8 = MLP_F + 16;      // LDS row stride (fp8 bytes)
-constexpr float FP8_MAX = 448.0f;         // largest finite E4M3 value
 
 // LDS bytes of the activations of SURR_ROWS rows (BF16 layout; the FP8
 // layout of the hidden layers' inputs, SURR_ROWS x SURR_LD8 bytes, fits in it)

@@ -11,7 +11,8 @@ features and target are described in include/pcsir_mlp.h. Here:
   backward kernels (pcsir_mlp_train_step), one shuffle per epoch, linear
   learning-rate decay;
 * calibrate: FP8 input scales of the three layers from the BF16 activations of
-  a sample of rows;
+  a sample of rows; optionally, quantisation-aware epochs after the BF16 ones
+  (pcsir_mlp_train_step_fp8) fit the network to the FP8 mode's quantisers;
 * evaluate: |l_surrogate - l_exact| in nats through the fused inference kernel.
 
 torch provides device memory, the row shuffle and the reductions of the error
@@ -64,39 +65,57 @@ def rows(f: Filter, frames, k0: int, n_frames: int, cap: int, X=None, y=None, st
 
 
 def train(X, y, epochs: int = 4, batch: int = 1024, lr: float = 1e-3, lr_end: float = 5e-5, seed: int = 0,
-          n_in: int = 230, log=None):
-    """Train on rows X [n, 256] BF16, y [n] FP32 (device). Returns (params FP32 device, history)."""
+          n_in: int = 230, log=None, qat_epochs: int = 0, qat_lr: float = 1e-4):
+    """Train on rows X [n, 256] BF16, y [n] FP32 (device). Returns (params FP32 device, history).
+
+    qat_epochs > 0: after the BF16 epochs, calibrate the FP8 input scales on the
+    trained network and continue for qat_epochs epochs with the FP8 inference's
+    quantisers in the forward pass (pcsir_mlp_train_step_fp8, learning rate
+    qat_lr decaying to lr_end); the history then holds those scales
+    ("fp8_scales"), which the FP8 mode must use with these parameters."""
     import torch
     n = (X.shape[0] // batch) * batch
     ym = float(y[:n].mean().item())
     params = torch.from_numpy(init_params(seed, n_in, ym)).to(X.device)
     tr = MLPTrainer(params, batch)
     steps_per_epoch = n // batch
-    total = epochs * steps_per_epoch
     g = torch.Generator(device=X.device)
     g.manual_seed(seed)
-    hist = []
+    hist, hist_q = [], []
     t0 = time.perf_counter()
     step = 0
-    for ep in range(epochs):
-        perm = torch.randperm(X.shape[0], device=X.device, generator=g)[:n]
-        Xs = X[perm].contiguous()
-        ys = y[perm].contiguous()
-        acc = torch.zeros((), dtype=torch.float32, device=X.device)
-        for b in range(steps_per_epoch):
-            frac = step / max(total - 1, 1)
-            cur = lr * (1.0 - frac) + lr_end * frac
-            loss = tr.step(Xs[b * batch:(b + 1) * batch], ys[b * batch:(b + 1) * batch], cur)
-            acc += loss[0]
-            step += 1
-        mse = float(acc.item()) / steps_per_epoch
-        hist.append(mse)
-        if log:
-            log(f"epoch {ep + 1}/{epochs}: mse {mse:.5f} (rms {math.sqrt(mse) * 100:.3f} nats), "
-                f"{time.perf_counter() - t0:.1f} s")
+
+    def run(n_ep, lr0, out, act_scale, tag):
+        nonlocal step
+        total = n_ep * steps_per_epoch
+        s0 = step
+        for ep in range(n_ep):
+            perm = torch.randperm(X.shape[0], device=X.device, generator=g)[:n]
+            Xs = X[perm].contiguous()
+            ys = y[perm].contiguous()
+            acc = torch.zeros((), dtype=torch.float32, device=X.device)
+            for b in range(steps_per_epoch):
+                frac = (step - s0) / max(total - 1, 1)
+                cur = lr0 * (1.0 - frac) + lr_end * frac
+                loss = tr.step(Xs[b * batch:(b + 1) * batch], ys[b * batch:(b + 1) * batch], cur, act_scale)
+                acc += loss[0]
+                step += 1
+            mse = float(acc.item()) / steps_per_epoch
+            out.append(mse)
+            if log:
+                log(f"{tag} epoch {ep + 1}/{n_ep}: mse {mse:.5f} (rms {math.sqrt(mse) * 100:.3f} nats), "
+                    f"{time.perf_counter() - t0:.1f} s")
+
+    run(epochs, lr, hist, None, "bf16")
+    info = {"mse_per_epoch": hist, "steps": step, "batch": batch, "rows": n}
+    if qat_epochs > 0:
+        scales = calibrate(tr.params, X)
+        sc = torch.tensor([float(v) for v in scales], dtype=torch.float32, device=X.device)
+        run(qat_epochs, qat_lr, hist_q, sc, "fp8-aware")
+        info.update({"qat_mse_per_epoch": hist_q, "fp8_scales": [float(v) for v in scales], "steps": step})
     torch.cuda.synchronize()
-    return tr.params.clone(), {"mse_per_epoch": hist, "train_s": time.perf_counter() - t0, "steps": step,
-                               "batch": batch, "rows": n}
+    info["train_s"] = time.perf_counter() - t0
+    return tr.params.clone(), info
 
 
 def calibrate(params, X, n: int = 65536, margin: float = 1.0):
