@@ -59,9 +59,9 @@ def parse():
     ap.add_argument("--h", type=float, default=0.5)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--train-rows", type=int, default=1_000_000)
-    ap.add_argument("--epochs", type=int, default=12)
-    ap.add_argument("--qat-epochs", type=int, default=2,
-                    help="FP8-aware epochs after the BF16 ones (their scales serve the FP8 mode)")
+    ap.add_argument("--epochs", type=int, default=24)
+    ap.add_argument("--qat-epochs", type=int, default=8,
+                    help="FP8-aware epochs on a copy of the BF16-trained network (the FP8 mode's network)")
     ap.add_argument("--check", type=float, default=0.01, help="share of dummies checked exactly per frame")
     ap.add_argument("--tol", type=float, default=2.0, help="surrogate fallback threshold (nats)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
@@ -466,7 +466,7 @@ def main():
 
     # ---- 2. surrogate: training rows, training, calibration, held-out error, tracking RMSE
     surr = None
-    params = scales = None
+    params = params8 = scales = None
     if not args.no_surrogate:
         t1 = time.perf_counter()
         wt = synth.preset("train-3d" if dim == 3 else "train-2d-512")
@@ -487,8 +487,11 @@ def main():
         log(f"surrogate: {n_rows} training rows from {seq} sequences in {gen_rows_s:.1f} s")
         n_in = w.patch ** 2 + 2 * dim + 1
         params, hist = sg.train(X[:n_rows], y[:n_rows], epochs=args.epochs, n_in=n_in, log=log,
-                                qat_epochs=args.qat_epochs)
-        scales = hist["fp8_scales"] if args.qat_epochs > 0 else sg.calibrate(params, X[:n_rows])
+                                qat_epochs=args.qat_epochs, qat_lr=3e-4)
+        if args.qat_epochs > 0:
+            params8, scales = hist["fp8_params"], hist["fp8_scales"]
+        else:
+            params8, scales = params, sg.calibrate(params, X[:n_rows])
         del X, y
         # held-out rows: exact pcSIR dummies of this workload (matching sequence 0)
         wr, trr, frr, initr = seqs[0]
@@ -499,12 +502,12 @@ def main():
         n_ev = sg.rows(f, frr, 1, min(Kmatch, 10), 400_000, Xe, ye)
         f.close()
         err_bf16 = sg.evaluate(params, Xe[:n_ev], ye[:n_ev])
-        err_fp8 = sg.evaluate(params, Xe[:n_ev], ye[:n_ev], act_scale=scales, fp8=True)
+        err_fp8 = sg.evaluate(params8, Xe[:n_ev], ye[:n_ev], act_scale=scales, fp8=True)
         del Xe, ye
         log(f"surrogate error (nats) bf16 {err_bf16}\n  fp8 {err_fp8}")
         st_b, st_8 = [], []
         a_b = track_rmse(False, h_match, LIK_SURR_BF16, params, None, st_b) if not args.no_match else None
-        a_8 = track_rmse(False, h_match, LIK_SURR_FP8, params, scales, st_8) if not args.no_match else None
+        a_8 = track_rmse(False, h_match, LIK_SURR_FP8, params8, scales, st_8) if not args.no_match else None
         r_b = None if a_b is None else float(np.mean(a_b))
         r_8 = None if a_8 is None else float(np.mean(a_8))
         surr = {"train": {"rows": n_rows, "sequences": seq, "workload": wt.name, "row_generation_s":
@@ -520,7 +523,10 @@ def main():
                 "rmse_px": {"bf16": r_b, "fp8": r_8},
                 "rmse_stats": {"bf16": None if a_b is None else summary(a_b),
                                "fp8": None if a_8 is None else summary(a_8)},
-                "checks_fallbacks": {"bf16": st_b, "fp8": st_8}}
+                "checks_fallbacks": {"bf16": st_b, "fp8": st_8},
+                "fallback_share_of_target_frames": {
+                    m: (None if not st else round(sum(x[1] for x in st) / (len(st) * T * Kmatch), 4))
+                    for m, st in (("bf16", st_b), ("fp8", st_8))}}
 
     # ---- 3. timed regions
     tuned = {}
@@ -528,7 +534,10 @@ def main():
     def timed(sir, h, lik, with_events, autotune=False, thr=float("inf"), **kw):
         f = make(w, init, h, lik, thr=thr, **kw)
         if lik >= LIK_SURR_BF16:
-            f.set_surrogate(params, scales if lik == LIK_SURR_FP8 else None, args.check, args.tol)
+            if lik == LIK_SURR_FP8:
+                f.set_surrogate(params8, scales, args.check, args.tol)
+            else:
+                f.set_surrogate(params, None, args.check, args.tol)
         if not sir and "shapes" in tuned:
             f.set_tuning(**tuned["shapes"])
         for k in range(1, args.warmup + 1):
@@ -652,11 +661,19 @@ def main():
         inf_ms = sb["per"].get("likelihood", float("nan"))
         flops = 2.0 * (w.patch ** 2 + 2 * dim + 1) * 256 + 2 * 2 * 256 * 256 + 2 * 256   # useful MLP work per dummy
         flops_padded = 2.0 * 3 * 256 * 256 + 2 * 256                                       # as computed (256 inputs)
+        # frames each timed filter stepped: warm-up, timed pass, event-timed pass
+        tf = T * (args.warmup + 2 * steps)
+
+        def share(st):
+            return None if st is None else round(st[1] / tf, 4)
         surr["timed"] = {
             "bf16": {"value": round(val["surr_bf16"], 1), "ms_per_step": round(1e3 * sb["el"] / steps, 4),
-                     "stats": sb["stats"]},
+                     "stats": sb["stats"], "fallback_share_of_target_frames": share(sb["stats"])},
             "fp8": {"value": round(val["surr_fp8"], 1),
-                    "ms_per_step": round(1e3 * runs["surr_fp8"]["el"] / steps, 4), "stats": runs["surr_fp8"]["stats"]},
+                    "ms_per_step": round(1e3 * runs["surr_fp8"]["el"] / steps, 4), "stats": runs["surr_fp8"]["stats"],
+                    "fallback_share_of_target_frames": share(runs["surr_fp8"]["stats"])},
+            "stats_fields": "dummies checked exactly, target-frames that fell back to the exact likelihood, "
+                            "largest checked |error| (nats); over the filter's warm-up and both timed passes",
             "inference_roofline_bf16": {"bound": "mfma", "unit": "TFLOP/s", "peak": BF16_PEAK_TFLOPS,
                                         "achieved": round(sb["B_avg"] * flops_padded / (inf_ms * 1e-3) / 1e12, 2),
                                         "dummies_per_step": round(sb["B_avg"], 1),

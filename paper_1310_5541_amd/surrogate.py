@@ -69,10 +69,12 @@ def train(X, y, epochs: int = 4, batch: int = 1024, lr: float = 1e-3, lr_end: fl
     """Train on rows X [n, 256] BF16, y [n] FP32 (device). Returns (params FP32 device, history).
 
     qat_epochs > 0: after the BF16 epochs, calibrate the FP8 input scales on the
-    trained network and continue for qat_epochs epochs with the FP8 inference's
-    quantisers in the forward pass (pcsir_mlp_train_step_fp8, learning rate
-    qat_lr decaying to lr_end); the history then holds those scales
-    ("fp8_scales"), which the FP8 mode must use with these parameters."""
+    trained network and train a copy of it for qat_epochs more epochs with the
+    FP8 inference's quantisers in the forward pass (pcsir_mlp_train_step_fp8,
+    learning rate qat_lr decaying to lr_end). The returned parameters stay
+    those of the BF16 epochs (for the BF16 mode); the history then holds the
+    FP8 mode's parameters ("fp8_params") and the scales they were trained
+    with ("fp8_scales"), which must be used together."""
     import torch
     n = (X.shape[0] // batch) * batch
     ym = float(y[:n].mean().item())
@@ -107,15 +109,17 @@ def train(X, y, epochs: int = 4, batch: int = 1024, lr: float = 1e-3, lr_end: fl
                     f"{time.perf_counter() - t0:.1f} s")
 
     run(epochs, lr, hist, None, "bf16")
+    params_bf16 = tr.params.clone()
     info = {"mse_per_epoch": hist, "steps": step, "batch": batch, "rows": n}
     if qat_epochs > 0:
-        scales = calibrate(tr.params, X)
+        scales = calibrate(params_bf16, X)
         sc = torch.tensor([float(v) for v in scales], dtype=torch.float32, device=X.device)
         run(qat_epochs, qat_lr, hist_q, sc, "fp8-aware")
-        info.update({"qat_mse_per_epoch": hist_q, "fp8_scales": [float(v) for v in scales], "steps": step})
+        info.update({"qat_mse_per_epoch": hist_q, "fp8_scales": [float(v) for v in scales], "steps": step,
+                     "fp8_params": tr.params.clone()})
     torch.cuda.synchronize()
     info["train_s"] = time.perf_counter() - t0
-    return tr.params.clone(), info
+    return params_bf16, info
 
 
 def calibrate(params, X, n: int = 65536, margin: float = 1.0):
