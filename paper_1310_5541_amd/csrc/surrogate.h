@@ -349,78 +349,103 @@ __device__ __forceinline__ void surr_put(uint8_t *act, int m, int f, float v) {
 // Surrogate log-likelihood of every dummy of the step: ll[s] = 100 f - A(z),
 // and every target's largest surrogate value (tmax, ordered bits, atomic max;
 // dummies are sorted by target, so a block's rows span consecutive targets).
-// Features: threads take (row m = tid % SURR_ROWS, window rows g, g + G, ...),
-// G = 256 / SURR_ROWS, and load the window's pixels row by row, adding their
-// squared residuals for A(z) in binary64; the G partial sums of a row are
-// added in a fixed order.
+// Features: wave w takes rows w, w + SURR_NW, ..., SURR_FR rows at a time; a
+// row's P^2 window pixels are spread over the lanes (pixel k = lane + 64 j),
+// and every pixel of the SURR_FR rows is loaded before any is used (from
+// clamped coordinates, pixels outside the frame then reading as the
+// background), so that the loads overlap instead of waiting one by one. The
+// squared residuals of a row add up for A(z) in binary64, in a fixed order
+// (per lane, then the wave's butterfly).
+constexpr int SURR_WJ = (MLP_F + WAVE - 1) / WAVE;  // window pixels per lane (P^2 < 256)
+constexpr int SURR_FR = 2;                          // rows whose windows are loaded together
 template <int DIM, bool FP8>
 __global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) void k_surr_infer(Params p, DummyView dv, const uint64_t *__restrict__ meta,
                                                             const StepDesc *__restrict__ desc, SurrWeights sw,
                                                             double *__restrict__ ll,
                                                             unsigned long long *__restrict__ tmax) {
-  constexpr int G = SURR_TPB / SURR_ROWS;
-  static_assert(G * SURR_ROWS == SURR_TPB, "rows must divide the block");
+  static_assert((SURR_ROWS / SURR_NW) % SURR_FR == 0, "rows of a wave in groups of SURR_FR");
   __shared__ __attribute__((aligned(16))) uint8_t act[SURR_ACT_BYTES];
   __shared__ float fpart[SURR_NW][SURR_ROWS];
-  __shared__ double apart[G > 1 ? G - 1 : 1][SURR_ROWS];
+  __shared__ double aw[SURR_ROWS];
   __shared__ int rinfo[4][SURR_ROWS];  // frame offset, c0, r0, valid
   __shared__ unsigned long long tmx[SURR_ROWS];
   const uint32_t B = (uint32_t)meta[META_B];
   const uint32_t NT = p.NT;
   const gfloat *frame = as_global(desc->frame);
-  const int tid = threadIdx.x, P = p.P, R = p.R, P2 = P * P, NF = P2 + 2 * DIM + 1;
+  const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+  const int P = p.P, R = p.R, P2 = P * P, NF = P2 + 2 * DIM + 1;
   for (uint32_t s0 = blockIdx.x * SURR_ROWS; s0 < B; s0 += gridDim.x * SURR_ROWS) {
     if (tid < SURR_ROWS) {
       const uint32_t s = s0 + tid;
       const bool valid = s < B;
-      const int t = valid ? dv.seg_t[s] : 0;
-      rinfo[0][tid] = p.per_target_frames ? t * p.H * p.W : 0;
-      rinfo[1][tid] = valid ? dv.dpix[s] : 0;
-      rinfo[2][tid] = valid ? dv.dpix[(size_t)NT + s] : 0;
-      rinfo[3][tid] = valid;
+      const uint32_t sc = valid ? s : B - 1;  // clamped: unconditional loads
+      const int t = dv.seg_t[sc];
+      const int c0 = dv.dpix[sc], r0 = dv.dpix[(size_t)NT + sc];
       // state features: offsets from the pixel (in-plane), the axial
       // coordinate in full / 10 (3D), velocities / 10, intensity / 100
       float st[2 * DIM + 1];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) st[a] = valid ? dv.doff[(size_t)a * NT + s] : 0.0f;
-      if (DIM == 3)
-        st[2] = valid ? ((float)dv.dpix[2 * (size_t)NT + s] + dv.doff[2 * (size_t)NT + s]) * MLP_VEL_SCALE : 0.0f;
+      for (int a = 0; a < 2; ++a) st[a] = dv.doff[(size_t)a * NT + sc];
+      if (DIM == 3) st[2] = ((float)dv.dpix[2 * (size_t)NT + sc] + dv.doff[2 * (size_t)NT + sc]) * MLP_VEL_SCALE;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) st[DIM + a] = valid ? dv.dvel[(size_t)a * NT + s] * MLP_VEL_SCALE : 0.0f;
-      st[2 * DIM] = valid ? dv.dint[s] * MLP_IN_SCALE : 0.0f;
+      for (int a = 0; a < DIM; ++a) st[DIM + a] = dv.dvel[(size_t)a * NT + sc] * MLP_VEL_SCALE;
+      st[2 * DIM] = dv.dint[sc] * MLP_IN_SCALE;
+      rinfo[0][tid] = p.per_target_frames ? t * p.H * p.W : 0;
+      rinfo[1][tid] = valid ? c0 : 0;
+      rinfo[2][tid] = valid ? r0 : 0;
+      rinfo[3][tid] = valid;
 #pragma unroll
-      for (int a = 0; a < 2 * DIM + 1; ++a) surr_put(act, tid, P2 + a, st[a]);
+      for (int a = 0; a < 2 * DIM + 1; ++a) surr_put(act, tid, P2 + a, valid ? st[a] : 0.0f);
       for (int f = NF; f < MLP_F; ++f) surr_put(act, tid, f, 0.0f);
     }
     __syncthreads();
-    const int m = tid % SURR_ROWS, g = tid / SURR_ROWS;
-    double a = 0.0;
-    {
-      const int base = rinfo[0][m], c0 = rinfo[1][m], r0 = rinfo[2][m];
-      const bool valid = rinfo[3][m] != 0;
-      for (int dy = g; dy < P; dy += G) {
-        const int r = r0 + dy - R;
-        const bool rok = valid && r >= 0 && r < p.H;
-        const gfloat *fr = frame + base + (ptrdiff_t)(rok ? r : 0) * p.W;
-        for (int dx = 0; dx < P; ++dx) {
-          const int c = c0 + dx - R;
-          const bool ok = rok && c >= 0 && c < p.W;
-          const float z = ok ? fr[c] : p.i_bg;
-          surr_put(act, m, dy * P + dx, (z - p.i_bg) * MLP_IN_SCALE);
-          if (ok) {
-            const double zb = (double)z - (double)p.i_bg;
+    // this lane's window pixels: offsets (dx, dy) from the window's corner,
+    // formed anew for every group of rows (the empty asm keeps the compiler
+    // from hoisting them out of the loop, which would keep them in registers
+    // across the layers and spill)
+    int wdx[SURR_WJ], wdy[SURR_WJ];
+#pragma unroll
+    for (int j = 0; j < SURR_WJ; ++j) {
+      int k = min(lane + WAVE * j, P2 - 1);
+      asm volatile("" : "+v"(k));
+      wdy[j] = k / P;
+      wdx[j] = k - wdy[j] * P;
+    }
+    for (int i0 = 0; i0 < SURR_ROWS / SURR_NW; i0 += SURR_FR) {
+      float z[SURR_FR][SURR_WJ];
+      bool in[SURR_FR][SURR_WJ];
+#pragma unroll
+      for (int r = 0; r < SURR_FR; ++r) {
+        const int m = w + SURR_NW * (i0 + r);
+        const int base = rinfo[0][m], c0 = rinfo[1][m] - R, r0 = rinfo[2][m] - R;
+        const bool valid = rinfo[3][m] != 0;
+#pragma unroll
+        for (int j = 0; j < SURR_WJ; ++j) {
+          const int rr = r0 + wdy[j], cc = c0 + wdx[j];
+          in[r][j] = valid && lane + WAVE * j < P2 && rr >= 0 && rr < p.H && cc >= 0 && cc < p.W;
+          z[r][j] = frame[base + (ptrdiff_t)min(max(rr, 0), p.H - 1) * p.W + min(max(cc, 0), p.W - 1)];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < SURR_FR; ++r) {
+        const int m = w + SURR_NW * (i0 + r);
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < SURR_WJ; ++j) {
+          const int k = lane + WAVE * j;
+          const float v = in[r][j] ? z[r][j] : p.i_bg;
+          if (k < P2) surr_put(act, m, k, (v - p.i_bg) * MLP_IN_SCALE);
+          if (in[r][j]) {
+            const double zb = (double)v - (double)p.i_bg;
             a += zb * zb;
           }
         }
+        a = wave_sum(a);
+        if (lane == 0) aw[m] = a;
       }
     }
-    if (G > 1 && g > 0) apart[g - 1][m] = a;
     __syncthreads();
-    double az = 0.0;
-    if (tid < SURR_ROWS) {
-      for (int gg = 1; gg < G; ++gg) a += apart[gg - 1][tid];
-      az = a * p.inv2sxi2;
-    }
+    const double az = tid < SURR_ROWS ? aw[tid] * p.inv2sxi2 : 0.0;
     surr_layers<FP8>(sw, act, fpart, nullptr);
     if (tid < SURR_ROWS) tmx[tid] = 0ull;
     __syncthreads();
