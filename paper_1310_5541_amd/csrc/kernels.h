@@ -1333,6 +1333,28 @@ __device__ __forceinline__ void psf_factor_pair(float U, float dh, float dl, flo
   exp2_neg_pair(ah, al, tbl, eh, el);
 }
 
+// The ratio of consecutive factors along an axis: 2^-(k ((U + delta - d)^2 -
+// (U - d)^2)) = 2^-(k (2 delta (U - d) + delta^2)) as a pair, for a power of
+// two delta (so that 2 delta (U - d) and delta^2 are exact scalings). Then
+// e(U + delta) = e(U) r(U) and r(U + delta) = r(U) c, c = 2^-(2 k delta^2),
+// which turns all but the first two exp2 of a lane's sub-samples into pair
+// products.
+__device__ __forceinline__ void psf_ratio_pair(float U, float dh, float dl, float kh, float kl, float delta,
+                                               const float2 *tbl, float &rh, float &rl) {
+  float uh, ue;
+  two_sum(U, -dh, uh, ue);
+  const float ul = ue - dl;  // U - d = uh + ul
+  const float tw = 2.0f * delta;
+  float th, tl;
+  two_sum(tw * uh, delta * delta, th, tl);
+  tl = fmaf(tw, ul, tl);     // 2 delta (U - d) + delta^2 = th + tl
+  const float ah = th * kh;
+  float al = fmaf(th, kh, -ah);
+  al = fmaf(th, kl, al);
+  al = fmaf(tl, kh, al);
+  exp2_neg_pair(ah, al, tbl, rh, rl);
+}
+
 // Evaluation sets of k_lik: every dummy / particle; the dummies picked for
 // the surrogate's exact check (list, see k_surr_pick); the dummies of targets
 // whose check failed (list, see k_surr_fallback_list).
@@ -1509,6 +1531,18 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
   const int s_part = s_rem - s_pixel * H;
   const float s_cc = (float)(s_pixel - R);
   const float inv_q2 = 1.0f / (float)(q * q);
+  // with a PSF scale that is the same for every evaluation and q and H powers
+  // of two, a lane's sub-samples (H / q apart) take the product recurrence of
+  // psf_ratio_pair after the first; c of the lane's axis is formed once
+  const bool s_rec = SEP && H >= 1 && (H & (H - 1)) == 0 && (DIM == 2 || p.psf != 1) && (q & (q - 1)) == 0 && q > H;
+  const float s_delta = (float)H / (float)q;
+  float s_ch = 0.0f, s_cl = 0.0f;
+  if (s_rec) {
+    const float c2 = 2.0f * s_delta * s_delta;  // exact: delta is a power of two
+    const float kh = s_axis ? ks_flat.yh : ks_flat.xh, kl = s_axis ? ks_flat.yl : ks_flat.xl;
+    const float ah = c2 * kh;
+    exp2_neg_pair(ah, fmaf(c2, kh, -ah) + c2 * kl, e2tbl, s_ch, s_cl);
+  }
   for (uint32_t idx = blockIdx.x * LIK_WAVES + wave_id(); idx < E; idx += gridDim.x * LIK_WAVES) {
     const uint32_t e = MODE == LIK_ALL ? idx : (MODE == LIK_STENCIL ? idx / 9u : chk.list[idx]);
     int t;
@@ -1600,10 +1634,27 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
         if (s_on) {
           const float d = s_axis ? dy : dx, dl = s_axis ? dyl : dxl;
           const float kh = s_axis ? ks.yh : ks.xh, kl = s_axis ? ks.yl : ks.xl;
-          for (int a = s_part; a < q; a += H) {
-            float vh, vl;
-            psf_factor_pair(s_cc + soff[a], d, dl, kh, kl, e2tbl, vh, vl);
+          if (s_rec) {
+            float vh, vl, rh, rl;
+            psf_factor_pair(s_cc + soff[s_part], d, dl, kh, kl, e2tbl, vh, vl);
+            psf_ratio_pair(s_cc + soff[s_part], d, dl, kh, kl, s_delta, e2tbl, rh, rl);
             pair_acc(ah, al, vh, vl);
+            for (int a = s_part + H; a < q; a += H) {
+              float th, tl;
+              pair_mul(vh, vl, rh, rl, th, tl);
+              vh = th;
+              vl = tl;
+              pair_acc(ah, al, vh, vl);
+              pair_mul(rh, rl, s_ch, s_cl, th, tl);
+              rh = th;
+              rl = tl;
+            }
+          } else {
+            for (int a = s_part; a < q; a += H) {
+              float vh, vl;
+              psf_factor_pair(s_cc + soff[a], d, dl, kh, kl, e2tbl, vh, vl);
+              pair_acc(ah, al, vh, vl);
+            }
           }
         }
         float th = ah, tl = al;
