@@ -95,7 +95,10 @@ def parse():
 def bytes_per_particle(D: int) -> dict:
     """Algorithmic HBM bytes per unit of each HBM-bound kernel of the pcSIR step
     (reads + writes the kernel cannot avoid): per particle, or for the sort and
-    segment kernels per entry of the distinct (tile, cell) key list (sort: per pass)."""
+    segment kernels per entry of the distinct (tile, cell) key list (sort: per pass).
+    The heavy-tile resampling search has none per particle: it moves the
+    cumulative weights and offspring of the few tiles with more offspring than
+    the scan resolves on chip."""
     return {
         "propagate": 4 * D + 4 + 4 * D,   # parent state + ancestor index in, new state out
         "keys": 4 * 2,                     # x, y in (3D: + z); distinct keys out (per list entry, small)
@@ -105,8 +108,7 @@ def bytes_per_particle(D: int) -> dict:
         "seg_mark": 4,                     # per list entry: sorted key in
         "bin_sums": 4 * D + 4,             # state in (key recomputed), bin number out
         "cdf_sum": 4,                      # bin number in
-        "cdf_scan": 4 + 8,                 # bin number in, cumulative weight out
-        "resample": 8 + 4,                 # cumulative weight in, parent index out
+        "cdf_scan": 4 + 4,                 # bin number in, parent index out (C stays on chip)
     }
 
 

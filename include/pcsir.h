@@ -194,7 +194,8 @@ pcsir_status pcsir_set_particles(pcsir_ctx *ctx, const float *src_dev);
  *  WEIGHTS     float64 [sum N]      normalised weights, storage order
  *  TARGET      float64 [T][4]       per target: max log-weight M, S = sum exp(logw - M),
  *                                   N_eff, resampling uniform u
- *  CDF         float64 [sum N]      cumulative weights per target, storage order
+ *  CDF         float64 [sum N]      cumulative weights per target, storage order (targets that
+ *                                   resampled; needs pcsir_set_debug)
  *  RESAMPLE    int32   [sum N]      s(j): parent of new particle j, index within its target
  *                                   (the identity for a target that did not resample)
  *  BINS_PER_PX int32   [T][3]       cells per pixel m of every target and axis in the last pcsir_step
@@ -228,9 +229,10 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *ctx, int32_t what, void *dst_dev, size_
  * kernels one by one while timing is on. */
 pcsir_status pcsir_set_graphs(pcsir_ctx *ctx, int32_t on);
 
-/* Allow PCSIR_DUMP_CDF (on != 0; off by default). The step always stores the
- * per-particle cumulative weights, which its resampling search reads; the
- * switch only gates the view of them. */
+/* Allow PCSIR_DUMP_CDF (on != 0; off by default). The step keeps the
+ * per-particle cumulative weights on chip except in tiles with many offspring;
+ * the view forms them again, for every target that resampled, with the step's
+ * own scan over the last step's weights. */
 pcsir_status pcsir_set_debug(pcsir_ctx *ctx, int32_t on);
 
 /* Per-kernel times, in milliseconds, of every launch since timing was turned
@@ -253,6 +255,10 @@ typedef struct {
                            width actually used is the narrowest that keeps the fewest passes */
   int32_t grid_per_cu;  /* workgroups per compute unit of the grid-stride kernels
                            (likelihood, surrogate, dummies): 4 .. 64 (default 32) */
+  int32_t resample_light; /* most new particles that one 2048-particle tile of the weight
+                           scan resolves itself, from its cumulative weights on chip:
+                           0 .. 4096 (default 4096); a tile with more offspring stores its
+                           cumulative weights, and blocks of 1024 new particles resolve them */
 } pcsir_tuning;
 
 /* Current launch shapes. */
@@ -265,11 +271,11 @@ pcsir_status pcsir_set_tuning(pcsir_ctx *ctx, const pcsir_tuning *tuning);
 
 /* Self-tuning of the launch shapes on the caller's data: a coordinate search,
  * one field at a time in the order above, over bin_tile {1024, 2048, 4096},
- * list_blocks {256, 512, 1024, 2048}, digit_bits {8, 9, 10, 11} and
- * grid_per_cu {8, 16, 32, 64}, keeping the best setting of each field before
- * moving to the next. A trial restores the particles, runs one untimed
- * pcsir_step on `frame_dev` with frame index k (graph capture), restores them
- * again and times `reps` steps with HIP events on the context's stream.
+ * list_blocks {256, 512, 1024, 2048}, digit_bits {8, 9, 10, 11},
+ * grid_per_cu {8, 16, 32, 64} and resample_light {1024, 2048, 4096},
+ * keeping the best setting of each field before moving to the next. A trial
+ * restores the particles, runs one untimed pcsir_step on `frame_dev` with
+ * frame index k (graph capture), restores them again and times `reps` steps with HIP events on the context's stream.
  * state_scratch_dev: caller buffer of D * sum(N_t) floats that receives the
  * current particles first; the particles are restored from it at the end
  * (no step has then run: pcsir_estimate needs a new step). The best setting is

@@ -16,6 +16,9 @@ constexpr int SCAN_ITEMS = 8;       // particles per thread in the weight scan a
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 constexpr int RS_ITEMS = 4;         // new particles per thread in the resampling search
 constexpr int RS_TILE = TPB * RS_ITEMS;
+constexpr int RS_LIGHT_DEFAULT = 4096;  // most offspring a scan tile resolves itself (tunable)
+constexpr int RS_LIGHT_MAX = 4096;     // run slots of the on-chip decode
+constexpr int RS_SEARCH_BLOCKS = 2048;  // most workgroups of the heavy-tile search (grid-stride)
 constexpr int MAX_QUAD = 16;        // largest number of sub-samples per pixel axis
 constexpr int PROP_TILES = 2;       // propagate tiles (TPB particles each) per block
 constexpr int LIK_WAVES = 4;        // likelihood evaluations per block (one per wave)
@@ -2106,9 +2109,10 @@ __global__ __launch_bounds__(TPB) void k_cdf_sum(const Tile *__restrict__ tiles,
 // Per target: exclusive, non-decreasing scan of its tiles' sums.
 __global__ __launch_bounds__(TPB) void k_cdf_prefix(const uint32_t *__restrict__ tfirst,
                                                     const double *__restrict__ tile_sum,
-                                                    double *__restrict__ tile_pre) {
+                                                    double *__restrict__ tile_pre, uint32_t *__restrict__ rs_count) {
   __shared__ double lds[TPB / WAVE];
   const int t = blockIdx.x;
+  if (t == 0 && threadIdx.x == 0) *rs_count = 0;  // this frame's resampling work list starts empty
   const uint32_t a0 = tfirst[t], a1 = tfirst[t + 1];
   __shared__ double last;
   double carry = 0.0;
@@ -2141,32 +2145,100 @@ __device__ __forceinline__ uint32_t count_below(double c, double u, uint32_t n) 
   return j;
 }
 
-// Cumulative weights of systematic resampling: each tile forms those of its
-// particles (block scan), with every boundary taken from one source (the next
-// thread's or tile's start, made non-decreasing), so that C is non-decreasing
-// across the whole target, and writes them (C_l, storage order). Weights are
-// loaded coalesced into LDS first, then each thread takes its SCAN_ITEMS
-// consecutive ones; the LDS array has one pad slot per SCAN_ITEMS entries so
-// that those strided reads do not collide in banks. A target that keeps its
-// particles (non-finite normalisation, or N_eff at or above the threshold)
-// gets identity ancestors and, with kept weights, its normalised log-weights.
-// The new particles whose parents lie in the tile are those with
-// theta_j in [tile start, next tile's start); for every multiple of SCAN_TILE
-// among them, the start of a block of the search below, the tile also records
-// that j's parent (chunk_par), from its cumulative weights in LDS.
+// count_below without divisions where they cannot change the answer. With
+// x = c n - u, theta_j < c holds exactly when j < x, except where j lies
+// within about 2^-52 (j + u) < 2^-20 of x (the roundings of j + u and of the
+// division); x itself comes from one fma, within 2^-20 of c n - u for
+// x < 2^32. So when x is more than 2^-10 from every integer, the count is
+// ceil(x) (clamped to [0, n]). Otherwise, with J the integer nearest x, every
+// j <= J - 2 counts and no j >= J + 1 does, and the two thresholds between
+// are compared as written.
+__device__ __forceinline__ uint32_t count_below_fast(double c, double u, uint32_t n) {
+  if (!(c > 0.0)) return 0;
+  if (!(c < 2.0)) return n;
+  const double dn = (double)n;
+  const double x = fma(c, dn, -u);
+  const double f = ceil(x);
+  const double g = 0x1p-10;
+  if (f - x > g && f - x < 1.0 - g) return (uint32_t)(f < 0.0 ? 0.0 : (f > dn ? dn : f));
+  const double J = rint(x);
+  uint32_t r = J < 1.0 ? 0u : (uint32_t)(J > dn ? dn : J - 1.0);  // thresholds below J - 1
+  for (int d = -1; d <= 0; ++d) {
+    const double j = J + d;
+    if (j >= 0.0 && j < dn && (j + u) / dn < c) ++r;
+  }
+  return r;
+}
+
+// LDS position of a tile's l-th cumulative weight: one pad slot per
+// SCAN_ITEMS entries, so that a thread's SCAN_ITEMS consecutive entries do
+// not collide in banks with its neighbours'.
 __device__ __forceinline__ uint32_t cpad(uint32_t l) { return l + l / SCAN_ITEMS; }
 
-template <bool SIR>
-__global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles, const uint32_t *__restrict__ off,
-                                                  const uint32_t *__restrict__ tile_last,
+// Index of the parent of threshold theta among the m cumulative weights of a
+// tile held in LDS (at cpad positions): the first entry above theta, the
+// tile's last entry when none of the others is (its C is the next tile's
+// start, or it is the target's last particle, which stands for +infinity).
+// RS_ITEMS searches advance together, one halving step at a time, so that
+// their LDS reads overlap.
+__device__ __forceinline__ void tile_search(const double *cl, uint32_t m, const double (&theta)[RS_ITEMS],
+                                            uint32_t (&a)[RS_ITEMS]) {
+  const uint32_t ns = m - 1;  // entries below the last one
+#pragma unroll
+  for (int it = 0; it < RS_ITEMS; ++it) a[it] = 0;
+  // a = number of those entries <= theta (a prefix: C is non-decreasing)
+  for (uint32_t step = ns ? 1u << (31 - __clz(ns)) : 0u; step > 0; step >>= 1) {
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it)
+      if (a[it] + step <= ns && cl[cpad(a[it] + step - 1)] <= theta[it]) a[it] += step;
+  }
+}
+
+// Systematic resampling over the cumulative weights C (non-decreasing across
+// the whole target): the new particle j takes the parent
+// s(j) = min{ l : C_l > theta_j }, theta_j = (j + u) / n, and the target's last
+// particle also takes any j left above C_{n-1} by rounding. So particle l has
+// the offspring j in [count_below(C_{l-1}), count_below(C_l)) (the last
+// particle up to n), one contiguous run per particle.
+//
+// One block per scan tile forms the tile's C by a block scan, with every
+// boundary taken from one source (the next thread's or tile's start, made
+// non-decreasing). Weights are loaded coalesced into LDS first, then each
+// thread takes its SCAN_ITEMS consecutive ones; the LDS array has one pad
+// slot per SCAN_ITEMS entries so that those strided reads do not collide in
+// banks. The tile's offspring are j in [count_below(tile start),
+// count_below(next tile's start)).
+// - A light tile (at most `light` offspring) decodes the runs on chip: each
+//   particle with offspring marks the first slot of its run in LDS, a block
+//   max-scan carries every mark to the end of its run, and the slots go out
+//   to anc in coalesced stores. C never leaves the chip.
+// - A heavy tile (one holding a large share of its target's weight, up to
+//   all N offspring) stores its C and appends one (search tile, scan tile)
+//   pair for every search tile of RS_TILE new particles that its offspring
+//   touch to a work list of `cap` entries; k_resample_search spreads the
+//   pairs over its grid.
+// A target that keeps its particles (non-finite normalisation, or N_eff at
+// or above the threshold) gets identity ancestors and, with kept weights, its
+// normalised log-weights. CDF_ONLY (the debug view) stores every tile's C and
+// nothing else.
+constexpr int DEC_ITEMS = RS_LIGHT_MAX / TPB;  // run slots per thread in the decode
+__device__ __forceinline__ uint32_t dpad(uint32_t k) { return k + k / DEC_ITEMS; }
+
+template <bool SIR, bool CDF_ONLY>
+__global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles, const uint32_t *__restrict__ tile_last,
                                                   WeightSrc ws, const double *__restrict__ tile_pre,
                                                   const int32_t *__restrict__ tflag, uint32_t *__restrict__ anc,
                                                   double *__restrict__ cdf, double neff_frac,
-                                                  int32_t *__restrict__ tuni_next, uint32_t *__restrict__ chunk_par,
-                                                  const uint32_t *__restrict__ tfirstR) {
+                                                  int32_t *__restrict__ tuni_next, const uint32_t *__restrict__ tfirstR,
+                                                  uint2 *__restrict__ rs_work, uint32_t *__restrict__ rs_count,
+                                                  uint32_t cap, uint32_t light) {
   __shared__ double lds[TPB / WAVE];
+  __shared__ uint32_t wmax[TPB / WAVE];
+  __shared__ uint32_t wpos;
   __shared__ double bound[TPB + 1];
   __shared__ double cl[SCAN_TILE + SCAN_TILE / SCAN_ITEMS];
+  static_assert(sizeof(cl) >= sizeof(uint32_t) * (RS_LIGHT_MAX + RS_LIGHT_MAX / DEC_ITEMS), "run slots fit in cl");
+  uint32_t *mk = reinterpret_cast<uint32_t *>(cl);  // run slots of a light tile (after C is in registers)
   const Tile tl = tiles[blockIdx.x];
   const int t = tl.t;
   const uint32_t base = tl.base, n = tl.n;
@@ -2209,8 +2281,9 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
   __syncthreads();  // also: every thread has read its weights from cl
   // kept weights: a target resamples only when N_eff < neff_frac * N
   const bool keep = ws.lw && !flag && !(neff < neff_frac * (double)n);
-  if (tuni_next && tl.i0 == 0 && threadIdx.x == 0) tuni_next[t] = keep ? 0 : 1;
   if (flag || keep) {
+    if (CDF_ONLY) return;
+    if (tuni_next && tl.i0 == 0 && threadIdx.x == 0) tuni_next[t] = keep ? 0 : 1;
     // the particles stay (identity resampling): after a non-finite
     // normalisation, or when N_eff is above the threshold; then they keep
     // their normalised log-weights for the next frame
@@ -2225,6 +2298,7 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
     }
     return;
   }
+  if (!CDF_ONLY && tuni_next && tl.i0 == 0 && threadIdx.x == 0) tuni_next[t] = 1;
   const double start = bound[threadIdx.x];
   double end = bound[threadIdx.x + 1];
   if (end < start) end = start;
@@ -2246,125 +2320,130 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
     c[it] = ci;
     cprev = ci;
   }
-  // through LDS, so that the stores to global memory are coalesced
+  // C in LDS, from where a heavy tile stores it (coalesced)
 #pragma unroll
   for (int it = 0; it < SCAN_ITEMS; ++it) cl[cpad(threadIdx.x * SCAN_ITEMS + it)] = c[it];
+  const uint32_t jlo = count_below_fast(pre, u, n);
+  const uint32_t jhi = last_tile ? n : count_below_fast(tile_end, u, n);
+  const uint32_t M = jhi - jlo;  // offspring of the tile
+  if (CDF_ONLY || M > light) {
+    // heavy: C through LDS, so that the stores to global memory are coalesced
+    // the search tiles that the offspring touch, appended to the work list
+    const uint32_t qa = jlo / RS_TILE, nq = CDF_ONLY ? 0 : (jhi - 1) / RS_TILE - qa + 1;
+    if (!CDF_ONLY && threadIdx.x == 0) wpos = atomicAdd(rs_count, nq);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+      const uint32_t li = it * TPB + threadIdx.x;
+      if (li < m) cdf[base + tl.i0 + li] = cl[cpad(li)];
+    }
+    if (CDF_ONLY) return;
+    const uint32_t first_rtile = tfirstR[t];
+    for (uint32_t k = threadIdx.x; k < nq; k += TPB)
+      if (wpos + k < cap) rs_work[wpos + k] = make_uint2(first_rtile + qa + k, blockIdx.x);
+    return;
+  }
+  // light: every particle's run [s, e) of offspring, relative to jlo
+  const uint32_t s_abs = count_below_fast(start, u, n);  // the thread's first run starts here
+  uint32_t e[SCAN_ITEMS];
+  {
+    uint32_t s0 = s_abs;
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+      const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
+      const uint32_t ei = i >= n ? s0 : (i + 1 == n ? n : count_below_fast(c[it], u, n));
+      s0 = ei > s0 ? ei : s0;
+      e[it] = s0 - jlo;
+    }
+  }
+  // clear the thread's own slots (every thread is done with C in LDS), then
+  // mark the first slot of every run
   __syncthreads();
 #pragma unroll
-  for (int it = 0; it < SCAN_ITEMS; ++it) {
-    const uint32_t li = it * TPB + threadIdx.x;
-    if (li < m) cdf[base + tl.i0 + li] = cl[cpad(li)];
-  }
-  // parents of the search blocks' first new particles that fall in this tile
-  const uint32_t jlo = count_below(pre, u, n);
-  const uint32_t jhi = last_tile ? n : count_below(tile_end, u, n);
-  const uint32_t first_rtile = tfirstR[t];  // the target's first search block
-  const double dn = (double)n;
-  for (uint32_t q = (jlo + RS_TILE - 1) / RS_TILE + threadIdx.x; q * RS_TILE < jhi; q += TPB) {
-    const double theta = ((double)(q * RS_TILE) + u) / dn;
-    // smallest li with C > theta; the tile's last particle qualifies (its C is
-    // the next tile's start, or the target's last particle)
-    uint32_t a = 0, b = m - 1;
-    while (a < b) {
-      const uint32_t mid = (a + b) >> 1;
-      if (cl[cpad(mid)] > theta) b = mid;
-      else a = mid + 1;
+  for (int r = 0; r < DEC_ITEMS; ++r) mk[dpad(threadIdx.x * DEC_ITEMS + r)] = 0u;
+  __syncthreads();
+  {
+    uint32_t sp = s_abs - jlo;
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+      if (e[it] > sp) mk[dpad(sp)] = threadIdx.x * SCAN_ITEMS + it + 1;  // local index + 1
+      sp = e[it];
     }
-    chunk_par[first_rtile + q] = tl.i0 + a;
   }
+  __syncthreads();
+  // running maximum over the slots (marks rise with the slot): thread r
+  // takes slots [r DEC_ITEMS, (r + 1) DEC_ITEMS)
+  uint32_t v[DEC_ITEMS];
+  uint32_t mx = 0;
+#pragma unroll
+  for (int r = 0; r < DEC_ITEMS; ++r) {
+    const uint32_t x = mk[dpad(threadIdx.x * DEC_ITEMS + r)];
+    mx = x > mx ? x : mx;
+    v[r] = mx;
+  }
+  {
+    const uint32_t incl = wave_incl_max_scan(mx);
+    uint32_t exw = __shfl_up(incl, 1, WAVE);
+    if (lane_id() == 0) exw = 0;
+    if (lane_id() == WAVE - 1) wmax[wave_id()] = incl;
+    __syncthreads();
+    uint32_t pw = 0;
+#pragma unroll
+    for (int i = 0; i < TPB / WAVE; ++i)
+      if (i < wave_id()) pw = wmax[i] > pw ? wmax[i] : pw;
+    const uint32_t pre_mx = exw > pw ? exw : pw;
+#pragma unroll
+    for (int r = 0; r < DEC_ITEMS; ++r) mk[dpad(threadIdx.x * DEC_ITEMS + r)] = (v[r] > pre_mx ? v[r] : pre_mx) - 1u;
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < M; k += TPB) anc[base + jlo + k] = tl.i0 + mk[dpad(k)];
 }
 
-// Systematic resampling proper, one block per RS_TILE new particles of a
-// target, so that the work does not follow
-// the weights: a tile holding most of a target's weight has as many parents
-// to find as it has offspring, which one block per particle tile would
-// serialise. The new particle j takes the parent s(j) = min{ l : C_l > theta_j },
-// theta_j = (j + u) / n, over the cumulative weights C (non-decreasing
-// across the whole target); the last particle also takes any j left above
-// C_{n-1} by rounding. The block's parents lie between the parents of its
-// first j and of the next block's first j (chunk_par); when that range fits
-// (up to twice the tile: weights need not be even), its C values are staged
-// in LDS, otherwise every stride-th of them. Each thread takes RS_ITEMS
-// j, TPB apart, one binary search each.
-constexpr uint32_t SEARCH_LDS = 2 * RS_TILE;
-
+// The offspring of heavy scan tiles, spread over the grid: each work-list
+// pair (search tile of RS_TILE new particles [j0, j1), heavy scan tile)
+// stages the scan tile's stored C in LDS and resolves the j of [j0, j1) in
+// [count_below(the tile's start), count_below(next tile's start)) by binary
+// search, with the scan kernel's thresholds. Pairs are disjoint in j, so
+// their order in the list does not matter.
 template <bool SIR>
-__global__ __launch_bounds__(TPB) void k_resample_search(const Tile *__restrict__ tiles,
-                                                         const uint32_t *__restrict__ off, WeightSrc ws,
+__global__ __launch_bounds__(TPB) void k_resample_search(const Tile *__restrict__ tilesR,
+                                                         const Tile *__restrict__ tilesS, WeightSrc ws,
                                                          const double *__restrict__ cdf,
-                                                         const uint32_t *__restrict__ chunk_par,
-                                                         const int32_t *__restrict__ tflag, uint32_t *__restrict__ anc,
-                                                         double neff_frac) {
-  __shared__ double cs[SEARCH_LDS];
-  const Tile tl = tiles[blockIdx.x];
-  const int t = tl.t;
-  const uint32_t base = tl.base, n = tl.n;
-  // the loads that do not depend on each other are issued together
-  const uint32_t p0 = chunk_par[blockIdx.x];
-  const uint32_t p1 = tl.i0 + RS_TILE < n ? chunk_par[blockIdx.x + 1] : n - 1;  // inclusive
-  const double u = ws.tgt[t * 4 + 3];
-  // targets that keep their particles were written by the scan
-  if (tflag[t] || (ws.lw && !(ws.tgt[t * 4 + 2] < neff_frac * (double)n))) return;
-  const double dn = (double)n;
-  const double *__restrict__ C = cdf + base;
-  // every stride-th C of the range in LDS (all of them when it fits); a
-  // search then takes the LDS samples, then at most stride - 1 values
-  const uint32_t span = p1 - p0 + 1;
-  const uint32_t stride = (span + SEARCH_LDS - 1) / SEARCH_LDS;
-  const uint32_t ns = (span + stride - 1) / stride;
-  {
-    // every load is issued before the first is used
-    constexpr int PER = SEARCH_LDS / TPB;
-    double v[PER];
+                                                         const double *__restrict__ tile_pre,
+                                                         const uint32_t *__restrict__ tile_last,
+                                                         const uint2 *__restrict__ rs_work,
+                                                         const uint32_t *__restrict__ rs_count, uint32_t cap,
+                                                         uint32_t *__restrict__ anc) {
+  __shared__ double cl[SCAN_TILE + SCAN_TILE / SCAN_ITEMS];
+  const uint32_t total = min(*rs_count, cap);
+  for (uint32_t wi = blockIdx.x; wi < total; wi += gridDim.x) {
+    const uint2 pr = rs_work[wi];
+    const Tile rt = tilesR[pr.x], st = tilesS[pr.y];
+    const uint32_t base = rt.base, n = rt.n;
+    const double u = ws.tgt[rt.t * 4 + 3];
+    const double dn = (double)n;
+    const uint32_t m = min((uint32_t)SCAN_TILE, n - st.i0);
+    const uint32_t lo = count_below_fast(tile_pre[pr.y], u, n);
+    const uint32_t hi = tile_last[pr.y] ? n : count_below_fast(tile_pre[pr.y + 1], u, n);
+    const uint32_t j0 = rt.i0, j1 = min(rt.i0 + RS_TILE, n);
+    const uint32_t a0 = max(lo, j0), a1 = min(hi, j1);
+    __syncthreads();  // the previous pair's searches are done with cl
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const uint32_t k = q * TPB + threadIdx.x;
-      const uint32_t l = p0 + k * stride;
-      v[q] = k < ns && l + 1 < n ? C[l] : INFINITY;  // the last particle stands for +infinity
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+      const uint32_t li = it * TPB + threadIdx.x;
+      if (li < m) cl[cpad(li)] = cdf[base + st.i0 + li];
     }
+    __syncthreads();
+    double theta[RS_ITEMS];
+    uint32_t a[RS_ITEMS];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const uint32_t k = q * TPB + threadIdx.x;
-      if (k < ns) cs[k] = v[q];
+    for (int it = 0; it < RS_ITEMS; ++it) theta[it] = ((double)(j0 + it * TPB + threadIdx.x) + u) / dn;
+    tile_search(cl, m, theta, a);
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+      const uint32_t j = j0 + it * TPB + threadIdx.x;
+      if (j >= a0 && j < a1) anc[base + j] = st.i0 + a[it];
     }
-  }
-  __syncthreads();
-  // new particle j = i0 + it TPB + thread (each store instruction covers
-  // consecutive slots); the RS_ITEMS searches of a thread advance together,
-  // one halving step at a time, so that their LDS reads overlap
-  double theta[RS_ITEMS];
-  uint32_t a[RS_ITEMS];
-#pragma unroll
-  for (int it = 0; it < RS_ITEMS; ++it) {
-    theta[it] = ((double)(tl.i0 + it * TPB + threadIdx.x) + u) / dn;
-    a[it] = 0;
-  }
-  // a = number of samples <= theta: the first sample above theta (ns if
-  // none: the answer is then in the last segment, whose end p1 is above theta)
-  for (uint32_t step = 1u << (31 - __clz(ns)); step > 0; step >>= 1) {
-#pragma unroll
-    for (int it = 0; it < RS_ITEMS; ++it)
-      if (a[it] + step <= ns && cs[a[it] + step - 1] <= theta[it]) a[it] += step;
-  }
-#pragma unroll
-  for (int it = 0; it < RS_ITEMS; ++it) {
-    const uint32_t j = tl.i0 + it * TPB + threadIdx.x;
-    if (j >= n) break;
-    uint32_t par;
-    if (stride == 1) {
-      par = p0 + min(a[it], ns - 1);
-    } else {
-      // the answer lies in (sample a-1, sample a]
-      uint32_t lo = a[it] == 0 ? p0 : p0 + (a[it] - 1) * stride + 1;
-      uint32_t hi = a[it] == ns ? p1 : p0 + a[it] * stride;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (mid + 1 >= n || C[mid] > theta[it]) hi = mid;
-        else lo = mid + 1;
-      }
-      par = lo;
-    }
-    anc[base + j] = par;
   }
 }
 

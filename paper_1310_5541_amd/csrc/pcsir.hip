@@ -25,14 +25,15 @@ constexpr size_t ALIGN = 256;
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint, dlo,
       ll, ll9, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
-      bbox_part, mom_part, tm, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf,
-      tiles256, tilesS, tilesR, tilesB, tilesK, tile_last, tfirst, tfirstR, t256_first, off, chunk_par;
+      bbox_part, mom_part, tm, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf, rs_work, rs_count,
+      tiles256, tilesS, tilesR, tilesB, tilesK, tile_last, tfirst, tfirstR, t256_first, off;
   size_t total;
   uint32_t G;    // workgroups of the sort and segment passes over the key list
   uint32_t n256; // propagate tiles
   uint64_t lut_cap;  // entries of the cell -> bin table
   uint32_t nS;   // scan tiles
   uint32_t nR;   // resampling search tiles
+  uint32_t nW;   // capacity of the resampling work list (search tile, heavy scan tile)
   uint32_t nB;   // bin-sum tiles
   uint32_t nK;   // key tiles
 };
@@ -202,7 +203,10 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.tile_sum = take(8 * (size_t)L.nS);
   L.tile_pre = take(8 * (size_t)L.nS);
   L.cdf = take(8 * NT);
-  L.chunk_par = take(4 * (size_t)L.nR);
+  // a heavy scan tile with M offspring touches at most M / RS_TILE + 2 search tiles
+  L.nW = L.nR + 2 * L.nS;
+  L.rs_work = take(8 * (size_t)L.nW);
+  L.rs_count = take(4);
   L.tiles256 = take(sizeof(Tile) * (size_t)L.n256);
   L.tilesS = take(sizeof(Tile) * (size_t)L.nS);
   L.tilesR = take(sizeof(Tile) * (size_t)L.nR);
@@ -252,7 +256,7 @@ struct pcsir_ctx {
   float surr_fraction = 0.01f, surr_tol = 1.0f;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2][2][2] = {};
-  pcsir_tuning tune{BIN_TILE_MAX, 1024, MAX_DIGIT_BITS, 32};
+  pcsir_tuning tune{BIN_TILE_MAX, 1024, MAX_DIGIT_BITS, 32, RS_LIGHT_DEFAULT};
   uint32_t nB = 0;  // bin tiles of the current tile size
 
   template <typename T>
@@ -541,15 +545,17 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
                                                                              c->at<double>(L.tile_sum));
   mark(c, "cdf_prefix");
   k_cdf_prefix<<<p.T, TPB, 0, st>>>(c->at<uint32_t>(L.tfirst), c->at<double>(L.tile_sum),
-                                    c->at<double>(L.tile_pre));
+                                    c->at<double>(L.tile_pre), c->at<uint32_t>(L.rs_count));
   mark(c, "cdf_scan");
-  k_cdf_scan<false><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
-                                          c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
-                                          keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par),
-                                          c->at<uint32_t>(L.tfirstR));
+  k_cdf_scan<false, false><<<L.nS, TPB, 0, st>>>(tS, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
+                                                 c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
+                                                 keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.tfirstR),
+                                                 c->at<uint2>(L.rs_work), c->at<uint32_t>(L.rs_count), L.nW,
+                                                 (uint32_t)c->tune.resample_light);
   mark(c, "resample");
-  k_resample_search<false><<<L.nR, TPB, 0, st>>>(c->at<Tile>(L.tilesR), off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
-                                                 c->at<int32_t>(L.tflag), anc, c->cfg.neff_threshold);
+  k_resample_search<false><<<std::min<uint32_t>(L.nW, RS_SEARCH_BLOCKS), TPB, 0, st>>>(
+      c->at<Tile>(L.tilesR), tS, ws, c->at<double>(L.cdf), c->at<double>(L.tile_pre), c->at<uint32_t>(L.tile_last),
+      c->at<uint2>(L.rs_work), c->at<uint32_t>(L.rs_count), L.nW, anc);
   mark(c, "end");
 }
 
@@ -589,15 +595,17 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
                                                                              c->at<double>(L.tile_sum));
   mark(c, "cdf_prefix");
   k_cdf_prefix<<<p.T, TPB, 0, st>>>(c->at<uint32_t>(L.tfirst), c->at<double>(L.tile_sum),
-                                    c->at<double>(L.tile_pre));
+                                    c->at<double>(L.tile_pre), c->at<uint32_t>(L.rs_count));
   mark(c, "cdf_scan");
-  k_cdf_scan<true><<<L.nS, TPB, 0, st>>>(tS, off, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
-                                         c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
-                                         keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.chunk_par),
-                                          c->at<uint32_t>(L.tfirstR));
+  k_cdf_scan<true, false><<<L.nS, TPB, 0, st>>>(tS, c->at<uint32_t>(L.tile_last), ws, c->at<double>(L.tile_pre),
+                                                 c->at<int32_t>(L.tflag), anc, c->at<double>(L.cdf), c->cfg.neff_threshold,
+                                                 keep ? c->at<int32_t>(L.tuni_next) : nullptr, c->at<uint32_t>(L.tfirstR),
+                                                 c->at<uint2>(L.rs_work), c->at<uint32_t>(L.rs_count), L.nW,
+                                                 (uint32_t)c->tune.resample_light);
   mark(c, "resample");
-  k_resample_search<true><<<L.nR, TPB, 0, st>>>(c->at<Tile>(L.tilesR), off, ws, c->at<double>(L.cdf), c->at<uint32_t>(L.chunk_par),
-                                                c->at<int32_t>(L.tflag), anc, c->cfg.neff_threshold);
+  k_resample_search<true><<<std::min<uint32_t>(L.nW, RS_SEARCH_BLOCKS), TPB, 0, st>>>(
+      c->at<Tile>(L.tilesR), tS, ws, c->at<double>(L.cdf), c->at<double>(L.tile_pre), c->at<uint32_t>(L.tile_last),
+      c->at<uint2>(L.rs_work), c->at<uint32_t>(L.rs_count), L.nW, anc);
   mark(c, "end");
 }
 
@@ -980,7 +988,18 @@ pcsir_status pcsir_debug_dump(pcsir_ctx *c, int32_t what, void *dst, size_t byte
     case PCSIR_DUMP_CDF:
       if (!c->debug) return fail(c, PCSIR_E_STATE, "the cumulative-weight view needs pcsir_set_debug(ctx, 1)");
       if (!need(8 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
-      e = hipMemcpyAsync(dst, c->at<double>(L.cdf), 8 * NT, hipMemcpyDeviceToDevice, st);
+      // the step keeps C on chip where it can; the view forms every
+      // resampling target's C again with the step's scan, from the same weights
+      if (c->last_sir)
+        k_cdf_scan<true, true><<<L.nS, TPB, 0, st>>>(c->at<Tile>(L.tilesS), c->at<uint32_t>(L.tile_last), weight_src(c),
+                                                    c->at<double>(L.tile_pre), c->at<int32_t>(L.tflag), nullptr,
+                                                    (double *)dst, c->cfg.neff_threshold, nullptr, nullptr, nullptr,
+                                                    nullptr, 0u, 0u);
+      else
+        k_cdf_scan<false, true><<<L.nS, TPB, 0, st>>>(c->at<Tile>(L.tilesS), c->at<uint32_t>(L.tile_last), weight_src(c),
+                                                     c->at<double>(L.tile_pre), c->at<int32_t>(L.tflag), nullptr,
+                                                     (double *)dst, c->cfg.neff_threshold, nullptr, nullptr, nullptr,
+                                                     nullptr, 0u, 0u);
       break;
     case PCSIR_DUMP_RESAMPLE:
       if (!need(4 * NT)) return fail(c, PCSIR_E_INVAL, "buffer too small");
@@ -1049,6 +1068,8 @@ pcsir_status pcsir_set_tuning(pcsir_ctx *c, const pcsir_tuning *t) {
   if (t->digit_bits < MIN_DIGIT_BITS || t->digit_bits > MAX_DIGIT_BITS)
     return fail(c, PCSIR_E_INVAL, "digit_bits must lie in [6, 11]");
   if (t->grid_per_cu < 4 || t->grid_per_cu > 64) return fail(c, PCSIR_E_INVAL, "grid_per_cu must lie in [4, 64]");
+  if (t->resample_light < 0 || t->resample_light > RS_LIGHT_MAX)
+    return fail(c, PCSIR_E_INVAL, "resample_light must lie in [0, 4096]");
   drop_graphs(c);  // captured graphs hold the launch shapes
   if (t->bin_tile != c->tune.bin_tile) {
     std::vector<BinTile> tB;
@@ -1098,13 +1119,14 @@ pcsir_status pcsir_autotune(pcsir_ctx *c, const float *frame_dev, int32_t H, int
   float best_ms = 0.0f;
   s = trial(best, &best_ms);
   const int tiles[] = {1024, 2048, BIN_TILE_MAX}, blocks[] = {256, 512, 1024, 2048}, bits[] = {8, 9, 10, 11},
-            grids[] = {8, 16, 32, 64};
-  const int *cands[4] = {tiles, blocks, bits, grids};
-  const int ncand[4] = {3, 4, 4, 4};
-  for (int f = 0; f < 4 && s == PCSIR_OK; ++f) {
+            grids[] = {8, 16, 32, 64}, lights[] = {1024, 2048, 4096};
+  const int *cands[5] = {tiles, blocks, bits, grids, lights};
+  const int ncand[5] = {3, 4, 4, 4, 3};
+  for (int f = 0; f < 5 && s == PCSIR_OK; ++f) {
     for (int i = 0; i < ncand[f] && s == PCSIR_OK; ++i) {
       pcsir_tuning t = best;
-      int32_t *field = f == 0 ? &t.bin_tile : f == 1 ? &t.list_blocks : f == 2 ? &t.digit_bits : &t.grid_per_cu;
+      int32_t *field = f == 0 ? &t.bin_tile : f == 1 ? &t.list_blocks : f == 2 ? &t.digit_bits
+                     : f == 3 ? &t.grid_per_cu : &t.resample_light;
       if (*field == cands[f][i]) continue;
       *field = cands[f][i];
       float ms = 0.0f;

@@ -329,8 +329,12 @@ def test_cell_index_at_adversarial_positions(m):
 
 def test_launch_shapes_do_not_change_results_and_autotune_restores_particles():
     """Every pcsir_tuning setting gives bit-identical steps (bins are the sorted
-    distinct keys, sums are exact integers, no reduction depends on the grid);
-    the autotuner returns a valid setting and leaves the particles as they were."""
+    distinct keys, sums are exact integers, no reduction depends on the grid,
+    and a scan tile's offspring get the same parents whether the tile resolves
+    them itself or leaves them to the search blocks: resample_light 0 sends
+    every tile with offspring to the search, 4096 only tiles with more than
+    4096); SIR steps too. The
+    autotuner returns a valid setting and leaves the particles as they were."""
     import torch
 
     from paper_1310_5541_amd import Filter
@@ -343,8 +347,8 @@ def test_launch_shapes_do_not_change_results_and_autotune_restores_particles():
     fr = torch.from_numpy(synth.frames(w, tr, seed=12)).cuda()
     cloud = torch.from_numpy(_clouds(w, counts, [tr[1, t] for t in range(len(counts))], 1.2, 5)).cuda()
     cfg = _cfg(w, seed=13, lik_mode=1)
-    shapes = [None, dict(bin_tile=1024, list_blocks=64, digit_bits=6, grid_per_cu=4),
-              dict(bin_tile=2048, list_blocks=512, digit_bits=8, grid_per_cu=16)]
+    shapes = [None, dict(bin_tile=1024, list_blocks=64, digit_bits=6, grid_per_cu=4, resample_light=0),
+              dict(bin_tile=2048, list_blocks=512, digit_bits=8, grid_per_cu=16, resample_light=1024)]
     outs = []
     for sh in shapes:
         log(f"case launch_shapes {sh}")
@@ -355,11 +359,15 @@ def test_launch_shapes_do_not_change_results_and_autotune_restores_particles():
             assert f.get_tuning() == sh
         for k in range(1, 4):
             f.pcsir_step(fr[k], k)
-        outs.append({n: f.dump(n).cpu().numpy() for n in ("loglik", "weights", "resample", "bin_key", "bin_n")}
+        outs.append({n: f.dump(n).cpu().numpy()
+                     for n in ("loglik", "weights", "resample", "cdf", "bin_key", "bin_n")}
                     | {"after": f.get_particles().cpu().numpy(), "passes": int(f.dump("counts")[1].item())})
+        f.sir_step(fr[3], 4)
+        outs[-1] |= {"sir_" + n: f.dump(n).cpu().numpy() for n in ("weights", "resample", "cdf")}
         f.close()
     for o in outs[1:]:
-        for n in ("loglik", "weights", "resample", "bin_key", "bin_n", "after"):
+        for n in ("loglik", "weights", "resample", "cdf", "bin_key", "bin_n", "after",
+                  "sir_weights", "sir_resample", "sir_cdf"):
             assert np.array_equal(o[n], outs[0][n]), n
     log(f"  sort passes per shape: {[o['passes'] for o in outs]}")
     # autotune
