@@ -203,19 +203,41 @@ __device__ __forceinline__ T wave_incl_max_scan(T v) {
   return v;
 }
 
+// Data-parallel-primitive lane moves within a row of 16 lanes (GCN / CDNA
+// dpp_ctrl codes): quad permutations [1,0,3,2] and [2,3,0,1], the mirror of
+// each half-row of 8 (lane i <-> 7 - i) and of the row (i <-> 15 - i). Each
+// pairs every lane with one in the other half of its group of 2, 4, 8, 16,
+// so that four of them in this order give every lane its row's total. They
+// move data in the vector ALU, without the LDS crossbar of a shuffle.
+constexpr int DPP_QUAD_XOR1 = 0xB1;
+constexpr int DPP_QUAD_XOR2 = 0x4E;
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_MIRROR = 0x140;
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// One level of the compensated pair sum: (s, e) += (s2, e2), the rounding
+// error of s + s2 (TwoSum) joining e.
+__device__ __forceinline__ void pair_sum_level(float &s, float &e, float s2, float e2) {
+  const float t = s + s2;
+  const float bp = t - s;
+  const float err = (s - (t - bp)) + (s2 - bp);
+  s = t;
+  e = e + e2 + err;
+}
+
 // Compensated wave reduction that keeps the result as an unevaluated pair
-// (hi, lo), returned in FP64 registers of every lane.
+// (hi, lo), returned in FP64 registers of every lane: four levels by lane
+// moves within rows of 16, then two shuffles across rows.
 __device__ __forceinline__ void wave_sum_pair(float s, float e, double &hi, double &lo) {
+  pair_sum_level(s, e, dpp_move<DPP_QUAD_XOR1>(s), dpp_move<DPP_QUAD_XOR1>(e));
+  pair_sum_level(s, e, dpp_move<DPP_QUAD_XOR2>(s), dpp_move<DPP_QUAD_XOR2>(e));
+  pair_sum_level(s, e, dpp_move<DPP_ROW_HALF_MIRROR>(s), dpp_move<DPP_ROW_HALF_MIRROR>(e));
+  pair_sum_level(s, e, dpp_move<DPP_ROW_MIRROR>(s), dpp_move<DPP_ROW_MIRROR>(e));
 #pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    const float s2 = __shfl_xor(s, o, WAVE);
-    const float e2 = __shfl_xor(e, o, WAVE);
-    const float t = s + s2;
-    const float bp = t - s;
-    const float err = (s - (t - bp)) + (s2 - bp);
-    s = t;
-    e = e + e2 + err;
-  }
+  for (int o = 16; o < WAVE; o <<= 1) pair_sum_level(s, e, __shfl_xor(s, o, WAVE), __shfl_xor(e, o, WAVE));
   hi = (double)s;
   lo = (double)e;
 }

@@ -1521,6 +1521,9 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
   // (SEPARABLE) the table of the pair exponential
   __shared__ float soff[MAX_QUAD];
   __shared__ float2 e2tbl[SEP ? EXP2_TBL : 1];
+  // SEPARABLE with H >= 1: each wave's per-axis sums (x scaled by the
+  // intensity), read by the pixels as one 8-byte LDS load per axis
+  __shared__ float2 fac[SEP ? LIK_WAVES : 1][SEP ? WAVE : 1];
   if (threadIdx.x < MAX_QUAD) soff[threadIdx.x] = (int)threadIdx.x < q ? sub_offset((int)threadIdx.x, q) : 0.0f;
   if (SEP) exp2_table_fill(e2tbl);
   __syncthreads();
@@ -1670,6 +1673,11 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
           ah = th;
           al = tl;
         }
+        if (s_on && s_part == 0) fac[SEP ? wave_id() : 0][s_axis * P + s_pixel] = make_float2(ah, al);
+        // the wave's own LDS writes before its reads of other lanes' entries
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       } else {
         if (lane < P) {
           const float cc = (float)(lane - R);
@@ -1706,10 +1714,11 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
         const int pcs = pc < P ? pc : 0, prs = pr < P ? pr : 0;
         float xh, xl, yh, yl;
         if (H >= 1) {
-          xh = __shfl(ah, pcs * H, WAVE);
-          xl = __shfl(al, pcs * H, WAVE);
-          yh = __shfl(ah, (P + prs) * H, WAVE);
-          yl = __shfl(al, (P + prs) * H, WAVE);
+          const float2 fx = fac[SEP ? wave_id() : 0][pcs], fy = fac[SEP ? wave_id() : 0][P + prs];
+          xh = fx.x;
+          xl = fx.y;
+          yh = fy.x;
+          yl = fy.y;
         } else if (P <= WAVE) {
           xh = __shfl(ah, pcs, WAVE);
           xl = __shfl(al, pcs, WAVE);
