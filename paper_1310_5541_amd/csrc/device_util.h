@@ -155,6 +155,11 @@ __device__ __forceinline__ int32_t floor_div(int32_t a, int32_t m) {
 // ---------------------------------------------------------------- wave / block primitives
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / WAVE); }
+// A value that every lane of the wave holds, moved to a scalar register.
+__device__ __forceinline__ int32_t wave_uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

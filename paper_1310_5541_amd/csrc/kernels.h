@@ -1498,8 +1498,10 @@ __global__ __launch_bounds__(TPB) void k_surr_fallback_list(const uint64_t *__re
   stage_flush(ls, 0, list, count);
 }
 
+// 2D: five waves per SIMD fit in the vector registers without spills (3D
+// would spill)
 template <int DIM, bool SIR, bool SEP, int Q, int MODE = LIK_ALL>
-__global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64_t *__restrict__ meta,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 5 : 1))) void k_lik(Params p, LikInput in, const uint64_t *__restrict__ meta,
                                              const StepDesc *__restrict__ desc, double *__restrict__ ll,
                                              SurrCheck chk = SurrCheck{0.0f, 0.0f, nullptr, nullptr, nullptr, nullptr,
                                                                        nullptr, nullptr},
@@ -1549,7 +1551,10 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
     const float ah = c2 * kh;
     exp2_neg_pair(ah, fmaf(c2, kh, -ah) + c2 * kl, e2tbl, s_ch, s_cl);
   }
-  for (uint32_t idx = blockIdx.x * LIK_WAVES + wave_id(); idx < E; idx += gridDim.x * LIK_WAVES) {
+  // one evaluation per wave: its index is wave-uniform (readfirstlane), so
+  // the evaluation's own values come through the scalar cache
+  for (uint32_t idx = __builtin_amdgcn_readfirstlane(blockIdx.x * LIK_WAVES + wave_id()); idx < E;
+       idx += gridDim.x * LIK_WAVES) {
     const uint32_t e = MODE == LIK_ALL ? idx : (MODE == LIK_STENCIL ? idx / 9u : chk.list[idx]);
     int t;
     int32_t c0, r0;
@@ -1574,18 +1579,19 @@ __global__ __launch_bounds__(TPB) void k_lik(Params p, LikInput in, const uint64
       if (DIM == 3) zpos = (double)in.state[(size_t)2 * p.NT + e];
       I0 = in.state[(size_t)(2 * DIM) * p.NT + e];
     } else {
-      t = in.seg_t[e];
-      c0 = in.dpix[e];
-      r0 = in.dpix[(size_t)p.NT + e];
-      dx = in.doff[e];
-      dy = in.doff[(size_t)p.NT + e];
-      dxl = in.dlo[e];
-      dyl = in.dlo[(size_t)p.NT + e];
+      // wave-uniform values, held in scalar registers
+      t = wave_uniform(in.seg_t[e]);
+      c0 = wave_uniform(in.dpix[e]);
+      r0 = wave_uniform(in.dpix[(size_t)p.NT + e]);
+      dx = wave_uniform(in.doff[e]);
+      dy = wave_uniform(in.doff[(size_t)p.NT + e]);
+      dxl = wave_uniform(in.dlo[e]);
+      dyl = wave_uniform(in.dlo[(size_t)p.NT + e]);
       if (DIM == 3)
         zpos = (double)in.dpix[(size_t)2 * p.NT + e] + (double)in.doff[(size_t)2 * p.NT + e] +
                (double)in.dlo[(size_t)2 * p.NT + e];
-      I0 = in.dint[e];
-      I0l = in.dlo[(size_t)DIM * p.NT + e];
+      I0 = wave_uniform(in.dint[e]);
+      I0l = wave_uniform(in.dlo[(size_t)DIM * p.NT + e]);
       if (MODE == LIK_STENCIL) {
         // the shifted position, formed in binary64 and split into a pair
         const int sidx = (int)(idx - 9u * e);
