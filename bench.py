@@ -637,7 +637,11 @@ def main():
     units = {k: NT for k in bpp}
     for k in ("sort_hist", "sort_scatter", "seg_count", "seg_mark"):
         units[k] = head["L_avg"]   # entries of the distinct-key list, mean over the timed frames
-    dom = max((k for k in k_pc if k in bpp), key=k_pc.get)
+    # the HBM-bound kernel that moves the most algorithmic bytes per step
+    # (the propagation; the bin sums take about as long with half the bytes,
+    # and every such kernel's rate is in hbm_gbs_per_kernel)
+    dom = max((k for k in k_pc if k in bpp),
+              key=lambda k: bpp[k] * units[k] * (passes if k.startswith("sort") else 1))
     launches = passes if dom.startswith("sort") else 1
     nb = bpp[dom] * units[dom] * launches
     achieved = nb / (k_pc[dom] * 1e-3) / 1e9
