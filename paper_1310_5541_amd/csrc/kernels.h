@@ -1498,6 +1498,11 @@ __global__ __launch_bounds__(TPB) void k_surr_fallback_list(const uint64_t *__re
   stage_flush(ls, 0, list, count);
 }
 
+template <int DIM, typename T>
+__device__ __forceinline__ T lik_uniform(T v) {
+  return DIM == 2 ? wave_uniform(v) : v;
+}
+
 // 2D: five waves per SIMD fit in the vector registers without spills (3D
 // would spill)
 template <int DIM, bool SIR, bool SEP, int Q, int MODE = LIK_ALL>
@@ -1523,9 +1528,11 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 
   // (SEPARABLE) the table of the pair exponential
   __shared__ float soff[MAX_QUAD];
   __shared__ float2 e2tbl[SEP ? EXP2_TBL : 1];
-  // SEPARABLE with H >= 1: each wave's per-axis sums (x scaled by the
-  // intensity), read by the pixels as one 8-byte LDS load per axis
-  __shared__ float2 fac[SEP ? LIK_WAVES : 1][SEP ? WAVE : 1];
+  // SEPARABLE with H >= 1, 2D: each wave's per-axis sums (x scaled by the
+  // intensity), read by the pixels as one 8-byte LDS load per axis (in 3D,
+  // where every evaluation forms its own PSF scale, shuffles measured faster)
+  constexpr bool FAC = SEP && DIM == 2;
+  __shared__ float2 fac[FAC ? LIK_WAVES : 1][FAC ? WAVE : 1];
   if (threadIdx.x < MAX_QUAD) soff[threadIdx.x] = (int)threadIdx.x < q ? sub_offset((int)threadIdx.x, q) : 0.0f;
   if (SEP) exp2_table_fill(e2tbl);
   __syncthreads();
@@ -1551,10 +1558,11 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 
     const float ah = c2 * kh;
     exp2_neg_pair(ah, fmaf(c2, kh, -ah) + c2 * kl, e2tbl, s_ch, s_cl);
   }
-  // one evaluation per wave: its index is wave-uniform (readfirstlane), so
-  // the evaluation's own values come through the scalar cache
-  for (uint32_t idx = __builtin_amdgcn_readfirstlane(blockIdx.x * LIK_WAVES + wave_id()); idx < E;
-       idx += gridDim.x * LIK_WAVES) {
+  // one evaluation per wave: in 2D its values are moved to scalar registers
+  // once loaded (in 3D the compiler then turned their loads into scalar-cache
+  // loads and spilled scalar registers, which measured slower)
+  const uint32_t idx0 = blockIdx.x * LIK_WAVES + wave_id();
+  for (uint32_t idx = DIM == 2 ? __builtin_amdgcn_readfirstlane(idx0) : idx0; idx < E; idx += gridDim.x * LIK_WAVES) {
     const uint32_t e = MODE == LIK_ALL ? idx : (MODE == LIK_STENCIL ? idx / 9u : chk.list[idx]);
     int t;
     int32_t c0, r0;
@@ -1579,19 +1587,19 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 
       if (DIM == 3) zpos = (double)in.state[(size_t)2 * p.NT + e];
       I0 = in.state[(size_t)(2 * DIM) * p.NT + e];
     } else {
-      // wave-uniform values, held in scalar registers
-      t = wave_uniform(in.seg_t[e]);
-      c0 = wave_uniform(in.dpix[e]);
-      r0 = wave_uniform(in.dpix[(size_t)p.NT + e]);
-      dx = wave_uniform(in.doff[e]);
-      dy = wave_uniform(in.doff[(size_t)p.NT + e]);
-      dxl = wave_uniform(in.dlo[e]);
-      dyl = wave_uniform(in.dlo[(size_t)p.NT + e]);
+      // wave-uniform values, held in scalar registers (2D)
+      t = lik_uniform<DIM>(in.seg_t[e]);
+      c0 = lik_uniform<DIM>(in.dpix[e]);
+      r0 = lik_uniform<DIM>(in.dpix[(size_t)p.NT + e]);
+      dx = lik_uniform<DIM>(in.doff[e]);
+      dy = lik_uniform<DIM>(in.doff[(size_t)p.NT + e]);
+      dxl = lik_uniform<DIM>(in.dlo[e]);
+      dyl = lik_uniform<DIM>(in.dlo[(size_t)p.NT + e]);
       if (DIM == 3)
         zpos = (double)in.dpix[(size_t)2 * p.NT + e] + (double)in.doff[(size_t)2 * p.NT + e] +
                (double)in.dlo[(size_t)2 * p.NT + e];
-      I0 = wave_uniform(in.dint[e]);
-      I0l = wave_uniform(in.dlo[(size_t)DIM * p.NT + e]);
+      I0 = lik_uniform<DIM>(in.dint[e]);
+      I0l = lik_uniform<DIM>(in.dlo[(size_t)DIM * p.NT + e]);
       if (MODE == LIK_STENCIL) {
         // the shifted position, formed in binary64 and split into a pair
         const int sidx = (int)(idx - 9u * e);
@@ -1679,11 +1687,13 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 
           ah = th;
           al = tl;
         }
-        if (s_on && s_part == 0) fac[SEP ? wave_id() : 0][s_axis * P + s_pixel] = make_float2(ah, al);
-        // the wave's own LDS writes before its reads of other lanes' entries
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (FAC) {
+          if (s_on && s_part == 0) fac[FAC ? wave_id() : 0][s_axis * P + s_pixel] = make_float2(ah, al);
+          // the wave's own LDS writes before its reads of other lanes' entries
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
       } else {
         if (lane < P) {
           const float cc = (float)(lane - R);
@@ -1719,12 +1729,17 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 
         const int pix = pix0 + lane;
         const int pcs = pc < P ? pc : 0, prs = pr < P ? pr : 0;
         float xh, xl, yh, yl;
-        if (H >= 1) {
-          const float2 fx = fac[SEP ? wave_id() : 0][pcs], fy = fac[SEP ? wave_id() : 0][P + prs];
+        if (H >= 1 && FAC) {
+          const float2 fx = fac[FAC ? wave_id() : 0][pcs], fy = fac[FAC ? wave_id() : 0][P + prs];
           xh = fx.x;
           xl = fx.y;
           yh = fy.x;
           yl = fy.y;
+        } else if (H >= 1) {
+          xh = __shfl(ah, pcs * H, WAVE);
+          xl = __shfl(al, pcs * H, WAVE);
+          yh = __shfl(ah, (P + prs) * H, WAVE);
+          yl = __shfl(al, (P + prs) * H, WAVE);
         } else if (P <= WAVE) {
           xh = __shfl(ah, pcs, WAVE);
           xl = __shfl(al, pcs, WAVE);
