@@ -1505,7 +1505,9 @@ __device__ __forceinline__ T lik_uniform(T v) {
 
 // 2D: five waves per SIMD fit in the vector registers without spills (3D
 // would spill)
-template <int DIM, bool SIR, bool SEP, int Q, int MODE = LIK_ALL>
+// PP: the window side when known at compile time (0: p.P), so that the pixel
+// rounds and the per-axis sub-sample loops have constant trip counts.
+template <int DIM, bool SIR, bool SEP, int Q, int MODE = LIK_ALL, int PP = 0>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 5 : 1))) void k_lik(Params p, LikInput in, const uint64_t *__restrict__ meta,
                                              const StepDesc *__restrict__ desc, double *__restrict__ ll,
                                              SurrCheck chk = SurrCheck{0.0f, 0.0f, nullptr, nullptr, nullptr, nullptr,
@@ -1516,7 +1518,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 
                          : (uint32_t)meta[MODE == LIK_CHECK ? META_NCHK : (MODE == LIK_FALLBACK ? META_NFB : META_B)] *
                                (MODE == LIK_STENCIL ? 9u : 1u);
   const int lane = lane_id();
-  const int P = p.P, R = p.R, P2 = P * P;
+  const int P = PP ? PP : p.P, R = PP ? (PP - 1) / 2 : p.R, P2 = P * P;
   const int q = Q ? Q : p.q;
   const ExpScale ks_flat = psf_scale(p, 0.0);  // the scale of a z-independent PSF, formed once
   // window column and row of this lane's pixel in round 0; each round of 64

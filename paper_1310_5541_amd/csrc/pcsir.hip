@@ -348,7 +348,11 @@ void launch_lik(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   double *ll = c->at<double>(c->L.ll);
   const StepDesc *desc = c->at<StepDesc>(c->L.desc);
   if (SEP) {
-    k_lik<DIM, SIR, true, 0><<<grid, TPB, 0, st>>>(c->p, in, meta, desc, ll);
+    // the common window (15 x 15 pixels, 8 x 8 sub-samples) with constant loop counts
+    if (c->p.P == 15 && c->p.q == 8)
+      k_lik<DIM, SIR, true, 8, LIK_ALL, 15><<<grid, TPB, 0, st>>>(c->p, in, meta, desc, ll);
+    else
+      k_lik<DIM, SIR, true, 0><<<grid, TPB, 0, st>>>(c->p, in, meta, desc, ll);
     return;
   }
   switch (c->p.q) {
