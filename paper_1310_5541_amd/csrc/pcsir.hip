@@ -408,13 +408,20 @@ void launch_surrogate(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   const Params &p = c->p;
   mark(c, "surr_check");
   k_surr_pick<<<pg, TPB, 0, st>>>(p, meta, desc, in.seg_t, c->surr_fraction, list_chk, meta_w + META_NCHK);
-  k_lik<DIM, false, true, 0, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
+  const bool common = p.P == 15 && p.q == 8;  // the window compiled with constant loop counts
+  if (common)
+    k_lik<DIM, false, true, 8, LIK_CHECK, 15><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
+  else
+    k_lik<DIM, false, true, 0, LIK_CHECK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
   k_surr_stats<<<1, TPB, 0, st>>>(chk.err, meta_w);
   k_surr_decide<<<(p.T + TPB - 1) / TPB, TPB, 0, st>>>(p.T, chk.tol, chk.tsse, chk.tcnt, tfb);
   mark(c, "surr_fallback");
   k_surr_fallback_list<<<pg, TPB, 0, st>>>(meta, in.seg_t, tfb, list_fb, meta_w + META_NFB);
   chk.list = list_fb;
-  k_lik<DIM, false, true, 0, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
+  if (common)
+    k_lik<DIM, false, true, 8, LIK_FALLBACK, 15><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
+  else
+    k_lik<DIM, false, true, 0, LIK_FALLBACK><<<lg, TPB, 0, st>>>(p, in, meta, desc, ll, chk, meta_w);
 }
 
 template <int DIM, bool SEP>
