@@ -401,16 +401,19 @@ __device__ __forceinline__ uint32_t particle_key(const float *__restrict__ s, ui
 }
 
 // Distinct cell keys of one key tile (at most KEYS_TILE particles of one
-// target), found with an open-addressing hash set in LDS of twice that many
-// slots (so it never fills). Larger tiles than the bin sums' repeat a cell in
+// target), found with an open-addressing hash set in LDS of as many slots
+// as the tile has particles: a tile has at most that many distinct keys, so
+// every insertion finds its key or an empty slot (typical tiles fill a few
+// percent of it), and 32 KB of LDS with two rounds of eight particles per
+// thread leave room for eight waves per SIMD. Larger tiles than the bin sums' repeat a cell in
 // fewer tiles, so the list to sort is shorter. A tile has at most as many
 // distinct keys as particles, so it writes them into its own particle range
 // of `sparse` (global index of its first particle on), and its count to
 // tcount[tile]; the last workgroup turns the counts into offsets, and
 // k_list_compact packs the tiles' keys into one list, in tile order, without
 // atomics. The list holds every occupied cell at least once.
-constexpr int DEDUP_LOG2 = 14;
-constexpr int DEDUP_SLOTS = 2 * KEYS_TILE;
+constexpr int DEDUP_LOG2 = 13;
+constexpr int DEDUP_SLOTS = KEYS_TILE;
 constexpr int DEDUP_SHIFT = 32 - DEDUP_LOG2;
 static_assert(DEDUP_SLOTS == 1 << DEDUP_LOG2, "hash slots");
 constexpr uint32_t KEY_EMPTY = 0xFFFFFFFFu;  // compacted keys are < 2^32 - 1 (checked range)
@@ -421,7 +424,7 @@ __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__re
                                               const int32_t *__restrict__ bbox_cur, const uint32_t *__restrict__ kbase,
                                               uint32_t *__restrict__ sparse, uint32_t *__restrict__ tcount,
                                               uint64_t *__restrict__ meta) {
-  constexpr int R = KEYS_TILE / KEYS_TPB;  // all of a thread's positions are loaded before use
+  constexpr int R = KEYS_TILE / KEYS_TPB / 2;  // a thread's positions of a round are loaded before use
   constexpr int PER = DEDUP_SLOTS / KEYS_TPB;
   __shared__ __attribute__((aligned(16))) uint32_t tab[DEDUP_SLOTS];
   __shared__ uint32_t lds[KEYS_TPB / WAVE];
@@ -436,7 +439,7 @@ __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__re
     reinterpret_cast<uint4 *>(tab)[i] = make_uint4(KEY_EMPTY, KEY_EMPTY, KEY_EMPTY, KEY_EMPTY);
   __syncthreads();
   for (uint32_t r0 = tl.i0; r0 < tl.i1; r0 += R * KEYS_TPB) {
-    // all positions loaded first, from clamped indices (a load under a bounds
+    // all of the round's positions loaded first, from clamped indices (a load under a bounds
     // branch would be waited for before the next one is issued), then keyed
     float xs[DIM][R];
 #pragma unroll
