@@ -405,10 +405,10 @@ __device__ __forceinline__ uint32_t particle_key(const float *__restrict__ s, ui
 // as the tile has particles: a tile has at most that many distinct keys, so
 // every insertion finds its key or an empty slot (typical tiles fill a few
 // percent of it), and 32 KB of LDS with two rounds of eight particles per
-// thread leave room for eight waves per SIMD. Larger tiles than the bin sums' repeat a cell in
-// fewer tiles, so the list to sort is shorter. A tile has at most as many
-// distinct keys as particles, so it writes them into its own particle range
-// of `sparse` (global index of its first particle on), and its count to
+// thread leave room for eight waves per SIMD. Larger tiles than the bin
+// sums' repeat a cell in fewer tiles, so the list to sort is shorter. A tile
+// has at most as many distinct keys as particles, so it writes them into its
+// own particle range of `sparse` (global index of its first particle on), and its count to
 // tcount[tile]; the last workgroup turns the counts into offsets, and
 // k_list_compact packs the tiles' keys into one list, in tile order, without
 // atomics. The list holds every occupied cell at least once.
