@@ -245,7 +245,8 @@ pcsir_status pcsir_kernel_times(pcsir_ctx *ctx, const char **names, float *ms, i
 
 /* Launch shapes of the pcSIR step. None of them changes any result: bins
  * are the sorted distinct cell keys whatever the tile size, bin sums are exact
- * integers, and no reduction depends on the grid. */
+ * integers, no reduction depends on the grid, and a scan tile's offspring get
+ * the same parents whichever resampling path resolves them. */
 typedef struct {
   int32_t bin_tile;     /* particles per work item of the bin sums: 1024, 2048 or 4096
                            (default 4096); the key deduplication takes 8192 */
