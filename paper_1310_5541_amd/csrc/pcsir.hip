@@ -384,9 +384,15 @@ void launch_surrogate(pcsir_ctx *c, const LikInput &in, hipStream_t st) {
   unsigned long long *tmax = c->at<unsigned long long>(L.tmax);
   k_clear_u64<<<(c->p.T + TPB - 1) / TPB, TPB, 0, st>>>(tmax, (uint32_t)c->p.T);
   if (c->cfg.lik_mode == PCSIR_LIK_SURR_FP8)
-    k_surr_infer<DIM, true><<<grid, SURR_TPB, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
+    if (c->p.P == 15)
+      k_surr_infer<DIM, true, 15><<<grid, SURR_TPB, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
+    else
+      k_surr_infer<DIM, true><<<grid, SURR_TPB, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
   else
-    k_surr_infer<DIM, false><<<grid, SURR_TPB, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
+    if (c->p.P == 15)
+      k_surr_infer<DIM, false, 15><<<grid, SURR_TPB, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
+    else
+      k_surr_infer<DIM, false><<<grid, SURR_TPB, 0, st>>>(c->p, dv, meta, desc, surr_weights(c), ll, tmax);
   // exact check of the picked dummies, then exact recomputation of the targets
   // that failed it; the lists reuse the sort buffers, free at this point
   uint32_t *list_chk = c->at<uint32_t>(L.kA), *list_fb = c->at<uint32_t>(L.kB);

@@ -358,7 +358,8 @@ __device__ __forceinline__ void surr_put(uint8_t *act, int m, int f, float v) {
 // (per lane, then the wave's butterfly).
 constexpr int SURR_WJ = (MLP_F + WAVE - 1) / WAVE;  // window pixels per lane (P^2 < 256)
 constexpr int SURR_FR = 2;                          // rows whose windows are loaded together
-template <int DIM, bool FP8>
+// PP: the window side when known at compile time (0: p.P).
+template <int DIM, bool FP8, int PP = 0>
 __global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) void k_surr_infer(Params p, DummyView dv, const uint64_t *__restrict__ meta,
                                                             const StepDesc *__restrict__ desc, SurrWeights sw,
                                                             double *__restrict__ ll,
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(SURR_TPB) __attribute__((amdgpu_waves_per_eu(4))) v
   const uint32_t NT = p.NT;
   const gfloat *frame = as_global(desc->frame);
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-  const int P = p.P, R = p.R, P2 = P * P, NF = P2 + 2 * DIM + 1;
+  const int P = PP ? PP : p.P, R = PP ? (PP - 1) / 2 : p.R, P2 = P * P, NF = P2 + 2 * DIM + 1;
   for (uint32_t s0 = blockIdx.x * SURR_ROWS; s0 < B; s0 += gridDim.x * SURR_ROWS) {
     if (tid < SURR_ROWS) {
       const uint32_t s = s0 + tid;
