@@ -2167,28 +2167,17 @@ __global__ __launch_bounds__(TPB) void k_cdf_prefix(const uint32_t *__restrict__
   }
 }
 
-// Number of thresholds theta_j = (j + u) / n below c, for j in [0, n).
+// Number of thresholds theta_j = (j + u) / n below c, for j in [0, n)
+// (theta_j formed as written: j + u, then divided by n, each rounded), without
+// divisions where they cannot change the answer. With x = c n - u,
+// theta_j < c holds exactly when j < x, except where j lies within about
+// 2^-52 (j + u) < 2^-20 of x (the roundings of j + u and of the division);
+// x itself comes from one fma, within 2^-20 of c n - u for x < 2^32. So when
+// x is more than 2^-10 from every integer, the count is ceil(x) (clamped to
+// [0, n]). Otherwise, with J the integer nearest x, every j <= J - 2 counts
+// and no j >= J + 1 does, and the two thresholds between are compared as
+// written.
 __device__ __forceinline__ uint32_t count_below(double c, double u, uint32_t n) {
-  if (!(c > 0.0)) return 0;
-  if (!(c < 2.0)) return n;
-  const double dn = (double)n;
-  double e = ceil(c * dn - u);
-  e = e < 0.0 ? 0.0 : (e > dn ? dn : e);
-  uint32_t j = (uint32_t)e;
-  while (j > 0 && (((double)(j - 1) + u) / dn) >= c) --j;
-  while (j < n && (((double)j + u) / dn) < c) ++j;
-  return j;
-}
-
-// count_below without divisions where they cannot change the answer. With
-// x = c n - u, theta_j < c holds exactly when j < x, except where j lies
-// within about 2^-52 (j + u) < 2^-20 of x (the roundings of j + u and of the
-// division); x itself comes from one fma, within 2^-20 of c n - u for
-// x < 2^32. So when x is more than 2^-10 from every integer, the count is
-// ceil(x) (clamped to [0, n]). Otherwise, with J the integer nearest x, every
-// j <= J - 2 counts and no j >= J + 1 does, and the two thresholds between
-// are compared as written.
-__device__ __forceinline__ uint32_t count_below_fast(double c, double u, uint32_t n) {
   if (!(c > 0.0)) return 0;
   if (!(c < 2.0)) return n;
   const double dn = (double)n;
@@ -2358,8 +2347,8 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
   // C in LDS, from where a heavy tile stores it (coalesced)
 #pragma unroll
   for (int it = 0; it < SCAN_ITEMS; ++it) cl[cpad(threadIdx.x * SCAN_ITEMS + it)] = c[it];
-  const uint32_t jlo = count_below_fast(pre, u, n);
-  const uint32_t jhi = last_tile ? n : count_below_fast(tile_end, u, n);
+  const uint32_t jlo = count_below(pre, u, n);
+  const uint32_t jhi = last_tile ? n : count_below(tile_end, u, n);
   const uint32_t M = jhi - jlo;  // offspring of the tile
   if (CDF_ONLY || M > light) {
     // heavy: C through LDS, so that the stores to global memory are coalesced
@@ -2379,14 +2368,14 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
     return;
   }
   // light: every particle's run [s, e) of offspring, relative to jlo
-  const uint32_t s_abs = count_below_fast(start, u, n);  // the thread's first run starts here
+  const uint32_t s_abs = count_below(start, u, n);  // the thread's first run starts here
   uint32_t e[SCAN_ITEMS];
   {
     uint32_t s0 = s_abs;
 #pragma unroll
     for (int it = 0; it < SCAN_ITEMS; ++it) {
       const uint32_t i = tl.i0 + threadIdx.x * SCAN_ITEMS + it;
-      const uint32_t ei = i >= n ? s0 : (i + 1 == n ? n : count_below_fast(c[it], u, n));
+      const uint32_t ei = i >= n ? s0 : (i + 1 == n ? n : count_below(c[it], u, n));
       s0 = ei > s0 ? ei : s0;
       e[it] = s0 - jlo;
     }
@@ -2458,8 +2447,8 @@ __global__ __launch_bounds__(TPB) void k_resample_search(const Tile *__restrict_
     const double u = ws.tgt[rt.t * 4 + 3];
     const double dn = (double)n;
     const uint32_t m = min((uint32_t)SCAN_TILE, n - st.i0);
-    const uint32_t lo = count_below_fast(tile_pre[pr.y], u, n);
-    const uint32_t hi = tile_last[pr.y] ? n : count_below_fast(tile_pre[pr.y + 1], u, n);
+    const uint32_t lo = count_below(tile_pre[pr.y], u, n);
+    const uint32_t hi = tile_last[pr.y] ? n : count_below(tile_pre[pr.y + 1], u, n);
     const uint32_t j0 = rt.i0, j1 = min(rt.i0 + RS_TILE, n);
     const uint32_t a0 = max(lo, j0), a1 = min(hi, j1);
     __syncthreads();  // the previous pair's searches are done with cl
