@@ -2259,7 +2259,7 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
   __shared__ double lds[TPB / WAVE];
   __shared__ uint32_t wmax[TPB / WAVE];
   __shared__ uint32_t wpos;
-  __shared__ double bound[TPB + 1];
+  __shared__ double wfirst[TPB / WAVE + 1];  // each wave's first thread boundary, and the tile's end
   __shared__ double cl[SCAN_TILE + SCAN_TILE / SCAN_ITEMS];
   static_assert(sizeof(cl) >= sizeof(uint32_t) * (RS_LIGHT_MAX + RS_LIGHT_MAX / DEC_ITEMS), "run slots fit in cl");
   uint32_t *mk = reinterpret_cast<uint32_t *>(cl);  // run slots of a light tile (after C is in registers)
@@ -2297,11 +2297,15 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
   double tot;
   const double ex = block_excl_scan_monotone<TPB>(loc, lds, &tot);
   // thread boundaries: non-decreasing, within [this tile's start, next tile's start]
+  // (each thread's end is the next thread's start: the next lane's, or the
+  // next wave's first, or the tile's end)
+  double start;
   {
     const double b = pre + ex;
-    bound[threadIdx.x] = b < tile_end ? b : tile_end;
+    start = b < tile_end ? b : tile_end;
   }
-  if (threadIdx.x == 0) bound[TPB] = tile_end;
+  if (lane_id() == 0) wfirst[wave_id()] = start;
+  if (threadIdx.x == 0) wfirst[TPB / WAVE] = tile_end;
   __syncthreads();  // also: every thread has read its weights from cl
   // kept weights: a target resamples only when N_eff < neff_frac * N
   const bool keep = ws.lw && !flag && !(neff < neff_frac * (double)n);
@@ -2323,8 +2327,8 @@ __global__ __launch_bounds__(TPB) void k_cdf_scan(const Tile *__restrict__ tiles
     return;
   }
   if (!CDF_ONLY && tuni_next && tl.i0 == 0 && threadIdx.x == 0) tuni_next[t] = 1;
-  const double start = bound[threadIdx.x];
-  double end = bound[threadIdx.x + 1];
+  double end = __shfl_down(start, 1, WAVE);
+  if (lane_id() == WAVE - 1) end = wfirst[wave_id() + 1];
   if (end < start) end = start;
   double run = 0.0;
   double cprev = start;
