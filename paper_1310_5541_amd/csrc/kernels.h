@@ -1683,9 +1683,14 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 
           }
         }
         float th = ah, tl = al;
-        for (int h = 1; h < H; ++h) {
-          const int src = (lane + h) & (WAVE - 1);
-          pair_acc(th, tl, __shfl(ah, src, WAVE), __shfl(al, src, WAVE));
+        if (H == 2) {
+          // the sum's other lane is lane ^ 1 (only the even lane's total is read)
+          pair_acc(th, tl, dpp_move<DPP_QUAD_XOR1>(ah), dpp_move<DPP_QUAD_XOR1>(al));
+        } else {
+          for (int h = 1; h < H; ++h) {
+            const int src = (lane + h) & (WAVE - 1);
+            pair_acc(th, tl, __shfl(ah, src, WAVE), __shfl(al, src, WAVE));
+          }
         }
         if (s_axis == 0) pair_mul(Iqh, Iql, th, tl, ah, al);
         else {
