@@ -726,7 +726,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "targets": T, "particles": NT, "frame": [w.H, w.W], "patch": w.patch,
                    "quad": w.quad, "likelihood": "exact, separable", "h_matched": h_match, "bins_at_h": B_pc,
-                   "distinct_tile_keys": Llist, "sort_passes": passes, "graphs": "one graph launch per frame"},
+                   "distinct_tile_keys": Llist, "sort_passes": passes,
+                   "bin_numbering": "radix sort" if tuned.get("shapes", {}).get("sort_bins") else "occupancy bitmap",
+                   "graphs": "one graph launch per frame"},
         "modes": {k: {"value": round(v, 1), "ms_per_step": round(1e3 * runs[k]["el"] / steps, 4),
                       "ms_per_step_event_timed": round(1e3 * runs[k]["el_ev"] / steps, 4)}
                   for k, v in val.items()},

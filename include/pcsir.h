@@ -129,8 +129,9 @@ typedef struct {
 } pcsir_config;
 
 /* Bytes of device workspace that a context with this config needs (0 if the
- * config is invalid). Grows linearly with sum N_t (about 175 B per particle
- * in 2D) and with T. */
+ * config is invalid): a fixed 768 MiB for the cell-occupancy bitmap (one bit
+ * per 32-bit cell key, and a 32-bit first bin per 64-bit word), plus a part
+ * that grows linearly with sum N_t (about 175 B per particle in 2D) and with T. */
 size_t pcsir_workspace_bytes(const pcsir_config *cfg);
 
 /* Create a context. init_state_dev: SoA [D][sum N] float32, copied into the
@@ -183,8 +184,9 @@ pcsir_status pcsir_set_particles(pcsir_ctx *ctx, const float *src_dev);
  * except PCSIR_DUMP_COUNTS, which synchronises. Layouts:
  *  PROPAGATED  float32 [D][sum N]   propagated states x~_k (before resampling)
  *  KEYS        int32   [3][sum N]   cell index (kx, ky, kz) of every particle; SIR: pixel index
- *  COUNTS      int64   [2] or [3]   (bins B over all targets, passes of the sort, length of the sorted
- *                                   list of distinct per-tile cell keys); the third when bytes >= 24
+ *  COUNTS      int64   [2] or [3]   (bins B over all targets, passes of the sort (0 with bins from the
+ *                                   occupancy bitmap), number of distinct per-tile cell keys); the
+ *                                   third when bytes >= 24
  *  BIN_TARGET  int32   [B]          target of every bin; bins in ascending (target, kz, ky, kx)
  *  BIN_KEY     int32   [3][B]       cell index of every bin
  *  BIN_N       int64   [B]          members per bin
@@ -251,7 +253,7 @@ typedef struct {
   int32_t bin_tile;     /* particles per work item of the bin sums: 1024, 2048 or 4096
                            (default 4096); the key deduplication takes 8192 */
   int32_t list_blocks;  /* workgroups of the sort and segment passes over the list of
-                           distinct keys: 64 .. 2048 (default 1024) */
+                           distinct keys (sort_bins = 1): 64 .. 2048 (default 1024) */
   int32_t digit_bits;   /* widest digit of the radix sort, 6 .. 11 (default 11); the
                            width actually used is the narrowest that keeps the fewest passes */
   int32_t grid_per_cu;  /* workgroups per compute unit of the grid-stride kernels
@@ -260,6 +262,10 @@ typedef struct {
                            scan resolves itself, from its cumulative weights on chip:
                            0 .. 4096 (default 4096); a tile with more offspring stores its
                            cumulative weights, and blocks of 1024 new particles resolve them */
+  int32_t sort_bins;    /* how the bins are numbered (the same bins either way: the occupied
+                           cells in ascending key order): 0 (default) from a bitmap of the
+                           occupied cells, one bit per cell key, and a popcount scan over its
+                           words; 1 by a radix sort of the list of distinct per-tile keys */
 } pcsir_tuning;
 
 /* Current launch shapes. */
@@ -271,8 +277,9 @@ pcsir_status pcsir_get_tuning(const pcsir_ctx *ctx, pcsir_tuning *out);
 pcsir_status pcsir_set_tuning(pcsir_ctx *ctx, const pcsir_tuning *tuning);
 
 /* Self-tuning of the launch shapes on the caller's data: a coordinate search,
- * one field at a time in the order above, over bin_tile {1024, 2048, 4096},
- * list_blocks {256, 512, 1024, 2048}, digit_bits {8, 9, 10, 11},
+ * one field at a time, over sort_bins {0, 1} first, then in the order above
+ * bin_tile {1024, 2048, 4096}, list_blocks {256, 512, 1024, 2048} and
+ * digit_bits {8, 9, 10, 11} (these two only when the sort numbers the bins),
  * grid_per_cu {8, 16, 32, 64} and resample_light {1024, 2048, 4096},
  * keeping the best setting of each field before moving to the next. A trial
  * restores the particles, runs one untimed pcsir_step on `frame_dev` with

@@ -53,7 +53,8 @@ _lib = None
 class Tuning(C.Structure):
     """Python mirror of ``pcsir_tuning`` (launch shapes; results do not depend on them)."""
     _fields_ = [("bin_tile", C.c_int32), ("list_blocks", C.c_int32), ("digit_bits", C.c_int32),
-                ("grid_per_cu", C.c_int32), ("resample_light", C.c_int32)]
+                ("grid_per_cu", C.c_int32), ("resample_light", C.c_int32),
+                ("sort_bins", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

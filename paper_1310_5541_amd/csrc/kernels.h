@@ -51,6 +51,15 @@ enum {
   META_N = 15
 };
 
+// Cell-occupancy bitmap: one bit per compacted cell key, 64 keys per word, as
+// many words as cover every 32-bit key (512 MB), so it holds any key range
+// the step accepts. Words in use for a key range of `range` keys:
+constexpr uint64_t BM_WORDS = 1ull << 26;
+__device__ __host__ __forceinline__ uint32_t bm_words(uint64_t range) {
+  const uint64_t r = range < (1ull << 32) ? range : (1ull << 32);
+  return (uint32_t)((r + 63) >> 6);
+}
+
 // Values one workgroup hands to another within a launch go through memory,
 // not through the XCD's own L2 (which the other workgroup's XCD does not
 // see): an agent-scope store writes through, and once the storing thread's
@@ -146,8 +155,10 @@ struct BinTile {
 // (pcSIR), each tile of TPB particles writes the extremes of its new
 // positions as the cell index clamps them (and, with adaptive bins, their
 // sums and squares) for k_bbox_reduce, and the bin accumulators that the
-// previous frame used (meta[META_DIRTY] of them) are cleared. A block takes
-// PROP_TILES tiles, so that their loads are in flight together.
+// previous frame used (meta[META_DIRTY] of them) are cleared, as are the words
+// of the cell-occupancy bitmap (bm) below the previous frame's key range, the
+// only ones its key pass can have set. A block takes PROP_TILES tiles, so that
+// their loads are in flight together.
 template <int DIM, bool KEYS>
 __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restrict__ tiles, uint32_t ntiles,
                                                    const uint32_t *__restrict__ off, const float *__restrict__ sin,
@@ -155,9 +166,14 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
                                                    int pending, const StepDesc *__restrict__ desc,
                                                    float *__restrict__ bbox_part, double *__restrict__ mom_part,
                                                    unsigned long long *__restrict__ acc,
-                                                   const uint64_t *__restrict__ meta) {
+                                                   const uint64_t *__restrict__ meta,
+                                                   unsigned long long *__restrict__ bm) {
   constexpr int D = 2 * DIM + 1;
   constexpr int K = PROP_TILES;
+  if (KEYS && bm) {
+    const uint32_t nw = bm_words(meta[META_RANGE]);
+    for (uint32_t w = blockIdx.x * TPB + threadIdx.x; w < nw; w += gridDim.x * TPB) bm[w] = 0ull;
+  }
   // the block's K tiles: their ancestor loads, then their state loads, are
   // issued together (a duplicate of the last tile pads the last block and
   // writes nothing)
@@ -311,7 +327,8 @@ __device__ __forceinline__ void bbox_scan(int T, const unsigned long long *__res
       bits = 32;
     }
     // fewest passes of at most max_bits bits, digits as narrow as that allows
-    const int passes = (bits + max_bits - 1) / max_bits;
+    // (max_bits = 0: bins numbered from the occupancy bitmap, no sort)
+    const int passes = max_bits > 0 ? (bits + max_bits - 1) / max_bits : 0;
     const int width = passes ? (bits + passes - 1) / passes : 1;
     meta[META_PASSES] = (uint64_t)passes;
     meta[META_DIGIT] = (uint64_t)width;
@@ -412,18 +429,28 @@ __device__ __forceinline__ uint32_t particle_key(const float *__restrict__ s, ui
 // tcount[tile]; the last workgroup turns the counts into offsets, and
 // k_list_compact packs the tiles' keys into one list, in tile order, without
 // atomics. The list holds every occupied cell at least once.
+// With the occupancy bitmap (bm) a tile instead sets the bits of its distinct
+// keys and adds its key count to the list length, which is then only
+// reported: the keys are first merged by bitmap word in a second LDS table
+// (cells next to each other along x share a word), and each word then takes
+// one 64-bit atomic OR to memory; a key that finds no free slot within a few
+// probes goes to memory by itself.
 constexpr int DEDUP_LOG2 = 13;
 constexpr int DEDUP_SLOTS = KEYS_TILE;
 constexpr int DEDUP_SHIFT = 32 - DEDUP_LOG2;
 static_assert(DEDUP_SLOTS == 1 << DEDUP_LOG2, "hash slots");
 constexpr uint32_t KEY_EMPTY = 0xFFFFFFFFu;  // compacted keys are < 2^32 - 1 (checked range)
+constexpr int WORD_SLOTS_LOG2 = 11;          // bitmap words of a key tile merged in LDS
+constexpr int WORD_SLOTS = 1 << WORD_SLOTS_LOG2;
+constexpr int WORD_PROBES = 8;
+static_assert(WORD_SLOTS * 12 <= DEDUP_SLOTS * 4, "the word table reuses the key table's LDS");
 
 template <int DIM>
 __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__restrict__ tiles,
                                               const uint32_t *__restrict__ off, const float *__restrict__ s,
                                               const int32_t *__restrict__ bbox_cur, const uint32_t *__restrict__ kbase,
                                               uint32_t *__restrict__ sparse, uint32_t *__restrict__ tcount,
-                                              uint64_t *__restrict__ meta) {
+                                              uint64_t *__restrict__ meta, unsigned long long *__restrict__ bm) {
   constexpr int R = KEYS_TILE / KEYS_TPB / 2;  // a thread's positions of a round are loaded before use
   constexpr int PER = DEDUP_SLOTS / KEYS_TPB;
   __shared__ __attribute__((aligned(16))) uint32_t tab[DEDUP_SLOTS];
@@ -478,6 +505,49 @@ __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__re
     }
   }
   __syncthreads();
+  if (bm) {
+    uint32_t ks[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) ks[j] = tab[j * KEYS_TPB + threadIdx.x];
+    __syncthreads();
+    // the key table's LDS becomes the word table: word numbers, then their masks
+    uint32_t *wkey = tab;
+    unsigned long long *wmask = reinterpret_cast<unsigned long long *>(tab + WORD_SLOTS);
+    for (int i = threadIdx.x; i < WORD_SLOTS; i += KEYS_TPB) {
+      wkey[i] = KEY_EMPTY;
+      wmask[i] = 0ull;
+    }
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const uint32_t k = ks[j];
+      if (k == KEY_EMPTY) continue;
+      ++c;
+      const uint32_t wd = k >> 6;  // below 2^26: never KEY_EMPTY
+      const unsigned long long bit = 1ull << (k & 63u);
+      uint32_t h = (wd * 0x9E3779B1u) >> (32 - WORD_SLOTS_LOG2);
+      bool merged = false;
+      for (int pr = 0; pr < WORD_PROBES; ++pr) {
+        const uint32_t v = atomicCAS(&wkey[h], KEY_EMPTY, wd);
+        if (v == KEY_EMPTY || v == wd) {
+          atomicOr(&wmask[h], bit);
+          merged = true;
+          break;
+        }
+        h = (h + 1) & (WORD_SLOTS - 1);
+      }
+      if (!merged) atomicOr(&bm[wd], bit);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < WORD_SLOTS; i += KEYS_TPB) {
+      const uint32_t wd = wkey[i];
+      if (wd != KEY_EMPTY) atomicOr(&bm[wd], wmask[i]);
+    }
+    const uint32_t tot = block_sum<KEYS_TPB, uint32_t>(c, lds);
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&meta[META_L], (unsigned long long)tot);
+    return;
+  }
   // thread t reads 16-byte groups t, t + KEYS_TPB, ... of slots (consecutive
   // lanes, consecutive banks), once, and keeps them for the write
   uint4 sl[PER / 4];
@@ -835,6 +905,115 @@ __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs
   }
 }
 
+// ---------------------------------------------------------------- bins from the occupancy bitmap
+// The same bins as the sorted list gives (distinct occupied cells, numbered in
+// ascending key order), without a sort: a bin is a set bit of the bitmap that
+// k_keys fills, and its number is the count of set bits below it. The G
+// workgroups each take a contiguous share of the words in use. k_map_count
+// counts the bits of its share. k_map_rank sums the counts of the shares
+// before its own (at most a few thousand loads, instead of one workgroup
+// waiting for all others), then writes every word's first bin (bpre), every
+// bin's key and target, and the first bin of every target whose key base
+// falls in its share; the last workgroup writes the bin count B (and
+// seg_first[T] = B). A particle with key k is in bin bpre[k / 64] plus the
+// number of set bits of word k / 64 below bit k % 64.
+__global__ __launch_bounds__(TPB) void k_map_count(uint32_t G, const unsigned long long *__restrict__ bm,
+                                                   const uint64_t *__restrict__ meta,
+                                                   uint32_t *__restrict__ chunk_count) {
+  __shared__ uint32_t lds[TPB / WAVE];
+  const uint32_t nw = bm_words(meta[META_RANGE]);
+  uint32_t j0, j1;
+  list_range(nw, G, blockIdx.x, j0, j1);
+  uint32_t c = 0;
+  for (uint32_t j = j0 + threadIdx.x; j < j1; j += TPB) c += (uint32_t)__popcll(bm[j]);
+  const uint32_t s = block_sum<TPB, uint32_t>(c, lds);
+  if (threadIdx.x == 0) chunk_count[blockIdx.x] = s;
+}
+
+// First t in [0, T) with kb[t] >= key (T if none); kb ascending.
+template <typename KB>
+__device__ __forceinline__ int first_target_at(uint32_t key, int T, KB kb) {
+  int lo = 0, hi = T;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (kb[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(TPB) void k_map_rank(Params p, uint32_t G, uint64_t *__restrict__ meta,
+                                                  const uint32_t *__restrict__ chunk_count,
+                                                  const uint32_t *__restrict__ kbase,
+                                                  const unsigned long long *__restrict__ bm,
+                                                  uint32_t *__restrict__ bpre, uint32_t *__restrict__ seg_key,
+                                                  int32_t *__restrict__ seg_t, uint32_t *__restrict__ seg_first) {
+  __shared__ uint32_t lds[TPB / WAVE];
+  __shared__ uint32_t kb_lds[KBASE_LDS];
+  __shared__ uint32_t wpre[TPB];
+  __shared__ unsigned long long wbits[TPB];
+  const bool kb_in_lds = p.T <= KBASE_LDS;
+  if (kb_in_lds)
+    for (int t = threadIdx.x; t < p.T; t += TPB) kb_lds[t] = kbase[t];
+  __syncthreads();
+  const uint32_t nw = bm_words(meta[META_RANGE]);
+  uint32_t j0, j1;
+  list_range(nw, G, blockIdx.x, j0, j1);
+  uint32_t before = 0;
+  for (uint32_t b = threadIdx.x; b < blockIdx.x; b += TPB) before += chunk_count[b];
+  uint32_t base = block_sum<TPB, uint32_t>(before, lds);
+  for (uint32_t r0 = j0; r0 < j1; r0 += TPB) {
+    const uint32_t j = r0 + threadIdx.x;
+    const unsigned long long wd = j < j1 ? bm[j] : 0ull;
+    uint32_t tot;
+    const uint32_t pre = base + block_excl_scan<TPB, uint32_t>((uint32_t)__popcll(wd), lds, &tot);
+    if (j < j1) bpre[j] = pre;
+    wpre[threadIdx.x] = pre;
+    wbits[threadIdx.x] = wd;
+    // the word's bins in key order: key and target of each (the target of
+    // its first bin by a search, then moved on at each key base passed)
+    unsigned long long rest = wd;
+    uint32_t r = pre;
+    if (rest) {
+      const uint32_t k0 = j * 64u + (uint32_t)__builtin_ctzll(rest);
+      int t = kb_in_lds ? key_target(k0, p.T, (const uint32_t *)kb_lds) : key_target(k0, p.T, kbase);
+      auto next_base = [&](int u) -> uint64_t {
+        return u + 1 < p.T ? (uint64_t)(kb_in_lds ? kb_lds[u + 1] : kbase[u + 1]) : (1ull << 32);
+      };
+      uint64_t nb = next_base(t);
+      while (rest) {
+        const uint32_t k = j * 64u + (uint32_t)__builtin_ctzll(rest);
+        while ((uint64_t)k >= nb) nb = next_base(++t);
+        if (r < p.NT) {  // always: every set bit is the cell of a particle of this frame
+          seg_key[r] = k;
+          seg_t[r] = t;
+        }
+        ++r;
+        rest &= rest - 1ull;
+      }
+    }
+    __syncthreads();
+    // first bin of every target whose key base lies in this round's words
+    const uint32_t klo = r0 * 64u;
+    const uint64_t khi = (uint64_t)min(r0 + (uint32_t)TPB, j1) * 64u;
+    const int t0 = kb_in_lds ? first_target_at(klo, p.T, (const uint32_t *)kb_lds) : first_target_at(klo, p.T, kbase);
+    for (int t = t0 + (int)threadIdx.x; t < p.T; t += TPB) {
+      const uint32_t kt = kbase[t];
+      if ((uint64_t)kt >= khi) break;  // key bases ascend
+      if (kt < klo) continue;          // only with an overflowed key range (reported)
+      const uint32_t wl = (kt >> 6) - r0;
+      seg_first[t] = wpre[wl] + (uint32_t)__popcll(wbits[wl] & ((1ull << (kt & 63u)) - 1ull));
+    }
+    __syncthreads();
+    base += tot;
+  }
+  if (blockIdx.x == G - 1 && threadIdx.x == 0) {
+    meta[META_B] = base;
+    meta[META_DIRTY] = base;  // accumulators [0, B) are written this frame
+    seg_first[p.T] = base;
+  }
+}
+
 // Members' sums of every bin as exact fixed-point integers: count, offsets of
 // the positions from the pixel that holds them (the pixel of a cell is the
 // pixel of each member, so x - pixel is exact and |.| <= 1/2), velocities and
@@ -842,10 +1021,12 @@ __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs
 // one target's tile and recomputes each particle's cell key. The target's
 // bins are taken in LDS chunks of BINS: for each chunk, the tile's particles
 // whose bin falls in it accumulate in LDS with 64-bit integer atomics, then
-// each bin of the chunk is flushed to HBM once. A particle's bin is one load
-// from this frame's cell -> bin table when the frame's key range fits it
-// (then the tile is loaded once for all chunks); otherwise a binary search
-// over the chunk's keys, staged in LDS, with the tile read once per chunk.
+// each bin of the chunk is flushed to HBM once. A particle's bin comes from
+// the occupancy bitmap (two loads and a popcount) or, with bins from the
+// sorted list, from this frame's cell -> bin table when the frame's key range
+// fits it (one load); either way the tile is loaded once for all chunks.
+// Otherwise it is a binary search over the chunk's keys, staged in LDS, with
+// the tile read once per chunk.
 // Integer sums are exact, so the result does not depend on order. Also
 // writes every particle's bin number.
 // MOM2 (second-order dummies, 2D) adds the second moments of the offsets:
@@ -909,13 +1090,16 @@ __global__ __launch_bounds__((BinLds<DIM, MOM2>::NTH)) void k_bin_sums(Params p,
                                                   const uint32_t *__restrict__ seg_first,
                                                   unsigned long long *__restrict__ acc, uint32_t *__restrict__ segid,
                                                   uint64_t *__restrict__ meta, const uint32_t *__restrict__ lut,
-                                                  uint64_t lut_cap) {
+                                                  uint64_t lut_cap, const unsigned long long *__restrict__ bm,
+                                                  const uint32_t *__restrict__ bpre) {
   constexpr int D = 2 * DIM + 1;
   constexpr int NC = BinLds<DIM, MOM2>::NC;
   static_assert(!MOM2 || DIM == 2, "second moments in 2D only");
-  // with the cell -> bin table of this frame (total key range within its
-  // capacity) a particle's bin is one load; otherwise a binary search
-  const bool use_lut = meta[META_RANGE] <= lut_cap;
+  // bins numbered from the occupancy bitmap (bm): a particle's bin is its
+  // word's first bin plus a popcount; with the sorted list, the cell -> bin
+  // table of this frame (total key range within its capacity) gives it in
+  // one load, and otherwise a binary search does
+  const bool use_lut = bm != nullptr || meta[META_RANGE] <= lut_cap;
   constexpr int BINS = BinLds<DIM, MOM2>::BINS;
   constexpr int R = BinLds<DIM, MOM2>::R;
   constexpr int NTH = BinLds<DIM, MOM2>::NTH;
@@ -956,8 +1140,16 @@ __global__ __launch_bounds__((BinLds<DIM, MOM2>::NTH)) void k_bin_sums(Params p,
       for (int a = 0; a < DIM; ++a) cc[a] = cell_index(x[q][a], p.tm[t * 3 + a]);
       bin[q] = compact_key<DIM>(cc, bb, kb);
     }
+    if (bm) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) bin[q] = lut[bin[q]];
+      for (int q = 0; q < R; ++q) {
+        const uint32_t k = bin[q];
+        bin[q] = bpre[k >> 6] + (uint32_t)__popcll(bm[k >> 6] & ((1ull << (k & 63u)) - 1ull));
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) bin[q] = lut[bin[q]];
+    }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const uint32_t i = tl.i0 + q * NTH + threadIdx.x;

@@ -24,7 +24,7 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint, dlo,
-      ll, ll9, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first,
+      ll, ll9, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first, bm, bpre,
       bbox_part, mom_part, tm, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf, rs_work, rs_count,
       tiles256, tilesS, tilesR, tilesB, tilesK, tile_last, tfirst, tfirstR, t256_first, off;
   size_t total;
@@ -218,6 +218,9 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.lut_cap = 1ull << 16;
   while (L.lut_cap < 8 * NT && L.lut_cap < (1ull << 25)) L.lut_cap <<= 1;
   L.lut = take(4 * L.lut_cap);
+  // cell-occupancy bitmap over every 32-bit key (512 MB) and each word's first bin (256 MB)
+  L.bm = take(8 * BM_WORDS);
+  L.bpre = take(4 * BM_WORDS);
   L.tile_last = take(4 * (size_t)L.nS);
   L.tfirst = take(4 * (T + 1));
   L.tfirstR = take(4 * (T + 1));
@@ -256,7 +259,7 @@ struct pcsir_ctx {
   float surr_fraction = 0.01f, surr_tol = 1.0f;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2][2][2] = {};
-  pcsir_tuning tune{BIN_TILE_MAX, 1024, MAX_DIGIT_BITS, 32, RS_LIGHT_DEFAULT};
+  pcsir_tuning tune{BIN_TILE_MAX, 1024, MAX_DIGIT_BITS, 32, RS_LIGHT_DEFAULT, 0};
   uint32_t nB = 0;  // bin tiles of the current tile size
 
   template <typename T>
@@ -442,6 +445,10 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   float *sout = c->state(1 - c->cur);
   uint32_t *anc = c->at<uint32_t>(L.anc);
   uint64_t *meta = c->at<uint64_t>(L.meta);
+  // bins numbered by the radix sort of the distinct keys, or (default) from the occupancy bitmap
+  const bool sort_bins = c->tune.sort_bins != 0;
+  unsigned long long *bm = sort_bins ? nullptr : c->at<unsigned long long>(L.bm);
+  uint32_t *bpre = sort_bins ? nullptr : c->at<uint32_t>(L.bpre);
 
   const bool keep = keeps_weights(&c->cfg);
   int32_t *tuni = keep ? c->at<int32_t>(L.tuni) : nullptr;
@@ -451,59 +458,70 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   mark(c, "propagate");
   k_propagate<DIM, true><<<(L.n256 + PROP_TILES - 1) / PROP_TILES, TPB, 0, st>>>(
       p, t256, L.n256, off, sin, sout, anc, c->pending, desc, c->at<float>(L.bbox_part), c->at<double>(L.mom_part),
-      c->at<unsigned long long>(L.acc), meta);
+      c->at<unsigned long long>(L.acc), meta, c->at<unsigned long long>(L.bm));
   mark(c, "bbox");
   k_bbox_reduce<<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.t256_first), off, c->at<float>(L.bbox_part),
                                      c->at<double>(L.mom_part), c->at<int32_t>(L.tm), c->at<int32_t>(L.bbox_cur),
                                      c->at<unsigned long long>(L.range), c->at<int32_t>(L.tfb),
-                                     c->at<uint32_t>(L.kbase), meta, c->tune.digit_bits);
+                                     c->at<uint32_t>(L.kbase), meta, sort_bins ? c->tune.digit_bits : 0);
   mark(c, "keys");
-  // distinct keys per tile into the tile's own range of kA, then packed into key (the sort's input)
+  // distinct keys per tile: their bits in the occupancy bitmap, or into the
+  // tile's own range of kA, then packed into key (the sort's input)
   k_keys<DIM><<<L.nK, KEYS_TPB, 0, st>>>(p, c->at<BinTile>(L.tilesK), off, sout, c->at<int32_t>(L.bbox_cur),
                                          c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.kA), c->at<uint32_t>(L.tcount),
-                                         meta);
-  k_list_compact<<<L.nK, TPB, 0, st>>>(c->at<BinTile>(L.tilesK), off, c->at<uint32_t>(L.tcount), L.nK, meta,
-                                        c->at<uint32_t>(L.kA), c->at<uint32_t>(L.key));
-  SortBufs sb = sort_bufs(c);
-  uint32_t *hist = c->at<uint32_t>(L.hist);
-  uint32_t *dtot = c->at<uint32_t>(L.dtot);
+                                         meta, bm);
   const uint32_t G = std::min<uint32_t>(L.G, (uint32_t)c->tune.list_blocks);
-  const int max_passes = (32 + c->tune.digit_bits - 1) / c->tune.digit_bits;
-  for (int pass = 0; pass < max_passes; ++pass) {
-    const uint32_t *kin = pass == 0 ? sb.key_store : ((pass & 1) ? sb.kB : sb.kA);
-    uint32_t *kout = (uint32_t *)((pass & 1) ? sb.kA : sb.kB);
-    mark(c, "sort_hist");
-    k_sort_hist<<<G, TPB, 0, st>>>(pass, kin, hist, G, meta);
-    mark(c, "sort_scan");
-    k_sort_scan<<<MAX_BUCKETS, TPB, 0, st>>>(pass, hist, G, dtot, meta);
-    mark(c, "sort_scatter");
-    k_sort_scatter<<<G, TPB, 0, st>>>(pass, kin, kout, hist, G, dtot, meta);
-  }
   uint32_t *chunk = c->at<uint32_t>(L.chunk_heads);
   unsigned long long *acc = c->at<unsigned long long>(L.acc);
-  mark(c, "seg_count");
-  k_seg_count<<<G, TPB, 0, st>>>(G, p.T, sb, meta, chunk, c->at<uint32_t>(L.seg_first));
-  mark(c, "seg_mark");
-  k_seg_mark<<<G, TPB, 0, st>>>(p, G, sb, meta, chunk, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
-                                  c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.lut), L.lut_cap,
-                                  c->at<uint32_t>(L.seg_first));
+  if (sort_bins) {
+    k_list_compact<<<L.nK, TPB, 0, st>>>(c->at<BinTile>(L.tilesK), off, c->at<uint32_t>(L.tcount), L.nK, meta,
+                                          c->at<uint32_t>(L.kA), c->at<uint32_t>(L.key));
+    SortBufs sb = sort_bufs(c);
+    uint32_t *hist = c->at<uint32_t>(L.hist);
+    uint32_t *dtot = c->at<uint32_t>(L.dtot);
+    const int max_passes = (32 + c->tune.digit_bits - 1) / c->tune.digit_bits;
+    for (int pass = 0; pass < max_passes; ++pass) {
+      const uint32_t *kin = pass == 0 ? sb.key_store : ((pass & 1) ? sb.kB : sb.kA);
+      uint32_t *kout = (uint32_t *)((pass & 1) ? sb.kA : sb.kB);
+      mark(c, "sort_hist");
+      k_sort_hist<<<G, TPB, 0, st>>>(pass, kin, hist, G, meta);
+      mark(c, "sort_scan");
+      k_sort_scan<<<MAX_BUCKETS, TPB, 0, st>>>(pass, hist, G, dtot, meta);
+      mark(c, "sort_scatter");
+      k_sort_scatter<<<G, TPB, 0, st>>>(pass, kin, kout, hist, G, dtot, meta);
+    }
+    mark(c, "seg_count");
+    k_seg_count<<<G, TPB, 0, st>>>(G, p.T, sb, meta, chunk, c->at<uint32_t>(L.seg_first));
+    mark(c, "seg_mark");
+    k_seg_mark<<<G, TPB, 0, st>>>(p, G, sb, meta, chunk, c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
+                                    c->at<int32_t>(L.seg_t), c->at<uint32_t>(L.lut), L.lut_cap,
+                                    c->at<uint32_t>(L.seg_first));
+  } else {
+    // as many workgroups as the list passes may have: most take one round of TPB words
+    mark(c, "map_count");
+    k_map_count<<<L.G, TPB, 0, st>>>(L.G, bm, meta, chunk);
+    mark(c, "map_rank");
+    k_map_rank<<<L.G, TPB, 0, st>>>(p, L.G, meta, chunk, c->at<uint32_t>(L.kbase), bm, bpre,
+                                    c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t),
+                                    c->at<uint32_t>(L.seg_first));
+  }
   mark(c, "bin_sums");
   if constexpr (DIM == 2) {
     if (c->cfg.dummy_mode == PCSIR_DUMMY_COM2)
       k_bin_sums<DIM, true><<<c->nB, BinLds<DIM, true>::NTH, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
-                                        c->at<uint32_t>(L.lut), L.lut_cap);
+                                        c->at<uint32_t>(L.lut), L.lut_cap, bm, bpre);
     else
       k_bin_sums<DIM><<<c->nB, BinLds<DIM>::NTH, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
-                                        c->at<uint32_t>(L.lut), L.lut_cap);
+                                        c->at<uint32_t>(L.lut), L.lut_cap, bm, bpre);
   } else {
     k_bin_sums<DIM><<<c->nB, BinLds<DIM>::NTH, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
-                                        c->at<uint32_t>(L.lut), L.lut_cap);
+                                        c->at<uint32_t>(L.lut), L.lut_cap, bm, bpre);
   }
   if (keep) {
     mark(c, "bin_wsums");
@@ -594,7 +612,7 @@ void launch_sir(pcsir_ctx *c, hipStream_t st) {
                                                       (uint32_t)p.T);
   mark(c, "propagate");
   k_propagate<DIM, false><<<(L.n256 + PROP_TILES - 1) / PROP_TILES, TPB, 0, st>>>(
-      p, t256, L.n256, off, sin, sout, anc, c->pending, desc, nullptr, nullptr, nullptr, meta);
+      p, t256, L.n256, off, sin, sout, anc, c->pending, desc, nullptr, nullptr, nullptr, meta, nullptr);
   LikInput in;
   memset(&in, 0, sizeof(in));
   in.state = sout;
@@ -825,6 +843,7 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tsse, 0, 8 * (size_t)T, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tcnt, 0, 4 * (size_t)T, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.acc, 0, 8 * (size_t)c->p.acc_rows * c->NT, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.bm, 0, 8 * BM_WORDS, c->stream);  // each step clears what it set
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->state(0), init_state_dev, 4 * (size_t)D * c->NT, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) {
@@ -1087,6 +1106,7 @@ pcsir_status pcsir_set_tuning(pcsir_ctx *c, const pcsir_tuning *t) {
   if (t->grid_per_cu < 4 || t->grid_per_cu > 64) return fail(c, PCSIR_E_INVAL, "grid_per_cu must lie in [4, 64]");
   if (t->resample_light < 0 || t->resample_light > RS_LIGHT_MAX)
     return fail(c, PCSIR_E_INVAL, "resample_light must lie in [0, 4096]");
+  if (t->sort_bins != 0 && t->sort_bins != 1) return fail(c, PCSIR_E_INVAL, "sort_bins must be 0 or 1");
   drop_graphs(c);  // captured graphs hold the launch shapes
   if (t->bin_tile != c->tune.bin_tile) {
     std::vector<BinTile> tB;
@@ -1136,14 +1156,16 @@ pcsir_status pcsir_autotune(pcsir_ctx *c, const float *frame_dev, int32_t H, int
   float best_ms = 0.0f;
   s = trial(best, &best_ms);
   const int tiles[] = {1024, 2048, BIN_TILE_MAX}, blocks[] = {256, 512, 1024, 2048}, bits[] = {8, 9, 10, 11},
-            grids[] = {8, 16, 32, 64}, lights[] = {1024, 2048, 4096};
-  const int *cands[5] = {tiles, blocks, bits, grids, lights};
-  const int ncand[5] = {3, 4, 4, 4, 3};
-  for (int f = 0; f < 5 && s == PCSIR_OK; ++f) {
+            grids[] = {8, 16, 32, 64}, lights[] = {1024, 2048, 4096}, numbering[] = {0, 1};
+  // the bin numbering first, so that the list and sort shapes are tuned for the one chosen
+  const int *cands[6] = {numbering, tiles, blocks, bits, grids, lights};
+  const int ncand[6] = {2, 3, 4, 4, 4, 3};
+  for (int f = 0; f < 6 && s == PCSIR_OK; ++f) {
+    if ((f == 2 || f == 3) && !best.sort_bins) continue;  // list blocks and digit width only shape the sort
     for (int i = 0; i < ncand[f] && s == PCSIR_OK; ++i) {
       pcsir_tuning t = best;
-      int32_t *field = f == 0 ? &t.bin_tile : f == 1 ? &t.list_blocks : f == 2 ? &t.digit_bits
-                     : f == 3 ? &t.grid_per_cu : &t.resample_light;
+      int32_t *field = f == 0 ? &t.sort_bins : f == 1 ? &t.bin_tile : f == 2 ? &t.list_blocks
+                     : f == 3 ? &t.digit_bits : f == 4 ? &t.grid_per_cu : &t.resample_light;
       if (*field == cands[f][i]) continue;
       *field = cands[f][i];
       float ms = 0.0f;

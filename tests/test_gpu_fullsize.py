@@ -89,13 +89,18 @@ def _sample(n, bins, most=10, spread=40):
     return sorted(int(t) for t in pick)
 
 
-@pytest.mark.parametrize("workload,lik,light", [("single-2d-512", 1, None), ("batched-2d-1024", 1, None),
+@pytest.mark.parametrize("workload,lik,extra", [("single-2d-512", 1, None), ("batched-2d-1024", 1, None),
                                                 ("3d-astig", 1, None), ("batched-2d-1024", 0, None),
-                                                ("batched-2d-1024", 1, 0), ("single-2d-512", 1, 0)])
-def test_full_size_step(workload, lik, light):
-    """light = 0: every scan tile with offspring leaves them to the search
-    over blocks of new particles (the path of tiles holding much of their
-    target's weight), at full size."""
+                                                ("batched-2d-1024", 1, dict(resample_light=0)),
+                                                ("single-2d-512", 1, dict(resample_light=0)),
+                                                ("batched-2d-1024", 1, dict(sort_bins=1)),
+                                                ("3d-astig", 1, dict(sort_bins=1))])
+def test_full_size_step(workload, lik, extra):
+    """extra: launch shapes beyond the benchmark's. resample_light = 0: every
+    scan tile with offspring leaves them to the search over blocks of new
+    particles (the path of tiles holding much of their target's weight);
+    sort_bins = 1: bins numbered by the radix sort instead of the occupancy
+    bitmap; both at full size."""
     from paper_1310_5541_amd import Config
     w = synth.preset(workload, K=4)
     frames = synth.frames(w, synth.truth(w))
@@ -103,10 +108,10 @@ def test_full_size_step(workload, lik, light):
     cfg = Config.from_workload(w, bins_per_px=(m, m, m if w.dim == 3 else 1), lik_mode=lik, seed=w.seed + 500)
     start = _start(w, cfg, frames, 4)
     n = w.counts()
-    log(f"case full_size {workload} lik_mode={lik} resample_light={light}: {int(n.sum())} particles, {len(n)} targets")
+    log(f"case full_size {workload} lik_mode={lik} {extra}: {int(n.sum())} particles, {len(n)} targets")
     bins = _properties(cfg, frames[3], start, 4)
     sample = _sample(n, bins)
     log(f"  checked {len(sample)} targets: {sample}; most bins {int(bins.max())}")
-    tuning = TUNING if light is None else dict(TUNING, resample_light=light)
+    tuning = dict(TUNING, **(extra or {}))
     dev, _ = run_step_parity(cfg, start, frames[3], 4, False, targets=sample, tuning=tuning)
     log(f"  deviations {dev}")
