@@ -129,9 +129,10 @@ typedef struct {
 } pcsir_config;
 
 /* Bytes of device workspace that a context with this config needs (0 if the
- * config is invalid): a fixed 768 MiB for the cell-occupancy bitmap (one bit
- * per 32-bit cell key, and a 32-bit first bin per 64-bit word), plus a part
- * that grows linearly with sum N_t (about 175 B per particle in 2D) and with T. */
+ * config is invalid): a fixed 1 GiB for the cell-occupancy bitmap (one bit
+ * per 32-bit cell key, each 64-bit word in a 16-byte entry with the number of
+ * its first bin), plus a part that grows linearly with sum N_t (about 175 B
+ * per particle in 2D) and with T. */
 size_t pcsir_workspace_bytes(const pcsir_config *cfg);
 
 /* Create a context. init_state_dev: SoA [D][sum N] float32, copied into the

@@ -52,9 +52,16 @@ enum {
 };
 
 // Cell-occupancy bitmap: one bit per compacted cell key, 64 keys per word, as
-// many words as cover every 32-bit key (512 MB), so it holds any key range
-// the step accepts. Words in use for a key range of `range` keys:
+// many words as cover every 32-bit key, so it holds any key range the step
+// accepts. Each word sits in a 16-byte entry with the number of the first bin
+// it holds, so that a particle's bin takes one load (1 GB in all).
+struct __attribute__((aligned(16))) BmWord {
+  unsigned long long bits;
+  uint32_t first;
+  uint32_t pad;
+};
 constexpr uint64_t BM_WORDS = 1ull << 26;
+// Words in use for a key range of `range` keys:
 __device__ __host__ __forceinline__ uint32_t bm_words(uint64_t range) {
   const uint64_t r = range < (1ull << 32) ? range : (1ull << 32);
   return (uint32_t)((r + 63) >> 6);
@@ -166,13 +173,12 @@ __global__ __launch_bounds__(TPB) void k_propagate(Params p, const Tile *__restr
                                                    int pending, const StepDesc *__restrict__ desc,
                                                    float *__restrict__ bbox_part, double *__restrict__ mom_part,
                                                    unsigned long long *__restrict__ acc,
-                                                   const uint64_t *__restrict__ meta,
-                                                   unsigned long long *__restrict__ bm) {
+                                                   const uint64_t *__restrict__ meta, BmWord *__restrict__ bm) {
   constexpr int D = 2 * DIM + 1;
   constexpr int K = PROP_TILES;
   if (KEYS && bm) {
     const uint32_t nw = bm_words(meta[META_RANGE]);
-    for (uint32_t w = blockIdx.x * TPB + threadIdx.x; w < nw; w += gridDim.x * TPB) bm[w] = 0ull;
+    for (uint32_t w = blockIdx.x * TPB + threadIdx.x; w < nw; w += gridDim.x * TPB) bm[w].bits = 0ull;
   }
   // the block's K tiles: their ancestor loads, then their state loads, are
   // issued together (a duplicate of the last tile pads the last block and
@@ -450,7 +456,7 @@ __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__re
                                               const uint32_t *__restrict__ off, const float *__restrict__ s,
                                               const int32_t *__restrict__ bbox_cur, const uint32_t *__restrict__ kbase,
                                               uint32_t *__restrict__ sparse, uint32_t *__restrict__ tcount,
-                                              uint64_t *__restrict__ meta, unsigned long long *__restrict__ bm) {
+                                              uint64_t *__restrict__ meta, BmWord *__restrict__ bm) {
   constexpr int R = KEYS_TILE / KEYS_TPB / 2;  // a thread's positions of a round are loaded before use
   constexpr int PER = DEDUP_SLOTS / KEYS_TPB;
   __shared__ __attribute__((aligned(16))) uint32_t tab[DEDUP_SLOTS];
@@ -537,12 +543,12 @@ __global__ __launch_bounds__(KEYS_TPB) void k_keys(Params p, const BinTile *__re
         }
         h = (h + 1) & (WORD_SLOTS - 1);
       }
-      if (!merged) atomicOr(&bm[wd], bit);
+      if (!merged) atomicOr(&bm[wd].bits, bit);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < WORD_SLOTS; i += KEYS_TPB) {
       const uint32_t wd = wkey[i];
-      if (wd != KEY_EMPTY) atomicOr(&bm[wd], wmask[i]);
+      if (wd != KEY_EMPTY) atomicOr(&bm[wd].bits, wmask[i]);
     }
     const uint32_t tot = block_sum<KEYS_TPB, uint32_t>(c, lds);
     if (threadIdx.x == 0) atomicAdd((unsigned long long *)&meta[META_L], (unsigned long long)tot);
@@ -912,12 +918,12 @@ __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs
 // workgroups each take a contiguous share of the words in use. k_map_count
 // counts the bits of its share. k_map_rank sums the counts of the shares
 // before its own (at most a few thousand loads, instead of one workgroup
-// waiting for all others), then writes every word's first bin (bpre), every
+// waiting for all others), then writes every word's first bin, every
 // bin's key and target, and the first bin of every target whose key base
 // falls in its share; the last workgroup writes the bin count B (and
-// seg_first[T] = B). A particle with key k is in bin bpre[k / 64] plus the
-// number of set bits of word k / 64 below bit k % 64.
-__global__ __launch_bounds__(TPB) void k_map_count(uint32_t G, const unsigned long long *__restrict__ bm,
+// seg_first[T] = B). A particle with key k is in its word's first bin plus
+// the number of set bits of word k / 64 below bit k % 64.
+__global__ __launch_bounds__(TPB) void k_map_count(uint32_t G, const BmWord *__restrict__ bm,
                                                    const uint64_t *__restrict__ meta,
                                                    uint32_t *__restrict__ chunk_count) {
   __shared__ uint32_t lds[TPB / WAVE];
@@ -925,7 +931,7 @@ __global__ __launch_bounds__(TPB) void k_map_count(uint32_t G, const unsigned lo
   uint32_t j0, j1;
   list_range(nw, G, blockIdx.x, j0, j1);
   uint32_t c = 0;
-  for (uint32_t j = j0 + threadIdx.x; j < j1; j += TPB) c += (uint32_t)__popcll(bm[j]);
+  for (uint32_t j = j0 + threadIdx.x; j < j1; j += TPB) c += (uint32_t)__popcll(bm[j].bits);
   const uint32_t s = block_sum<TPB, uint32_t>(c, lds);
   if (threadIdx.x == 0) chunk_count[blockIdx.x] = s;
 }
@@ -945,8 +951,7 @@ __device__ __forceinline__ int first_target_at(uint32_t key, int T, KB kb) {
 __global__ __launch_bounds__(TPB) void k_map_rank(Params p, uint32_t G, uint64_t *__restrict__ meta,
                                                   const uint32_t *__restrict__ chunk_count,
                                                   const uint32_t *__restrict__ kbase,
-                                                  const unsigned long long *__restrict__ bm,
-                                                  uint32_t *__restrict__ bpre, uint32_t *__restrict__ seg_key,
+                                                  BmWord *__restrict__ bm, uint32_t *__restrict__ seg_key,
                                                   int32_t *__restrict__ seg_t, uint32_t *__restrict__ seg_first) {
   __shared__ uint32_t lds[TPB / WAVE];
   __shared__ uint32_t kb_lds[KBASE_LDS];
@@ -964,10 +969,10 @@ __global__ __launch_bounds__(TPB) void k_map_rank(Params p, uint32_t G, uint64_t
   uint32_t base = block_sum<TPB, uint32_t>(before, lds);
   for (uint32_t r0 = j0; r0 < j1; r0 += TPB) {
     const uint32_t j = r0 + threadIdx.x;
-    const unsigned long long wd = j < j1 ? bm[j] : 0ull;
+    const unsigned long long wd = j < j1 ? bm[j].bits : 0ull;
     uint32_t tot;
     const uint32_t pre = base + block_excl_scan<TPB, uint32_t>((uint32_t)__popcll(wd), lds, &tot);
-    if (j < j1) bpre[j] = pre;
+    if (j < j1) bm[j].first = pre;
     wpre[threadIdx.x] = pre;
     wbits[threadIdx.x] = wd;
     // the word's bins in key order: key and target of each (the target of
@@ -1090,8 +1095,7 @@ __global__ __launch_bounds__((BinLds<DIM, MOM2>::NTH)) void k_bin_sums(Params p,
                                                   const uint32_t *__restrict__ seg_first,
                                                   unsigned long long *__restrict__ acc, uint32_t *__restrict__ segid,
                                                   uint64_t *__restrict__ meta, const uint32_t *__restrict__ lut,
-                                                  uint64_t lut_cap, const unsigned long long *__restrict__ bm,
-                                                  const uint32_t *__restrict__ bpre) {
+                                                  uint64_t lut_cap, const BmWord *__restrict__ bm) {
   constexpr int D = 2 * DIM + 1;
   constexpr int NC = BinLds<DIM, MOM2>::NC;
   static_assert(!MOM2 || DIM == 2, "second moments in 2D only");
@@ -1144,7 +1148,9 @@ __global__ __launch_bounds__((BinLds<DIM, MOM2>::NTH)) void k_bin_sums(Params p,
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const uint32_t k = bin[q];
-        bin[q] = bpre[k >> 6] + (uint32_t)__popcll(bm[k >> 6] & ((1ull << (k & 63u)) - 1ull));
+        const uint4 e = *reinterpret_cast<const uint4 *>(&bm[k >> 6]);
+        const unsigned long long bits = ((unsigned long long)e.y << 32) | e.x;
+        bin[q] = e.z + (uint32_t)__popcll(bits & ((1ull << (k & 63u)) - 1ull));
       }
     } else {
 #pragma unroll

@@ -24,7 +24,7 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t S0, S1, anc, key, kA, kB, hist, dtot, chunk_heads, acc, seg_key, seg_t, segid, dpix, doff, dint, dlo,
-      ll, ll9, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first, bm, bpre,
+      ll, ll9, wbin, lw, wacc, tuni, tuni_next, desc, dvel, surr, tfb, tmax, tsse, tcnt, tcount, lut, seg_first, bm,
       bbox_part, mom_part, tm, range, bbox_cur, kbase, meta, tgt, est, tflag, part, tile_sum, tile_pre, cdf, rs_work, rs_count,
       tiles256, tilesS, tilesR, tilesB, tilesK, tile_last, tfirst, tfirstR, t256_first, off;
   size_t total;
@@ -218,9 +218,8 @@ Layout plan(const pcsir_config *c, const Tables &tb) {
   L.lut_cap = 1ull << 16;
   while (L.lut_cap < 8 * NT && L.lut_cap < (1ull << 25)) L.lut_cap <<= 1;
   L.lut = take(4 * L.lut_cap);
-  // cell-occupancy bitmap over every 32-bit key (512 MB) and each word's first bin (256 MB)
-  L.bm = take(8 * BM_WORDS);
-  L.bpre = take(4 * BM_WORDS);
+  // cell-occupancy bitmap over every 32-bit key, with each word's first bin (1 GB)
+  L.bm = take(sizeof(BmWord) * BM_WORDS);
   L.tile_last = take(4 * (size_t)L.nS);
   L.tfirst = take(4 * (T + 1));
   L.tfirstR = take(4 * (T + 1));
@@ -447,8 +446,7 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   uint64_t *meta = c->at<uint64_t>(L.meta);
   // bins numbered by the radix sort of the distinct keys, or (default) from the occupancy bitmap
   const bool sort_bins = c->tune.sort_bins != 0;
-  unsigned long long *bm = sort_bins ? nullptr : c->at<unsigned long long>(L.bm);
-  uint32_t *bpre = sort_bins ? nullptr : c->at<uint32_t>(L.bpre);
+  BmWord *bm = sort_bins ? nullptr : c->at<BmWord>(L.bm);
 
   const bool keep = keeps_weights(&c->cfg);
   int32_t *tuni = keep ? c->at<int32_t>(L.tuni) : nullptr;
@@ -458,7 +456,7 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
   mark(c, "propagate");
   k_propagate<DIM, true><<<(L.n256 + PROP_TILES - 1) / PROP_TILES, TPB, 0, st>>>(
       p, t256, L.n256, off, sin, sout, anc, c->pending, desc, c->at<float>(L.bbox_part), c->at<double>(L.mom_part),
-      c->at<unsigned long long>(L.acc), meta, c->at<unsigned long long>(L.bm));
+      c->at<unsigned long long>(L.acc), meta, c->at<BmWord>(L.bm));
   mark(c, "bbox");
   k_bbox_reduce<<<p.T, TPB, 0, st>>>(p, c->at<uint32_t>(L.t256_first), off, c->at<float>(L.bbox_part),
                                      c->at<double>(L.mom_part), c->at<int32_t>(L.tm), c->at<int32_t>(L.bbox_cur),
@@ -501,7 +499,7 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
     mark(c, "map_count");
     k_map_count<<<L.G, TPB, 0, st>>>(L.G, bm, meta, chunk);
     mark(c, "map_rank");
-    k_map_rank<<<L.G, TPB, 0, st>>>(p, L.G, meta, chunk, c->at<uint32_t>(L.kbase), bm, bpre,
+    k_map_rank<<<L.G, TPB, 0, st>>>(p, L.G, meta, chunk, c->at<uint32_t>(L.kbase), bm,
                                     c->at<uint32_t>(L.seg_key), c->at<int32_t>(L.seg_t),
                                     c->at<uint32_t>(L.seg_first));
   }
@@ -511,17 +509,17 @@ void launch_pcsir(pcsir_ctx *c, hipStream_t st) {
       k_bin_sums<DIM, true><<<c->nB, BinLds<DIM, true>::NTH, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
-                                        c->at<uint32_t>(L.lut), L.lut_cap, bm, bpre);
+                                        c->at<uint32_t>(L.lut), L.lut_cap, bm);
     else
       k_bin_sums<DIM><<<c->nB, BinLds<DIM>::NTH, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
-                                        c->at<uint32_t>(L.lut), L.lut_cap, bm, bpre);
+                                        c->at<uint32_t>(L.lut), L.lut_cap, bm);
   } else {
     k_bin_sums<DIM><<<c->nB, BinLds<DIM>::NTH, 0, st>>>(p, c->at<BinTile>(L.tilesB), off, sout, c->at<int32_t>(L.bbox_cur),
                                         c->at<uint32_t>(L.kbase), c->at<uint32_t>(L.seg_key),
                                         c->at<uint32_t>(L.seg_first), acc, c->at<uint32_t>(L.segid), meta,
-                                        c->at<uint32_t>(L.lut), L.lut_cap, bm, bpre);
+                                        c->at<uint32_t>(L.lut), L.lut_cap, bm);
   }
   if (keep) {
     mark(c, "bin_wsums");
@@ -843,7 +841,7 @@ pcsir_status pcsir_init(const pcsir_config *cfg, const float *init_state_dev, vo
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tsse, 0, 8 * (size_t)T, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.tcnt, 0, 4 * (size_t)T, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.acc, 0, 8 * (size_t)c->p.acc_rows * c->NT, c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.bm, 0, 8 * BM_WORDS, c->stream);  // each step clears what it set
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.bm, 0, sizeof(BmWord) * BM_WORDS, c->stream);  // each step clears what it set
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->state(0), init_state_dev, 4 * (size_t)D * c->NT, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) {

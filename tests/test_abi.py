@@ -67,9 +67,9 @@ def test_workspace_bytes_and_validation(L):
     b = L.pcsir_workspace_bytes(C.byref(c))
     assert b > 0 and b % 256 == 0
     # a fixed part (the occupancy bitmap over every 32-bit cell key: 2^26
-    # 64-bit words and a 32-bit first bin per word), and a part that grows
-    # with the particle count, roughly linearly
-    fixed = 8 * 2 ** 26 + 4 * 2 ** 26
+    # 16-byte entries of a 64-bit word and its first bin), and a part that
+    # grows with the particle count, roughly linearly
+    fixed = 16 * 2 ** 26
     assert b > fixed
     c2, keep2 = _cfg(n_particles=(100000, 3700))._c()
     b2 = L.pcsir_workspace_bytes(C.byref(c2))
