@@ -957,7 +957,9 @@ __global__ __launch_bounds__(TPB) void k_map_rank(Params p, uint32_t G, uint64_t
   __shared__ uint32_t kb_lds[KBASE_LDS];
   __shared__ uint32_t wpre[TPB];
   __shared__ unsigned long long wbits[TPB];
+  __shared__ int32_t wtgt[TPB];
   const bool kb_in_lds = p.T <= KBASE_LDS;
+  auto kb_at = [&](int t) -> uint32_t { return kb_in_lds ? kb_lds[t] : kbase[t]; };
   if (kb_in_lds)
     for (int t = threadIdx.x; t < p.T; t += TPB) kb_lds[t] = kbase[t];
   __syncthreads();
@@ -975,29 +977,46 @@ __global__ __launch_bounds__(TPB) void k_map_rank(Params p, uint32_t G, uint64_t
     if (j < j1) bm[j].first = pre;
     wpre[threadIdx.x] = pre;
     wbits[threadIdx.x] = wd;
-    // the word's bins in key order: key and target of each (the target of
-    // its first bin by a search, then moved on at each key base passed)
-    unsigned long long rest = wd;
-    uint32_t r = pre;
-    if (rest) {
-      const uint32_t k0 = j * 64u + (uint32_t)__builtin_ctzll(rest);
-      int t = kb_in_lds ? key_target(k0, p.T, (const uint32_t *)kb_lds) : key_target(k0, p.T, kbase);
-      auto next_base = [&](int u) -> uint64_t {
-        return u + 1 < p.T ? (uint64_t)(kb_in_lds ? kb_lds[u + 1] : kbase[u + 1]) : (1ull << 32);
-      };
-      uint64_t nb = next_base(t);
-      while (rest) {
-        const uint32_t k = j * 64u + (uint32_t)__builtin_ctzll(rest);
-        while ((uint64_t)k >= nb) nb = next_base(++t);
-        if (r < p.NT) {  // always: every set bit is the cell of a particle of this frame
-          seg_key[r] = k;
-          seg_t[r] = t;
+    // target of the word's first bin (by a search, once per word)
+    int tw = 0;
+    if (wd) {
+      const uint32_t k0 = j * 64u + (uint32_t)__builtin_ctzll(wd);
+      tw = kb_in_lds ? key_target(k0, p.T, (const uint32_t *)kb_lds) : key_target(k0, p.T, kbase);
+    }
+    wtgt[threadIdx.x] = tw;
+    __syncthreads();
+    // the round's bins, consecutive lanes taking consecutive bins: the word
+    // that holds bin r is the last one whose first bin is <= r (words after
+    // the share have no bits and first bin base + tot), the bin is the n-th
+    // set bit of that word (found by halving with popcounts), and its target
+    // is the word's first target, moved on past any key base it crosses
+    for (uint32_t i = threadIdx.x; i < tot; i += TPB) {
+      const uint32_t r = base + i;
+      int lo = 0, hi = TPB - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (wpre[mid] <= r) lo = mid;
+        else hi = mid - 1;
+      }
+      unsigned long long b = wbits[lo];
+      uint32_t n = r - wpre[lo], pos = 0;
+#pragma unroll
+      for (int sh = 32; sh >= 1; sh >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(b & ((1ull << sh) - 1ull));
+        if (n >= c) {
+          n -= c;
+          b >>= sh;
+          pos += (uint32_t)sh;
         }
-        ++r;
-        rest &= rest - 1ull;
+      }
+      const uint32_t k = (r0 + (uint32_t)lo) * 64u + pos;
+      int t = wtgt[lo];
+      while (t + 1 < p.T && k >= kb_at(t + 1)) ++t;
+      if (r < p.NT) {  // always: every set bit is the cell of a particle of this frame
+        seg_key[r] = k;
+        seg_t[r] = t;
       }
     }
-    __syncthreads();
     // first bin of every target whose key base lies in this round's words
     const uint32_t klo = r0 * 64u;
     const uint64_t khi = (uint64_t)min(r0 + (uint32_t)TPB, j1) * 64u;
