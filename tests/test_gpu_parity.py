@@ -392,6 +392,41 @@ def test_launch_shapes_do_not_change_results_and_autotune_restores_particles():
     f.close()
 
 
+def test_bin_numbering_across_steps_with_changing_key_ranges():
+    """The occupancy bitmap keeps no stale bits between steps: on one filter,
+    particle sets with wide and narrow clouds alternate (the key range grows
+    and shrinks by orders of magnitude) while the bin numbering switches
+    between the bitmap and the sort, and every step equals the same step on a
+    fresh filter bit for bit (the bits a step sets are cleared by the next
+    step's propagation, over the previous key range)."""
+    import torch
+
+    from paper_1310_5541_amd import Filter
+    counts = (3000, 700, 4000)
+    w = synth.preset("tiny", H=128, W=128, T=len(counts), n=counts, m=(8, 8, 1), K=2, i0=(20.0, 100.0))
+    tr, fr = _scene(w, seed=17)
+    cfg = _cfg(w, seed=19, lik_mode=1)
+    centres = [tr[1, t] for t in range(len(counts))]
+    wide = torch.from_numpy(_clouds(w, counts, centres, 12.0, 7)).cuda()
+    narrow = torch.from_numpy(_clouds(w, counts, centres, 0.3, 8)).cuda()
+    frame = torch.from_numpy(fr[1]).cuda()
+    names = ("bin_key", "bin_n", "loglik", "weights", "resample")
+    f = Filter(cfg, narrow)
+    for i, (cl, sb) in enumerate([(wide, 0), (narrow, 0), (wide, 1), (narrow, 1), (wide, 0), (narrow, 0), (wide, 0)]):
+        log(f"case bin_numbering_across_steps step {i} {'wide' if cl is wide else 'narrow'} sort_bins={sb}")
+        f.set_particles(cl)
+        f.set_tuning(sort_bins=sb)
+        f.pcsir_step(frame, 1)
+        got = {n: f.dump(n).cpu().numpy() for n in names}
+        g = Filter(cfg, cl)
+        g.pcsir_step(frame, 1)
+        ref = {n: g.dump(n).cpu().numpy() for n in names}
+        g.close()
+        for n in names:
+            assert np.array_equal(got[n], ref[n]), (i, n)
+    f.close()
+
+
 @pytest.mark.parametrize("lik", [0, 1])
 def test_second_order_dummies(lik):
     """Dummies that carry their members' position covariance: nine shifted
