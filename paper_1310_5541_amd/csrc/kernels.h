@@ -66,6 +66,12 @@ __device__ __host__ __forceinline__ uint32_t bm_words(uint64_t range) {
   const uint64_t r = range < (1ull << 32) ? range : (1ull << 32);
   return (uint32_t)((r + 63) >> 6);
 }
+// A frame whose cell range of all targets does not fit 32-bit keys (reported
+// as ERR_KEY_RANGE) gets no bins: its keys and key bases have wrapped, and
+// bins numbered from them would not be ordered by target.
+__device__ __forceinline__ bool key_range_overflow(const uint64_t *meta) {
+  return meta[META_RANGE] > 0xFFFFFFFFull;
+}
 
 // Values one workgroup hands to another within a launch go through memory,
 // not through the XCD's own L2 (which the other workgroup's XCD does not
@@ -810,6 +816,7 @@ __global__ __launch_bounds__(TPB) void k_seg_count(uint32_t G, int T, SortBufs s
     if (b < G) chunk_heads[b] = carry + ex;
     carry += tot;
   }
+  if (key_range_overflow(meta)) carry = 0;  // no bins (k_seg_mark writes nothing)
   if (threadIdx.x == 0) {
     meta[META_B] = carry;
     meta[META_DIRTY] = carry;  // accumulators [0, B) are written this frame
@@ -871,6 +878,7 @@ __global__ __launch_bounds__(TPB) void k_seg_mark(Params p, uint32_t G, SortBufs
                                                   const uint32_t *__restrict__ kbase, uint32_t *__restrict__ seg_key,
                                                   int32_t *__restrict__ seg_t, uint32_t *__restrict__ lut,
                                                   uint64_t lut_cap, uint32_t *__restrict__ seg_first) {
+  if (key_range_overflow(meta)) return;  // no bins this frame (k_seg_count)
   const bool use_lut = meta[META_RANGE] <= lut_cap;
   __shared__ uint32_t lds[TPB / WAVE];
   __shared__ uint32_t kb_lds[KBASE_LDS];
@@ -927,7 +935,7 @@ __global__ __launch_bounds__(TPB) void k_map_count(uint32_t G, const BmWord *__r
                                                    const uint64_t *__restrict__ meta,
                                                    uint32_t *__restrict__ chunk_count) {
   __shared__ uint32_t lds[TPB / WAVE];
-  const uint32_t nw = bm_words(meta[META_RANGE]);
+  const uint32_t nw = key_range_overflow(meta) ? 0u : bm_words(meta[META_RANGE]);
   uint32_t j0, j1;
   list_range(nw, G, blockIdx.x, j0, j1);
   uint32_t c = 0;
@@ -963,7 +971,10 @@ __global__ __launch_bounds__(TPB) void k_map_rank(Params p, uint32_t G, uint64_t
   if (kb_in_lds)
     for (int t = threadIdx.x; t < p.T; t += TPB) kb_lds[t] = kbase[t];
   __syncthreads();
-  const uint32_t nw = bm_words(meta[META_RANGE]);
+  const bool overflow = key_range_overflow(meta);
+  const uint32_t nw = overflow ? 0u : bm_words(meta[META_RANGE]);
+  if (overflow)  // no bins: every target's first bin is 0
+    for (int t = blockIdx.x * TPB + threadIdx.x; t < p.T; t += G * TPB) seg_first[t] = 0;
   uint32_t j0, j1;
   list_range(nw, G, blockIdx.x, j0, j1);
   uint32_t before = 0;

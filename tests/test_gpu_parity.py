@@ -239,6 +239,29 @@ def test_nonfinite_frame_is_reported_and_particles_kept():
     f.close()
 
 
+@pytest.mark.parametrize("sort_bins", [0, 1])
+def test_key_range_overflow_is_reported(sort_bins):
+    """A frame whose occupied cell range does not fit 32-bit keys (4096 cells
+    per pixel over a cloud of about 100 px: about 10^11 cells) gets no bins,
+    whichever numbering is chosen, and the step reports the cell range
+    instead of binning with wrapped keys."""
+    import torch
+
+    from paper_1310_5541_amd import Filter, PcsirError
+    w = synth.preset("tiny", n=(2000,), m=(4096, 4096, 1))
+    tr, fr = _scene(w)
+    cfg = _cfg(w, seed=4)
+    cloud = _clouds(w, [2000], [tr[1, 0]], 20.0, 3)
+    log(f"case key_range_overflow sort_bins={sort_bins}")
+    f = Filter(cfg, torch.from_numpy(cloud).cuda())
+    f.set_tuning(sort_bins=sort_bins)
+    f.step(torch.from_numpy(fr[1]).cuda(), 1)
+    with pytest.raises(PcsirError) as ei:
+        f.estimate()
+    assert "cell range" in str(ei.value)
+    f.close()
+
+
 def test_api_state_errors():
     import torch
 
