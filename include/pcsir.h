@@ -162,7 +162,11 @@ pcsir_status sir_step(pcsir_ctx *ctx, const float *frame_dev, int32_t H, int32_t
  * (posterior mean, taken after weighting and before resampling) and, if not
  * NULL, neff_host [T] float64 (N_eff = 1 / sum w^2). Synchronises the stream.
  * Returns PCSIR_E_NUMERIC if a device-side condition was raised since the
- * last call (the flag is then cleared). */
+ * last call (the flag is then cleared; pcsir_last_error names it): a
+ * target's normalisation not finite (its particles are kept), a velocity or
+ * intensity outside the bin sums' fixed-point range, or all targets' cell
+ * boxes together above 2^32 cells (the frame then gets no bins, so its
+ * targets keep their particles). */
 pcsir_status pcsir_estimate(pcsir_ctx *ctx, double *est_host, double *neff_host);
 
 /* Synchronise the stream and free the host context. The workspace may be
